@@ -1,0 +1,365 @@
+"""Sequential CPU oracle for HyP-DESPOT leaf expansion.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py``.  The GPU library and its binding
+never import it.
+
+The arithmetic lives in ``oracle.c`` (plain loops, FP64 values); this module
+marshals numpy arrays to it and holds the Bellman backup of Eq. 4 written out
+in Python.  States use the library's documented struct-of-arrays layout:
+
+* RockSample: ``{"w": int32[n]}`` with x in bits 0-4, y in bits 5-9, rock i's
+  quality in bit 10+i and the terminal flag in bit 30;
+* crowd driving: ``{"s": f32[n], "car": int32[n] (speed level | terminal<<8),
+  "px": f32[P, n], "py": f32[P, n], "goal": u8[P, n]}``.
+
+Parity pins for every function here live in ``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc (plain host code, contraction off)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Model(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_actions", C.c_int32), ("gamma", C.c_double),
+                ("n", C.c_int32), ("m", C.c_int32),
+                ("rock_x", C.c_int32 * 20), ("rock_y", C.c_int32 * 20),
+                ("n_peds", C.c_int32), ("n_goals", C.c_int32), ("n_levels", C.c_int32),
+                ("pad_", C.c_int32),
+                ("goal_x", C.c_float * 8), ("goal_y", C.c_float * 8),
+                ("path_len", C.c_float), ("dt", C.c_float), ("ped_speed", C.c_float),
+                ("sigma_h", C.c_float), ("coll_radius", C.c_float),
+                ("r_collision", C.c_float), ("r_step", C.c_float), ("r_goal", C.c_float),
+                ("p_fail", C.c_double)]
+
+
+class _Cfg(C.Structure):
+    _fields_ = [("policy", C.c_int32), ("const_action", C.c_int32),
+                ("max_steps", C.c_int32), ("max_depth", C.c_int32)]
+
+
+class _Soa(C.Structure):
+    _fields_ = [("w", C.c_void_p), ("s", C.c_void_p), ("car", C.c_void_p),
+                ("px", C.c_void_p), ("py", C.c_void_p), ("goal", C.c_void_p),
+                ("stride", C.c_int64)]
+
+
+class _Out(C.Structure):
+    _fields_ = [("states", _Soa), ("ids", C.c_void_p), ("sprime", _Soa),
+                ("r", C.c_void_p), ("z", C.c_void_p), ("U", C.c_void_p), ("L", C.c_void_p),
+                ("child_of", C.c_void_p), ("perm", C.c_void_p), ("n_children", C.c_void_p),
+                ("child_z", C.c_void_p), ("child_n", C.c_void_p), ("child_off", C.c_void_p),
+                ("child_u0", C.c_void_p), ("child_l0", C.c_void_p), ("r_mean", C.c_void_p),
+                ("expand_steps", C.c_void_p), ("rollout_steps", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        L.or_philox4x32_10.argtypes = [P, P, P, C.c_int64]
+        L.or_step_batch.argtypes = [P, P, P, C.c_int64, C.c_int32, C.c_int32, C.c_uint32,
+                                    C.c_uint32, P, P, P]
+        L.or_sample_scenarios.argtypes = [P, C.c_int32, C.c_uint32, C.c_uint32, C.c_int32,
+                                          C.c_int32, P, C.c_float, C.c_int32, P, P, P, P]
+        L.or_rollout_bounds.argtypes = [P, P, C.c_uint32, C.c_uint32, P, P, P, C.c_int64, P, P, P]
+        L.or_expand_leaf.argtypes = [P, P, C.c_uint32, C.c_uint32, P, P, P, C.c_int32, C.c_int32,
+                                     C.c_int32, C.c_int32, P]
+        L.or_expand_leaf.restype = C.c_int
+        L.or_rs_sense_threshold.argtypes = [C.c_int32]
+        L.or_rs_sense_threshold.restype = C.c_uint64
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10 and the state layout
+# --------------------------------------------------------------------------
+def philox(ctr, key) -> np.ndarray:
+    """Philox4x32-10 blocks for counters ``ctr`` (N x 4 uint32), key (2,)."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    key = np.ascontiguousarray(key, dtype=np.uint32).reshape(2)
+    out = np.empty_like(ctr)
+    lib().or_philox4x32_10(_ptr(ctr), _ptr(key), _ptr(out), ctr.shape[0])
+    return out
+
+
+def rs_pack(x, y, rocks, term) -> np.ndarray:
+    """RockSample state words from fields (rocks: bool [n, m])."""
+    rocks = np.asarray(rocks, dtype=bool)
+    n = rocks.shape[0]
+    w = np.full(n, int(x) | (int(y) << 5), dtype=np.int64)
+    for i in range(rocks.shape[1]):
+        w |= rocks[:, i].astype(np.int64) << (10 + i)
+    w |= np.asarray(term, dtype=np.int64) << 30
+    return w.astype(np.int32)
+
+
+def rs_unpack(w) -> dict:
+    w = np.asarray(w, dtype=np.int64)
+    return dict(x=w & 31, y=(w >> 5) & 31, rocks=(w >> 10) & 0xFFFFF, term=(w >> 30) & 1)
+
+
+def parent_states(desc: dict, leaf: dict) -> dict:
+    """States dict for a synthetic leaf's parent (fields from ``workloads``)."""
+    if desc["kind"] == 0:
+        return dict(w=rs_pack(leaf["x"], leaf["y"], leaf["rocks"], leaf["term"]))
+    car = leaf["level"].astype(np.int32) | (leaf["term"].astype(np.int32) << 8)
+    return dict(s=np.ascontiguousarray(leaf["s"], dtype=np.float32), car=car.astype(np.int32),
+                px=np.ascontiguousarray(leaf["px"], dtype=np.float32),
+                py=np.ascontiguousarray(leaf["py"], dtype=np.float32),
+                goal=np.ascontiguousarray(leaf["goal"], dtype=np.uint8))
+
+
+def empty_states(desc: dict, n: int) -> dict:
+    if desc["kind"] == 0:
+        return dict(w=np.zeros(n, np.int32))
+    P = desc["n_peds"]
+    return dict(s=np.zeros(n, np.float32), car=np.zeros(n, np.int32),
+                px=np.zeros((P, n), np.float32), py=np.zeros((P, n), np.float32),
+                goal=np.zeros((P, n), np.uint8))
+
+
+def _soa(desc: dict, st: dict | None, n: int) -> _Soa:
+    v = _Soa()
+    if st is None:
+        return v
+    if desc["kind"] == 0:
+        v.w = _ptr(st["w"])
+    else:
+        v.s, v.car = _ptr(st["s"]), _ptr(st["car"])
+        v.px, v.py, v.goal = _ptr(st["px"]), _ptr(st["py"]), _ptr(st["goal"])
+    v.stride = n
+    return v
+
+
+def _check_states(desc, st):
+    if desc["kind"] == 0:
+        assert st["w"].dtype == np.int32 and st["w"].flags.c_contiguous
+        return st["w"].shape[0]
+    n = st["s"].shape[0]
+    P = desc["n_peds"]
+    assert st["px"].shape == (P, n) and st["goal"].dtype == np.uint8
+    for k in ("s", "car", "px", "py", "goal"):
+        assert st[k].flags.c_contiguous
+    return n
+
+
+def model(desc: dict) -> _Model:
+    m = _Model()
+    m.kind = desc["kind"]
+    m.n_actions = desc["n_actions"]
+    m.gamma = desc["gamma"]
+    if desc["kind"] == 0:
+        m.n, m.m = desc["n"], desc["m"]
+        for i in range(desc["m"]):
+            m.rock_x[i] = int(desc["rock_x"][i])
+            m.rock_y[i] = int(desc["rock_y"][i])
+    else:
+        m.n_peds, m.n_goals, m.n_levels = desc["n_peds"], desc["n_goals"], desc["n_levels"]
+        for g in range(desc["n_goals"]):
+            m.goal_x[g] = float(desc["goal_x"][g])
+            m.goal_y[g] = float(desc["goal_y"][g])
+        for f in ("path_len", "dt", "ped_speed", "sigma_h", "coll_radius", "r_collision",
+                  "r_step", "r_goal"):
+            setattr(m, f, float(desc[f]))
+        m.p_fail = desc["p_fail"]
+    return m
+
+
+def cfg(policy: int = 0, max_steps: int = 1 << 30, max_depth: int = -1,
+        const_action: int = 0) -> _Cfg:
+    """Rollout configuration: policy 0 = model default (RockSample: move
+    east; crowd driving: brake for a pedestrian ahead, else accelerate),
+    1 = constant action, 2 = uniform random action per step."""
+    c = _Cfg()
+    c.policy, c.const_action, c.max_steps, c.max_depth = policy, const_action, max_steps, max_depth
+    return c
+
+
+# --------------------------------------------------------------------------
+# Model entry points
+# --------------------------------------------------------------------------
+def step(desc, states, ids, action, depth, seed, step_idx):
+    """One application of g with a single action to every state."""
+    n = _check_states(desc, states)
+    out = empty_states(desc, n)
+    r = np.zeros(n, np.float32)
+    z = np.zeros(n, np.uint64)
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    M = model(desc)
+    lib().or_step_batch(C.byref(M), C.byref(_soa(desc, states, n)), _ptr(ids), n, action, depth,
+                        seed, step_idx, C.byref(_soa(desc, out, n)), _ptr(r), _ptr(z))
+    return out, r, z
+
+
+def sample_scenarios(desc, belief, K, seed, step_idx):
+    out = empty_states(desc, K)
+    M = model(desc)
+    if desc["kind"] == 0:
+        p = np.ascontiguousarray(belief["p"], dtype=np.float64)
+        lib().or_sample_scenarios(C.byref(M), K, seed, step_idx, belief["x"], belief["y"], _ptr(p),
+                                  0.0, 0, None, None, None, C.byref(_soa(desc, out, K)))
+    else:
+        px = np.ascontiguousarray(belief["px"], dtype=np.float32)
+        py = np.ascontiguousarray(belief["py"], dtype=np.float32)
+        gp = np.ascontiguousarray(belief["goal_p"], dtype=np.float64)
+        lib().or_sample_scenarios(C.byref(M), K, seed, step_idx, 0, 0, None,
+                                  float(belief["s"]), int(belief["level"]), _ptr(px), _ptr(py),
+                                  _ptr(gp), C.byref(_soa(desc, out, K)))
+    return out
+
+
+def rollout_bounds(desc, rcfg, states, ids, depths, seed, step_idx):
+    n = _check_states(desc, states)
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    depths = np.ascontiguousarray(np.broadcast_to(depths, (n,)), dtype=np.int32)
+    U = np.zeros(n)
+    L = np.zeros(n)
+    steps = np.zeros(n, np.int64)
+    M = model(desc)
+    lib().or_rollout_bounds(C.byref(M), C.byref(rcfg), seed, step_idx,
+                            C.byref(_soa(desc, states, n)), _ptr(ids), _ptr(depths), n,
+                            _ptr(U), _ptr(L), _ptr(steps))
+    return U, L, steps
+
+
+def max_children(desc: dict, n: int) -> int:
+    """Most children one action can have: RockSample observations take 3
+    values; crowd-driving observations are hashes, so up to one per scenario."""
+    return min(n, 3) if desc["kind"] == 0 else n
+
+
+def expand_leaf(desc, rcfg, parent, parent_ids, idx, depth, last_action, seed, step_idx,
+                per_pair: bool = False, cap: int | None = None) -> dict:
+    """Expand one leaf and initialise its children's bounds (Sec. III-D)."""
+    n_par = _check_states(desc, parent)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    parent_ids = np.ascontiguousarray(parent_ids, dtype=np.uint32)
+    assert parent_ids.shape[0] == n_par
+    n = idx.shape[0]
+    A = desc["n_actions"]
+    cap = max_children(desc, n) if cap is None else cap
+    capc = max(cap, 1)
+    res = dict(states=empty_states(desc, n), ids=np.zeros(n, np.uint32),
+               perm=np.zeros((A, n), np.int32), child_of=np.zeros((A, n), np.int32),
+               n_children=np.zeros(A, np.int32), child_z=np.zeros((A, capc), np.uint64),
+               child_n=np.zeros((A, capc), np.int32), child_off=np.zeros((A, capc), np.int32),
+               child_u0=np.zeros((A, capc)), child_l0=np.zeros((A, capc)),
+               r_mean=np.zeros(A), expand_steps=np.zeros(1, np.int64),
+               rollout_steps=np.zeros(1, np.int64))
+    o = _Out()
+    o.states = _soa(desc, res["states"], n)
+    if per_pair:
+        res.update(sprime=empty_states(desc, A * n), r=np.zeros((A, n), np.float32),
+                   z=np.zeros((A, n), np.uint64), U=np.zeros((A, n)), L=np.zeros((A, n)))
+        o.sprime = _soa(desc, res["sprime"], A * n)
+        o.r, o.z, o.U, o.L = _ptr(res["r"]), _ptr(res["z"]), _ptr(res["U"]), _ptr(res["L"])
+    for f in ("ids", "child_of", "perm", "n_children", "child_z", "child_n", "child_off",
+              "child_u0", "child_l0", "r_mean", "expand_steps", "rollout_steps"):
+        setattr(o, f, _ptr(res[f]))
+    M = model(desc)
+    rc = lib().or_expand_leaf(C.byref(M), C.byref(rcfg), seed, step_idx,
+                              C.byref(_soa(desc, parent, n_par)), _ptr(parent_ids), _ptr(idx),
+                              n, depth, last_action, cap, C.byref(o))
+    if rc != 0:
+        raise ValueError("child capacity %d exceeded" % cap)
+    res["expand_steps"] = int(res["expand_steps"][0])
+    res["rollout_steps"] = int(res["rollout_steps"][0])
+    if per_pair:
+        sp = res["sprime"]
+        if desc["kind"] == 0:
+            sp["w"] = sp["w"].reshape(A, n)
+        else:
+            P = desc["n_peds"]
+            sp["s"], sp["car"] = sp["s"].reshape(A, n), sp["car"].reshape(A, n)
+            for f in ("px", "py", "goal"):
+                sp[f] = sp[f].reshape(P, A, n)
+    return res
+
+
+def rs_sense_threshold(d2: int) -> int:
+    return int(lib().or_rs_sense_threshold(d2))
+
+
+def take_states(desc: dict, st: dict, positions) -> dict:
+    """Sub-array of states at ``positions`` (for walking down a tree)."""
+    positions = np.asarray(positions, dtype=np.int64)
+    if desc["kind"] == 0:
+        return dict(w=np.ascontiguousarray(st["w"][positions]))
+    return dict(s=np.ascontiguousarray(st["s"][positions]),
+                car=np.ascontiguousarray(st["car"][positions]),
+                px=np.ascontiguousarray(st["px"][:, positions]),
+                py=np.ascontiguousarray(st["py"][:, positions]),
+                goal=np.ascontiguousarray(st["goal"][:, positions]))
+
+
+# --------------------------------------------------------------------------
+# Eq. 4: Bellman backup over a DESPOT tree, FP64
+# --------------------------------------------------------------------------
+class Node:
+    __slots__ = ("parent", "n", "u", "l", "u0", "l0", "actions")
+
+    def __init__(self, parent, n, u0, l0):
+        self.parent = parent
+        self.n = n
+        self.u0, self.l0 = float(u0), float(l0)
+        self.u, self.l = float(u0), float(l0)
+        self.actions = None  # list of (r_mean, [child nodes])
+
+
+def attach_children(desc, node: Node, res: dict) -> None:
+    """Create the action and observation branches of an expanded node (Eq. 11)."""
+    node.actions = []
+    for a in range(desc["n_actions"]):
+        kids = []
+        for c in range(int(res["n_children"][a])):
+            kids.append(Node(node, int(res["child_n"][a, c]), res["child_u0"][a, c],
+                             res["child_l0"][a, c]))
+        node.actions.append((float(res["r_mean"][a]), kids))
+
+
+def node_value(node: Node, gamma: float, which: str) -> float:
+    """V(b) = max_a { R(b,a) + gamma sum_z |Phi_b'|/|Phi_b| V(b') } (Eq. 4)."""
+    best = -np.inf
+    for r_mean, kids in node.actions:
+        q = r_mean + gamma * sum((k.n / node.n) * getattr(k, which) for k in kids)
+        best = max(best, q)
+    return best
+
+
+def backup(node: Node, gamma: float) -> None:
+    """Update u and l from ``node`` up to the root (Sec. III-A, Backup)."""
+    while node is not None:
+        if node.actions:
+            node.u = node_value(node, gamma, "u")
+            node.l = node_value(node, gamma, "l")
+        node = node.parent

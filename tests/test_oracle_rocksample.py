@@ -1,0 +1,188 @@
+"""Pins for the oracle's RockSample model (Sec. IV-A, one robot).
+
+Each test ties the oracle to something other than its own code: hand-built
+states with known outcomes, the closed-form value of moving east, the sensor
+accuracy law 0.5 + 0.5 2^(-d/20) as a binomial statistic, and the belief's
+prior as a frequency.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+SEED, STEP = 11, 0
+
+
+def rs_model(n, rocks):
+    rx = np.array([r[0] for r in rocks], np.int32)
+    ry = np.array([r[1] for r in rocks], np.int32)
+    return dict(kind=0, n=n, m=len(rocks), rock_x=rx, rock_y=ry, gamma=0.95,
+                start_x=0, start_y=n // 2, n_actions=5 + len(rocks))
+
+
+def one(desc, x, y, rocks, term=False, action=0, depth=0, ids=(0,)):
+    st = dict(w=oracle.rs_pack(x, y, np.array([rocks] * len(ids), bool).reshape(len(ids), -1),
+                               [term] * len(ids)))
+    out, r, z = oracle.step(desc, st, np.array(ids), action, depth, SEED, STEP)
+    return oracle.rs_unpack(out["w"]), r, z
+
+
+def test_moves_and_walls():
+    d = rs_model(5, [(2, 2)])
+    s, r, z = one(d, 1, 4, [0], action=0)  # north into the wall
+    assert (s["x"][0], s["y"][0], r[0], z[0]) == (1, 4, 0, 0)
+    s, r, z = one(d, 1, 0, [0], action=1)  # south into the wall
+    assert (s["x"][0], s["y"][0]) == (1, 0)
+    s, r, z = one(d, 0, 3, [0], action=3)  # west into the wall
+    assert (s["x"][0], s["y"][0]) == (0, 3)
+    s, r, z = one(d, 1, 3, [0], action=0)
+    assert (s["x"][0], s["y"][0]) == (1, 4)
+    s, r, z = one(d, 1, 3, [0], action=2)
+    assert (s["x"][0], s["y"][0], s["term"][0]) == (2, 3, 0)
+
+
+def test_exit_east_is_rewarded_and_terminal():
+    d = rs_model(5, [(2, 2)])
+    s, r, z = one(d, 4, 1, [1], action=2)
+    assert r[0] == 10.0 and s["term"][0] == 1 and z[0] == 0
+    # terminal states are absorbing: no reward, no observation, no change
+    for a in range(d["n_actions"]):
+        s2, r2, z2 = one(d, 4, 1, [1], term=True, action=a)
+        assert r2[0] == 0 and z2[0] == 0 and s2["term"][0] == 1 and s2["rocks"][0] == 1
+
+
+def test_sample_good_bad_empty():
+    d = rs_model(5, [(2, 2), (3, 1)])
+    s, r, z = one(d, 2, 2, [1, 1], action=4)
+    assert r[0] == 10.0 and s["rocks"][0] == 0b10  # sampled rock turns bad
+    s, r, z = one(d, 2, 2, [0, 1], action=4)
+    assert r[0] == -10.0 and s["rocks"][0] == 0b10
+    s, r, z = one(d, 1, 2, [1, 1], action=4)  # no rock here
+    assert r[0] == 0.0 and s["rocks"][0] == 0b11
+
+
+def test_sense_at_zero_distance_is_exact():
+    d = rs_model(5, [(2, 2)])
+    ids = np.arange(2000)
+    for q in (0, 1):
+        s, r, z = one(d, 2, 2, [q], action=5, ids=ids)
+        assert np.all(z == (1 if q else 2)) and np.all(r == 0)
+
+
+def test_sense_threshold_law():
+    # floor(acc * 2^32) with acc = 0.5 + 0.5 * 2^(-d/20): checked through
+    # exact identities of the law rather than by re-evaluating it
+    assert oracle.rs_sense_threshold(0) == 2**32
+    thr = [oracle.rs_sense_threshold(d2) for d2 in range(0, 800)]
+    assert all(a >= b for a, b in zip(thr, thr[1:]))  # accuracy decays with distance
+    assert all(t > 2**31 for t in thr)  # never worse than a coin flip
+    # at d = 20 the excess accuracy has halved: acc = 0.75
+    assert abs(oracle.rs_sense_threshold(400) - 0.75 * 2**32) <= 1
+    # at d = 40 it has halved twice: acc = 0.625
+    assert abs(oracle.rs_sense_threshold(1600) - 0.625 * 2**32) <= 1
+
+
+@pytest.mark.parametrize("d2", [1, 2, 5, 13, 25, 50, 98, 200, 400])
+def test_sense_accuracy_frequency(d2):
+    # binomial frequency of a correct reading over many scenario ids
+    cells = [(x, y) for x in range(21) for y in range(21) if x * x + y * y == d2]
+    x, y = cells[0]
+    d = rs_model(21, [(0, 0)])
+    K = 200000
+    ids = np.arange(K)
+    s, r, z = one(d, x, y, [1], action=5, depth=3, ids=ids)
+    p = 0.5 + 0.5 * 2 ** (-np.sqrt(d2) / 20)
+    frac = np.mean(z == 1)
+    assert abs(frac - p) < 5 * np.sqrt(p * (1 - p) / K)
+
+
+def test_common_random_numbers_across_actions():
+    # all sense actions at a depth read the same word: two rocks at the same
+    # distance, with equal quality, give identical readings scenario by scenario
+    d = rs_model(9, [(4, 0), (4, 8)])
+    ids = np.arange(5000)
+    s1, r1, z1 = one(d, 4, 4, [1, 1], action=5, depth=2, ids=ids)
+    s2, r2, z2 = one(d, 4, 4, [1, 1], action=6, depth=2, ids=ids)
+    assert np.array_equal(z1, z2)
+    _, _, z3 = one(d, 4, 4, [1, 1], action=5, depth=3, ids=ids)
+    assert not np.array_equal(z1, z3)  # a different depth draws new numbers
+
+
+def test_sample_scenarios_prior_frequency():
+    d = W.rocksample_model(7, 8, 3)
+    p = np.array([0.0, 1.0, 0.5, 0.1, 0.9, 0.3, 0.7, 0.5])
+    K = 100000
+    st = oracle.sample_scenarios(d, dict(x=0, y=3, p=p), K, 5, 2)
+    u = oracle.rs_unpack(st["w"])
+    assert np.all(u["x"] == 0) and np.all(u["y"] == 3) and np.all(u["term"] == 0)
+    bits = (u["rocks"][:, None] >> np.arange(8)) & 1
+    frac = bits.mean(0)
+    sd = np.sqrt(p * (1 - p) / K) + 1e-12
+    assert np.all(np.abs(frac - p) <= 5 * sd)
+    # rocks are drawn independently: correlation of two p=0.5 rocks ~ 0
+    c = np.corrcoef(bits[:, 2], bits[:, 7])[0, 1]
+    assert abs(c) < 5 / np.sqrt(K)
+
+
+def test_rs7_root_closed_form():
+    g = json.load(open(os.path.join(GOLD, "rs7_root_closed_form.json")))
+    for model_seed in range(1, 11):
+        d = W.rocksample_model(7, 8, model_seed)
+        st = oracle.sample_scenarios(d, W.rocksample_belief(d), 100, model_seed, 0)
+        res = oracle.expand_leaf(d, oracle.cfg(0, 30), st, np.arange(100), np.arange(100), 0, -1,
+                                 model_seed, 0)
+        A = d["n_actions"]
+        for a in range(A):
+            want = g["l0_east_child"] if a == 2 else g["l0_other_child"]
+            nc = res["n_children"][a]
+            assert np.allclose(res["child_l0"][a, :nc], want, rtol=1e-12, atol=0)
+            assert res["r_mean"][a] == 0.0
+        assert res["rollout_steps"] == g["root_rollout_steps"]
+        assert res["expand_steps"] == g["root_expand_steps"]
+        root = oracle.Node(None, 100, 0.0, 0.0)
+        oracle.attach_children(d, root, res)
+        oracle.backup(root, d["gamma"])
+        assert abs(root.l - g["root_lower_bound_after_backup"]) < 1e-12
+
+
+def test_upper_bound_closed_form():
+    d = rs_model(7, [(3, 3), (5, 1)])
+    st = dict(w=oracle.rs_pack(2, 1, np.array([[1, 1], [1, 0], [0, 0]], bool), [0, 0, 0]))
+    U, L, steps = oracle.rollout_bounds(d, oracle.cfg(0, 100), st, np.arange(3), 4, SEED, STEP)
+    g = 0.95
+    assert np.isclose(U[0], 10 * g ** 3 + 10 * g ** 3 + 10 * g ** 4, rtol=1e-14)
+    assert np.isclose(U[1], 10 * g ** 3 + 10 * g ** 4, rtol=1e-14)
+    assert np.isclose(U[2], 10 * g ** 4, rtol=1e-14)
+    assert np.allclose(L, 10 * g ** 4, rtol=1e-14) and np.all(steps == 5)
+
+
+def test_rollout_horizon_truncation():
+    d = rs_model(7, [])
+    st = dict(w=oracle.rs_pack(0, 3, np.zeros((1, 0), bool), [0]))
+    # depth cap D: steps at depths d0 .. D-1 only
+    U, L, steps = oracle.rollout_bounds(d, oracle.cfg(0, 1000, max_depth=10), st, [0], 5, 1, 0)
+    assert steps[0] == 5 and L[0] == 0.0
+    U, L, steps = oracle.rollout_bounds(d, oracle.cfg(0, 1000, max_depth=12), st, [0], 5, 1, 0)
+    assert steps[0] == 7 and np.isclose(L[0], 10 * 0.95 ** 6)
+    U, L, steps = oracle.rollout_bounds(d, oracle.cfg(0, 3), st, [0], 5, 1, 0)
+    assert steps[0] == 3 and L[0] == 0.0
+
+
+def test_random_policy_draws():
+    # from the east edge of an empty grid (5 actions), a one-step random
+    # rollout earns 10 exactly when the drawn action is east: the action is
+    # word 0 of the POLICY block at (id, depth), reduced mod |A|
+    d = rs_model(6, [])
+    K = 50000
+    st = dict(w=oracle.rs_pack(5, 2, np.zeros((K, 0), bool), np.zeros(K, bool)))
+    U, L, steps = oracle.rollout_bounds(d, oracle.cfg(2, 1), st, np.arange(K), 7, 3, 1)
+    assert np.all(steps == 1)
+    ctr = np.stack([np.arange(K), np.full(K, 7), np.zeros(K), np.full(K, 2)], 1)
+    a = oracle.philox(ctr, (3, 1))[:, 0] % 5
+    assert np.array_equal(L > 0, a == 2)
+    assert abs(L.mean() - 2.0) < 5 * np.sqrt(100 * 0.2 * 0.8 / K)
