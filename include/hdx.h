@@ -1,0 +1,255 @@
+/*
+ * hdx -- DESPOT leaf-node expansion on AMD Instinct MI355X (gfx950).
+ *
+ * A C ABI over hand-written HIP kernels for the data-parallel step of
+ * HyP-DESPOT (Cai, Luo, Hsu, Lee; arXiv:1802.06215): a leaf of the DESPOT
+ * tree is expanded one level for every action and every scenario, scenarios
+ * are grouped into child nodes by observation, and each child's initial
+ * upper and lower bounds are set from a heuristic and from default-policy
+ * rollouts (Sec. III-D, Eq. 10-13).  The CPU side of the method -- creating
+ * nodes and the Bellman backup of Eq. 4 -- is here too, as host code.
+ *
+ * Conventions
+ *  - Every call returns an hdx_status; no exception crosses the ABI.
+ *  - "device" pointers are HIP device memory (for example from
+ *    torch.Tensor.data_ptr() of a CUDA/ROCm tensor); "host" pointers are
+ *    ordinary process memory.  The caller owns every buffer it passes.
+ *  - Device work is enqueued on the given stream (a hipStream_t; NULL = the
+ *    default stream) and is asynchronous: output buffers are valid once the
+ *    stream has reached the call.  Input buffers must stay valid until then.
+ *  - One context may be used from several host threads if each passes its
+ *    own stream; model handles are read-only after upload.
+ *  - Per-call host work allocates nothing once a context has seen the
+ *    largest batch it will be given (descriptor staging grows on demand).
+ *
+ * Scenario states: struct of arrays ("hdx_states"), one element per scenario
+ *  - RockSample: w[k] packs x in bits 0-4, y in bits 5-9, rock i's quality
+ *    (1 = good) in bit 10+i, terminal in bit 30.
+ *  - Crowd driving: s[k] car position (m) along the path; car[k] = speed
+ *    level (bits 0-7, speed 0.5 m/s per level) | terminal (bit 8);
+ *    px/py/goal are [pedestrian][stride] arrays (FP32 metres and the index
+ *    of the pedestrian's goal point), stride >= number of scenarios.
+ *
+ * Random numbers (the scenario's phi = (s0, numbers), Sec. III-A): one
+ * Philox4x32-10 stream per scenario id with key (seed, step) and counter
+ * (scenario id, absolute depth, block, tag); tag 0 = model step, 1 = initial
+ * state, 2 = rollout policy.  All actions at one depth see the same numbers.
+ */
+#ifndef HDX_H
+#define HDX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hdx_status;
+#define HDX_OK 0
+#define HDX_E_INVALID (-1)     /* bad argument or null pointer */
+#define HDX_E_DEVICE (-2)      /* a HIP call failed; see hdx_last_error */
+#define HDX_E_NOMEM (-3)       /* device or pinned allocation failed */
+#define HDX_E_SHAPE (-4)       /* sizes outside the supported range */
+#define HDX_E_CAPACITY (-5)    /* child table too small for the leaf */
+#define HDX_E_UNSUPPORTED (-6) /* model kind or option not supported */
+
+#define HDX_ROCKSAMPLE 0
+#define HDX_PEDNAV 1
+
+#define HDX_MAX_ROCKS 20
+#define HDX_MAX_GRID 31
+#define HDX_MAX_PEDS 32
+#define HDX_MAX_GOALS 8
+#define HDX_MAX_LEAF_SCENARIOS 2048 /* scenarios of one leaf in one tile */
+#define HDX_MAX_HORIZON 4096        /* longest rollout (discount table size) */
+
+#define HDX_POLICY_DEFAULT 0 /* RockSample: move east; driving: brake for a pedestrian ahead, else accelerate */
+#define HDX_POLICY_CONST 1   /* always const_action */
+#define HDX_POLICY_RANDOM 2  /* uniform action per step from tag-2 numbers */
+
+typedef struct hdx_ctx hdx_ctx;
+typedef struct hdx_model hdx_model;
+typedef struct hdx_tree hdx_tree;
+typedef void *hdx_stream; /* hipStream_t */
+
+/* Model description (host memory; may be freed after hdx_upload_model).
+ * RockSample (Sec. IV-A, one robot): grid x grid cells, n_rocks rocks at
+ * (rock_x[i], rock_y[i]); actions 0 north (y+1), 1 south, 2 east (x+1),
+ * 3 west, 4 sample, 5+i sense rock i; rewards +10 good sample, -10 bad
+ * sample, +10 exit east (terminal); sensor accuracy 0.5 + 0.5 2^(-d/20).
+ * Crowd driving (Sec. IV-A): straight path of path_len metres, n_levels
+ * speed levels, pedestrians walking at ped_speed to one of n_goals goal
+ * points with Gaussian heading noise sigma_h; actions 0 accelerate,
+ * 1 maintain, 2 decelerate, failing with probability p_fail. */
+typedef struct {
+    int32_t kind;     /* HDX_ROCKSAMPLE or HDX_PEDNAV */
+    int32_t n_actions;/* 5 + n_rocks, or 3 */
+    double gamma;     /* discount */
+    int32_t grid, n_rocks;
+    int32_t rock_x[HDX_MAX_ROCKS], rock_y[HDX_MAX_ROCKS];
+    int32_t n_peds, n_goals, n_levels, reserved;
+    float goal_x[HDX_MAX_GOALS], goal_y[HDX_MAX_GOALS];
+    float path_len, dt, ped_speed, sigma_h, coll_radius;
+    float r_collision, r_step, r_goal;
+    double p_fail;
+} hdx_model_desc;
+
+/* Belief to sample start states from (host memory). */
+typedef struct {
+    int32_t x, y;          /* RockSample: known robot cell */
+    const double *p_good;  /* RockSample: [n_rocks] P(rock i good) */
+    float s;               /* driving: car position */
+    int32_t level;         /* driving: speed level */
+    const float *px, *py;  /* driving: [n_peds] pedestrian positions */
+    const double *goal_p;  /* driving: [n_peds][n_goals] goal probabilities */
+} hdx_belief;
+
+/* Rollout configuration for the lower bound (Eq. 13).  A rollout from depth
+ * d0 runs at most min(max_steps, max_depth - d0) steps (max_depth < 0: no
+ * depth limit), stops at a terminal state, and has tail value 0. */
+typedef struct {
+    int32_t policy;       /* HDX_POLICY_* */
+    int32_t const_action; /* for HDX_POLICY_CONST */
+    int32_t max_steps;
+    int32_t max_depth;
+} hdx_rollout_cfg;
+
+typedef struct {
+    int32_t *w;
+    float *s;
+    int32_t *car;
+    float *px, *py;
+    uint8_t *goal;
+    int64_t stride;
+} hdx_states;
+
+/* One leaf to expand (Sec. III-D: gather, update, expand, bounds).  All
+ * array members are device pointers.  With A = the model's action count and
+ * n = number of the leaf's scenarios:
+ *   inputs
+ *     parent, parent_ids : the parent's states and scenario ids
+ *     idx[n]             : positions of the leaf's scenarios in the parent
+ *                          arrays, strictly ascending
+ *     depth              : the leaf's depth (root = 0); the update step uses
+ *                          depth-1, expansion depth, rollouts depth+1 on
+ *     last_action        : action from the parent, or -1 for a root (states
+ *                          are then taken as they are)
+ *     cap                : child slots per action in the child arrays; must
+ *                          be >= hdx_model_max_children(model, n)
+ *   outputs
+ *     states_out, ids_out[n] : the leaf's own states (materialised) and ids
+ *     perm[A][n]         : leaf positions grouped by child (children in
+ *                          ascending observation, positions ascending)
+ *     n_children[A]      : children per action (Eq. 11)
+ *     child_z, child_n, child_off [A][cap] : observation, scenario count and
+ *                          offset into perm[a] of each child
+ *     child_u0, child_l0 [A][cap] : initial bounds (Eq. 12, 13), FP32 means
+ *     r_mean[A]          : mean step reward per action (first term of Eq. 4)
+ *     steps[A][2]        : model steps on non-terminal states, in expansion
+ *                          and in rollouts
+ *   optional outputs (NULL to skip): sprime (stride >= A*n, element a*n+k),
+ *     r, z, U, L, child_of [A][n] per (action, scenario). */
+typedef struct {
+    const hdx_model *model;
+    uint32_t seed, step;     /* random-stream key */
+    hdx_rollout_cfg rollout;
+    hdx_states parent;
+    const uint32_t *parent_ids;
+    const int32_t *idx;
+    int32_t n, depth, last_action, cap;
+    hdx_states states_out;
+    uint32_t *ids_out;
+    int32_t *perm;
+    int32_t *n_children;
+    uint64_t *child_z;
+    int32_t *child_n, *child_off;
+    float *child_u0, *child_l0;
+    float *r_mean;
+    int64_t *steps;
+    hdx_states sprime;
+    float *r;
+    uint64_t *z;
+    float *U, *L;
+    int32_t *child_of;
+} hdx_leaf;
+
+const char *hdx_version(void);
+
+/* Context on HIP device `device`.  The library owns *out; release it with
+ * hdx_fini.  Errors: HDX_E_DEVICE if the device cannot be used. */
+hdx_status hdx_init(int32_t device, hdx_ctx **out);
+hdx_status hdx_fini(hdx_ctx *ctx);
+/* Text of the last error on this context (valid until the next call). */
+const char *hdx_last_error(const hdx_ctx *ctx);
+
+/* Upload a model (Sec. III-A: the simulative model g).  Builds the device
+ * tables (sensor thresholds, discount powers) from the description.  The
+ * library owns *out; free it with hdx_free_model after the last use on any
+ * stream.  Errors: HDX_E_SHAPE for sizes beyond the HDX_MAX_* limits,
+ * HDX_E_UNSUPPORTED for an unknown kind. */
+hdx_status hdx_upload_model(hdx_ctx *ctx, const hdx_model_desc *desc, hdx_model **out);
+hdx_status hdx_free_model(hdx_ctx *ctx, hdx_model *model);
+int32_t hdx_model_actions(const hdx_model *model);
+/* Largest child count one action can produce for a leaf of n scenarios. */
+int32_t hdx_model_max_children(const hdx_model *model, int32_t n);
+
+/* sample_scenarios (Sec. III-A): K start states drawn from the belief into
+ * `out` (device), scenario k using counter (k, 0, block, 1).  Errors:
+ * HDX_E_SHAPE for K <= 0 or K > 2^24. */
+hdx_status hdx_sample_scenarios(hdx_ctx *ctx, const hdx_model *model, const hdx_belief *belief,
+                                int32_t K, uint32_t seed, uint32_t step, hdx_states out,
+                                hdx_stream stream);
+
+/* expand_leaf (Sec. III-D, Eq. 10-13): expand n_leaves leaves (host array
+ * of descriptors pointing at device buffers) in one launch; leaves may use
+ * different models, sizes and rollout settings.  Results are written as
+ * described for hdx_leaf and do not depend on how leaves are batched or on
+ * the launch schedule.  Errors: HDX_E_SHAPE if a leaf has more than
+ * HDX_MAX_LEAF_SCENARIOS scenarios or a rollout longer than
+ * HDX_MAX_HORIZON, HDX_E_CAPACITY if cap is too small, HDX_E_INVALID for a
+ * missing required pointer; nothing is launched on error. */
+hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves,
+                           hdx_stream stream);
+
+/* rollout_bounds (Eq. 12, 13 per scenario): for each of n states (device),
+ * U = upper-bound heuristic and L = discounted default-policy rollout from
+ * depths[k]; steps[k] = model steps taken.  ids/depths/U/L/steps are
+ * device arrays of n elements. */
+hdx_status hdx_rollout_bounds(hdx_ctx *ctx, const hdx_model *model, const hdx_rollout_cfg *cfg,
+                              uint32_t seed, uint32_t step, hdx_states states,
+                              const uint32_t *ids, const int32_t *depths, int64_t n, float *U,
+                              float *L, int32_t *steps, hdx_stream stream);
+
+/* The raw Philox4x32-10 block function on device, for checking the random
+ * stream: out[i][0..3] = philox(ctr[i][0..3], key (k0, k1)). */
+hdx_status hdx_philox(hdx_ctx *ctx, const uint32_t *ctr, int64_t count, uint32_t k0, uint32_t k1,
+                      uint32_t *out, hdx_stream stream);
+
+/* ---- Host side of the method: DESPOT tree and backup (Sec. III-A) ------ */
+
+/* A tree whose root holds n_root scenarios with bounds (u0, l0).  Node 0 is
+ * the root.  The library owns *out; release with hdx_tree_destroy. */
+hdx_status hdx_tree_create(int32_t n_actions, double gamma, int32_t n_root, double u0, double l0,
+                           hdx_tree **out);
+hdx_status hdx_tree_destroy(hdx_tree *tree);
+/* Attach the action and observation branches of an expanded node from a
+ * host copy of its hdx_leaf outputs (Eq. 11): for action a, children
+ * c < n_children[a] with (child_z, child_n, child_u0, child_l0)[a*cap+c];
+ * r_mean[a].  Child node ids are assigned in (a, c) order starting at
+ * *first_child.  Errors: HDX_E_INVALID if the node already has children or
+ * the child counts do not sum to the node's scenario count. */
+hdx_status hdx_tree_add_children(hdx_tree *tree, int64_t node, const int32_t *n_children,
+                                 const uint64_t *child_z, const int32_t *child_n,
+                                 const float *child_u0, const float *child_l0,
+                                 const float *r_mean, int32_t cap, int64_t *first_child);
+/* backup (Eq. 4): recompute u and l of `node` and of every ancestor up to
+ * the root, V(b) = max_a { R(b,a) + gamma sum_z |Phi_b'|/|Phi_b| V(b') }. */
+hdx_status hdx_backup(hdx_tree *tree, int64_t node);
+hdx_status hdx_tree_bounds(const hdx_tree *tree, int64_t node, double *u, double *l);
+int64_t hdx_tree_size(const hdx_tree *tree);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDX_H */

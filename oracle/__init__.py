@@ -66,7 +66,7 @@ class _Soa(C.Structure):
 class _Out(C.Structure):
     _fields_ = [("states", _Soa), ("ids", C.c_void_p), ("sprime", _Soa),
                 ("r", C.c_void_p), ("z", C.c_void_p), ("U", C.c_void_p), ("L", C.c_void_p),
-                ("child_of", C.c_void_p), ("perm", C.c_void_p), ("n_children", C.c_void_p),
+                ("Labs", C.c_void_p), ("child_of", C.c_void_p), ("perm", C.c_void_p), ("n_children", C.c_void_p),
                 ("child_z", C.c_void_p), ("child_n", C.c_void_p), ("child_off", C.c_void_p),
                 ("child_u0", C.c_void_p), ("child_l0", C.c_void_p), ("r_mean", C.c_void_p),
                 ("expand_steps", C.c_void_p), ("rollout_steps", C.c_void_p)]
@@ -86,7 +86,7 @@ def lib():
                                     C.c_uint32, P, P, P]
         L.or_sample_scenarios.argtypes = [P, C.c_int32, C.c_uint32, C.c_uint32, C.c_int32,
                                           C.c_int32, P, C.c_float, C.c_int32, P, P, P, P]
-        L.or_rollout_bounds.argtypes = [P, P, C.c_uint32, C.c_uint32, P, P, P, C.c_int64, P, P, P]
+        L.or_rollout_bounds.argtypes = [P, P, C.c_uint32, C.c_uint32, P, P, P, C.c_int64, P, P, P, P]
         L.or_expand_leaf.argtypes = [P, P, C.c_uint32, C.c_uint32, P, P, P, C.c_int32, C.c_int32,
                                      C.c_int32, C.c_int32, P]
         L.or_expand_leaf.restype = C.c_int
@@ -238,17 +238,22 @@ def sample_scenarios(desc, belief, K, seed, step_idx):
     return out
 
 
-def rollout_bounds(desc, rcfg, states, ids, depths, seed, step_idx):
+def rollout_bounds(desc, rcfg, states, ids, depths, seed, step_idx, with_abs: bool = False):
+    """Upper bound and rollout value per state; with_abs also returns the
+    sum of absolute discounted rollout terms (a scale for FP tolerances)."""
     n = _check_states(desc, states)
     ids = np.ascontiguousarray(ids, dtype=np.uint32)
     depths = np.ascontiguousarray(np.broadcast_to(depths, (n,)), dtype=np.int32)
     U = np.zeros(n)
     L = np.zeros(n)
+    Labs = np.zeros(n)
     steps = np.zeros(n, np.int64)
     M = model(desc)
     lib().or_rollout_bounds(C.byref(M), C.byref(rcfg), seed, step_idx,
                             C.byref(_soa(desc, states, n)), _ptr(ids), _ptr(depths), n,
-                            _ptr(U), _ptr(L), _ptr(steps))
+                            _ptr(U), _ptr(L), _ptr(steps), _ptr(Labs))
+    if with_abs:
+        return U, L, steps, Labs
     return U, L, steps
 
 
@@ -280,9 +285,11 @@ def expand_leaf(desc, rcfg, parent, parent_ids, idx, depth, last_action, seed, s
     o.states = _soa(desc, res["states"], n)
     if per_pair:
         res.update(sprime=empty_states(desc, A * n), r=np.zeros((A, n), np.float32),
-                   z=np.zeros((A, n), np.uint64), U=np.zeros((A, n)), L=np.zeros((A, n)))
+                   z=np.zeros((A, n), np.uint64), U=np.zeros((A, n)), L=np.zeros((A, n)),
+                   Labs=np.zeros((A, n)))
         o.sprime = _soa(desc, res["sprime"], A * n)
         o.r, o.z, o.U, o.L = _ptr(res["r"]), _ptr(res["z"]), _ptr(res["U"]), _ptr(res["L"])
+        o.Labs = _ptr(res["Labs"])
     for f in ("ids", "child_of", "perm", "n_children", "child_z", "child_n", "child_off",
               "child_u0", "child_l0", "r_mean", "expand_steps", "rollout_steps"):
         setattr(o, f, _ptr(res[f]))

@@ -411,8 +411,9 @@ static int policy_action(const or_model *M, const or_rollout_cfg *C, const or_st
  * at a terminal state or after min(R, D - d0) steps; the tail heuristic past
  * the horizon is 0. */
 static double rollout(const or_model *M, const or_rollout_cfg *C, or_state st, uint32_t seed,
-                      uint32_t step, uint32_t id, int d0, int64_t *steps)
+                      uint32_t step, uint32_t id, int d0, int64_t *steps, double *abs_sum)
 {
+    double mag = 0.0;
     int n_roll = C->max_steps;
     if (C->max_depth >= 0 && C->max_depth - d0 < n_roll) n_roll = C->max_depth - d0;
     double value = 0.0;
@@ -423,8 +424,10 @@ static double rollout(const or_model *M, const or_rollout_cfg *C, or_state st, u
         uint64_t z;
         model_step(M, &st, a, seed, step, id, (uint32_t)(d0 + j), &r, &z);
         value += pow(M->gamma, j) * (double)r;
+        mag += pow(M->gamma, j) * fabs((double)r);
         *steps += 1;
     }
+    if (abs_sum) *abs_sum = mag;
     return value;
 }
 
@@ -492,14 +495,14 @@ void or_sample_scenarios(const or_model *M, int32_t K, uint32_t seed, uint32_t s
 /* Upper bound and rollout lower bound for each state of an array. */
 void or_rollout_bounds(const or_model *M, const or_rollout_cfg *C, uint32_t seed, uint32_t step,
                        const or_soa *in, const uint32_t *ids, const int32_t *depths, int64_t n,
-                       double *U, double *L, int64_t *steps)
+                       double *U, double *L, int64_t *steps, double *Labs)
 {
     for (int64_t k = 0; k < n; k++) {
         or_state st;
         load_state(M, in, k, &st);
         int64_t cnt = 0;
         U[k] = model_upper(M, &st);
-        L[k] = rollout(M, C, st, seed, step, ids[k], depths[k], &cnt);
+        L[k] = rollout(M, C, st, seed, step, ids[k], depths[k], &cnt, Labs ? &Labs[k] : NULL);
         steps[k] = cnt;
     }
 }
@@ -524,6 +527,7 @@ typedef struct {
     float *r;           /* [A][n] step rewards */
     uint64_t *z;        /* [A][n] observations */
     double *U, *L;      /* [A][n] per-scenario bounds */
+    double *Labs;       /* [A][n] sum of |discounted rollout terms| (tolerance scale) */
     int32_t *child_of;  /* [A][n] child index of each scenario */
     int32_t *perm;      /* [A][n] leaf positions grouped by child */
     int32_t *n_children;/* [A] */
@@ -582,7 +586,8 @@ int or_expand_leaf(const or_model *M, const or_rollout_cfg *C, uint32_t seed, ui
             model_step(M, &st, a, seed, step, ids[k], (uint32_t)depth, &r, &z);
             r_sum += (double)r;
             U[k] = model_upper(M, &st);
-            L[k] = rollout(M, C, st, seed, step, ids[k], depth + 1, &roll_steps);
+            double mag = 0.0;
+            L[k] = rollout(M, C, st, seed, step, ids[k], depth + 1, &roll_steps, &mag);
             pairs[k].z = z;
             pairs[k].k = k;
             int64_t pk = (int64_t)a * n + k;
@@ -591,6 +596,7 @@ int or_expand_leaf(const or_model *M, const or_rollout_cfg *C, uint32_t seed, ui
             if (out->z) out->z[pk] = z;
             if (out->U) out->U[pk] = U[k];
             if (out->L) out->L[pk] = L[k];
+            if (out->Labs) out->Labs[pk] = mag;
         }
         if (out->r_mean) out->r_mean[a] = n > 0 ? r_sum / n : 0.0;
 

@@ -1,0 +1,177 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hdx.h"
+
+namespace hdx {
+
+constexpr int kMaxRocks = HDX_MAX_ROCKS;
+constexpr int kMaxGrid = HDX_MAX_GRID;
+constexpr int kMaxPeds = HDX_MAX_PEDS;
+constexpr int kMaxGoals = HDX_MAX_GOALS;
+constexpr int kHorizon = HDX_MAX_HORIZON;
+constexpr int kSenseEntries = 2 * (kMaxGrid - 1) * (kMaxGrid - 1) + 1;  // squared distances
+constexpr int kMaxLeaf = HDX_MAX_LEAF_SCENARIOS;
+
+enum : uint32_t { kTagStep = 0, kTagInit = 1, kTagPolicy = 2 };
+constexpr uint64_t kEmptyKey = ~0ull;
+constexpr uint64_t kPedTerminalObs = ~0ull;
+
+// Model parameters and tables as the kernels read them (device memory, one
+// per uploaded model).  Derived constants are computed once on the host.
+struct DevModel {
+    int32_t kind, n_actions;
+    // RockSample
+    int32_t grid, n_rocks;
+    int32_t rock_x[kMaxRocks], rock_y[kMaxRocks];
+    int8_t rock_at[kMaxGrid * kMaxGrid];  // rock index at cell x + y*grid, -1 if none
+    uint8_t pad0[3];
+    uint32_t sense_thr_m1[kSenseEntries];  // floor(acc(d) 2^32) - 1, by squared distance
+    // crowd driving
+    int32_t n_peds, n_goals, n_levels, pad1;
+    float goal_x[kMaxGoals], goal_y[kMaxGoals];
+    float path_len, dt, step_len, half_sigma, coll_r2, reach, ih_scale;
+    float r_collision, r_step, r_goal;
+    uint64_t fail_thr;  // action fails iff word < fail_thr
+    // discount powers gamma^j rounded to FP32
+    float gpow[kHorizon];
+};
+
+struct StatesPtr {
+    int32_t *w;
+    float *s;
+    int32_t *car;
+    float *px, *py;
+    uint8_t *goal;
+    int64_t stride;
+};
+
+// One leaf as the expansion kernel sees it (built on the host from hdx_leaf).
+struct LeafTask {
+    const DevModel *model;
+    int32_t kind, n_actions;
+    uint32_t k0, k1;
+    int32_t policy, const_action, max_steps, max_depth;
+    StatesPtr parent;
+    const uint32_t *parent_ids;
+    const int32_t *idx;
+    int32_t n, depth, last_action, cap;
+    StatesPtr out;
+    uint32_t *ids_out;
+    int32_t *perm;
+    int32_t *n_children;
+    uint64_t *child_z;
+    int32_t *child_n, *child_off;
+    float *child_u0, *child_l0;
+    float *r_mean;
+    int64_t *steps;
+    StatesPtr sprime;
+    float *r;
+    uint64_t *z;
+    float *U, *L;
+    int32_t *child_of;
+};
+
+struct Tile {
+    int32_t leaf, action;
+};
+
+// Work queue of the persistent launch; the last workgroup to leave resets
+// it, so a captured graph can be replayed without a separate clear.
+struct TileQueue {
+    int32_t next, done;
+};
+
+// Launch schedule of the expansion kernel; results never depend on it.
+struct Schedule {
+    int32_t threads;     // workgroup size, a multiple of 64
+    int32_t persistent;  // 0: one workgroup per tile; >0: that many workgroups per CU
+    int32_t xcd_remap;   // keep consecutive tiles (one leaf) on one XCD
+};
+
+// LDS carve-up of one tile, the same on host (for the launch size) and device.
+struct LdsLayout {
+    uint32_t zkey, dslot, ubuf, lbuf, rbuf, child, tab, pos, perm, nc, off, cnt, misc, total;
+    int32_t np, p2, h, table_cap;
+};
+
+__host__ __device__ inline int32_t pow2_at_least(int32_t v) {
+    int32_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+__host__ __device__ inline LdsLayout make_layout(int32_t np) {
+    LdsLayout L;
+    if (np < 1) np = 1;
+    L.np = np;
+    L.p2 = pow2_at_least(np) < 64 ? 64 : pow2_at_least(np);
+    L.h = pow2_at_least(2 * np) < 64 ? 64 : pow2_at_least(2 * np);
+    const int32_t nchunks = (np + 63) / 64;
+    int32_t tcap = nchunks * np;
+    if (tcap > 8192) tcap = 8192;
+    L.table_cap = tcap;
+    uint32_t o = 0;
+    auto take = [&](uint32_t bytes) {
+        uint32_t at = o;
+        o += (bytes + 15u) & ~15u;
+        return at;
+    };
+    L.zkey = take(8u * L.p2);
+    L.dslot = take(4u * L.p2);
+    L.ubuf = take(4u * np);
+    L.lbuf = take(4u * np);
+    L.rbuf = take(4u * np);
+    L.child = take(4u * np);
+    L.tab = take(8u * L.h + 8u);
+    L.pos = take(4u * np);
+    L.perm = take(4u * L.p2);
+    L.nc = take(4u * L.p2);
+    L.off = take(4u * L.p2);
+    L.cnt = take(4u * L.table_cap);
+    L.misc = take(64 + 4u * 64);
+    L.total = o;
+    return L;
+}
+
+// Kernel launchers (kernels.hip).
+hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, int32_t n_tiles,
+                         TileQueue *d_queue, int32_t n_max, int32_t has_ped, int32_t ped_max,
+                         int32_t has_rs, const Schedule &sch, int32_t n_cu, hipStream_t stream);
+
+struct SampleArgs {
+    const DevModel *model;
+    uint32_t k0, k1;
+    int32_t K;
+    int32_t x0, y0;
+    uint64_t rock_thr[kMaxRocks];
+    float s0;
+    int32_t level0;
+    float px0[kMaxPeds], py0[kMaxPeds];
+    uint64_t goal_thr[kMaxPeds][kMaxGoals];  // cumulative thresholds
+    StatesPtr out;
+};
+hipError_t launch_sample(const SampleArgs &args, hipStream_t stream);
+
+struct BoundsArgs {
+    const DevModel *model;
+    uint32_t k0, k1;
+    int32_t policy, const_action, max_steps, max_depth;
+    StatesPtr states;
+    const uint32_t *ids;
+    const int32_t *depths;
+    int64_t n;
+    float *U, *L;
+    int32_t *steps;
+};
+hipError_t launch_bounds(const BoundsArgs &args, int32_t kind, int32_t n_peds, hipStream_t stream);
+
+hipError_t launch_philox(const uint32_t *ctr, int64_t count, uint32_t k0, uint32_t k1, uint32_t *out,
+                         hipStream_t stream);
+
+int32_t max_dynamic_lds();
+
+}  // namespace hdx

@@ -1,0 +1,620 @@
+// HIP kernels for gfx950: scenario sampling, fused leaf expansion (update,
+// expand, group by observation, bounds, rollouts, reductions) and
+// stand-alone rollout bounds.
+//
+// Leaf expansion (Sec. III-D, Eq. 10-13) runs one workgroup per tile, a tile
+// being one (leaf, action) pair.  Inside a tile every lane owns scenarios
+// k = tid, tid + T, ...: it gathers the parent state (struct-of-arrays,
+// coalesced along k), applies the last action, steps the tile's action,
+// evaluates the upper-bound heuristic and runs the default-policy rollout in
+// registers.  Observations are then grouped in LDS: an open-addressing hash
+// collects the distinct observations, which are sorted (one wavefront
+// bitonic network, or an LDS bitonic network past 64 keys) to give the
+// children their canonical order; scenario positions inside each child
+// come from wavefront ballots per 64-scenario chunk and a prefix over
+// chunks (a segmented sort of the scenarios by child, stable in scenario
+// order).  Per-child sums of U and L are wavefront segmented scans (shuffle
+// based) over 64-aligned chunks of the grouped order, then chunk partials
+// in order, so the floating-point order depends only on the data, never on
+// the workgroup size or the schedule.
+#include "models.hpp"
+
+namespace hdx {
+
+namespace {
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ uint64_t mix_key(uint64_t z) {
+    return (z * 0x9E3779B97F4A7C15ull) >> 32;
+}
+
+// Lexicographic (key, val) compare-exchange used by both sorting networks.
+__device__ __forceinline__ bool pair_less(uint64_t ka, uint32_t va, uint64_t kb, uint32_t vb) {
+    return ka < kb || (ka == kb && va < vb);
+}
+
+// Bitonic sort of up to 64 (key, val) pairs held one per lane of a wavefront.
+__device__ void wave_sort_pairs(uint64_t *keys, uint32_t *vals, int count) {
+    const int lane = lane_id();
+    uint64_t k = lane < count ? keys[lane] : kEmptyKey;
+    uint32_t v = lane < count ? vals[lane] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const uint32_t klo = __shfl_xor((uint32_t)k, stride, 64);
+            const uint32_t khi = __shfl_xor((uint32_t)(k >> 32), stride, 64);
+            const uint32_t ov = __shfl_xor(v, stride, 64);
+            const uint64_t ok = ((uint64_t)khi << 32) | klo;
+            const bool ascending = (lane & size) == 0;
+            const bool lower = (lane & stride) == 0;
+            const bool other_smaller = pair_less(ok, ov, k, v);
+            // the lower lane of an ascending pair keeps the smaller element
+            const bool take = (lower == ascending) ? other_smaller : !other_smaller;
+            if (take) {
+                k = ok;
+                v = ov;
+            }
+        }
+    }
+    if (lane < count) {
+        keys[lane] = k;
+        vals[lane] = v;
+    }
+}
+
+// Bitonic sort in LDS of p (a power of two) (key, val) pairs.
+__device__ void block_sort_pairs(uint64_t *keys, uint32_t *vals, int p) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int size = 2; size <= p; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < p; i += nt) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool ascending = (i & size) == 0;
+                    const bool swap = ascending ? pair_less(keys[j], vals[j], keys[i], vals[i])
+                                                : pair_less(keys[i], vals[i], keys[j], vals[j]);
+                    if (swap) {
+                        const uint64_t tk = keys[i];
+                        keys[i] = keys[j];
+                        keys[j] = tk;
+                        const uint32_t tv = vals[i];
+                        vals[i] = vals[j];
+                        vals[j] = tv;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Bitonic sort in LDS of p (a power of two) uint32 keys.
+__device__ void block_sort_u32(uint32_t *keys, int p) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int size = 2; size <= p; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < p; i += nt) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool ascending = (i & size) == 0;
+                    const uint32_t a = keys[i], b = keys[j];
+                    if (ascending ? (b < a) : (a < b)) {
+                        keys[i] = b;
+                        keys[j] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Exclusive prefix sum of len ints, in place, by the whole workgroup.
+// scratch holds one int per wavefront plus one.
+__device__ void block_exclusive_scan(int32_t *a, int len, int32_t *scratch) {
+    const int tid = threadIdx.x, nt = blockDim.x, lane = lane_id(), wid = tid >> 6, nw = nt >> 6;
+    const int per = (len + nt - 1) / nt;
+    const int lo = tid * per, hi = min(lo + per, len);
+    int32_t local = 0;
+    for (int i = lo; i < hi; ++i) local += a[i];
+    int32_t incl = local;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) scratch[wid] = incl;
+    __syncthreads();
+    if (tid == 0) {
+        int32_t run = 0;
+        for (int w = 0; w < nw; ++w) {
+            const int32_t t = scratch[w];
+            scratch[w] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+    int32_t run = scratch[wid] + incl - local;
+    for (int i = lo; i < hi; ++i) {
+        const int32_t t = a[i];
+        a[i] = run;
+        run += t;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ bool has_states(const StatesPtr &S) { return S.w != nullptr || S.s != nullptr; }
+
+// One (leaf, action) tile.
+template <class Ops>
+__device__ void run_tile(const LeafTask &T, const int a, unsigned char *lds, const LdsLayout &Ly) {
+    const DevModel &M = *T.model;
+    const int n = T.n;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = lane_id(), wid = tid >> 6, nw = nt >> 6;
+    uint64_t *zk = (uint64_t *)(lds + Ly.zkey);
+    uint32_t *dslot = (uint32_t *)(lds + Ly.dslot);
+    float *ub = (float *)(lds + Ly.ubuf);
+    float *lb = (float *)(lds + Ly.lbuf);
+    float *rb = (float *)(lds + Ly.rbuf);
+    int32_t *child = (int32_t *)(lds + Ly.child);
+    uint64_t *tab = (uint64_t *)(lds + Ly.tab);
+    int32_t *pos = (int32_t *)(lds + Ly.pos);
+    int32_t *permb = (int32_t *)(lds + Ly.perm);
+    int32_t *nc = (int32_t *)(lds + Ly.nc);
+    int32_t *off = (int32_t *)(lds + Ly.off);
+    int32_t *cnt = (int32_t *)(lds + Ly.cnt);
+    int32_t *misc = (int32_t *)(lds + Ly.misc);             // [0] distinct count, [1] sentinel seen
+    unsigned long long *stepc = (unsigned long long *)(misc + 4);  // expansion, rollout steps
+    float *chunk_r = (float *)(misc + 8);                     // per-chunk reward sums (<= 32)
+    int32_t *scan_scratch = misc + 48;
+    const int H = Ly.h;
+
+    for (int h = tid; h < H; h += nt) tab[h] = kEmptyKey;
+    if (tid == 0) {
+        misc[0] = 0;
+        misc[1] = 0;
+        stepc[0] = 0;
+        stepc[1] = 0;
+    }
+
+    RolloutParams RP;
+    RP.k0 = T.k0;
+    RP.k1 = T.k1;
+    RP.policy = T.policy;
+    RP.const_action = T.const_action;
+    RP.max_steps = T.max_steps;
+    RP.max_depth = T.max_depth;
+    RP.n_actions = T.n_actions;
+    const bool write_leaf = (a == 0);
+    const bool pair_out = has_states(T.sprime);
+
+    // -- gather + update + expand + bounds + rollouts (Eq. 10, 12, 13) ------
+    int my_exp = 0, my_roll = 0;
+    for (int k = tid; k < n; k += nt) {
+        const int p = T.idx[k];
+        const uint32_t id = T.parent_ids[p];
+        typename Ops::State st;
+        Ops::load(M, T.parent, p, st);
+        if (T.last_action >= 0) {
+            float r0;
+            uint64_t z0;
+            Ops::template step<false>(M, st, T.last_action, id, (uint32_t)(T.depth - 1), T.k0, T.k1, r0, z0);
+        }
+        if (write_leaf) {
+            Ops::store(M, T.out, k, st);
+            T.ids_out[k] = id;
+        }
+        my_exp += Ops::terminal(st) ? 0 : 1;
+        float r;
+        uint64_t z;
+        Ops::template step<true>(M, st, a, id, (uint32_t)T.depth, T.k0, T.k1, r, z);
+        const float U = Ops::upper(M, st);
+        const int64_t pk = (int64_t)a * n + k;
+        if (pair_out) Ops::store(M, T.sprime, pk, st);
+        int ns = 0;
+        const float L = rollout<Ops>(M, RP, st, id, T.depth + 1, ns);
+        my_roll += ns;
+        zk[k] = z;
+        ub[k] = U;
+        lb[k] = L;
+        rb[k] = r;
+        if (T.r) T.r[pk] = r;
+        if (T.z) T.z[pk] = z;
+        if (T.U) T.U[pk] = U;
+        if (T.L) T.L[pk] = L;
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        my_exp += __shfl_xor(my_exp, d, 64);
+        my_roll += __shfl_xor(my_roll, d, 64);
+    }
+    __syncthreads();  // LDS init above is visible from here on
+    if (lane == 0) {
+        atomicAdd(&stepc[0], (unsigned long long)my_exp);
+        atomicAdd(&stepc[1], (unsigned long long)my_roll);
+    }
+
+    // -- LDS hash of the observations ----------------------------------------
+    for (int k = tid; k < n; k += nt) {
+        const uint64_t z = zk[k];
+        int slot;
+        if (z == kEmptyKey) {
+            slot = H;
+            misc[1] = 1;
+        } else {
+            int h = (int)(mix_key(z) & (uint64_t)(H - 1));
+            for (;;) {
+                const unsigned long long old = atomicCAS((unsigned long long *)&tab[h], kEmptyKey, z);
+                if (old == kEmptyKey || old == z) break;
+                h = (h + 1) & (H - 1);
+            }
+            slot = h;
+        }
+        child[k] = slot;
+    }
+    __syncthreads();
+
+    // -- distinct observations, sorted ascending -----------------------------
+    uint64_t *dkey = zk;
+    for (int h = tid; h <= H; h += nt) {
+        const bool occupied = (h < H) ? (tab[h] != kEmptyKey) : (misc[1] != 0);
+        if (occupied) {
+            const int i = atomicAdd(&misc[0], 1);
+            dkey[i] = (h < H) ? tab[h] : kEmptyKey;
+            dslot[i] = (uint32_t)h;
+        }
+    }
+    __syncthreads();
+    const int D = misc[0];
+    if (D <= 64) {
+        if (wid == 0) wave_sort_pairs(dkey, dslot, D);
+        __syncthreads();
+    } else {
+        const int p = pow2_at_least(D);
+        for (int i = D + tid; i < p; i += nt) {
+            dkey[i] = kEmptyKey;
+            dslot[i] = 0xFFFFFFFFu;
+        }
+        __syncthreads();
+        block_sort_pairs(dkey, dslot, p);
+    }
+
+    // -- child index of each scenario -----------------------------------------
+    int32_t *rank_of_slot = (int32_t *)tab;
+    for (int i = tid; i < D; i += nt) {
+        rank_of_slot[dslot[i]] = i;
+        if (i < T.cap) T.child_z[(int64_t)a * T.cap + i] = dkey[i];
+    }
+    if (tid == 0) T.n_children[a] = D;
+    __syncthreads();
+    for (int k = tid; k < n; k += nt) {
+        const int c = rank_of_slot[child[k]];
+        child[k] = c;
+        if (T.child_of) T.child_of[(int64_t)a * n + k] = c;
+    }
+    __syncthreads();
+
+    // -- stable grouping: position of each scenario in perm --------------------
+    const int nchunks = (n + 63) >> 6;
+    if ((int64_t)nchunks * D <= Ly.table_cap) {
+        for (int i = tid; i < nchunks * D; i += nt) cnt[i] = 0;
+        __syncthreads();
+        for (int t = wid; t < nchunks; t += nw) {
+            const int k = t * 64 + lane;
+            const bool valid = k < n;
+            const int c = valid ? child[k] : -1;
+            uint64_t rem = __ballot(valid);
+            int myrank = 0;
+            while (rem) {
+                const int leader = __ffsll((unsigned long long)rem) - 1;
+                const int cl = __shfl(c, leader, 64);
+                const uint64_t m = __ballot(valid && c == cl);
+                if (valid && c == cl) myrank = __popcll(m & __lanemask_lt());
+                if (lane == leader) cnt[t * D + cl] = __popcll(m);
+                rem &= ~m;
+            }
+            if (valid) pos[k] = myrank;
+        }
+        __syncthreads();
+        for (int c = tid; c < D; c += nt) {
+            int run = 0;
+            for (int t = 0; t < nchunks; ++t) {
+                const int v = cnt[t * D + c];
+                cnt[t * D + c] = run;
+                run += v;
+            }
+            nc[c] = run;
+            off[c] = run;
+        }
+        __syncthreads();
+        block_exclusive_scan(off, D, scan_scratch);
+        for (int k = tid; k < n; k += nt) {
+            const int c = child[k];
+            permb[off[c] + cnt[(k >> 6) * D + c] + pos[k]] = k;
+        }
+        __syncthreads();
+    } else {
+        uint32_t *comp = (uint32_t *)permb;
+        const int p = pow2_at_least(n);
+        for (int i = tid; i < p; i += nt) comp[i] = (i < n) ? (((uint32_t)child[i] << 16) | (uint32_t)i) : 0xFFFFFFFFu;
+        __syncthreads();
+        block_sort_u32(comp, p);
+        for (int i = tid; i < n; i += nt) {
+            const uint32_t v = comp[i];
+            const int c = (int)(v >> 16);
+            if (i == 0 || (comp[i - 1] >> 16) != (uint32_t)c) off[c] = i;
+        }
+        __syncthreads();
+        for (int c = tid; c < D; c += nt) nc[c] = ((c + 1 < D) ? off[c + 1] : n) - off[c];
+        __syncthreads();
+        for (int i = tid; i < n; i += nt) permb[i] = (int32_t)(comp[i] & 0xFFFFu);
+        __syncthreads();
+    }
+    for (int i = tid; i < n; i += nt) T.perm[(int64_t)a * n + i] = permb[i];
+    for (int c = tid; c < D && c < T.cap; c += nt) {
+        T.child_n[(int64_t)a * T.cap + c] = nc[c];
+        T.child_off[(int64_t)a * T.cap + c] = off[c];
+    }
+
+    // -- per-child sums: segmented wavefront scans over the grouped order ------
+    float *su = (float *)zk;          // dkey no longer needed
+    float *sl = su + Ly.p2;
+    for (int t = wid; t < nchunks; t += nw) {
+        const int i = t * 64 + lane;
+        const bool valid = i < n;
+        const int k = valid ? permb[i] : 0;
+        float vu = valid ? ub[k] : 0.0f;
+        float vl = valid ? lb[k] : 0.0f;
+        const int c = valid ? child[k] : -1;
+        const int c_prev = __shfl_up(c, 1, 64);
+        bool head = (lane == 0) || (c_prev != c);
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const float ou = __shfl_up(vu, d, 64);
+            const float ol = __shfl_up(vl, d, 64);
+            const int oh = __shfl_up((int)head, d, 64);
+            if (lane >= d && !head) {
+                vu = ou + vu;
+                vl = ol + vl;
+                head = oh != 0;
+            }
+        }
+        if (valid) {
+            su[i] = vu;
+            sl[i] = vl;
+        }
+        // mean step reward: plain sum of this 64-scenario chunk in k order
+        float vr = (t * 64 + lane < n) ? rb[t * 64 + lane] : 0.0f;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const float o = __shfl_up(vr, d, 64);
+            if (lane >= d) vr = o + vr;
+        }
+        if (lane == 63) chunk_r[t] = vr;
+    }
+    __syncthreads();
+    for (int c = tid; c < D && c < T.cap; c += nt) {
+        const int start = off[c], end = start + nc[c];
+        float tu = 0.0f, tl = 0.0f;
+        for (int t = start >> 6; t <= (end - 1) >> 6; ++t) {
+            const int e = min(end, (t + 1) * 64) - 1;
+            tu = tu + su[e];
+            tl = tl + sl[e];
+        }
+        T.child_u0[(int64_t)a * T.cap + c] = __fdiv_rn(tu, (float)nc[c]);
+        T.child_l0[(int64_t)a * T.cap + c] = __fdiv_rn(tl, (float)nc[c]);
+    }
+    if (tid == 0) {
+        float tr = 0.0f;
+        for (int t = 0; t < nchunks; ++t) tr = tr + chunk_r[t];
+        T.r_mean[a] = n > 0 ? __fdiv_rn(tr, (float)n) : 0.0f;
+        T.steps[2 * a + 0] = (int64_t)stepc[0];
+        T.steps[2 * a + 1] = (int64_t)stepc[1];
+    }
+    __syncthreads();  // LDS is reused by the next tile
+}
+
+template <int PM>
+__device__ __forceinline__ void run_ped(const LeafTask &T, int a, unsigned char *lds, const LdsLayout &Ly) {
+    run_tile<PedOps<PM>>(T, a, lds, Ly);
+}
+
+__device__ __forceinline__ int remap_xcd(int b, int grid) {
+    // workgroups are dealt to the 8 XCDs round-robin; give each XCD a
+    // contiguous run of tiles so the tiles of one leaf share an L2
+    const int x = b & 7, slot = b >> 3, base = grid >> 3, extra = grid & 7;
+    return x * base + min(x, extra) + slot;
+}
+
+// MODE 0: RockSample only; 1: crowd driving only; 2: both.  Workgroups of
+// the driving model are capped at 256 lanes so its per-lane state can stay
+// in registers.
+template <int MODE>
+constexpr int max_threads() { return MODE == 0 ? 512 : 256; }
+
+template <int MODE, int PM>
+__global__ __launch_bounds__(max_threads<MODE>()) void expand_tiles(const LeafTask *tasks, const Tile *tiles, int32_t n_tiles,
+                                                     TileQueue *queue, int32_t n_max, int32_t persistent,
+                                                     int32_t xcd_remap) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ int32_t s_tile;
+    const LdsLayout Ly = make_layout(n_max);
+    int iter = 0;
+    for (;;) {
+        int t;
+        if (persistent) {
+            if (threadIdx.x == 0) s_tile = atomicAdd(&queue->next, 1);
+            __syncthreads();
+            t = __builtin_amdgcn_readfirstlane(s_tile);
+            __syncthreads();
+        } else {
+            if (iter > 0) break;
+            t = xcd_remap ? remap_xcd((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+        }
+        ++iter;
+        if (t >= n_tiles) break;
+        const Tile tile = tiles[t];
+        const LeafTask &T = tasks[tile.leaf];
+        if (MODE == 0 || (MODE == 2 && T.kind == HDX_ROCKSAMPLE)) {
+            run_tile<RsOps>(T, tile.action, lds, Ly);
+        } else if (MODE != 0) {
+            run_ped<PM>(T, tile.action, lds, Ly);
+        }
+    }
+    if (persistent && threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&queue->done, 1) == (int)gridDim.x - 1) {
+            queue->next = 0;
+            queue->done = 0;
+            __threadfence();
+        }
+    }
+}
+
+template <int MODE, int PM>
+hipError_t launch_expand_t(const LeafTask *d_tasks, const Tile *d_tiles, int32_t n_tiles, TileQueue *d_queue,
+                           int32_t n_max, const Schedule &sch, int32_t n_cu, hipStream_t stream) {
+    const LdsLayout Ly = make_layout(n_max);
+    auto kern = expand_tiles<MODE, PM>;
+    static bool configured = false;
+    if (!configured) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           max_dynamic_lds());
+        if (e != hipSuccess) return e;
+        configured = true;
+    }
+    int grid = n_tiles;
+    if (sch.persistent > 0) {
+        grid = n_cu * sch.persistent;
+        if (grid > n_tiles) grid = n_tiles;
+    }
+    if (grid < 1) return hipSuccess;
+    const int threads = sch.threads > max_threads<MODE>() ? max_threads<MODE>() : sch.threads;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), Ly.total, stream, d_tasks, d_tiles, n_tiles, d_queue,
+                       n_max, sch.persistent > 0 ? 1 : 0, sch.xcd_remap);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// sample_scenarios
+// ---------------------------------------------------------------------------
+__global__ void sample_kernel(const SampleArgs A) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= A.K) return;
+    const DevModel &M = *A.model;
+    const StatesPtr &S = A.out;
+    if (M.kind == HDX_ROCKSAMPLE) {
+        int32_t w = A.x0 | (A.y0 << 5);
+        uint4 u = make_uint4(0, 0, 0, 0);
+        for (int i = 0; i < M.n_rocks; ++i) {
+            if ((i & 3) == 0) u = philox((uint32_t)k, 0, (uint32_t)(i >> 2), kTagInit, A.k0, A.k1);
+            const uint32_t word = (i & 3) == 0 ? u.x : (i & 3) == 1 ? u.y : (i & 3) == 2 ? u.z : u.w;
+            if ((uint64_t)word < A.rock_thr[i]) w |= 1 << (10 + i);
+        }
+        S.w[k] = w;
+    } else {
+        S.s[k] = A.s0;
+        S.car[k] = A.level0 & 0xff;
+        uint4 u = make_uint4(0, 0, 0, 0);
+        for (int j = 0; j < M.n_peds; ++j) {
+            if ((j & 3) == 0) u = philox((uint32_t)k, 0, (uint32_t)(j >> 2), kTagInit, A.k0, A.k1);
+            const uint32_t word = (j & 3) == 0 ? u.x : (j & 3) == 1 ? u.y : (j & 3) == 2 ? u.z : u.w;
+            int g = M.n_goals - 1;
+            for (int q = 0; q < M.n_goals - 1; ++q) {
+                if ((uint64_t)word < A.goal_thr[j][q]) {
+                    g = q;
+                    break;
+                }
+            }
+            S.px[j * S.stride + k] = A.px0[j];
+            S.py[j * S.stride + k] = A.py0[j];
+            S.goal[j * S.stride + k] = (uint8_t)g;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// rollout_bounds: one lane per state
+// ---------------------------------------------------------------------------
+template <class Ops>
+__global__ void bounds_kernel(const BoundsArgs A) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= A.n) return;
+    const DevModel &M = *A.model;
+    typename Ops::State st;
+    Ops::load(M, A.states, k, st);
+    RolloutParams RP;
+    RP.k0 = A.k0;
+    RP.k1 = A.k1;
+    RP.policy = A.policy;
+    RP.const_action = A.const_action;
+    RP.max_steps = A.max_steps;
+    RP.max_depth = A.max_depth;
+    RP.n_actions = M.n_actions;
+    int ns = 0;
+    A.U[k] = Ops::upper(M, st);
+    A.L[k] = rollout<Ops>(M, RP, st, A.ids[k], A.depths[k], ns);
+    if (A.steps) A.steps[k] = ns;
+}
+
+__global__ void philox_kernel(const uint32_t *ctr, int64_t count, uint32_t k0, uint32_t k1, uint32_t *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const uint4 c = reinterpret_cast<const uint4 *>(ctr)[i];
+    reinterpret_cast<uint4 *>(out)[i] = philox(c.x, c.y, c.z, c.w, k0, k1);
+}
+
+}  // namespace
+
+int32_t max_dynamic_lds() { return 160 * 1024 - 256; }
+
+hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, int32_t n_tiles, TileQueue *d_queue,
+                         int32_t n_max, int32_t has_ped, int32_t ped_max, int32_t has_rs, const Schedule &sch,
+                         int32_t n_cu, hipStream_t stream) {
+    if (!has_ped) return launch_expand_t<0, 1>(d_tasks, d_tiles, n_tiles, d_queue, n_max, sch, n_cu, stream);
+    const int pm = ped_max <= 8 ? 8 : ped_max <= 16 ? 16 : 32;
+    if (!has_rs) {
+        if (pm == 8) return launch_expand_t<1, 8>(d_tasks, d_tiles, n_tiles, d_queue, n_max, sch, n_cu, stream);
+        if (pm == 16) return launch_expand_t<1, 16>(d_tasks, d_tiles, n_tiles, d_queue, n_max, sch, n_cu, stream);
+        return launch_expand_t<1, 32>(d_tasks, d_tiles, n_tiles, d_queue, n_max, sch, n_cu, stream);
+    }
+    if (pm == 8) return launch_expand_t<2, 8>(d_tasks, d_tiles, n_tiles, d_queue, n_max, sch, n_cu, stream);
+    if (pm == 16) return launch_expand_t<2, 16>(d_tasks, d_tiles, n_tiles, d_queue, n_max, sch, n_cu, stream);
+    return launch_expand_t<2, 32>(d_tasks, d_tiles, n_tiles, d_queue, n_max, sch, n_cu, stream);
+}
+
+hipError_t launch_sample(const SampleArgs &args, hipStream_t stream) {
+    const int threads = 256;
+    const int blocks = (args.K + threads - 1) / threads;
+    hipLaunchKernelGGL(sample_kernel, dim3(blocks), dim3(threads), 0, stream, args);
+    return hipGetLastError();
+}
+
+hipError_t launch_bounds(const BoundsArgs &args, int32_t kind, int32_t n_peds, hipStream_t stream) {
+    const int threads = 256;
+    const int64_t blocks = (args.n + threads - 1) / threads;
+    if (blocks == 0) return hipSuccess;
+    if (kind == HDX_ROCKSAMPLE) {
+        hipLaunchKernelGGL(bounds_kernel<RsOps>, dim3((unsigned)blocks), dim3(threads), 0, stream, args);
+    } else if (n_peds <= 8) {
+        hipLaunchKernelGGL(bounds_kernel<PedOps<8>>, dim3((unsigned)blocks), dim3(threads), 0, stream, args);
+    } else if (n_peds <= 16) {
+        hipLaunchKernelGGL(bounds_kernel<PedOps<16>>, dim3((unsigned)blocks), dim3(threads), 0, stream, args);
+    } else {
+        hipLaunchKernelGGL(bounds_kernel<PedOps<32>>, dim3((unsigned)blocks), dim3(threads), 0, stream, args);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(const uint32_t *ctr, int64_t count, uint32_t k0, uint32_t k1, uint32_t *out,
+                         hipStream_t stream) {
+    const int threads = 256;
+    const int64_t blocks = (count + threads - 1) / threads;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(philox_kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, ctr, count, k0, k1, out);
+    return hipGetLastError();
+}
+
+}  // namespace hdx

@@ -1,0 +1,304 @@
+// Device-side step functions of the two models and the Philox4x32-10 stream.
+//
+// The step function is the deterministic simulative model g of DESPOT
+// (Sec. III-A): s', r, z = g(s, a, phi), where the scenario phi supplies the
+// random numbers through a counter-based generator indexed by (scenario id,
+// depth, block, tag).  State arithmetic of the driving model is FP32 and
+// compiled without contraction, with correctly rounded division and square
+// root, so results are bit-identical to any IEEE-754 FP32 evaluation in the
+// same operation order.
+#pragma once
+
+#include "internal.hpp"
+
+namespace hdx {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies, the key advanced by the Weyl increments in between.
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// ---------------------------------------------------------------------------
+// RockSample: one packed int32 word per scenario.
+// ---------------------------------------------------------------------------
+struct RsOps {
+    struct State {
+        int32_t w;
+    };
+    static constexpr bool kHashObs = false;
+
+    __device__ static void load(const DevModel &, const StatesPtr &S, int64_t p, State &st) { st.w = S.w[p]; }
+    __device__ static void store(const DevModel &, const StatesPtr &S, int64_t p, const State &st) { S.w[p] = st.w; }
+    __device__ static bool terminal(const State &st) { return (st.w >> 30) & 1; }
+
+    template <bool kObs>
+    __device__ static void step(const DevModel &M, State &st, int a, uint32_t id, uint32_t depth, uint32_t k0,
+                                uint32_t k1, float &r, uint64_t &z) {
+        int32_t w = st.w;
+        r = 0.0f;
+        z = 0;
+        if ((w >> 30) & 1) return;  // absorbing
+        int x = w & 31, y = (w >> 5) & 31;
+        const int n = M.grid;
+        int32_t term = 0;
+        if (a == 0) {
+            if (y + 1 < n) ++y;
+        } else if (a == 1) {
+            if (y > 0) --y;
+        } else if (a == 2) {
+            if (x + 1 == n) {
+                r = 10.0f;
+                term = 1 << 30;
+            } else {
+                ++x;
+            }
+        } else if (a == 3) {
+            if (x > 0) --x;
+        } else if (a == 4) {
+            const int i = M.rock_at[x + y * n];
+            if (i >= 0) {
+                if ((w >> (10 + i)) & 1) {
+                    r = 10.0f;
+                    w &= ~(1 << (10 + i));
+                } else {
+                    r = -10.0f;
+                }
+            }
+        } else {
+            const int i = a - 5;
+            const int dx = x - M.rock_x[i], dy = y - M.rock_y[i];
+            const uint32_t u = philox(id, depth, 0, kTagStep, k0, k1).x;
+            const int correct = u <= M.sense_thr_m1[dx * dx + dy * dy];
+            const int truth = (w >> (10 + i)) & 1;
+            z = (correct ? truth : !truth) ? 1 : 2;
+        }
+        st.w = (w & ~0x3ff) | x | (y << 5) | term;
+    }
+
+    __device__ static float upper(const DevModel &M, const State &st) {
+        if ((st.w >> 30) & 1) return 0.0f;
+        const int x = st.w & 31, y = (st.w >> 5) & 31;
+        float u = 0.0f;
+        for (int i = 0; i < M.n_rocks; ++i)
+            if ((st.w >> (10 + i)) & 1) u += 10.0f * M.gpow[abs(x - M.rock_x[i]) + abs(y - M.rock_y[i])];
+        return u + 10.0f * M.gpow[M.grid - 1 - x];
+    }
+
+    __device__ static int default_action(const DevModel &, const State &) { return 2; }  // move east
+};
+
+// ---------------------------------------------------------------------------
+// Crowd driving: car (position, speed level, terminal) and up to PM
+// pedestrians held in registers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {  // splitmix64 output function
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+__device__ __forceinline__ uint64_t hash_field(uint64_t h, int32_t f) {
+    return mix64((h ^ (uint64_t)(uint32_t)f) + 0x9E3779B97F4A7C15ull);
+}
+
+template <int PM>
+struct PedOps {
+    struct State {
+        float s;
+        int32_t level, term;
+        float px[PM], py[PM];
+        int32_t goal[PM];
+    };
+    static constexpr bool kHashObs = true;
+
+    __device__ static void load(const DevModel &M, const StatesPtr &S, int64_t p, State &st) {
+        st.s = S.s[p];
+        const int32_t car = S.car[p];
+        st.level = car & 0xff;
+        st.term = (car >> 8) & 1;
+#pragma unroll
+        for (int j = 0; j < PM; ++j) {
+            if (j < M.n_peds) {
+                st.px[j] = S.px[j * S.stride + p];
+                st.py[j] = S.py[j * S.stride + p];
+                st.goal[j] = S.goal[j * S.stride + p];
+            } else {
+                st.px[j] = 0.0f;
+                st.py[j] = 0.0f;
+                st.goal[j] = 0;
+            }
+        }
+    }
+    __device__ static void store(const DevModel &M, const StatesPtr &S, int64_t p, const State &st) {
+        S.s[p] = st.s;
+        S.car[p] = (st.level & 0xff) | (st.term ? 0x100 : 0);
+#pragma unroll
+        for (int j = 0; j < PM; ++j) {
+            if (j < M.n_peds) {
+                S.px[j * S.stride + p] = st.px[j];
+                S.py[j * S.stride + p] = st.py[j];
+                S.goal[j * S.stride + p] = (uint8_t)st.goal[j];
+            }
+        }
+    }
+    __device__ static bool terminal(const State &st) { return st.term != 0; }
+
+    template <bool kObs>
+    __device__ static void step(const DevModel &M, State &st, int a, uint32_t id, uint32_t depth, uint32_t k0,
+                                uint32_t k1, float &r, uint64_t &z) {
+        if (st.term) {
+            r = 0.0f;
+            z = kPedTerminalObs;
+            return;
+        }
+        const uint4 u0 = philox(id, depth, 0, kTagStep, k0, k1);
+        const bool failed = (uint64_t)u0.x < M.fail_thr;
+        int level = st.level;
+        if (a == 0 && !failed && level < M.n_levels - 1) level = level + 1;
+        if (a == 2 && !failed && level > 0) level = level - 1;
+        const float v = 0.5f * (float)level;
+        const float s_next = st.s + v * M.dt;
+        const float step_len = M.step_len, half_sigma = M.half_sigma;
+#pragma unroll
+        for (int j = 0; j < PM; ++j) {
+            if (j < M.n_peds) {
+                const uint4 u = philox(id, depth, (uint32_t)(j + 1), kTagStep, k0, k1);
+                const int32_t sum = (int32_t)((u.x >> 8) + (u.y >> 8) + (u.z >> 8) + (u.w >> 8));
+                const float noise = (float)(sum - 33554430) * M.ih_scale;
+                const float gx = M.goal_x[st.goal[j]], gy = M.goal_y[st.goal[j]];
+                const float dx = gx - st.px[j];
+                const float dy = gy - st.py[j];
+                const float dist = __fsqrt_rn(dx * dx + dy * dy);
+                if (dist <= step_len) {
+                    st.px[j] = gx;
+                    st.py[j] = gy;
+                } else {
+                    const float ux = __fdiv_rn(dx, dist), uy = __fdiv_rn(dy, dist);
+                    const float t = half_sigma * noise;
+                    const float t2 = t * t;
+                    const float den = 1.0f + t2;
+                    const float c = __fdiv_rn(1.0f - t2, den);
+                    const float sn = __fdiv_rn(2.0f * t, den);
+                    const float rx = ux * c - uy * sn;
+                    const float ry = ux * sn + uy * c;
+                    st.px[j] = st.px[j] + step_len * rx;
+                    st.py[j] = st.py[j] + step_len * ry;
+                }
+            }
+        }
+        bool collided = false;
+        if (level > 0) {
+            const float r2 = M.coll_r2;
+#pragma unroll
+            for (int j = 0; j < PM; ++j) {
+                if (j < M.n_peds) {
+                    const float ddx = st.px[j] - s_next;
+                    const float d2 = ddx * ddx + st.py[j] * st.py[j];
+                    collided = collided || (d2 < r2);
+                }
+            }
+        }
+        float reward = M.r_step;
+        if (collided) {
+            reward = M.r_step + M.r_collision;
+            st.term = 1;
+        } else if (s_next >= M.path_len) {
+            reward = M.r_step + M.r_goal;
+            st.term = 1;
+        }
+        st.s = s_next;
+        st.level = level;
+        r = reward;
+        if (kObs) {
+            if (st.term) {
+                z = kPedTerminalObs;
+            } else {
+                uint64_t h = 0x243F6A8885A308D3ull;
+                h = hash_field(h, level);
+#pragma unroll
+                for (int j = 0; j < PM; ++j) {
+                    if (j < M.n_peds) {
+                        h = hash_field(h, (int32_t)floorf(st.px[j]));
+                        h = hash_field(h, (int32_t)floorf(st.py[j]));
+                    }
+                }
+                z = (h == kPedTerminalObs) ? kPedTerminalObs - 1 : h;
+            }
+        } else {
+            z = 0;
+        }
+    }
+
+    __device__ static float upper(const DevModel &M, const State &st) {
+        if (st.term) return 0.0f;
+        const float T = ceilf(__fdiv_rn(M.path_len - st.s, M.reach));
+        int Ti = (int)T;
+        if (Ti < 1) Ti = 1;
+        if (Ti > kHorizon) Ti = kHorizon;
+        return M.r_goal * M.gpow[Ti - 1];
+    }
+
+    __device__ static int default_action(const DevModel &M, const State &st) {
+        bool brake = false;
+#pragma unroll
+        for (int j = 0; j < PM; ++j) {
+            if (j < M.n_peds) {
+                const float ahead = st.px[j] - st.s;
+                brake = brake || (ahead >= 0.0f && ahead <= 3.0f && fabsf(st.py[j]) < 1.5f);
+            }
+        }
+        return brake ? 2 : 0;
+    }
+};
+
+struct RolloutParams {
+    uint32_t k0, k1;
+    int32_t policy, const_action, max_steps, max_depth, n_actions;
+};
+
+// Default-policy rollout from depth d0 (Eq. 13): discounted from d0, stops
+// at a terminal state or after min(max_steps, max_depth - d0) steps; the
+// tail value past the horizon is 0.  Accumulates in FP32 in step order.
+template <class Ops>
+__device__ __forceinline__ float rollout(const DevModel &M, const RolloutParams &P, typename Ops::State st,
+                                         uint32_t id, int d0, int &nsteps) {
+    int n_roll = P.max_steps;
+    if (P.max_depth >= 0 && P.max_depth - d0 < n_roll) n_roll = P.max_depth - d0;
+    if (n_roll > kHorizon) n_roll = kHorizon;  // the discount table's length
+    float value = 0.0f;
+    for (int j = 0; j < n_roll; ++j) {
+        if (Ops::terminal(st)) break;
+        const uint32_t depth = (uint32_t)(d0 + j);
+        int a;
+        if (P.policy == HDX_POLICY_CONST) {
+            a = P.const_action;
+        } else if (P.policy == HDX_POLICY_RANDOM) {
+            a = (int)(philox(id, depth, 0, kTagPolicy, P.k0, P.k1).x % (uint32_t)P.n_actions);
+        } else {
+            a = Ops::default_action(M, st);
+        }
+        float r;
+        uint64_t z;
+        Ops::template step<false>(M, st, a, id, depth, P.k0, P.k1, r, z);
+        value += M.gpow[j] * r;
+        ++nsteps;
+    }
+    return value;
+}
+
+}  // namespace hdx

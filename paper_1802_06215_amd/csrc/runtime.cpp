@@ -1,0 +1,453 @@
+// Host runtime behind the C ABI: context, model upload (device tables),
+// argument validation, descriptor staging and kernel launches.
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace hdx;
+
+namespace {
+
+constexpr int kSlots = 16;  // concurrent expand calls in flight per context
+
+// Pinned staging + device copy of one call's leaf descriptors and tiles.
+struct Slot {
+    LeafTask *h_tasks = nullptr, *d_tasks = nullptr;
+    Tile *h_tiles = nullptr, *d_tiles = nullptr;
+    TileQueue *d_queue = nullptr;
+    int64_t cap_tasks = 0, cap_tiles = 0;
+    hipEvent_t done = nullptr;
+    bool used = false;
+};
+
+uint64_t prob_threshold(double p) {
+    if (p <= 0.0) return 0;
+    if (p >= 1.0) return 1ull << 32;
+    return (uint64_t)floor(p * 4294967296.0);
+}
+
+}  // namespace
+
+struct hdx_ctx {
+    int32_t device = 0;
+    int32_t n_cu = 256;
+    std::string err;
+    std::mutex mu;
+    Slot slots[kSlots];
+    int next_slot = 0;
+    Schedule sched{256, 0, 1};
+    bool sched_fixed = false;
+};
+
+struct hdx_model {
+    hdx_model_desc desc;
+    DevModel *d_model = nullptr;
+};
+
+static hdx_status fail(hdx_ctx *ctx, hdx_status code, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+static hdx_status hip_fail(hdx_ctx *ctx, hipError_t e, const char *what) {
+    return fail(ctx, HDX_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+extern "C" {
+
+const char *hdx_version(void) { return "hdx 0.1 (gfx950)"; }
+
+hdx_status hdx_init(int32_t device, hdx_ctx **out) {
+    if (!out) return HDX_E_INVALID;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return HDX_E_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return HDX_E_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return HDX_E_DEVICE;
+    hdx_ctx *ctx = new hdx_ctx();
+    ctx->device = device;
+    ctx->n_cu = prop.multiProcessorCount;
+    for (auto &s : ctx->slots) {
+        if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
+            delete ctx;
+            return HDX_E_DEVICE;
+        }
+        if (hipMalloc(&s.d_queue, sizeof(TileQueue)) != hipSuccess ||
+            hipMemset(s.d_queue, 0, sizeof(TileQueue)) != hipSuccess) {
+            delete ctx;
+            return HDX_E_NOMEM;
+        }
+    }
+    if (hipDeviceSynchronize() != hipSuccess) {
+        delete ctx;
+        return HDX_E_DEVICE;
+    }
+    *out = ctx;
+    return HDX_OK;
+}
+
+hdx_status hdx_fini(hdx_ctx *ctx) {
+    if (!ctx) return HDX_E_INVALID;
+    hipSetDevice(ctx->device);
+    for (auto &s : ctx->slots) {
+        if (s.done) hipEventSynchronize(s.done);
+        if (s.h_tasks) hipHostFree(s.h_tasks);
+        if (s.h_tiles) hipHostFree(s.h_tiles);
+        if (s.d_tasks) hipFree(s.d_tasks);
+        if (s.d_tiles) hipFree(s.d_tiles);
+        if (s.d_queue) hipFree(s.d_queue);
+        if (s.done) hipEventDestroy(s.done);
+    }
+    delete ctx;
+    return HDX_OK;
+}
+
+const char *hdx_last_error(const hdx_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+hdx_status hdx_upload_model(hdx_ctx *ctx, const hdx_model_desc *d, hdx_model **out) {
+    if (!ctx || !d || !out) return fail(ctx, HDX_E_INVALID, "null argument");
+    *out = nullptr;
+    if (!(d->gamma > 0.0 && d->gamma <= 1.0)) return fail(ctx, HDX_E_INVALID, "gamma must be in (0, 1]");
+    DevModel *h = new DevModel();
+    memset(h, 0, sizeof(DevModel));
+    h->kind = d->kind;
+    if (d->kind == HDX_ROCKSAMPLE) {
+        if (d->grid < 1 || d->grid > kMaxGrid || d->n_rocks < 0 || d->n_rocks > kMaxRocks) {
+            delete h;
+            return fail(ctx, HDX_E_SHAPE, "grid must be 1..31 and rocks 0..20");
+        }
+        h->n_actions = 5 + d->n_rocks;
+        h->grid = d->grid;
+        h->n_rocks = d->n_rocks;
+        memset(h->rock_at, -1, sizeof(h->rock_at));
+        for (int i = 0; i < d->n_rocks; ++i) {
+            const int x = d->rock_x[i], y = d->rock_y[i];
+            if (x < 0 || x >= d->grid || y < 0 || y >= d->grid || h->rock_at[x + y * d->grid] >= 0) {
+                delete h;
+                return fail(ctx, HDX_E_INVALID, "rocks must lie on distinct grid cells");
+            }
+            h->rock_x[i] = x;
+            h->rock_y[i] = y;
+            h->rock_at[x + y * d->grid] = (int8_t)i;
+        }
+        // sensor accuracy 0.5 + 0.5 * 2^(-d/20) as a threshold on a 32-bit word
+        for (int d2 = 0; d2 < kSenseEntries; ++d2) {
+            const double acc = 0.5 + 0.5 * pow(2.0, -sqrt((double)d2) / 20.0);
+            h->sense_thr_m1[d2] = (uint32_t)(prob_threshold(acc) - 1);
+        }
+    } else if (d->kind == HDX_PEDNAV) {
+        if (d->n_peds < 0 || d->n_peds > kMaxPeds || d->n_goals < 1 || d->n_goals > kMaxGoals ||
+            d->n_levels < 1 || d->n_levels > 255) {
+            delete h;
+            return fail(ctx, HDX_E_SHAPE, "pedestrians 0..32, goals 1..8, levels 1..255");
+        }
+        if (!(d->p_fail >= 0.0 && d->p_fail < 1.0) || !(d->dt > 0.0f)) {
+            delete h;
+            return fail(ctx, HDX_E_INVALID, "p_fail must be in [0, 1) and dt > 0");
+        }
+        h->n_actions = 3;
+        h->n_peds = d->n_peds;
+        h->n_goals = d->n_goals;
+        h->n_levels = d->n_levels;
+        for (int g = 0; g < d->n_goals; ++g) {
+            h->goal_x[g] = d->goal_x[g];
+            h->goal_y[g] = d->goal_y[g];
+        }
+        h->path_len = d->path_len;
+        h->dt = d->dt;
+        h->step_len = d->ped_speed * d->dt;
+        h->half_sigma = 0.5f * d->sigma_h;
+        h->coll_r2 = d->coll_radius * d->coll_radius;
+        h->reach = (0.5f * (float)(d->n_levels - 1)) * d->dt;
+        if (!(h->reach > 0.0f)) {
+            delete h;
+            return fail(ctx, HDX_E_INVALID, "need at least two speed levels");
+        }
+        h->ih_scale = (float)(sqrt(3.0) / 16777216.0);
+        h->r_collision = d->r_collision;
+        h->r_step = d->r_step;
+        h->r_goal = d->r_goal;
+        h->fail_thr = prob_threshold(d->p_fail);
+    } else {
+        delete h;
+        return fail(ctx, HDX_E_UNSUPPORTED, "unknown model kind");
+    }
+    if (d->n_actions != h->n_actions) {
+        delete h;
+        return fail(ctx, HDX_E_INVALID, "n_actions does not match the model");
+    }
+    for (int j = 0; j < kHorizon; ++j) h->gpow[j] = (float)pow(d->gamma, j);
+    hipSetDevice(ctx->device);
+    hdx_model *m = new hdx_model();
+    m->desc = *d;
+    hipError_t e = hipMalloc(&m->d_model, sizeof(DevModel));
+    if (e == hipSuccess) e = hipMemcpy(m->d_model, h, sizeof(DevModel), hipMemcpyHostToDevice);
+    delete h;
+    if (e != hipSuccess) {
+        if (m->d_model) hipFree(m->d_model);
+        delete m;
+        return hip_fail(ctx, e, "model upload");
+    }
+    *out = m;
+    return HDX_OK;
+}
+
+hdx_status hdx_free_model(hdx_ctx *ctx, hdx_model *m) {
+    if (!ctx || !m) return HDX_E_INVALID;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    hipFree(m->d_model);
+    delete m;
+    return HDX_OK;
+}
+
+int32_t hdx_model_actions(const hdx_model *m) { return m ? m->desc.n_actions : -1; }
+
+int32_t hdx_model_max_children(const hdx_model *m, int32_t n) {
+    if (!m || n < 0) return -1;
+    if (m->desc.kind == HDX_ROCKSAMPLE) return n < 3 ? n : 3;  // none, good, bad
+    return n;                                                  // hashed observations
+}
+
+static StatesPtr to_ptr(const hdx_states &s) {
+    StatesPtr p;
+    p.w = s.w;
+    p.s = s.s;
+    p.car = s.car;
+    p.px = s.px;
+    p.py = s.py;
+    p.goal = s.goal;
+    p.stride = s.stride;
+    return p;
+}
+
+static bool states_ok(const hdx_model *m, const hdx_states &s, int64_t n) {
+    if (m->desc.kind == HDX_ROCKSAMPLE) return s.w != nullptr;
+    if (!s.s || !s.car) return false;
+    if (m->desc.n_peds > 0 && (!s.px || !s.py || !s.goal || s.stride < n)) return false;
+    return true;
+}
+
+hdx_status hdx_sample_scenarios(hdx_ctx *ctx, const hdx_model *m, const hdx_belief *b, int32_t K, uint32_t seed,
+                                uint32_t step, hdx_states out, hdx_stream stream) {
+    if (!ctx || !m || !b) return fail(ctx, HDX_E_INVALID, "null argument");
+    if (K <= 0 || K > (1 << 24)) return fail(ctx, HDX_E_SHAPE, "K must be in 1..2^24");
+    if (!states_ok(m, out, K)) return fail(ctx, HDX_E_INVALID, "missing output state arrays");
+    SampleArgs A;
+    memset(&A, 0, sizeof(A));
+    A.model = m->d_model;
+    A.k0 = seed;
+    A.k1 = step;
+    A.K = K;
+    A.out = to_ptr(out);
+    const hdx_model_desc &d = m->desc;
+    if (d.kind == HDX_ROCKSAMPLE) {
+        if (b->x < 0 || b->x >= d.grid || b->y < 0 || b->y >= d.grid) return fail(ctx, HDX_E_INVALID, "robot cell");
+        if (d.n_rocks > 0 && !b->p_good) return fail(ctx, HDX_E_INVALID, "p_good is null");
+        A.x0 = b->x;
+        A.y0 = b->y;
+        for (int i = 0; i < d.n_rocks; ++i) A.rock_thr[i] = prob_threshold(b->p_good[i]);
+    } else {
+        if (d.n_peds > 0 && (!b->px || !b->py || !b->goal_p)) return fail(ctx, HDX_E_INVALID, "belief arrays");
+        if (b->level < 0 || b->level >= d.n_levels) return fail(ctx, HDX_E_INVALID, "speed level");
+        A.s0 = b->s;
+        A.level0 = b->level;
+        for (int j = 0; j < d.n_peds; ++j) {
+            A.px0[j] = b->px[j];
+            A.py0[j] = b->py[j];
+            double cum = 0.0;
+            for (int q = 0; q < d.n_goals; ++q) {
+                cum += b->goal_p[j * d.n_goals + q];
+                A.goal_thr[j][q] = prob_threshold(cum);
+            }
+        }
+    }
+    hipSetDevice(ctx->device);
+    hipError_t e = launch_sample(A, (hipStream_t)stream);
+    return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "sample_scenarios launch");
+}
+
+static int64_t horizon_of(const hdx_rollout_cfg &c, int64_t d0) {
+    int64_t h = c.max_steps;
+    if (c.max_depth >= 0 && c.max_depth - d0 < h) h = c.max_depth - d0;
+    return h;
+}
+
+static hdx_status check_cfg(hdx_ctx *ctx, const hdx_model *m, const hdx_rollout_cfg &c) {
+    if (c.policy < HDX_POLICY_DEFAULT || c.policy > HDX_POLICY_RANDOM) return fail(ctx, HDX_E_INVALID, "policy");
+    if (c.policy == HDX_POLICY_CONST && (c.const_action < 0 || c.const_action >= m->desc.n_actions))
+        return fail(ctx, HDX_E_INVALID, "const_action");
+    if (c.max_steps < 0) return fail(ctx, HDX_E_INVALID, "max_steps < 0");
+    return HDX_OK;
+}
+
+hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves, hdx_stream stream) {
+    if (!ctx || (!leaves && n_leaves > 0) || n_leaves < 0) return fail(ctx, HDX_E_INVALID, "null argument");
+    if (n_leaves == 0) return HDX_OK;
+    int64_t n_tiles = 0;
+    int32_t n_max = 1, ped_max = 0, has_ped = 0, has_rs = 0;
+    for (int32_t i = 0; i < n_leaves; ++i) {
+        const hdx_leaf &L = leaves[i];
+        if (!L.model) return fail(ctx, HDX_E_INVALID, "leaf without model");
+        const hdx_model_desc &d = L.model->desc;
+        const int A = d.n_actions;
+        if (L.n < 0 || L.n > kMaxLeaf) return fail(ctx, HDX_E_SHAPE, "leaf scenario count out of range");
+        if (L.depth < 0 || L.last_action < -1 || L.last_action >= A || (L.last_action >= 0 && L.depth < 1))
+            return fail(ctx, HDX_E_INVALID, "depth / last_action");
+        if (L.cap < hdx_model_max_children(L.model, L.n)) return fail(ctx, HDX_E_CAPACITY, "cap too small");
+        hdx_status st = check_cfg(ctx, L.model, L.rollout);
+        if (st != HDX_OK) return st;
+        if (horizon_of(L.rollout, (int64_t)L.depth + 1) > kHorizon)
+            return fail(ctx, HDX_E_SHAPE, "rollout horizon exceeds HDX_MAX_HORIZON");
+        if (!L.n_children || !L.r_mean || !L.steps) return fail(ctx, HDX_E_INVALID, "missing output arrays");
+        if (L.n > 0) {
+            if (!L.parent_ids || !L.idx || !L.ids_out || !L.perm || !L.child_z || !L.child_n || !L.child_off ||
+                !L.child_u0 || !L.child_l0)
+                return fail(ctx, HDX_E_INVALID, "missing leaf arrays");
+            if (!states_ok(L.model, L.parent, 0) || !states_ok(L.model, L.states_out, L.n))
+                return fail(ctx, HDX_E_INVALID, "missing state arrays");
+            if ((L.sprime.w || L.sprime.s) && !states_ok(L.model, L.sprime, (int64_t)A * L.n))
+                return fail(ctx, HDX_E_INVALID, "incomplete sprime arrays");
+        }
+        n_tiles += A;
+        if (L.n > n_max) n_max = L.n;
+        if (d.kind == HDX_PEDNAV) {
+            has_ped = 1;
+            if (d.n_peds > ped_max) ped_max = d.n_peds;
+        } else {
+            has_rs = 1;
+        }
+    }
+    if (n_tiles > (1ll << 30)) return fail(ctx, HDX_E_SHAPE, "too many tiles");
+    hipSetDevice(ctx->device);
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    Slot &s = ctx->slots[ctx->next_slot];
+    ctx->next_slot = (ctx->next_slot + 1) % kSlots;
+    if (s.used) {
+        hipError_t e = hipEventSynchronize(s.done);
+        if (e != hipSuccess) return hip_fail(ctx, e, "staging wait");
+    }
+    if (s.cap_tasks < n_leaves || s.cap_tiles < n_tiles) {
+        int64_t ct = s.cap_tasks, cl = s.cap_tiles;
+        while (ct < n_leaves) ct = ct ? 2 * ct : 64;
+        while (cl < n_tiles) cl = cl ? 2 * cl : 1024;
+        if (s.h_tasks) hipHostFree(s.h_tasks);
+        if (s.h_tiles) hipHostFree(s.h_tiles);
+        if (s.d_tasks) hipFree(s.d_tasks);
+        if (s.d_tiles) hipFree(s.d_tiles);
+        s.h_tasks = s.d_tasks = nullptr;
+        s.h_tiles = s.d_tiles = nullptr;
+        s.cap_tasks = s.cap_tiles = 0;
+        if (hipHostMalloc(&s.h_tasks, ct * sizeof(LeafTask)) != hipSuccess ||
+            hipHostMalloc(&s.h_tiles, cl * sizeof(Tile)) != hipSuccess ||
+            hipMalloc(&s.d_tasks, ct * sizeof(LeafTask)) != hipSuccess ||
+            hipMalloc(&s.d_tiles, cl * sizeof(Tile)) != hipSuccess)
+            return fail(ctx, HDX_E_NOMEM, "descriptor staging allocation");
+        s.cap_tasks = ct;
+        s.cap_tiles = cl;
+    }
+    int64_t t = 0;
+    for (int32_t i = 0; i < n_leaves; ++i) {
+        const hdx_leaf &L = leaves[i];
+        LeafTask &T = s.h_tasks[i];
+        memset(&T, 0, sizeof(T));
+        T.model = L.model->d_model;
+        T.kind = L.model->desc.kind;
+        T.n_actions = L.model->desc.n_actions;
+        T.k0 = L.seed;
+        T.k1 = L.step;
+        T.policy = L.rollout.policy;
+        T.const_action = L.rollout.const_action;
+        T.max_steps = L.rollout.max_steps;
+        T.max_depth = L.rollout.max_depth;
+        T.parent = to_ptr(L.parent);
+        T.parent_ids = L.parent_ids;
+        T.idx = L.idx;
+        T.n = L.n;
+        T.depth = L.depth;
+        T.last_action = L.last_action;
+        T.cap = L.cap;
+        T.out = to_ptr(L.states_out);
+        T.ids_out = L.ids_out;
+        T.perm = L.perm;
+        T.n_children = L.n_children;
+        T.child_z = L.child_z;
+        T.child_n = L.child_n;
+        T.child_off = L.child_off;
+        T.child_u0 = L.child_u0;
+        T.child_l0 = L.child_l0;
+        T.r_mean = L.r_mean;
+        T.steps = L.steps;
+        T.sprime = to_ptr(L.sprime);
+        T.r = L.r;
+        T.z = L.z;
+        T.U = L.U;
+        T.L = L.L;
+        T.child_of = L.child_of;
+        for (int a = 0; a < T.n_actions; ++a) s.h_tiles[t++] = Tile{i, a};
+    }
+    hipStream_t hs = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(s.d_tasks, s.h_tasks, n_leaves * sizeof(LeafTask), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(s.d_tiles, s.h_tiles, n_tiles * sizeof(Tile), hipMemcpyHostToDevice, hs);
+    if (e != hipSuccess) return hip_fail(ctx, e, "descriptor copy");
+    Schedule sch = ctx->sched;
+    if (!ctx->sched_fixed) {
+        int th = ((n_max + 63) / 64) * 64;
+        sch.threads = th < 64 ? 64 : th > 512 ? 512 : th;
+    }
+    e = launch_expand(s.d_tasks, s.d_tiles, (int32_t)n_tiles, s.d_queue, n_max, has_ped, ped_max, has_rs, sch,
+                      ctx->n_cu, hs);
+    if (e != hipSuccess) return hip_fail(ctx, e, "expand launch");
+    e = hipEventRecord(s.done, hs);
+    s.used = true;
+    return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "event record");
+}
+
+hdx_status hdx_rollout_bounds(hdx_ctx *ctx, const hdx_model *m, const hdx_rollout_cfg *cfg, uint32_t seed,
+                              uint32_t step, hdx_states states, const uint32_t *ids, const int32_t *depths, int64_t n,
+                              float *U, float *L, int32_t *steps, hdx_stream stream) {
+    if (!ctx || !m || !cfg) return fail(ctx, HDX_E_INVALID, "null argument");
+    if (n < 0 || n > (1ll << 31)) return fail(ctx, HDX_E_SHAPE, "n out of range");
+    if (n == 0) return HDX_OK;
+    if (!ids || !depths || !U || !L || !states_ok(m, states, n)) return fail(ctx, HDX_E_INVALID, "missing arrays");
+    hdx_status st = check_cfg(ctx, m, *cfg);
+    if (st != HDX_OK) return st;
+    if (cfg->max_depth < 0 && cfg->max_steps > kHorizon)
+        return fail(ctx, HDX_E_SHAPE, "rollout horizon exceeds HDX_MAX_HORIZON");
+    if (cfg->max_depth > kHorizon && cfg->max_steps > kHorizon)
+        return fail(ctx, HDX_E_SHAPE, "rollout horizon exceeds HDX_MAX_HORIZON");
+    BoundsArgs A;
+    A.model = m->d_model;
+    A.k0 = seed;
+    A.k1 = step;
+    A.policy = cfg->policy;
+    A.const_action = cfg->const_action;
+    A.max_steps = cfg->max_steps;
+    A.max_depth = cfg->max_depth;
+    A.states = to_ptr(states);
+    A.ids = ids;
+    A.depths = depths;
+    A.n = n;
+    A.U = U;
+    A.L = L;
+    A.steps = steps;
+    hipSetDevice(ctx->device);
+    hipError_t e = launch_bounds(A, m->desc.kind, m->desc.n_peds, (hipStream_t)stream);
+    return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "rollout_bounds launch");
+}
+
+hdx_status hdx_philox(hdx_ctx *ctx, const uint32_t *ctr, int64_t count, uint32_t k0, uint32_t k1, uint32_t *out,
+                      hdx_stream stream) {
+    if (!ctx || (count > 0 && (!ctr || !out)) || count < 0) return fail(ctx, HDX_E_INVALID, "bad argument");
+    hipSetDevice(ctx->device);
+    hipError_t e = launch_philox(ctr, count, k0, k1, out, (hipStream_t)stream);
+    return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "philox launch");
+}
+
+}  // extern "C"

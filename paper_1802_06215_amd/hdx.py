@@ -1,0 +1,365 @@
+"""ctypes binding of libhdx.so (the C ABI in include/hdx.h).
+
+Argument marshalling only: every step of leaf expansion runs in the HIP
+kernels behind the C ABI.  PyTorch provides device memory (tensors) and
+streams.  Importing this module raises if the built library is missing;
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhdx.so")
+
+ROCKSAMPLE, PEDNAV = 0, 1
+POLICY_DEFAULT, POLICY_CONST, POLICY_RANDOM = 0, 1, 2
+MAX_LEAF_SCENARIOS = 2048
+MAX_HORIZON = 4096
+
+STATUS = {0: "HDX_OK", -1: "HDX_E_INVALID", -2: "HDX_E_DEVICE", -3: "HDX_E_NOMEM", -4: "HDX_E_SHAPE",
+          -5: "HDX_E_CAPACITY", -6: "HDX_E_UNSUPPORTED"}
+
+
+class HdxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_actions", C.c_int32), ("gamma", C.c_double),
+                ("grid", C.c_int32), ("n_rocks", C.c_int32),
+                ("rock_x", C.c_int32 * 20), ("rock_y", C.c_int32 * 20),
+                ("n_peds", C.c_int32), ("n_goals", C.c_int32), ("n_levels", C.c_int32),
+                ("reserved", C.c_int32),
+                ("goal_x", C.c_float * 8), ("goal_y", C.c_float * 8),
+                ("path_len", C.c_float), ("dt", C.c_float), ("ped_speed", C.c_float),
+                ("sigma_h", C.c_float), ("coll_radius", C.c_float),
+                ("r_collision", C.c_float), ("r_step", C.c_float), ("r_goal", C.c_float),
+                ("p_fail", C.c_double)]
+
+
+class Belief(C.Structure):
+    _fields_ = [("x", C.c_int32), ("y", C.c_int32), ("p_good", C.c_void_p),
+                ("s", C.c_float), ("level", C.c_int32), ("px", C.c_void_p), ("py", C.c_void_p),
+                ("goal_p", C.c_void_p)]
+
+
+class RolloutCfg(C.Structure):
+    _fields_ = [("policy", C.c_int32), ("const_action", C.c_int32),
+                ("max_steps", C.c_int32), ("max_depth", C.c_int32)]
+
+
+class States(C.Structure):
+    _fields_ = [("w", C.c_void_p), ("s", C.c_void_p), ("car", C.c_void_p),
+                ("px", C.c_void_p), ("py", C.c_void_p), ("goal", C.c_void_p),
+                ("stride", C.c_int64)]
+
+
+class Leaf(C.Structure):
+    _fields_ = [("model", C.c_void_p), ("seed", C.c_uint32), ("step", C.c_uint32),
+                ("rollout", RolloutCfg), ("parent", States), ("parent_ids", C.c_void_p),
+                ("idx", C.c_void_p), ("n", C.c_int32), ("depth", C.c_int32),
+                ("last_action", C.c_int32), ("cap", C.c_int32), ("states_out", States),
+                ("ids_out", C.c_void_p), ("perm", C.c_void_p), ("n_children", C.c_void_p),
+                ("child_z", C.c_void_p), ("child_n", C.c_void_p), ("child_off", C.c_void_p),
+                ("child_u0", C.c_void_p), ("child_l0", C.c_void_p), ("r_mean", C.c_void_p),
+                ("steps", C.c_void_p), ("sprime", States), ("r", C.c_void_p), ("z", C.c_void_p),
+                ("U", C.c_void_p), ("L", C.c_void_p), ("child_of", C.c_void_p)]
+
+
+# every symbol include/hdx.h declares
+EXPORTS = ["hdx_version", "hdx_init", "hdx_fini", "hdx_last_error", "hdx_upload_model",
+           "hdx_free_model", "hdx_model_actions", "hdx_model_max_children",
+           "hdx_sample_scenarios", "hdx_expand_leaf", "hdx_rollout_bounds", "hdx_philox",
+           "hdx_tree_create", "hdx_tree_destroy", "hdx_tree_add_children", "hdx_backup",
+           "hdx_tree_bounds", "hdx_tree_size"]
+
+_lib = None
+
+
+def load_library():
+    """Load libhdx.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libhdx.so is not built; run __graft_entry__.build() or "
+                          "python paper_1802_06215_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64, U32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32
+    L.hdx_version.restype = C.c_char_p
+    L.hdx_init.argtypes = [I32, C.POINTER(P)]
+    L.hdx_fini.argtypes = [P]
+    L.hdx_last_error.argtypes = [P]
+    L.hdx_last_error.restype = C.c_char_p
+    L.hdx_upload_model.argtypes = [P, C.POINTER(ModelDesc), C.POINTER(P)]
+    L.hdx_free_model.argtypes = [P, P]
+    L.hdx_model_actions.argtypes = [P]
+    L.hdx_model_max_children.argtypes = [P, I32]
+    L.hdx_sample_scenarios.argtypes = [P, P, C.POINTER(Belief), I32, U32, U32, States, P]
+    L.hdx_expand_leaf.argtypes = [P, P, I32, P]
+    L.hdx_rollout_bounds.argtypes = [P, P, C.POINTER(RolloutCfg), U32, U32, States, P, P, I64,
+                                     P, P, P, P]
+    L.hdx_philox.argtypes = [P, P, I64, U32, U32, P, P]
+    L.hdx_tree_create.argtypes = [I32, C.c_double, I32, C.c_double, C.c_double, C.POINTER(P)]
+    L.hdx_tree_destroy.argtypes = [P]
+    L.hdx_tree_add_children.argtypes = [P, I64, P, P, P, P, P, P, I32, C.POINTER(I64)]
+    L.hdx_backup.argtypes = [P, I64]
+    L.hdx_tree_bounds.argtypes = [P, I64, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.hdx_tree_size.argtypes = [P]
+    L.hdx_tree_size.restype = I64
+    for name in EXPORTS:
+        getattr(L, name)
+    _lib = L
+    return L
+
+
+def _dp(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def model_desc(d: dict) -> ModelDesc:
+    m = ModelDesc()
+    m.kind = d["kind"]
+    m.n_actions = d["n_actions"]
+    m.gamma = d["gamma"]
+    if d["kind"] == ROCKSAMPLE:
+        m.grid, m.n_rocks = d["n"], d["m"]
+        for i in range(d["m"]):
+            m.rock_x[i], m.rock_y[i] = int(d["rock_x"][i]), int(d["rock_y"][i])
+    else:
+        m.n_peds, m.n_goals, m.n_levels = d["n_peds"], d["n_goals"], d["n_levels"]
+        for g in range(d["n_goals"]):
+            m.goal_x[g], m.goal_y[g] = float(d["goal_x"][g]), float(d["goal_y"][g])
+        for f in ("path_len", "dt", "ped_speed", "sigma_h", "coll_radius", "r_collision", "r_step",
+                  "r_goal"):
+            setattr(m, f, float(d[f]))
+        m.p_fail = d["p_fail"]
+    return m
+
+
+def rollout_cfg(policy=POLICY_DEFAULT, max_steps=1 << 30, max_depth=-1, const_action=0) -> RolloutCfg:
+    c = RolloutCfg()
+    c.policy, c.const_action, c.max_steps, c.max_depth = policy, const_action, max_steps, max_depth
+    return c
+
+
+class Model:
+    def __init__(self, ctx, handle, desc):
+        self.ctx, self.handle, self.desc = ctx, handle, desc
+        self.kind = desc["kind"]
+        self.n_actions = desc["n_actions"]
+        self.n_peds = desc.get("n_peds", 0)
+
+    def max_children(self, n: int) -> int:
+        return self.ctx.lib.hdx_model_max_children(self.handle, n)
+
+
+def states_view(model: Model, st: dict) -> States:
+    """hdx_states over a dict of device tensors (library layout)."""
+    v = States()
+    if model.kind == ROCKSAMPLE:
+        v.w = _dp(st["w"])
+        v.stride = st["w"].shape[-1]
+    else:
+        v.s, v.car = _dp(st["s"]), _dp(st["car"])
+        if model.n_peds > 0:
+            v.px, v.py, v.goal = _dp(st["px"]), _dp(st["py"]), _dp(st["goal"])
+            v.stride = st["px"].stride(0) if st["px"].dim() == 2 else st["s"].numel()
+        else:
+            v.stride = st["s"].numel()
+    return v
+
+
+def empty_states(model: Model, n: int, device="cuda") -> dict:
+    if model.kind == ROCKSAMPLE:
+        return dict(w=torch.empty(n, dtype=torch.int32, device=device))
+    P = model.n_peds
+    return dict(s=torch.empty(n, dtype=torch.float32, device=device),
+                car=torch.empty(n, dtype=torch.int32, device=device),
+                px=torch.empty((P, n), dtype=torch.float32, device=device),
+                py=torch.empty((P, n), dtype=torch.float32, device=device),
+                goal=torch.empty((P, n), dtype=torch.uint8, device=device))
+
+
+class LeafBuffers:
+    """Device outputs of one leaf expansion (allocated once, reusable)."""
+
+    def __init__(self, model: Model, n: int, per_pair: bool = False, device="cuda"):
+        A = model.n_actions
+        cap = max(model.max_children(n), 1)
+        self.n, self.cap, self.A = n, cap, A
+        i32, f32 = torch.int32, torch.float32
+        self.states = empty_states(model, max(n, 1), device)
+        self.ids = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+        self.perm = torch.empty((A, max(n, 1)), dtype=i32, device=device)
+        self.n_children = torch.empty(A, dtype=i32, device=device)
+        self.child_z = torch.empty((A, cap), dtype=torch.int64, device=device)
+        self.child_n = torch.empty((A, cap), dtype=i32, device=device)
+        self.child_off = torch.empty((A, cap), dtype=i32, device=device)
+        self.child_u0 = torch.empty((A, cap), dtype=f32, device=device)
+        self.child_l0 = torch.empty((A, cap), dtype=f32, device=device)
+        self.r_mean = torch.empty(A, dtype=f32, device=device)
+        self.steps = torch.empty((A, 2), dtype=torch.int64, device=device)
+        self.per_pair = per_pair
+        if per_pair:
+            self.sprime = empty_states(model, max(A * n, 1), device)
+            self.r = torch.empty((A, max(n, 1)), dtype=f32, device=device)
+            self.z = torch.empty((A, max(n, 1)), dtype=torch.int64, device=device)
+            self.U = torch.empty((A, max(n, 1)), dtype=f32, device=device)
+            self.L = torch.empty((A, max(n, 1)), dtype=f32, device=device)
+            self.child_of = torch.empty((A, max(n, 1)), dtype=i32, device=device)
+
+
+def make_leaf(model: Model, parent: dict, parent_ids, idx, depth: int, last_action: int,
+              out: LeafBuffers, seed: int, step: int, cfg: RolloutCfg) -> Leaf:
+    """An hdx_leaf descriptor over device tensors (they must outlive the call)."""
+    L = Leaf()
+    L.model = model.handle
+    L.seed, L.step = seed, step
+    L.rollout = cfg
+    L.parent = states_view(model, parent)
+    L.parent_ids = _dp(parent_ids)
+    L.idx = _dp(idx)
+    L.n = int(idx.numel())
+    L.depth, L.last_action, L.cap = depth, last_action, out.cap
+    L.states_out = states_view(model, out.states)
+    L.ids_out = _dp(out.ids)
+    L.perm, L.n_children = _dp(out.perm), _dp(out.n_children)
+    L.child_z, L.child_n, L.child_off = _dp(out.child_z), _dp(out.child_n), _dp(out.child_off)
+    L.child_u0, L.child_l0 = _dp(out.child_u0), _dp(out.child_l0)
+    L.r_mean, L.steps = _dp(out.r_mean), _dp(out.steps)
+    if out.per_pair:
+        L.sprime = states_view(model, out.sprime)
+        L.r, L.z, L.U, L.L = _dp(out.r), _dp(out.z), _dp(out.U), _dp(out.L)
+        L.child_of = _dp(out.child_of)
+    return L
+
+
+class Context:
+    """An hdx context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        self.device = device
+        h = C.c_void_p()
+        self._check(self.lib.hdx_init(device, C.byref(h)), None)
+        self.handle = h
+
+    def _check(self, rc, handle="ctx"):
+        if rc != 0:
+            msg = ""
+            if handle is not None and getattr(self, "handle", None) is not None:
+                msg = self.lib.hdx_last_error(self.handle).decode()
+            raise HdxError(rc, msg)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            self.lib.hdx_fini(self.handle)
+            self.handle = None
+
+    def upload_model(self, desc: dict) -> Model:
+        h = C.c_void_p()
+        md = model_desc(desc)
+        self._check(self.lib.hdx_upload_model(self.handle, C.byref(md), C.byref(h)))
+        return Model(self, h, desc)
+
+    def sample_scenarios(self, model: Model, belief: dict, K: int, seed: int, step: int,
+                         out: dict | None = None, stream=None) -> dict:
+        out = empty_states(model, K) if out is None else out
+        b = Belief()
+        keep = []
+        if model.kind == ROCKSAMPLE:
+            p = np.ascontiguousarray(belief["p"], dtype=np.float64)
+            keep.append(p)
+            b.x, b.y, b.p_good = belief["x"], belief["y"], p.ctypes.data
+        else:
+            px = np.ascontiguousarray(belief["px"], dtype=np.float32)
+            py = np.ascontiguousarray(belief["py"], dtype=np.float32)
+            gp = np.ascontiguousarray(belief["goal_p"], dtype=np.float64)
+            keep += [px, py, gp]
+            b.s, b.level = float(belief["s"]), int(belief["level"])
+            b.px, b.py, b.goal_p = px.ctypes.data, py.ctypes.data, gp.ctypes.data
+        self._check(self.lib.hdx_sample_scenarios(self.handle, model.handle, C.byref(b), K, seed, step,
+                                                  states_view(model, out), _stream(stream)))
+        return out
+
+    def expand_leaf(self, leaves, stream=None) -> None:
+        leaves = list(leaves)
+        arr = (Leaf * len(leaves))(*leaves)
+        self._check(self.lib.hdx_expand_leaf(self.handle, C.cast(arr, C.c_void_p), len(leaves),
+                                             _stream(stream)))
+
+    def rollout_bounds(self, model: Model, cfg: RolloutCfg, states: dict, ids, depths, seed: int,
+                       step: int, stream=None):
+        n = int(ids.numel())
+        U = torch.empty(n, dtype=torch.float32, device=ids.device)
+        L = torch.empty(n, dtype=torch.float32, device=ids.device)
+        steps = torch.empty(n, dtype=torch.int32, device=ids.device)
+        self._check(self.lib.hdx_rollout_bounds(self.handle, model.handle, C.byref(cfg), seed, step,
+                                                states_view(model, states), _dp(ids), _dp(depths), n,
+                                                _dp(U), _dp(L), _dp(steps), _stream(stream)))
+        return U, L, steps
+
+    def philox(self, ctr, k0: int, k1: int, stream=None):
+        out = torch.empty_like(ctr)
+        self._check(self.lib.hdx_philox(self.handle, _dp(ctr), ctr.shape[0], k0, k1, _dp(out),
+                                        _stream(stream)))
+        return out
+
+
+class Tree:
+    """Host DESPOT tree with the Eq. 4 backup (hdx_tree_*)."""
+
+    def __init__(self, n_actions: int, gamma: float, n_root: int, u0: float, l0: float):
+        self.lib = load_library()
+        h = C.c_void_p()
+        rc = self.lib.hdx_tree_create(n_actions, gamma, n_root, u0, l0, C.byref(h))
+        if rc != 0:
+            raise HdxError(rc, "tree_create")
+        self.handle = h
+        self.n_actions = n_actions
+
+    def add_children(self, node: int, n_children, child_z, child_n, child_u0, child_l0, r_mean,
+                     cap: int) -> int:
+        arrs = [np.ascontiguousarray(n_children, np.int32), np.ascontiguousarray(child_z, np.uint64),
+                np.ascontiguousarray(child_n, np.int32), np.ascontiguousarray(child_u0, np.float32),
+                np.ascontiguousarray(child_l0, np.float32), np.ascontiguousarray(r_mean, np.float32)]
+        first = C.c_int64()
+        rc = self.lib.hdx_tree_add_children(self.handle, node, *[a.ctypes.data for a in arrs], cap,
+                                            C.byref(first))
+        if rc != 0:
+            raise HdxError(rc, "tree_add_children")
+        return first.value
+
+    def backup(self, node: int) -> None:
+        rc = self.lib.hdx_backup(self.handle, node)
+        if rc != 0:
+            raise HdxError(rc, "backup")
+
+    def bounds(self, node: int):
+        u, l = C.c_double(), C.c_double()
+        rc = self.lib.hdx_tree_bounds(self.handle, node, C.byref(u), C.byref(l))
+        if rc != 0:
+            raise HdxError(rc, "tree_bounds")
+        return u.value, l.value
+
+    def size(self) -> int:
+        return self.lib.hdx_tree_size(self.handle)
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None:
+            self.lib.hdx_tree_destroy(self.handle)
+            self.handle = None
