@@ -226,6 +226,13 @@ hdx_status hdx_rollout_bounds(hdx_ctx *ctx, const hdx_model *model, const hdx_ro
 hdx_status hdx_philox(hdx_ctx *ctx, const uint32_t *ctr, int64_t count, uint32_t k0, uint32_t k1,
                       uint32_t *out, hdx_stream stream);
 
+/* Rounding self-test of the FP32 operations the driving model's state
+ * update relies on being IEEE-754 exact on the device (device arrays of n):
+ * out[0][i] = sqrt(|a_i|), out[1][i] = a_i / b_i, out[2][i] = a_i*b_i + c_i
+ * (two roundings, no fused multiply-add), out[3][i] = floor(a_i). */
+hdx_status hdx_fp32_selftest(hdx_ctx *ctx, const float *a, const float *b, const float *c, int64_t n,
+                             float *out, hdx_stream stream);
+
 /* ---- Host side of the method: DESPOT tree and backup (Sec. III-A) ------ */
 
 /* A tree whose root holds n_root scenarios with bounds (u0, l0).  Node 0 is

@@ -172,6 +172,9 @@ hipError_t launch_bounds(const BoundsArgs &args, int32_t kind, int32_t n_peds, h
 hipError_t launch_philox(const uint32_t *ctr, int64_t count, uint32_t k0, uint32_t k1, uint32_t *out,
                          hipStream_t stream);
 
+hipError_t launch_fp32_selftest(const float *a, const float *b, const float *c, int64_t n, float *out,
+                                hipStream_t stream);
+
 int32_t max_dynamic_lds();
 
 }  // namespace hdx

@@ -403,13 +403,13 @@ __device__ void run_tile(const LeafTask &T, const int a, unsigned char *lds, con
             tu = tu + su[e];
             tl = tl + sl[e];
         }
-        T.child_u0[(int64_t)a * T.cap + c] = __fdiv_rn(tu, (float)nc[c]);
-        T.child_l0[(int64_t)a * T.cap + c] = __fdiv_rn(tl, (float)nc[c]);
+        T.child_u0[(int64_t)a * T.cap + c] = tu / (float)nc[c];
+        T.child_l0[(int64_t)a * T.cap + c] = tl / (float)nc[c];
     }
     if (tid == 0) {
         float tr = 0.0f;
         for (int t = 0; t < nchunks; ++t) tr = tr + chunk_r[t];
-        T.r_mean[a] = n > 0 ? __fdiv_rn(tr, (float)n) : 0.0f;
+        T.r_mean[a] = n > 0 ? tr / (float)n : 0.0f;
         T.steps[2 * a + 0] = (int64_t)stepc[0];
         T.steps[2 * a + 1] = (int64_t)stepc[1];
     }
@@ -559,6 +559,17 @@ __global__ void bounds_kernel(const BoundsArgs A) {
     if (A.steps) A.steps[k] = ns;
 }
 
+// FP32 rounding self-test: the operations the models' state updates use.
+__global__ void fp32_selftest_kernel(const float *a, const float *b, const float *c, int64_t n, float *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float x = a[i], y = b[i], z = c[i];
+    out[i] = __builtin_sqrtf(fabsf(x));
+    out[n + i] = x / y;
+    out[2 * n + i] = x * y + z;
+    out[3 * n + i] = floorf(x);
+}
+
 __global__ void philox_kernel(const uint32_t *ctr, int64_t count, uint32_t k0, uint32_t k1, uint32_t *out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
@@ -567,6 +578,15 @@ __global__ void philox_kernel(const uint32_t *ctr, int64_t count, uint32_t k0, u
 }
 
 }  // namespace
+
+hipError_t launch_fp32_selftest(const float *a, const float *b, const float *c, int64_t n, float *out,
+                                hipStream_t stream) {
+    const int threads = 256;
+    const int64_t blocks = (n + threads - 1) / threads;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(fp32_selftest_kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, a, b, c, n, out);
+    return hipGetLastError();
+}
 
 int32_t max_dynamic_lds() { return 160 * 1024 - 256; }
 

@@ -3,10 +3,13 @@
 // The step function is the deterministic simulative model g of DESPOT
 // (Sec. III-A): s', r, z = g(s, a, phi), where the scenario phi supplies the
 // random numbers through a counter-based generator indexed by (scenario id,
-// depth, block, tag).  State arithmetic of the driving model is FP32 and
-// compiled without contraction, with correctly rounded division and square
-// root, so results are bit-identical to any IEEE-754 FP32 evaluation in the
-// same operation order.
+// depth, block, tag).  State arithmetic of the driving model is FP32,
+// compiled without contraction and with correctly rounded division and
+// square root (plain "/" and __builtin_sqrtf under
+// -fhip-fp32-correctly-rounded-divide-sqrt; HIP's __fsqrt_rn/__fdiv_rn are
+// native approximations unless OCML_BASIC_ROUNDED_OPERATIONS is set), so the
+// results are bit-identical to any IEEE-754 FP32 evaluation in the same
+// operation order.
 #pragma once
 
 #include "internal.hpp"
@@ -183,17 +186,17 @@ struct PedOps {
                 const float gx = M.goal_x[st.goal[j]], gy = M.goal_y[st.goal[j]];
                 const float dx = gx - st.px[j];
                 const float dy = gy - st.py[j];
-                const float dist = __fsqrt_rn(dx * dx + dy * dy);
+                const float dist = __builtin_sqrtf(dx * dx + dy * dy);
                 if (dist <= step_len) {
                     st.px[j] = gx;
                     st.py[j] = gy;
                 } else {
-                    const float ux = __fdiv_rn(dx, dist), uy = __fdiv_rn(dy, dist);
+                    const float ux = dx / dist, uy = dy / dist;
                     const float t = half_sigma * noise;
                     const float t2 = t * t;
                     const float den = 1.0f + t2;
-                    const float c = __fdiv_rn(1.0f - t2, den);
-                    const float sn = __fdiv_rn(2.0f * t, den);
+                    const float c = (1.0f - t2) / den;
+                    const float sn = (2.0f * t) / den;
                     const float rx = ux * c - uy * sn;
                     const float ry = ux * sn + uy * c;
                     st.px[j] = st.px[j] + step_len * rx;
@@ -246,7 +249,7 @@ struct PedOps {
 
     __device__ static float upper(const DevModel &M, const State &st) {
         if (st.term) return 0.0f;
-        const float T = ceilf(__fdiv_rn(M.path_len - st.s, M.reach));
+        const float T = ceilf((M.path_len - st.s) / M.reach);
         int Ti = (int)T;
         if (Ti < 1) Ti = 1;
         if (Ti > kHorizon) Ti = kHorizon;

@@ -450,4 +450,12 @@ hdx_status hdx_philox(hdx_ctx *ctx, const uint32_t *ctr, int64_t count, uint32_t
     return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "philox launch");
 }
 
+hdx_status hdx_fp32_selftest(hdx_ctx *ctx, const float *a, const float *b, const float *c, int64_t n, float *out,
+                             hdx_stream stream) {
+    if (!ctx || n < 0 || (n > 0 && (!a || !b || !c || !out))) return fail(ctx, HDX_E_INVALID, "bad argument");
+    hipSetDevice(ctx->device);
+    hipError_t e = launch_fp32_selftest(a, b, c, n, out, (hipStream_t)stream);
+    return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "fp32 selftest launch");
+}
+
 }  // extern "C"

@@ -77,6 +77,7 @@ class Leaf(C.Structure):
 EXPORTS = ["hdx_version", "hdx_init", "hdx_fini", "hdx_last_error", "hdx_upload_model",
            "hdx_free_model", "hdx_model_actions", "hdx_model_max_children",
            "hdx_sample_scenarios", "hdx_expand_leaf", "hdx_rollout_bounds", "hdx_philox",
+           "hdx_fp32_selftest",
            "hdx_tree_create", "hdx_tree_destroy", "hdx_tree_add_children", "hdx_backup",
            "hdx_tree_bounds", "hdx_tree_size"]
 
@@ -107,6 +108,7 @@ def load_library():
     L.hdx_rollout_bounds.argtypes = [P, P, C.POINTER(RolloutCfg), U32, U32, States, P, P, I64,
                                      P, P, P, P]
     L.hdx_philox.argtypes = [P, P, I64, U32, U32, P, P]
+    L.hdx_fp32_selftest.argtypes = [P, P, P, P, I64, P, P]
     L.hdx_tree_create.argtypes = [I32, C.c_double, I32, C.c_double, C.c_double, C.POINTER(P)]
     L.hdx_tree_destroy.argtypes = [P]
     L.hdx_tree_add_children.argtypes = [P, I64, P, P, P, P, P, P, I32, C.POINTER(I64)]
@@ -318,6 +320,14 @@ class Context:
         self._check(self.lib.hdx_philox(self.handle, _dp(ctr), ctr.shape[0], k0, k1, _dp(out),
                                         _stream(stream)))
         return out
+
+
+def fp32_selftest(ctx: "Context", a, b, c, stream=None):
+    """Device results of sqrt|a|, a/b, a*b+c (unfused) and floor(a)."""
+    n = a.numel()
+    out = torch.empty((4, n), dtype=torch.float32, device=a.device)
+    ctx._check(ctx.lib.hdx_fp32_selftest(ctx.handle, _dp(a), _dp(b), _dp(c), n, _dp(out), _stream(stream)))
+    return out
 
 
 class Tree:

@@ -286,3 +286,23 @@ def test_argument_errors(ctx):
     with pytest.raises(H.HdxError) as e:
         ctx.expand_leaf([leaf])
     assert e.value.code == -4
+
+
+def test_fp32_rounding_selftest(ctx):
+    # sqrt and division correctly rounded, products and sums rounded
+    # separately (no fused multiply-add), denormals kept: numpy's float32
+    # arithmetic is the IEEE-754 reference
+    from paper_1802_06215_amd import hdx as H
+    rng = np.random.default_rng(11)
+    n = 1 << 20
+    a = (rng.standard_normal(n) * np.exp(rng.uniform(-20, 20, n))).astype(np.float32)
+    b = (rng.standard_normal(n) * np.exp(rng.uniform(-20, 20, n))).astype(np.float32)
+    c = (rng.standard_normal(n) * np.exp(rng.uniform(-20, 20, n))).astype(np.float32)
+    a[:1000] = (np.arange(1000) * np.float32(1e-42)).astype(np.float32)  # denormals
+    b[b == 0] = 1.0
+    dev = [torch.from_numpy(v).cuda() for v in (a, b, c)]
+    out = host(H.fp32_selftest(ctx, *dev))
+    with np.errstate(all="ignore"):
+        want = [np.sqrt(np.abs(a)), a / b, a * b + c, np.floor(a)]
+    for i, w in enumerate(want):
+        assert np.array_equal(out[i].view(np.uint32), w.astype(np.float32).view(np.uint32)), i
