@@ -1,0 +1,271 @@
+#!/usr/bin/env python3
+"""Throughput of DESPOT leaf expansion + rollouts (HyP-DESPOT, Sec. III-D)
+on one MI355X.
+
+One step = one pass of the hot path over a batch of leaves: gather + update,
+expansion of every (action, scenario) pair, grouping by observation, upper
+bounds, default-policy rollouts and the per-child reductions, for every
+leaf of the batch in one launch (a replayed HIP graph of the autotuned
+persistent or per-tile kernel).  Inputs are resident in device memory
+before timing starts.  Prints one JSON line.
+
+Workloads (all synthetic, seeded; see workloads/):
+  rs15  RockSample 15x15, 15 rocks, |A|=20, K=500, horizon 90, move-east
+        rollouts; 2048 leaves with n in {500,250,125,63,32}, depth 1..30
+  rs7   RockSample 7x7, 8 rocks, |A|=13, K=100, rollouts of depth 30
+  ped16 crowd driving, 16 pedestrians, 5 goals, |A|=3, K=500, rollouts 50
+  mix64 64 planner instances (RockSample 7..20 / driving, K in 100..500)
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: full-rate 32-bit VALU lane-ops/s
+PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+METRIC = "scenario-steps/s in leaf expand+rollout; search trials/s; surrogate vs rollout"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rs15", choices=["rs15", "rs7", "ped16", "mix64"])
+    ap.add_argument("--leaves", type=int, default=0, help="leaves per batch (0 = workload default)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU-baseline budget")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    return ap.parse_args()
+
+
+# ---------------------------------------------------------------------------
+# Algorithmic work per unit (32-bit lane operations the model definitions
+# require, counted from the equations, not from compiled code).
+# ---------------------------------------------------------------------------
+PHILOX_OPS = 10 * 8 + 9 * 2  # per round: 2 mul-lo, 2 mul-hi, 4 xor; key bumps
+
+
+def rs_ops(m):
+    step = 8                                  # decode, move/exit test, reward, discount, accumulate
+    return dict(step=step, sense_extra=PHILOX_OPS + 6, upper=3 + 6 * m, group=12, reduce=3)
+
+
+def ped_ops(P):
+    ped = 30                                  # Irwin-Hall, heading, sqrt, 2 div, rotation, update
+    step = (P + 1) * PHILOX_OPS + 6 + P * ped + 5 * P + 3
+    obs = (2 * P + 1) * 12                    # hash of speed and floored positions
+    return dict(step=step, obs=obs, upper=6, group=12, reduce=3)
+
+
+def algorithmic_ops(desc, n, A, expand_steps, rollout_steps):
+    """ALU work of one leaf: update + expansion + bounds + grouping + sums."""
+    pairs = n * A
+    if desc["kind"] == 0:
+        c = rs_ops(desc["m"])
+        sense_pairs = n * desc["m"]
+        return (n * c["step"] * A                # update step recomputed per action tile
+                + pairs * (c["step"] + c["upper"] + c["group"] + c["reduce"])
+                + sense_pairs * c["sense_extra"] + rollout_steps * c["step"])
+    c = ped_ops(desc["n_peds"])
+    return (n * c["step"] * A + pairs * (c["step"] + c["obs"] + c["upper"] + c["group"] + c["reduce"])
+            + rollout_steps * c["step"])
+
+
+# ---------------------------------------------------------------------------
+# Workloads
+# ---------------------------------------------------------------------------
+def build(ctx, args):
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1802_06215_amd import hdx as H
+
+    wl = args.workload
+    items = []  # (desc, model, fields, n_parent, idx, depth, last_action, seed, cfg tuple)
+    if wl in ("rs15", "rs7"):
+        grid, rocks, K, B = (15, 15, 500, 2048) if wl == "rs15" else (7, 8, 100, 8192)
+        B = args.leaves or B
+        desc = W.rocksample_model(grid, rocks, 1)
+        cfg = (0, 1 << 30, 90) if wl == "rs15" else (0, 30, -1)
+        for i in range(B):
+            n_leaf = max(1, K >> (i % 5))
+            lf = W.rocksample_leaf(desc, K, n_leaf, 1000 + i, depth=1 + i % 30)
+            items.append((desc, lf, 7, cfg))
+    elif wl == "ped16":
+        B = args.leaves or 512
+        desc = W.pednav_model(16, 5, 1)
+        for i in range(B):
+            n_leaf = max(1, 500 >> (i % 3))
+            lf = W.pednav_leaf(desc, 500, n_leaf, 1000 + i, depth=1 + i % 12)
+            items.append((desc, lf, 7, (0, 50, -1)))
+    else:
+        inst = W.mixed_instances(64, 42)
+        per = max(1, (args.leaves or 1024) // 64)
+        for j, it in enumerate(inst):
+            d, K = it["model"], it["K"]
+            for r in range(per):
+                n_leaf = max(1, K >> (r % 3))
+                if d["kind"] == 0:
+                    lf = W.rocksample_leaf(d, K, n_leaf, 5000 + j * per + r, depth=1 + r % 20)
+                    items.append((d, lf, j, (0, 1 << 30, 90)))
+                else:
+                    lf = W.pednav_leaf(d, K, n_leaf, 5000 + j * per + r, depth=1 + r % 12)
+                    items.append((d, lf, j, (0, 50, -1)))
+
+    models = {}
+    groups = {}
+    for k, (d, lf, seed, cfg) in enumerate(items):
+        key = id(d)
+        if key not in models:
+            models[key] = ctx.upload_model(d)
+        groups.setdefault(key, []).append(k)
+    leaves = [None] * len(items)
+    keep = []
+    slabs = []
+    for key, ks in groups.items():
+        m = models[key]
+        d = items[ks[0]][0]
+        n_max = max(len(items[k][1]["idx"]) for k in ks)
+        bufs, slab, st_slab = H.leaf_buffer_slab(m, len(ks), n_max)
+        slabs.append(slab)
+        for b, k in zip(bufs, ks):
+            _, lf, seed, cfg = items[k]
+            if d["kind"] == 0:
+                par = H.rocksample_states(lf["x"], lf["y"], lf["rocks"], lf["term"])
+            else:
+                par = H.pednav_states(lf["s"], lf["level"], lf["term"], lf["px"], lf["py"], lf["goal"])
+            pids = torch.from_numpy(lf["ids"].astype(np.int32)).cuda()
+            idx = torch.from_numpy(lf["idx"]).cuda()
+            b.n = len(lf["idx"])
+            leaves[k] = H.make_leaf(m, par, pids, idx, lf["depth"], lf["last_action"], b, seed, 0,
+                                    H.rollout_cfg(*cfg))
+            keep += [par, pids, idx]
+    torch.cuda.synchronize()
+    return dict(items=items, leaves=leaves, keep=keep, slabs=slabs, models=models, groups=list(groups.values()))
+
+
+def cpu_baseline(items, seconds):
+    """The oracle as it stands, single-threaded, over leaves of the same
+    batch until the time budget is spent."""
+    import numpy as np
+
+    import oracle
+    steps = 0
+    done = 0
+    t0 = time.perf_counter()
+    for d, lf, seed, cfg in items:
+        par = oracle.parent_states(d, lf)
+        res = oracle.expand_leaf(d, oracle.cfg(*cfg), par, lf["ids"].astype(np.uint32), lf["idx"],
+                                 lf["depth"], lf["last_action"], seed, 0)
+        steps += res["expand_steps"] + res["rollout_steps"]
+        done += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=steps / dt, unit="scenario-steps/s", cores=1, kind="oracle",
+                sample="first %d of %d leaves of the same batch, %.1f s, single thread" % (done, len(items), dt))
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the leaf-expansion path is measured on one MI355X; "
+              "multi-GPU runs are not part of this build (got --gpus %d, WORLD_SIZE %d)" % (args.gpus, world),
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1802_06215_amd import hdx as H
+
+    torch.cuda.set_device(0)
+    ctx = H.Context(0)
+    log("building workload", args.workload)
+    wl = build(ctx, args)
+    leaves, items = wl["leaves"], wl["items"]
+    n_tiles = sum(it[0]["n_actions"] for it in items)
+    batch = H.Batch(ctx, len(leaves), n_tiles)
+    batch.set_leaves(leaves)
+    torch.cuda.synchronize()
+    log("leaves %d tiles %d" % (len(leaves), n_tiles))
+    tuned_ms = None
+    if not args.no_autotune:
+        tuned_ms = batch.autotune(2)
+        log("autotuned schedule", batch.schedule(), "%.3f ms" % tuned_ms)
+    batch.use_graph(True)
+    for _ in range(args.warmup):
+        batch.launch()
+    torch.cuda.synchronize()
+    exp_steps = int(sum(s["steps"][..., 0].sum().item() for s in wl["slabs"]))
+    roll_steps = int(sum(s["steps"][..., 1].sum().item() for s in wl["slabs"]))
+    steps_per_launch = exp_steps + roll_steps
+
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        batch.launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = e0.elapsed_time(e1) / args.steps
+    value = steps_per_launch * args.steps / wall
+
+    # algorithmic ALU work per launch, from per-leaf step counts (slabs are
+    # grouped per model, in the order build() recorded)
+    ops = 0
+    for slab, ks in zip(wl["slabs"], wl["groups"]):
+        st = slab["steps"].sum(dim=1).cpu().numpy()
+        for j, k in enumerate(ks):
+            d, lf = items[k][0], items[k][1]
+            ops += algorithmic_ops(d, len(lf["idx"]), d["n_actions"], int(st[j, 0]), int(st[j, 1]))
+    achieved_tops = ops / (kernel_ms * 1e-3) / 1e12
+    roofline = dict(bound="alu", achieved=round(achieved_tops, 3), peak=round(PEAK_ALU_TOPS, 2),
+                    unit="TOP/s", frac=round(achieved_tops / PEAK_ALU_TOPS, 4), traffic=None,
+                    ops_per_launch=int(ops), kernel_ms=round(kernel_ms, 4))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)...")
+        cpu = cpu_baseline(items, args.cpu_seconds)
+        cpu["value"] = round(cpu["value"], 1)
+
+    names = dict(rs15="RS15 leaf expansion: RockSample 15x15, 15 rocks, |A|=20, K=500, horizon 90, move-east "
+                      "rollouts; %d synthetic leaves (n in {500,250,125,63,32}, depth 1..30)",
+                 rs7="RS7 leaf expansion: RockSample 7x7, 8 rocks, |A|=13, K=100, move-east rollouts of "
+                     "depth 30; %d synthetic leaves",
+                 ped16="PED16 leaf expansion: 16 pedestrians, 5 goals, |A|=3, K=500, rollouts of 50; "
+                       "%d synthetic leaves",
+                 mix64="MIX64: 64 planner instances (RockSample 7..20 / driving, K in {100,200,500}); "
+                       "%d leaves in one launch")
+    t, p, x = batch.schedule()
+    out = dict(metric=METRIC, value=round(value, 1), unit="scenario-steps/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=round(wall * 1e3 / args.steps, 4), higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="int32+fp32", data="synthetic",
+               config=dict(workload=names[args.workload] % len(leaves), leaves=len(leaves), tiles=n_tiles,
+                           scenario_steps_per_step=steps_per_launch, expand_steps=exp_steps,
+                           rollout_steps=roll_steps, schedule=dict(threads=t, persistent=p, xcd_remap=x),
+                           hip_graph=True, autotune_ms=tuned_ms),
+               roofline=roofline, cpu_baseline=cpu)
+    print(json.dumps(out), flush=True)
+    batch.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -212,6 +212,42 @@ hdx_status hdx_sample_scenarios(hdx_ctx *ctx, const hdx_model *model, const hdx_
 hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves,
                            hdx_stream stream);
 
+/* ---- Batched form: many leaves, many instances, one launch ------------- */
+
+/* A reusable batch of leaves (node-level parallelism of Sec. III-D, leaves
+ * from many search threads and many planner instances in one launch).  The
+ * descriptors live in device memory owned by the batch, so a launch does no
+ * host work and can be captured in a HIP graph and replayed; in persistent
+ * mode the kernel drains a tile queue with a fixed grid, so one captured
+ * graph serves every batch of the same kernel variant.  The library owns
+ * *out (release with hdx_batch_destroy).  A batch is used on one stream at
+ * a time. */
+typedef struct hdx_batch hdx_batch;
+hdx_status hdx_batch_create(hdx_ctx *ctx, int32_t max_leaves, int64_t max_tiles, hdx_batch **out);
+hdx_status hdx_batch_destroy(hdx_ctx *ctx, hdx_batch *batch);
+/* Validate and stage n_leaves leaves (same rules and errors as
+ * hdx_expand_leaf, plus HDX_E_CAPACITY beyond the batch's capacity); the
+ * copy to device memory is enqueued on `stream`. */
+hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *batch, const hdx_leaf *leaves, int32_t n_leaves,
+                                hdx_stream stream);
+/* Launch schedule: workgroup size (multiple of 64; capped at 512 for
+ * RockSample-only batches and 256 otherwise), persistent workgroups per CU
+ * (0 = one workgroup per tile), and the XCD-contiguous tile mapping.
+ * Results are bit-identical under every schedule. */
+hdx_status hdx_batch_set_schedule(hdx_ctx *ctx, hdx_batch *batch, int32_t threads, int32_t persistent,
+                                  int32_t xcd_remap);
+hdx_status hdx_batch_get_schedule(const hdx_batch *batch, int32_t *threads, int32_t *persistent,
+                                  int32_t *xcd_remap);
+/* Launch through a captured HIP graph (captured on first use and again
+ * when the kernel variant or schedule changes). */
+hdx_status hdx_batch_use_graph(hdx_ctx *ctx, hdx_batch *batch, int32_t enable);
+/* Expand every staged leaf: one kernel launch (or graph replay), no copies. */
+hdx_status hdx_batch_launch(hdx_ctx *ctx, hdx_batch *batch, hdx_stream stream);
+/* Autotuner: time each candidate schedule `reps` times on the staged leaves
+ * (an internal stream; blocks until done) and keep the fastest; *best_ms is
+ * its mean launch time.  Outputs are rewritten with identical values. */
+hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *batch, int32_t reps, float *best_ms);
+
 /* rollout_bounds (Eq. 12, 13 per scenario): for each of n states (device),
  * U = upper-bound heuristic and L = discounted default-policy rollout from
  * depths[k]; steps[k] = model steps taken.  ids/depths/U/L/steps are

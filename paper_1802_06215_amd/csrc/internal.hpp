@@ -82,7 +82,7 @@ struct Tile {
 // Work queue of the persistent launch; the last workgroup to leave resets
 // it, so a captured graph can be replayed without a separate clear.
 struct TileQueue {
-    int32_t next, done;
+    int32_t next, done, n_tiles, pad;
 };
 
 // Launch schedule of the expansion kernel; results never depend on it.
@@ -137,10 +137,20 @@ __host__ __device__ inline LdsLayout make_layout(int32_t np) {
     return L;
 }
 
-// Kernel launchers (kernels.hip).
-hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, int32_t n_tiles,
-                         TileQueue *d_queue, int32_t n_max, int32_t has_ped, int32_t ped_max,
-                         int32_t has_rs, const Schedule &sch, int32_t n_cu, hipStream_t stream);
+// Kernel variant a set of leaves needs: mode 0 RockSample only, 1 driving
+// only, 2 both; pm = pedestrian capacity of the register state; n_max sizes
+// the LDS carve-up.
+struct Variant {
+    int32_t mode, pm, n_max;
+};
+Variant pick_variant(int32_t has_rs, int32_t has_ped, int32_t ped_max, int32_t n_max);
+int32_t variant_max_threads(const Variant &v);
+
+// Kernel launchers (kernels.hip).  The expansion kernel reads the tile
+// count from d_queue->n_tiles; n_tiles here only sizes a non-persistent grid.
+hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queue, int32_t n_tiles,
+                         const Variant &v, const Schedule &sch, int32_t n_cu, hipStream_t stream);
+hipError_t configure_expand_kernels();
 
 struct SampleArgs {
     const DevModel *model;

@@ -435,12 +435,13 @@ template <int MODE>
 constexpr int max_threads() { return MODE == 0 ? 512 : 256; }
 
 template <int MODE, int PM>
-__global__ __launch_bounds__(max_threads<MODE>()) void expand_tiles(const LeafTask *tasks, const Tile *tiles, int32_t n_tiles,
-                                                     TileQueue *queue, int32_t n_max, int32_t persistent,
-                                                     int32_t xcd_remap) {
+__global__ __launch_bounds__(max_threads<MODE>()) void expand_tiles(const LeafTask *tasks, const Tile *tiles,
+                                                                    TileQueue *queue, int32_t n_max,
+                                                                    int32_t persistent, int32_t xcd_remap) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ int32_t s_tile;
     const LdsLayout Ly = make_layout(n_max);
+    const int32_t n_tiles = __builtin_amdgcn_readfirstlane(queue->n_tiles);
     int iter = 0;
     for (;;) {
         int t;
@@ -474,26 +475,22 @@ __global__ __launch_bounds__(max_threads<MODE>()) void expand_tiles(const LeafTa
 }
 
 template <int MODE, int PM>
-hipError_t launch_expand_t(const LeafTask *d_tasks, const Tile *d_tiles, int32_t n_tiles, TileQueue *d_queue,
+hipError_t configure_t() {
+    return hipFuncSetAttribute((const void *)expand_tiles<MODE, PM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               max_dynamic_lds());
+}
+
+template <int MODE, int PM>
+hipError_t launch_expand_t(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queue, int32_t n_tiles,
                            int32_t n_max, const Schedule &sch, int32_t n_cu, hipStream_t stream) {
     const LdsLayout Ly = make_layout(n_max);
-    auto kern = expand_tiles<MODE, PM>;
-    static bool configured = false;
-    if (!configured) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           max_dynamic_lds());
-        if (e != hipSuccess) return e;
-        configured = true;
-    }
-    int grid = n_tiles;
-    if (sch.persistent > 0) {
-        grid = n_cu * sch.persistent;
-        if (grid > n_tiles) grid = n_tiles;
-    }
+    // persistent: a fixed grid that drains the tile queue, so a captured
+    // graph stays valid for any tile count
+    const int grid = sch.persistent > 0 ? n_cu * sch.persistent : n_tiles;
     if (grid < 1) return hipSuccess;
     const int threads = sch.threads > max_threads<MODE>() ? max_threads<MODE>() : sch.threads;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), Ly.total, stream, d_tasks, d_tiles, n_tiles, d_queue,
-                       n_max, sch.persistent > 0 ? 1 : 0, sch.xcd_remap);
+    hipLaunchKernelGGL((expand_tiles<MODE, PM>), dim3(grid), dim3(threads), Ly.total, stream, d_tasks, d_tiles,
+                       d_queue, n_max, sch.persistent > 0 ? 1 : 0, sch.xcd_remap);
     return hipGetLastError();
 }
 
@@ -590,19 +587,34 @@ hipError_t launch_fp32_selftest(const float *a, const float *b, const float *c, 
 
 int32_t max_dynamic_lds() { return 160 * 1024 - 256; }
 
-hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, int32_t n_tiles, TileQueue *d_queue,
-                         int32_t n_max, int32_t has_ped, int32_t ped_max, int32_t has_rs, const Schedule &sch,
-                         int32_t n_cu, hipStream_t stream) {
-    if (!has_ped) return launch_expand_t<0, 1>(d_tasks, d_tiles, n_tiles, d_queue, n_max, sch, n_cu, stream);
-    const int pm = ped_max <= 8 ? 8 : ped_max <= 16 ? 16 : 32;
-    if (!has_rs) {
-        if (pm == 8) return launch_expand_t<1, 8>(d_tasks, d_tiles, n_tiles, d_queue, n_max, sch, n_cu, stream);
-        if (pm == 16) return launch_expand_t<1, 16>(d_tasks, d_tiles, n_tiles, d_queue, n_max, sch, n_cu, stream);
-        return launch_expand_t<1, 32>(d_tasks, d_tiles, n_tiles, d_queue, n_max, sch, n_cu, stream);
-    }
-    if (pm == 8) return launch_expand_t<2, 8>(d_tasks, d_tiles, n_tiles, d_queue, n_max, sch, n_cu, stream);
-    if (pm == 16) return launch_expand_t<2, 16>(d_tasks, d_tiles, n_tiles, d_queue, n_max, sch, n_cu, stream);
-    return launch_expand_t<2, 32>(d_tasks, d_tiles, n_tiles, d_queue, n_max, sch, n_cu, stream);
+Variant pick_variant(int32_t has_rs, int32_t has_ped, int32_t ped_max, int32_t n_max) {
+    Variant v;
+    v.mode = !has_ped ? 0 : (has_rs ? 2 : 1);
+    v.pm = !has_ped ? 1 : ped_max <= 8 ? 8 : ped_max <= 16 ? 16 : 32;
+    v.n_max = n_max < 1 ? 1 : n_max;
+    return v;
+}
+
+int32_t variant_max_threads(const Variant &v) { return v.mode == 0 ? max_threads<0>() : max_threads<1>(); }
+
+hipError_t configure_expand_kernels() {
+    hipError_t e = configure_t<0, 1>();
+    if (e == hipSuccess) e = configure_t<1, 8>();
+    if (e == hipSuccess) e = configure_t<1, 16>();
+    if (e == hipSuccess) e = configure_t<1, 32>();
+    if (e == hipSuccess) e = configure_t<2, 8>();
+    if (e == hipSuccess) e = configure_t<2, 16>();
+    if (e == hipSuccess) e = configure_t<2, 32>();
+    return e;
+}
+
+hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queue, int32_t n_tiles,
+                         const Variant &v, const Schedule &sch, int32_t n_cu, hipStream_t stream) {
+#define HDX_LAUNCH(M, P) launch_expand_t<M, P>(d_tasks, d_tiles, d_queue, n_tiles, v.n_max, sch, n_cu, stream)
+    if (v.mode == 0) return HDX_LAUNCH(0, 1);
+    if (v.mode == 1) return v.pm == 8 ? HDX_LAUNCH(1, 8) : v.pm == 16 ? HDX_LAUNCH(1, 16) : HDX_LAUNCH(1, 32);
+    return v.pm == 8 ? HDX_LAUNCH(2, 8) : v.pm == 16 ? HDX_LAUNCH(2, 16) : HDX_LAUNCH(2, 32);
+#undef HDX_LAUNCH
 }
 
 hipError_t launch_sample(const SampleArgs &args, hipStream_t stream) {

@@ -19,7 +19,7 @@ constexpr int kSlots = 16;  // concurrent expand calls in flight per context
 struct Slot {
     LeafTask *h_tasks = nullptr, *d_tasks = nullptr;
     Tile *h_tiles = nullptr, *d_tiles = nullptr;
-    TileQueue *d_queue = nullptr;
+    TileQueue *h_queue = nullptr, *d_queue = nullptr;
     int64_t cap_tasks = 0, cap_tiles = 0;
     hipEvent_t done = nullptr;
     bool used = false;
@@ -79,12 +79,13 @@ hdx_status hdx_init(int32_t device, hdx_ctx **out) {
             return HDX_E_DEVICE;
         }
         if (hipMalloc(&s.d_queue, sizeof(TileQueue)) != hipSuccess ||
+            hipHostMalloc(&s.h_queue, sizeof(TileQueue)) != hipSuccess ||
             hipMemset(s.d_queue, 0, sizeof(TileQueue)) != hipSuccess) {
             delete ctx;
             return HDX_E_NOMEM;
         }
     }
-    if (hipDeviceSynchronize() != hipSuccess) {
+    if (configure_expand_kernels() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         delete ctx;
         return HDX_E_DEVICE;
     }
@@ -102,6 +103,7 @@ hdx_status hdx_fini(hdx_ctx *ctx) {
         if (s.d_tasks) hipFree(s.d_tasks);
         if (s.d_tiles) hipFree(s.d_tiles);
         if (s.d_queue) hipFree(s.d_queue);
+        if (s.h_queue) hipHostFree(s.h_queue);
         if (s.done) hipEventDestroy(s.done);
     }
     delete ctx;
@@ -287,11 +289,19 @@ static hdx_status check_cfg(hdx_ctx *ctx, const hdx_model *m, const hdx_rollout_
     return HDX_OK;
 }
 
-hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves, hdx_stream stream) {
-    if (!ctx || (!leaves && n_leaves > 0) || n_leaves < 0) return fail(ctx, HDX_E_INVALID, "null argument");
-    if (n_leaves == 0) return HDX_OK;
+}  // extern "C"
+
+namespace {
+
+struct Shape {
     int64_t n_tiles = 0;
-    int32_t n_max = 1, ped_max = 0, has_ped = 0, has_rs = 0;
+    int32_t n_max = 1, has_rs = 0, has_ped = 0, ped_max = 0;
+};
+
+hdx_status validate_leaves(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves, Shape *sh) {
+    if (!leaves && n_leaves > 0) return fail(ctx, HDX_E_INVALID, "null leaves");
+    if (n_leaves < 0) return fail(ctx, HDX_E_INVALID, "negative leaf count");
+    Shape s;
     for (int32_t i = 0; i < n_leaves; ++i) {
         const hdx_leaf &L = leaves[i];
         if (!L.model) return fail(ctx, HDX_E_INVALID, "leaf without model");
@@ -315,47 +325,25 @@ hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
             if ((L.sprime.w || L.sprime.s) && !states_ok(L.model, L.sprime, (int64_t)A * L.n))
                 return fail(ctx, HDX_E_INVALID, "incomplete sprime arrays");
         }
-        n_tiles += A;
-        if (L.n > n_max) n_max = L.n;
+        s.n_tiles += A;
+        if (L.n > s.n_max) s.n_max = L.n;
         if (d.kind == HDX_PEDNAV) {
-            has_ped = 1;
-            if (d.n_peds > ped_max) ped_max = d.n_peds;
+            s.has_ped = 1;
+            if (d.n_peds > s.ped_max) s.ped_max = d.n_peds;
         } else {
-            has_rs = 1;
+            s.has_rs = 1;
         }
     }
-    if (n_tiles > (1ll << 30)) return fail(ctx, HDX_E_SHAPE, "too many tiles");
-    hipSetDevice(ctx->device);
-    std::lock_guard<std::mutex> lock(ctx->mu);
-    Slot &s = ctx->slots[ctx->next_slot];
-    ctx->next_slot = (ctx->next_slot + 1) % kSlots;
-    if (s.used) {
-        hipError_t e = hipEventSynchronize(s.done);
-        if (e != hipSuccess) return hip_fail(ctx, e, "staging wait");
-    }
-    if (s.cap_tasks < n_leaves || s.cap_tiles < n_tiles) {
-        int64_t ct = s.cap_tasks, cl = s.cap_tiles;
-        while (ct < n_leaves) ct = ct ? 2 * ct : 64;
-        while (cl < n_tiles) cl = cl ? 2 * cl : 1024;
-        if (s.h_tasks) hipHostFree(s.h_tasks);
-        if (s.h_tiles) hipHostFree(s.h_tiles);
-        if (s.d_tasks) hipFree(s.d_tasks);
-        if (s.d_tiles) hipFree(s.d_tiles);
-        s.h_tasks = s.d_tasks = nullptr;
-        s.h_tiles = s.d_tiles = nullptr;
-        s.cap_tasks = s.cap_tiles = 0;
-        if (hipHostMalloc(&s.h_tasks, ct * sizeof(LeafTask)) != hipSuccess ||
-            hipHostMalloc(&s.h_tiles, cl * sizeof(Tile)) != hipSuccess ||
-            hipMalloc(&s.d_tasks, ct * sizeof(LeafTask)) != hipSuccess ||
-            hipMalloc(&s.d_tiles, cl * sizeof(Tile)) != hipSuccess)
-            return fail(ctx, HDX_E_NOMEM, "descriptor staging allocation");
-        s.cap_tasks = ct;
-        s.cap_tiles = cl;
-    }
+    if (s.n_tiles > (1ll << 30)) return fail(ctx, HDX_E_SHAPE, "too many tiles");
+    *sh = s;
+    return HDX_OK;
+}
+
+void pack_leaves(const hdx_leaf *leaves, int32_t n_leaves, LeafTask *tasks, Tile *tiles) {
     int64_t t = 0;
     for (int32_t i = 0; i < n_leaves; ++i) {
         const hdx_leaf &L = leaves[i];
-        LeafTask &T = s.h_tasks[i];
+        LeafTask &T = tasks[i];
         memset(&T, 0, sizeof(T));
         T.model = L.model->d_model;
         T.kind = L.model->desc.kind;
@@ -390,23 +378,297 @@ hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
         T.U = L.U;
         T.L = L.L;
         T.child_of = L.child_of;
-        for (int a = 0; a < T.n_actions; ++a) s.h_tiles[t++] = Tile{i, a};
+        for (int a = 0; a < T.n_actions; ++a) tiles[t++] = Tile{i, a};
     }
+}
+
+// Default schedule: one scenario per lane up to the variant's workgroup cap,
+// one workgroup per tile, consecutive tiles kept on one XCD.
+Schedule default_schedule(const Variant &v) {
+    Schedule s;
+    int th = ((v.n_max + 63) / 64) * 64;
+    const int cap = variant_max_threads(v);
+    s.threads = th < 64 ? 64 : th > cap ? cap : th;
+    s.persistent = 0;
+    s.xcd_remap = 1;
+    return s;
+}
+
+hdx_status grow_pinned(hdx_ctx *ctx, LeafTask **h_tasks, LeafTask **d_tasks, int64_t *cap_tasks, Tile **h_tiles,
+                       Tile **d_tiles, int64_t *cap_tiles, int64_t need_tasks, int64_t need_tiles) {
+    if (*cap_tasks >= need_tasks && *cap_tiles >= need_tiles) return HDX_OK;
+    int64_t ct = *cap_tasks, cl = *cap_tiles;
+    while (ct < need_tasks) ct = ct ? 2 * ct : 64;
+    while (cl < need_tiles) cl = cl ? 2 * cl : 1024;
+    if (*h_tasks) hipHostFree(*h_tasks);
+    if (*h_tiles) hipHostFree(*h_tiles);
+    if (*d_tasks) hipFree(*d_tasks);
+    if (*d_tiles) hipFree(*d_tiles);
+    *h_tasks = *d_tasks = nullptr;
+    *h_tiles = *d_tiles = nullptr;
+    *cap_tasks = *cap_tiles = 0;
+    if (hipHostMalloc((void **)h_tasks, ct * sizeof(LeafTask)) != hipSuccess ||
+        hipHostMalloc((void **)h_tiles, cl * sizeof(Tile)) != hipSuccess ||
+        hipMalloc((void **)d_tasks, ct * sizeof(LeafTask)) != hipSuccess ||
+        hipMalloc((void **)d_tiles, cl * sizeof(Tile)) != hipSuccess)
+        return fail(ctx, HDX_E_NOMEM, "descriptor staging allocation");
+    *cap_tasks = ct;
+    *cap_tiles = cl;
+    return HDX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves, hdx_stream stream) {
+    if (!ctx) return HDX_E_INVALID;
+    Shape sh;
+    hdx_status st = validate_leaves(ctx, leaves, n_leaves, &sh);
+    if (st != HDX_OK || n_leaves == 0) return st;
+    hipSetDevice(ctx->device);
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    Slot &s = ctx->slots[ctx->next_slot];
+    ctx->next_slot = (ctx->next_slot + 1) % kSlots;
+    if (s.used) {
+        hipError_t e = hipEventSynchronize(s.done);
+        if (e != hipSuccess) return hip_fail(ctx, e, "staging wait");
+    }
+    st = grow_pinned(ctx, &s.h_tasks, &s.d_tasks, &s.cap_tasks, &s.h_tiles, &s.d_tiles, &s.cap_tiles, n_leaves,
+                     sh.n_tiles);
+    if (st != HDX_OK) return st;
+    pack_leaves(leaves, n_leaves, s.h_tasks, s.h_tiles);
+    *s.h_queue = TileQueue{0, 0, (int32_t)sh.n_tiles, 0};
     hipStream_t hs = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(s.d_tasks, s.h_tasks, n_leaves * sizeof(LeafTask), hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess) e = hipMemcpyAsync(s.d_tiles, s.h_tiles, n_tiles * sizeof(Tile), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(s.d_tiles, s.h_tiles, sh.n_tiles * sizeof(Tile), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(s.d_queue, s.h_queue, sizeof(TileQueue), hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return hip_fail(ctx, e, "descriptor copy");
-    Schedule sch = ctx->sched;
-    if (!ctx->sched_fixed) {
-        int th = ((n_max + 63) / 64) * 64;
-        sch.threads = th < 64 ? 64 : th > 512 ? 512 : th;
-    }
-    e = launch_expand(s.d_tasks, s.d_tiles, (int32_t)n_tiles, s.d_queue, n_max, has_ped, ped_max, has_rs, sch,
-                      ctx->n_cu, hs);
+    const Variant v = pick_variant(sh.has_rs, sh.has_ped, sh.ped_max, sh.n_max);
+    const Schedule sch = ctx->sched_fixed ? ctx->sched : default_schedule(v);
+    e = launch_expand(s.d_tasks, s.d_tiles, s.d_queue, (int32_t)sh.n_tiles, v, sch, ctx->n_cu, hs);
     if (e != hipSuccess) return hip_fail(ctx, e, "expand launch");
     e = hipEventRecord(s.done, hs);
     s.used = true;
     return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "event record");
+}
+
+}  // extern "C"
+
+struct hdx_batch {
+    LeafTask *h_tasks = nullptr, *d_tasks = nullptr;
+    Tile *h_tiles = nullptr, *d_tiles = nullptr;
+    TileQueue *h_queue = nullptr, *d_queue = nullptr;
+    int64_t cap_tasks = 0, cap_tiles = 0;
+    int32_t n_leaves = 0;
+    int64_t n_tiles = 0;
+    Variant var{0, 1, 1};
+    int32_t lds_n = 1;  // LDS sized for the largest leaf seen, so graphs survive smaller batches
+    Schedule sched{256, 0, 1};
+    bool sched_set = false;
+    hipStream_t work = nullptr;  // capture and tuning stream
+    hipEvent_t staged = nullptr, t0 = nullptr, t1 = nullptr;
+    bool staged_used = false;
+    bool graph_on = false, graph_ok = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    Variant g_var{0, 1, 1};
+    Schedule g_sched{0, 0, 0};
+    int64_t g_tiles = 0;
+};
+
+namespace {
+
+Variant batch_variant(const hdx_batch *b) {
+    Variant v = b->var;
+    v.n_max = b->lds_n;
+    return v;
+}
+
+hipError_t batch_direct_launch(hdx_ctx *ctx, hdx_batch *b, const Schedule &s, hipStream_t st) {
+    return launch_expand(b->d_tasks, b->d_tiles, b->d_queue, (int32_t)b->n_tiles, batch_variant(b), s, ctx->n_cu, st);
+}
+
+void drop_graph(hdx_batch *b) {
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_ok = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+hdx_status hdx_batch_create(hdx_ctx *ctx, int32_t max_leaves, int64_t max_tiles, hdx_batch **out) {
+    if (!ctx || !out || max_leaves < 1 || max_tiles < 1) return fail(ctx, HDX_E_INVALID, "bad argument");
+    hipSetDevice(ctx->device);
+    hdx_batch *b = new hdx_batch();
+    hdx_status st = grow_pinned(ctx, &b->h_tasks, &b->d_tasks, &b->cap_tasks, &b->h_tiles, &b->d_tiles, &b->cap_tiles,
+                                max_leaves, max_tiles);
+    if (st == HDX_OK &&
+        (hipHostMalloc(&b->h_queue, sizeof(TileQueue)) != hipSuccess ||
+         hipMalloc(&b->d_queue, sizeof(TileQueue)) != hipSuccess ||
+         hipMemset(b->d_queue, 0, sizeof(TileQueue)) != hipSuccess ||
+         hipStreamCreateWithFlags(&b->work, hipStreamNonBlocking) != hipSuccess ||
+         hipEventCreate(&b->staged) != hipSuccess || hipEventCreate(&b->t0) != hipSuccess ||
+         hipEventCreate(&b->t1) != hipSuccess || hipDeviceSynchronize() != hipSuccess))
+        st = fail(ctx, HDX_E_NOMEM, "batch allocation");
+    if (st != HDX_OK) {
+        hdx_batch_destroy(ctx, b);
+        return st;
+    }
+    *out = b;
+    return HDX_OK;
+}
+
+hdx_status hdx_batch_destroy(hdx_ctx *ctx, hdx_batch *b) {
+    if (!ctx || !b) return HDX_E_INVALID;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    drop_graph(b);
+    if (b->h_tasks) hipHostFree(b->h_tasks);
+    if (b->h_tiles) hipHostFree(b->h_tiles);
+    if (b->h_queue) hipHostFree(b->h_queue);
+    if (b->d_tasks) hipFree(b->d_tasks);
+    if (b->d_tiles) hipFree(b->d_tiles);
+    if (b->d_queue) hipFree(b->d_queue);
+    if (b->work) hipStreamDestroy(b->work);
+    if (b->staged) hipEventDestroy(b->staged);
+    if (b->t0) hipEventDestroy(b->t0);
+    if (b->t1) hipEventDestroy(b->t1);
+    delete b;
+    return HDX_OK;
+}
+
+hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *b, const hdx_leaf *leaves, int32_t n_leaves,
+                                hdx_stream stream) {
+    if (!ctx || !b) return HDX_E_INVALID;
+    Shape sh;
+    hdx_status st = validate_leaves(ctx, leaves, n_leaves, &sh);
+    if (st != HDX_OK) return st;
+    if (n_leaves > b->cap_tasks || sh.n_tiles > b->cap_tiles) return fail(ctx, HDX_E_CAPACITY, "batch capacity");
+    hipSetDevice(ctx->device);
+    if (b->staged_used) {
+        hipError_t e = hipEventSynchronize(b->staged);
+        if (e != hipSuccess) return hip_fail(ctx, e, "staging wait");
+    }
+    pack_leaves(leaves, n_leaves, b->h_tasks, b->h_tiles);
+    *b->h_queue = TileQueue{0, 0, (int32_t)sh.n_tiles, 0};
+    hipStream_t hs = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (n_leaves > 0) e = hipMemcpyAsync(b->d_tasks, b->h_tasks, n_leaves * sizeof(LeafTask), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && sh.n_tiles > 0)
+        e = hipMemcpyAsync(b->d_tiles, b->h_tiles, sh.n_tiles * sizeof(Tile), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_queue, b->h_queue, sizeof(TileQueue), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipEventRecord(b->staged, hs);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch descriptor copy");
+    b->staged_used = true;
+    b->n_leaves = n_leaves;
+    b->n_tiles = sh.n_tiles;
+    b->var = pick_variant(sh.has_rs, sh.has_ped, sh.ped_max, sh.n_max);
+    if (sh.n_max > b->lds_n) b->lds_n = sh.n_max;
+    if (!b->sched_set) b->sched = default_schedule(batch_variant(b));
+    return HDX_OK;
+}
+
+hdx_status hdx_batch_set_schedule(hdx_ctx *ctx, hdx_batch *b, int32_t threads, int32_t persistent,
+                                  int32_t xcd_remap) {
+    if (!ctx || !b) return HDX_E_INVALID;
+    if (threads < 64 || threads > 1024 || threads % 64 != 0 || persistent < 0 || persistent > 64)
+        return fail(ctx, HDX_E_INVALID, "schedule");
+    b->sched = Schedule{threads, persistent, xcd_remap ? 1 : 0};
+    b->sched_set = true;
+    return HDX_OK;
+}
+
+hdx_status hdx_batch_get_schedule(const hdx_batch *b, int32_t *threads, int32_t *persistent, int32_t *xcd_remap) {
+    if (!b || !threads || !persistent || !xcd_remap) return HDX_E_INVALID;
+    *threads = b->sched.threads > variant_max_threads(b->var) ? variant_max_threads(b->var) : b->sched.threads;
+    *persistent = b->sched.persistent;
+    *xcd_remap = b->sched.xcd_remap;
+    return HDX_OK;
+}
+
+hdx_status hdx_batch_use_graph(hdx_ctx *ctx, hdx_batch *b, int32_t enable) {
+    if (!ctx || !b) return HDX_E_INVALID;
+    b->graph_on = enable != 0;
+    return HDX_OK;
+}
+
+hdx_status hdx_batch_launch(hdx_ctx *ctx, hdx_batch *b, hdx_stream stream) {
+    if (!ctx || !b) return HDX_E_INVALID;
+    if (b->n_tiles == 0) return HDX_OK;
+    hipSetDevice(ctx->device);
+    hipStream_t hs = (hipStream_t)stream;
+    hipError_t e;
+    if (!b->graph_on) {
+        e = batch_direct_launch(ctx, b, b->sched, hs);
+        return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "batch launch");
+    }
+    const Variant v = batch_variant(b);
+    const bool same = b->graph_ok && v.mode == b->g_var.mode && v.pm == b->g_var.pm && v.n_max == b->g_var.n_max &&
+                      b->sched.threads == b->g_sched.threads && b->sched.persistent == b->g_sched.persistent &&
+                      b->sched.xcd_remap == b->g_sched.xcd_remap &&
+                      (b->sched.persistent > 0 || b->n_tiles == b->g_tiles);
+    if (!same) {
+        drop_graph(b);
+        e = hipStreamBeginCapture(b->work, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(ctx, e, "begin capture");
+        hipError_t le = batch_direct_launch(ctx, b, b->sched, b->work);
+        e = hipStreamEndCapture(b->work, &b->graph);
+        if (le != hipSuccess) return hip_fail(ctx, le, "captured launch");
+        if (e != hipSuccess) return hip_fail(ctx, e, "end capture");
+        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(b);
+            return hip_fail(ctx, e, "graph instantiate");
+        }
+        b->graph_ok = true;
+        b->g_var = v;
+        b->g_sched = b->sched;
+        b->g_tiles = b->n_tiles;
+    }
+    e = hipGraphLaunch(b->exec, hs);
+    return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "graph launch");
+}
+
+hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *b, int32_t reps, float *best_ms) {
+    if (!ctx || !b || reps < 1) return HDX_E_INVALID;
+    if (b->n_tiles == 0) return HDX_OK;
+    hipSetDevice(ctx->device);
+    if (b->staged_used) hipEventSynchronize(b->staged);
+    const Variant v = batch_variant(b);
+    const int tmax = variant_max_threads(v);
+    std::vector<Schedule> cand;
+    for (int th = 64; th <= tmax; th *= 2) {
+        cand.push_back(Schedule{th, 0, 0});
+        cand.push_back(Schedule{th, 0, 1});
+        for (int p : {1, 2, 4, 8}) cand.push_back(Schedule{th, p, 0});
+    }
+    float best = 1e30f;
+    Schedule best_s = b->sched;
+    for (const Schedule &s : cand) {
+        hipError_t e = batch_direct_launch(ctx, b, s, b->work);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(b->t0, b->work);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = batch_direct_launch(ctx, b, s, b->work);
+        if (e == hipSuccess) e = hipEventRecord(b->t1, b->work);
+        if (e == hipSuccess) e = hipEventSynchronize(b->t1);
+        if (e != hipSuccess) return hip_fail(ctx, e, "autotune launch");
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, b->t0, b->t1);
+        ms /= (float)reps;
+        if (ms < best) {
+            best = ms;
+            best_s = s;
+        }
+    }
+    b->sched = best_s;
+    b->sched_set = true;
+    drop_graph(b);
+    if (best_ms) *best_ms = best;
+    return HDX_OK;
 }
 
 hdx_status hdx_rollout_bounds(hdx_ctx *ctx, const hdx_model *m, const hdx_rollout_cfg *cfg, uint32_t seed,

@@ -77,7 +77,9 @@ class Leaf(C.Structure):
 EXPORTS = ["hdx_version", "hdx_init", "hdx_fini", "hdx_last_error", "hdx_upload_model",
            "hdx_free_model", "hdx_model_actions", "hdx_model_max_children",
            "hdx_sample_scenarios", "hdx_expand_leaf", "hdx_rollout_bounds", "hdx_philox",
-           "hdx_fp32_selftest",
+           "hdx_fp32_selftest", "hdx_batch_create", "hdx_batch_destroy", "hdx_batch_set_leaves",
+           "hdx_batch_set_schedule", "hdx_batch_get_schedule", "hdx_batch_use_graph",
+           "hdx_batch_launch", "hdx_batch_autotune",
            "hdx_tree_create", "hdx_tree_destroy", "hdx_tree_add_children", "hdx_backup",
            "hdx_tree_bounds", "hdx_tree_size"]
 
@@ -109,6 +111,14 @@ def load_library():
                                      P, P, P, P]
     L.hdx_philox.argtypes = [P, P, I64, U32, U32, P, P]
     L.hdx_fp32_selftest.argtypes = [P, P, P, P, I64, P, P]
+    L.hdx_batch_create.argtypes = [P, I32, I64, C.POINTER(P)]
+    L.hdx_batch_destroy.argtypes = [P, P]
+    L.hdx_batch_set_leaves.argtypes = [P, P, P, I32, P]
+    L.hdx_batch_set_schedule.argtypes = [P, P, I32, I32, I32]
+    L.hdx_batch_get_schedule.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]
+    L.hdx_batch_use_graph.argtypes = [P, P, I32]
+    L.hdx_batch_launch.argtypes = [P, P, P]
+    L.hdx_batch_autotune.argtypes = [P, P, I32, C.POINTER(C.c_float)]
     L.hdx_tree_create.argtypes = [I32, C.c_double, I32, C.c_double, C.c_double, C.POINTER(P)]
     L.hdx_tree_destroy.argtypes = [P]
     L.hdx_tree_add_children.argtypes = [P, I64, P, P, P, P, P, P, I32, C.POINTER(I64)]
@@ -225,6 +235,65 @@ class LeafBuffers:
             self.child_of = torch.empty((A, max(n, 1)), dtype=i32, device=device)
 
 
+class _SlabLeaf:
+    """Per-leaf views into slab tensors (same attributes as LeafBuffers)."""
+
+
+def leaf_buffer_slab(model: Model, count: int, n_max: int, device="cuda") -> list:
+    """Output buffers for `count` leaves of up to n_max scenarios, carved
+    from a few large tensors (one allocation per field)."""
+    A = model.n_actions
+    cap = max(model.max_children(n_max), 1)
+    n1 = max(n_max, 1)
+    i32, f32 = torch.int32, torch.float32
+    slabs = dict(ids=torch.empty((count, n1), dtype=i32, device=device),
+                 perm=torch.empty((count, A, n1), dtype=i32, device=device),
+                 n_children=torch.empty((count, A), dtype=i32, device=device),
+                 child_z=torch.empty((count, A, cap), dtype=torch.int64, device=device),
+                 child_n=torch.empty((count, A, cap), dtype=i32, device=device),
+                 child_off=torch.empty((count, A, cap), dtype=i32, device=device),
+                 child_u0=torch.empty((count, A, cap), dtype=f32, device=device),
+                 child_l0=torch.empty((count, A, cap), dtype=f32, device=device),
+                 r_mean=torch.empty((count, A), dtype=f32, device=device),
+                 steps=torch.empty((count, A, 2), dtype=torch.int64, device=device))
+    if model.kind == ROCKSAMPLE:
+        st = dict(w=torch.empty((count, n1), dtype=i32, device=device))
+    else:
+        P = model.n_peds
+        st = dict(s=torch.empty((count, n1), dtype=f32, device=device),
+                  car=torch.empty((count, n1), dtype=i32, device=device),
+                  px=torch.empty((count, P, n1), dtype=f32, device=device),
+                  py=torch.empty((count, P, n1), dtype=f32, device=device),
+                  goal=torch.empty((count, P, n1), dtype=torch.uint8, device=device))
+    out = []
+    for i in range(count):
+        b = _SlabLeaf()
+        b.n, b.cap, b.A, b.per_pair = n_max, cap, A, False
+        for k, v in slabs.items():
+            setattr(b, k, v[i])
+        b.states = {k: v[i] for k, v in st.items()}
+        out.append(b)
+    return out, slabs, st
+
+
+def rocksample_states(x, y, rocks, term, device="cuda") -> dict:
+    """Pack RockSample fields (robot cell, rock qualities [n, m], terminal
+    flags) into the library's state word layout, on the device."""
+    rocks = np.asarray(rocks, dtype=bool)
+    w = np.full(rocks.shape[0], int(x) | (int(y) << 5), dtype=np.int64)
+    w |= (rocks.astype(np.int64) << (10 + np.arange(rocks.shape[1]))).sum(1) if rocks.shape[1] else 0
+    w |= np.asarray(term, dtype=np.int64) << 30
+    return dict(w=torch.from_numpy(w.astype(np.int32)).to(device))
+
+
+def pednav_states(s, level, term, px, py, goal, device="cuda") -> dict:
+    """Crowd-driving fields in the library's struct-of-arrays layout."""
+    car = np.asarray(level, np.int32) | (np.asarray(term, np.int32) << 8)
+    f = lambda a, t: torch.from_numpy(np.ascontiguousarray(a, dtype=t)).to(device)
+    return dict(s=f(s, np.float32), car=f(car, np.int32), px=f(px, np.float32), py=f(py, np.float32),
+                goal=f(goal, np.uint8))
+
+
 def make_leaf(model: Model, parent: dict, parent_ids, idx, depth: int, last_action: int,
               out: LeafBuffers, seed: int, step: int, cfg: RolloutCfg) -> Leaf:
     """An hdx_leaf descriptor over device tensors (they must outlive the call)."""
@@ -320,6 +389,50 @@ class Context:
         self._check(self.lib.hdx_philox(self.handle, _dp(ctr), ctr.shape[0], k0, k1, _dp(out),
                                         _stream(stream)))
         return out
+
+
+class Batch:
+    """hdx_batch: leaves staged in device memory, launched as one kernel (or
+    a replayed HIP graph) with an autotuned schedule."""
+
+    def __init__(self, ctx: "Context", max_leaves: int, max_tiles: int):
+        self.ctx, self.lib = ctx, ctx.lib
+        h = C.c_void_p()
+        ctx._check(self.lib.hdx_batch_create(ctx.handle, max_leaves, max_tiles, C.byref(h)))
+        self.handle = h
+        self._keep = None
+
+    def set_leaves(self, leaves, stream=None):
+        leaves = list(leaves)
+        arr = (Leaf * max(len(leaves), 1))(*leaves)
+        self._keep = arr
+        self.ctx._check(self.lib.hdx_batch_set_leaves(self.ctx.handle, self.handle, C.cast(arr, C.c_void_p),
+                                                      len(leaves), _stream(stream)))
+
+    def set_schedule(self, threads: int, persistent: int, xcd_remap: int):
+        self.ctx._check(self.lib.hdx_batch_set_schedule(self.ctx.handle, self.handle, threads, persistent,
+                                                        xcd_remap))
+
+    def schedule(self):
+        t, p, x = C.c_int32(), C.c_int32(), C.c_int32()
+        self.ctx._check(self.lib.hdx_batch_get_schedule(self.handle, C.byref(t), C.byref(p), C.byref(x)))
+        return t.value, p.value, x.value
+
+    def use_graph(self, enable: bool = True):
+        self.ctx._check(self.lib.hdx_batch_use_graph(self.ctx.handle, self.handle, int(enable)))
+
+    def launch(self, stream=None):
+        self.ctx._check(self.lib.hdx_batch_launch(self.ctx.handle, self.handle, _stream(stream)))
+
+    def autotune(self, reps: int = 3) -> float:
+        ms = C.c_float()
+        self.ctx._check(self.lib.hdx_batch_autotune(self.ctx.handle, self.handle, reps, C.byref(ms)))
+        return ms.value
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            self.lib.hdx_batch_destroy(self.ctx.handle, self.handle)
+            self.handle = None
 
 
 def fp32_selftest(ctx: "Context", a, b, c, stream=None):
