@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (x3), to scale HBM byte counters")
+    ap.add_argument("--schedule", default="", help="threads,persistent,xcd_remap (skips the autotuner)")
     return ap.parse_args()
 
 
@@ -133,12 +136,14 @@ def build(ctx, args):
     leaves = [None] * len(items)
     keep = []
     slabs = []
+    state_slabs = []
     for key, ks in groups.items():
         m = models[key]
         d = items[ks[0]][0]
         n_max = max(len(items[k][1]["idx"]) for k in ks)
         bufs, slab, st_slab = H.leaf_buffer_slab(m, len(ks), n_max)
         slabs.append(slab)
+        state_slabs.append(st_slab)
         for b, k in zip(bufs, ks):
             _, lf, seed, cfg = items[k]
             if d["kind"] == 0:
@@ -152,7 +157,8 @@ def build(ctx, args):
                                     H.rollout_cfg(*cfg))
             keep += [par, pids, idx]
     torch.cuda.synchronize()
-    return dict(items=items, leaves=leaves, keep=keep, slabs=slabs, models=models, groups=list(groups.values()))
+    return dict(items=items, leaves=leaves, keep=keep, slabs=slabs, state_slabs=state_slabs, models=models,
+                groups=list(groups.values()))
 
 
 def cpu_baseline(items, seconds):
@@ -191,6 +197,14 @@ def main():
     from paper_1802_06215_amd import hdx as H
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        a = torch.ones(1 << 26, device="cuda")
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        log("copied %d bytes x3" % (a.numel() * 4))
+        return
     ctx = H.Context(0)
     log("building workload", args.workload)
     wl = build(ctx, args)
@@ -201,7 +215,9 @@ def main():
     torch.cuda.synchronize()
     log("leaves %d tiles %d" % (len(leaves), n_tiles))
     tuned_ms = None
-    if not args.no_autotune:
+    if args.schedule:
+        batch.set_schedule(*[int(v) for v in args.schedule.split(",")])
+    elif not args.no_autotune:
         tuned_ms = batch.autotune(2)
         log("autotuned schedule", batch.schedule(), "%.3f ms" % tuned_ms)
     batch.use_graph(True)

@@ -22,22 +22,27 @@ constexpr uint64_t kPedTerminalObs = ~0ull;
 
 // Model parameters and tables as the kernels read them (device memory, one
 // per uploaded model).  Derived constants are computed once on the host.
-struct DevModel {
+// The header is read with scalar loads; per-lane lookups of the discount
+// table go through an LDS copy of its first kGpowLds entries.
+struct ModelHdr {
     int32_t kind, n_actions;
     // RockSample
     int32_t grid, n_rocks;
     int32_t rock_x[kMaxRocks], rock_y[kMaxRocks];
-    int8_t rock_at[kMaxGrid * kMaxGrid];  // rock index at cell x + y*grid, -1 if none
-    uint8_t pad0[3];
-    uint32_t sense_thr_m1[kSenseEntries];  // floor(acc(d) 2^32) - 1, by squared distance
     // crowd driving
     int32_t n_peds, n_goals, n_levels, pad1;
     float goal_x[kMaxGoals], goal_y[kMaxGoals];
     float path_len, dt, step_len, half_sigma, coll_r2, reach, ih_scale;
-    float r_collision, r_step, r_goal;
+    float r_collision, r_step, r_goal, pad2;
     uint64_t fail_thr;  // action fails iff word < fail_thr
-    // discount powers gamma^j rounded to FP32
-    float gpow[kHorizon];
+};
+
+constexpr int kGpowLds = 256;
+
+struct DevModel {
+    ModelHdr h;
+    uint32_t sense_thr_m1[kSenseEntries];  // floor(acc(d) 2^32) - 1, by squared distance
+    float gpow[kHorizon];                  // discount powers gamma^j rounded to FP32
 };
 
 struct StatesPtr {
@@ -92,9 +97,19 @@ struct Schedule {
     int32_t xcd_remap;   // keep consecutive tiles (one leaf) on one XCD
 };
 
-// LDS carve-up of one tile, the same on host (for the launch size) and device.
+// LDS carve-up of one tile, the same on host (for the launch size) and
+// device.  Regions live in phases and are reused:
+//   zkey | tab    observations, then the open-addressing hash; after the
+//                 children are ranked the pair holds the chunk count table
+//                 (cnt), and later the grouped per-scenario sums (su, sl)
+//   dslot         slot of each distinct observation, then child sizes (nc)
+//   off           child offsets in the grouped order
+//   ubuf, lbuf    per-scenario U and L
+//   child         child index of each scenario (bits 0-15) and its rank
+//                 inside its 64-scenario chunk (bits 16-23)
+//   perm          grouped order (or the bitonic keys of the fallback path)
 struct LdsLayout {
-    uint32_t zkey, dslot, ubuf, lbuf, rbuf, child, tab, pos, perm, nc, off, cnt, misc, total;
+    uint32_t zkey, tab, dslot, off, ubuf, lbuf, child, perm, misc, gpow, total;
     int32_t np, p2, h, table_cap;
 };
 
@@ -110,10 +125,6 @@ __host__ __device__ inline LdsLayout make_layout(int32_t np) {
     L.np = np;
     L.p2 = pow2_at_least(np) < 64 ? 64 : pow2_at_least(np);
     L.h = pow2_at_least(2 * np) < 64 ? 64 : pow2_at_least(2 * np);
-    const int32_t nchunks = (np + 63) / 64;
-    int32_t tcap = nchunks * np;
-    if (tcap > 8192) tcap = 8192;
-    L.table_cap = tcap;
     uint32_t o = 0;
     auto take = [&](uint32_t bytes) {
         uint32_t at = o;
@@ -121,18 +132,16 @@ __host__ __device__ inline LdsLayout make_layout(int32_t np) {
         return at;
     };
     L.zkey = take(8u * L.p2);
+    L.tab = take(8u * L.h + 16u);
+    L.table_cap = (int32_t)((8u * L.p2 + 8u * L.h + 16u) / 4u);
     L.dslot = take(4u * L.p2);
+    L.off = take(4u * L.p2);
     L.ubuf = take(4u * np);
     L.lbuf = take(4u * np);
-    L.rbuf = take(4u * np);
     L.child = take(4u * np);
-    L.tab = take(8u * L.h + 8u);
-    L.pos = take(4u * np);
     L.perm = take(4u * L.p2);
-    L.nc = take(4u * L.p2);
-    L.off = take(4u * L.p2);
-    L.cnt = take(4u * L.table_cap);
     L.misc = take(64 + 4u * 64);
+    L.gpow = take(4u * (kGpowLds + 2 * kMaxGoals));
     L.total = o;
     return L;
 }

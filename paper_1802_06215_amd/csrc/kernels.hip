@@ -149,25 +149,25 @@ __device__ __forceinline__ bool has_states(const StatesPtr &S) { return S.w != n
 
 // One (leaf, action) tile.
 template <class Ops>
-__device__ void run_tile(const LeafTask &T, const int a, unsigned char *lds, const LdsLayout &Ly) {
-    const DevModel &M = *T.model;
-    const int n = T.n;
+__device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char *lds, const LdsLayout &Ly) {
+    float *gpow_lds = (float *)(lds + Ly.gpow);
+    const MView M = make_view(T->model, gpow_lds);
+    const int n = T->n;
+    const int cap = T->cap;
     const int tid = threadIdx.x, nt = blockDim.x, lane = lane_id(), wid = tid >> 6, nw = nt >> 6;
     uint64_t *zk = (uint64_t *)(lds + Ly.zkey);
+    uint64_t *tab = (uint64_t *)(lds + Ly.tab);
     uint32_t *dslot = (uint32_t *)(lds + Ly.dslot);
+    int32_t *nc = (int32_t *)(lds + Ly.dslot);  // after ranking
+    int32_t *off = (int32_t *)(lds + Ly.off);
     float *ub = (float *)(lds + Ly.ubuf);
     float *lb = (float *)(lds + Ly.lbuf);
-    float *rb = (float *)(lds + Ly.rbuf);
     int32_t *child = (int32_t *)(lds + Ly.child);
-    uint64_t *tab = (uint64_t *)(lds + Ly.tab);
-    int32_t *pos = (int32_t *)(lds + Ly.pos);
     int32_t *permb = (int32_t *)(lds + Ly.perm);
-    int32_t *nc = (int32_t *)(lds + Ly.nc);
-    int32_t *off = (int32_t *)(lds + Ly.off);
-    int32_t *cnt = (int32_t *)(lds + Ly.cnt);
-    int32_t *misc = (int32_t *)(lds + Ly.misc);             // [0] distinct count, [1] sentinel seen
+    int32_t *cnt = (int32_t *)(lds + Ly.zkey);  // zkey and tab are contiguous
+    int32_t *misc = (int32_t *)(lds + Ly.misc);                   // [0] distinct count, [1] sentinel seen
     unsigned long long *stepc = (unsigned long long *)(misc + 4);  // expansion, rollout steps
-    float *chunk_r = (float *)(misc + 8);                     // per-chunk reward sums (<= 32)
+    float *chunk_r = (float *)(misc + 8);                          // per-chunk reward sums (<= 32)
     int32_t *scan_scratch = misc + 48;
     const int H = Ly.h;
 
@@ -178,59 +178,76 @@ __device__ void run_tile(const LeafTask &T, const int a, unsigned char *lds, con
         stepc[0] = 0;
         stepc[1] = 0;
     }
+    stage_gpow(T->model, gpow_lds);
+    __syncthreads();
 
     RolloutParams RP;
-    RP.k0 = T.k0;
-    RP.k1 = T.k1;
-    RP.policy = T.policy;
-    RP.const_action = T.const_action;
-    RP.max_steps = T.max_steps;
-    RP.max_depth = T.max_depth;
-    RP.n_actions = T.n_actions;
+    RP.k0 = T->k0;
+    RP.k1 = T->k1;
+    RP.policy = T->policy;
+    RP.const_action = T->const_action;
+    RP.max_steps = T->max_steps;
+    RP.max_depth = T->max_depth;
+    RP.n_actions = T->n_actions;
+    const int depth = T->depth, last_action = T->last_action;
+    const StatesPtr parent = load_states(&T->parent);
+    const StatesPtr leaf_out = load_states(&T->out);
+    const StatesPtr sprime = load_states(&T->sprime);
     const bool write_leaf = (a == 0);
-    const bool pair_out = has_states(T.sprime);
+    const bool pair_out = has_states(sprime);
 
     // -- gather + update + expand + bounds + rollouts (Eq. 10, 12, 13) ------
+    // Every lane of a wavefront runs the same number of rounds, so the
+    // reward of a 64-scenario chunk can be summed with shuffles right here.
     int my_exp = 0, my_roll = 0;
-    for (int k = tid; k < n; k += nt) {
-        const int p = T.idx[k];
-        const uint32_t id = T.parent_ids[p];
-        typename Ops::State st;
-        Ops::load(M, T.parent, p, st);
-        if (T.last_action >= 0) {
-            float r0;
-            uint64_t z0;
-            Ops::template step<false>(M, st, T.last_action, id, (uint32_t)(T.depth - 1), T.k0, T.k1, r0, z0);
+    for (int base = 0; base < n; base += nt) {
+        const int k = base + tid;
+        const bool valid = k < n;
+        float r = 0.0f;
+        if (valid) {
+            const int p = T->idx[k];
+            const uint32_t id = T->parent_ids[p];
+            typename Ops::State st;
+            Ops::load(M, parent, p, st);
+            if (last_action >= 0) {
+                float r0;
+                uint64_t z0;
+                Ops::template step<false>(M, st, last_action, id, (uint32_t)(depth - 1), RP.k0, RP.k1, r0, z0);
+            }
+            if (write_leaf) {
+                Ops::store(M, leaf_out, k, st);
+                T->ids_out[k] = id;
+            }
+            my_exp += Ops::terminal(st) ? 0 : 1;
+            uint64_t z;
+            Ops::template step<true>(M, st, a, id, (uint32_t)depth, RP.k0, RP.k1, r, z);
+            const float U = Ops::upper(M, st);
+            const int64_t pk = (int64_t)a * n + k;
+            if (pair_out) Ops::store(M, sprime, pk, st);
+            int ns = 0;
+            const float L = rollout<Ops>(M, RP, st, id, depth + 1, ns);
+            my_roll += ns;
+            zk[k] = z;
+            ub[k] = U;
+            lb[k] = L;
+            if (T->r) T->r[pk] = r;
+            if (T->z) T->z[pk] = z;
+            if (T->U) T->U[pk] = U;
+            if (T->L) T->L[pk] = L;
         }
-        if (write_leaf) {
-            Ops::store(M, T.out, k, st);
-            T.ids_out[k] = id;
+        // mean step reward: plain sum of this 64-scenario chunk in k order
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const float o = __shfl_up(r, d, 64);
+            if (lane >= d) r = o + r;
         }
-        my_exp += Ops::terminal(st) ? 0 : 1;
-        float r;
-        uint64_t z;
-        Ops::template step<true>(M, st, a, id, (uint32_t)T.depth, T.k0, T.k1, r, z);
-        const float U = Ops::upper(M, st);
-        const int64_t pk = (int64_t)a * n + k;
-        if (pair_out) Ops::store(M, T.sprime, pk, st);
-        int ns = 0;
-        const float L = rollout<Ops>(M, RP, st, id, T.depth + 1, ns);
-        my_roll += ns;
-        zk[k] = z;
-        ub[k] = U;
-        lb[k] = L;
-        rb[k] = r;
-        if (T.r) T.r[pk] = r;
-        if (T.z) T.z[pk] = z;
-        if (T.U) T.U[pk] = U;
-        if (T.L) T.L[pk] = L;
+        if (lane == 63 && base + wid * 64 < n) chunk_r[(base >> 6) + wid] = r;
     }
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) {
         my_exp += __shfl_xor(my_exp, d, 64);
         my_roll += __shfl_xor(my_roll, d, 64);
     }
-    __syncthreads();  // LDS init above is visible from here on
     if (lane == 0) {
         atomicAdd(&stepc[0], (unsigned long long)my_exp);
         atomicAdd(&stepc[1], (unsigned long long)my_roll);
@@ -282,17 +299,18 @@ __device__ void run_tile(const LeafTask &T, const int a, unsigned char *lds, con
     }
 
     // -- child index of each scenario -----------------------------------------
+    // rank_of_slot overlays the hash table; the distinct keys stay in zkey
     int32_t *rank_of_slot = (int32_t *)tab;
     for (int i = tid; i < D; i += nt) {
         rank_of_slot[dslot[i]] = i;
-        if (i < T.cap) T.child_z[(int64_t)a * T.cap + i] = dkey[i];
+        if (i < cap) T->child_z[(int64_t)a * cap + i] = dkey[i];
     }
-    if (tid == 0) T.n_children[a] = D;
+    if (tid == 0) T->n_children[a] = D;
     __syncthreads();
     for (int k = tid; k < n; k += nt) {
         const int c = rank_of_slot[child[k]];
         child[k] = c;
-        if (T.child_of) T.child_of[(int64_t)a * n + k] = c;
+        if (T->child_of) T->child_of[(int64_t)a * n + k] = c;
     }
     __syncthreads();
 
@@ -315,7 +333,7 @@ __device__ void run_tile(const LeafTask &T, const int a, unsigned char *lds, con
                 if (lane == leader) cnt[t * D + cl] = __popcll(m);
                 rem &= ~m;
             }
-            if (valid) pos[k] = myrank;
+            if (valid) child[k] = c | (myrank << 16);
         }
         __syncthreads();
         for (int c = tid; c < D; c += nt) {
@@ -331,8 +349,10 @@ __device__ void run_tile(const LeafTask &T, const int a, unsigned char *lds, con
         __syncthreads();
         block_exclusive_scan(off, D, scan_scratch);
         for (int k = tid; k < n; k += nt) {
-            const int c = child[k];
-            permb[off[c] + cnt[(k >> 6) * D + c] + pos[k]] = k;
+            const int cw = child[k];
+            const int c = cw & 0xFFFF;
+            permb[off[c] + cnt[(k >> 6) * D + c] + (cw >> 16)] = k;
+            child[k] = c;
         }
         __syncthreads();
     } else {
@@ -352,14 +372,14 @@ __device__ void run_tile(const LeafTask &T, const int a, unsigned char *lds, con
         for (int i = tid; i < n; i += nt) permb[i] = (int32_t)(comp[i] & 0xFFFFu);
         __syncthreads();
     }
-    for (int i = tid; i < n; i += nt) T.perm[(int64_t)a * n + i] = permb[i];
-    for (int c = tid; c < D && c < T.cap; c += nt) {
-        T.child_n[(int64_t)a * T.cap + c] = nc[c];
-        T.child_off[(int64_t)a * T.cap + c] = off[c];
+    for (int i = tid; i < n; i += nt) T->perm[(int64_t)a * n + i] = permb[i];
+    for (int c = tid; c < D && c < cap; c += nt) {
+        T->child_n[(int64_t)a * cap + c] = nc[c];
+        T->child_off[(int64_t)a * cap + c] = off[c];
     }
 
     // -- per-child sums: segmented wavefront scans over the grouped order ------
-    float *su = (float *)zk;          // dkey no longer needed
+    float *su = (float *)(lds + Ly.zkey);  // keys, table and counts are done
     float *sl = su + Ly.p2;
     for (int t = wid; t < nchunks; t += nw) {
         const int i = t * 64 + lane;
@@ -385,17 +405,9 @@ __device__ void run_tile(const LeafTask &T, const int a, unsigned char *lds, con
             su[i] = vu;
             sl[i] = vl;
         }
-        // mean step reward: plain sum of this 64-scenario chunk in k order
-        float vr = (t * 64 + lane < n) ? rb[t * 64 + lane] : 0.0f;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const float o = __shfl_up(vr, d, 64);
-            if (lane >= d) vr = o + vr;
-        }
-        if (lane == 63) chunk_r[t] = vr;
     }
     __syncthreads();
-    for (int c = tid; c < D && c < T.cap; c += nt) {
+    for (int c = tid; c < D && c < cap; c += nt) {
         const int start = off[c], end = start + nc[c];
         float tu = 0.0f, tl = 0.0f;
         for (int t = start >> 6; t <= (end - 1) >> 6; ++t) {
@@ -403,21 +415,21 @@ __device__ void run_tile(const LeafTask &T, const int a, unsigned char *lds, con
             tu = tu + su[e];
             tl = tl + sl[e];
         }
-        T.child_u0[(int64_t)a * T.cap + c] = tu / (float)nc[c];
-        T.child_l0[(int64_t)a * T.cap + c] = tl / (float)nc[c];
+        T->child_u0[(int64_t)a * cap + c] = tu / (float)nc[c];
+        T->child_l0[(int64_t)a * cap + c] = tl / (float)nc[c];
     }
     if (tid == 0) {
         float tr = 0.0f;
         for (int t = 0; t < nchunks; ++t) tr = tr + chunk_r[t];
-        T.r_mean[a] = n > 0 ? tr / (float)n : 0.0f;
-        T.steps[2 * a + 0] = (int64_t)stepc[0];
-        T.steps[2 * a + 1] = (int64_t)stepc[1];
+        T->r_mean[a] = n > 0 ? tr / (float)n : 0.0f;
+        T->steps[2 * a + 0] = (int64_t)stepc[0];
+        T->steps[2 * a + 1] = (int64_t)stepc[1];
     }
     __syncthreads();  // LDS is reused by the next tile
 }
 
 template <int PM>
-__device__ __forceinline__ void run_ped(const LeafTask &T, int a, unsigned char *lds, const LdsLayout &Ly) {
+__device__ __forceinline__ void run_ped(const HDX_CONST LeafTask *T, int a, unsigned char *lds, const LdsLayout &Ly) {
     run_tile<PedOps<PM>>(T, a, lds, Ly);
 }
 
@@ -456,12 +468,13 @@ __global__ __launch_bounds__(max_threads<MODE>()) void expand_tiles(const LeafTa
         }
         ++iter;
         if (t >= n_tiles) break;
-        const Tile tile = tiles[t];
-        const LeafTask &T = tasks[tile.leaf];
-        if (MODE == 0 || (MODE == 2 && T.kind == HDX_ROCKSAMPLE)) {
-            run_tile<RsOps>(T, tile.action, lds, Ly);
+        const HDX_CONST Tile *tile = (const HDX_CONST Tile *)(tiles + t);
+        const HDX_CONST LeafTask *T = (const HDX_CONST LeafTask *)(tasks + tile->leaf);
+        const int a = tile->action;
+        if (MODE == 0 || (MODE == 2 && T->kind == HDX_ROCKSAMPLE)) {
+            run_tile<RsOps>(T, a, lds, Ly);
         } else if (MODE != 0) {
-            run_ped<PM>(T, tile.action, lds, Ly);
+            run_ped<PM>(T, a, lds, Ly);
         }
     }
     if (persistent && threadIdx.x == 0) {
@@ -500,12 +513,12 @@ hipError_t launch_expand_t(const LeafTask *d_tasks, const Tile *d_tiles, TileQue
 __global__ void sample_kernel(const SampleArgs A) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= A.K) return;
-    const DevModel &M = *A.model;
+    const HDX_CONST ModelHdr *M = (const HDX_CONST ModelHdr *)&A.model->h;
     const StatesPtr &S = A.out;
-    if (M.kind == HDX_ROCKSAMPLE) {
+    if (M->kind == HDX_ROCKSAMPLE) {
         int32_t w = A.x0 | (A.y0 << 5);
         uint4 u = make_uint4(0, 0, 0, 0);
-        for (int i = 0; i < M.n_rocks; ++i) {
+        for (int i = 0; i < M->n_rocks; ++i) {
             if ((i & 3) == 0) u = philox((uint32_t)k, 0, (uint32_t)(i >> 2), kTagInit, A.k0, A.k1);
             const uint32_t word = (i & 3) == 0 ? u.x : (i & 3) == 1 ? u.y : (i & 3) == 2 ? u.z : u.w;
             if ((uint64_t)word < A.rock_thr[i]) w |= 1 << (10 + i);
@@ -515,11 +528,11 @@ __global__ void sample_kernel(const SampleArgs A) {
         S.s[k] = A.s0;
         S.car[k] = A.level0 & 0xff;
         uint4 u = make_uint4(0, 0, 0, 0);
-        for (int j = 0; j < M.n_peds; ++j) {
+        for (int j = 0; j < M->n_peds; ++j) {
             if ((j & 3) == 0) u = philox((uint32_t)k, 0, (uint32_t)(j >> 2), kTagInit, A.k0, A.k1);
             const uint32_t word = (j & 3) == 0 ? u.x : (j & 3) == 1 ? u.y : (j & 3) == 2 ? u.z : u.w;
-            int g = M.n_goals - 1;
-            for (int q = 0; q < M.n_goals - 1; ++q) {
+            int g = M->n_goals - 1;
+            for (int q = 0; q < M->n_goals - 1; ++q) {
                 if ((uint64_t)word < A.goal_thr[j][q]) {
                     g = q;
                     break;
@@ -536,10 +549,13 @@ __global__ void sample_kernel(const SampleArgs A) {
 // rollout_bounds: one lane per state
 // ---------------------------------------------------------------------------
 template <class Ops>
-__global__ void bounds_kernel(const BoundsArgs A) {
+__global__ __launch_bounds__(256) void bounds_kernel(const BoundsArgs A) {
+    __shared__ float gpow_lds[kModelLdsFloats];
+    stage_gpow(A.model, gpow_lds);
+    __syncthreads();
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= A.n) return;
-    const DevModel &M = *A.model;
+    const MView M = make_view(A.model, gpow_lds);
     typename Ops::State st;
     Ops::load(M, A.states, k, st);
     RolloutParams RP;
@@ -549,7 +565,7 @@ __global__ void bounds_kernel(const BoundsArgs A) {
     RP.const_action = A.const_action;
     RP.max_steps = A.max_steps;
     RP.max_depth = A.max_depth;
-    RP.n_actions = M.n_actions;
+    RP.n_actions = M.h->n_actions;
     int ns = 0;
     A.U[k] = Ops::upper(M, st);
     A.L[k] = rollout<Ops>(M, RP, st, A.ids[k], A.depths[k], ns);

@@ -16,6 +16,66 @@
 
 namespace hdx {
 
+// Constant address space on the device (the host pass parses the same
+// declarations without it).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define HDX_CONST __attribute__((address_space(4)))
+#else
+#define HDX_CONST
+#endif
+
+// A model as the kernels see it: the header and the device tables through
+// the constant address space (never written by a kernel, so uniform
+// addresses become scalar loads), and the first kGpowLds discount powers
+// in LDS for per-lane lookups.
+struct MView {
+    const HDX_CONST ModelHdr *h;
+    const HDX_CONST uint32_t *thr;
+    const HDX_CONST float *gg;
+    const float *gl;
+    __device__ float gpow_uniform(int j) const { return gg[j]; }
+    __device__ float gpow_lane(int j) const { return j < kGpowLds ? gl[j] : gg[j]; }
+    // goal point coordinates, staged in LDS after the discount powers
+    __device__ float goal_x(int g) const { return gl[kGpowLds + g]; }
+    __device__ float goal_y(int g) const { return gl[kGpowLds + kMaxGoals + g]; }
+};
+
+__device__ __forceinline__ MView make_view(const DevModel *gm, const float *gpow_lds) {
+    MView v;
+    v.h = (const HDX_CONST ModelHdr *)&gm->h;
+    v.thr = (const HDX_CONST uint32_t *)gm->sense_thr_m1;
+    v.gg = (const HDX_CONST float *)gm->gpow;
+    v.gl = gpow_lds;
+    return v;
+}
+
+__device__ __forceinline__ StatesPtr load_states(const HDX_CONST StatesPtr *s) {
+    StatesPtr r;
+    r.w = s->w;
+    r.s = s->s;
+    r.car = s->car;
+    r.px = s->px;
+    r.py = s->py;
+    r.goal = s->goal;
+    r.stride = s->stride;
+    return r;
+}
+
+// Stage the first kGpowLds discount powers and the goal points of a model
+// into LDS (kModelLdsFloats floats; the caller synchronises afterwards).
+constexpr int kModelLdsFloats = kGpowLds + 2 * kMaxGoals;
+__device__ __forceinline__ void stage_gpow(const DevModel *gm, float *gpow_lds) {
+    const HDX_CONST float *g = (const HDX_CONST float *)gm->gpow;
+    const HDX_CONST ModelHdr *h = (const HDX_CONST ModelHdr *)&gm->h;
+    for (int j = threadIdx.x; j < kModelLdsFloats; j += blockDim.x) {
+        float v;
+        if (j < kGpowLds) v = g[j];
+        else if (j < kGpowLds + kMaxGoals) v = h->goal_x[j - kGpowLds];
+        else v = h->goal_y[j - kGpowLds - kMaxGoals];
+        gpow_lds[j] = v;
+    }
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64 multiplies, the key advanced by the Weyl increments in between.
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
@@ -46,19 +106,19 @@ struct RsOps {
     };
     static constexpr bool kHashObs = false;
 
-    __device__ static void load(const DevModel &, const StatesPtr &S, int64_t p, State &st) { st.w = S.w[p]; }
-    __device__ static void store(const DevModel &, const StatesPtr &S, int64_t p, const State &st) { S.w[p] = st.w; }
+    __device__ static void load(const MView &, const StatesPtr &S, int64_t p, State &st) { st.w = S.w[p]; }
+    __device__ static void store(const MView &, const StatesPtr &S, int64_t p, const State &st) { S.w[p] = st.w; }
     __device__ static bool terminal(const State &st) { return (st.w >> 30) & 1; }
 
     template <bool kObs>
-    __device__ static void step(const DevModel &M, State &st, int a, uint32_t id, uint32_t depth, uint32_t k0,
+    __device__ static void step(const MView &M, State &st, int a, uint32_t id, uint32_t depth, uint32_t k0,
                                 uint32_t k1, float &r, uint64_t &z) {
         int32_t w = st.w;
         r = 0.0f;
         z = 0;
         if ((w >> 30) & 1) return;  // absorbing
         int x = w & 31, y = (w >> 5) & 31;
-        const int n = M.grid;
+        const int n = M.h->grid;
         int32_t term = 0;
         if (a == 0) {
             if (y + 1 < n) ++y;
@@ -74,7 +134,9 @@ struct RsOps {
         } else if (a == 3) {
             if (x > 0) --x;
         } else if (a == 4) {
-            const int i = M.rock_at[x + y * n];
+            int i = -1;
+            for (int q = 0; q < M.h->n_rocks; ++q)
+                if (M.h->rock_x[q] == x && M.h->rock_y[q] == y) i = q;
             if (i >= 0) {
                 if ((w >> (10 + i)) & 1) {
                     r = 10.0f;
@@ -85,25 +147,25 @@ struct RsOps {
             }
         } else {
             const int i = a - 5;
-            const int dx = x - M.rock_x[i], dy = y - M.rock_y[i];
+            const int dx = x - M.h->rock_x[i], dy = y - M.h->rock_y[i];
             const uint32_t u = philox(id, depth, 0, kTagStep, k0, k1).x;
-            const int correct = u <= M.sense_thr_m1[dx * dx + dy * dy];
+            const int correct = u <= M.thr[dx * dx + dy * dy];
             const int truth = (w >> (10 + i)) & 1;
             z = (correct ? truth : !truth) ? 1 : 2;
         }
         st.w = (w & ~0x3ff) | x | (y << 5) | term;
     }
 
-    __device__ static float upper(const DevModel &M, const State &st) {
+    __device__ static float upper(const MView &M, const State &st) {
         if ((st.w >> 30) & 1) return 0.0f;
         const int x = st.w & 31, y = (st.w >> 5) & 31;
         float u = 0.0f;
-        for (int i = 0; i < M.n_rocks; ++i)
-            if ((st.w >> (10 + i)) & 1) u += 10.0f * M.gpow[abs(x - M.rock_x[i]) + abs(y - M.rock_y[i])];
-        return u + 10.0f * M.gpow[M.grid - 1 - x];
+        for (int i = 0; i < M.h->n_rocks; ++i)
+            if ((st.w >> (10 + i)) & 1) u += 10.0f * M.gpow_lane(abs(x - M.h->rock_x[i]) + abs(y - M.h->rock_y[i]));
+        return u + 10.0f * M.gpow_lane(M.h->grid - 1 - x);
     }
 
-    __device__ static int default_action(const DevModel &, const State &) { return 2; }  // move east
+    __device__ static int default_action(const MView &, const State &) { return 2; }  // move east
 };
 
 // ---------------------------------------------------------------------------
@@ -129,14 +191,14 @@ struct PedOps {
     };
     static constexpr bool kHashObs = true;
 
-    __device__ static void load(const DevModel &M, const StatesPtr &S, int64_t p, State &st) {
+    __device__ static void load(const MView &M, const StatesPtr &S, int64_t p, State &st) {
         st.s = S.s[p];
         const int32_t car = S.car[p];
         st.level = car & 0xff;
         st.term = (car >> 8) & 1;
 #pragma unroll
         for (int j = 0; j < PM; ++j) {
-            if (j < M.n_peds) {
+            if (j < M.h->n_peds) {
                 st.px[j] = S.px[j * S.stride + p];
                 st.py[j] = S.py[j * S.stride + p];
                 st.goal[j] = S.goal[j * S.stride + p];
@@ -147,12 +209,12 @@ struct PedOps {
             }
         }
     }
-    __device__ static void store(const DevModel &M, const StatesPtr &S, int64_t p, const State &st) {
+    __device__ static void store(const MView &M, const StatesPtr &S, int64_t p, const State &st) {
         S.s[p] = st.s;
         S.car[p] = (st.level & 0xff) | (st.term ? 0x100 : 0);
 #pragma unroll
         for (int j = 0; j < PM; ++j) {
-            if (j < M.n_peds) {
+            if (j < M.h->n_peds) {
                 S.px[j * S.stride + p] = st.px[j];
                 S.py[j * S.stride + p] = st.py[j];
                 S.goal[j * S.stride + p] = (uint8_t)st.goal[j];
@@ -162,7 +224,7 @@ struct PedOps {
     __device__ static bool terminal(const State &st) { return st.term != 0; }
 
     template <bool kObs>
-    __device__ static void step(const DevModel &M, State &st, int a, uint32_t id, uint32_t depth, uint32_t k0,
+    __device__ static void step(const MView &M, State &st, int a, uint32_t id, uint32_t depth, uint32_t k0,
                                 uint32_t k1, float &r, uint64_t &z) {
         if (st.term) {
             r = 0.0f;
@@ -170,20 +232,20 @@ struct PedOps {
             return;
         }
         const uint4 u0 = philox(id, depth, 0, kTagStep, k0, k1);
-        const bool failed = (uint64_t)u0.x < M.fail_thr;
+        const bool failed = (uint64_t)u0.x < M.h->fail_thr;
         int level = st.level;
-        if (a == 0 && !failed && level < M.n_levels - 1) level = level + 1;
+        if (a == 0 && !failed && level < M.h->n_levels - 1) level = level + 1;
         if (a == 2 && !failed && level > 0) level = level - 1;
         const float v = 0.5f * (float)level;
-        const float s_next = st.s + v * M.dt;
-        const float step_len = M.step_len, half_sigma = M.half_sigma;
+        const float s_next = st.s + v * M.h->dt;
+        const float step_len = M.h->step_len, half_sigma = M.h->half_sigma;
 #pragma unroll
         for (int j = 0; j < PM; ++j) {
-            if (j < M.n_peds) {
+            if (j < M.h->n_peds) {
                 const uint4 u = philox(id, depth, (uint32_t)(j + 1), kTagStep, k0, k1);
                 const int32_t sum = (int32_t)((u.x >> 8) + (u.y >> 8) + (u.z >> 8) + (u.w >> 8));
-                const float noise = (float)(sum - 33554430) * M.ih_scale;
-                const float gx = M.goal_x[st.goal[j]], gy = M.goal_y[st.goal[j]];
+                const float noise = (float)(sum - 33554430) * M.h->ih_scale;
+                const float gx = M.goal_x(st.goal[j]), gy = M.goal_y(st.goal[j]);
                 const float dx = gx - st.px[j];
                 const float dy = gy - st.py[j];
                 const float dist = __builtin_sqrtf(dx * dx + dy * dy);
@@ -206,22 +268,22 @@ struct PedOps {
         }
         bool collided = false;
         if (level > 0) {
-            const float r2 = M.coll_r2;
+            const float r2 = M.h->coll_r2;
 #pragma unroll
             for (int j = 0; j < PM; ++j) {
-                if (j < M.n_peds) {
+                if (j < M.h->n_peds) {
                     const float ddx = st.px[j] - s_next;
                     const float d2 = ddx * ddx + st.py[j] * st.py[j];
                     collided = collided || (d2 < r2);
                 }
             }
         }
-        float reward = M.r_step;
+        float reward = M.h->r_step;
         if (collided) {
-            reward = M.r_step + M.r_collision;
+            reward = M.h->r_step + M.h->r_collision;
             st.term = 1;
-        } else if (s_next >= M.path_len) {
-            reward = M.r_step + M.r_goal;
+        } else if (s_next >= M.h->path_len) {
+            reward = M.h->r_step + M.h->r_goal;
             st.term = 1;
         }
         st.s = s_next;
@@ -235,7 +297,7 @@ struct PedOps {
                 h = hash_field(h, level);
 #pragma unroll
                 for (int j = 0; j < PM; ++j) {
-                    if (j < M.n_peds) {
+                    if (j < M.h->n_peds) {
                         h = hash_field(h, (int32_t)floorf(st.px[j]));
                         h = hash_field(h, (int32_t)floorf(st.py[j]));
                     }
@@ -247,20 +309,20 @@ struct PedOps {
         }
     }
 
-    __device__ static float upper(const DevModel &M, const State &st) {
+    __device__ static float upper(const MView &M, const State &st) {
         if (st.term) return 0.0f;
-        const float T = ceilf((M.path_len - st.s) / M.reach);
+        const float T = ceilf((M.h->path_len - st.s) / M.h->reach);
         int Ti = (int)T;
         if (Ti < 1) Ti = 1;
         if (Ti > kHorizon) Ti = kHorizon;
-        return M.r_goal * M.gpow[Ti - 1];
+        return M.h->r_goal * M.gpow_lane(Ti - 1);
     }
 
-    __device__ static int default_action(const DevModel &M, const State &st) {
+    __device__ static int default_action(const MView &M, const State &st) {
         bool brake = false;
 #pragma unroll
         for (int j = 0; j < PM; ++j) {
-            if (j < M.n_peds) {
+            if (j < M.h->n_peds) {
                 const float ahead = st.px[j] - st.s;
                 brake = brake || (ahead >= 0.0f && ahead <= 3.0f && fabsf(st.py[j]) < 1.5f);
             }
@@ -278,7 +340,7 @@ struct RolloutParams {
 // at a terminal state or after min(max_steps, max_depth - d0) steps; the
 // tail value past the horizon is 0.  Accumulates in FP32 in step order.
 template <class Ops>
-__device__ __forceinline__ float rollout(const DevModel &M, const RolloutParams &P, typename Ops::State st,
+__device__ __forceinline__ float rollout(const MView &M, const RolloutParams &P, typename Ops::State st,
                                          uint32_t id, int d0, int &nsteps) {
     int n_roll = P.max_steps;
     if (P.max_depth >= 0 && P.max_depth - d0 < n_roll) n_roll = P.max_depth - d0;
@@ -298,7 +360,7 @@ __device__ __forceinline__ float rollout(const DevModel &M, const RolloutParams 
         float r;
         uint64_t z;
         Ops::template step<false>(M, st, a, id, depth, P.k0, P.k1, r, z);
-        value += M.gpow[j] * r;
+        value += M.gpow_uniform(j) * r;
         ++nsteps;
     }
     return value;

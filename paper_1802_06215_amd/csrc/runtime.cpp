@@ -116,41 +116,42 @@ hdx_status hdx_upload_model(hdx_ctx *ctx, const hdx_model_desc *d, hdx_model **o
     if (!ctx || !d || !out) return fail(ctx, HDX_E_INVALID, "null argument");
     *out = nullptr;
     if (!(d->gamma > 0.0 && d->gamma <= 1.0)) return fail(ctx, HDX_E_INVALID, "gamma must be in (0, 1]");
-    DevModel *h = new DevModel();
-    memset(h, 0, sizeof(DevModel));
+    DevModel *dm = new DevModel();
+    memset(dm, 0, sizeof(DevModel));
+    ModelHdr *h = &dm->h;
     h->kind = d->kind;
     if (d->kind == HDX_ROCKSAMPLE) {
         if (d->grid < 1 || d->grid > kMaxGrid || d->n_rocks < 0 || d->n_rocks > kMaxRocks) {
-            delete h;
+            delete dm;
             return fail(ctx, HDX_E_SHAPE, "grid must be 1..31 and rocks 0..20");
         }
         h->n_actions = 5 + d->n_rocks;
         h->grid = d->grid;
         h->n_rocks = d->n_rocks;
-        memset(h->rock_at, -1, sizeof(h->rock_at));
+        std::vector<int8_t> rock_at(kMaxGrid * kMaxGrid, -1);
         for (int i = 0; i < d->n_rocks; ++i) {
             const int x = d->rock_x[i], y = d->rock_y[i];
-            if (x < 0 || x >= d->grid || y < 0 || y >= d->grid || h->rock_at[x + y * d->grid] >= 0) {
-                delete h;
+            if (x < 0 || x >= d->grid || y < 0 || y >= d->grid || rock_at[x + y * d->grid] >= 0) {
+                delete dm;
                 return fail(ctx, HDX_E_INVALID, "rocks must lie on distinct grid cells");
             }
             h->rock_x[i] = x;
             h->rock_y[i] = y;
-            h->rock_at[x + y * d->grid] = (int8_t)i;
+            rock_at[x + y * d->grid] = (int8_t)i;
         }
         // sensor accuracy 0.5 + 0.5 * 2^(-d/20) as a threshold on a 32-bit word
         for (int d2 = 0; d2 < kSenseEntries; ++d2) {
             const double acc = 0.5 + 0.5 * pow(2.0, -sqrt((double)d2) / 20.0);
-            h->sense_thr_m1[d2] = (uint32_t)(prob_threshold(acc) - 1);
+            dm->sense_thr_m1[d2] = (uint32_t)(prob_threshold(acc) - 1);
         }
     } else if (d->kind == HDX_PEDNAV) {
         if (d->n_peds < 0 || d->n_peds > kMaxPeds || d->n_goals < 1 || d->n_goals > kMaxGoals ||
             d->n_levels < 1 || d->n_levels > 255) {
-            delete h;
+            delete dm;
             return fail(ctx, HDX_E_SHAPE, "pedestrians 0..32, goals 1..8, levels 1..255");
         }
         if (!(d->p_fail >= 0.0 && d->p_fail < 1.0) || !(d->dt > 0.0f)) {
-            delete h;
+            delete dm;
             return fail(ctx, HDX_E_INVALID, "p_fail must be in [0, 1) and dt > 0");
         }
         h->n_actions = 3;
@@ -168,7 +169,7 @@ hdx_status hdx_upload_model(hdx_ctx *ctx, const hdx_model_desc *d, hdx_model **o
         h->coll_r2 = d->coll_radius * d->coll_radius;
         h->reach = (0.5f * (float)(d->n_levels - 1)) * d->dt;
         if (!(h->reach > 0.0f)) {
-            delete h;
+            delete dm;
             return fail(ctx, HDX_E_INVALID, "need at least two speed levels");
         }
         h->ih_scale = (float)(sqrt(3.0) / 16777216.0);
@@ -177,20 +178,20 @@ hdx_status hdx_upload_model(hdx_ctx *ctx, const hdx_model_desc *d, hdx_model **o
         h->r_goal = d->r_goal;
         h->fail_thr = prob_threshold(d->p_fail);
     } else {
-        delete h;
+        delete dm;
         return fail(ctx, HDX_E_UNSUPPORTED, "unknown model kind");
     }
     if (d->n_actions != h->n_actions) {
-        delete h;
+        delete dm;
         return fail(ctx, HDX_E_INVALID, "n_actions does not match the model");
     }
-    for (int j = 0; j < kHorizon; ++j) h->gpow[j] = (float)pow(d->gamma, j);
+    for (int j = 0; j < kHorizon; ++j) dm->gpow[j] = (float)pow(d->gamma, j);
     hipSetDevice(ctx->device);
     hdx_model *m = new hdx_model();
     m->desc = *d;
     hipError_t e = hipMalloc(&m->d_model, sizeof(DevModel));
-    if (e == hipSuccess) e = hipMemcpy(m->d_model, h, sizeof(DevModel), hipMemcpyHostToDevice);
-    delete h;
+    if (e == hipSuccess) e = hipMemcpy(m->d_model, dm, sizeof(DevModel), hipMemcpyHostToDevice);
+    delete dm;
     if (e != hipSuccess) {
         if (m->d_model) hipFree(m->d_model);
         delete m;
@@ -460,6 +461,7 @@ struct hdx_batch {
     Tile *h_tiles = nullptr, *d_tiles = nullptr;
     TileQueue *h_queue = nullptr, *d_queue = nullptr;
     int64_t cap_tasks = 0, cap_tiles = 0;
+    int64_t max_leaves = 0, max_tiles = 0;  // capacity the caller asked for
     int32_t n_leaves = 0;
     int64_t n_tiles = 0;
     Variant var{0, 1, 1};
@@ -505,6 +507,8 @@ hdx_status hdx_batch_create(hdx_ctx *ctx, int32_t max_leaves, int64_t max_tiles,
     if (!ctx || !out || max_leaves < 1 || max_tiles < 1) return fail(ctx, HDX_E_INVALID, "bad argument");
     hipSetDevice(ctx->device);
     hdx_batch *b = new hdx_batch();
+    b->max_leaves = max_leaves;
+    b->max_tiles = max_tiles;
     hdx_status st = grow_pinned(ctx, &b->h_tasks, &b->d_tasks, &b->cap_tasks, &b->h_tiles, &b->d_tiles, &b->cap_tiles,
                                 max_leaves, max_tiles);
     if (st == HDX_OK &&
@@ -548,7 +552,7 @@ hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *b, const hdx_leaf *leav
     Shape sh;
     hdx_status st = validate_leaves(ctx, leaves, n_leaves, &sh);
     if (st != HDX_OK) return st;
-    if (n_leaves > b->cap_tasks || sh.n_tiles > b->cap_tiles) return fail(ctx, HDX_E_CAPACITY, "batch capacity");
+    if (n_leaves > b->max_leaves || sh.n_tiles > b->max_tiles) return fail(ctx, HDX_E_CAPACITY, "batch capacity");
     hipSetDevice(ctx->device);
     if (b->staged_used) {
         hipError_t e = hipEventSynchronize(b->staged);
