@@ -145,7 +145,9 @@ struct RsOps {
                     r = -10.0f;
                 }
             }
-        } else {
+        } else if (kObs) {
+            // a sense leaves the state unchanged; its random reading is only
+            // drawn when the observation is wanted
             const int i = a - 5;
             const int dx = x - M.h->rock_x[i], dy = y - M.h->rock_y[i];
             const uint32_t u = philox(id, depth, 0, kTagStep, k0, k1).x;
