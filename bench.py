@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (x3), to scale HBM byte counters")
+    ap.add_argument("--search-seconds", type=float, default=1.0,
+                    help="planning budget of each search measurement (rs15 only; 0 = skip)")
     ap.add_argument("--schedule", default="", help="threads,persistent,xcd_remap (skips the autotuner)")
     return ap.parse_args()
 
@@ -255,6 +257,24 @@ def main():
                     unit="TOP/s", frac=round(achieved_tops / PEAK_ALU_TOPS, 4), traffic=None,
                     ops_per_launch=int(ops), kernel_ms=round(kernel_ms, 4))
 
+    search = None
+    if args.workload == "rs15" and args.search_seconds > 0:
+        import workloads as W
+        desc = items[0][0]
+        m = wl["models"][id(desc)]
+        search = []
+        for threads, batch in ((4, 0), (8, 0), (8, 8), (16, 16)):
+            res = ctx.search(m, W.rocksample_belief(desc), K=500, n_threads=threads, max_depth=90,
+                             batch_leaves=batch, time_budget_s=args.search_seconds,
+                             rollout=H.rollout_cfg(0, 1 << 30, 90), seed=3)
+            search.append(dict(threads=threads, leaf_batcher=batch > 0,
+                               trials_per_s=round(res["trials"] / res["elapsed_s"], 1),
+                               expansions=res["expansions"], launches=res["launches"],
+                               scenario_steps_per_s=round(res["scenario_steps"] / res["elapsed_s"], 1),
+                               nodes=res["nodes"], depth=res["max_depth_reached"],
+                               root_gap=round(res["u_root"] - res["l_root"], 4)))
+            log("search", search[-1])
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)...")
@@ -277,7 +297,9 @@ def main():
                            scenario_steps_per_step=steps_per_launch, expand_steps=exp_steps,
                            rollout_steps=roll_steps, schedule=dict(threads=t, persistent=p, xcd_remap=x),
                            hip_graph=True, autotune_ms=tuned_ms),
-               roofline=roofline, cpu_baseline=cpu)
+               roofline=roofline, cpu_baseline=cpu,
+               search=dict(config="RockSample 15x15, 15 rocks, K=500, max depth 90, %.1f s planning step"
+                           % args.search_seconds, runs=search) if search else None)
     print(json.dumps(out), flush=True)
     batch.close()
     ctx.close()

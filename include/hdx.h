@@ -292,6 +292,56 @@ hdx_status hdx_backup(hdx_tree *tree, int64_t node);
 hdx_status hdx_tree_bounds(const hdx_tree *tree, int64_t node, double *u, double *l);
 int64_t hdx_tree_size(const hdx_tree *tree);
 
+/* ---- Parallel DESPOT search (Sec. III-A, III-C) over the GPU expansion -- */
+
+/* One planning step of DESPOT run by n_threads CPU threads on one shared
+ * tree.  Each trial descends from the root choosing the action by the
+ * scenario-based PO-UCT bound (Eq. 8; Eq. 5 when c_a = 0) and the
+ * observation branch by the weighted excess uncertainty with virtual loss
+ * (Eq. 6-7, 9), stopping where the excess uncertainty is not positive; a
+ * leaf it reaches above max_depth is expanded on the GPU (hdx_expand_leaf:
+ * Eq. 10-13), its children attached (Eq. 11) and the path backed up (Eq. 4).
+ * Leaves are expanded either on one HIP stream per thread (batch_leaves <=
+ * 1) or by a batcher thread that fuses up to batch_leaves pending leaves of
+ * all threads into one launch.  The search stops at the time budget, after
+ * max_trials trials (if > 0), or when the root gap u - l falls below
+ * gap_epsilon; it returns the action with the largest lower bound.  Device
+ * memory for the tree comes from an arena of arena_bytes; when it is full
+ * the search stops early (reported in the result). */
+typedef struct {
+    int32_t K;             /* scenarios sampled at the root */
+    int32_t n_threads;     /* concurrent search threads (1..64) */
+    int32_t max_depth;     /* search horizon D: leaves at this depth are not expanded */
+    int32_t batch_leaves;  /* <= 1: one stream per thread; > 1: batcher with this many leaves per launch */
+    double time_budget_s;  /* planning time */
+    int64_t max_trials;    /* 0 = no limit */
+    double xi;             /* target uncertainty of Eq. 7 */
+    double c_a, c_o;       /* exploration constants of Eq. 8 and Eq. 9 */
+    double gap_epsilon;    /* stop when u(b0) - l(b0) <= gap_epsilon */
+    int64_t arena_bytes;   /* device memory for node data */
+    uint32_t seed, step;   /* random-stream key of this planning step */
+    hdx_rollout_cfg rollout;
+} hdx_search_cfg;
+
+typedef struct {
+    int32_t best_action;            /* argmax_a of the root's action lower bounds */
+    double u_root, l_root;          /* root bounds after the search */
+    double u0_root, l0_root;        /* root bounds before the first expansion */
+    int64_t trials;                 /* completed trials (expansion or stop, then backup) */
+    int64_t expansions;             /* leaves expanded on the GPU */
+    int64_t nodes;                  /* tree size */
+    int64_t scenario_steps;         /* model steps in expansions and rollouts */
+    int64_t launches;               /* expansion kernel launches */
+    int32_t max_depth_reached;
+    int32_t arena_full;             /* 1 if the device arena ran out */
+    double elapsed_s;
+    double action_l[HDX_MAX_ROCKS + 5]; /* per-action lower bounds at the root (first n_actions) */
+    double action_u[HDX_MAX_ROCKS + 5];
+} hdx_search_result;
+
+hdx_status hdx_search(hdx_ctx *ctx, const hdx_model *model, const hdx_belief *belief,
+                      const hdx_search_cfg *cfg, hdx_search_result *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libhdx.so")
 OBJ = os.path.join(PKG, "_build")
-SOURCES = ["kernels.hip", "runtime.cpp", "tree.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "tree.cpp", "search.cpp"]
 HEADERS = ["internal.hpp", "models.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -197,3 +197,10 @@ hipError_t launch_fp32_selftest(const float *a, const float *b, const float *c, 
 int32_t max_dynamic_lds();
 
 }  // namespace hdx
+
+// The description a model was uploaded from (host side, runtime.cpp).
+const hdx_model_desc *hdx_internal_desc(const hdx_model *m);
+
+namespace hdx {
+
+}  // namespace hdx

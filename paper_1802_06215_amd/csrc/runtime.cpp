@@ -212,6 +212,12 @@ hdx_status hdx_free_model(hdx_ctx *ctx, hdx_model *m) {
 
 int32_t hdx_model_actions(const hdx_model *m) { return m ? m->desc.n_actions : -1; }
 
+}  // extern "C"
+
+const hdx_model_desc *hdx_internal_desc(const hdx_model *m) { return &m->desc; }
+
+extern "C" {
+
 int32_t hdx_model_max_children(const hdx_model *m, int32_t n) {
     if (!m || n < 0) return -1;
     if (m->desc.kind == HDX_ROCKSAMPLE) return n < 3 ? n : 3;  // none, good, bad

@@ -1,0 +1,564 @@
+// Parallel DESPOT search on the CPU feeding leaf expansion to the GPU
+// (HyP-DESPOT, Sec. III-A and III-C).  Several host threads share one tree:
+// each trial walks down by the scenario-based PO-UCT action bound (Eq. 8)
+// and the weighted excess uncertainty with virtual loss (Eq. 7, 9), expands
+// the leaf it reaches through hdx_expand_leaf (Eq. 10-13), attaches the
+// children (Eq. 11) and backs the bounds up to the root (Eq. 4).  Node
+// states stay on the device: a node's scenarios are a segment of its
+// parent's grouped order, and its own states are materialised when it is
+// expanded.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <limits>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+// Offsets of one expansion record (device arena).  The head block holds
+// what the host needs to build nodes and is copied back in one transfer.
+struct RecLayout {
+    size_t n_children, r_mean, steps, child_z, child_n, child_off, child_u0, child_l0, head;
+    size_t w, s, car, px, py, goal, ids, perm, total;
+};
+
+RecLayout rec_layout(const hdx_model_desc &d, int n, int cap) {
+    RecLayout L;
+    const int A = d.n_actions;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align16(o + bytes);
+        return at;
+    };
+    L.n_children = take(4ull * A);
+    L.r_mean = take(4ull * A);
+    L.steps = take(16ull * A);
+    L.child_z = take(8ull * A * cap);
+    L.child_n = take(4ull * A * cap);
+    L.child_off = take(4ull * A * cap);
+    L.child_u0 = take(4ull * A * cap);
+    L.child_l0 = take(4ull * A * cap);
+    L.head = o;
+    L.w = L.s = L.car = L.px = L.py = L.goal = 0;
+    if (d.kind == HDX_ROCKSAMPLE) {
+        L.w = take(4ull * n);
+    } else {
+        L.s = take(4ull * n);
+        L.car = take(4ull * n);
+        L.px = take(4ull * d.n_peds * n);
+        L.py = take(4ull * d.n_peds * n);
+        L.goal = take(1ull * d.n_peds * n);
+    }
+    L.ids = take(4ull * n);
+    L.perm = take(4ull * A * n);
+    L.total = o;
+    return L;
+}
+
+struct Rec {
+    char *dev = nullptr;
+    RecLayout L;
+    int n = 0;
+};
+
+struct Node {
+    int32_t parent = -1;
+    int32_t action = -1;  // action from the parent
+    int32_t n = 0;        // |Phi_b|
+    int32_t depth = 0;
+    double u = 0.0, l = 0.0;
+    int32_t parent_rec = -1;          // record holding the parent's states
+    const int32_t *idx_dev = nullptr;  // positions in that record
+    int32_t state = 0;                // 0 leaf, 1 being expanded, 2 expanded
+    int32_t visits = 0, vloss = 0;
+    int32_t act_begin = -1;
+    int32_t rec = -1;
+};
+
+struct Act {
+    double r;
+    int32_t child_begin, n_children, visits;
+};
+
+struct Request {
+    hdx_leaf leaf;
+    const Rec *rec;
+    char *head_host;
+    bool done = false;
+    hdx_status status = HDX_OK;
+};
+
+hdx_states rec_states(const hdx_model_desc &d, const Rec &r) {
+    hdx_states s;
+    memset(&s, 0, sizeof(s));
+    if (d.kind == HDX_ROCKSAMPLE) {
+        s.w = (int32_t *)(r.dev + r.L.w);
+    } else {
+        s.s = (float *)(r.dev + r.L.s);
+        s.car = (int32_t *)(r.dev + r.L.car);
+        s.px = (float *)(r.dev + r.L.px);
+        s.py = (float *)(r.dev + r.L.py);
+        s.goal = (uint8_t *)(r.dev + r.L.goal);
+    }
+    s.stride = r.n;
+    return s;
+}
+
+struct Search {
+    hdx_ctx *ctx;
+    const hdx_model *model;
+    hdx_model_desc d;
+    hdx_search_cfg cfg;
+    int A;
+    char *arena = nullptr;
+    std::atomic<int64_t> arena_used{0};
+    std::atomic<int> arena_full{0};
+    std::mutex mu;  // tree
+    std::vector<Node> nodes;
+    std::vector<Act> acts;
+    std::deque<Rec> recs;  // stable addresses
+    std::atomic<int64_t> trials{0}, expansions{0}, steps{0}, launches{0};
+    std::atomic<int> max_depth{0};
+    std::atomic<bool> stop{false};
+    Clock::time_point t0;
+    // batcher
+    std::mutex qmu;
+    std::condition_variable qcv, dcv;
+    std::deque<Request *> queue;
+    bool batcher_exit = false;
+
+    int cap_for(int n) const { return std::max(1, hdx_model_max_children(model, n)); }
+
+    bool alloc_rec(int n, Rec *out) {
+        RecLayout L = rec_layout(d, n, cap_for(n));
+        const int64_t at = arena_used.fetch_add((int64_t)L.total);
+        if (at + (int64_t)L.total > cfg.arena_bytes) {
+            arena_full = 1;
+            return false;
+        }
+        out->dev = arena + at;
+        out->L = L;
+        out->n = n;
+        return true;
+    }
+
+    double root_gap() const { return std::max(nodes[0].u - nodes[0].l, 0.0); }
+
+    // Eq. 4 for one expanded node
+    void bellman(Node &b) {
+        double bu = -std::numeric_limits<double>::infinity(), bl = bu;
+        for (int a = 0; a < A; ++a) {
+            const Act &x = acts[b.act_begin + a];
+            double su = 0.0, sl = 0.0;
+            for (int c = 0; c < x.n_children; ++c) {
+                const Node &k = nodes[x.child_begin + c];
+                const double w = (double)k.n / (double)b.n;
+                su += w * k.u;
+                sl += w * k.l;
+            }
+            bu = std::max(bu, x.r + d.gamma * su);
+            bl = std::max(bl, x.r + d.gamma * sl);
+        }
+        b.u = bu;
+        b.l = bl;
+    }
+
+    // Action bound of Eq. 8: u(b,a) plus the scenario-based exploration bonus
+    int choose_action(const Node &b) const {
+        int best = 0;
+        double best_v = -std::numeric_limits<double>::infinity();
+        const double nb = (double)b.n * (double)std::max(b.visits, 1);
+        for (int a = 0; a < A; ++a) {
+            const Act &x = acts[b.act_begin + a];
+            double su = 0.0;
+            for (int c = 0; c < x.n_children; ++c) {
+                const Node &k = nodes[x.child_begin + c];
+                su += (double)k.n / (double)b.n * k.u;
+            }
+            double v = x.r + d.gamma * su;
+            if (cfg.c_a > 0.0) {
+                if (x.visits == 0) {
+                    v = std::numeric_limits<double>::infinity();
+                } else {
+                    v += cfg.c_a * sqrt(log(nb) / ((double)b.n * (double)x.visits));
+                }
+            }
+            if (v > best_v) {
+                best_v = v;
+                best = a;
+            }
+        }
+        return best;
+    }
+
+    bool expand(int node_id, hipStream_t stream, char *head_host);
+
+    void attach(int node_id, const Rec &r, const char *head) {
+        Node &b = nodes[node_id];
+        const int cap = cap_for(b.n);
+        const int32_t *nch = (const int32_t *)(head + r.L.n_children);
+        const float *rm = (const float *)(head + r.L.r_mean);
+        const int64_t *st = (const int64_t *)(head + r.L.steps);
+        const int32_t *cn = (const int32_t *)(head + r.L.child_n);
+        const int32_t *co = (const int32_t *)(head + r.L.child_off);
+        const float *cu = (const float *)(head + r.L.child_u0);
+        const float *cl = (const float *)(head + r.L.child_l0);
+        int64_t s = 0;
+        for (int a = 0; a < A; ++a) s += st[2 * a] + st[2 * a + 1];
+        steps += s;
+        const int32_t rec_index = b.rec;
+        const int parent_depth = b.depth;
+        const int parent_n = b.n;
+        nodes[node_id].act_begin = (int32_t)acts.size();
+        for (int a = 0; a < A; ++a) {
+            acts.push_back(Act{(double)rm[a], (int32_t)nodes.size(), nch[a], 0});
+            for (int c = 0; c < nch[a]; ++c) {
+                Node k;
+                k.parent = node_id;
+                k.action = a;
+                k.n = cn[a * cap + c];
+                k.depth = parent_depth + 1;
+                k.u = cu[a * cap + c];
+                k.l = cl[a * cap + c];
+                k.parent_rec = rec_index;
+                k.idx_dev = (const int32_t *)(r.dev + r.L.perm) + (size_t)a * parent_n + co[a * cap + c];
+                nodes.push_back(k);
+            }
+        }
+        nodes[node_id].state = 2;
+        int md = parent_depth + 1;
+        int cur = max_depth.load();
+        while (md > cur && !max_depth.compare_exchange_weak(cur, md)) {
+        }
+    }
+};
+
+bool Search::expand(int node_id, hipStream_t stream, char *head_host) {
+    // builds the leaf descriptor; the caller holds no lock
+    Node b;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        b = nodes[node_id];
+    }
+    Rec r;
+    if (!alloc_rec(b.n, &r)) return false;
+    const Rec *parent = nullptr;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        parent = &recs[b.parent_rec];
+    }
+    hdx_leaf L;
+    memset(&L, 0, sizeof(L));
+    L.model = model;
+    L.seed = cfg.seed;
+    L.step = cfg.step;
+    L.rollout = cfg.rollout;
+    L.parent = rec_states(d, *parent);
+    L.parent_ids = (const uint32_t *)(parent->dev + parent->L.ids);
+    L.idx = b.idx_dev;
+    L.n = b.n;
+    L.depth = b.depth;
+    L.last_action = b.action;
+    L.cap = cap_for(b.n);
+    L.states_out = rec_states(d, r);
+    L.ids_out = (uint32_t *)(r.dev + r.L.ids);
+    L.perm = (int32_t *)(r.dev + r.L.perm);
+    L.n_children = (int32_t *)(r.dev + r.L.n_children);
+    L.child_z = (uint64_t *)(r.dev + r.L.child_z);
+    L.child_n = (int32_t *)(r.dev + r.L.child_n);
+    L.child_off = (int32_t *)(r.dev + r.L.child_off);
+    L.child_u0 = (float *)(r.dev + r.L.child_u0);
+    L.child_l0 = (float *)(r.dev + r.L.child_l0);
+    L.r_mean = (float *)(r.dev + r.L.r_mean);
+    L.steps = (int64_t *)(r.dev + r.L.steps);
+    hdx_status st = HDX_OK;
+    if (cfg.batch_leaves > 1) {
+        Request q;
+        q.leaf = L;
+        q.rec = nullptr;
+        q.head_host = head_host;
+        Rec *rp = nullptr;
+        {
+            std::lock_guard<std::mutex> g(mu);
+            recs.push_back(r);
+            rp = &recs.back();
+            nodes[node_id].rec = (int32_t)recs.size() - 1;
+        }
+        q.rec = rp;
+        {
+            std::unique_lock<std::mutex> lk(qmu);
+            queue.push_back(&q);
+            qcv.notify_one();
+            dcv.wait(lk, [&] { return q.done; });
+        }
+        st = q.status;
+    } else {
+        st = hdx_expand_leaf(ctx, &L, 1, stream);
+        if (st == HDX_OK &&
+            hipMemcpyAsync(head_host, r.dev, r.L.head, hipMemcpyDeviceToHost, stream) != hipSuccess)
+            st = HDX_E_DEVICE;
+        if (st == HDX_OK && hipStreamSynchronize(stream) != hipSuccess) st = HDX_E_DEVICE;
+        launches++;
+        std::lock_guard<std::mutex> g(mu);
+        recs.push_back(r);
+        nodes[node_id].rec = (int32_t)recs.size() - 1;
+    }
+    if (st != HDX_OK) return false;
+    expansions++;
+    std::lock_guard<std::mutex> g(mu);
+    attach(node_id, recs[nodes[node_id].rec], head_host);
+    return true;
+}
+
+void batcher_loop(Search *S, hipStream_t stream) {
+    std::vector<Request *> batch;
+    std::vector<hdx_leaf> leaves;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(S->qmu);
+            S->qcv.wait(lk, [&] { return S->batcher_exit || !S->queue.empty(); });
+            if (S->queue.empty() && S->batcher_exit) return;
+            batch.clear();
+            while (!S->queue.empty() && (int)batch.size() < S->cfg.batch_leaves) {
+                batch.push_back(S->queue.front());
+                S->queue.pop_front();
+            }
+        }
+        leaves.clear();
+        for (Request *q : batch) leaves.push_back(q->leaf);
+        hdx_status st = hdx_expand_leaf(S->ctx, leaves.data(), (int32_t)leaves.size(), stream);
+        for (Request *q : batch)
+            if (st == HDX_OK &&
+                hipMemcpyAsync(q->head_host, q->rec->dev, q->rec->L.head, hipMemcpyDeviceToHost, stream) != hipSuccess)
+                st = HDX_E_DEVICE;
+        if (st == HDX_OK && hipStreamSynchronize(stream) != hipSuccess) st = HDX_E_DEVICE;
+        S->launches++;
+        {
+            std::lock_guard<std::mutex> lk(S->qmu);
+            for (Request *q : batch) {
+                q->status = st;
+                q->done = true;
+            }
+        }
+        S->dcv.notify_all();
+    }
+}
+
+void worker(Search *S, int tid, size_t head_bytes) {
+    hipStream_t stream = nullptr;
+    hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
+    char *head_host = nullptr;
+    hipHostMalloc((void **)&head_host, head_bytes);
+    std::vector<int> path;
+    const double K = (double)S->cfg.K;
+    while (!S->stop.load()) {
+        const double elapsed = std::chrono::duration<double>(Clock::now() - S->t0).count();
+        if (elapsed >= S->cfg.time_budget_s || S->arena_full.load()) break;
+        if (S->cfg.max_trials > 0 && S->trials.load() >= S->cfg.max_trials) break;
+        int leaf = -1;
+        path.clear();
+        {
+            std::lock_guard<std::mutex> g(S->mu);
+            if (S->root_gap() <= S->cfg.gap_epsilon) {
+                S->stop = true;
+                break;
+            }
+            const double eps0 = S->root_gap();
+            int b = 0;
+            path.push_back(0);
+            for (;;) {
+                Node &nb = S->nodes[b];
+                nb.visits++;
+                if (nb.state != 2) {
+                    if (nb.state == 0 && nb.depth < S->cfg.max_depth && nb.n > 0) {
+                        nb.state = 1;
+                        leaf = b;
+                    }
+                    break;
+                }
+                const int a = S->choose_action(nb);
+                Act &x = S->acts[nb.act_begin + a];
+                x.visits++;
+                // Eq. 7 with the virtual loss of Eq. 9
+                int best = -1;
+                double best_e = -std::numeric_limits<double>::infinity(), best_plain = 0.0;
+                for (int c = 0; c < x.n_children; ++c) {
+                    const Node &k = S->nodes[x.child_begin + c];
+                    const double e = (k.u - k.l) - (double)k.n / K * S->cfg.xi * eps0;
+                    const double ep = e - (double)k.vloss * S->cfg.c_o * eps0;
+                    if (ep > best_e) {
+                        best_e = ep;
+                        best = x.child_begin + c;
+                        best_plain = e;
+                    }
+                }
+                if (best < 0 || best_plain <= 0.0) break;  // the path ends where E is not positive
+                S->nodes[best].vloss++;
+                b = best;
+                path.push_back(b);
+            }
+        }
+        bool ok = true;
+        if (leaf >= 0) {
+            ok = S->expand(leaf, stream, head_host);
+            if (!ok) {
+                std::lock_guard<std::mutex> g(S->mu);
+                S->nodes[leaf].state = 0;
+            }
+        }
+        {
+            std::lock_guard<std::mutex> g(S->mu);
+            for (size_t i = path.size(); i-- > 0;) {
+                Node &nb = S->nodes[path[i]];
+                if (nb.state == 2) S->bellman(nb);
+                if (i > 0) nb.vloss--;
+            }
+        }
+        if (!ok) break;
+        S->trials++;
+    }
+    hipHostFree(head_host);
+    hipStreamDestroy(stream);
+}
+
+}  // namespace
+
+extern "C" hdx_status hdx_search(hdx_ctx *ctx, const hdx_model *model, const hdx_belief *belief,
+                                 const hdx_search_cfg *cfg, hdx_search_result *out) {
+    if (!ctx || !model || !belief || !cfg || !out) return HDX_E_INVALID;
+    const int A = hdx_model_actions(model);
+    if (cfg->K < 1 || cfg->K > HDX_MAX_LEAF_SCENARIOS || cfg->n_threads < 1 || cfg->n_threads > 64 ||
+        cfg->max_depth < 1 || cfg->arena_bytes < (1 << 20) || A > HDX_MAX_ROCKS + 5)
+        return HDX_E_INVALID;
+    Search S;
+    S.ctx = ctx;
+    S.model = model;
+    S.d = *hdx_internal_desc(model);
+    S.cfg = *cfg;
+    S.A = A;
+    memset(out, 0, sizeof(*out));
+    if (hipMalloc((void **)&S.arena, (size_t)cfg->arena_bytes) != hipSuccess) return HDX_E_NOMEM;
+    hipStream_t main_stream = nullptr;
+    hipStreamCreateWithFlags(&main_stream, hipStreamNonBlocking);
+    hdx_status st = HDX_OK;
+
+    // root: sample K scenarios (Sec. III-A) and set the initial bounds
+    Rec root_rec;
+    int32_t *iota = nullptr, *depths = nullptr;
+    float *U = nullptr, *L = nullptr;
+    const size_t K = (size_t)cfg->K;
+    if (!S.alloc_rec(cfg->K, &root_rec)) st = HDX_E_NOMEM;
+    if (st == HDX_OK) {
+        const int64_t at = S.arena_used.fetch_add((int64_t)align16(16 * K));
+        if (at + (int64_t)align16(16 * K) > cfg->arena_bytes) st = HDX_E_NOMEM;
+        iota = (int32_t *)(S.arena + at);
+        depths = iota + K;
+        U = (float *)(depths + K);
+        L = U + K;
+    }
+    std::vector<int32_t> h_iota(K), h_zero(K, 0);
+    std::vector<float> hU(K), hL(K);
+    for (size_t k = 0; k < K; ++k) h_iota[k] = (int32_t)k;
+    if (st == HDX_OK)
+        st = hdx_sample_scenarios(ctx, model, belief, cfg->K, cfg->seed, cfg->step, rec_states(S.d, root_rec),
+                                  main_stream);
+    if (st == HDX_OK && (hipMemcpyAsync(iota, h_iota.data(), 4 * K, hipMemcpyHostToDevice, main_stream) != hipSuccess ||
+                         hipMemcpyAsync(depths, h_zero.data(), 4 * K, hipMemcpyHostToDevice, main_stream) != hipSuccess ||
+                         hipMemcpyAsync(root_rec.dev + root_rec.L.ids, h_iota.data(), 4 * K, hipMemcpyHostToDevice,
+                                        main_stream) != hipSuccess))
+        st = HDX_E_DEVICE;
+    if (st == HDX_OK)
+        st = hdx_rollout_bounds(ctx, model, &cfg->rollout, cfg->seed, cfg->step, rec_states(S.d, root_rec),
+                                (const uint32_t *)(root_rec.dev + root_rec.L.ids), depths, cfg->K, U, L, nullptr,
+                                main_stream);
+    if (st == HDX_OK && (hipMemcpyAsync(hU.data(), U, 4 * K, hipMemcpyDeviceToHost, main_stream) != hipSuccess ||
+                         hipMemcpyAsync(hL.data(), L, 4 * K, hipMemcpyDeviceToHost, main_stream) != hipSuccess ||
+                         hipStreamSynchronize(main_stream) != hipSuccess))
+        st = HDX_E_DEVICE;
+    if (st != HDX_OK) {
+        hipStreamDestroy(main_stream);
+        hipFree(S.arena);
+        return st;
+    }
+    double su = 0.0, sl = 0.0;
+    for (size_t k = 0; k < K; ++k) {
+        su += hU[k];
+        sl += hL[k];
+    }
+    S.recs.push_back(root_rec);
+    Node root;
+    root.n = cfg->K;
+    root.u = su / (double)K;
+    root.l = sl / (double)K;
+    root.parent_rec = 0;
+    root.idx_dev = iota;
+    S.nodes.reserve(1 << 16);
+    S.nodes.push_back(root);
+    out->u0_root = root.u;
+    out->l0_root = root.l;
+
+    const RecLayout big = rec_layout(S.d, cfg->K, S.cap_for(cfg->K));
+    S.t0 = Clock::now();
+    std::thread batcher;
+    if (cfg->batch_leaves > 1) batcher = std::thread(batcher_loop, &S, main_stream);
+    std::vector<std::thread> workers;
+    for (int t = 0; t < cfg->n_threads; ++t) workers.emplace_back(worker, &S, t, big.head);
+    for (auto &w : workers) w.join();
+    if (batcher.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(S.qmu);
+            S.batcher_exit = true;
+        }
+        S.qcv.notify_all();
+        batcher.join();
+    }
+    out->elapsed_s = std::chrono::duration<double>(Clock::now() - S.t0).count();
+    const Node &r = S.nodes[0];
+    out->u_root = r.u;
+    out->l_root = r.l;
+    out->trials = S.trials.load();
+    out->expansions = S.expansions.load();
+    out->nodes = (int64_t)S.nodes.size();
+    out->scenario_steps = S.steps.load();
+    out->launches = S.launches.load();
+    out->max_depth_reached = S.max_depth.load();
+    out->arena_full = S.arena_full.load();
+    out->best_action = 0;
+    if (r.state == 2) {
+        double best = -std::numeric_limits<double>::infinity();
+        for (int a = 0; a < A; ++a) {
+            const Act &x = S.acts[r.act_begin + a];
+            double sum_u = 0.0, sum_l = 0.0;
+            for (int c = 0; c < x.n_children; ++c) {
+                const Node &k = S.nodes[x.child_begin + c];
+                sum_u += (double)k.n / (double)r.n * k.u;
+                sum_l += (double)k.n / (double)r.n * k.l;
+            }
+            out->action_u[a] = x.r + S.d.gamma * sum_u;
+            out->action_l[a] = x.r + S.d.gamma * sum_l;
+            if (out->action_l[a] > best) {
+                best = out->action_l[a];
+                out->best_action = a;
+            }
+        }
+    }
+    hipStreamSynchronize(main_stream);
+    hipStreamDestroy(main_stream);
+    hipDeviceSynchronize();
+    hipFree(S.arena);
+    return HDX_OK;
+}

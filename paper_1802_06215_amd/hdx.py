@@ -61,6 +61,22 @@ class States(C.Structure):
                 ("stride", C.c_int64)]
 
 
+class SearchCfg(C.Structure):
+    _fields_ = [("K", C.c_int32), ("n_threads", C.c_int32), ("max_depth", C.c_int32),
+                ("batch_leaves", C.c_int32), ("time_budget_s", C.c_double), ("max_trials", C.c_int64),
+                ("xi", C.c_double), ("c_a", C.c_double), ("c_o", C.c_double), ("gap_epsilon", C.c_double),
+                ("arena_bytes", C.c_int64), ("seed", C.c_uint32), ("step", C.c_uint32),
+                ("rollout", RolloutCfg)]
+
+
+class SearchResult(C.Structure):
+    _fields_ = [("best_action", C.c_int32), ("u_root", C.c_double), ("l_root", C.c_double),
+                ("u0_root", C.c_double), ("l0_root", C.c_double), ("trials", C.c_int64),
+                ("expansions", C.c_int64), ("nodes", C.c_int64), ("scenario_steps", C.c_int64),
+                ("launches", C.c_int64), ("max_depth_reached", C.c_int32), ("arena_full", C.c_int32),
+                ("elapsed_s", C.c_double), ("action_l", C.c_double * 25), ("action_u", C.c_double * 25)]
+
+
 class Leaf(C.Structure):
     _fields_ = [("model", C.c_void_p), ("seed", C.c_uint32), ("step", C.c_uint32),
                 ("rollout", RolloutCfg), ("parent", States), ("parent_ids", C.c_void_p),
@@ -79,7 +95,7 @@ EXPORTS = ["hdx_version", "hdx_init", "hdx_fini", "hdx_last_error", "hdx_upload_
            "hdx_sample_scenarios", "hdx_expand_leaf", "hdx_rollout_bounds", "hdx_philox",
            "hdx_fp32_selftest", "hdx_batch_create", "hdx_batch_destroy", "hdx_batch_set_leaves",
            "hdx_batch_set_schedule", "hdx_batch_get_schedule", "hdx_batch_use_graph",
-           "hdx_batch_launch", "hdx_batch_autotune",
+           "hdx_batch_launch", "hdx_batch_autotune", "hdx_search",
            "hdx_tree_create", "hdx_tree_destroy", "hdx_tree_add_children", "hdx_backup",
            "hdx_tree_bounds", "hdx_tree_size"]
 
@@ -119,6 +135,7 @@ def load_library():
     L.hdx_batch_use_graph.argtypes = [P, P, I32]
     L.hdx_batch_launch.argtypes = [P, P, P]
     L.hdx_batch_autotune.argtypes = [P, P, I32, C.POINTER(C.c_float)]
+    L.hdx_search.argtypes = [P, P, C.POINTER(Belief), C.POINTER(SearchCfg), C.POINTER(SearchResult)]
     L.hdx_tree_create.argtypes = [I32, C.c_double, I32, C.c_double, C.c_double, C.POINTER(P)]
     L.hdx_tree_destroy.argtypes = [P]
     L.hdx_tree_add_children.argtypes = [P, I64, P, P, P, P, P, P, I32, C.POINTER(I64)]
@@ -350,19 +367,7 @@ class Context:
     def sample_scenarios(self, model: Model, belief: dict, K: int, seed: int, step: int,
                          out: dict | None = None, stream=None) -> dict:
         out = empty_states(model, K) if out is None else out
-        b = Belief()
-        keep = []
-        if model.kind == ROCKSAMPLE:
-            p = np.ascontiguousarray(belief["p"], dtype=np.float64)
-            keep.append(p)
-            b.x, b.y, b.p_good = belief["x"], belief["y"], p.ctypes.data
-        else:
-            px = np.ascontiguousarray(belief["px"], dtype=np.float32)
-            py = np.ascontiguousarray(belief["py"], dtype=np.float32)
-            gp = np.ascontiguousarray(belief["goal_p"], dtype=np.float64)
-            keep += [px, py, gp]
-            b.s, b.level = float(belief["s"]), int(belief["level"])
-            b.px, b.py, b.goal_p = px.ctypes.data, py.ctypes.data, gp.ctypes.data
+        b, keep = self._belief(model, belief)
         self._check(self.lib.hdx_sample_scenarios(self.handle, model.handle, C.byref(b), K, seed, step,
                                                   states_view(model, out), _stream(stream)))
         return out
@@ -383,6 +388,37 @@ class Context:
                                                 states_view(model, states), _dp(ids), _dp(depths), n,
                                                 _dp(U), _dp(L), _dp(steps), _stream(stream)))
         return U, L, steps
+
+    def search(self, model: Model, belief: dict, K: int = 500, n_threads: int = 8, max_depth: int = 90,
+               batch_leaves: int = 0, time_budget_s: float = 1.0, max_trials: int = 0, xi: float = 0.95,
+               c_a: float = 0.0, c_o: float = 0.1, gap_epsilon: float = 0.0, arena_bytes: int = 8 << 30,
+               seed: int = 1, step: int = 0, rollout: RolloutCfg | None = None) -> dict:
+        """hdx_search: one planning step of parallel DESPOT over GPU leaf expansion."""
+        b, keep = self._belief(model, belief)
+        cfg = SearchCfg(K, n_threads, max_depth, batch_leaves, time_budget_s, max_trials, xi, c_a, c_o,
+                        gap_epsilon, arena_bytes, seed, step, rollout or rollout_cfg())
+        res = SearchResult()
+        self._check(self.lib.hdx_search(self.handle, model.handle, C.byref(b), C.byref(cfg), C.byref(res)))
+        out = {f: getattr(res, f) for f, _ in SearchResult._fields_ if not f.startswith("action_")}
+        out["action_l"] = list(res.action_l)[:model.n_actions]
+        out["action_u"] = list(res.action_u)[:model.n_actions]
+        return out
+
+    def _belief(self, model: Model, belief: dict):
+        b = Belief()
+        keep = []
+        if model.kind == ROCKSAMPLE:
+            p = np.ascontiguousarray(belief["p"], dtype=np.float64)
+            keep.append(p)
+            b.x, b.y, b.p_good = belief["x"], belief["y"], p.ctypes.data
+        else:
+            px = np.ascontiguousarray(belief["px"], dtype=np.float32)
+            py = np.ascontiguousarray(belief["py"], dtype=np.float32)
+            gp = np.ascontiguousarray(belief["goal_p"], dtype=np.float64)
+            keep += [px, py, gp]
+            b.s, b.level = float(belief["s"]), int(belief["level"])
+            b.px, b.py, b.goal_p = px.ctypes.data, py.ctypes.data, gp.ctypes.data
+        return b, keep
 
     def philox(self, ctr, k0: int, k1: int, stream=None):
         out = torch.empty_like(ctr)
