@@ -263,12 +263,14 @@ def main():
         desc = items[0][0]
         m = wl["models"][id(desc)]
         search = []
-        for threads, batch in ((4, 0), (8, 0), (8, 8), (16, 16)):
+        for threads, nb in ((4, 0), (8, 0), (8, 8), (16, 16)):
             res = ctx.search(m, W.rocksample_belief(desc), K=500, n_threads=threads, max_depth=90,
-                             batch_leaves=batch, time_budget_s=args.search_seconds,
+                             batch_leaves=nb, time_budget_s=args.search_seconds,
                              rollout=H.rollout_cfg(0, 1 << 30, 90), seed=3)
-            search.append(dict(threads=threads, leaf_batcher=batch > 0,
+            search.append(dict(threads=threads, leaf_batcher=nb > 0,
                                trials_per_s=round(res["trials"] / res["elapsed_s"], 1),
+                               expanding_trials_per_s=round(res["expansions"] / res["elapsed_s"], 1),
+                               idle_trials=res["idle_trials"],
                                expansions=res["expansions"], launches=res["launches"],
                                scenario_steps_per_s=round(res["scenario_steps"] / res["elapsed_s"], 1),
                                nodes=res["nodes"], depth=res["max_depth_reached"],

@@ -307,7 +307,8 @@ int64_t hdx_tree_size(const hdx_tree *tree);
  * max_trials trials (if > 0), or when the root gap u - l falls below
  * gap_epsilon; it returns the action with the largest lower bound.  Device
  * memory for the tree comes from an arena of arena_bytes; when it is full
- * the search stops early (reported in the result). */
+ * the search stops early (reported in the result).  A failing expansion
+ * stops the search and its error is returned (text via hdx_last_error). */
 typedef struct {
     int32_t K;             /* scenarios sampled at the root */
     int32_t n_threads;     /* concurrent search threads (1..64) */
@@ -316,7 +317,8 @@ typedef struct {
     double time_budget_s;  /* planning time */
     int64_t max_trials;    /* 0 = no limit */
     double xi;             /* target uncertainty of Eq. 7 */
-    double c_a, c_o;       /* exploration constants of Eq. 8 and Eq. 9 */
+    double c_a, c_o;       /* exploration constants of Eq. 8 and Eq. 9, as multiples of the
+                              root gap u(b0) - l(b0) (c_a: initial gap, c_o: current gap) */
     double gap_epsilon;    /* stop when u(b0) - l(b0) <= gap_epsilon */
     int64_t arena_bytes;   /* device memory for node data */
     uint32_t seed, step;   /* random-stream key of this planning step */
@@ -328,6 +330,7 @@ typedef struct {
     double u_root, l_root;          /* root bounds after the search */
     double u0_root, l0_root;        /* root bounds before the first expansion */
     int64_t trials;                 /* completed trials (expansion or stop, then backup) */
+    int64_t idle_trials;            /* trials that ended without expanding a leaf */
     int64_t expansions;             /* leaves expanded on the GPU */
     int64_t nodes;                  /* tree size */
     int64_t scenario_steps;         /* model steps in expansions and rollouts */

@@ -200,6 +200,7 @@ int32_t max_dynamic_lds();
 
 // The description a model was uploaded from (host side, runtime.cpp).
 const hdx_model_desc *hdx_internal_desc(const hdx_model *m);
+void hdx_internal_set_error(hdx_ctx *ctx, const char *msg);
 
 namespace hdx {
 

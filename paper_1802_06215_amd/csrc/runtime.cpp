@@ -216,6 +216,11 @@ int32_t hdx_model_actions(const hdx_model *m) { return m ? m->desc.n_actions : -
 
 const hdx_model_desc *hdx_internal_desc(const hdx_model *m) { return &m->desc; }
 
+void hdx_internal_set_error(hdx_ctx *ctx, const char *msg) {
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    ctx->err = msg;
+}
+
 extern "C" {
 
 int32_t hdx_model_max_children(const hdx_model *m, int32_t n) {

@@ -17,6 +17,7 @@
 #include <deque>
 #include <limits>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -134,7 +135,21 @@ struct Search {
     std::atomic<int64_t> trials{0}, expansions{0}, steps{0}, launches{0};
     std::atomic<int> max_depth{0};
     std::atomic<bool> stop{false};
+    std::atomic<int64_t> idle_trials{0};
+    double c_a_abs = 0.0;  // c_a scaled by the initial root gap
+    std::mutex emu;
+    hdx_status error = HDX_OK;
+    std::string error_msg;
     Clock::time_point t0;
+
+    void fail(hdx_status st, const char *where) {
+        std::lock_guard<std::mutex> g(emu);
+        if (error == HDX_OK) {
+            error = st;
+            error_msg = std::string(where) + ": " + hdx_last_error(ctx);
+        }
+        stop = true;
+    }
     // batcher
     std::mutex qmu;
     std::condition_variable qcv, dcv;
@@ -190,11 +205,11 @@ struct Search {
                 su += (double)k.n / (double)b.n * k.u;
             }
             double v = x.r + d.gamma * su;
-            if (cfg.c_a > 0.0) {
+            if (c_a_abs > 0.0) {
                 if (x.visits == 0) {
                     v = std::numeric_limits<double>::infinity();
                 } else {
-                    v += cfg.c_a * sqrt(log(nb) / ((double)b.n * (double)x.visits));
+                    v += c_a_abs * sqrt(log(nb) / ((double)b.n * (double)x.visits));
                 }
             }
             if (v > best_v) {
@@ -308,10 +323,21 @@ bool Search::expand(int node_id, hipStream_t stream, char *head_host) {
         st = q.status;
     } else {
         st = hdx_expand_leaf(ctx, &L, 1, stream);
-        if (st == HDX_OK &&
-            hipMemcpyAsync(head_host, r.dev, r.L.head, hipMemcpyDeviceToHost, stream) != hipSuccess)
-            st = HDX_E_DEVICE;
-        if (st == HDX_OK && hipStreamSynchronize(stream) != hipSuccess) st = HDX_E_DEVICE;
+        if (st != HDX_OK) {
+            fail(st, "expand_leaf");
+        } else {
+            hipError_t e = hipMemcpyAsync(head_host, r.dev, r.L.head, hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) {
+                st = HDX_E_DEVICE;
+                std::lock_guard<std::mutex> g(emu);
+                if (error == HDX_OK) {
+                    error = st;
+                    error_msg = std::string("head copy: ") + hipGetErrorString(e);
+                }
+                stop = true;
+            }
+        }
         launches++;
         std::lock_guard<std::mutex> g(mu);
         recs.push_back(r);
@@ -341,6 +367,7 @@ void batcher_loop(Search *S, hipStream_t stream) {
         leaves.clear();
         for (Request *q : batch) leaves.push_back(q->leaf);
         hdx_status st = hdx_expand_leaf(S->ctx, leaves.data(), (int32_t)leaves.size(), stream);
+        if (st != HDX_OK) S->fail(st, "batched expand_leaf");
         for (Request *q : batch)
             if (st == HDX_OK &&
                 hipMemcpyAsync(q->head_host, q->rec->dev, q->rec->L.head, hipMemcpyDeviceToHost, stream) != hipSuccess)
@@ -430,6 +457,12 @@ void worker(Search *S, int tid, size_t head_bytes) {
         }
         if (!ok) break;
         S->trials++;
+        if (leaf < 0) {
+            // the path ended where the excess uncertainty is not positive:
+            // nothing was expanded; let the other threads take the lock
+            S->idle_trials++;
+            std::this_thread::yield();
+        }
     }
     hipHostFree(head_host);
     hipStreamDestroy(stream);
@@ -510,6 +543,7 @@ extern "C" hdx_status hdx_search(hdx_ctx *ctx, const hdx_model *model, const hdx
     S.nodes.push_back(root);
     out->u0_root = root.u;
     out->l0_root = root.l;
+    S.c_a_abs = cfg->c_a * std::max(root.u - root.l, 0.0);
 
     const RecLayout big = rec_layout(S.d, cfg->K, S.cap_for(cfg->K));
     S.t0 = Clock::now();
@@ -531,6 +565,7 @@ extern "C" hdx_status hdx_search(hdx_ctx *ctx, const hdx_model *model, const hdx
     out->u_root = r.u;
     out->l_root = r.l;
     out->trials = S.trials.load();
+    out->idle_trials = S.idle_trials.load();
     out->expansions = S.expansions.load();
     out->nodes = (int64_t)S.nodes.size();
     out->scenario_steps = S.steps.load();
@@ -560,5 +595,9 @@ extern "C" hdx_status hdx_search(hdx_ctx *ctx, const hdx_model *model, const hdx
     hipStreamDestroy(main_stream);
     hipDeviceSynchronize();
     hipFree(S.arena);
+    if (S.error != HDX_OK) {
+        hdx_internal_set_error(ctx, S.error_msg.c_str());
+        return S.error;
+    }
     return HDX_OK;
 }

@@ -72,6 +72,7 @@ class SearchCfg(C.Structure):
 class SearchResult(C.Structure):
     _fields_ = [("best_action", C.c_int32), ("u_root", C.c_double), ("l_root", C.c_double),
                 ("u0_root", C.c_double), ("l0_root", C.c_double), ("trials", C.c_int64),
+                ("idle_trials", C.c_int64),
                 ("expansions", C.c_int64), ("nodes", C.c_int64), ("scenario_steps", C.c_int64),
                 ("launches", C.c_int64), ("max_depth_reached", C.c_int32), ("arena_full", C.c_int32),
                 ("elapsed_s", C.c_double), ("action_l", C.c_double * 25), ("action_u", C.c_double * 25)]
@@ -391,7 +392,7 @@ class Context:
 
     def search(self, model: Model, belief: dict, K: int = 500, n_threads: int = 8, max_depth: int = 90,
                batch_leaves: int = 0, time_budget_s: float = 1.0, max_trials: int = 0, xi: float = 0.95,
-               c_a: float = 0.0, c_o: float = 0.1, gap_epsilon: float = 0.0, arena_bytes: int = 8 << 30,
+               c_a: float = 0.1, c_o: float = 0.1, gap_epsilon: float = 0.0, arena_bytes: int = 8 << 30,
                seed: int = 1, step: int = 0, rollout: RolloutCfg | None = None) -> dict:
         """hdx_search: one planning step of parallel DESPOT over GPU leaf expansion."""
         b, keep = self._belief(model, belief)
