@@ -161,6 +161,15 @@ hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue
                          const Variant &v, const Schedule &sch, int32_t n_cu, hipStream_t stream);
 hipError_t configure_expand_kernels();
 
+// Up to kArgLeaves leaves passed by value in the kernel arguments.
+constexpr int kArgLeaves = 4;
+struct ArgPack {
+    LeafTask t[kArgLeaves];
+    int32_t tile_begin[kArgLeaves + 1];
+    int32_t n_leaves, n_max, xcd_remap;
+};
+hipError_t launch_expand_args(const ArgPack &pack, const Variant &v, const Schedule &sch, hipStream_t stream);
+
 struct SampleArgs {
     const DevModel *model;
     uint32_t k0, k1;
@@ -201,6 +210,7 @@ int32_t max_dynamic_lds();
 // The description a model was uploaded from (host side, runtime.cpp).
 const hdx_model_desc *hdx_internal_desc(const hdx_model *m);
 void hdx_internal_set_error(hdx_ctx *ctx, const char *msg);
+void hdx_internal_quiesce(hdx_ctx *ctx);
 
 namespace hdx {
 

@@ -487,10 +487,50 @@ __global__ __launch_bounds__(max_threads<MODE>()) void expand_tiles(const LeafTa
     }
 }
 
+// A few leaves carried in the kernel arguments: no descriptor staging, so
+// the launch is ordered by its stream alone.  The pack is read in place in
+// the kernarg segment (constant address space, scalar loads).
+template <int MODE, int PM>
+__global__ __launch_bounds__(max_threads<MODE>()) void expand_args(const ArgPack pack) {
+    extern __shared__ __align__(16) unsigned char lds[];
+#if defined(__HIP_DEVICE_COMPILE__)
+    const HDX_CONST ArgPack *P = (const HDX_CONST ArgPack *)__builtin_amdgcn_kernarg_segment_ptr();
+#else
+    const ArgPack *P = &pack;
+#endif
+    const LdsLayout Ly = make_layout(P->n_max);
+    const int n_leaves = P->n_leaves;
+    const int n_tiles = P->tile_begin[n_leaves];
+    const int t = P->xcd_remap ? remap_xcd((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    if (t >= n_tiles) return;
+    int i = 0;
+    while (i + 1 < n_leaves && t >= P->tile_begin[i + 1]) ++i;
+    const HDX_CONST LeafTask *T = &P->t[i];
+    const int a = t - P->tile_begin[i];
+    if (MODE == 0 || (MODE == 2 && T->kind == HDX_ROCKSAMPLE)) {
+        run_tile<RsOps>(T, a, lds, Ly);
+    } else if (MODE != 0) {
+        run_ped<PM>(T, a, lds, Ly);
+    }
+}
+
 template <int MODE, int PM>
 hipError_t configure_t() {
-    return hipFuncSetAttribute((const void *)expand_tiles<MODE, PM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void *)expand_tiles<MODE, PM>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, max_dynamic_lds());
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)expand_args<MODE, PM>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                max_dynamic_lds());
+}
+
+template <int MODE, int PM>
+hipError_t launch_args_t(const ArgPack &pack, const Schedule &sch, hipStream_t stream) {
+    const LdsLayout Ly = make_layout(pack.n_max);
+    const int grid = pack.tile_begin[pack.n_leaves];
+    if (grid < 1) return hipSuccess;
+    const int threads = sch.threads > max_threads<MODE>() ? max_threads<MODE>() : sch.threads;
+    hipLaunchKernelGGL((expand_args<MODE, PM>), dim3(grid), dim3(threads), Ly.total, stream, pack);
+    return hipGetLastError();
 }
 
 template <int MODE, int PM>
@@ -627,6 +667,14 @@ hipError_t configure_expand_kernels() {
 hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queue, int32_t n_tiles,
                          const Variant &v, const Schedule &sch, int32_t n_cu, hipStream_t stream) {
 #define HDX_LAUNCH(M, P) launch_expand_t<M, P>(d_tasks, d_tiles, d_queue, n_tiles, v.n_max, sch, n_cu, stream)
+    if (v.mode == 0) return HDX_LAUNCH(0, 1);
+    if (v.mode == 1) return v.pm == 8 ? HDX_LAUNCH(1, 8) : v.pm == 16 ? HDX_LAUNCH(1, 16) : HDX_LAUNCH(1, 32);
+    return v.pm == 8 ? HDX_LAUNCH(2, 8) : v.pm == 16 ? HDX_LAUNCH(2, 16) : HDX_LAUNCH(2, 32);
+#undef HDX_LAUNCH
+}
+
+hipError_t launch_expand_args(const ArgPack &pack, const Variant &v, const Schedule &sch, hipStream_t stream) {
+#define HDX_LAUNCH(M, P) launch_args_t<M, P>(pack, sch, stream)
     if (v.mode == 0) return HDX_LAUNCH(0, 1);
     if (v.mode == 1) return v.pm == 8 ? HDX_LAUNCH(1, 8) : v.pm == 16 ? HDX_LAUNCH(1, 16) : HDX_LAUNCH(1, 32);
     return v.pm == 8 ? HDX_LAUNCH(2, 8) : v.pm == 16 ? HDX_LAUNCH(2, 16) : HDX_LAUNCH(2, 32);

@@ -221,6 +221,16 @@ void hdx_internal_set_error(hdx_ctx *ctx, const char *msg) {
     ctx->err = msg;
 }
 
+// Wait for every staged call of the context and forget the streams its
+// events were recorded on (call before destroying those streams).
+void hdx_internal_quiesce(hdx_ctx *ctx) {
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    for (auto &s : ctx->slots) {
+        if (s.used) hipEventSynchronize(s.done);
+        s.used = false;
+    }
+}
+
 extern "C" {
 
 int32_t hdx_model_max_children(const hdx_model *m, int32_t n) {
@@ -439,6 +449,23 @@ hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
     hdx_status st = validate_leaves(ctx, leaves, n_leaves, &sh);
     if (st != HDX_OK || n_leaves == 0) return st;
     hipSetDevice(ctx->device);
+    const Variant v0 = pick_variant(sh.has_rs, sh.has_ped, sh.ped_max, sh.n_max);
+    if (n_leaves <= kArgLeaves) {
+        // small calls carry their descriptors in the kernel arguments
+        static_assert(sizeof(ArgPack) <= 4096, "kernel argument pack too large");
+        ArgPack pack;
+        memset(&pack, 0, sizeof(pack));
+        Tile tiles[kArgLeaves * (kMaxRocks + 5)];
+        pack_leaves(leaves, n_leaves, pack.t, tiles);
+        pack.tile_begin[0] = 0;
+        for (int32_t i = 0; i < n_leaves; ++i) pack.tile_begin[i + 1] = pack.tile_begin[i] + pack.t[i].n_actions;
+        pack.n_leaves = n_leaves;
+        pack.n_max = v0.n_max;
+        const Schedule sch = ctx->sched_fixed ? ctx->sched : default_schedule(v0);
+        pack.xcd_remap = sch.xcd_remap;
+        hipError_t e = launch_expand_args(pack, v0, sch, (hipStream_t)stream);
+        return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "expand launch");
+    }
     std::lock_guard<std::mutex> lock(ctx->mu);
     Slot &s = ctx->slots[ctx->next_slot];
     ctx->next_slot = (ctx->next_slot + 1) % kSlots;

@@ -592,6 +592,7 @@ extern "C" hdx_status hdx_search(hdx_ctx *ctx, const hdx_model *model, const hdx
         }
     }
     hipStreamSynchronize(main_stream);
+    hdx_internal_quiesce(ctx);
     hipStreamDestroy(main_stream);
     hipDeviceSynchronize();
     hipFree(S.arena);
