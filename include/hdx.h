@@ -292,6 +292,45 @@ hdx_status hdx_backup(hdx_tree *tree, int64_t node);
 hdx_status hdx_tree_bounds(const hdx_tree *tree, int64_t node, double *u, double *l);
 int64_t hdx_tree_size(const hdx_tree *tree);
 
+/* ---- Rollout-value surrogate ------------------------------------------- */
+
+/* A small MLP that estimates the default-policy rollout value of a state
+ * (the lower-bound term of Eq. 13) from 64 state features:
+ * 64 -> 256 -> 256 -> 256 -> 1 with ReLU, BF16 weights and activations on
+ * MFMA with FP32 accumulation, FP32 master weights trained with Adam on the
+ * mean squared error.  Parameters are one packed FP32 vector:
+ * W1[64][256], b1[256], W2[256][256], b2[256], W3[256][256], b3[256],
+ * w4[256], b4[1] (W[in][out], row-major).  Feature matrices are BF16
+ * [n][64] in device memory.  Forward, backward and the optimizer are the
+ * library's own kernels.  The library owns the handle; the first call with
+ * a larger batch allocates scratch. */
+#define HDX_MLP_IN 64
+#define HDX_MLP_HIDDEN 256
+#define HDX_MLP_PARAMS 148481
+typedef struct hdx_mlp hdx_mlp;
+/* He-uniform initialisation from `seed`. */
+hdx_status hdx_mlp_create(hdx_ctx *ctx, uint32_t seed, hdx_mlp **out);
+hdx_status hdx_mlp_destroy(hdx_ctx *ctx, hdx_mlp *mlp);
+/* Copy the FP32 parameters to / from host memory (set resets Adam). */
+hdx_status hdx_mlp_get_params(hdx_ctx *ctx, const hdx_mlp *mlp, float *host_params);
+hdx_status hdx_mlp_set_params(hdx_ctx *ctx, hdx_mlp *mlp, const float *host_params);
+/* y[i] = MLP(X[i]) for n rows (device arrays). */
+hdx_status hdx_mlp_forward(hdx_ctx *ctx, hdx_mlp *mlp, const uint16_t *X, int64_t n, float *y, hdx_stream stream);
+/* Gradients of mean((MLP(X) - t)^2) over a batch (a multiple of 64, at
+ * most 65536 rows) into grads (device, HDX_MLP_PARAMS floats); loss
+ * (device float) may be NULL.  No update. */
+hdx_status hdx_mlp_gradients(hdx_ctx *ctx, hdx_mlp *mlp, const uint16_t *X, const float *t, int32_t batch,
+                             float *grads, float *loss, hdx_stream stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on one batch. */
+hdx_status hdx_mlp_train_step(hdx_ctx *ctx, hdx_mlp *mlp, const uint16_t *X, const float *t, int32_t batch,
+                              float lr, float *loss, hdx_stream stream);
+/* Surrogate input features of n states (device): RockSample x/n, y/n,
+ * terminal, (horizon - depth)/100, rock qualities, rock offsets dx/n and
+ * dy/n; driving s/L, speed level, terminal, (horizon - depth)/100, then per
+ * pedestrian (px - s)/10, py/10, goal/n_goals; zero padding to 64. */
+hdx_status hdx_features(hdx_ctx *ctx, const hdx_model *model, hdx_states states, const int32_t *depths, int64_t n,
+                        int32_t horizon, uint16_t *X, hdx_stream stream);
+
 /* ---- Parallel DESPOT search (Sec. III-A, III-C) over the GPU expansion -- */
 
 /* One planning step of DESPOT run by n_threads CPU threads on one shared

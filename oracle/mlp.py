@@ -1,0 +1,99 @@
+"""FP64 reference of the rollout-value surrogate (test infrastructure only).
+
+An MLP 64 -> 256 -> 256 -> 256 -> 1 with ReLU, evaluated and
+differentiated in FP64 with plain numpy by the chain rule.  Parameters are
+one packed vector in the library's documented order: W1[64][256], b1,
+W2[256][256], b2, W3[256][256], b3, w4[256], b4 (W[in][out]).  Also the
+surrogate's state features, written from their documented definition.
+
+Pinned by central finite differences (tests/test_oracle_mlp.py).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+IN, HID = 64, 256
+SIZES = [("W1", (IN, HID)), ("b1", (HID,)), ("W2", (HID, HID)), ("b2", (HID,)),
+         ("W3", (HID, HID)), ("b3", (HID,)), ("w4", (HID,)), ("b4", (1,))]
+N_PARAMS = sum(int(np.prod(s)) for _, s in SIZES)
+
+
+def unpack(p: np.ndarray) -> dict:
+    out, o = {}, 0
+    for name, shape in SIZES:
+        n = int(np.prod(shape))
+        out[name] = np.asarray(p[o:o + n], dtype=np.float64).reshape(shape)
+        o += n
+    return out
+
+
+def pack(d: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(d[name], np.float64).ravel() for name, _ in SIZES])
+
+
+def forward(p: np.ndarray, X: np.ndarray, keep: bool = False):
+    w = unpack(p)
+    X = np.asarray(X, np.float64)
+    z1 = X @ w["W1"] + w["b1"]
+    h1 = np.maximum(z1, 0.0)
+    z2 = h1 @ w["W2"] + w["b2"]
+    h2 = np.maximum(z2, 0.0)
+    z3 = h2 @ w["W3"] + w["b3"]
+    h3 = np.maximum(z3, 0.0)
+    y = h3 @ w["w4"] + w["b4"][0]
+    if keep:
+        return y, dict(X=X, z1=z1, h1=h1, z2=z2, h2=h2, z3=z3, h3=h3)
+    return y
+
+
+def loss(p: np.ndarray, X: np.ndarray, t: np.ndarray) -> float:
+    y = forward(p, X)
+    return float(np.mean((y - np.asarray(t, np.float64)) ** 2))
+
+
+def gradients(p: np.ndarray, X: np.ndarray, t: np.ndarray) -> np.ndarray:
+    """d loss / d p for loss = mean((y - t)^2), by backpropagation."""
+    w = unpack(p)
+    y, c = forward(p, X, keep=True)
+    B = X.shape[0]
+    dy = 2.0 * (y - np.asarray(t, np.float64)) / B
+    g = {}
+    g["w4"] = c["h3"].T @ dy
+    g["b4"] = np.array([dy.sum()])
+    dz3 = np.outer(dy, w["w4"]) * (c["z3"] > 0)
+    g["W3"] = c["h2"].T @ dz3
+    g["b3"] = dz3.sum(0)
+    dz2 = (dz3 @ w["W3"].T) * (c["z2"] > 0)
+    g["W2"] = c["h1"].T @ dz2
+    g["b2"] = dz2.sum(0)
+    dz1 = (dz2 @ w["W2"].T) * (c["z1"] > 0)
+    g["W1"] = c["X"].T @ dz1
+    g["b1"] = dz1.sum(0)
+    return pack(g)
+
+
+def bf16_round(a) -> np.ndarray:
+    """Round FP32 values to BF16 (nearest even), returned as float32."""
+    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return (r & 0xFFFFFFFF).astype(np.uint32).view(np.float32)
+
+
+def rocksample_features(desc: dict, w: np.ndarray, depths: np.ndarray, horizon: int) -> np.ndarray:
+    """Features of RockSample states as FP32 before BF16 rounding: x/n, y/n,
+    terminal, (horizon - depth)/100, rock qualities, (rock_x - x)/n,
+    (rock_y - y)/n, zeros to 64 columns."""
+    w = np.asarray(w, np.int64)
+    n, m = desc["n"], desc["m"]
+    inv = np.float32(1.0) / np.float32(n)
+    x, y = w & 31, (w >> 5) & 31
+    f = np.zeros((w.shape[0], IN), np.float32)
+    f[:, 0] = x.astype(np.float32) * inv
+    f[:, 1] = y.astype(np.float32) * inv
+    f[:, 2] = ((w >> 30) & 1).astype(np.float32)
+    f[:, 3] = np.maximum(horizon - np.asarray(depths), 0).astype(np.float32) * np.float32(0.01)
+    for i in range(m):
+        f[:, 4 + i] = ((w >> (10 + i)) & 1).astype(np.float32)
+        f[:, 4 + m + i] = (np.float32(desc["rock_x"][i]) - x.astype(np.float32)) * inv
+        f[:, 4 + 2 * m + i] = (np.float32(desc["rock_y"][i]) - y.astype(np.float32)) * inv
+    return f

@@ -12,8 +12,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libhdx.so")
 OBJ = os.path.join(PKG, "_build")
-SOURCES = ["kernels.hip", "runtime.cpp", "tree.cpp", "search.cpp"]
-HEADERS = ["internal.hpp", "models.hpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "tree.cpp", "search.cpp", "mlp.hip", "mlp_abi.cpp"]
+HEADERS = ["internal.hpp", "models.hpp", "mlp.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

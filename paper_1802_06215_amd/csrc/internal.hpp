@@ -211,6 +211,7 @@ int32_t max_dynamic_lds();
 const hdx_model_desc *hdx_internal_desc(const hdx_model *m);
 void hdx_internal_set_error(hdx_ctx *ctx, const char *msg);
 void hdx_internal_quiesce(hdx_ctx *ctx);
+const hdx::DevModel *hdx_internal_devmodel(const hdx_model *m);
 
 namespace hdx {
 

@@ -1,0 +1,59 @@
+// Surrogate MLP: parameter layout, device buffers and kernel launchers.
+#pragma once
+
+#include "internal.hpp"
+
+namespace hdx {
+
+constexpr int kMlpIn = HDX_MLP_IN;          // 64 features
+constexpr int kMlpHidden = HDX_MLP_HIDDEN;  // 256
+constexpr int64_t kMlpChunkRows = 1 << 16;  // rows per forward chunk
+// packed parameter vector: W1 [64][256], b1, W2 [256][256], b2, W3, b3, w4 [256], b4
+constexpr int64_t kOffW1 = 0;
+constexpr int64_t kOffB1 = kOffW1 + (int64_t)kMlpIn * kMlpHidden;
+constexpr int64_t kOffW2 = kOffB1 + kMlpHidden;
+constexpr int64_t kOffB2 = kOffW2 + (int64_t)kMlpHidden * kMlpHidden;
+constexpr int64_t kOffW3 = kOffB2 + kMlpHidden;
+constexpr int64_t kOffB3 = kOffW3 + (int64_t)kMlpHidden * kMlpHidden;
+constexpr int64_t kOffW4 = kOffB3 + kMlpHidden;
+constexpr int64_t kOffB4 = kOffW4 + kMlpHidden;
+constexpr int64_t kMlpParams = kOffB4 + 1;
+static_assert(kMlpParams == HDX_MLP_PARAMS, "parameter count");
+
+struct MlpDev {
+    float *p;      // FP32 master parameters
+    uint16_t *pb;  // BF16 copy
+    float *m, *v;  // Adam moments
+    float *g;      // gradients
+    const uint16_t *w1b, *w2b, *w3b, *w4b;
+    const float *b1, *b2, *b3, *b4;
+};
+
+struct MlpScratch {
+    int64_t rows = 0;
+    uint16_t *h1 = nullptr, *h2 = nullptr, *h3 = nullptr, *g1 = nullptr, *g2 = nullptr, *g3 = nullptr;
+    float *y = nullptr, *dy = nullptr, *loss_part = nullptr;
+};
+
+struct FeatArgs {
+    const DevModel *model;
+    StatesPtr states;
+    const int32_t *depths;
+    int64_t n;
+    int32_t horizon;
+    uint16_t *X;
+};
+
+hipError_t mlp_gemm(int M, int N, int K, const uint16_t *A, int lda, int a_t, const uint16_t *B, int ldb, int b_t,
+                    int epi, const float *bias, const uint16_t *mask, int ldm, uint16_t *out_bf, float *out_f, int ldo,
+                    hipStream_t s);
+hipError_t mlp_forward(const MlpDev &P, const uint16_t *X, int64_t n, uint16_t *H1, uint16_t *H2, uint16_t *H3,
+                       float *y, hipStream_t s);
+hipError_t mlp_backward(const MlpDev &P, const uint16_t *X, const float *t, int B, MlpScratch &S, float *grads,
+                        hipStream_t s);
+hipError_t mlp_adam(MlpDev &P, const float *grads, float lr, int step, hipStream_t s);
+hipError_t mlp_refresh_bf16(MlpDev &P, hipStream_t s);
+hipError_t launch_features(const FeatArgs &a, hipStream_t s);
+hipError_t mlp_sum_loss(const float *part, int n, float *out, hipStream_t s);
+
+}  // namespace hdx

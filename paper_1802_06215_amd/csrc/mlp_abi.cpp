@@ -1,0 +1,189 @@
+// C ABI of the rollout-value surrogate: create, parameters, forward,
+// gradients, training step (Adam) and state features.
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "mlp.hpp"
+
+using namespace hdx;
+
+struct hdx_mlp {
+    MlpDev P;
+    MlpScratch S;
+    float *grads = nullptr;
+    float *loss = nullptr;
+    int step = 0;
+    std::mutex mu;
+};
+
+namespace {
+
+// He-uniform initialisation from a splitmix64 sequence (host, deterministic)
+uint64_t splitmix(uint64_t &s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+void init_params(uint32_t seed, std::vector<float> &p) {
+    uint64_t s = 0x6D6C7000ull ^ seed;
+    auto uni = [&]() { return (double)(splitmix(s) >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0; };
+    auto fill = [&](int64_t off, int64_t n, double bound) {
+        for (int64_t i = 0; i < n; ++i) p[off + i] = (float)(bound * uni());
+    };
+    fill(kOffW1, kOffB1 - kOffW1, sqrt(6.0 / kMlpIn));
+    fill(kOffW2, kOffB2 - kOffW2, sqrt(6.0 / kMlpHidden));
+    fill(kOffW3, kOffB3 - kOffW3, sqrt(6.0 / kMlpHidden));
+    fill(kOffW4, kOffB4 - kOffW4, sqrt(3.0 / kMlpHidden));
+}
+
+bool grow_scratch(MlpScratch &S, int64_t rows) {
+    if (S.rows >= rows) return true;
+    for (void *ptr : {(void *)S.h1, (void *)S.h2, (void *)S.h3, (void *)S.g1, (void *)S.g2, (void *)S.g3,
+                      (void *)S.y, (void *)S.dy, (void *)S.loss_part})
+        if (ptr) hipFree(ptr);
+    S = MlpScratch();
+    const size_t hb = (size_t)rows * kMlpHidden * sizeof(uint16_t);
+    if (hipMalloc(&S.h1, hb) != hipSuccess || hipMalloc(&S.h2, hb) != hipSuccess || hipMalloc(&S.h3, hb) != hipSuccess ||
+        hipMalloc(&S.g1, hb) != hipSuccess || hipMalloc(&S.g2, hb) != hipSuccess || hipMalloc(&S.g3, hb) != hipSuccess ||
+        hipMalloc(&S.y, rows * sizeof(float)) != hipSuccess || hipMalloc(&S.dy, rows * sizeof(float)) != hipSuccess ||
+        hipMalloc(&S.loss_part, ((rows + 255) / 256) * sizeof(float)) != hipSuccess)
+        return false;
+    S.rows = rows;
+    return true;
+}
+
+void bind(MlpDev &P) {
+    P.w1b = P.pb + kOffW1;
+    P.w2b = P.pb + kOffW2;
+    P.w3b = P.pb + kOffW3;
+    P.w4b = P.pb + kOffW4;
+    P.b1 = P.p + kOffB1;
+    P.b2 = P.p + kOffB2;
+    P.b3 = P.p + kOffB3;
+    P.b4 = P.p + kOffB4;
+}
+
+StatesPtr to_states(const hdx_states &s) {
+    StatesPtr p;
+    p.w = s.w;
+    p.s = s.s;
+    p.car = s.car;
+    p.px = s.px;
+    p.py = s.py;
+    p.goal = s.goal;
+    p.stride = s.stride;
+    return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+hdx_status hdx_mlp_create(hdx_ctx *ctx, uint32_t seed, hdx_mlp **out) {
+    if (!ctx || !out) return HDX_E_INVALID;
+    *out = nullptr;
+    hdx_mlp *m = new hdx_mlp();
+    const size_t pbytes = kMlpParams * sizeof(float);
+    if (hipMalloc(&m->P.p, pbytes) != hipSuccess || hipMalloc(&m->P.pb, kMlpParams * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&m->P.m, pbytes) != hipSuccess || hipMalloc(&m->P.v, pbytes) != hipSuccess ||
+        hipMalloc(&m->grads, pbytes) != hipSuccess || hipMalloc(&m->loss, sizeof(float)) != hipSuccess) {
+        hdx_mlp_destroy(ctx, m);
+        return HDX_E_NOMEM;
+    }
+    bind(m->P);
+    std::vector<float> p(kMlpParams, 0.0f);
+    init_params(seed, p);
+    hdx_status st = hdx_mlp_set_params(ctx, m, p.data());
+    if (st != HDX_OK) {
+        hdx_mlp_destroy(ctx, m);
+        return st;
+    }
+    *out = m;
+    return HDX_OK;
+}
+
+hdx_status hdx_mlp_destroy(hdx_ctx *ctx, hdx_mlp *m) {
+    if (!ctx || !m) return HDX_E_INVALID;
+    hipDeviceSynchronize();
+    for (void *ptr : {(void *)m->P.p, (void *)m->P.pb, (void *)m->P.m, (void *)m->P.v, (void *)m->grads,
+                      (void *)m->loss})
+        if (ptr) hipFree(ptr);
+    grow_scratch(m->S, 0);
+    for (void *ptr : {(void *)m->S.h1, (void *)m->S.h2, (void *)m->S.h3, (void *)m->S.g1, (void *)m->S.g2,
+                      (void *)m->S.g3, (void *)m->S.y, (void *)m->S.dy, (void *)m->S.loss_part})
+        if (ptr) hipFree(ptr);
+    delete m;
+    return HDX_OK;
+}
+
+hdx_status hdx_mlp_get_params(hdx_ctx *ctx, const hdx_mlp *m, float *host) {
+    if (!ctx || !m || !host) return HDX_E_INVALID;
+    return hipMemcpy(host, m->P.p, kMlpParams * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess ? HDX_OK
+                                                                                                   : HDX_E_DEVICE;
+}
+
+hdx_status hdx_mlp_set_params(hdx_ctx *ctx, hdx_mlp *m, const float *host) {
+    if (!ctx || !m || !host) return HDX_E_INVALID;
+    const size_t pbytes = kMlpParams * sizeof(float);
+    if (hipMemcpy(m->P.p, host, pbytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(m->P.m, 0, pbytes) != hipSuccess || hipMemset(m->P.v, 0, pbytes) != hipSuccess ||
+        mlp_refresh_bf16(m->P, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        return HDX_E_DEVICE;
+    m->step = 0;
+    return HDX_OK;
+}
+
+hdx_status hdx_mlp_forward(hdx_ctx *ctx, hdx_mlp *m, const uint16_t *X, int64_t n, float *y, hdx_stream stream) {
+    if (!ctx || !m || (n > 0 && (!X || !y)) || n < 0) return HDX_E_INVALID;
+    if (n == 0) return HDX_OK;
+    std::lock_guard<std::mutex> g(m->mu);
+    if (!grow_scratch(m->S, std::min<int64_t>(n, kMlpChunkRows))) return HDX_E_NOMEM;
+    return mlp_forward(m->P, X, n, m->S.h1, m->S.h2, m->S.h3, y, (hipStream_t)stream) == hipSuccess ? HDX_OK
+                                                                                                   : HDX_E_DEVICE;
+}
+
+hdx_status hdx_mlp_gradients(hdx_ctx *ctx, hdx_mlp *m, const uint16_t *X, const float *t, int32_t batch, float *grads,
+                             float *loss, hdx_stream stream) {
+    if (!ctx || !m || !X || !t || !grads) return HDX_E_INVALID;
+    if (batch < 64 || batch % 64 != 0 || batch > kMlpChunkRows) return HDX_E_SHAPE;
+    std::lock_guard<std::mutex> g(m->mu);
+    if (!grow_scratch(m->S, batch)) return HDX_E_NOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    if (mlp_backward(m->P, X, t, batch, m->S, grads, s) != hipSuccess) return HDX_E_DEVICE;
+    if (loss && mlp_sum_loss(m->S.loss_part, (batch + 255) / 256, loss, s) != hipSuccess) return HDX_E_DEVICE;
+    return HDX_OK;
+}
+
+hdx_status hdx_mlp_train_step(hdx_ctx *ctx, hdx_mlp *m, const uint16_t *X, const float *t, int32_t batch, float lr,
+                              float *loss, hdx_stream stream) {
+    if (!ctx || !m || !X || !t || !(lr > 0.0f)) return HDX_E_INVALID;
+    if (batch < 64 || batch % 64 != 0 || batch > kMlpChunkRows) return HDX_E_SHAPE;
+    std::lock_guard<std::mutex> g(m->mu);
+    if (!grow_scratch(m->S, batch)) return HDX_E_NOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    if (mlp_backward(m->P, X, t, batch, m->S, m->grads, s) != hipSuccess) return HDX_E_DEVICE;
+    if (loss && mlp_sum_loss(m->S.loss_part, (batch + 255) / 256, loss, s) != hipSuccess) return HDX_E_DEVICE;
+    m->step += 1;
+    return mlp_adam(m->P, m->grads, lr, m->step, s) == hipSuccess ? HDX_OK : HDX_E_DEVICE;
+}
+
+hdx_status hdx_features(hdx_ctx *ctx, const hdx_model *model, hdx_states states, const int32_t *depths, int64_t n,
+                        int32_t horizon, uint16_t *X, hdx_stream stream) {
+    if (!ctx || !model || n < 0 || (n > 0 && (!depths || !X))) return HDX_E_INVALID;
+    if (n == 0) return HDX_OK;
+    FeatArgs a;
+    a.model = hdx_internal_devmodel(model);
+    a.states = to_states(states);
+    a.depths = depths;
+    a.n = n;
+    a.horizon = horizon;
+    a.X = X;
+    return launch_features(a, (hipStream_t)stream) == hipSuccess ? HDX_OK : HDX_E_DEVICE;
+}
+
+}  // extern "C"

@@ -216,6 +216,8 @@ int32_t hdx_model_actions(const hdx_model *m) { return m ? m->desc.n_actions : -
 
 const hdx_model_desc *hdx_internal_desc(const hdx_model *m) { return &m->desc; }
 
+const hdx::DevModel *hdx_internal_devmodel(const hdx_model *m) { return m->d_model; }
+
 void hdx_internal_set_error(hdx_ctx *ctx, const char *msg) {
     std::lock_guard<std::mutex> lock(ctx->mu);
     ctx->err = msg;

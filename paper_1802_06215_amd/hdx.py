@@ -96,7 +96,9 @@ EXPORTS = ["hdx_version", "hdx_init", "hdx_fini", "hdx_last_error", "hdx_upload_
            "hdx_sample_scenarios", "hdx_expand_leaf", "hdx_rollout_bounds", "hdx_philox",
            "hdx_fp32_selftest", "hdx_batch_create", "hdx_batch_destroy", "hdx_batch_set_leaves",
            "hdx_batch_set_schedule", "hdx_batch_get_schedule", "hdx_batch_use_graph",
-           "hdx_batch_launch", "hdx_batch_autotune", "hdx_search",
+           "hdx_batch_launch", "hdx_batch_autotune", "hdx_search", "hdx_mlp_create", "hdx_mlp_destroy",
+           "hdx_mlp_get_params", "hdx_mlp_set_params", "hdx_mlp_forward", "hdx_mlp_gradients",
+           "hdx_mlp_train_step", "hdx_features",
            "hdx_tree_create", "hdx_tree_destroy", "hdx_tree_add_children", "hdx_backup",
            "hdx_tree_bounds", "hdx_tree_size"]
 
@@ -137,6 +139,14 @@ def load_library():
     L.hdx_batch_launch.argtypes = [P, P, P]
     L.hdx_batch_autotune.argtypes = [P, P, I32, C.POINTER(C.c_float)]
     L.hdx_search.argtypes = [P, P, C.POINTER(Belief), C.POINTER(SearchCfg), C.POINTER(SearchResult)]
+    L.hdx_mlp_create.argtypes = [P, U32, C.POINTER(P)]
+    L.hdx_mlp_destroy.argtypes = [P, P]
+    L.hdx_mlp_get_params.argtypes = [P, P, P]
+    L.hdx_mlp_set_params.argtypes = [P, P, P]
+    L.hdx_mlp_forward.argtypes = [P, P, P, I64, P, P]
+    L.hdx_mlp_gradients.argtypes = [P, P, P, P, I32, P, P, P]
+    L.hdx_mlp_train_step.argtypes = [P, P, P, P, I32, C.c_float, P, P]
+    L.hdx_features.argtypes = [P, P, States, P, I64, I32, P, P]
     L.hdx_tree_create.argtypes = [I32, C.c_double, I32, C.c_double, C.c_double, C.POINTER(P)]
     L.hdx_tree_destroy.argtypes = [P]
     L.hdx_tree_add_children.argtypes = [P, I64, P, P, P, P, P, P, I32, C.POINTER(I64)]
@@ -470,6 +480,61 @@ class Batch:
         if getattr(self, "handle", None) is not None:
             self.lib.hdx_batch_destroy(self.ctx.handle, self.handle)
             self.handle = None
+
+
+MLP_IN, MLP_HIDDEN, MLP_PARAMS = 64, 256, 148481
+
+
+class Mlp:
+    """hdx_mlp: the rollout-value surrogate (BF16 MFMA, FP32 master weights)."""
+
+    def __init__(self, ctx: "Context", seed: int = 0):
+        self.ctx, self.lib = ctx, ctx.lib
+        h = C.c_void_p()
+        ctx._check(self.lib.hdx_mlp_create(ctx.handle, seed, C.byref(h)))
+        self.handle = h
+
+    def params(self) -> np.ndarray:
+        out = np.empty(MLP_PARAMS, np.float32)
+        self.ctx._check(self.lib.hdx_mlp_get_params(self.ctx.handle, self.handle, out.ctypes.data))
+        return out
+
+    def set_params(self, p) -> None:
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.shape == (MLP_PARAMS,)
+        self.ctx._check(self.lib.hdx_mlp_set_params(self.ctx.handle, self.handle, p.ctypes.data))
+
+    def forward(self, X: torch.Tensor, stream=None) -> torch.Tensor:
+        """X: int16/uint16 BF16 bits [n, 64] on the device."""
+        n = X.shape[0]
+        y = torch.empty(n, dtype=torch.float32, device=X.device)
+        self.ctx._check(self.lib.hdx_mlp_forward(self.ctx.handle, self.handle, _dp(X), n, _dp(y), _stream(stream)))
+        return y
+
+    def gradients(self, X, t, stream=None):
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        self.ctx._check(self.lib.hdx_mlp_gradients(self.ctx.handle, self.handle, _dp(X), _dp(t), X.shape[0], _dp(g),
+                                                   _dp(loss), _stream(stream)))
+        return g, loss
+
+    def train_step(self, X, t, lr: float, loss=None, stream=None):
+        self.ctx._check(self.lib.hdx_mlp_train_step(self.ctx.handle, self.handle, _dp(X), _dp(t), X.shape[0], lr,
+                                                    _dp(loss), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            self.lib.hdx_mlp_destroy(self.ctx.handle, self.handle)
+            self.handle = None
+
+
+def features(ctx: "Context", model: Model, states: dict, depths, horizon: int, stream=None) -> torch.Tensor:
+    """hdx_features: BF16 surrogate features [n, 64] (as int16 bits)."""
+    n = int(depths.numel())
+    X = torch.empty((n, MLP_IN), dtype=torch.int16, device=depths.device)
+    ctx._check(ctx.lib.hdx_features(ctx.handle, model.handle, states_view(model, states), _dp(depths), n, horizon,
+                                    _dp(X), _stream(stream)))
+    return X
 
 
 def fp32_selftest(ctx: "Context", a, b, c, stream=None):
