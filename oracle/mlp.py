@@ -31,42 +31,53 @@ def pack(d: dict) -> np.ndarray:
     return np.concatenate([np.asarray(d[name], np.float64).ravel() for name, _ in SIZES])
 
 
-def forward(p: np.ndarray, X: np.ndarray, keep: bool = False):
+def _q(a, on: bool):
+    """BF16 rounding point (identity when off)."""
+    return bf16_round(np.asarray(a, np.float32)).astype(np.float64) if on else a
+
+
+def forward(p: np.ndarray, X: np.ndarray, keep: bool = False, bf16: bool = False):
+    """MLP output; with bf16=True the hidden activations are rounded to BF16
+    after each layer (the library's mixed-precision definition)."""
     w = unpack(p)
     X = np.asarray(X, np.float64)
     z1 = X @ w["W1"] + w["b1"]
-    h1 = np.maximum(z1, 0.0)
+    h1 = _q(np.maximum(z1, 0.0), bf16)
     z2 = h1 @ w["W2"] + w["b2"]
-    h2 = np.maximum(z2, 0.0)
+    h2 = _q(np.maximum(z2, 0.0), bf16)
     z3 = h2 @ w["W3"] + w["b3"]
-    h3 = np.maximum(z3, 0.0)
+    h3 = _q(np.maximum(z3, 0.0), bf16)
     y = h3 @ w["w4"] + w["b4"][0]
     if keep:
         return y, dict(X=X, z1=z1, h1=h1, z2=z2, h2=h2, z3=z3, h3=h3)
     return y
 
 
-def loss(p: np.ndarray, X: np.ndarray, t: np.ndarray) -> float:
-    y = forward(p, X)
+def loss(p: np.ndarray, X: np.ndarray, t: np.ndarray, bf16: bool = False) -> float:
+    y = forward(p, X, bf16=bf16)
     return float(np.mean((y - np.asarray(t, np.float64)) ** 2))
 
 
-def gradients(p: np.ndarray, X: np.ndarray, t: np.ndarray) -> np.ndarray:
-    """d loss / d p for loss = mean((y - t)^2), by backpropagation."""
+def gradients(p: np.ndarray, X: np.ndarray, t: np.ndarray, bf16: bool = False) -> np.ndarray:
+    """d loss / d p for loss = mean((y - t)^2), by backpropagation; with
+    bf16=True the activations and the back-propagated gradients of the
+    hidden layers are rounded to BF16 where the library stores them."""
     w = unpack(p)
-    y, c = forward(p, X, keep=True)
+    y, c = forward(p, X, keep=True, bf16=bf16)
     B = X.shape[0]
     dy = 2.0 * (y - np.asarray(t, np.float64)) / B
+    if bf16:
+        dy = np.asarray(dy, np.float32).astype(np.float64)
     g = {}
     g["w4"] = c["h3"].T @ dy
     g["b4"] = np.array([dy.sum()])
-    dz3 = np.outer(dy, w["w4"]) * (c["z3"] > 0)
+    dz3 = _q(np.outer(dy, w["w4"]) * (c["h3"] > 0 if bf16 else c["z3"] > 0), bf16)
     g["W3"] = c["h2"].T @ dz3
     g["b3"] = dz3.sum(0)
-    dz2 = (dz3 @ w["W3"].T) * (c["z2"] > 0)
+    dz2 = _q((dz3 @ w["W3"].T) * (c["h2"] > 0 if bf16 else c["z2"] > 0), bf16)
     g["W2"] = c["h1"].T @ dz2
     g["b2"] = dz2.sum(0)
-    dz1 = (dz2 @ w["W2"].T) * (c["z1"] > 0)
+    dz1 = _q((dz2 @ w["W2"].T) * (c["h1"] > 0 if bf16 else c["z1"] > 0), bf16)
     g["W1"] = c["X"].T @ dz1
     g["b1"] = dz1.sum(0)
     return pack(g)
