@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--search-seconds", type=float, default=1.0,
                     help="planning budget of each search measurement (rs15 only; 0 = skip)")
     ap.add_argument("--schedule", default="", help="threads,persistent,xcd_remap (skips the autotuner)")
+    ap.add_argument("--surrogate-epochs", type=int, default=4,
+                    help="training epochs of the surrogate comparison (rs15 only; 0 = skip)")
+    ap.add_argument("--surrogate-leaves", type=int, default=1024,
+                    help="training leaves of 100 scenarios each (x 20 actions = pairs / 2000)")
     return ap.parse_args()
 
 
@@ -161,6 +165,113 @@ def build(ctx, args):
     torch.cuda.synchronize()
     return dict(items=items, leaves=leaves, keep=keep, slabs=slabs, state_slabs=state_slabs, models=models,
                 groups=list(groups.values()))
+
+
+def surrogate_section(ctx, args):
+    """Learned rollout values against full rollouts on RockSample 15x15:
+    uniform-random rollout policy of depth 90 (the expensive case a
+    surrogate can pay for), training pairs from expansions of synthetic
+    leaves, held-out leaves of the benchmark's shape, and the search with
+    either source of leaf lower bounds at an equal planning budget."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1802_06215_amd import Mlp, hdx as H
+    from paper_1802_06215_amd import surrogate as S
+
+    desc = W.rocksample_model(15, 15, 1)
+    m = ctx.upload_model(desc)
+    rcfg = H.rollout_cfg(H.POLICY_RANDOM, 1 << 30, 90)
+
+    def leafset(specs, per_pair):
+        descs, outs, keep = [], [], []
+        for seed, n, depth in specs:
+            lf = W.rocksample_leaf(desc, 500, n, seed, depth=depth)
+            par = H.rocksample_states(lf["x"], lf["y"], lf["rocks"], lf["term"])
+            pids = torch.from_numpy(lf["ids"].astype(np.int32)).cuda()
+            idx = torch.from_numpy(lf["idx"]).cuda()
+            out = H.LeafBuffers(m, n, per_pair=per_pair)
+            descs.append(H.make_leaf(m, par, pids, idx, lf["depth"], lf["last_action"], out, seed, 0, rcfg))
+            outs.append((out, lf["depth"]))
+            keep += [par, pids, idx]
+        torch.cuda.synchronize()
+        return descs, outs, keep
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    # training set: expansions with full rollouts, per-pair outputs kept
+    specs = [(50000 + i, 100, 1 + (7 * i) % 89) for i in range(args.surrogate_leaves)]
+    descs, outs, keep = leafset(specs, True)
+    gen_s = timed(lambda: ctx.expand_leaf(descs), 1)
+    pairs = [S.leaf_pairs(ctx, m, o, d, 90) for o, d in outs]
+    X = torch.cat([p[0] for p in pairs])
+    t = torch.cat([p[1] for p in pairs])
+    del pairs, outs, descs, keep
+    net = Mlp(ctx, seed=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = S.fit(net, X, t, epochs=args.surrogate_epochs, batch=4096, lr=1e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    samples = (X.shape[0] // 4096) * 4096 * args.surrogate_epochs
+    fwd_s = timed(lambda: net.forward(X), 3)
+    log("surrogate: %d pairs, fit %.2f s, losses %s" % (X.shape[0], train_s, ["%.3f" % h for h in hist]))
+    n_pairs = int(X.shape[0])
+    del X, t
+
+    # held-out leaves with the benchmark's shapes
+    specs = [(1000 + i, max(1, 500 >> (i % 5)), 1 + i % 30) for i in range(512)]
+    descs, outs, keep = leafset(specs, False)
+    full_s = timed(lambda: ctx.expand_leaf(descs), 3)
+    full = [(o.child_l0.cpu().numpy().copy(), o.n_children.cpu().numpy().copy(), o.steps.cpu().numpy().copy())
+            for o, _ in outs]
+    sur_s = timed(lambda: ctx.expand_leaf_surrogate(descs, net, 90), 3)
+    err, ref = [], []
+    for (o, _), (l0, nc, _) in zip(outs, full):
+        ls = o.child_l0.cpu().numpy()
+        for a in range(len(nc)):
+            err.append(np.abs(ls[a, :nc[a]] - l0[a, :nc[a]]))
+            ref.append(np.abs(l0[a, :nc[a]]))
+    err, ref = np.concatenate(err), np.concatenate(ref)
+    steps_full = int(sum(st.sum() for _, _, st in full))
+
+    # search at equal budget
+    runs = {}
+    for name, sur in (("rollouts", None), ("surrogate", net)):
+        r = ctx.search(m, W.rocksample_belief(desc), K=500, n_threads=8, max_depth=90, batch_leaves=8,
+                       time_budget_s=args.search_seconds, rollout=rcfg, surrogate=sur, surrogate_horizon=90,
+                       seed=3)
+        runs[name] = dict(trials_per_s=round(r["trials"] / r["elapsed_s"], 1),
+                          expansions_per_s=round(r["expansions"] / r["elapsed_s"], 1),
+                          l_root=round(r["l_root"], 5), u_root=round(r["u_root"], 5),
+                          best_action=r["best_action"], nodes=r["nodes"])
+        log("search", name, runs[name])
+    lf_, ls_ = runs["rollouts"]["l_root"], runs["surrogate"]["l_root"]
+    net.close()
+    return dict(
+        config="RockSample 15x15, 15 rocks, uniform-random rollouts of depth 90; MLP 64-256-256-256-1 "
+               "(BF16 MFMA, FP32 accumulate)",
+        train=dict(pairs=n_pairs, leaves=args.surrogate_leaves, data_gen_s=round(gen_s, 3), epochs=args.surrogate_epochs,
+                   fit_s=round(train_s, 3), samples_per_s=round(samples / train_s, 1),
+                   tflops=round(S.FLOPS_TRAIN * samples / train_s / 1e12, 2), losses=[round(h, 4) for h in hist]),
+        forward=dict(rows=n_pairs, ms=round(fwd_s * 1e3, 3),
+                     tflops=round(S.FLOPS_FWD * n_pairs / fwd_s / 1e12, 2)),
+        heldout=dict(leaves=len(specs), full_rollout_ms=round(full_s * 1e3, 3),
+                     surrogate_ms=round(sur_s * 1e3, 3), speedup=round(full_s / sur_s, 2),
+                     full_scenario_steps=steps_full,
+                     child_l0_mae=round(float(err.mean()), 5), child_l0_mean_abs=round(float(ref.mean()), 5),
+                     child_l0_err_p50=round(float(np.median(err)), 5),
+                     child_l0_err_p90=round(float(np.percentile(err, 90)), 5)),
+        search=dict(threads=8, leaf_batch=8, budget_s=args.search_seconds, runs=runs,
+                    root_value_rel_err=round(abs(ls_ - lf_) / max(abs(lf_), 1e-9), 5)))
 
 
 def cpu_baseline(items, seconds):
@@ -277,6 +388,11 @@ def main():
                                root_gap=round(res["u_root"] - res["l_root"], 4)))
             log("search", search[-1])
 
+    sur = None
+    if args.workload == "rs15" and args.surrogate_epochs > 0 and args.search_seconds > 0:
+        log("surrogate comparison...")
+        sur = surrogate_section(ctx, args)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)...")
@@ -301,7 +417,8 @@ def main():
                            hip_graph=True, autotune_ms=tuned_ms),
                roofline=roofline, cpu_baseline=cpu,
                search=dict(config="RockSample 15x15, 15 rocks, K=500, max depth 90, %.1f s planning step"
-                           % args.search_seconds, runs=search) if search else None)
+                           % args.search_seconds, runs=search) if search else None,
+               surrogate=sur)
     print(json.dumps(out), flush=True)
     batch.close()
     ctx.close()

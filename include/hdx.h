@@ -331,6 +331,16 @@ hdx_status hdx_mlp_train_step(hdx_ctx *ctx, hdx_mlp *mlp, const uint16_t *X, con
 hdx_status hdx_features(hdx_ctx *ctx, const hdx_model *model, hdx_states states, const int32_t *depths, int64_t n,
                         int32_t horizon, uint16_t *X, hdx_stream stream);
 
+/* expand_leaf with the surrogate in place of the default-policy rollouts:
+ * the same outputs as hdx_expand_leaf, except that child_l0 is the mean of
+ * MLP(features(s')) over the child's scenarios (features at depth+1 with
+ * the given horizon), steps[a][1] is 0, and L (if given) receives the
+ * surrogate value per (action, scenario).  Scratch for the stepped states,
+ * features and values belongs to the MLP handle (grown on demand); calls
+ * on one handle are serialised. */
+hdx_status hdx_expand_leaf_surrogate(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves, hdx_mlp *mlp,
+                                     int32_t horizon, hdx_stream stream);
+
 /* ---- Parallel DESPOT search (Sec. III-A, III-C) over the GPU expansion -- */
 
 /* One planning step of DESPOT run by n_threads CPU threads on one shared
@@ -362,6 +372,9 @@ typedef struct {
     int64_t arena_bytes;   /* device memory for node data */
     uint32_t seed, step;   /* random-stream key of this planning step */
     hdx_rollout_cfg rollout;
+    hdx_mlp *surrogate;    /* non-NULL: leaves are expanded with hdx_expand_leaf_surrogate (the
+                              root's initial bounds still come from rollouts) */
+    int32_t surrogate_horizon; /* horizon of the surrogate's remaining-depth feature */
 } hdx_search_cfg;
 
 typedef struct {

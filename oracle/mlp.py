@@ -108,3 +108,25 @@ def rocksample_features(desc: dict, w: np.ndarray, depths: np.ndarray, horizon: 
         f[:, 4 + m + i] = (np.float32(desc["rock_x"][i]) - x.astype(np.float32)) * inv
         f[:, 4 + 2 * m + i] = (np.float32(desc["rock_y"][i]) - y.astype(np.float32)) * inv
     return f
+
+
+def pednav_features(desc: dict, st: dict, depths: np.ndarray, horizon: int) -> np.ndarray:
+    """Features of crowd-driving states as FP32 before BF16 rounding: s/path_len,
+    speed level/(levels-1), terminal, (horizon - depth)/100, then per
+    pedestrian (up to 20): (px - s)/10, py/10, goal index/n_goals."""
+    s = np.asarray(st["s"], np.float32)
+    car = np.asarray(st["car"], np.int64)
+    n = s.shape[0]
+    f = np.zeros((n, IN), np.float32)
+    f[:, 0] = s / np.float32(desc["path_len"])
+    f[:, 1] = (car & 0xFF).astype(np.float32) / np.float32(max(desc["n_levels"] - 1, 1))
+    f[:, 2] = ((car >> 8) & 1).astype(np.float32)
+    f[:, 3] = np.maximum(horizon - np.asarray(depths), 0).astype(np.float32) * np.float32(0.01)
+    P = min(desc["n_peds"], (IN - 4) // 3)
+    px, py = np.asarray(st["px"], np.float32), np.asarray(st["py"], np.float32)
+    goal = np.asarray(st["goal"], np.int64)
+    for j in range(P):
+        f[:, 4 + 3 * j] = (px[j] - s) * np.float32(0.1)
+        f[:, 5 + 3 * j] = py[j] * np.float32(0.1)
+        f[:, 6 + 3 * j] = goal[j].astype(np.float32) / np.float32(desc["n_goals"])
+    return f

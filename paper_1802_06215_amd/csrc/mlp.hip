@@ -188,7 +188,7 @@ __global__ void features_kernel(const FeatArgs A) {
     const HDX_CONST ModelHdr *M = (const HDX_CONST ModelHdr *)&A.model->h;
     float f[kMlpIn];
     for (int i = 0; i < kMlpIn; ++i) f[i] = 0.f;
-    const int depth = A.depths[k];
+    const int depth = A.depths ? A.depths[k] : A.depth_const;
     const float remain = (float)max(A.horizon - depth, 0) * 0.01f;
     if (M->kind == HDX_ROCKSAMPLE) {
         const int32_t w = A.states.w[k];
@@ -321,6 +321,34 @@ __global__ void sum_parts(const float *part, int n, float *out) {
     }
 }
 }  // namespace
+
+namespace {
+// Surrogate lower bounds of one leaf's children: for action a (blockIdx.y)
+// and child c, l0 = mean of the surrogate values of the child's scenarios,
+// summed in grouped order; per-scenario values copied out on request.
+__global__ void surrogate_reduce(const SurArgs A) {
+    const int a = blockIdx.y;
+    const int n = A.n;
+    const float *v = A.values + (int64_t)a * n;
+    const int nch = A.n_children[a];
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nch && c < A.cap; c += gridDim.x * blockDim.x) {
+        const int off = A.child_off[a * A.cap + c], cnt = A.child_n[a * A.cap + c];
+        const int32_t *perm = A.perm + (int64_t)a * n;
+        float s = 0.f;
+        for (int i = 0; i < cnt; ++i) s = s + v[perm[off + i]];
+        A.child_l0[a * A.cap + c] = s / (float)cnt;
+    }
+    if (A.L_out)
+        for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
+            A.L_out[(int64_t)a * n + k] = v[k];
+}
+}  // namespace
+
+hipError_t launch_surrogate_reduce(const SurArgs &a, int n_actions, hipStream_t s) {
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(surrogate_reduce, dim3(1, n_actions), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
 
 hipError_t mlp_sum_loss(const float *part, int n, float *out, hipStream_t s) {
     hipLaunchKernelGGL(sum_parts, dim3(1), dim3(64), 0, s, part, n, out);

@@ -38,9 +38,9 @@ struct MlpScratch {
 struct FeatArgs {
     const DevModel *model;
     StatesPtr states;
-    const int32_t *depths;
+    const int32_t *depths;  // per state, or NULL to use depth_const
     int64_t n;
-    int32_t horizon;
+    int32_t horizon, depth_const;
     uint16_t *X;
 };
 
@@ -55,5 +55,14 @@ hipError_t mlp_adam(MlpDev &P, const float *grads, float lr, int step, hipStream
 hipError_t mlp_refresh_bf16(MlpDev &P, hipStream_t s);
 hipError_t launch_features(const FeatArgs &a, hipStream_t s);
 hipError_t mlp_sum_loss(const float *part, int n, float *out, hipStream_t s);
+
+struct SurArgs {
+    const float *values;  // [A][n] surrogate value per (action, scenario)
+    const int32_t *perm, *n_children, *child_n, *child_off;
+    float *child_l0;
+    float *L_out;  // optional [A][n]
+    int32_t n, cap;
+};
+hipError_t launch_surrogate_reduce(const SurArgs &a, int n_actions, hipStream_t s);
 
 }  // namespace hdx

@@ -16,6 +16,9 @@ struct hdx_mlp {
     float *grads = nullptr;
     float *loss = nullptr;
     int step = 0;
+    void *sur = nullptr;  // scratch of surrogate expansions
+    size_t sur_bytes = 0;
+    hipEvent_t last = nullptr;  // completion of the latest call (orders calls across streams)
     std::mutex mu;
 };
 
@@ -80,6 +83,24 @@ StatesPtr to_states(const hdx_states &s) {
     return p;
 }
 
+// The handle's weights and scratch are shared by every call: each call
+// waits for the previous one's work, whichever stream it ran on, and marks
+// its own end.  Under stream capture the caller orders the work.
+struct Ordered {
+    hdx_mlp *m;
+    hipStream_t s;
+    bool on;
+    Ordered(hdx_mlp *m_, hipStream_t s_) : m(m_), s(s_), on(false) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess) cs = hipStreamCaptureStatusNone;
+        on = cs == hipStreamCaptureStatusNone && m->last != nullptr;
+        if (on) hipStreamWaitEvent(s, m->last, 0);
+    }
+    ~Ordered() {
+        if (on) hipEventRecord(m->last, s);
+    }
+};
+
 }  // namespace
 
 extern "C" {
@@ -91,7 +112,8 @@ hdx_status hdx_mlp_create(hdx_ctx *ctx, uint32_t seed, hdx_mlp **out) {
     const size_t pbytes = kMlpParams * sizeof(float);
     if (hipMalloc(&m->P.p, pbytes) != hipSuccess || hipMalloc(&m->P.pb, kMlpParams * sizeof(uint16_t)) != hipSuccess ||
         hipMalloc(&m->P.m, pbytes) != hipSuccess || hipMalloc(&m->P.v, pbytes) != hipSuccess ||
-        hipMalloc(&m->grads, pbytes) != hipSuccess || hipMalloc(&m->loss, sizeof(float)) != hipSuccess) {
+        hipMalloc(&m->grads, pbytes) != hipSuccess || hipMalloc(&m->loss, sizeof(float)) != hipSuccess ||
+        hipEventCreateWithFlags(&m->last, hipEventDisableTiming) != hipSuccess) {
         hdx_mlp_destroy(ctx, m);
         return HDX_E_NOMEM;
     }
@@ -111,9 +133,9 @@ hdx_status hdx_mlp_destroy(hdx_ctx *ctx, hdx_mlp *m) {
     if (!ctx || !m) return HDX_E_INVALID;
     hipDeviceSynchronize();
     for (void *ptr : {(void *)m->P.p, (void *)m->P.pb, (void *)m->P.m, (void *)m->P.v, (void *)m->grads,
-                      (void *)m->loss})
+                      (void *)m->loss, m->sur})
         if (ptr) hipFree(ptr);
-    grow_scratch(m->S, 0);
+    if (m->last) hipEventDestroy(m->last);
     for (void *ptr : {(void *)m->S.h1, (void *)m->S.h2, (void *)m->S.h3, (void *)m->S.g1, (void *)m->S.g2,
                       (void *)m->S.g3, (void *)m->S.y, (void *)m->S.dy, (void *)m->S.loss_part})
         if (ptr) hipFree(ptr);
@@ -143,6 +165,7 @@ hdx_status hdx_mlp_forward(hdx_ctx *ctx, hdx_mlp *m, const uint16_t *X, int64_t 
     if (n == 0) return HDX_OK;
     std::lock_guard<std::mutex> g(m->mu);
     if (!grow_scratch(m->S, std::min<int64_t>(n, kMlpChunkRows))) return HDX_E_NOMEM;
+    Ordered o(m, (hipStream_t)stream);
     return mlp_forward(m->P, X, n, m->S.h1, m->S.h2, m->S.h3, y, (hipStream_t)stream) == hipSuccess ? HDX_OK
                                                                                                    : HDX_E_DEVICE;
 }
@@ -154,6 +177,7 @@ hdx_status hdx_mlp_gradients(hdx_ctx *ctx, hdx_mlp *m, const uint16_t *X, const 
     std::lock_guard<std::mutex> g(m->mu);
     if (!grow_scratch(m->S, batch)) return HDX_E_NOMEM;
     hipStream_t s = (hipStream_t)stream;
+    Ordered o(m, s);
     if (mlp_backward(m->P, X, t, batch, m->S, grads, s) != hipSuccess) return HDX_E_DEVICE;
     if (loss && mlp_sum_loss(m->S.loss_part, (batch + 255) / 256, loss, s) != hipSuccess) return HDX_E_DEVICE;
     return HDX_OK;
@@ -166,6 +190,7 @@ hdx_status hdx_mlp_train_step(hdx_ctx *ctx, hdx_mlp *m, const uint16_t *X, const
     std::lock_guard<std::mutex> g(m->mu);
     if (!grow_scratch(m->S, batch)) return HDX_E_NOMEM;
     hipStream_t s = (hipStream_t)stream;
+    Ordered o(m, s);
     if (mlp_backward(m->P, X, t, batch, m->S, m->grads, s) != hipSuccess) return HDX_E_DEVICE;
     if (loss && mlp_sum_loss(m->S.loss_part, (batch + 255) / 256, loss, s) != hipSuccess) return HDX_E_DEVICE;
     m->step += 1;
@@ -182,8 +207,98 @@ hdx_status hdx_features(hdx_ctx *ctx, const hdx_model *model, hdx_states states,
     a.depths = depths;
     a.n = n;
     a.horizon = horizon;
+    a.depth_const = 0;
     a.X = X;
     return launch_features(a, (hipStream_t)stream) == hipSuccess ? HDX_OK : HDX_E_DEVICE;
+}
+
+hdx_status hdx_expand_leaf_surrogate(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves, hdx_mlp *mlp,
+                                     int32_t horizon, hdx_stream stream) {
+    if (!ctx || !mlp || n_leaves < 0 || (n_leaves > 0 && !leaves)) return HDX_E_INVALID;
+    if (n_leaves == 0) return HDX_OK;
+    // scratch: stepped states of every (action, scenario), their features and values
+    std::vector<size_t> st_off(n_leaves), pair_off(n_leaves);
+    size_t st_bytes = 0;
+    int64_t pairs = 0;
+    for (int32_t i = 0; i < n_leaves; ++i) {
+        if (!leaves[i].model) return HDX_E_INVALID;
+        const hdx_model_desc &d = *hdx_internal_desc(leaves[i].model);
+        const int64_t np = (int64_t)d.n_actions * (leaves[i].n > 0 ? leaves[i].n : 0);
+        st_off[i] = st_bytes;
+        pair_off[i] = (size_t)pairs;
+        const size_t per = d.kind == HDX_ROCKSAMPLE ? 4 : (size_t)(8 + 9 * d.n_peds);
+        st_bytes += ((size_t)np * per + 64) & ~(size_t)15;
+        pairs += np;
+    }
+    std::lock_guard<std::mutex> g(mlp->mu);
+    Ordered o(mlp, (hipStream_t)stream);
+    const size_t need = st_bytes + (size_t)pairs * (kMlpIn * sizeof(uint16_t) + sizeof(float)) + 64;
+    if (mlp->sur_bytes < need) {
+        if (mlp->sur) hipFree(mlp->sur);
+        mlp->sur = nullptr;
+        mlp->sur_bytes = 0;
+        if (hipMalloc(&mlp->sur, need) != hipSuccess) return HDX_E_NOMEM;
+        mlp->sur_bytes = need;
+    }
+    char *base = (char *)mlp->sur;
+    uint16_t *X = (uint16_t *)(base + st_bytes);
+    float *vals = (float *)(base + st_bytes + (size_t)pairs * kMlpIn * sizeof(uint16_t));
+    // expansion without rollouts, stepped states kept
+    std::vector<hdx_leaf> mod(leaves, leaves + n_leaves);
+    for (int32_t i = 0; i < n_leaves; ++i) {
+        const hdx_model_desc &d = *hdx_internal_desc(leaves[i].model);
+        const int64_t np = (int64_t)d.n_actions * (leaves[i].n > 0 ? leaves[i].n : 0);
+        hdx_leaf &L = mod[i];
+        L.rollout.max_steps = 0;
+        L.L = nullptr;
+        if (d.kind == HDX_ROCKSAMPLE ? L.sprime.w != nullptr : L.sprime.s != nullptr) continue;  // caller's
+        memset(&L.sprime, 0, sizeof(L.sprime));
+        char *p = base + st_off[i];
+        if (d.kind == HDX_ROCKSAMPLE) {
+            L.sprime.w = (int32_t *)p;
+        } else {
+            L.sprime.s = (float *)p;
+            L.sprime.car = (int32_t *)(p + 4 * np);
+            L.sprime.px = (float *)(p + 8 * np);
+            L.sprime.py = (float *)(p + (8 + 4 * (size_t)d.n_peds) * np);
+            L.sprime.goal = (uint8_t *)(p + (8 + 8 * (size_t)d.n_peds) * np);
+        }
+        L.sprime.stride = np;
+    }
+    hdx_status st = hdx_expand_leaf(ctx, mod.data(), n_leaves, stream);
+    if (st != HDX_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    for (int32_t i = 0; i < n_leaves; ++i) {
+        const int64_t np = (int64_t)hdx_model_actions(leaves[i].model) * (leaves[i].n > 0 ? leaves[i].n : 0);
+        if (np == 0) continue;
+        FeatArgs a;
+        a.model = hdx_internal_devmodel(leaves[i].model);
+        a.states = to_states(mod[i].sprime);
+        a.depths = nullptr;
+        a.depth_const = leaves[i].depth + 1;
+        a.n = np;
+        a.horizon = horizon;
+        a.X = X + pair_off[i] * kMlpIn;
+        if (launch_features(a, s) != hipSuccess) return HDX_E_DEVICE;
+    }
+    if (!grow_scratch(mlp->S, std::min<int64_t>(pairs, kMlpChunkRows))) return HDX_E_NOMEM;
+    if (pairs > 0 && mlp_forward(mlp->P, X, pairs, mlp->S.h1, mlp->S.h2, mlp->S.h3, vals, s) != hipSuccess)
+        return HDX_E_DEVICE;
+    for (int32_t i = 0; i < n_leaves; ++i) {
+        if (leaves[i].n <= 0) continue;
+        SurArgs a;
+        a.values = vals + pair_off[i];
+        a.perm = leaves[i].perm;
+        a.n_children = leaves[i].n_children;
+        a.child_n = leaves[i].child_n;
+        a.child_off = leaves[i].child_off;
+        a.child_l0 = leaves[i].child_l0;
+        a.L_out = leaves[i].L;
+        a.n = leaves[i].n;
+        a.cap = leaves[i].cap;
+        if (launch_surrogate_reduce(a, hdx_model_actions(leaves[i].model), s) != hipSuccess) return HDX_E_DEVICE;
+    }
+    return HDX_OK;
 }
 
 }  // extern "C"

@@ -322,7 +322,8 @@ bool Search::expand(int node_id, hipStream_t stream, char *head_host) {
         }
         st = q.status;
     } else {
-        st = hdx_expand_leaf(ctx, &L, 1, stream);
+        st = cfg.surrogate ? hdx_expand_leaf_surrogate(ctx, &L, 1, cfg.surrogate, cfg.surrogate_horizon, stream)
+                           : hdx_expand_leaf(ctx, &L, 1, stream);
         if (st != HDX_OK) {
             fail(st, "expand_leaf");
         } else {
@@ -366,7 +367,10 @@ void batcher_loop(Search *S, hipStream_t stream) {
         }
         leaves.clear();
         for (Request *q : batch) leaves.push_back(q->leaf);
-        hdx_status st = hdx_expand_leaf(S->ctx, leaves.data(), (int32_t)leaves.size(), stream);
+        const int32_t nl = (int32_t)leaves.size();
+        hdx_status st = S->cfg.surrogate ? hdx_expand_leaf_surrogate(S->ctx, leaves.data(), nl, S->cfg.surrogate,
+                                                                     S->cfg.surrogate_horizon, stream)
+                                         : hdx_expand_leaf(S->ctx, leaves.data(), nl, stream);
         if (st != HDX_OK) S->fail(st, "batched expand_leaf");
         for (Request *q : batch)
             if (st == HDX_OK &&

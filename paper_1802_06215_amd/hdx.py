@@ -66,7 +66,7 @@ class SearchCfg(C.Structure):
                 ("batch_leaves", C.c_int32), ("time_budget_s", C.c_double), ("max_trials", C.c_int64),
                 ("xi", C.c_double), ("c_a", C.c_double), ("c_o", C.c_double), ("gap_epsilon", C.c_double),
                 ("arena_bytes", C.c_int64), ("seed", C.c_uint32), ("step", C.c_uint32),
-                ("rollout", RolloutCfg)]
+                ("rollout", RolloutCfg), ("surrogate", C.c_void_p), ("surrogate_horizon", C.c_int32)]
 
 
 class SearchResult(C.Structure):
@@ -98,7 +98,7 @@ EXPORTS = ["hdx_version", "hdx_init", "hdx_fini", "hdx_last_error", "hdx_upload_
            "hdx_batch_set_schedule", "hdx_batch_get_schedule", "hdx_batch_use_graph",
            "hdx_batch_launch", "hdx_batch_autotune", "hdx_search", "hdx_mlp_create", "hdx_mlp_destroy",
            "hdx_mlp_get_params", "hdx_mlp_set_params", "hdx_mlp_forward", "hdx_mlp_gradients",
-           "hdx_mlp_train_step", "hdx_features",
+           "hdx_mlp_train_step", "hdx_features", "hdx_expand_leaf_surrogate",
            "hdx_tree_create", "hdx_tree_destroy", "hdx_tree_add_children", "hdx_backup",
            "hdx_tree_bounds", "hdx_tree_size"]
 
@@ -147,6 +147,7 @@ def load_library():
     L.hdx_mlp_gradients.argtypes = [P, P, P, P, I32, P, P, P]
     L.hdx_mlp_train_step.argtypes = [P, P, P, P, I32, C.c_float, P, P]
     L.hdx_features.argtypes = [P, P, States, P, I64, I32, P, P]
+    L.hdx_expand_leaf_surrogate.argtypes = [P, P, I32, P, I32, P]
     L.hdx_tree_create.argtypes = [I32, C.c_double, I32, C.c_double, C.c_double, C.POINTER(P)]
     L.hdx_tree_destroy.argtypes = [P]
     L.hdx_tree_add_children.argtypes = [P, I64, P, P, P, P, P, P, I32, C.POINTER(I64)]
@@ -389,6 +390,12 @@ class Context:
         self._check(self.lib.hdx_expand_leaf(self.handle, C.cast(arr, C.c_void_p), len(leaves),
                                              _stream(stream)))
 
+    def expand_leaf_surrogate(self, leaves, mlp: "Mlp", horizon: int, stream=None) -> None:
+        leaves = list(leaves)
+        arr = (Leaf * len(leaves))(*leaves)
+        self._check(self.lib.hdx_expand_leaf_surrogate(self.handle, C.cast(arr, C.c_void_p), len(leaves),
+                                                       mlp.handle, horizon, _stream(stream)))
+
     def rollout_bounds(self, model: Model, cfg: RolloutCfg, states: dict, ids, depths, seed: int,
                        step: int, stream=None):
         n = int(ids.numel())
@@ -403,11 +410,14 @@ class Context:
     def search(self, model: Model, belief: dict, K: int = 500, n_threads: int = 8, max_depth: int = 90,
                batch_leaves: int = 0, time_budget_s: float = 1.0, max_trials: int = 0, xi: float = 0.95,
                c_a: float = 0.1, c_o: float = 0.1, gap_epsilon: float = 0.0, arena_bytes: int = 8 << 30,
-               seed: int = 1, step: int = 0, rollout: RolloutCfg | None = None) -> dict:
-        """hdx_search: one planning step of parallel DESPOT over GPU leaf expansion."""
+               seed: int = 1, step: int = 0, rollout: RolloutCfg | None = None,
+               surrogate: "Mlp | None" = None, surrogate_horizon: int = 0) -> dict:
+        """hdx_search: one planning step of parallel DESPOT over GPU leaf expansion
+        (with `surrogate`, leaf lower bounds come from the MLP instead of rollouts)."""
         b, keep = self._belief(model, belief)
         cfg = SearchCfg(K, n_threads, max_depth, batch_leaves, time_budget_s, max_trials, xi, c_a, c_o,
-                        gap_epsilon, arena_bytes, seed, step, rollout or rollout_cfg())
+                        gap_epsilon, arena_bytes, seed, step, rollout or rollout_cfg(),
+                        surrogate.handle if surrogate is not None else None, surrogate_horizon)
         res = SearchResult()
         self._check(self.lib.hdx_search(self.handle, model.handle, C.byref(b), C.byref(cfg), C.byref(res)))
         out = {f: getattr(res, f) for f, _ in SearchResult._fields_ if not f.startswith("action_")}

@@ -1,0 +1,240 @@
+"""GPU tests of leaf expansion with the surrogate in place of the rollouts.
+
+Everything but the lower bounds must equal the plain expansion and the
+oracle bit for bit (states, groupings, rewards, observations, upper bounds);
+no rollout steps are taken; the per-scenario value is the MLP at the
+features of the stepped state (depth + 1), matched against the FP64
+reference of the network fed the same BF16 weights and features (2e-2 of
+the output scale); each child's l0 is the mean of its scenarios' values
+(1e-5 relative)."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from gpu_util import cfg_pair, collect, gpu_leaf_desc, ids_dev, to_dev, assert_states_equal, bits
+from oracle import mlp as ref
+
+pytestmark = pytest.mark.gpu
+
+HORIZON = 90
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1802_06215_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def net(ctx):
+    from paper_1802_06215_amd import Mlp
+    m = Mlp(ctx, seed=11)
+    yield m
+    m.close()
+
+
+def reference_values(desc, net, sprime, depth):
+    """MLP(features(s')) over every (action, scenario), FP64 with BF16 weights."""
+    A = desc["n_actions"]
+    if desc["kind"] == W.ROCKSAMPLE:
+        n = sprime["w"].shape[1]
+        f = ref.rocksample_features(desc, sprime["w"].reshape(-1), np.full(A * n, depth + 1), HORIZON)
+    else:
+        n = sprime["s"].shape[1]
+        st = dict(s=sprime["s"].reshape(-1), car=sprime["car"].reshape(-1),
+                  px=sprime["px"].reshape(-1, A * n), py=sprime["py"].reshape(-1, A * n),
+                  goal=sprime["goal"].reshape(-1, A * n))
+        f = ref.pednav_features(desc, st, np.full(A * n, depth + 1), HORIZON)
+    w = ref.unpack(net.params().astype(np.float64))
+    for k in ("W1", "W2", "W3", "w4"):
+        w[k] = ref.bf16_round(w[k].astype(np.float32)).astype(np.float64)
+    return ref.forward(ref.pack(w), ref.bf16_round(f), bf16=True).reshape(A, n)
+
+
+def run_surrogate(ctx, net, m, lf, seed, step, hcfg):
+    parent = to_dev(oracle.parent_states(m.desc, lf))
+    pids = ids_dev(lf["ids"])
+    leaf, out, keep = gpu_leaf_desc(m, parent, pids, lf["idx"], lf["depth"], lf["last_action"], seed, step, hcfg)
+    ctx.expand_leaf_surrogate([leaf], net, HORIZON)
+    torch.cuda.synchronize()
+    return collect(m, out)
+
+
+def check(ctx, net, desc, lf, seed, step, cfgs):
+    ocfg, hcfg = cfgs
+    m = ctx.upload_model(desc)
+    n = len(lf["idx"])
+    print("surrogate leaf: kind=%d n=%d depth=%d seed=%d" % (desc["kind"], n, lf["depth"], seed), flush=True)
+    gpu = run_surrogate(ctx, net, m, lf, seed, step, hcfg)
+    want = oracle.expand_leaf(desc, ocfg, oracle.parent_states(desc, lf), np.asarray(lf["ids"], np.uint32),
+                              lf["idx"], lf["depth"], lf["last_action"], seed, step, per_pair=True)
+    A = desc["n_actions"]
+    assert_states_equal(gpu["states"], want["states"])
+    assert_states_equal(gpu["sprime"], want["sprime"])
+    for f in ("n_children", "perm", "child_of"):
+        assert np.array_equal(gpu[f], want[f]), f
+    assert np.array_equal(bits(gpu["r"]), bits(want["r"]))
+    assert np.array_equal(gpu["z"], want["z"])
+    assert int(gpu["steps"][:, 0].sum()) == want["expand_steps"]
+    assert int(gpu["steps"][:, 1].sum()) == 0
+    vals = reference_values(desc, net, want["sprime"], lf["depth"])
+    scale = (np.abs(vals).mean() if n else 0.0) + 1e-3
+    err = np.max(np.abs(gpu["L"] - vals)) if n else 0.0
+    assert err <= 2e-2 * scale + 1e-3, (err, scale)
+    for a in range(A):
+        nc = int(want["n_children"][a])
+        for f in ("child_z", "child_n", "child_off"):
+            assert np.array_equal(gpu[f][a, :nc], want[f][a, :nc]), (f, a)
+        assert np.allclose(gpu["child_u0"][a, :nc], want["child_u0"][a, :nc], rtol=1e-5, atol=0)
+        for c in range(nc):
+            off, cnt = want["child_off"][a, c], want["child_n"][a, c]
+            seg = want["perm"][a, off:off + cnt]
+            mean = gpu["L"][a, seg].astype(np.float64).mean()
+            tol = 1e-5 * max(abs(mean), np.abs(gpu["L"][a, seg]).mean()) + 1e-30
+            assert abs(gpu["child_l0"][a, c] - mean) <= tol, (a, c, gpu["child_l0"][a, c], mean)
+    return gpu
+
+
+@pytest.mark.parametrize("n_leaf", [1, 63, 500, 777])
+def test_surrogate_expansion_rocksample(ctx, net, n_leaf):
+    desc = W.rocksample_model(15, 15, 2)
+    lf = W.rocksample_leaf(desc, max(n_leaf, 500), n_leaf, 4, p_term=0.05, depth=7)
+    check(ctx, net, desc, lf, 4, 1, cfg_pair(0, 1 << 30, HORIZON))
+
+
+@pytest.mark.parametrize("n_peds", [0, 6, 16, 32])
+def test_surrogate_expansion_pednav(ctx, net, n_peds):
+    desc = W.pednav_model(n_peds, 5, 3)
+    lf = W.pednav_leaf(desc, 500, 300, 6, p_term=0.05)
+    check(ctx, net, desc, lf, 6, 2, cfg_pair(0, 50))
+
+
+def test_surrogate_empty_leaf(ctx, net):
+    desc = W.rocksample_model(7, 8, 1)
+    lf = W.rocksample_leaf(desc, 100, 0, 1)
+    gpu = check(ctx, net, desc, lf, 1, 0, cfg_pair(0, 30))
+    assert np.all(gpu["n_children"] == 0)
+
+
+def test_surrogate_batch_matches_single_calls(ctx, net):
+    """Several leaves (both models, one empty) in one call give the same
+    bits as one call per leaf: a row's MLP value does not depend on its
+    neighbours."""
+    from paper_1802_06215_amd import hdx as H
+    specs = [(W.rocksample_model(15, 15, 2), 400), (W.pednav_model(16, 5, 3), 250),
+             (W.rocksample_model(7, 8, 1), 0), (W.rocksample_model(11, 11, 1), 130)]
+    leaves, outs, keep = [], [], []
+    singles = []
+    for i, (desc, n) in enumerate(specs):
+        m = ctx.upload_model(desc)
+        gen = W.rocksample_leaf if desc["kind"] == W.ROCKSAMPLE else W.pednav_leaf
+        lf = gen(desc, 500, n, 10 + i, p_term=0.05)
+        hcfg = H.rollout_cfg(0, 1 << 30, HORIZON)
+        singles.append(run_surrogate(ctx, net, m, lf, 10 + i, 3, hcfg))
+        parent = to_dev(oracle.parent_states(desc, lf))
+        pids = ids_dev(lf["ids"])
+        leaf, out, k = gpu_leaf_desc(m, parent, pids, lf["idx"], lf["depth"], lf["last_action"], 10 + i, 3, hcfg)
+        leaves.append(leaf)
+        outs.append((m, out))
+        keep += [parent, pids, k]
+    ctx.expand_leaf_surrogate(leaves, net, HORIZON)
+    torch.cuda.synchronize()
+    for (m, out), one in zip(outs, singles):
+        got = collect(m, out)
+        assert np.array_equal(got["n_children"], one["n_children"])
+        assert np.array_equal(got["perm"], one["perm"])
+        assert np.array_equal(bits(got["L"]), bits(one["L"]))
+        for a, nc in enumerate(one["n_children"]):
+            for f in ("child_n", "child_off", "child_z", "child_l0", "child_u0"):
+                assert np.array_equal(bits(got[f][a, :nc]), bits(one[f][a, :nc])), (f, a)
+
+
+def expand_with_rollouts(ctx, m, desc, leaves_spec, hcfg):
+    """Expand leaves with full rollouts and per-pair outputs (one call)."""
+    from paper_1802_06215_amd import hdx as H
+    descs, outs, keep = [], [], []
+    for seed, n, depth in leaves_spec:
+        lf = W.rocksample_leaf(desc, 500, n, seed, depth=depth)
+        par = H.rocksample_states(lf["x"], lf["y"], lf["rocks"], lf["term"])
+        pids = torch.from_numpy(lf["ids"].astype(np.int32)).cuda()
+        idx = torch.from_numpy(lf["idx"]).cuda()
+        out = H.LeafBuffers(m, n, per_pair=True)
+        descs.append(H.make_leaf(m, par, pids, idx, lf["depth"], lf["last_action"], out, seed, 0, hcfg))
+        outs.append((out, lf["depth"]))
+        keep += [par, pids, idx]
+    ctx.expand_leaf(descs)
+    torch.cuda.synchronize()
+    return descs, outs, keep
+
+
+def test_surrogate_training_beats_constant(ctx):
+    """Fit the surrogate to random-policy depth-90 RockSample 15x15 rollout
+    values and check it generalises to held-out leaves: pair-level error
+    below the targets' variance and child-level l0 closer to the rollout
+    l0 than the best constant."""
+    from paper_1802_06215_amd import Mlp, hdx as H
+    from paper_1802_06215_amd import surrogate as S
+    desc = W.rocksample_model(15, 15, 1)
+    m = ctx.upload_model(desc)
+    hcfg = H.rollout_cfg(H.POLICY_RANDOM, 1 << 30, HORIZON)
+    # many small leaves: the value depends on the robot's cell, the rocks
+    # and the remaining depth, so breadth over leaves is what generalises
+    spec = [(2000 + i, 100, 1 + (7 * i) % 60) for i in range(640)]
+    _, outs, keep = expand_with_rollouts(ctx, m, desc, spec, hcfg)
+    Xs, ts = zip(*(S.leaf_pairs(ctx, m, o, d, HORIZON) for o, d in outs))
+    X, t = torch.cat(Xs), torch.cat(ts)
+    print("training pairs %d, target mean %.4f var %.4f" % (len(t), float(t.mean()), float(t.var())), flush=True)
+    net = Mlp(ctx, seed=2)
+    t0 = time.perf_counter()
+    hist = S.fit(net, X, t, epochs=3, batch=4096, lr=1e-3)
+    torch.cuda.synchronize()
+    print("fit: %.2f s" % (time.perf_counter() - t0), flush=True)
+    print("epoch losses", ["%.4f" % h for h in hist], flush=True)
+    assert hist[-1] < hist[0]
+    # held-out leaves
+    spec = [(9000 + i, 500 >> (i % 3), 1 + (11 * i) % 60) for i in range(24)]
+    descs, outs, keep2 = expand_with_rollouts(ctx, m, desc, spec, hcfg)
+    Xh, th = zip(*(S.leaf_pairs(ctx, m, o, d, HORIZON) for o, d in outs))
+    Xh, th = torch.cat(Xh), torch.cat(th)
+    mse = float(((net.forward(Xh) - th) ** 2).mean())
+    var = float(th.var())
+    print("held-out pair mse %.4f vs target variance %.4f" % (mse, var), flush=True)
+    assert mse < var
+    full = [out.child_l0.cpu().numpy().copy() for out, _ in outs]
+    nch = [out.n_children.cpu().numpy().copy() for out, _ in outs]
+    ctx.expand_leaf_surrogate(descs, net, HORIZON)
+    torch.cuda.synchronize()
+    e_sur, e_const = [], []
+    vals = np.concatenate([f[a, :nc[a]] for f, nc in zip(full, nch) for a in range(len(nc))])
+    c = vals.mean()
+    for (out, _), f, nc in zip(outs, full, nch):
+        sur = out.child_l0.cpu().numpy()
+        for a in range(len(nc)):
+            e_sur.append(np.abs(sur[a, :nc[a]] - f[a, :nc[a]]))
+            e_const.append(np.abs(c - f[a, :nc[a]]))
+    e_sur, e_const = np.concatenate(e_sur).mean(), np.concatenate(e_const).mean()
+    print("child l0 mean abs error: surrogate %.4f, constant %.4f" % (e_sur, e_const), flush=True)
+    assert e_sur < e_const
+    net.close()
+
+
+@pytest.mark.parametrize("threads,batch", [(4, 0), (8, 8)])
+def test_search_with_surrogate(ctx, net, threads, batch):
+    from paper_1802_06215_amd import hdx as H
+    desc = W.rocksample_model(15, 15, 1)
+    m = ctx.upload_model(desc)
+    b = W.rocksample_belief(desc)
+    print("search: threads=%d batch=%d" % (threads, batch), flush=True)
+    r = ctx.search(m, b, K=500, n_threads=threads, batch_leaves=batch, time_budget_s=0.3, max_depth=HORIZON,
+                   rollout=H.rollout_cfg(H.POLICY_RANDOM, 1 << 30, HORIZON), surrogate=net,
+                   surrogate_horizon=HORIZON, seed=5, arena_bytes=2 << 30)
+    print(r["trials"], r["expansions"], r["l_root"], r["u_root"], flush=True)
+    assert r["expansions"] > 0 and r["trials"] >= r["expansions"]
+    assert 0 <= r["best_action"] < desc["n_actions"]
+    assert np.isfinite(r["l_root"]) and np.isfinite(r["u_root"])

@@ -67,3 +67,15 @@ def test_rocksample_features_definition():
     assert np.allclose(f[0, :10], [0.4, 0.2, 0, 0.8, 1, 0, -0.2, 0.4, 0.4, -0.2], atol=1e-7)
     assert np.allclose(f[1, :10], [0.8, 0.8, 1, 0, 0, 1, -0.6, 0.0, -0.2, -0.8], atol=1e-7)
     assert np.all(f[:, 10:] == 0)
+
+
+def test_pednav_features_definition():
+    desc = dict(path_len=40.0, n_levels=5, n_peds=2, n_goals=4)
+    st = dict(s=np.array([10.0, 20.0], np.float32), car=np.array([2, 4 | (1 << 8)], np.int32),
+              px=np.array([[15.0, 18.0], [5.0, 30.0]], np.float32),
+              py=np.array([[1.0, -2.0], [3.0, 0.5]], np.float32),
+              goal=np.array([[1, 3], [0, 2]], np.uint8))
+    f = mlp.pednav_features(desc, st, np.array([0, 100]), 90)
+    assert np.allclose(f[0, :10], [0.25, 0.5, 0, 0.9, 0.5, 0.1, 0.25, -0.5, 0.3, 0.0], atol=1e-7)
+    assert np.allclose(f[1, :10], [0.5, 1.0, 1, 0, -0.2, -0.2, 0.75, 1.0, 0.05, 0.5], atol=1e-7)
+    assert np.all(f[:, 10:] == 0)
