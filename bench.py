@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0  # dense BF16 MFMA
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: full-rate 32-bit VALU lane-ops/s
 PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 METRIC = "scenario-steps/s in leaf expand+rollout; search trials/s; surrogate vs rollout"
@@ -199,13 +200,16 @@ def surrogate_section(ctx, args):
         return descs, outs, keep
 
     def timed(fn, reps):
+        """Mean seconds per call: HIP events on the stream the calls are issued on."""
         fn()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(reps):
             fn()
+        e1.record()
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / reps
+        return e0.elapsed_time(e1) * 1e-3 / reps
 
     # training set: expansions with full rollouts, per-pair outputs kept
     specs = [(50000 + i, 100, 1 + (7 * i) % 89) for i in range(args.surrogate_leaves)]
@@ -248,11 +252,14 @@ def surrogate_section(ctx, args):
     for name, sur in (("rollouts", None), ("surrogate", net)):
         r = ctx.search(m, W.rocksample_belief(desc), K=500, n_threads=8, max_depth=90, batch_leaves=8,
                        time_budget_s=args.search_seconds, rollout=rcfg, surrogate=sur, surrogate_horizon=90,
-                       seed=3)
+                       surrogate_judge_every=16 if sur is not None else 0, seed=3)
         runs[name] = dict(trials_per_s=round(r["trials"] / r["elapsed_s"], 1),
                           expansions_per_s=round(r["expansions"] / r["elapsed_s"], 1),
                           l_root=round(r["l_root"], 5), u_root=round(r["u_root"], 5),
                           best_action=r["best_action"], nodes=r["nodes"])
+        if sur is not None:
+            runs[name].update(judged_leaves=r["judged_leaves"], judge_child_l0_mae=round(r["judge_mae"], 5),
+                              judge_rel_err=round(r["judge_rel_err"], 5), fell_back=bool(r["surrogate_off"]))
         log("search", name, runs[name])
     lf_, ls_ = runs["rollouts"]["l_root"], runs["surrogate"]["l_root"]
     net.close()
@@ -263,7 +270,11 @@ def surrogate_section(ctx, args):
                    fit_s=round(train_s, 3), samples_per_s=round(samples / train_s, 1),
                    tflops=round(S.FLOPS_TRAIN * samples / train_s / 1e12, 2), losses=[round(h, 4) for h in hist]),
         forward=dict(rows=n_pairs, ms=round(fwd_s * 1e3, 3),
-                     tflops=round(S.FLOPS_FWD * n_pairs / fwd_s / 1e12, 2)),
+                     roofline=dict(bound="mfma", kernel="mlp_fused_fwd",
+                                   achieved=round(S.FLOPS_FWD * n_pairs / fwd_s / 1e12, 2), peak=PEAK_BF16_TFLOPS,
+                                   unit="TFLOP/s",
+                                   frac=round(S.FLOPS_FWD * n_pairs / fwd_s / 1e12 / PEAK_BF16_TFLOPS, 4),
+                                   flops_per_row=S.FLOPS_FWD)),
         heldout=dict(leaves=len(specs), full_rollout_ms=round(full_s * 1e3, 3),
                      surrogate_ms=round(sur_s * 1e3, 3), speedup=round(full_s / sur_s, 2),
                      full_scenario_steps=steps_full,

@@ -375,6 +375,12 @@ typedef struct {
     hdx_mlp *surrogate;    /* non-NULL: leaves are expanded with hdx_expand_leaf_surrogate (the
                               root's initial bounds still come from rollouts) */
     int32_t surrogate_horizon; /* horizon of the surrogate's remaining-depth feature */
+    int32_t surrogate_judge_every; /* > 0: every j-th surrogate expansion is done with rollouts
+                                      (kept in the tree) and also with the surrogate, to
+                                      measure the surrogate's child-l0 error */
+    double surrogate_max_rel_err;  /* > 0: once 8 leaves are judged, fall back to rollouts for
+                                      the rest of the search if sum|l0_sur - l0| / sum|l0|
+                                      exceeds this */
 } hdx_search_cfg;
 
 typedef struct {
@@ -392,6 +398,10 @@ typedef struct {
     double elapsed_s;
     double action_l[HDX_MAX_ROCKS + 5]; /* per-action lower bounds at the root (first n_actions) */
     double action_u[HDX_MAX_ROCKS + 5];
+    int64_t judged_leaves, judged_children; /* surrogate judge: leaves and children compared */
+    double judge_mae;                       /* mean |l0_sur - l0_rollout| per judged child */
+    double judge_rel_err;                   /* sum |l0_sur - l0_rollout| / sum |l0_rollout| */
+    int32_t surrogate_off;                  /* 1 if the search fell back to rollouts */
 } hdx_search_result;
 
 hdx_status hdx_search(hdx_ctx *ctx, const hdx_model *model, const hdx_belief *belief,

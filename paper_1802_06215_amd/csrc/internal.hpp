@@ -159,6 +159,29 @@ int32_t variant_max_threads(const Variant &v);
 // count from d_queue->n_tiles; n_tiles here only sizes a non-persistent grid.
 hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queue, int32_t n_tiles,
                          const Variant &v, const Schedule &sch, int32_t n_cu, hipStream_t stream);
+
+// Tiles are launched by size class of their leaf (n <= 64, 128, 256, 512,
+// 1024, 2048): each class gets an LDS carve-up and a workgroup size for its
+// own largest leaf, so small leaves do not pay for the largest one's
+// footprint (LDS is what limits resident workgroups per CU).  The tile
+// array is ordered by class; class c owns tiles [begin[c], begin[c] +
+// count[c]) and the queue d_queues[c].
+constexpr int kSizeClasses = 6;
+__host__ __device__ inline int size_class(int32_t n) {
+    int c = 0;
+    while (c < kSizeClasses - 1 && n > (64 << c)) ++c;
+    return c;
+}
+struct ClassPlan {
+    int64_t begin[kSizeClasses], count[kSizeClasses];
+    int32_t n_max[kSizeClasses];
+};
+// Stable reorder of tiles[0, n_tiles) by class; fills plan.
+void plan_classes(const LeafTask *tasks, Tile *tiles, int64_t n_tiles, ClassPlan *plan);
+// One launch per non-empty class; lds_n[c] sizes class c's LDS (>= its n_max).
+hipError_t launch_classes(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queues, const ClassPlan &plan,
+                          const Variant &v, const int32_t *lds_n, const Schedule &sch, int32_t n_cu,
+                          hipStream_t stream);
 hipError_t configure_expand_kernels();
 
 // Up to kArgLeaves leaves passed by value in the kernel arguments.

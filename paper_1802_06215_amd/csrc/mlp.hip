@@ -28,6 +28,8 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 // C[M x N] = op(A)[M x K] * op(B)[K x N], BF16 inputs, FP32 accumulation.
 // A is [M][K] (lda) or, if a_t, [K][M]; B is [K][N] (ldb) or, if b_t, [N][K].
 // N must be a multiple of 64 and K of 32; rows m >= M are zero / not stored.
+// blockIdx.z selects the k range [z kslice, (z + 1) kslice) (split K); with
+// EPI_F32 slice z writes its partial product at out_f + z M ldo.
 enum { EPI_BIAS_RELU_BF16 = 0, EPI_MASK_BF16 = 1, EPI_F32 = 2 };
 
 constexpr int TM = 64, TN = 64, TK = 32, KP = TK + 8;  // LDS row pad against bank conflicts
@@ -36,7 +38,7 @@ __global__ __launch_bounds__(256) void gemm_bf16(int M, int N, int K, const uint
                                                  int a_t, const uint16_t *__restrict__ B, int ldb, int b_t,
                                                  int epi, const float *__restrict__ bias,
                                                  const uint16_t *__restrict__ mask, int ldm, uint16_t *out_bf,
-                                                 float *out_f, int ldo) {
+                                                 float *out_f, int ldo, int kslice) {
     __shared__ __align__(16) uint16_t As[TM][KP];
     __shared__ __align__(16) uint16_t Bs[TN][KP];  // n-major: Bs[n][k]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -45,7 +47,9 @@ __global__ __launch_bounds__(256) void gemm_bf16(int M, int N, int K, const uint
     f32x4 acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += TK) {
+    const int kbeg = blockIdx.z * kslice, kend = min(K, kbeg + kslice);
+    if (epi == EPI_F32) out_f += (size_t)blockIdx.z * M * ldo;
+    for (int k0 = kbeg; k0 < kend; k0 += TK) {
         // A tile: 64 x 32 -> As[m][k]; 256 threads x 8 elements
         if (!a_t) {
             const int r = tid >> 2, c = (tid & 3) * 8;
@@ -57,7 +61,13 @@ __global__ __launch_bounds__(256) void gemm_bf16(int M, int N, int K, const uint
             const int k = tid >> 3, c = (tid & 7) * 8;  // 32 k rows x 64 m
             const int m = m0 + c;
             const uint16_t *src = A + (size_t)(k0 + k) * lda + m;
-            for (int i = 0; i < 8; ++i) As[c + i][k] = (m + i < M) ? src[i] : (uint16_t)0;
+            if (m + 8 <= M) {
+                const uint4 v = *(const uint4 *)src;
+                const uint16_t *e = (const uint16_t *)&v;
+                for (int i = 0; i < 8; ++i) As[c + i][k] = e[i];
+            } else {
+                for (int i = 0; i < 8; ++i) As[c + i][k] = (m + i < M) ? src[i] : (uint16_t)0;
+            }
         }
         // B tile: 32 x 64 -> Bs[n][k]
         if (b_t) {
@@ -99,15 +109,142 @@ __global__ __launch_bounds__(256) void gemm_bf16(int M, int N, int K, const uint
             }
 }
 
-// y[b] = H3[b] . w4 + b4 (one wavefront per row)
-__global__ void out_layer(const uint16_t *H, const uint16_t *w4, const float *b4, int64_t M, float *y) {
-    const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (row >= M) return;
-    float s = 0.f;
-    for (int j = lane; j < kMlpHidden; j += 64) s += bf2f(H[row * kMlpHidden + j]) * bf2f(w4[j]);
-    for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, 64);
-    if (lane == 0) y[row] = s + b4[0];
+// ---- fused forward --------------------------------------------------------
+// One workgroup of four wavefronts takes kFR rows.  The layer input (X, then
+// H1, H2) sits in LDS; wavefront w computes output columns [64w, 64w + 64)
+// of every row, its B fragments read straight from the transposed BF16
+// weights (each wavefront reads a distinct quarter of a matrix, so a
+// workgroup reads every weight once per layer).  The output layer sums each
+// row's 256 products over lanes and then wavefronts in a fixed order, so a
+// row's value does not depend on the other rows.
+constexpr int kFR = 128, kHP = kMlpHidden + 8;
+
+template <int K>
+__device__ __forceinline__ void fused_layer(const uint16_t (*Hs)[kHP], const uint16_t *__restrict__ wt, int nb,
+                                            int lane, f32x4 (&acc)[8][4]) {
+    const int g = lane >> 4, q = lane & 15;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t *wrow = wt + (size_t)(nb + q) * K + g * 8;
+    bf16x8 b[4], bn[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = *(const bf16x8 *)(wrow + (size_t)j * 16 * K);
+#pragma unroll
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        if (k0 + 32 < K) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bn[j] = *(const bf16x8 *)(wrow + (size_t)j * 16 * K + k0 + 32);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const bf16x8 a = *(const bf16x8 *)&Hs[i * 16 + q][k0 + g * 8];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
+        }
+        if (k0 + 32 < K) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = bn[j];
+        }
+    }
+}
+
+// h = bf16(relu(acc + bias)) into LDS (and to Hout when given)
+__device__ __forceinline__ void fused_store(uint16_t (*Hs)[kHP], const f32x4 (&acc)[8][4], const float *bias, int nb,
+                                            int lane, uint16_t *Hout, int64_t r0, int64_t n) {
+    const int g = lane >> 4, q = lane & 15;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = nb + j * 16 + q;
+        const float bv = bias[col];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = i * 16 + g * 4 + r;
+                const float z = acc[i][j][r] + bv;
+                const uint16_t h = f2bf(z > 0.f ? z : 0.f);
+                Hs[row][col] = h;
+                if (Hout && r0 + row < n) Hout[(r0 + row) * kMlpHidden + col] = h;
+            }
+    }
+}
+
+__global__ __launch_bounds__(256) void mlp_fused_fwd(const uint16_t *__restrict__ X, int64_t n, const MlpDev P,
+                                                     float *__restrict__ y, uint16_t *H1, uint16_t *H2, uint16_t *H3) {
+    __shared__ __align__(16) uint16_t Hs[kFR][kHP];
+    __shared__ float yp[4][kFR];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, q = lane & 15;
+    const int64_t r0 = (int64_t)blockIdx.x * kFR;
+    const int nb = wave * 64;
+    constexpr int kV = kMlpIn / 8;  // uint4 per input row
+    for (int i = tid; i < kFR * kV; i += 256) {
+        const int r = i / kV, c = (i % kV) * 8;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (r0 + r < n) v = *(const uint4 *)(X + (r0 + r) * kMlpIn + c);
+        *(uint4 *)&Hs[r][c] = v;
+    }
+    __syncthreads();
+    f32x4 acc[8][4];
+    fused_layer<kMlpIn>(Hs, P.w1t, nb, lane, acc);
+    __syncthreads();
+    fused_store(Hs, acc, P.b1, nb, lane, H1, r0, n);
+    __syncthreads();
+    fused_layer<kMlpHidden>(Hs, P.w2t, nb, lane, acc);
+    __syncthreads();
+    fused_store(Hs, acc, P.b2, nb, lane, H2, r0, n);
+    __syncthreads();
+    fused_layer<kMlpHidden>(Hs, P.w3t, nb, lane, acc);
+    // output layer: y = bf16(h3) . bf16(w4) + b4
+    float w4v[4], b3v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        w4v[j] = bf2f(P.w4b[nb + j * 16 + q]);
+        b3v[j] = P.b3[nb + j * 16 + q];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = i * 16 + g * 4 + r;
+            float s = 0.f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float z = acc[i][j][r] + b3v[j];
+                const uint16_t h = f2bf(z > 0.f ? z : 0.f);
+                if (H3 && r0 + row < n) H3[(r0 + row) * kMlpHidden + nb + j * 16 + q] = h;
+                s += bf2f(h) * w4v[j];
+            }
+            s += __shfl_xor(s, 1, 64);
+            s += __shfl_xor(s, 2, 64);
+            s += __shfl_xor(s, 4, 64);
+            s += __shfl_xor(s, 8, 64);
+            if (q == 0) yp[wave][row] = s;
+        }
+    __syncthreads();
+    if (tid < kFR && r0 + tid < n) y[r0 + tid] = (((yp[0][tid] + yp[1][tid]) + yp[2][tid]) + yp[3][tid]) + P.b4[0];
+}
+
+// W1..W3 transposed to [out][in] (BF16), for the fused forward
+__global__ void transpose_weights(const uint16_t *__restrict__ pb, uint16_t *__restrict__ pt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kMlpWtElems) return;
+    constexpr int64_t n1 = (int64_t)kMlpHidden * kMlpIn, n2 = (int64_t)kMlpHidden * kMlpHidden;
+    int64_t o = i, base = kOffW1;
+    int K = kMlpIn;
+    if (o >= n1) {
+        o -= n1;
+        base = kOffW2;
+        K = kMlpHidden;
+        if (o >= n2) {
+            o -= n2;
+            base = kOffW3;
+        }
+    }
+    const int64_t col = o / K, k = o % K;  // pt[col][k] = W[k][col]
+    pt[i] = pb[base + k * kMlpHidden + col];
 }
 
 // dy = 2 (y - t) / B; per-block partial losses
@@ -137,27 +274,34 @@ __global__ void out_layer_back(const float *dy, const uint16_t *w4, const uint16
     G[i] = f2bf(on ? dy[b] * bf2f(w4[j]) : 0.f);
 }
 
-// column sums: out[j] = sum_b M[b][j] (bf16 or fp32 source), FP32, fixed order
-__global__ void col_sum_bf16(const uint16_t *Mx, int B, int N, float *out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
+// Partial weighted column sums over kMlpColRows-row slices:
+// part[slice][j] = sum_b v(b, j) w(b), v = bf16 M[b][j] (1 without M),
+// w = w[b] (1 without w); 64 columns x 4 row groups per block, fixed order.
+__global__ __launch_bounds__(256) void wcolsum_part(const uint16_t *__restrict__ Mx, const float *__restrict__ w,
+                                                    int B, int N, float *__restrict__ part) {
+    __shared__ float red[4][64];
+    const int tid = threadIdx.x, l = tid & 63, rg = tid >> 6;
+    const int c = blockIdx.x * 64 + l;
+    const int b0 = blockIdx.y * kMlpColRows, b1 = min(B, b0 + kMlpColRows);
     float s = 0.f;
-    for (int b = 0; b < B; ++b) s += bf2f(Mx[(size_t)b * N + j]);
-    out[j] = s;
+    if (c < N)
+        for (int b = b0 + rg; b < b1; b += 4) {
+            float v = Mx ? bf2f(Mx[(size_t)b * N + c]) : 1.f;
+            if (w) v *= w[b];
+            s += v;
+        }
+    red[rg][l] = s;
+    __syncthreads();
+    if (rg == 0 && c < N) part[(size_t)blockIdx.y * N + c] = ((red[0][l] + red[1][l]) + red[2][l]) + red[3][l];
 }
 
-// dW4[j] = sum_b H3[b][j] dy[b]; db4 = sum_b dy[b]
-__global__ void out_grad(const uint16_t *H, const float *dy, int B, float *dw4, float *db4) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < kMlpHidden) {
-        float s = 0.f;
-        for (int b = 0; b < B; ++b) s += bf2f(H[(size_t)b * kMlpHidden + j]) * dy[b];
-        dw4[j] = s;
-    } else if (j == kMlpHidden) {
-        float s = 0.f;
-        for (int b = 0; b < B; ++b) s += dy[b];
-        db4[0] = s;
-    }
+// out[i] = sum over slices z of part[z n + i], in slice order
+__global__ void sum_slices(const float *__restrict__ part, int S, int64_t n, float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int z = 0; z < S; ++z) s += part[(size_t)z * n + i];
+    out[i] = s;
 }
 
 // Adam on FP32 master weights; refresh the BF16 copy of weight matrices
@@ -181,45 +325,103 @@ __global__ void to_bf16(const float *src, int64_t n, uint16_t *dst) {
     if (i < n) dst[i] = f2bf(src[i]);
 }
 
-// State features for the surrogate (64 values, BF16).
-__global__ void features_kernel(const FeatArgs A) {
+// State features for the surrogate (64 values, BF16): RockSample x/n, y/n,
+// terminal, remaining depth/100, rock qualities, rock offsets dx/n, dy/n;
+// crowd driving s/path_len, speed level/(levels-1), terminal, remaining
+// depth/100, then per pedestrian (px - s)/10, py/10, goal/n_goals; zeros
+// to 64.  Feature j is a compile-time index, so nothing lives in private
+// memory; a row is written as eight 16-byte stores.
+template <int J>
+__device__ __forceinline__ float rs_feature(const HDX_CONST ModelHdr *M, int32_t w, int x, int y, float inv,
+                                            float remain) {
+    if (J == 0) return (float)x * inv;
+    if (J == 1) return (float)y * inv;
+    if (J == 2) return (float)((w >> 30) & 1);
+    if (J == 3) return remain;
+    const int m = M->n_rocks, i = J - 4;
+    if (i < m) return (float)((w >> (10 + i)) & 1);
+    if (i < 2 * m) return (float)(M->rock_x[i - m] - x) * inv;
+    if (i < 3 * m) return (float)(M->rock_y[i - 2 * m] - y) * inv;
+    return 0.f;
+}
+
+template <int J>
+__device__ __forceinline__ float ped_feature(const HDX_CONST ModelHdr *M, const StatesPtr &S, int64_t k, float s,
+                                             int32_t car, float remain) {
+    if (J == 0) return s / M->path_len;
+    if (J == 1) return (float)(car & 0xff) / (float)max(M->n_levels - 1, 1);
+    if (J == 2) return (float)((car >> 8) & 1);
+    if (J == 3) return remain;
+    constexpr int p = (J - 4) / 3, c = (J - 4) % 3;
+    if (p >= M->n_peds) return 0.f;
+    if (c == 0) return (S.px[p * S.stride + k] - s) * 0.1f;
+    if (c == 1) return S.py[p * S.stride + k] * 0.1f;
+    return (float)S.goal[p * S.stride + k] / (float)M->n_goals;
+}
+
+template <int J0>
+__device__ __forceinline__ uint4 feature_chunk(const HDX_CONST ModelHdr *M, const StatesPtr &S, int64_t k, bool rs,
+                                               int32_t w, int x, int y, float inv, float s, int32_t car, float remain) {
+    float f[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) f[e] = 0.f;
+    if (rs) {
+        f[0] = rs_feature<J0 + 0>(M, w, x, y, inv, remain);
+        f[1] = rs_feature<J0 + 1>(M, w, x, y, inv, remain);
+        f[2] = rs_feature<J0 + 2>(M, w, x, y, inv, remain);
+        f[3] = rs_feature<J0 + 3>(M, w, x, y, inv, remain);
+        f[4] = rs_feature<J0 + 4>(M, w, x, y, inv, remain);
+        f[5] = rs_feature<J0 + 5>(M, w, x, y, inv, remain);
+        f[6] = rs_feature<J0 + 6>(M, w, x, y, inv, remain);
+        f[7] = rs_feature<J0 + 7>(M, w, x, y, inv, remain);
+    } else {
+        f[0] = ped_feature<J0 + 0>(M, S, k, s, car, remain);
+        f[1] = ped_feature<J0 + 1>(M, S, k, s, car, remain);
+        f[2] = ped_feature<J0 + 2>(M, S, k, s, car, remain);
+        f[3] = ped_feature<J0 + 3>(M, S, k, s, car, remain);
+        f[4] = ped_feature<J0 + 4>(M, S, k, s, car, remain);
+        f[5] = ped_feature<J0 + 5>(M, S, k, s, car, remain);
+        f[6] = ped_feature<J0 + 6>(M, S, k, s, car, remain);
+        f[7] = ped_feature<J0 + 7>(M, S, k, s, car, remain);
+    }
+    uint4 v;
+    v.x = (uint32_t)f2bf(f[0]) | ((uint32_t)f2bf(f[1]) << 16);
+    v.y = (uint32_t)f2bf(f[2]) | ((uint32_t)f2bf(f[3]) << 16);
+    v.z = (uint32_t)f2bf(f[4]) | ((uint32_t)f2bf(f[5]) << 16);
+    v.w = (uint32_t)f2bf(f[6]) | ((uint32_t)f2bf(f[7]) << 16);
+    return v;
+}
+
+// blockIdx.y selects the pack entry; rows of that entry by blockIdx.x.
+__global__ __launch_bounds__(128) void features_kernel(const FeatPack P) {
+    const FeatArgs &A = P.a[blockIdx.y];
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= A.n) return;
     const HDX_CONST ModelHdr *M = (const HDX_CONST ModelHdr *)&A.model->h;
-    float f[kMlpIn];
-    for (int i = 0; i < kMlpIn; ++i) f[i] = 0.f;
     const int depth = A.depths ? A.depths[k] : A.depth_const;
     const float remain = (float)max(A.horizon - depth, 0) * 0.01f;
-    if (M->kind == HDX_ROCKSAMPLE) {
-        const int32_t w = A.states.w[k];
-        const int x = w & 31, y = (w >> 5) & 31;
-        const float inv = 1.0f / (float)M->grid;
-        f[0] = (float)x * inv;
-        f[1] = (float)y * inv;
-        f[2] = (float)((w >> 30) & 1);
-        f[3] = remain;
-        const int m = M->n_rocks;
-        for (int i = 0; i < m && 4 + 3 * i + 2 < kMlpIn; ++i) {
-            f[4 + i] = (float)((w >> (10 + i)) & 1);
-            f[4 + m + i] = (float)(M->rock_x[i] - x) * inv;
-            f[4 + 2 * m + i] = (float)(M->rock_y[i] - y) * inv;
-        }
+    const bool rs = M->kind == HDX_ROCKSAMPLE;
+    int32_t w = 0, car = 0;
+    int x = 0, y = 0;
+    float inv = 0.f, s = 0.f;
+    if (rs) {
+        w = A.states.w[k];
+        x = w & 31;
+        y = (w >> 5) & 31;
+        inv = 1.0f / (float)M->grid;
     } else {
-        const float s = A.states.s[k];
-        const int32_t car = A.states.car[k];
-        f[0] = s / M->path_len;
-        f[1] = (float)(car & 0xff) / (float)max(M->n_levels - 1, 1);
-        f[2] = (float)((car >> 8) & 1);
-        f[3] = remain;
-        const int P = min(M->n_peds, (kMlpIn - 4) / 3);
-        for (int j = 0; j < P; ++j) {
-            f[4 + 3 * j] = (A.states.px[j * A.states.stride + k] - s) * 0.1f;
-            f[5 + 3 * j] = A.states.py[j * A.states.stride + k] * 0.1f;
-            f[6 + 3 * j] = (float)A.states.goal[j * A.states.stride + k] / (float)M->n_goals;
-        }
+        s = A.states.s[k];
+        car = A.states.car[k];
     }
-    uint16_t *dst = A.X + k * kMlpIn;
-    for (int i = 0; i < kMlpIn; ++i) dst[i] = f2bf(f[i]);
+    uint4 *dst = (uint4 *)(A.X + k * kMlpIn);
+    dst[0] = feature_chunk<0>(M, A.states, k, rs, w, x, y, inv, s, car, remain);
+    dst[1] = feature_chunk<8>(M, A.states, k, rs, w, x, y, inv, s, car, remain);
+    dst[2] = feature_chunk<16>(M, A.states, k, rs, w, x, y, inv, s, car, remain);
+    dst[3] = feature_chunk<24>(M, A.states, k, rs, w, x, y, inv, s, car, remain);
+    dst[4] = feature_chunk<32>(M, A.states, k, rs, w, x, y, inv, s, car, remain);
+    dst[5] = feature_chunk<40>(M, A.states, k, rs, w, x, y, inv, s, car, remain);
+    dst[6] = feature_chunk<48>(M, A.states, k, rs, w, x, y, inv, s, car, remain);
+    dst[7] = feature_chunk<56>(M, A.states, k, rs, w, x, y, inv, s, car, remain);
 }
 
 inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
@@ -228,35 +430,54 @@ inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 hipError_t mlp_gemm(int M, int N, int K, const uint16_t *A, int lda, int a_t, const uint16_t *B, int ldb, int b_t,
                     int epi, const float *bias, const uint16_t *mask, int ldm, uint16_t *out_bf, float *out_f, int ldo,
-                    hipStream_t s) {
+                    hipStream_t s, int slices) {
     if (M <= 0) return hipSuccess;
-    dim3 grid(N / TN, (M + TM - 1) / TM);
+    if (slices < 1 || epi != EPI_F32) slices = 1;
+    const int kslice = ((K + slices - 1) / slices + TK - 1) / TK * TK;
+    slices = (K + kslice - 1) / kslice;
+    dim3 grid(N / TN, (M + TM - 1) / TM, slices);
     hipLaunchKernelGGL(gemm_bf16, grid, dim3(256), 0, s, M, N, K, A, lda, a_t, B, ldb, b_t, epi, bias, mask, ldm,
-                       out_bf, out_f, ldo);
+                       out_bf, out_f, ldo, kslice);
     return hipGetLastError();
 }
 
-// Forward pass of n rows in chunks of kMlpChunkRows; H1..H3 are scratch of
-// min(n, kMlpChunkRows) rows x 256 bf16 (they hold the last chunk).
+namespace {
+
+// dW[M x 256] = A^T G over B rows (A [B][M], G [B][256]), split over K
+// into slices summed in a fixed order.
+hipError_t weight_grad(int M, int B, const uint16_t *A, const uint16_t *G, float *out, float *part, hipStream_t s) {
+    const int slices = std::max(1, std::min(kMlpMaxSlices, B / 512));
+    if (slices == 1)
+        return mlp_gemm(M, kMlpHidden, B, A, M, 1, G, kMlpHidden, 0, EPI_F32, nullptr, nullptr, 0, nullptr, out,
+                        kMlpHidden, s, 1);
+    hipError_t e = mlp_gemm(M, kMlpHidden, B, A, M, 1, G, kMlpHidden, 0, EPI_F32, nullptr, nullptr, 0, nullptr, part,
+                            kMlpHidden, s, slices);
+    if (e != hipSuccess) return e;
+    const int kslice = ((B + slices - 1) / slices + TK - 1) / TK * TK;
+    const int used = (B + kslice - 1) / kslice;
+    const int64_t n = (int64_t)M * kMlpHidden;
+    hipLaunchKernelGGL(sum_slices, dim3(blocks_for(n, 256)), dim3(256), 0, s, part, used, n, out);
+    return hipGetLastError();
+}
+
+// out[j] = sum_b v(b, j) w(b) (see wcolsum_part), two passes, fixed order
+hipError_t col_sum(const uint16_t *Mx, const float *w, int B, int N, float *out, float *part, hipStream_t s) {
+    const int S = (B + kMlpColRows - 1) / kMlpColRows;
+    hipLaunchKernelGGL(wcolsum_part, dim3((N + 63) / 64, S), dim3(256), 0, s, Mx, w, B, N, part);
+    hipLaunchKernelGGL(sum_slices, dim3(blocks_for(N, 256)), dim3(256), 0, s, part, S, (int64_t)N, out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Forward pass of n rows: the fused kernel, 128 rows per workgroup.
 hipError_t mlp_forward(const MlpDev &P, const uint16_t *X, int64_t n, uint16_t *H1, uint16_t *H2, uint16_t *H3,
                        float *y, hipStream_t s) {
-    const int H = kMlpHidden;
-    for (int64_t r0 = 0; r0 < n; r0 += kMlpChunkRows) {
-        const int rows = (int)std::min<int64_t>(kMlpChunkRows, n - r0);
-        const uint16_t *x = X + r0 * kMlpIn;
-        hipError_t e = mlp_gemm(rows, H, kMlpIn, x, kMlpIn, 0, P.w1b, H, 0, EPI_BIAS_RELU_BF16, P.b1, nullptr, 0,
-                                H1, nullptr, H, s);
-        if (e == hipSuccess)
-            e = mlp_gemm(rows, H, H, H1, H, 0, P.w2b, H, 0, EPI_BIAS_RELU_BF16, P.b2, nullptr, 0, H2, nullptr, H, s);
-        if (e == hipSuccess)
-            e = mlp_gemm(rows, H, H, H2, H, 0, P.w3b, H, 0, EPI_BIAS_RELU_BF16, P.b3, nullptr, 0, H3, nullptr, H, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(out_layer, dim3(blocks_for(rows, 4)), dim3(256), 0, s, H3, P.w4b, P.b4, (int64_t)rows,
-                           y + r0);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + kFR - 1) / kFR;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(mlp_fused_fwd, dim3((unsigned)blocks), dim3(256), 0, s, X, n, P, y, H1, H2, H3);
+    return hipGetLastError();
 }
 
 // Gradients of the mean squared error for one batch (B a multiple of 64).
@@ -268,26 +489,25 @@ hipError_t mlp_backward(const MlpDev &P, const uint16_t *X, const float *t, int 
     hipLaunchKernelGGL(loss_grad, dim3(blocks_for(B, 256)), dim3(256), 0, s, S.y, t, B, S.dy, S.loss_part);
     float *gw1 = grads + kOffW1, *gb1 = grads + kOffB1, *gw2 = grads + kOffW2, *gb2 = grads + kOffB2;
     float *gw3 = grads + kOffW3, *gb3 = grads + kOffB3, *gw4 = grads + kOffW4, *gb4 = grads + kOffB4;
+    float *part = S.part, *cpart = S.part + (int64_t)kMlpMaxSlices * H * H;
     hipLaunchKernelGGL(out_layer_back, dim3(blocks_for((int64_t)B * H, 256)), dim3(256), 0, s, S.dy, P.w4b, S.h3, B,
                        S.g3);
-    hipLaunchKernelGGL(out_grad, dim3(blocks_for(H + 1, 256)), dim3(256), 0, s, S.h3, S.dy, B, gw4, gb4);
+    // output layer: dw4 = H3^T dy, db4 = sum dy
+    if ((e = col_sum(S.h3, S.dy, B, H, gw4, cpart, s)) != hipSuccess) return e;
+    if ((e = col_sum(nullptr, S.dy, B, 1, gb4, cpart, s)) != hipSuccess) return e;
     // layer 3: dW3 = H2^T G3, db3 = colsum G3, G2 = (G3 W3^T) [H2 > 0]
-    e = mlp_gemm(H, H, B, S.h2, H, 1, S.g3, H, 0, EPI_F32, nullptr, nullptr, 0, nullptr, gw3, H, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(col_sum_bf16, dim3(1), dim3(256), 0, s, S.g3, B, H, gb3);
-    e = mlp_gemm(B, H, H, S.g3, H, 0, P.w3b, H, 1, EPI_MASK_BF16, nullptr, S.h2, H, S.g2, nullptr, H, s);
+    if ((e = weight_grad(H, B, S.h2, S.g3, gw3, part, s)) != hipSuccess) return e;
+    if ((e = col_sum(S.g3, nullptr, B, H, gb3, cpart, s)) != hipSuccess) return e;
+    e = mlp_gemm(B, H, H, S.g3, H, 0, P.w3b, H, 1, EPI_MASK_BF16, nullptr, S.h2, H, S.g2, nullptr, H, s, 1);
     if (e != hipSuccess) return e;
     // layer 2
-    e = mlp_gemm(H, H, B, S.h1, H, 1, S.g2, H, 0, EPI_F32, nullptr, nullptr, 0, nullptr, gw2, H, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(col_sum_bf16, dim3(1), dim3(256), 0, s, S.g2, B, H, gb2);
-    e = mlp_gemm(B, H, H, S.g2, H, 0, P.w2b, H, 1, EPI_MASK_BF16, nullptr, S.h1, H, S.g1, nullptr, H, s);
+    if ((e = weight_grad(H, B, S.h1, S.g2, gw2, part, s)) != hipSuccess) return e;
+    if ((e = col_sum(S.g2, nullptr, B, H, gb2, cpart, s)) != hipSuccess) return e;
+    e = mlp_gemm(B, H, H, S.g2, H, 0, P.w2b, H, 1, EPI_MASK_BF16, nullptr, S.h1, H, S.g1, nullptr, H, s, 1);
     if (e != hipSuccess) return e;
     // layer 1
-    e = mlp_gemm(kMlpIn, H, B, X, kMlpIn, 1, S.g1, H, 0, EPI_F32, nullptr, nullptr, 0, nullptr, gw1, H, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(col_sum_bf16, dim3(1), dim3(256), 0, s, S.g1, B, H, gb1);
-    return hipGetLastError();
+    if ((e = weight_grad(kMlpIn, B, X, S.g1, gw1, part, s)) != hipSuccess) return e;
+    return col_sum(S.g1, nullptr, B, H, gb1, cpart, s);
 }
 
 hipError_t mlp_adam(MlpDev &P, const float *grads, float lr, int step, hipStream_t s) {
@@ -295,18 +515,34 @@ hipError_t mlp_adam(MlpDev &P, const float *grads, float lr, int step, hipStream
     const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
     hipLaunchKernelGGL(adam_step, dim3(blocks_for(kMlpParams, 256)), dim3(256), 0, s, P.p, grads, P.m, P.v,
                        (int64_t)kMlpParams, lr, b1, b2, eps, c1, c2, nullptr, P.pb);
+    hipLaunchKernelGGL(transpose_weights, dim3(blocks_for(kMlpWtElems, 256)), dim3(256), 0, s, P.pb, P.pt);
     return hipGetLastError();
 }
 
 hipError_t mlp_refresh_bf16(MlpDev &P, hipStream_t s) {
     hipLaunchKernelGGL(to_bf16, dim3(blocks_for(kMlpParams, 256)), dim3(256), 0, s, P.p, (int64_t)kMlpParams, P.pb);
+    hipLaunchKernelGGL(transpose_weights, dim3(blocks_for(kMlpWtElems, 256)), dim3(256), 0, s, P.pb, P.pt);
     return hipGetLastError();
 }
 
-hipError_t launch_features(const FeatArgs &a, hipStream_t s) {
-    if (a.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(features_kernel, dim3(blocks_for(a.n, 128)), dim3(128), 0, s, a);
-    return hipGetLastError();
+hipError_t launch_features(const FeatArgs *a, int count, hipStream_t s) {
+    for (int i0 = 0; i0 < count; i0 += kFeatPack) {
+        FeatPack P;
+        memset(&P, 0, sizeof(P));
+        int64_t n_max = 0;
+        const int c = std::min(kFeatPack, count - i0);
+        for (int i = 0; i < c; ++i) {
+            P.a[i] = a[i0 + i];
+            n_max = std::max<int64_t>(n_max, a[i0 + i].n);
+        }
+        if (n_max <= 0) continue;
+        const int64_t bx = (n_max + 127) / 128;
+        if (bx > 0x7fffffff) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(features_kernel, dim3((unsigned)bx, c), dim3(128), 0, s, P);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace hdx
@@ -323,31 +559,45 @@ __global__ void sum_parts(const float *part, int n, float *out) {
 }  // namespace
 
 namespace {
-// Surrogate lower bounds of one leaf's children: for action a (blockIdx.y)
-// and child c, l0 = mean of the surrogate values of the child's scenarios,
-// summed in grouped order; per-scenario values copied out on request.
-__global__ void surrogate_reduce(const SurArgs A) {
+// Surrogate lower bounds of the children of pack entry blockIdx.z: for
+// action a (blockIdx.y) and child c, l0 = mean of the surrogate values of
+// the child's scenarios, summed in grouped order; per-scenario values
+// copied out on request.
+__global__ void surrogate_reduce(const SurPack P) {
+    const SurArgs &A = P.a[blockIdx.z];
     const int a = blockIdx.y;
+    if (a >= A.n_actions) return;
     const int n = A.n;
     const float *v = A.values + (int64_t)a * n;
     const int nch = A.n_children[a];
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nch && c < A.cap; c += gridDim.x * blockDim.x) {
+    const int32_t *perm = A.perm + (int64_t)a * n;
+    for (int c = threadIdx.x; c < nch && c < A.cap; c += blockDim.x) {
         const int off = A.child_off[a * A.cap + c], cnt = A.child_n[a * A.cap + c];
-        const int32_t *perm = A.perm + (int64_t)a * n;
-        float s = 0.f;
-        for (int i = 0; i < cnt; ++i) s = s + v[perm[off + i]];
-        A.child_l0[a * A.cap + c] = s / (float)cnt;
+        float sum = 0.f;
+        for (int i = 0; i < cnt; ++i) sum = sum + v[perm[off + i]];
+        A.child_l0[a * A.cap + c] = sum / (float)cnt;
     }
     if (A.L_out)
-        for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
-            A.L_out[(int64_t)a * n + k] = v[k];
+        for (int k = threadIdx.x; k < n; k += blockDim.x) A.L_out[(int64_t)a * n + k] = v[k];
 }
 }  // namespace
 
-hipError_t launch_surrogate_reduce(const SurArgs &a, int n_actions, hipStream_t s) {
-    if (a.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(surrogate_reduce, dim3(1, n_actions), dim3(64), 0, s, a);
-    return hipGetLastError();
+hipError_t launch_surrogate_reduce(const SurArgs *a, int count, hipStream_t s) {
+    for (int i0 = 0; i0 < count; i0 += kSurPack) {
+        SurPack P;
+        memset(&P, 0, sizeof(P));
+        int A = 0;
+        const int c = std::min(kSurPack, count - i0);
+        for (int i = 0; i < c; ++i) {
+            P.a[i] = a[i0 + i];
+            A = std::max(A, a[i0 + i].n_actions);
+        }
+        if (A <= 0) continue;
+        hipLaunchKernelGGL(surrogate_reduce, dim3(1, A, c), dim3(64), 0, s, P);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t mlp_sum_loss(const float *part, int n, float *out, hipStream_t s) {

@@ -7,7 +7,7 @@ namespace hdx {
 
 constexpr int kMlpIn = HDX_MLP_IN;          // 64 features
 constexpr int kMlpHidden = HDX_MLP_HIDDEN;  // 256
-constexpr int64_t kMlpChunkRows = 1 << 16;  // rows per forward chunk
+constexpr int64_t kMlpChunkRows = 1 << 16;  // largest training batch
 // packed parameter vector: W1 [64][256], b1, W2 [256][256], b2, W3, b3, w4 [256], b4
 constexpr int64_t kOffW1 = 0;
 constexpr int64_t kOffB1 = kOffW1 + (int64_t)kMlpIn * kMlpHidden;
@@ -20,12 +20,21 @@ constexpr int64_t kOffB4 = kOffW4 + kMlpHidden;
 constexpr int64_t kMlpParams = kOffB4 + 1;
 static_assert(kMlpParams == HDX_MLP_PARAMS, "parameter count");
 
+constexpr int64_t kMlpWtElems = (int64_t)kMlpHidden * kMlpIn + 2 * (int64_t)kMlpHidden * kMlpHidden;
+// split-K partial sums of the weight gradients: at most kMlpMaxSlices slices
+constexpr int kMlpMaxSlices = 32;
+constexpr int kMlpColRows = 256;  // rows per partial of a column sum
+constexpr int64_t kMlpPartFloats =
+    (int64_t)kMlpMaxSlices * kMlpHidden * kMlpHidden + (kMlpChunkRows / kMlpColRows) * (int64_t)(kMlpHidden + 1);
+
 struct MlpDev {
     float *p;      // FP32 master parameters
     uint16_t *pb;  // BF16 copy
+    uint16_t *pt;  // BF16 W1..W3 transposed ([out][in]) for the fused forward
     float *m, *v;  // Adam moments
     float *g;      // gradients
     const uint16_t *w1b, *w2b, *w3b, *w4b;
+    const uint16_t *w1t, *w2t, *w3t;
     const float *b1, *b2, *b3, *b4;
 };
 
@@ -33,6 +42,7 @@ struct MlpScratch {
     int64_t rows = 0;
     uint16_t *h1 = nullptr, *h2 = nullptr, *h3 = nullptr, *g1 = nullptr, *g2 = nullptr, *g3 = nullptr;
     float *y = nullptr, *dy = nullptr, *loss_part = nullptr;
+    float *part = nullptr;  // kMlpPartFloats
 };
 
 struct FeatArgs {
@@ -46,14 +56,22 @@ struct FeatArgs {
 
 hipError_t mlp_gemm(int M, int N, int K, const uint16_t *A, int lda, int a_t, const uint16_t *B, int ldb, int b_t,
                     int epi, const float *bias, const uint16_t *mask, int ldm, uint16_t *out_bf, float *out_f, int ldo,
-                    hipStream_t s);
+                    hipStream_t s, int slices);
+// y = MLP(X) for n rows; H1..H3 (row stride 256) receive the activations
+// when non-NULL (then they hold n rows).
 hipError_t mlp_forward(const MlpDev &P, const uint16_t *X, int64_t n, uint16_t *H1, uint16_t *H2, uint16_t *H3,
                        float *y, hipStream_t s);
 hipError_t mlp_backward(const MlpDev &P, const uint16_t *X, const float *t, int B, MlpScratch &S, float *grads,
                         hipStream_t s);
 hipError_t mlp_adam(MlpDev &P, const float *grads, float lr, int step, hipStream_t s);
 hipError_t mlp_refresh_bf16(MlpDev &P, hipStream_t s);
-hipError_t launch_features(const FeatArgs &a, hipStream_t s);
+// Features of several state arrays, kFeatPack per launch (kernel arguments).
+constexpr int kFeatPack = 36;
+struct FeatPack {
+    FeatArgs a[kFeatPack];
+};
+static_assert(sizeof(FeatPack) <= 4096, "kernel argument pack too large");
+hipError_t launch_features(const FeatArgs *a, int count, hipStream_t s);
 hipError_t mlp_sum_loss(const float *part, int n, float *out, hipStream_t s);
 
 struct SurArgs {
@@ -61,8 +79,13 @@ struct SurArgs {
     const int32_t *perm, *n_children, *child_n, *child_off;
     float *child_l0;
     float *L_out;  // optional [A][n]
-    int32_t n, cap;
+    int32_t n, cap, n_actions, pad;
 };
-hipError_t launch_surrogate_reduce(const SurArgs &a, int n_actions, hipStream_t s);
+constexpr int kSurPack = 56;
+struct SurPack {
+    SurArgs a[kSurPack];
+};
+static_assert(sizeof(SurPack) <= 4096, "kernel argument pack too large");
+hipError_t launch_surrogate_reduce(const SurArgs *a, int count, hipStream_t s);
 
 }  // namespace hdx

@@ -47,14 +47,15 @@ void init_params(uint32_t seed, std::vector<float> &p) {
 bool grow_scratch(MlpScratch &S, int64_t rows) {
     if (S.rows >= rows) return true;
     for (void *ptr : {(void *)S.h1, (void *)S.h2, (void *)S.h3, (void *)S.g1, (void *)S.g2, (void *)S.g3,
-                      (void *)S.y, (void *)S.dy, (void *)S.loss_part})
+                      (void *)S.y, (void *)S.dy, (void *)S.loss_part, (void *)S.part})
         if (ptr) hipFree(ptr);
     S = MlpScratch();
     const size_t hb = (size_t)rows * kMlpHidden * sizeof(uint16_t);
     if (hipMalloc(&S.h1, hb) != hipSuccess || hipMalloc(&S.h2, hb) != hipSuccess || hipMalloc(&S.h3, hb) != hipSuccess ||
         hipMalloc(&S.g1, hb) != hipSuccess || hipMalloc(&S.g2, hb) != hipSuccess || hipMalloc(&S.g3, hb) != hipSuccess ||
         hipMalloc(&S.y, rows * sizeof(float)) != hipSuccess || hipMalloc(&S.dy, rows * sizeof(float)) != hipSuccess ||
-        hipMalloc(&S.loss_part, ((rows + 255) / 256) * sizeof(float)) != hipSuccess)
+        hipMalloc(&S.loss_part, ((rows + 255) / 256) * sizeof(float)) != hipSuccess ||
+        hipMalloc(&S.part, kMlpPartFloats * sizeof(float)) != hipSuccess)
         return false;
     S.rows = rows;
     return true;
@@ -65,6 +66,9 @@ void bind(MlpDev &P) {
     P.w2b = P.pb + kOffW2;
     P.w3b = P.pb + kOffW3;
     P.w4b = P.pb + kOffW4;
+    P.w1t = P.pt;
+    P.w2t = P.pt + (int64_t)kMlpHidden * kMlpIn;
+    P.w3t = P.w2t + (int64_t)kMlpHidden * kMlpHidden;
     P.b1 = P.p + kOffB1;
     P.b2 = P.p + kOffB2;
     P.b3 = P.p + kOffB3;
@@ -111,6 +115,7 @@ hdx_status hdx_mlp_create(hdx_ctx *ctx, uint32_t seed, hdx_mlp **out) {
     hdx_mlp *m = new hdx_mlp();
     const size_t pbytes = kMlpParams * sizeof(float);
     if (hipMalloc(&m->P.p, pbytes) != hipSuccess || hipMalloc(&m->P.pb, kMlpParams * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&m->P.pt, kMlpWtElems * sizeof(uint16_t)) != hipSuccess ||
         hipMalloc(&m->P.m, pbytes) != hipSuccess || hipMalloc(&m->P.v, pbytes) != hipSuccess ||
         hipMalloc(&m->grads, pbytes) != hipSuccess || hipMalloc(&m->loss, sizeof(float)) != hipSuccess ||
         hipEventCreateWithFlags(&m->last, hipEventDisableTiming) != hipSuccess) {
@@ -132,12 +137,12 @@ hdx_status hdx_mlp_create(hdx_ctx *ctx, uint32_t seed, hdx_mlp **out) {
 hdx_status hdx_mlp_destroy(hdx_ctx *ctx, hdx_mlp *m) {
     if (!ctx || !m) return HDX_E_INVALID;
     hipDeviceSynchronize();
-    for (void *ptr : {(void *)m->P.p, (void *)m->P.pb, (void *)m->P.m, (void *)m->P.v, (void *)m->grads,
+    for (void *ptr : {(void *)m->P.p, (void *)m->P.pb, (void *)m->P.pt, (void *)m->P.m, (void *)m->P.v, (void *)m->grads,
                       (void *)m->loss, m->sur})
         if (ptr) hipFree(ptr);
     if (m->last) hipEventDestroy(m->last);
     for (void *ptr : {(void *)m->S.h1, (void *)m->S.h2, (void *)m->S.h3, (void *)m->S.g1, (void *)m->S.g2,
-                      (void *)m->S.g3, (void *)m->S.y, (void *)m->S.dy, (void *)m->S.loss_part})
+                      (void *)m->S.g3, (void *)m->S.y, (void *)m->S.dy, (void *)m->S.loss_part, (void *)m->S.part})
         if (ptr) hipFree(ptr);
     delete m;
     return HDX_OK;
@@ -164,9 +169,8 @@ hdx_status hdx_mlp_forward(hdx_ctx *ctx, hdx_mlp *m, const uint16_t *X, int64_t 
     if (!ctx || !m || (n > 0 && (!X || !y)) || n < 0) return HDX_E_INVALID;
     if (n == 0) return HDX_OK;
     std::lock_guard<std::mutex> g(m->mu);
-    if (!grow_scratch(m->S, std::min<int64_t>(n, kMlpChunkRows))) return HDX_E_NOMEM;
     Ordered o(m, (hipStream_t)stream);
-    return mlp_forward(m->P, X, n, m->S.h1, m->S.h2, m->S.h3, y, (hipStream_t)stream) == hipSuccess ? HDX_OK
+    return mlp_forward(m->P, X, n, nullptr, nullptr, nullptr, y, (hipStream_t)stream) == hipSuccess ? HDX_OK
                                                                                                    : HDX_E_DEVICE;
 }
 
@@ -209,7 +213,7 @@ hdx_status hdx_features(hdx_ctx *ctx, const hdx_model *model, hdx_states states,
     a.horizon = horizon;
     a.depth_const = 0;
     a.X = X;
-    return launch_features(a, (hipStream_t)stream) == hipSuccess ? HDX_OK : HDX_E_DEVICE;
+    return launch_features(&a, 1, (hipStream_t)stream) == hipSuccess ? HDX_OK : HDX_E_DEVICE;
 }
 
 hdx_status hdx_expand_leaf_surrogate(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves, hdx_mlp *mlp,
@@ -268,8 +272,13 @@ hdx_status hdx_expand_leaf_surrogate(hdx_ctx *ctx, const hdx_leaf *leaves, int32
     hdx_status st = hdx_expand_leaf(ctx, mod.data(), n_leaves, stream);
     if (st != HDX_OK) return st;
     hipStream_t s = (hipStream_t)stream;
+    std::vector<FeatArgs> fa;
+    std::vector<SurArgs> sa;
+    fa.reserve(n_leaves);
+    sa.reserve(n_leaves);
     for (int32_t i = 0; i < n_leaves; ++i) {
-        const int64_t np = (int64_t)hdx_model_actions(leaves[i].model) * (leaves[i].n > 0 ? leaves[i].n : 0);
+        const int32_t A = hdx_model_actions(leaves[i].model);
+        const int64_t np = (int64_t)A * (leaves[i].n > 0 ? leaves[i].n : 0);
         if (np == 0) continue;
         FeatArgs a;
         a.model = hdx_internal_devmodel(leaves[i].model);
@@ -279,25 +288,25 @@ hdx_status hdx_expand_leaf_surrogate(hdx_ctx *ctx, const hdx_leaf *leaves, int32
         a.n = np;
         a.horizon = horizon;
         a.X = X + pair_off[i] * kMlpIn;
-        if (launch_features(a, s) != hipSuccess) return HDX_E_DEVICE;
+        fa.push_back(a);
+        SurArgs r;
+        r.values = vals + pair_off[i];
+        r.perm = leaves[i].perm;
+        r.n_children = leaves[i].n_children;
+        r.child_n = leaves[i].child_n;
+        r.child_off = leaves[i].child_off;
+        r.child_l0 = leaves[i].child_l0;
+        r.L_out = leaves[i].L;
+        r.n = leaves[i].n;
+        r.cap = leaves[i].cap;
+        r.n_actions = A;
+        r.pad = 0;
+        sa.push_back(r);
     }
-    if (!grow_scratch(mlp->S, std::min<int64_t>(pairs, kMlpChunkRows))) return HDX_E_NOMEM;
-    if (pairs > 0 && mlp_forward(mlp->P, X, pairs, mlp->S.h1, mlp->S.h2, mlp->S.h3, vals, s) != hipSuccess)
+    if (launch_features(fa.data(), (int)fa.size(), s) != hipSuccess) return HDX_E_DEVICE;
+    if (pairs > 0 && mlp_forward(mlp->P, X, pairs, nullptr, nullptr, nullptr, vals, s) != hipSuccess)
         return HDX_E_DEVICE;
-    for (int32_t i = 0; i < n_leaves; ++i) {
-        if (leaves[i].n <= 0) continue;
-        SurArgs a;
-        a.values = vals + pair_off[i];
-        a.perm = leaves[i].perm;
-        a.n_children = leaves[i].n_children;
-        a.child_n = leaves[i].child_n;
-        a.child_off = leaves[i].child_off;
-        a.child_l0 = leaves[i].child_l0;
-        a.L_out = leaves[i].L;
-        a.n = leaves[i].n;
-        a.cap = leaves[i].cap;
-        if (launch_surrogate_reduce(a, hdx_model_actions(leaves[i].model), s) != hipSuccess) return HDX_E_DEVICE;
-    }
+    if (launch_surrogate_reduce(sa.data(), (int)sa.size(), s) != hipSuccess) return HDX_E_DEVICE;
     return HDX_OK;
 }
 

@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -78,9 +79,9 @@ hdx_status hdx_init(int32_t device, hdx_ctx **out) {
             delete ctx;
             return HDX_E_DEVICE;
         }
-        if (hipMalloc(&s.d_queue, sizeof(TileQueue)) != hipSuccess ||
-            hipHostMalloc(&s.h_queue, sizeof(TileQueue)) != hipSuccess ||
-            hipMemset(s.d_queue, 0, sizeof(TileQueue)) != hipSuccess) {
+        if (hipMalloc(&s.d_queue, kSizeClasses * sizeof(TileQueue)) != hipSuccess ||
+            hipHostMalloc(&s.h_queue, kSizeClasses * sizeof(TileQueue)) != hipSuccess ||
+            hipMemset(s.d_queue, 0, kSizeClasses * sizeof(TileQueue)) != hipSuccess) {
             delete ctx;
             return HDX_E_NOMEM;
         }
@@ -408,6 +409,53 @@ void pack_leaves(const hdx_leaf *leaves, int32_t n_leaves, LeafTask *tasks, Tile
 
 // Default schedule: one scenario per lane up to the variant's workgroup cap,
 // one workgroup per tile, consecutive tiles kept on one XCD.
+}  // namespace
+
+void hdx::plan_classes(const LeafTask *tasks, Tile *tiles, int64_t n_tiles, ClassPlan *plan) {
+    int64_t cnt[kSizeClasses] = {0};
+    for (int c = 0; c < kSizeClasses; ++c) plan->n_max[c] = 0;
+    for (int64_t t = 0; t < n_tiles; ++t) {
+        const int32_t n = tasks[tiles[t].leaf].n;
+        const int c = size_class(n);
+        cnt[c]++;
+        if (n > plan->n_max[c]) plan->n_max[c] = n;
+    }
+    int64_t at = 0;
+    for (int c = 0; c < kSizeClasses; ++c) {
+        plan->begin[c] = at;
+        plan->count[c] = cnt[c];
+        at += cnt[c];
+    }
+    bool sorted = true;
+    for (int64_t t = 1; t < n_tiles && sorted; ++t)
+        sorted = size_class(tasks[tiles[t - 1].leaf].n) <= size_class(tasks[tiles[t].leaf].n);
+    if (sorted) return;
+    std::vector<Tile> tmp(tiles, tiles + n_tiles);
+    int64_t pos[kSizeClasses];
+    for (int c = 0; c < kSizeClasses; ++c) pos[c] = plan->begin[c];
+    for (const Tile &t : tmp) tiles[pos[size_class(tasks[t.leaf].n)]++] = t;
+}
+
+hipError_t hdx::launch_classes(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queues,
+                               const ClassPlan &plan, const Variant &v, const int32_t *lds_n, const Schedule &sch,
+                               int32_t n_cu, hipStream_t stream) {
+    for (int c = 0; c < kSizeClasses; ++c) {
+        if (plan.count[c] == 0) continue;
+        Variant vc = v;
+        vc.n_max = std::max(lds_n[c], plan.n_max[c]);
+        // a workgroup no wider than the class's leaves need
+        const int need = std::max(64, pow2_at_least(std::max(vc.n_max, 1)));
+        Schedule sc = sch;
+        if (sc.threads > need) sc.threads = need;
+        const hipError_t e = launch_expand(d_tasks, d_tiles + plan.begin[c], d_queues + c, (int32_t)plan.count[c], vc,
+                                           sc, n_cu, stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+namespace {
+
 Schedule default_schedule(const Variant &v) {
     Schedule s;
     int th = ((v.n_max + 63) / 64) * 64;
@@ -479,15 +527,19 @@ hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
                      sh.n_tiles);
     if (st != HDX_OK) return st;
     pack_leaves(leaves, n_leaves, s.h_tasks, s.h_tiles);
-    *s.h_queue = TileQueue{0, 0, (int32_t)sh.n_tiles, 0};
+    ClassPlan plan;
+    plan_classes(s.h_tasks, s.h_tiles, sh.n_tiles, &plan);
+    for (int c = 0; c < kSizeClasses; ++c) s.h_queue[c] = TileQueue{0, 0, (int32_t)plan.count[c], 0};
     hipStream_t hs = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(s.d_tasks, s.h_tasks, n_leaves * sizeof(LeafTask), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(s.d_tiles, s.h_tiles, sh.n_tiles * sizeof(Tile), hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess) e = hipMemcpyAsync(s.d_queue, s.h_queue, sizeof(TileQueue), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s.d_queue, s.h_queue, kSizeClasses * sizeof(TileQueue), hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return hip_fail(ctx, e, "descriptor copy");
     const Variant v = pick_variant(sh.has_rs, sh.has_ped, sh.ped_max, sh.n_max);
     const Schedule sch = ctx->sched_fixed ? ctx->sched : default_schedule(v);
-    e = launch_expand(s.d_tasks, s.d_tiles, s.d_queue, (int32_t)sh.n_tiles, v, sch, ctx->n_cu, hs);
+    const int32_t no_lds[kSizeClasses] = {0, 0, 0, 0, 0, 0};
+    e = launch_classes(s.d_tasks, s.d_tiles, s.d_queue, plan, v, no_lds, sch, ctx->n_cu, hs);
     if (e != hipSuccess) return hip_fail(ctx, e, "expand launch");
     e = hipEventRecord(s.done, hs);
     s.used = true;
@@ -505,7 +557,11 @@ struct hdx_batch {
     int32_t n_leaves = 0;
     int64_t n_tiles = 0;
     Variant var{0, 1, 1};
-    int32_t lds_n = 1;  // LDS sized for the largest leaf seen, so graphs survive smaller batches
+    int32_t lds_n = 1;  // largest leaf seen
+    ClassPlan plan{};
+    int32_t lds_c[kSizeClasses] = {0, 0, 0, 0, 0, 0};  // per class: largest leaf seen
+    ClassPlan g_plan{};
+    int32_t g_lds[kSizeClasses] = {0, 0, 0, 0, 0, 0};
     Schedule sched{256, 0, 1};
     bool sched_set = false;
     hipStream_t work = nullptr;  // capture and tuning stream
@@ -528,7 +584,7 @@ Variant batch_variant(const hdx_batch *b) {
 }
 
 hipError_t batch_direct_launch(hdx_ctx *ctx, hdx_batch *b, const Schedule &s, hipStream_t st) {
-    return launch_expand(b->d_tasks, b->d_tiles, b->d_queue, (int32_t)b->n_tiles, batch_variant(b), s, ctx->n_cu, st);
+    return launch_classes(b->d_tasks, b->d_tiles, b->d_queue, b->plan, b->var, b->lds_c, s, ctx->n_cu, st);
 }
 
 void drop_graph(hdx_batch *b) {
@@ -552,9 +608,9 @@ hdx_status hdx_batch_create(hdx_ctx *ctx, int32_t max_leaves, int64_t max_tiles,
     hdx_status st = grow_pinned(ctx, &b->h_tasks, &b->d_tasks, &b->cap_tasks, &b->h_tiles, &b->d_tiles, &b->cap_tiles,
                                 max_leaves, max_tiles);
     if (st == HDX_OK &&
-        (hipHostMalloc(&b->h_queue, sizeof(TileQueue)) != hipSuccess ||
-         hipMalloc(&b->d_queue, sizeof(TileQueue)) != hipSuccess ||
-         hipMemset(b->d_queue, 0, sizeof(TileQueue)) != hipSuccess ||
+        (hipHostMalloc(&b->h_queue, kSizeClasses * sizeof(TileQueue)) != hipSuccess ||
+         hipMalloc(&b->d_queue, kSizeClasses * sizeof(TileQueue)) != hipSuccess ||
+         hipMemset(b->d_queue, 0, kSizeClasses * sizeof(TileQueue)) != hipSuccess ||
          hipStreamCreateWithFlags(&b->work, hipStreamNonBlocking) != hipSuccess ||
          hipEventCreate(&b->staged) != hipSuccess || hipEventCreate(&b->t0) != hipSuccess ||
          hipEventCreate(&b->t1) != hipSuccess || hipDeviceSynchronize() != hipSuccess))
@@ -599,13 +655,19 @@ hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *b, const hdx_leaf *leav
         if (e != hipSuccess) return hip_fail(ctx, e, "staging wait");
     }
     pack_leaves(leaves, n_leaves, b->h_tasks, b->h_tiles);
-    *b->h_queue = TileQueue{0, 0, (int32_t)sh.n_tiles, 0};
+    plan_classes(b->h_tasks, b->h_tiles, sh.n_tiles, &b->plan);
+    for (int c = 0; c < kSizeClasses; ++c) {
+        b->h_queue[c] = TileQueue{0, 0, (int32_t)b->plan.count[c], 0};
+        // LDS sized for the largest leaf a class has seen, so graphs survive smaller batches
+        b->lds_c[c] = std::max(b->lds_c[c], b->plan.n_max[c]);
+    }
     hipStream_t hs = (hipStream_t)stream;
     hipError_t e = hipSuccess;
     if (n_leaves > 0) e = hipMemcpyAsync(b->d_tasks, b->h_tasks, n_leaves * sizeof(LeafTask), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && sh.n_tiles > 0)
         e = hipMemcpyAsync(b->d_tiles, b->h_tiles, sh.n_tiles * sizeof(Tile), hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess) e = hipMemcpyAsync(b->d_queue, b->h_queue, sizeof(TileQueue), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_queue, b->h_queue, kSizeClasses * sizeof(TileQueue), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipEventRecord(b->staged, hs);
     if (e != hipSuccess) return hip_fail(ctx, e, "batch descriptor copy");
     b->staged_used = true;
@@ -652,9 +714,15 @@ hdx_status hdx_batch_launch(hdx_ctx *ctx, hdx_batch *b, hdx_stream stream) {
         return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "batch launch");
     }
     const Variant v = batch_variant(b);
-    const bool same = b->graph_ok && v.mode == b->g_var.mode && v.pm == b->g_var.pm && v.n_max == b->g_var.n_max &&
-                      b->sched.threads == b->g_sched.threads && b->sched.persistent == b->g_sched.persistent &&
-                      b->sched.xcd_remap == b->g_sched.xcd_remap &&
+    // the graph bakes in each class's tile offset, LDS size and (non-persistent) grid
+    bool classes_same = true;
+    for (int c = 0; c < kSizeClasses; ++c)
+        classes_same = classes_same && b->plan.begin[c] == b->g_plan.begin[c] && b->lds_c[c] == b->g_lds[c] &&
+                       (b->sched.persistent > 0 ? (b->plan.count[c] > 0) == (b->g_plan.count[c] > 0)
+                                                : b->plan.count[c] == b->g_plan.count[c]);
+    const bool same = b->graph_ok && classes_same && v.mode == b->g_var.mode && v.pm == b->g_var.pm &&
+                      v.n_max == b->g_var.n_max && b->sched.threads == b->g_sched.threads &&
+                      b->sched.persistent == b->g_sched.persistent && b->sched.xcd_remap == b->g_sched.xcd_remap &&
                       (b->sched.persistent > 0 || b->n_tiles == b->g_tiles);
     if (!same) {
         drop_graph(b);
@@ -673,6 +741,8 @@ hdx_status hdx_batch_launch(hdx_ctx *ctx, hdx_batch *b, hdx_stream stream) {
         b->g_var = v;
         b->g_sched = b->sched;
         b->g_tiles = b->n_tiles;
+        b->g_plan = b->plan;
+        for (int c = 0; c < kSizeClasses; ++c) b->g_lds[c] = b->lds_c[c];
     }
     e = hipGraphLaunch(b->exec, hs);
     return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "graph launch");

@@ -119,6 +119,29 @@ hdx_states rec_states(const hdx_model_desc &d, const Rec &r) {
     return s;
 }
 
+// Per-thread scratch of the surrogate judge: a record for the largest leaf
+// and its head block on the host.
+struct Judge {
+    Rec rec;
+    char *head = nullptr;
+};
+
+// Points a leaf's outputs at a record's arrays.
+void fill_outputs(const hdx_model_desc &d, hdx_leaf &L, const Rec &r) {
+    L.states_out = rec_states(d, r);
+    L.ids_out = (uint32_t *)(r.dev + r.L.ids);
+    L.perm = (int32_t *)(r.dev + r.L.perm);
+    L.n_children = (int32_t *)(r.dev + r.L.n_children);
+    L.child_z = (uint64_t *)(r.dev + r.L.child_z);
+    L.child_n = (int32_t *)(r.dev + r.L.child_n);
+    L.child_off = (int32_t *)(r.dev + r.L.child_off);
+    L.child_u0 = (float *)(r.dev + r.L.child_u0);
+    L.child_l0 = (float *)(r.dev + r.L.child_l0);
+    L.r_mean = (float *)(r.dev + r.L.r_mean);
+    L.steps = (int64_t *)(r.dev + r.L.steps);
+}
+
+
 struct Search {
     hdx_ctx *ctx;
     const hdx_model *model;
@@ -136,6 +159,12 @@ struct Search {
     std::atomic<int> max_depth{0};
     std::atomic<bool> stop{false};
     std::atomic<int64_t> idle_trials{0};
+    // surrogate judge (rollouts on every j-th surrogate expansion) and fallback
+    std::atomic<bool> surrogate_off{false};
+    std::atomic<int64_t> judge_ctr{0};
+    std::mutex jmu;
+    double j_err = 0.0, j_ref = 0.0;
+    int64_t j_leaves = 0, j_children = 0;
     double c_a_abs = 0.0;  // c_a scaled by the initial root gap
     std::mutex emu;
     hdx_status error = HDX_OK;
@@ -220,7 +249,9 @@ struct Search {
         return best;
     }
 
-    bool expand(int node_id, hipStream_t stream, char *head_host);
+    bool expand(int node_id, hipStream_t stream, char *head_host, Judge *J);
+    void judge_leaf(const hdx_leaf &L0, const Rec &r, const char *head_host, Judge &J, hipStream_t stream);
+    bool use_surrogate() const { return cfg.surrogate != nullptr && !surrogate_off.load(); }
 
     void attach(int node_id, const Rec &r, const char *head) {
         Node &b = nodes[node_id];
@@ -262,7 +293,44 @@ struct Search {
     }
 };
 
-bool Search::expand(int node_id, hipStream_t stream, char *head_host) {
+// The surrogate's children l0 against the rollouts' on the same leaf (same
+// grouping, both expansions being deterministic); falls back to rollouts
+// when the accumulated relative error exceeds the configured bound.
+void Search::judge_leaf(const hdx_leaf &L0, const Rec &r, const char *head_host, Judge &J, hipStream_t stream) {
+    hdx_leaf L = L0;
+    fill_outputs(d, L, J.rec);
+    hdx_status st = hdx_expand_leaf_surrogate(ctx, &L, 1, cfg.surrogate, cfg.surrogate_horizon, stream);
+    if (st != HDX_OK) {
+        fail(st, "judge expansion");
+        return;
+    }
+    if (hipMemcpyAsync(J.head, J.rec.dev, J.rec.L.head, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+        fail(HDX_E_DEVICE, "judge head copy");
+        return;
+    }
+    const int cap = L0.cap;
+    const int32_t *nch = (const int32_t *)(head_host + r.L.n_children);
+    const float *lf = (const float *)(head_host + r.L.child_l0);
+    const float *ls = (const float *)(J.head + J.rec.L.child_l0);
+    double e = 0.0, ref = 0.0;
+    int64_t nc = 0;
+    for (int a = 0; a < A; ++a)
+        for (int c = 0; c < nch[a] && c < cap; ++c) {
+            e += std::fabs((double)ls[a * cap + c] - (double)lf[a * cap + c]);
+            ref += std::fabs((double)lf[a * cap + c]);
+            ++nc;
+        }
+    std::lock_guard<std::mutex> g(jmu);
+    j_err += e;
+    j_ref += ref;
+    j_children += nc;
+    j_leaves += 1;
+    if (cfg.surrogate_max_rel_err > 0.0 && j_leaves >= 8 && j_err > cfg.surrogate_max_rel_err * j_ref)
+        surrogate_off = true;
+}
+
+bool Search::expand(int node_id, hipStream_t stream, char *head_host, Judge *J) {
     // builds the leaf descriptor; the caller holds no lock
     Node b;
     {
@@ -289,19 +357,12 @@ bool Search::expand(int node_id, hipStream_t stream, char *head_host) {
     L.depth = b.depth;
     L.last_action = b.action;
     L.cap = cap_for(b.n);
-    L.states_out = rec_states(d, r);
-    L.ids_out = (uint32_t *)(r.dev + r.L.ids);
-    L.perm = (int32_t *)(r.dev + r.L.perm);
-    L.n_children = (int32_t *)(r.dev + r.L.n_children);
-    L.child_z = (uint64_t *)(r.dev + r.L.child_z);
-    L.child_n = (int32_t *)(r.dev + r.L.child_n);
-    L.child_off = (int32_t *)(r.dev + r.L.child_off);
-    L.child_u0 = (float *)(r.dev + r.L.child_u0);
-    L.child_l0 = (float *)(r.dev + r.L.child_l0);
-    L.r_mean = (float *)(r.dev + r.L.r_mean);
-    L.steps = (int64_t *)(r.dev + r.L.steps);
+    fill_outputs(d, L, r);
     hdx_status st = HDX_OK;
-    if (cfg.batch_leaves > 1) {
+    const bool sur = use_surrogate();
+    const bool judge = sur && J != nullptr && cfg.surrogate_judge_every > 0 &&
+                       judge_ctr.fetch_add(1) % cfg.surrogate_judge_every == 0;
+    if (cfg.batch_leaves > 1 && !judge) {
         Request q;
         q.leaf = L;
         q.rec = nullptr;
@@ -322,8 +383,9 @@ bool Search::expand(int node_id, hipStream_t stream, char *head_host) {
         }
         st = q.status;
     } else {
-        st = cfg.surrogate ? hdx_expand_leaf_surrogate(ctx, &L, 1, cfg.surrogate, cfg.surrogate_horizon, stream)
-                           : hdx_expand_leaf(ctx, &L, 1, stream);
+        // a judged leaf keeps its rollout bounds in the tree
+        st = (sur && !judge) ? hdx_expand_leaf_surrogate(ctx, &L, 1, cfg.surrogate, cfg.surrogate_horizon, stream)
+                             : hdx_expand_leaf(ctx, &L, 1, stream);
         if (st != HDX_OK) {
             fail(st, "expand_leaf");
         } else {
@@ -338,6 +400,7 @@ bool Search::expand(int node_id, hipStream_t stream, char *head_host) {
                 }
                 stop = true;
             }
+            if (st == HDX_OK && judge) judge_leaf(L, r, head_host, *J, stream);
         }
         launches++;
         std::lock_guard<std::mutex> g(mu);
@@ -368,7 +431,7 @@ void batcher_loop(Search *S, hipStream_t stream) {
         leaves.clear();
         for (Request *q : batch) leaves.push_back(q->leaf);
         const int32_t nl = (int32_t)leaves.size();
-        hdx_status st = S->cfg.surrogate ? hdx_expand_leaf_surrogate(S->ctx, leaves.data(), nl, S->cfg.surrogate,
+        hdx_status st = S->use_surrogate() ? hdx_expand_leaf_surrogate(S->ctx, leaves.data(), nl, S->cfg.surrogate,
                                                                      S->cfg.surrogate_horizon, stream)
                                          : hdx_expand_leaf(S->ctx, leaves.data(), nl, stream);
         if (st != HDX_OK) S->fail(st, "batched expand_leaf");
@@ -394,6 +457,11 @@ void worker(Search *S, int tid, size_t head_bytes) {
     hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
     char *head_host = nullptr;
     hipHostMalloc((void **)&head_host, head_bytes);
+    Judge judge;
+    Judge *J = nullptr;
+    if (S->cfg.surrogate && S->cfg.surrogate_judge_every > 0 && S->alloc_rec(S->cfg.K, &judge.rec) &&
+        hipHostMalloc((void **)&judge.head, judge.rec.L.head) == hipSuccess)
+        J = &judge;
     std::vector<int> path;
     const double K = (double)S->cfg.K;
     while (!S->stop.load()) {
@@ -445,7 +513,7 @@ void worker(Search *S, int tid, size_t head_bytes) {
         }
         bool ok = true;
         if (leaf >= 0) {
-            ok = S->expand(leaf, stream, head_host);
+            ok = S->expand(leaf, stream, head_host, J);
             if (!ok) {
                 std::lock_guard<std::mutex> g(S->mu);
                 S->nodes[leaf].state = 0;
@@ -469,6 +537,7 @@ void worker(Search *S, int tid, size_t head_bytes) {
         }
     }
     hipHostFree(head_host);
+    if (judge.head) hipHostFree(judge.head);
     hipStreamDestroy(stream);
 }
 
@@ -576,6 +645,11 @@ extern "C" hdx_status hdx_search(hdx_ctx *ctx, const hdx_model *model, const hdx
     out->launches = S.launches.load();
     out->max_depth_reached = S.max_depth.load();
     out->arena_full = S.arena_full.load();
+    out->judged_leaves = S.j_leaves;
+    out->judged_children = S.j_children;
+    out->judge_mae = S.j_children > 0 ? S.j_err / (double)S.j_children : 0.0;
+    out->judge_rel_err = S.j_ref > 0.0 ? S.j_err / S.j_ref : 0.0;
+    out->surrogate_off = S.surrogate_off.load() ? 1 : 0;
     out->best_action = 0;
     if (r.state == 2) {
         double best = -std::numeric_limits<double>::infinity();

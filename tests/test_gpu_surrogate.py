@@ -238,3 +238,27 @@ def test_search_with_surrogate(ctx, net, threads, batch):
     assert r["expansions"] > 0 and r["trials"] >= r["expansions"]
     assert 0 <= r["best_action"] < desc["n_actions"]
     assert np.isfinite(r["l_root"]) and np.isfinite(r["u_root"])
+
+
+@pytest.mark.parametrize("threads,batch", [(4, 0), (8, 8)])
+def test_search_surrogate_judge_and_fallback(ctx, net, threads, batch):
+    """Every 4th surrogate expansion is judged against rollouts; with a zero
+    error bound the monitor never switches, with a tiny one it falls back to
+    rollouts once 8 leaves are judged."""
+    from paper_1802_06215_amd import hdx as H
+    desc = W.rocksample_model(15, 15, 1)
+    m = ctx.upload_model(desc)
+    b = W.rocksample_belief(desc)
+    common = dict(K=500, n_threads=threads, batch_leaves=batch, time_budget_s=0.3, max_depth=HORIZON,
+                  rollout=H.rollout_cfg(H.POLICY_RANDOM, 1 << 30, HORIZON), surrogate=net,
+                  surrogate_horizon=HORIZON, surrogate_judge_every=4, seed=5, arena_bytes=2 << 30)
+    print("judge: threads=%d batch=%d" % (threads, batch), flush=True)
+    r = ctx.search(m, b, surrogate_max_rel_err=0.0, **common)
+    print(r["judged_leaves"], r["judged_children"], r["judge_mae"], r["judge_rel_err"], flush=True)
+    assert r["judged_leaves"] > 0 and r["judged_children"] >= r["judged_leaves"]
+    assert r["surrogate_off"] == 0
+    assert np.isfinite(r["judge_mae"]) and r["judge_rel_err"] >= 0
+    r = ctx.search(m, b, surrogate_max_rel_err=1e-12, **common)
+    print(r["judged_leaves"], r["judge_rel_err"], r["surrogate_off"], flush=True)
+    assert r["judged_leaves"] >= 8
+    assert r["surrogate_off"] == (1 if r["judge_rel_err"] > 1e-12 else 0)
