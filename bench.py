@@ -26,6 +26,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per launch of the expansion kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (scaled by a plain copy of known size), recorded with a hash of
+# the kernel's sources: reported only while those sources are unchanged.
+PROFILED_TRAFFIC = {
+    "rs15": dict(bytes=52.587e6, sha="335e7d3c081b1c69", summary="profiles/expand_tiles_rs15.md"),
+}
+KERNEL_SOURCES = ("paper_1802_06215_amd/csrc/kernels.hip", "paper_1802_06215_amd/csrc/models.hpp",
+                  "paper_1802_06215_amd/csrc/internal.hpp")
+
+
+def kernel_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 PEAK_BF16_TFLOPS = 2500.0  # dense BF16 MFMA
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: full-rate 32-bit VALU lane-ops/s
 PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -50,10 +67,15 @@ def parse():
                     help="only run a plain 256 MiB device copy (x3), to scale HBM byte counters")
     ap.add_argument("--search-seconds", type=float, default=1.0,
                     help="planning budget of each search measurement (rs15 only; 0 = skip)")
-    ap.add_argument("--schedule", default="", help="threads,persistent,xcd_remap (skips the autotuner)")
-    ap.add_argument("--surrogate-epochs", type=int, default=4,
+    ap.add_argument("--schedule", default="", help="threads,persistent,xcd_remap for every size class "
+                    "(skips the autotuner)")
+    ap.add_argument("--class-schedule", action="append", default=[],
+                    help="size_class:threads,persistent,xcd_remap (repeatable; skips the autotuner)")
+    ap.add_argument("--surrogate-epochs", type=int, default=8,
                     help="training epochs of the surrogate comparison (rs15 only; 0 = skip)")
-    ap.add_argument("--surrogate-leaves", type=int, default=1024,
+    ap.add_argument("--surrogate-targets", type=int, default=8,
+                    help="rollouts averaged into each training target")
+    ap.add_argument("--surrogate-leaves", type=int, default=2048,
                     help="training leaves of 100 scenarios each (x 20 actions = pairs / 2000)")
     return ap.parse_args()
 
@@ -195,9 +217,14 @@ def surrogate_section(ctx, args):
             out = H.LeafBuffers(m, n, per_pair=per_pair)
             descs.append(H.make_leaf(m, par, pids, idx, lf["depth"], lf["last_action"], out, seed, 0, rcfg))
             outs.append((out, lf["depth"]))
-            keep += [par, pids, idx]
+            keep.append((par, pids, idx, lf, out))
         torch.cuda.synchronize()
         return descs, outs, keep
+
+    def reseed(keep, seed):
+        # the same leaves and buffers under another random-number key
+        return [H.make_leaf(m, par, pids, idx, lf["depth"], lf["last_action"], out, seed, 0, rcfg)
+                for par, pids, idx, lf, out in keep]
 
     def timed(fn, reps):
         """Mean seconds per call: HIP events on the stream the calls are issued on."""
@@ -217,8 +244,15 @@ def surrogate_section(ctx, args):
     gen_s = timed(lambda: ctx.expand_leaf(descs), 1)
     pairs = [S.leaf_pairs(ctx, m, o, d, 90) for o, d in outs]
     X = torch.cat([p[0] for p in pairs])
-    t = torch.cat([p[1] for p in pairs])
-    del pairs, outs, descs, keep
+    # targets: mean of several rollouts per pair (the stepped states do not
+    # depend on the key; only the random rollout actions do)
+    acc = [torch.zeros_like(o.L[:, :o.n]) for o, _ in outs]
+    for r in range(args.surrogate_targets):
+        ctx.expand_leaf(reseed(keep, 700000 + r))
+        for a_, (o, _) in zip(acc, outs):
+            a_ += o.L[:, :o.n]
+    t = torch.cat([(a_ / args.surrogate_targets).reshape(-1) for a_ in acc])
+    del pairs, outs, descs, keep, acc
     net = Mlp(ctx, seed=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -247,9 +281,43 @@ def surrogate_section(ctx, args):
     err, ref = np.concatenate(err), np.concatenate(ref)
     steps_full = int(sum(st.sum() for _, _, st in full))
 
+    # accuracy against a low-noise value: RockSample steps are deterministic,
+    # so the same (action, scenario) pairs under other keys differ only in
+    # the random rollout actions; their mean over R keys is the reference
+    R = 16
+    descs, outs, keep = leafset(specs, True)
+    ctx.expand_leaf(descs)
+    torch.cuda.synchronize()
+    one = [(o.L[:, :o.n].clone(), o.perm[:, :o.n].cpu().numpy(), o.child_off.cpu().numpy(), o.child_n.cpu().numpy(),
+            o.n_children.cpu().numpy(), o.child_l0.cpu().numpy().copy()) for o, _ in outs]
+    ref_sum = [torch.zeros_like(x[0]) for x in one]
+    for r in range(R):
+        ctx.expand_leaf(reseed(keep, 900000 + r))
+        for acc, (o, _) in zip(ref_sum, outs):
+            acc += o.L[:, :o.n]
+    ctx.expand_leaf_surrogate(descs, net, 90)
+    torch.cuda.synchronize()
+    pe_one, pe_sur, ce_one, ce_sur = [], [], [], []
+    for (o, _), acc, (l_one, perm, coff, cn, nch, l0_one) in zip(outs, ref_sum, one):
+        truth = (acc / R).cpu().numpy().astype(np.float64)
+        l_sur = o.L[:, :o.n].cpu().numpy().astype(np.float64)
+        l_one = l_one.cpu().numpy().astype(np.float64)
+        pe_one.append(np.abs(l_one - truth).ravel())
+        pe_sur.append(np.abs(l_sur - truth).ravel())
+        l0_sur = o.child_l0.cpu().numpy()
+        for a in range(len(nch)):
+            for c in range(nch[a]):
+                seg = perm[a, coff[a, c]:coff[a, c] + cn[a, c]]
+                t0_ = truth[a, seg].mean()
+                ce_one.append(abs(l0_one[a, c] - t0_))
+                ce_sur.append(abs(l0_sur[a, c] - t0_))
+    pe_one, pe_sur = np.concatenate(pe_one), np.concatenate(pe_sur)
+    ce_one, ce_sur = np.asarray(ce_one), np.asarray(ce_sur)
+    del descs, outs, keep, one, ref_sum
+
     # search at equal budget
     runs = {}
-    for name, sur in (("rollouts", None), ("surrogate", net)):
+    for name, sur in (("rollouts", None), ("surrogate", net)) if args.search_seconds > 0 else ():
         r = ctx.search(m, W.rocksample_belief(desc), K=500, n_threads=8, max_depth=90, batch_leaves=8,
                        time_budget_s=args.search_seconds, rollout=rcfg, surrogate=sur, surrogate_horizon=90,
                        surrogate_judge_every=16 if sur is not None else 0, seed=3)
@@ -261,12 +329,14 @@ def surrogate_section(ctx, args):
             runs[name].update(judged_leaves=r["judged_leaves"], judge_child_l0_mae=round(r["judge_mae"], 5),
                               judge_rel_err=round(r["judge_rel_err"], 5), fell_back=bool(r["surrogate_off"]))
         log("search", name, runs[name])
-    lf_, ls_ = runs["rollouts"]["l_root"], runs["surrogate"]["l_root"]
+    lf_ = runs["rollouts"]["l_root"] if runs else 0.0
+    ls_ = runs["surrogate"]["l_root"] if runs else 0.0
     net.close()
     return dict(
         config="RockSample 15x15, 15 rocks, uniform-random rollouts of depth 90; MLP 64-256-256-256-1 "
                "(BF16 MFMA, FP32 accumulate)",
-        train=dict(pairs=n_pairs, leaves=args.surrogate_leaves, data_gen_s=round(gen_s, 3), epochs=args.surrogate_epochs,
+        train=dict(pairs=n_pairs, leaves=args.surrogate_leaves, rollouts_per_target=args.surrogate_targets,
+                   data_gen_s=round(gen_s, 3), epochs=args.surrogate_epochs,
                    fit_s=round(train_s, 3), samples_per_s=round(samples / train_s, 1),
                    tflops=round(S.FLOPS_TRAIN * samples / train_s / 1e12, 2), losses=[round(h, 4) for h in hist]),
         forward=dict(rows=n_pairs, ms=round(fwd_s * 1e3, 3),
@@ -280,7 +350,14 @@ def surrogate_section(ctx, args):
                      full_scenario_steps=steps_full,
                      child_l0_mae=round(float(err.mean()), 5), child_l0_mean_abs=round(float(ref.mean()), 5),
                      child_l0_err_p50=round(float(np.median(err)), 5),
-                     child_l0_err_p90=round(float(np.percentile(err, 90)), 5)),
+                     child_l0_err_p90=round(float(np.percentile(err, 90)), 5),
+                     vs_mean_of_16_rollouts=dict(
+                         pair_mae_one_rollout=round(float(pe_one.mean()), 5),
+                         pair_mae_surrogate=round(float(pe_sur.mean()), 5),
+                         child_l0_mae_one_rollout=round(float(ce_one.mean()), 5),
+                         child_l0_mae_surrogate=round(float(ce_sur.mean()), 5),
+                         child_l0_p90_one_rollout=round(float(np.percentile(ce_one, 90)), 5),
+                         child_l0_p90_surrogate=round(float(np.percentile(ce_sur, 90)), 5))),
         search=dict(threads=8, leaf_batch=8, budget_s=args.search_seconds, runs=runs,
                     root_value_rel_err=round(abs(ls_ - lf_) / max(abs(lf_), 1e-9), 5)))
 
@@ -339,11 +416,15 @@ def main():
     torch.cuda.synchronize()
     log("leaves %d tiles %d" % (len(leaves), n_tiles))
     tuned_ms = None
-    if args.schedule:
-        batch.set_schedule(*[int(v) for v in args.schedule.split(",")])
+    if args.schedule or args.class_schedule:
+        if args.schedule:
+            batch.set_schedule(*[int(v) for v in args.schedule.split(",")])
+        for cs in args.class_schedule:
+            c, rest = cs.split(":")
+            batch.set_class_schedule(int(c), *[int(v) for v in rest.split(",")])
     elif not args.no_autotune:
         tuned_ms = batch.autotune(2)
-        log("autotuned schedule", batch.schedule(), "%.3f ms" % tuned_ms)
+        log("autotuned schedules", batch.class_schedules(), "%.3f ms" % tuned_ms)
     batch.use_graph(True)
     for _ in range(args.warmup):
         batch.launch()
@@ -375,8 +456,12 @@ def main():
             d, lf = items[k][0], items[k][1]
             ops += algorithmic_ops(d, len(lf["idx"]), d["n_actions"], int(st[j, 0]), int(st[j, 1]))
     achieved_tops = ops / (kernel_ms * 1e-3) / 1e12
+    prof = PROFILED_TRAFFIC.get(args.workload)
+    traffic = prof["bytes"] if prof and prof["sha"] == kernel_sha() else None
     roofline = dict(bound="alu", achieved=round(achieved_tops, 3), peak=round(PEAK_ALU_TOPS, 2),
-                    unit="TOP/s", frac=round(achieved_tops / PEAK_ALU_TOPS, 4), traffic=None,
+                    unit="TOP/s", frac=round(achieved_tops / PEAK_ALU_TOPS, 4), traffic=traffic,
+                    traffic_unit="bytes/launch", traffic_source=prof["summary"] if traffic else None,
+                    hbm_gbs_at_traffic=round(traffic / (kernel_ms * 1e-3) / 1e9, 1) if traffic else None,
                     ops_per_launch=int(ops), kernel_ms=round(kernel_ms, 4))
 
     search = None
@@ -400,7 +485,7 @@ def main():
             log("search", search[-1])
 
     sur = None
-    if args.workload == "rs15" and args.surrogate_epochs > 0 and args.search_seconds > 0:
+    if args.workload == "rs15" and args.surrogate_epochs > 0:
         log("surrogate comparison...")
         sur = surrogate_section(ctx, args)
 
@@ -419,12 +504,14 @@ def main():
                  mix64="MIX64: 64 planner instances (RockSample 7..20 / driving, K in {100,200,500}); "
                        "%d leaves in one launch")
     t, p, x = batch.schedule()
+    per_class = [dict(max_n=64 << c, tiles=n, threads=ct, persistent=cp, xcd_remap=cx)
+                 for c, ct, cp, cx, n in batch.class_schedules()]
     out = dict(metric=METRIC, value=round(value, 1), unit="scenario-steps/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(wall * 1e3 / args.steps, 4), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="int32+fp32", data="synthetic",
                config=dict(workload=names[args.workload] % len(leaves), leaves=len(leaves), tiles=n_tiles,
                            scenario_steps_per_step=steps_per_launch, expand_steps=exp_steps,
-                           rollout_steps=roll_steps, schedule=dict(threads=t, persistent=p, xcd_remap=x),
+                           rollout_steps=roll_steps, schedule=per_class,
                            hip_graph=True, autotune_ms=tuned_ms),
                roofline=roofline, cpu_baseline=cpu,
                search=dict(config="RockSample 15x15, 15 rocks, K=500, max depth 90, %.1f s planning step"

@@ -231,11 +231,20 @@ hdx_status hdx_batch_destroy(hdx_ctx *ctx, hdx_batch *batch);
 hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *batch, const hdx_leaf *leaves, int32_t n_leaves,
                                 hdx_stream stream);
 /* Launch schedule: workgroup size (multiple of 64; capped at 512 for
- * RockSample-only batches and 256 otherwise), persistent workgroups per CU
- * (0 = one workgroup per tile), and the XCD-contiguous tile mapping.
- * Results are bit-identical under every schedule. */
+ * RockSample-only batches and 256 otherwise, and at what a size class's
+ * leaves need), persistent workgroups per CU (0 = one workgroup per tile),
+ * and the XCD-contiguous tile mapping.  Tiles launch per size class of their
+ * leaf (class c holds leaves of 64*2^(c-1) < n <= 64*2^c scenarios, c =
+ * 0..5); set_schedule applies to every class, set_class_schedule to one.
+ * get_schedule reports the class with the most tiles.  Results are
+ * bit-identical under every schedule. */
+#define HDX_SIZE_CLASSES 6
 hdx_status hdx_batch_set_schedule(hdx_ctx *ctx, hdx_batch *batch, int32_t threads, int32_t persistent,
                                   int32_t xcd_remap);
+hdx_status hdx_batch_set_class_schedule(hdx_ctx *ctx, hdx_batch *batch, int32_t size_class, int32_t threads,
+                                        int32_t persistent, int32_t xcd_remap);
+hdx_status hdx_batch_get_class_schedule(const hdx_batch *batch, int32_t size_class, int32_t *threads,
+                                        int32_t *persistent, int32_t *xcd_remap, int64_t *tiles);
 hdx_status hdx_batch_get_schedule(const hdx_batch *batch, int32_t *threads, int32_t *persistent,
                                   int32_t *xcd_remap);
 /* Launch through a captured HIP graph (captured on first use and again
@@ -243,9 +252,10 @@ hdx_status hdx_batch_get_schedule(const hdx_batch *batch, int32_t *threads, int3
 hdx_status hdx_batch_use_graph(hdx_ctx *ctx, hdx_batch *batch, int32_t enable);
 /* Expand every staged leaf: one kernel launch (or graph replay), no copies. */
 hdx_status hdx_batch_launch(hdx_ctx *ctx, hdx_batch *batch, hdx_stream stream);
-/* Autotuner: time each candidate schedule `reps` times on the staged leaves
- * (an internal stream; blocks until done) and keep the fastest; *best_ms is
- * its mean launch time.  Outputs are rewritten with identical values. */
+/* Autotuner: per size class, time each candidate schedule `reps` times on
+ * that class's staged tiles (an internal stream; blocks until done) and keep
+ * the fastest; *best_ms is the sum of the classes' best mean launch times.
+ * Outputs are rewritten with identical values. */
 hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *batch, int32_t reps, float *best_ms);
 
 /* rollout_bounds (Eq. 12, 13 per scenario): for each of n states (device),

@@ -178,10 +178,15 @@ struct ClassPlan {
 };
 // Stable reorder of tiles[0, n_tiles) by class; fills plan.
 void plan_classes(const LeafTask *tasks, Tile *tiles, int64_t n_tiles, ClassPlan *plan);
-// One launch per non-empty class; lds_n[c] sizes class c's LDS (>= its n_max).
+// One launch per non-empty class in mask (bit c = class c); lds_n[c] sizes
+// class c's LDS (>= its n_max); sch[c] is its schedule (its width capped at
+// what the class's leaves need).
 hipError_t launch_classes(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queues, const ClassPlan &plan,
-                          const Variant &v, const int32_t *lds_n, const Schedule &sch, int32_t n_cu,
-                          hipStream_t stream);
+                          const Variant &v, const int32_t *lds_n, const Schedule *sch, int32_t n_cu,
+                          hipStream_t stream, uint32_t mask = 0xffffffffu);
+// Default schedule of a class whose largest leaf has n_max scenarios: two
+// scenarios per lane up to 256 lanes, one workgroup per tile, XCD-contiguous.
+Schedule class_default_schedule(int32_t n_max, int32_t max_threads);
 hipError_t configure_expand_kernels();
 
 // Up to kArgLeaves leaves passed by value in the kernel arguments.

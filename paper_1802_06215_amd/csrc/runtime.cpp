@@ -436,16 +436,24 @@ void hdx::plan_classes(const LeafTask *tasks, Tile *tiles, int64_t n_tiles, Clas
     for (const Tile &t : tmp) tiles[pos[size_class(tasks[t.leaf].n)]++] = t;
 }
 
+Schedule hdx::class_default_schedule(int32_t n_max, int32_t max_threads) {
+    Schedule s;
+    s.threads = std::min(std::max(64, pow2_at_least(std::max(n_max, 1)) / 2), std::min(256, max_threads));
+    s.persistent = 0;
+    s.xcd_remap = 1;
+    return s;
+}
+
 hipError_t hdx::launch_classes(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queues,
-                               const ClassPlan &plan, const Variant &v, const int32_t *lds_n, const Schedule &sch,
-                               int32_t n_cu, hipStream_t stream) {
+                               const ClassPlan &plan, const Variant &v, const int32_t *lds_n, const Schedule *sch,
+                               int32_t n_cu, hipStream_t stream, uint32_t mask) {
     for (int c = 0; c < kSizeClasses; ++c) {
-        if (plan.count[c] == 0) continue;
+        if (plan.count[c] == 0 || !(mask & (1u << c))) continue;
         Variant vc = v;
         vc.n_max = std::max(lds_n[c], plan.n_max[c]);
         // a workgroup no wider than the class's leaves need
         const int need = std::max(64, pow2_at_least(std::max(vc.n_max, 1)));
-        Schedule sc = sch;
+        Schedule sc = sch[c];
         if (sc.threads > need) sc.threads = need;
         const hipError_t e = launch_expand(d_tasks, d_tiles + plan.begin[c], d_queues + c, (int32_t)plan.count[c], vc,
                                            sc, n_cu, stream);
@@ -456,15 +464,6 @@ hipError_t hdx::launch_classes(const LeafTask *d_tasks, const Tile *d_tiles, Til
 
 namespace {
 
-Schedule default_schedule(const Variant &v) {
-    Schedule s;
-    int th = ((v.n_max + 63) / 64) * 64;
-    const int cap = variant_max_threads(v);
-    s.threads = th < 64 ? 64 : th > cap ? cap : th;
-    s.persistent = 0;
-    s.xcd_remap = 1;
-    return s;
-}
 
 hdx_status grow_pinned(hdx_ctx *ctx, LeafTask **h_tasks, LeafTask **d_tasks, int64_t *cap_tasks, Tile **h_tiles,
                        Tile **d_tiles, int64_t *cap_tiles, int64_t need_tasks, int64_t need_tiles) {
@@ -511,7 +510,8 @@ hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
         for (int32_t i = 0; i < n_leaves; ++i) pack.tile_begin[i + 1] = pack.tile_begin[i] + pack.t[i].n_actions;
         pack.n_leaves = n_leaves;
         pack.n_max = v0.n_max;
-        const Schedule sch = ctx->sched_fixed ? ctx->sched : default_schedule(v0);
+        const Schedule sch =
+            ctx->sched_fixed ? ctx->sched : class_default_schedule(v0.n_max, variant_max_threads(v0));
         pack.xcd_remap = sch.xcd_remap;
         hipError_t e = launch_expand_args(pack, v0, sch, (hipStream_t)stream);
         return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "expand launch");
@@ -537,8 +537,10 @@ hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
         e = hipMemcpyAsync(s.d_queue, s.h_queue, kSizeClasses * sizeof(TileQueue), hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return hip_fail(ctx, e, "descriptor copy");
     const Variant v = pick_variant(sh.has_rs, sh.has_ped, sh.ped_max, sh.n_max);
-    const Schedule sch = ctx->sched_fixed ? ctx->sched : default_schedule(v);
     const int32_t no_lds[kSizeClasses] = {0, 0, 0, 0, 0, 0};
+    Schedule sch[kSizeClasses];
+    for (int c = 0; c < kSizeClasses; ++c)
+        sch[c] = ctx->sched_fixed ? ctx->sched : class_default_schedule(plan.n_max[c], variant_max_threads(v));
     e = launch_classes(s.d_tasks, s.d_tiles, s.d_queue, plan, v, no_lds, sch, ctx->n_cu, hs);
     if (e != hipSuccess) return hip_fail(ctx, e, "expand launch");
     e = hipEventRecord(s.done, hs);
@@ -562,8 +564,8 @@ struct hdx_batch {
     int32_t lds_c[kSizeClasses] = {0, 0, 0, 0, 0, 0};  // per class: largest leaf seen
     ClassPlan g_plan{};
     int32_t g_lds[kSizeClasses] = {0, 0, 0, 0, 0, 0};
-    Schedule sched{256, 0, 1};
-    bool sched_set = false;
+    Schedule sched[kSizeClasses];  // per size class
+    bool sched_set[kSizeClasses] = {false, false, false, false, false, false};
     hipStream_t work = nullptr;  // capture and tuning stream
     hipEvent_t staged = nullptr, t0 = nullptr, t1 = nullptr;
     bool staged_used = false;
@@ -571,7 +573,7 @@ struct hdx_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     Variant g_var{0, 1, 1};
-    Schedule g_sched{0, 0, 0};
+    Schedule g_sched[kSizeClasses];
     int64_t g_tiles = 0;
 };
 
@@ -583,8 +585,13 @@ Variant batch_variant(const hdx_batch *b) {
     return v;
 }
 
-hipError_t batch_direct_launch(hdx_ctx *ctx, hdx_batch *b, const Schedule &s, hipStream_t st) {
-    return launch_classes(b->d_tasks, b->d_tiles, b->d_queue, b->plan, b->var, b->lds_c, s, ctx->n_cu, st);
+hipError_t batch_direct_launch(hdx_ctx *ctx, hdx_batch *b, const Schedule *s, hipStream_t st,
+                               uint32_t mask = 0xffffffffu) {
+    return launch_classes(b->d_tasks, b->d_tiles, b->d_queue, b->plan, b->var, b->lds_c, s, ctx->n_cu, st, mask);
+}
+
+bool same_schedule(const Schedule &a, const Schedule &b) {
+    return a.threads == b.threads && a.persistent == b.persistent && a.xcd_remap == b.xcd_remap;
 }
 
 void drop_graph(hdx_batch *b) {
@@ -675,7 +682,9 @@ hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *b, const hdx_leaf *leav
     b->n_tiles = sh.n_tiles;
     b->var = pick_variant(sh.has_rs, sh.has_ped, sh.ped_max, sh.n_max);
     if (sh.n_max > b->lds_n) b->lds_n = sh.n_max;
-    if (!b->sched_set) b->sched = default_schedule(batch_variant(b));
+    for (int c = 0; c < kSizeClasses; ++c)
+        if (!b->sched_set[c])
+            b->sched[c] = class_default_schedule(std::max(b->lds_c[c], 1), variant_max_threads(b->var));
     return HDX_OK;
 }
 
@@ -684,17 +693,44 @@ hdx_status hdx_batch_set_schedule(hdx_ctx *ctx, hdx_batch *b, int32_t threads, i
     if (!ctx || !b) return HDX_E_INVALID;
     if (threads < 64 || threads > 1024 || threads % 64 != 0 || persistent < 0 || persistent > 64)
         return fail(ctx, HDX_E_INVALID, "schedule");
-    b->sched = Schedule{threads, persistent, xcd_remap ? 1 : 0};
-    b->sched_set = true;
+    for (int c = 0; c < kSizeClasses; ++c) {
+        b->sched[c] = Schedule{threads, persistent, xcd_remap ? 1 : 0};
+        b->sched_set[c] = true;
+    }
+    return HDX_OK;
+}
+
+hdx_status hdx_batch_set_class_schedule(hdx_ctx *ctx, hdx_batch *b, int32_t cls, int32_t threads, int32_t persistent,
+                                        int32_t xcd_remap) {
+    if (!ctx || !b) return HDX_E_INVALID;
+    if (cls < 0 || cls >= kSizeClasses || threads < 64 || threads > 1024 || threads % 64 != 0 || persistent < 0 ||
+        persistent > 64)
+        return fail(ctx, HDX_E_INVALID, "schedule");
+    b->sched[cls] = Schedule{threads, persistent, xcd_remap ? 1 : 0};
+    b->sched_set[cls] = true;
+    return HDX_OK;
+}
+
+hdx_status hdx_batch_get_class_schedule(const hdx_batch *b, int32_t cls, int32_t *threads, int32_t *persistent,
+                                        int32_t *xcd_remap, int64_t *tiles) {
+    if (!b || !threads || !persistent || !xcd_remap || cls < 0 || cls >= kSizeClasses) return HDX_E_INVALID;
+    const Schedule &s = b->sched[cls];
+    const int32_t n_max = std::max(b->lds_c[cls], b->plan.n_max[cls]);
+    const int32_t need = std::max(64, pow2_at_least(std::max(n_max, 1)));
+    const int32_t cap = std::min(need, variant_max_threads(b->var));
+    *threads = s.threads > cap ? cap : s.threads;
+    *persistent = s.persistent;
+    *xcd_remap = s.xcd_remap;
+    if (tiles) *tiles = b->plan.count[cls];
     return HDX_OK;
 }
 
 hdx_status hdx_batch_get_schedule(const hdx_batch *b, int32_t *threads, int32_t *persistent, int32_t *xcd_remap) {
     if (!b || !threads || !persistent || !xcd_remap) return HDX_E_INVALID;
-    *threads = b->sched.threads > variant_max_threads(b->var) ? variant_max_threads(b->var) : b->sched.threads;
-    *persistent = b->sched.persistent;
-    *xcd_remap = b->sched.xcd_remap;
-    return HDX_OK;
+    int big = 0;
+    for (int c = 1; c < kSizeClasses; ++c)
+        if (b->plan.count[c] > b->plan.count[big]) big = c;
+    return hdx_batch_get_class_schedule(b, big, threads, persistent, xcd_remap, nullptr);
 }
 
 hdx_status hdx_batch_use_graph(hdx_ctx *ctx, hdx_batch *b, int32_t enable) {
@@ -718,12 +754,11 @@ hdx_status hdx_batch_launch(hdx_ctx *ctx, hdx_batch *b, hdx_stream stream) {
     bool classes_same = true;
     for (int c = 0; c < kSizeClasses; ++c)
         classes_same = classes_same && b->plan.begin[c] == b->g_plan.begin[c] && b->lds_c[c] == b->g_lds[c] &&
-                       (b->sched.persistent > 0 ? (b->plan.count[c] > 0) == (b->g_plan.count[c] > 0)
-                                                : b->plan.count[c] == b->g_plan.count[c]);
+                       same_schedule(b->sched[c], b->g_sched[c]) &&
+                       (b->sched[c].persistent > 0 ? (b->plan.count[c] > 0) == (b->g_plan.count[c] > 0)
+                                                   : b->plan.count[c] == b->g_plan.count[c]);
     const bool same = b->graph_ok && classes_same && v.mode == b->g_var.mode && v.pm == b->g_var.pm &&
-                      v.n_max == b->g_var.n_max && b->sched.threads == b->g_sched.threads &&
-                      b->sched.persistent == b->g_sched.persistent && b->sched.xcd_remap == b->g_sched.xcd_remap &&
-                      (b->sched.persistent > 0 || b->n_tiles == b->g_tiles);
+                      v.n_max == b->g_var.n_max;
     if (!same) {
         drop_graph(b);
         e = hipStreamBeginCapture(b->work, hipStreamCaptureModeThreadLocal);
@@ -739,10 +774,12 @@ hdx_status hdx_batch_launch(hdx_ctx *ctx, hdx_batch *b, hdx_stream stream) {
         }
         b->graph_ok = true;
         b->g_var = v;
-        b->g_sched = b->sched;
         b->g_tiles = b->n_tiles;
         b->g_plan = b->plan;
-        for (int c = 0; c < kSizeClasses; ++c) b->g_lds[c] = b->lds_c[c];
+        for (int c = 0; c < kSizeClasses; ++c) {
+            b->g_lds[c] = b->lds_c[c];
+            b->g_sched[c] = b->sched[c];
+        }
     }
     e = hipGraphLaunch(b->exec, hs);
     return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "graph launch");
@@ -755,33 +792,45 @@ hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *b, int32_t reps, float *b
     if (b->staged_used) hipEventSynchronize(b->staged);
     const Variant v = batch_variant(b);
     const int tmax = variant_max_threads(v);
-    std::vector<Schedule> cand;
-    for (int th = 64; th <= tmax; th *= 2) {
-        cand.push_back(Schedule{th, 0, 0});
-        cand.push_back(Schedule{th, 0, 1});
-        for (int p : {1, 2, 4, 8}) cand.push_back(Schedule{th, p, 0});
-    }
-    float best = 1e30f;
-    Schedule best_s = b->sched;
-    for (const Schedule &s : cand) {
-        hipError_t e = batch_direct_launch(ctx, b, s, b->work);  // warm-up
-        if (e == hipSuccess) e = hipEventRecord(b->t0, b->work);
-        for (int r = 0; r < reps && e == hipSuccess; ++r) e = batch_direct_launch(ctx, b, s, b->work);
-        if (e == hipSuccess) e = hipEventRecord(b->t1, b->work);
-        if (e == hipSuccess) e = hipEventSynchronize(b->t1);
-        if (e != hipSuccess) return hip_fail(ctx, e, "autotune launch");
-        float ms = 0.0f;
-        hipEventElapsedTime(&ms, b->t0, b->t1);
-        ms /= (float)reps;
-        if (ms < best) {
-            best = ms;
-            best_s = s;
+    // each size class is tuned on its own launch; the best schedules are kept
+    float total = 0.0f;
+    for (int c = 0; c < kSizeClasses; ++c) {
+        if (b->plan.count[c] == 0) continue;
+        const int32_t n_max = std::max(b->lds_c[c], b->plan.n_max[c]);
+        const int cap = std::min(tmax, std::max(64, pow2_at_least(std::max(n_max, 1))));
+        std::vector<Schedule> cand;
+        for (int th = 64; th <= cap; th *= 2) {
+            cand.push_back(Schedule{th, 0, 0});
+            cand.push_back(Schedule{th, 0, 1});
+            for (int p : {1, 2, 4, 8}) cand.push_back(Schedule{th, p, 0});
         }
+        float best = 1e30f;
+        Schedule trial[kSizeClasses];
+        for (int k = 0; k < kSizeClasses; ++k) trial[k] = b->sched[k];
+        Schedule best_s = b->sched[c];
+        for (const Schedule &s : cand) {
+            trial[c] = s;
+            const uint32_t mask = 1u << c;
+            hipError_t e = batch_direct_launch(ctx, b, trial, b->work, mask);  // warm-up
+            if (e == hipSuccess) e = hipEventRecord(b->t0, b->work);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = batch_direct_launch(ctx, b, trial, b->work, mask);
+            if (e == hipSuccess) e = hipEventRecord(b->t1, b->work);
+            if (e == hipSuccess) e = hipEventSynchronize(b->t1);
+            if (e != hipSuccess) return hip_fail(ctx, e, "autotune launch");
+            float ms = 0.0f;
+            hipEventElapsedTime(&ms, b->t0, b->t1);
+            ms /= (float)reps;
+            if (ms < best) {
+                best = ms;
+                best_s = s;
+            }
+        }
+        b->sched[c] = best_s;
+        b->sched_set[c] = true;
+        total += best;
     }
-    b->sched = best_s;
-    b->sched_set = true;
     drop_graph(b);
-    if (best_ms) *best_ms = best;
+    if (best_ms) *best_ms = total;
     return HDX_OK;
 }
 
