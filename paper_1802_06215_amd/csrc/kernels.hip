@@ -221,7 +221,7 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
             my_exp += Ops::terminal(st) ? 0 : 1;
             uint64_t z;
             Ops::template step<true>(M, st, a, id, (uint32_t)depth, RP.k0, RP.k1, r, z);
-            const float U = Ops::upper(M, st);
+            const float U = Ops::upper_wave(M, st);
             const int64_t pk = (int64_t)a * n + k;
             if (pair_out) Ops::store(M, sprime, pk, st);
             int ns = 0;

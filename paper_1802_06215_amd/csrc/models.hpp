@@ -105,6 +105,7 @@ struct RsOps {
         int32_t w;
     };
     static constexpr bool kHashObs = false;
+    static constexpr bool kSplitRollout = true;  // small step: one rollout loop per policy
 
     __device__ static void load(const MView &, const StatesPtr &S, int64_t p, State &st) { st.w = S.w[p]; }
     __device__ static void store(const MView &, const StatesPtr &S, int64_t p, const State &st) { S.w[p] = st.w; }
@@ -167,6 +168,29 @@ struct RsOps {
         return u + 10.0f * M.gpow_lane(M.h->grid - 1 - x);
     }
 
+    // The same value, bit for bit.  Robot cells are deterministic, so the
+    // live scenarios of a tile usually share one cell: then each rock's
+    // discounted reward is computed once per wavefront (scalar) and a lane
+    // only selects the terms of its good rocks (adding +0 for the others
+    // leaves the sum unchanged).  Called by every active lane of a wavefront.
+    __device__ static float upper_wave(const MView &M, const State &st) {
+        const bool live = !((st.w >> 30) & 1);
+        const int x = st.w & 31, y = (st.w >> 5) & 31;
+        const uint64_t lv = __ballot(live);
+        if (lv == 0) return 0.0f;
+        const int leader = __ffsll((unsigned long long)lv) - 1;
+        const int x0 = __shfl(x, leader, 64), y0 = __shfl(y, leader, 64);
+        if (__ballot(live && (x != x0 || y != y0)) != 0) return upper(M, st);
+        const int xs = __builtin_amdgcn_readfirstlane(x0), ys = __builtin_amdgcn_readfirstlane(y0);
+        float u = 0.0f;
+        for (int i = 0; i < M.h->n_rocks; ++i) {
+            const float c = 10.0f * M.gpow_uniform(abs(xs - M.h->rock_x[i]) + abs(ys - M.h->rock_y[i]));
+            u += ((st.w >> (10 + i)) & 1) ? c : 0.0f;
+        }
+        u = u + 10.0f * M.gpow_uniform(M.h->grid - 1 - xs);
+        return live ? u : 0.0f;
+    }
+
     __device__ static int default_action(const MView &, const State &) { return 2; }  // move east
 };
 
@@ -192,6 +216,7 @@ struct PedOps {
         int32_t goal[PM];
     };
     static constexpr bool kHashObs = true;
+    static constexpr bool kSplitRollout = false;  // large step: one loop keeps the code small
 
     __device__ static void load(const MView &M, const StatesPtr &S, int64_t p, State &st) {
         st.s = S.s[p];
@@ -319,6 +344,7 @@ struct PedOps {
         if (Ti > kHorizon) Ti = kHorizon;
         return M.h->r_goal * M.gpow_lane(Ti - 1);
     }
+    __device__ static float upper_wave(const MView &M, const State &st) { return upper(M, st); }
 
     __device__ static int default_action(const MView &M, const State &st) {
         bool brake = false;
@@ -341,20 +367,20 @@ struct RolloutParams {
 // Default-policy rollout from depth d0 (Eq. 13): discounted from d0, stops
 // at a terminal state or after min(max_steps, max_depth - d0) steps; the
 // tail value past the horizon is 0.  Accumulates in FP32 in step order.
-template <class Ops>
-__device__ __forceinline__ float rollout(const MView &M, const RolloutParams &P, typename Ops::State st,
-                                         uint32_t id, int d0, int &nsteps) {
-    int n_roll = P.max_steps;
-    if (P.max_depth >= 0 && P.max_depth - d0 < n_roll) n_roll = P.max_depth - d0;
-    if (n_roll > kHorizon) n_roll = kHorizon;  // the discount table's length
+// The loop is compiled once per policy, so the policy is not re-decided at
+// every step and a model whose default action is a constant (RockSample's
+// move east) steps through that action's code alone.
+template <class Ops, int POL>
+__device__ __forceinline__ float rollout_loop(const MView &M, const RolloutParams &P, typename Ops::State st,
+                                              uint32_t id, int d0, int n_roll, int &nsteps) {
     float value = 0.0f;
     for (int j = 0; j < n_roll; ++j) {
         if (Ops::terminal(st)) break;
         const uint32_t depth = (uint32_t)(d0 + j);
         int a;
-        if (P.policy == HDX_POLICY_CONST) {
+        if (POL == HDX_POLICY_CONST) {
             a = P.const_action;
-        } else if (P.policy == HDX_POLICY_RANDOM) {
+        } else if (POL == HDX_POLICY_RANDOM) {
             a = (int)(philox(id, depth, 0, kTagPolicy, P.k0, P.k1).x % (uint32_t)P.n_actions);
         } else {
             a = Ops::default_action(M, st);
@@ -366,6 +392,38 @@ __device__ __forceinline__ float rollout(const MView &M, const RolloutParams &P,
         ++nsteps;
     }
     return value;
+}
+
+template <class Ops>
+__device__ __forceinline__ float rollout(const MView &M, const RolloutParams &P, typename Ops::State st,
+                                         uint32_t id, int d0, int &nsteps) {
+    int n_roll = P.max_steps;
+    if (P.max_depth >= 0 && P.max_depth - d0 < n_roll) n_roll = P.max_depth - d0;
+    if (n_roll > kHorizon) n_roll = kHorizon;  // the discount table's length
+    if (!Ops::kSplitRollout) {
+        float value = 0.0f;
+        for (int j = 0; j < n_roll; ++j) {
+            if (Ops::terminal(st)) break;
+            const uint32_t depth = (uint32_t)(d0 + j);
+            int a;
+            if (P.policy == HDX_POLICY_CONST) {
+                a = P.const_action;
+            } else if (P.policy == HDX_POLICY_RANDOM) {
+                a = (int)(philox(id, depth, 0, kTagPolicy, P.k0, P.k1).x % (uint32_t)P.n_actions);
+            } else {
+                a = Ops::default_action(M, st);
+            }
+            float r;
+            uint64_t z;
+            Ops::template step<false>(M, st, a, id, depth, P.k0, P.k1, r, z);
+            value += M.gpow_uniform(j) * r;
+            ++nsteps;
+        }
+        return value;
+    }
+    if (P.policy == HDX_POLICY_CONST) return rollout_loop<Ops, HDX_POLICY_CONST>(M, P, st, id, d0, n_roll, nsteps);
+    if (P.policy == HDX_POLICY_RANDOM) return rollout_loop<Ops, HDX_POLICY_RANDOM>(M, P, st, id, d0, n_roll, nsteps);
+    return rollout_loop<Ops, HDX_POLICY_DEFAULT>(M, P, st, id, d0, n_roll, nsteps);
 }
 
 }  // namespace hdx

@@ -23,8 +23,25 @@ struct Slot {
     TileQueue *h_queue = nullptr, *d_queue = nullptr;
     int64_t cap_tasks = 0, cap_tiles = 0;
     hipEvent_t done = nullptr;
+    hipEvent_t fork = nullptr, join[kSizeClasses] = {};  // size classes run side by side
     bool used = false;
 };
+
+bool create_events(hipEvent_t *fork, hipEvent_t *join) {
+    if (hipEventCreateWithFlags(fork, hipEventDisableTiming) != hipSuccess) return false;
+    for (int c = 0; c < kSizeClasses; ++c)
+        if (hipEventCreateWithFlags(&join[c], hipEventDisableTiming) != hipSuccess) return false;
+    return true;
+}
+
+void destroy_events(hipEvent_t *fork, hipEvent_t *join) {
+    if (*fork) hipEventDestroy(*fork);
+    *fork = nullptr;
+    for (int c = 0; c < kSizeClasses; ++c) {
+        if (join[c]) hipEventDestroy(join[c]);
+        join[c] = nullptr;
+    }
+}
 
 uint64_t prob_threshold(double p) {
     if (p <= 0.0) return 0;
@@ -41,6 +58,7 @@ struct hdx_ctx {
     std::mutex mu;
     Slot slots[kSlots];
     int next_slot = 0;
+    hipStream_t cls_stream[kSizeClasses] = {};  // one stream per size class (default priority)
     Schedule sched{256, 0, 1};
     bool sched_fixed = false;
 };
@@ -74,20 +92,25 @@ hdx_status hdx_init(int32_t device, hdx_ctx **out) {
     hdx_ctx *ctx = new hdx_ctx();
     ctx->device = device;
     ctx->n_cu = prop.multiProcessorCount;
+    for (int c = 0; c < kSizeClasses; ++c)
+        if (hipStreamCreateWithFlags(&ctx->cls_stream[c], hipStreamNonBlocking) != hipSuccess) {
+            hdx_fini(ctx);
+            return HDX_E_DEVICE;
+        }
     for (auto &s : ctx->slots) {
-        if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
-            delete ctx;
+        if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess || !create_events(&s.fork, s.join)) {
+            hdx_fini(ctx);
             return HDX_E_DEVICE;
         }
         if (hipMalloc(&s.d_queue, kSizeClasses * sizeof(TileQueue)) != hipSuccess ||
             hipHostMalloc(&s.h_queue, kSizeClasses * sizeof(TileQueue)) != hipSuccess ||
             hipMemset(s.d_queue, 0, kSizeClasses * sizeof(TileQueue)) != hipSuccess) {
-            delete ctx;
+            hdx_fini(ctx);
             return HDX_E_NOMEM;
         }
     }
     if (configure_expand_kernels() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
-        delete ctx;
+        hdx_fini(ctx);
         return HDX_E_DEVICE;
     }
     *out = ctx;
@@ -106,7 +129,10 @@ hdx_status hdx_fini(hdx_ctx *ctx) {
         if (s.d_queue) hipFree(s.d_queue);
         if (s.h_queue) hipHostFree(s.h_queue);
         if (s.done) hipEventDestroy(s.done);
+        destroy_events(&s.fork, s.join);
     }
+    for (int c = 0; c < kSizeClasses; ++c)
+        if (ctx->cls_stream[c]) hipStreamDestroy(ctx->cls_stream[c]);
     delete ctx;
     return HDX_OK;
 }
@@ -464,6 +490,30 @@ hipError_t hdx::launch_classes(const LeafTask *d_tasks, const Tile *d_tiles, Til
 
 namespace {
 
+// Each non-empty class of `mask` on its own stream, forked from `st` and
+// joined back into it (inside a stream capture this becomes parallel graph
+// branches), so one class's slow tail overlaps the others; a single class
+// launches on `st` directly.
+hipError_t launch_classes_forked(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queues,
+                                 const ClassPlan &plan, const Variant &v, const int32_t *lds_n, const Schedule *sch,
+                                 int32_t n_cu, hipStream_t st, const hipStream_t *cls, hipEvent_t fork,
+                                 const hipEvent_t *join, uint32_t mask = 0xffffffffu) {
+    int active = 0;
+    for (int c = 0; c < kSizeClasses; ++c)
+        if (plan.count[c] > 0 && (mask & (1u << c))) ++active;
+    if (active <= 1) return launch_classes(d_tasks, d_tiles, d_queues, plan, v, lds_n, sch, n_cu, st, mask);
+    hipError_t e = hipEventRecord(fork, st);
+    // largest class first: its tail is the longest
+    for (int c = kSizeClasses - 1; c >= 0 && e == hipSuccess; --c) {
+        if (plan.count[c] == 0 || !(mask & (1u << c))) continue;
+        e = hipStreamWaitEvent(cls[c], fork, 0);
+        if (e == hipSuccess) e = launch_classes(d_tasks, d_tiles, d_queues, plan, v, lds_n, sch, n_cu, cls[c], 1u << c);
+        if (e == hipSuccess) e = hipEventRecord(join[c], cls[c]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, join[c], 0);
+    }
+    return e;
+}
+
 
 hdx_status grow_pinned(hdx_ctx *ctx, LeafTask **h_tasks, LeafTask **d_tasks, int64_t *cap_tasks, Tile **h_tiles,
                        Tile **d_tiles, int64_t *cap_tiles, int64_t need_tasks, int64_t need_tiles) {
@@ -541,7 +591,8 @@ hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
     Schedule sch[kSizeClasses];
     for (int c = 0; c < kSizeClasses; ++c)
         sch[c] = ctx->sched_fixed ? ctx->sched : class_default_schedule(plan.n_max[c], variant_max_threads(v));
-    e = launch_classes(s.d_tasks, s.d_tiles, s.d_queue, plan, v, no_lds, sch, ctx->n_cu, hs);
+    e = launch_classes_forked(s.d_tasks, s.d_tiles, s.d_queue, plan, v, no_lds, sch, ctx->n_cu, hs, ctx->cls_stream,
+                              s.fork, s.join);
     if (e != hipSuccess) return hip_fail(ctx, e, "expand launch");
     e = hipEventRecord(s.done, hs);
     s.used = true;
@@ -567,6 +618,8 @@ struct hdx_batch {
     Schedule sched[kSizeClasses];  // per size class
     bool sched_set[kSizeClasses] = {false, false, false, false, false, false};
     hipStream_t work = nullptr;  // capture and tuning stream
+    hipStream_t cls[kSizeClasses] = {};  // size classes side by side
+    hipEvent_t fork = nullptr, join[kSizeClasses] = {};
     hipEvent_t staged = nullptr, t0 = nullptr, t1 = nullptr;
     bool staged_used = false;
     bool graph_on = false, graph_ok = false;
@@ -587,7 +640,8 @@ Variant batch_variant(const hdx_batch *b) {
 
 hipError_t batch_direct_launch(hdx_ctx *ctx, hdx_batch *b, const Schedule *s, hipStream_t st,
                                uint32_t mask = 0xffffffffu) {
-    return launch_classes(b->d_tasks, b->d_tiles, b->d_queue, b->plan, b->var, b->lds_c, s, ctx->n_cu, st, mask);
+    return launch_classes_forked(b->d_tasks, b->d_tiles, b->d_queue, b->plan, b->var, b->lds_c, s, ctx->n_cu, st,
+                                 b->cls, b->fork, b->join, mask);
 }
 
 bool same_schedule(const Schedule &a, const Schedule &b) {
@@ -618,10 +672,14 @@ hdx_status hdx_batch_create(hdx_ctx *ctx, int32_t max_leaves, int64_t max_tiles,
         (hipHostMalloc(&b->h_queue, kSizeClasses * sizeof(TileQueue)) != hipSuccess ||
          hipMalloc(&b->d_queue, kSizeClasses * sizeof(TileQueue)) != hipSuccess ||
          hipMemset(b->d_queue, 0, kSizeClasses * sizeof(TileQueue)) != hipSuccess ||
-         hipStreamCreateWithFlags(&b->work, hipStreamNonBlocking) != hipSuccess ||
+         hipStreamCreateWithFlags(&b->work, hipStreamNonBlocking) != hipSuccess || !create_events(&b->fork, b->join) ||
          hipEventCreate(&b->staged) != hipSuccess || hipEventCreate(&b->t0) != hipSuccess ||
-         hipEventCreate(&b->t1) != hipSuccess || hipDeviceSynchronize() != hipSuccess))
+         hipEventCreate(&b->t1) != hipSuccess))
         st = fail(ctx, HDX_E_NOMEM, "batch allocation");
+    for (int c = 0; c < kSizeClasses && st == HDX_OK; ++c)
+        if (hipStreamCreateWithFlags(&b->cls[c], hipStreamNonBlocking) != hipSuccess)
+            st = fail(ctx, HDX_E_NOMEM, "batch streams");
+    if (st == HDX_OK && hipDeviceSynchronize() != hipSuccess) st = fail(ctx, HDX_E_DEVICE, "batch allocation");
     if (st != HDX_OK) {
         hdx_batch_destroy(ctx, b);
         return st;
@@ -642,6 +700,9 @@ hdx_status hdx_batch_destroy(hdx_ctx *ctx, hdx_batch *b) {
     if (b->d_tiles) hipFree(b->d_tiles);
     if (b->d_queue) hipFree(b->d_queue);
     if (b->work) hipStreamDestroy(b->work);
+    for (int c = 0; c < kSizeClasses; ++c)
+        if (b->cls[c]) hipStreamDestroy(b->cls[c]);
+    destroy_events(&b->fork, b->join);
     if (b->staged) hipEventDestroy(b->staged);
     if (b->t0) hipEventDestroy(b->t0);
     if (b->t1) hipEventDestroy(b->t1);
