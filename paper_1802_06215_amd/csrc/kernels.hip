@@ -171,14 +171,16 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
     int32_t *scan_scratch = misc + 48;
     const int H = Ly.h;
 
-    for (int h = tid; h < H; h += nt) tab[h] = kEmptyKey;
+    if constexpr (!Ops::kSmallObs)
+        for (int h = tid; h < H; h += nt) tab[h] = kEmptyKey;
     if (tid == 0) {
         misc[0] = 0;
         misc[1] = 0;
+        misc[2] = 0;
         stepc[0] = 0;
         stepc[1] = 0;
     }
-    stage_gpow(T->model, gpow_lds);
+    if constexpr (Ops::kLdsModel) stage_gpow(T->model, gpow_lds);
     __syncthreads();
 
     RolloutParams RP;
@@ -253,66 +255,94 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
         atomicAdd(&stepc[1], (unsigned long long)my_roll);
     }
 
-    // -- LDS hash of the observations ----------------------------------------
-    for (int k = tid; k < n; k += nt) {
-        const uint64_t z = zk[k];
-        int slot;
-        if (z == kEmptyKey) {
-            slot = H;
-            misc[1] = 1;
-        } else {
-            int h = (int)(mix_key(z) & (uint64_t)(H - 1));
-            for (;;) {
-                const unsigned long long old = atomicCAS((unsigned long long *)&tab[h], kEmptyKey, z);
-                if (old == kEmptyKey || old == z) break;
-                h = (h + 1) & (H - 1);
-            }
-            slot = h;
+    int D;
+    if constexpr (Ops::kSmallObs) {
+        // -- small observation alphabet (every key below 32) ---------------------
+        // presence mask by wavefront OR plus one LDS atomic per wavefront; the
+        // child of a key is the rank of its bit, which is ascending key order
+        uint32_t m = 0;
+        for (int k = tid; k < n; k += nt) m |= 1u << (uint32_t)zk[k];
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) m |= (uint32_t)__shfl_xor((int)m, d, 64);
+        if (lane == 0 && m) atomicOr((unsigned int *)&misc[2], m);
+        __syncthreads();
+        const uint32_t mask = (uint32_t)misc[2];
+        D = __popc(mask);
+        for (int i = tid; i < D && i < cap; i += nt) {
+            uint32_t mm = mask;
+            for (int q = 0; q < i; ++q) mm &= mm - 1u;  // drop the i lowest keys
+            T->child_z[(int64_t)a * cap + i] = (uint64_t)(__ffs(mm) - 1);
         }
-        child[k] = slot;
-    }
-    __syncthreads();
-
-    // -- distinct observations, sorted ascending -----------------------------
-    uint64_t *dkey = zk;
-    for (int h = tid; h <= H; h += nt) {
-        const bool occupied = (h < H) ? (tab[h] != kEmptyKey) : (misc[1] != 0);
-        if (occupied) {
-            const int i = atomicAdd(&misc[0], 1);
-            dkey[i] = (h < H) ? tab[h] : kEmptyKey;
-            dslot[i] = (uint32_t)h;
+        if (tid == 0) T->n_children[a] = D;
+        for (int k = tid; k < n; k += nt) {
+            const int c = __popc(mask & ((1u << (uint32_t)zk[k]) - 1u));
+            child[k] = c;
+            if (T->child_of) T->child_of[(int64_t)a * n + k] = c;
         }
-    }
-    __syncthreads();
-    const int D = misc[0];
-    if (D <= 64) {
-        if (wid == 0) wave_sort_pairs(dkey, dslot, D);
         __syncthreads();
     } else {
-        const int p = pow2_at_least(D);
-        for (int i = D + tid; i < p; i += nt) {
-            dkey[i] = kEmptyKey;
-            dslot[i] = 0xFFFFFFFFu;
+        // -- LDS hash of the observations ----------------------------------------
+        for (int k = tid; k < n; k += nt) {
+            const uint64_t z = zk[k];
+            int slot;
+            if (z == kEmptyKey) {
+                slot = H;
+                misc[1] = 1;
+            } else {
+                int h = (int)(mix_key(z) & (uint64_t)(H - 1));
+                for (;;) {
+                    const unsigned long long old = atomicCAS((unsigned long long *)&tab[h], kEmptyKey, z);
+                    if (old == kEmptyKey || old == z) break;
+                    h = (h + 1) & (H - 1);
+                }
+                slot = h;
+            }
+            child[k] = slot;
         }
         __syncthreads();
-        block_sort_pairs(dkey, dslot, p);
-    }
 
-    // -- child index of each scenario -----------------------------------------
-    // rank_of_slot overlays the hash table; the distinct keys stay in zkey
-    int32_t *rank_of_slot = (int32_t *)tab;
-    for (int i = tid; i < D; i += nt) {
-        rank_of_slot[dslot[i]] = i;
-        if (i < cap) T->child_z[(int64_t)a * cap + i] = dkey[i];
+        // -- distinct observations, sorted ascending -----------------------------
+        uint64_t *dkey = zk;
+        for (int h = tid; h <= H; h += nt) {
+            const bool occupied = (h < H) ? (tab[h] != kEmptyKey) : (misc[1] != 0);
+            if (occupied) {
+                const int i = atomicAdd(&misc[0], 1);
+                dkey[i] = (h < H) ? tab[h] : kEmptyKey;
+                dslot[i] = (uint32_t)h;
+            }
+        }
+        __syncthreads();
+        D = misc[0];
+        if (D <= 64) {
+            if (wid == 0) wave_sort_pairs(dkey, dslot, D);
+            __syncthreads();
+        } else {
+            const int p = pow2_at_least(D);
+            for (int i = D + tid; i < p; i += nt) {
+                dkey[i] = kEmptyKey;
+                dslot[i] = 0xFFFFFFFFu;
+            }
+            __syncthreads();
+            block_sort_pairs(dkey, dslot, p);
+        }
+
+        // -- child index of each scenario -----------------------------------------
+        // rank_of_slot overlays the hash table; the distinct keys stay in zkey
+        int32_t *rank_of_slot = (int32_t *)tab;
+        for (int i = tid; i < D; i += nt) {
+            rank_of_slot[dslot[i]] = i;
+            if (i < cap) T->child_z[(int64_t)a * cap + i] = dkey[i];
+        }
+        if (tid == 0) T->n_children[a] = D;
+        __syncthreads();
+        for (int k = tid; k < n; k += nt) {
+            const int c = rank_of_slot[child[k]];
+            child[k] = c;
+            if (T->child_of) T->child_of[(int64_t)a * n + k] = c;
+        }
+        __syncthreads();
+
     }
-    if (tid == 0) T->n_children[a] = D;
-    __syncthreads();
-    for (int k = tid; k < n; k += nt) {
-        const int c = rank_of_slot[child[k]];
-        child[k] = c;
-        if (T->child_of) T->child_of[(int64_t)a * n + k] = c;
-    }
-    __syncthreads();
 
     // -- stable grouping: position of each scenario in perm --------------------
     const int nchunks = (n + 63) >> 6;

@@ -17,11 +17,11 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even; NaN stays NaN
+    const uint32_t u = __float_as_uint(f);
+    const uint32_t rn = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    const uint32_t special = (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);  // Inf, NaN
+    return (uint16_t)(((u & 0x7f800000u) == 0x7f800000u) ? special : rn);
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -110,119 +110,133 @@ __global__ __launch_bounds__(256) void gemm_bf16(int M, int N, int K, const uint
 }
 
 // ---- fused forward --------------------------------------------------------
-// One workgroup of four wavefronts takes kFR rows.  The layer input (X, then
-// H1, H2) sits in LDS; wavefront w computes output columns [64w, 64w + 64)
-// of every row, its B fragments read straight from the transposed BF16
-// weights (each wavefront reads a distinct quarter of a matrix, so a
-// workgroup reads every weight once per layer).  The output layer sums each
-// row's 256 products over lanes and then wavefronts in a fixed order, so a
-// row's value does not depend on the other rows.
-constexpr int kFR = 128, kHP = kMlpHidden + 8;
+// One workgroup of eight wavefronts takes kFR = 128 rows.  The layer input
+// (X, then H1, H2) sits in LDS; wavefront w computes rows [64 (w / 4), +64)
+// x columns [64 (w % 4), +64) with 16x16x32 BF16 MFMAs, its weight
+// fragments read straight from the transposed BF16 weights.  The MFMA is
+// fed (weights, activations), i.e. it produces the transposed tile, so a
+// lane ends up holding four consecutive output columns of one row: the
+// epilogue (bias, ReLU, BF16) writes them as one 8-byte LDS store.  The
+// output layer sums each row's 256 products over a lane's 16 columns, the
+// four lanes of the row, then the four column wavefronts, in a fixed order,
+// so a row's value does not depend on the other rows.
+constexpr int kFR = 128, kHP = kMlpHidden + 8, kFwdThreads = 512;
 
+// acc[i][j][r] = output (row rb + 16 i + q, column nb + 16 j + 4 g + r)
 template <int K>
-__device__ __forceinline__ void fused_layer(const uint16_t (*Hs)[kHP], const uint16_t *__restrict__ wt, int nb,
-                                            int lane, f32x4 (&acc)[8][4]) {
+__device__ __forceinline__ void fused_layer(const uint16_t (*Hs)[kHP], const uint16_t *__restrict__ wt, int rb,
+                                            int nb, int lane, f32x4 (&acc)[4][4]) {
     const int g = lane >> 4, q = lane & 15;
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const uint16_t *wrow = wt + (size_t)(nb + q) * K + g * 8;
-    bf16x8 b[4], bn[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) b[j] = *(const bf16x8 *)(wrow + (size_t)j * 16 * K);
-#pragma unroll
+#pragma unroll 2
     for (int k0 = 0; k0 < K; k0 += 32) {
-        if (k0 + 32 < K) {
+        bf16x8 b[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bn[j] = *(const bf16x8 *)(wrow + (size_t)j * 16 * K + k0 + 32);
-        }
+        for (int j = 0; j < 4; ++j) b[j] = *(const bf16x8 *)(wrow + (size_t)j * 16 * K + k0);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const bf16x8 a = *(const bf16x8 *)&Hs[i * 16 + q][k0 + g * 8];
+        for (int i = 0; i < 4; ++i) {
+            const bf16x8 a = *(const bf16x8 *)&Hs[rb + i * 16 + q][k0 + g * 8];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
-        }
-        if (k0 + 32 < K) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = bn[j];
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], a, acc[i][j], 0, 0, 0);
         }
     }
 }
 
-// h = bf16(relu(acc + bias)) into LDS (and to Hout when given)
-__device__ __forceinline__ void fused_store(uint16_t (*Hs)[kHP], const f32x4 (&acc)[8][4], const float *bias, int nb,
-                                            int lane, uint16_t *Hout, int64_t r0, int64_t n) {
+// BF16 of a finite or infinite non-negative value (post-ReLU), nearest even
+__device__ __forceinline__ uint32_t f2bf_pos(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+// h = bf16(relu(acc + bias)) into LDS (and, when STORE, to Hout)
+template <bool STORE>
+__device__ __forceinline__ void fused_store(uint16_t (*Hs)[kHP], const f32x4 (&acc)[4][4], const float *__restrict__ bias,
+                                            int rb, int nb, int lane, uint16_t *Hout, int64_t r0, int64_t n) {
     const int g = lane >> 4, q = lane & 15;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int col = nb + j * 16 + q;
-        const float bv = bias[col];
+        const int col = nb + j * 16 + g * 4;
+        const float4 bv = *(const float4 *)(bias + col);
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = i * 16 + g * 4 + r;
-                const float z = acc[i][j][r] + bv;
-                const uint16_t h = f2bf(z > 0.f ? z : 0.f);
-                Hs[row][col] = h;
-                if (Hout && r0 + row < n) Hout[(r0 + row) * kMlpHidden + col] = h;
-            }
+        for (int i = 0; i < 4; ++i) {
+            const int row = rb + i * 16 + q;
+            const uint32_t h0 = f2bf_pos(fmaxf(acc[i][j][0] + bv.x, 0.f));
+            const uint32_t h1 = f2bf_pos(fmaxf(acc[i][j][1] + bv.y, 0.f));
+            const uint32_t h2 = f2bf_pos(fmaxf(acc[i][j][2] + bv.z, 0.f));
+            const uint32_t h3 = f2bf_pos(fmaxf(acc[i][j][3] + bv.w, 0.f));
+            const uint2 v = make_uint2(h0 | (h1 << 16), h2 | (h3 << 16));
+            *(uint2 *)&Hs[row][col] = v;
+            if (STORE && r0 + row < n) *(uint2 *)(Hout + (r0 + row) * kMlpHidden + col) = v;
+        }
     }
 }
 
-__global__ __launch_bounds__(256) void mlp_fused_fwd(const uint16_t *__restrict__ X, int64_t n, const MlpDev P,
-                                                     float *__restrict__ y, uint16_t *H1, uint16_t *H2, uint16_t *H3) {
+// STORE: also write H1..H3 (training); the inference form writes only y.
+template <bool STORE>
+__global__ __launch_bounds__(kFwdThreads, 4) void mlp_fused_fwd(const uint16_t *__restrict__ X, int64_t n,
+                                                             const MlpDev P, float *__restrict__ y, uint16_t *H1,
+                                                             uint16_t *H2, uint16_t *H3) {
     __shared__ __align__(16) uint16_t Hs[kFR][kHP];
     __shared__ float yp[4][kFR];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, q = lane & 15;
     const int64_t r0 = (int64_t)blockIdx.x * kFR;
-    const int nb = wave * 64;
+    const int rb = (wave >> 2) * 64, cw = wave & 3, nb = cw * 64;
     constexpr int kV = kMlpIn / 8;  // uint4 per input row
-    for (int i = tid; i < kFR * kV; i += 256) {
+    for (int i = tid; i < kFR * kV; i += kFwdThreads) {
         const int r = i / kV, c = (i % kV) * 8;
         uint4 v = make_uint4(0, 0, 0, 0);
         if (r0 + r < n) v = *(const uint4 *)(X + (r0 + r) * kMlpIn + c);
         *(uint4 *)&Hs[r][c] = v;
     }
     __syncthreads();
-    f32x4 acc[8][4];
-    fused_layer<kMlpIn>(Hs, P.w1t, nb, lane, acc);
+    f32x4 acc[4][4];
+    fused_layer<kMlpIn>(Hs, P.w1t, rb, nb, lane, acc);
     __syncthreads();
-    fused_store(Hs, acc, P.b1, nb, lane, H1, r0, n);
+    fused_store<STORE>(Hs, acc, P.b1, rb, nb, lane, H1, r0, n);
     __syncthreads();
-    fused_layer<kMlpHidden>(Hs, P.w2t, nb, lane, acc);
+    fused_layer<kMlpHidden>(Hs, P.w2t, rb, nb, lane, acc);
     __syncthreads();
-    fused_store(Hs, acc, P.b2, nb, lane, H2, r0, n);
+    fused_store<STORE>(Hs, acc, P.b2, rb, nb, lane, H2, r0, n);
     __syncthreads();
-    fused_layer<kMlpHidden>(Hs, P.w3t, nb, lane, acc);
+    fused_layer<kMlpHidden>(Hs, P.w3t, rb, nb, lane, acc);
     // output layer: y = bf16(h3) . bf16(w4) + b4
-    float w4v[4], b3v[4];
+    float rowsum[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        w4v[j] = bf2f(P.w4b[nb + j * 16 + q]);
-        b3v[j] = P.b3[nb + j * 16 + q];
+        const int col = nb + j * 16 + g * 4;
+        const float4 bv = *(const float4 *)(P.b3 + col);
+        const uint2 wv = *(const uint2 *)(P.w4b + col);
+        const float w0 = __uint_as_float(wv.x << 16), w1 = __uint_as_float(wv.x & 0xffff0000u);
+        const float w2 = __uint_as_float(wv.y << 16), w3 = __uint_as_float(wv.y & 0xffff0000u);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = rb + i * 16 + q;
+            const uint32_t h0 = f2bf_pos(fmaxf(acc[i][j][0] + bv.x, 0.f));
+            const uint32_t h1 = f2bf_pos(fmaxf(acc[i][j][1] + bv.y, 0.f));
+            const uint32_t h2 = f2bf_pos(fmaxf(acc[i][j][2] + bv.z, 0.f));
+            const uint32_t h3 = f2bf_pos(fmaxf(acc[i][j][3] + bv.w, 0.f));
+            if (STORE && r0 + row < n)
+                *(uint2 *)(H3 + (r0 + row) * kMlpHidden + col) = make_uint2(h0 | (h1 << 16), h2 | (h3 << 16));
+            float s = rowsum[i];
+            s += __uint_as_float(h0 << 16) * w0;
+            s += __uint_as_float(h1 << 16) * w1;
+            s += __uint_as_float(h2 << 16) * w2;
+            s += __uint_as_float(h3 << 16) * w3;
+            rowsum[i] = s;
+        }
     }
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = i * 16 + g * 4 + r;
-            float s = 0.f;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float z = acc[i][j][r] + b3v[j];
-                const uint16_t h = f2bf(z > 0.f ? z : 0.f);
-                if (H3 && r0 + row < n) H3[(r0 + row) * kMlpHidden + nb + j * 16 + q] = h;
-                s += bf2f(h) * w4v[j];
-            }
-            s += __shfl_xor(s, 1, 64);
-            s += __shfl_xor(s, 2, 64);
-            s += __shfl_xor(s, 4, 64);
-            s += __shfl_xor(s, 8, 64);
-            if (q == 0) yp[wave][row] = s;
-        }
+    for (int i = 0; i < 4; ++i) {
+        float s = rowsum[i];
+        s += __shfl_xor(s, 16, 64);
+        s += __shfl_xor(s, 32, 64);
+        if (g == 0) yp[cw][rb + i * 16 + q] = s;
+    }
     __syncthreads();
     if (tid < kFR && r0 + tid < n) y[r0 + tid] = (((yp[0][tid] + yp[1][tid]) + yp[2][tid]) + yp[3][tid]) + P.b4[0];
 }
@@ -339,7 +353,7 @@ __device__ __forceinline__ float rs_feature(const HDX_CONST ModelHdr *M, int32_t
     if (J == 2) return (float)((w >> 30) & 1);
     if (J == 3) return remain;
     const int m = M->n_rocks, i = J - 4;
-    if (i < m) return (float)((w >> (10 + i)) & 1);
+    if (i < m) return (float)((w >> ((10 + i) & 31)) & 1);  // i < m <= 20
     if (i < 2 * m) return (float)(M->rock_x[i - m] - x) * inv;
     if (i < 3 * m) return (float)(M->rock_y[i - 2 * m] - y) * inv;
     return 0.f;
@@ -476,7 +490,12 @@ hipError_t mlp_forward(const MlpDev &P, const uint16_t *X, int64_t n, uint16_t *
     if (n <= 0) return hipSuccess;
     const int64_t blocks = (n + kFR - 1) / kFR;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(mlp_fused_fwd, dim3((unsigned)blocks), dim3(256), 0, s, X, n, P, y, H1, H2, H3);
+    if (H1 && H2 && H3)
+        hipLaunchKernelGGL(mlp_fused_fwd<true>, dim3((unsigned)blocks), dim3(kFwdThreads), 0, s, X, n, P, y, H1, H2,
+                           H3);
+    else
+        hipLaunchKernelGGL(mlp_fused_fwd<false>, dim3((unsigned)blocks), dim3(kFwdThreads), 0, s, X, n, P, y,
+                           nullptr, nullptr, nullptr);
     return hipGetLastError();
 }
 

@@ -106,6 +106,8 @@ struct RsOps {
     };
     static constexpr bool kHashObs = false;
     static constexpr bool kSplitRollout = true;  // small step: one rollout loop per policy
+    static constexpr bool kSmallObs = true;       // observations 0 (none), 1, 2 (sensor readings)
+    static constexpr bool kLdsModel = false;      // expansion reads no per-lane table from LDS
 
     __device__ static void load(const MView &, const StatesPtr &S, int64_t p, State &st) { st.w = S.w[p]; }
     __device__ static void store(const MView &, const StatesPtr &S, int64_t p, const State &st) { S.w[p] = st.w; }
@@ -180,7 +182,15 @@ struct RsOps {
         if (lv == 0) return 0.0f;
         const int leader = __ffsll((unsigned long long)lv) - 1;
         const int x0 = __shfl(x, leader, 64), y0 = __shfl(y, leader, 64);
-        if (__ballot(live && (x != x0 || y != y0)) != 0) return upper(M, st);
+        if (__ballot(live && (x != x0 || y != y0)) != 0) {
+            // cells differ: per-lane terms, discount powers read from the model table
+            if (!live) return 0.0f;
+            float u = 0.0f;
+            for (int i = 0; i < M.h->n_rocks; ++i)
+                if ((st.w >> (10 + i)) & 1)
+                    u += 10.0f * M.gg[abs(x - M.h->rock_x[i]) + abs(y - M.h->rock_y[i])];
+            return u + 10.0f * M.gg[M.h->grid - 1 - x];
+        }
         const int xs = __builtin_amdgcn_readfirstlane(x0), ys = __builtin_amdgcn_readfirstlane(y0);
         float u = 0.0f;
         for (int i = 0; i < M.h->n_rocks; ++i) {
@@ -217,6 +227,8 @@ struct PedOps {
     };
     static constexpr bool kHashObs = true;
     static constexpr bool kSplitRollout = false;  // large step: one loop keeps the code small
+    static constexpr bool kSmallObs = false;      // 64-bit hashed observations
+    static constexpr bool kLdsModel = true;       // discount powers and goal points staged in LDS
 
     __device__ static void load(const MView &M, const StatesPtr &S, int64_t p, State &st) {
         st.s = S.s[p];
