@@ -252,10 +252,12 @@ hdx_status hdx_batch_get_schedule(const hdx_batch *batch, int32_t *threads, int3
 hdx_status hdx_batch_use_graph(hdx_ctx *ctx, hdx_batch *batch, int32_t enable);
 /* Expand every staged leaf: one kernel launch (or graph replay), no copies. */
 hdx_status hdx_batch_launch(hdx_ctx *ctx, hdx_batch *batch, hdx_stream stream);
-/* Autotuner: per size class, time each candidate schedule `reps` times on
- * that class's staged tiles (an internal stream; blocks until done) and keep
- * the fastest; *best_ms is the sum of the classes' best mean launch times.
- * Outputs are rewritten with identical values. */
+/* Autotuner (an internal stream; blocks until done): per size class, time
+ * each candidate schedule `reps` times on that class's staged tiles alone;
+ * then, as the classes run side by side, refine each class's schedule once
+ * more against the whole launch.  *best_ms is the mean time of the chosen
+ * whole launch (of the single class when there is one).  Outputs are
+ * rewritten with identical values. */
 hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *batch, int32_t reps, float *best_ms);
 
 /* rollout_bounds (Eq. 12, 13 per scenario): for each of n states (device),

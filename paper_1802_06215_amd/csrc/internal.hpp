@@ -111,6 +111,7 @@ struct Schedule {
 struct LdsLayout {
     uint32_t zkey, tab, dslot, off, ubuf, lbuf, child, perm, misc, gpow, total;
     int32_t np, p2, h, table_cap;
+    int32_t small;  // small-alphabet carve-up: no hash table, chunk counts in tab
 };
 
 __host__ __device__ inline int32_t pow2_at_least(int32_t v) {
@@ -119,10 +120,15 @@ __host__ __device__ inline int32_t pow2_at_least(int32_t v) {
     return p;
 }
 
-__host__ __device__ inline LdsLayout make_layout(int32_t np) {
+// small: every observation key is below 32 and no model table is staged
+// (RockSample-only launches): no hash table; the per-chunk child counts get
+// a region of their own (32 per 64-scenario chunk) and the child sizes one
+// of 32 entries, so the tile needs about 60% of the general carve-up.
+__host__ __device__ inline LdsLayout make_layout(int32_t np, bool small = false) {
     LdsLayout L;
     if (np < 1) np = 1;
     L.np = np;
+    L.small = small ? 1 : 0;
     L.p2 = pow2_at_least(np) < 64 ? 64 : pow2_at_least(np);
     L.h = pow2_at_least(2 * np) < 64 ? 64 : pow2_at_least(2 * np);
     uint32_t o = 0;
@@ -132,16 +138,23 @@ __host__ __device__ inline LdsLayout make_layout(int32_t np) {
         return at;
     };
     L.zkey = take(8u * L.p2);
-    L.tab = take(8u * L.h + 16u);
-    L.table_cap = (int32_t)((8u * L.p2 + 8u * L.h + 16u) / 4u);
-    L.dslot = take(4u * L.p2);
+    if (small) {
+        const uint32_t chunks = (uint32_t)((np + 63) / 64);
+        L.tab = take(4u * 32u * chunks);
+        L.table_cap = (int32_t)(32u * chunks);
+        L.dslot = take(4u * 32u);
+    } else {
+        L.tab = take(8u * L.h + 16u);
+        L.table_cap = (int32_t)((8u * L.p2 + 8u * L.h + 16u) / 4u);
+        L.dslot = take(4u * L.p2);
+    }
     L.off = take(4u * L.p2);
     L.ubuf = take(4u * np);
     L.lbuf = take(4u * np);
     L.child = take(4u * np);
     L.perm = take(4u * L.p2);
     L.misc = take(64 + 4u * 64);
-    L.gpow = take(4u * (kGpowLds + 2 * kMaxGoals));
+    L.gpow = small ? L.misc : take(4u * (kGpowLds + 2 * kMaxGoals));
     L.total = o;
     return L;
 }

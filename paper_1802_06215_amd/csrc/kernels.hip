@@ -164,7 +164,9 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
     float *lb = (float *)(lds + Ly.lbuf);
     int32_t *child = (int32_t *)(lds + Ly.child);
     int32_t *permb = (int32_t *)(lds + Ly.perm);
-    int32_t *cnt = (int32_t *)(lds + Ly.zkey);  // zkey and tab are contiguous
+    // per-chunk child counts: over zkey and tab (contiguous), or tab alone in
+    // the small carve-up, where they are cleared with the tile's other state
+    int32_t *cnt = (int32_t *)(lds + (Ly.small ? Ly.tab : Ly.zkey));
     int32_t *misc = (int32_t *)(lds + Ly.misc);                   // [0] distinct count, [1] sentinel seen
     unsigned long long *stepc = (unsigned long long *)(misc + 4);  // expansion, rollout steps
     float *chunk_r = (float *)(misc + 8);                          // per-chunk reward sums (<= 32)
@@ -173,6 +175,8 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
 
     if constexpr (!Ops::kSmallObs)
         for (int h = tid; h < H; h += nt) tab[h] = kEmptyKey;
+    if (Ly.small)
+        for (int i = tid; i < Ly.table_cap; i += nt) cnt[i] = 0;
     if (tid == 0) {
         misc[0] = 0;
         misc[1] = 0;
@@ -347,8 +351,10 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
     // -- stable grouping: position of each scenario in perm --------------------
     const int nchunks = (n + 63) >> 6;
     if ((int64_t)nchunks * D <= Ly.table_cap) {
-        for (int i = tid; i < nchunks * D; i += nt) cnt[i] = 0;
-        __syncthreads();
+        if (!Ly.small) {
+            for (int i = tid; i < nchunks * D; i += nt) cnt[i] = 0;
+            __syncthreads();
+        }
         for (int t = wid; t < nchunks; t += nw) {
             const int k = t * 64 + lane;
             const bool valid = k < n;
@@ -366,18 +372,43 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
             if (valid) child[k] = c | (myrank << 16);
         }
         __syncthreads();
-        for (int c = tid; c < D; c += nt) {
-            int run = 0;
-            for (int t = 0; t < nchunks; ++t) {
-                const int v = cnt[t * D + c];
-                cnt[t * D + c] = run;
-                run += v;
+        if (D <= 64) {
+            // one wavefront: lane c turns child c's chunk counts into an
+            // exclusive prefix, then the child offsets are a lane scan
+            if (wid == 0) {
+                int run = 0;
+                if (lane < D)
+                    for (int t = 0; t < nchunks; ++t) {
+                        const int v = cnt[t * D + lane];
+                        cnt[t * D + lane] = run;
+                        run += v;
+                    }
+                int incl = run;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int o = __shfl_up(incl, d, 64);
+                    if (lane >= d) incl += o;
+                }
+                if (lane < D) {
+                    nc[lane] = run;
+                    off[lane] = incl - run;
+                }
             }
-            nc[c] = run;
-            off[c] = run;
+            __syncthreads();
+        } else {
+            for (int c = tid; c < D; c += nt) {
+                int run = 0;
+                for (int t = 0; t < nchunks; ++t) {
+                    const int v = cnt[t * D + c];
+                    cnt[t * D + c] = run;
+                    run += v;
+                }
+                nc[c] = run;
+                off[c] = run;
+            }
+            __syncthreads();
+            block_exclusive_scan(off, D, scan_scratch);
         }
-        __syncthreads();
-        block_exclusive_scan(off, D, scan_scratch);
         for (int k = tid; k < n; k += nt) {
             const int cw = child[k];
             const int c = cw & 0xFFFF;
@@ -482,7 +513,7 @@ __global__ __launch_bounds__(max_threads<MODE>()) void expand_tiles(const LeafTa
                                                                     int32_t persistent, int32_t xcd_remap) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ int32_t s_tile;
-    const LdsLayout Ly = make_layout(n_max);
+    const LdsLayout Ly = make_layout(n_max, MODE == 0);
     const int32_t n_tiles = __builtin_amdgcn_readfirstlane(queue->n_tiles);
     int iter = 0;
     for (;;) {
@@ -528,7 +559,7 @@ __global__ __launch_bounds__(max_threads<MODE>()) void expand_args(const ArgPack
 #else
     const ArgPack *P = &pack;
 #endif
-    const LdsLayout Ly = make_layout(P->n_max);
+    const LdsLayout Ly = make_layout(P->n_max, MODE == 0);
     const int n_leaves = P->n_leaves;
     const int n_tiles = P->tile_begin[n_leaves];
     const int t = P->xcd_remap ? remap_xcd((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
@@ -555,7 +586,7 @@ hipError_t configure_t() {
 
 template <int MODE, int PM>
 hipError_t launch_args_t(const ArgPack &pack, const Schedule &sch, hipStream_t stream) {
-    const LdsLayout Ly = make_layout(pack.n_max);
+    const LdsLayout Ly = make_layout(pack.n_max, MODE == 0);
     const int grid = pack.tile_begin[pack.n_leaves];
     if (grid < 1) return hipSuccess;
     const int threads = sch.threads > max_threads<MODE>() ? max_threads<MODE>() : sch.threads;
@@ -566,7 +597,7 @@ hipError_t launch_args_t(const ArgPack &pack, const Schedule &sch, hipStream_t s
 template <int MODE, int PM>
 hipError_t launch_expand_t(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queue, int32_t n_tiles,
                            int32_t n_max, const Schedule &sch, int32_t n_cu, hipStream_t stream) {
-    const LdsLayout Ly = make_layout(n_max);
+    const LdsLayout Ly = make_layout(n_max, MODE == 0);
     // persistent: a fixed grid that drains the tile queue, so a captured
     // graph stays valid for any tile count
     const int grid = sch.persistent > 0 ? n_cu * sch.persistent : n_tiles;

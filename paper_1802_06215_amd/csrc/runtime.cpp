@@ -853,10 +853,7 @@ hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *b, int32_t reps, float *b
     if (b->staged_used) hipEventSynchronize(b->staged);
     const Variant v = batch_variant(b);
     const int tmax = variant_max_threads(v);
-    // each size class is tuned on its own launch; the best schedules are kept
-    float total = 0.0f;
-    for (int c = 0; c < kSizeClasses; ++c) {
-        if (b->plan.count[c] == 0) continue;
+    auto candidates = [&](int c) {
         const int32_t n_max = std::max(b->lds_c[c], b->plan.n_max[c]);
         const int cap = std::min(tmax, std::max(64, pow2_at_least(std::max(n_max, 1))));
         std::vector<Schedule> cand;
@@ -865,31 +862,72 @@ hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *b, int32_t reps, float *b
             cand.push_back(Schedule{th, 0, 1});
             for (int p : {1, 2, 4, 8}) cand.push_back(Schedule{th, p, 0});
         }
+        return cand;
+    };
+    // mean ms of `reps` launches of the classes in mask under schedules s
+    auto time_launch = [&](const Schedule *s, uint32_t mask, float *ms) -> hipError_t {
+        hipError_t e = batch_direct_launch(ctx, b, s, b->work, mask);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(b->t0, b->work);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = batch_direct_launch(ctx, b, s, b->work, mask);
+        if (e == hipSuccess) e = hipEventRecord(b->t1, b->work);
+        if (e == hipSuccess) e = hipEventSynchronize(b->t1);
+        if (e == hipSuccess) e = hipEventElapsedTime(ms, b->t0, b->t1);
+        *ms /= (float)reps;
+        return e;
+    };
+    int active = 0;
+    for (int c = 0; c < kSizeClasses; ++c) active += b->plan.count[c] > 0;
+    // 1: each size class on its own launch
+    Schedule trial[kSizeClasses];
+    for (int k = 0; k < kSizeClasses; ++k) trial[k] = b->sched[k];
+    float total = 0.0f;
+    for (int c = 0; c < kSizeClasses; ++c) {
+        if (b->plan.count[c] == 0) continue;
         float best = 1e30f;
-        Schedule trial[kSizeClasses];
-        for (int k = 0; k < kSizeClasses; ++k) trial[k] = b->sched[k];
         Schedule best_s = b->sched[c];
-        for (const Schedule &s : cand) {
+        for (const Schedule &s : candidates(c)) {
             trial[c] = s;
-            const uint32_t mask = 1u << c;
-            hipError_t e = batch_direct_launch(ctx, b, trial, b->work, mask);  // warm-up
-            if (e == hipSuccess) e = hipEventRecord(b->t0, b->work);
-            for (int r = 0; r < reps && e == hipSuccess; ++r) e = batch_direct_launch(ctx, b, trial, b->work, mask);
-            if (e == hipSuccess) e = hipEventRecord(b->t1, b->work);
-            if (e == hipSuccess) e = hipEventSynchronize(b->t1);
-            if (e != hipSuccess) return hip_fail(ctx, e, "autotune launch");
             float ms = 0.0f;
-            hipEventElapsedTime(&ms, b->t0, b->t1);
-            ms /= (float)reps;
+            const hipError_t e = time_launch(trial, 1u << c, &ms);
+            if (e != hipSuccess) return hip_fail(ctx, e, "autotune launch");
             if (ms < best) {
                 best = ms;
                 best_s = s;
             }
         }
-        b->sched[c] = best_s;
-        b->sched_set[c] = true;
+        trial[c] = best_s;
         total += best;
     }
+    // 2: the classes run side by side, so each class's schedule is refined
+    // once more against the whole launch with the others at their choice
+    if (active > 1) {
+        float best = 0.0f;
+        hipError_t e = time_launch(trial, 0xffffffffu, &best);
+        if (e != hipSuccess) return hip_fail(ctx, e, "autotune launch");
+        for (int c = kSizeClasses - 1; c >= 0; --c) {
+            if (b->plan.count[c] == 0) continue;
+            const Schedule keep = trial[c];
+            Schedule best_s = keep;
+            for (const Schedule &s : candidates(c)) {
+                if (same_schedule(s, keep)) continue;
+                trial[c] = s;
+                float ms = 0.0f;
+                e = time_launch(trial, 0xffffffffu, &ms);
+                if (e != hipSuccess) return hip_fail(ctx, e, "autotune launch");
+                if (ms < best) {
+                    best = ms;
+                    best_s = s;
+                }
+            }
+            trial[c] = best_s;
+        }
+        total = best;
+    }
+    for (int c = 0; c < kSizeClasses; ++c)
+        if (b->plan.count[c] > 0) {
+            b->sched[c] = trial[c];
+            b->sched_set[c] = true;
+        }
     drop_graph(b);
     if (best_ms) *best_ms = total;
     return HDX_OK;
