@@ -210,10 +210,13 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
         const int k = base + tid;
         const bool valid = k < n;
         float r = 0.0f;
-        if (valid) {
+        uint64_t z = 0;
+        uint32_t id = 0;
+        typename Ops::State st;
+        // gather + update + expansion step of one scenario
+        auto expand_one = [&]() {
             const int p = T->idx[k];
-            const uint32_t id = T->parent_ids[p];
-            typename Ops::State st;
+            id = T->parent_ids[p];
             Ops::load(M, parent, p, st);
             if (last_action >= 0) {
                 float r0;
@@ -225,9 +228,20 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
                 T->ids_out[k] = id;
             }
             my_exp += Ops::terminal(st) ? 0 : 1;
-            uint64_t z;
             Ops::template step<true>(M, st, a, id, (uint32_t)depth, RP.k0, RP.k1, r, z);
-            const float U = Ops::upper_wave(M, st);
+        };
+        float U = 0.0f;
+        if constexpr (Ops::kWaveUpper) {
+            // every lane of the wavefront takes part in the bound (it shares
+            // per-rock terms across lanes); lanes past n stay terminal
+            Ops::make_terminal(st);
+            if (valid) expand_one();
+            U = Ops::upper_wave(M, st);
+        } else if (valid) {
+            expand_one();
+            U = Ops::upper(M, st);
+        }
+        if (valid) {
             const int64_t pk = (int64_t)a * n + k;
             if (pair_out) Ops::store(M, sprime, pk, st);
             int ns = 0;

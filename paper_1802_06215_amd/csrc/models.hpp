@@ -112,8 +112,10 @@ struct RsOps {
     static constexpr bool kSplitRollout = true;  // small step: one rollout loop per policy
     static constexpr bool kSmallObs = true;       // observations 0 (none), 1, 2 (sensor readings)
     static constexpr bool kLdsModel = false;      // expansion reads no per-lane table from LDS
+    static constexpr bool kWaveUpper = true;      // upper bound evaluated by whole wavefronts
 
     __device__ static void load(const MView &, const StatesPtr &S, int64_t p, State &st) { st.w = S.w[p]; }
+    __device__ static void make_terminal(State &st) { st.w = 1 << 30; }
     __device__ static void store(const MView &, const StatesPtr &S, int64_t p, const State &st) { S.w[p] = st.w; }
     __device__ static bool terminal(const State &st) { return (st.w >> 30) & 1; }
 
@@ -175,10 +177,10 @@ struct RsOps {
     }
 
     // The same value, bit for bit.  Robot cells are deterministic, so the
-    // live scenarios of a tile usually share one cell: then each rock's
-    // discounted reward is computed once per wavefront (scalar) and a lane
-    // only selects the terms of its good rocks (adding +0 for the others
-    // leaves the sum unchanged).  Called by every active lane of a wavefront.
+    // live scenarios of a tile usually share one cell: then lane i computes
+    // rock i's discounted reward once for the wavefront and every lane only
+    // selects the terms of its good rocks (adding +0 for the others leaves
+    // the sum unchanged).  Called by all 64 lanes of a wavefront.
     __device__ static float upper_wave(const MView &M, const State &st) {
         const bool live = !((st.w >> 30) & 1);
         const int x = st.w & 31, y = (st.w >> 5) & 31;
@@ -196,9 +198,13 @@ struct RsOps {
             return u + 10.0f * M.gg[M.h->grid - 1 - x];
         }
         const int xs = __builtin_amdgcn_readfirstlane(x0), ys = __builtin_amdgcn_readfirstlane(y0);
+        const int nr = M.h->n_rocks;
+        const int lane = (int)__lane_id();
+        float ci = 0.0f;
+        if (lane < nr) ci = 10.0f * M.gg[abs(xs - M.h->rock_x[lane]) + abs(ys - M.h->rock_y[lane])];
         float u = 0.0f;
-        for (int i = 0; i < M.h->n_rocks; ++i) {
-            const float c = 10.0f * M.gpow_uniform(abs(xs - M.h->rock_x[i]) + abs(ys - M.h->rock_y[i]));
+        for (int i = 0; i < nr; ++i) {
+            const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ci), i));
             u += ((st.w >> (10 + i)) & 1) ? c : 0.0f;
         }
         u = u + 10.0f * M.gpow_uniform(M.h->grid - 1 - xs);
@@ -233,6 +239,7 @@ struct PedOps {
     static constexpr bool kSplitRollout = false;  // large step: one loop keeps the code small
     static constexpr bool kSmallObs = false;      // 64-bit hashed observations
     static constexpr bool kLdsModel = true;       // discount powers and goal points staged in LDS
+    static constexpr bool kWaveUpper = false;     // per-lane upper bound
 
     __device__ static void load(const MView &M, const StatesPtr &S, int64_t p, State &st) {
         st.s = S.s[p];
@@ -360,7 +367,6 @@ struct PedOps {
         if (Ti > kHorizon) Ti = kHorizon;
         return M.h->r_goal * M.gpow_lane(Ti - 1);
     }
-    __device__ static float upper_wave(const MView &M, const State &st) { return upper(M, st); }
 
     __device__ static int default_action(const MView &M, const State &st) {
         bool brake = false;
