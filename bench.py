@@ -30,7 +30,7 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE (scaled by a plain copy of known size), recorded with a hash of
 # the kernel's sources: reported only while those sources are unchanged.
 PROFILED_TRAFFIC = {
-    "rs15": dict(bytes=74.868e6, sha="49ff3cea98fe2350", summary="profiles/expand_tiles_rs15.md"),
+    "rs15": dict(bytes=52.317e6, sha="03a79afef7fb6d81", summary="profiles/expand_tiles_rs15.md"),
 }
 KERNEL_SOURCES = ("paper_1802_06215_amd/csrc/kernels.hip", "paper_1802_06215_amd/csrc/models.hpp",
                   "paper_1802_06215_amd/csrc/internal.hpp")
@@ -73,9 +73,9 @@ def parse():
                     "(skips the autotuner)")
     ap.add_argument("--class-schedule", action="append", default=[],
                     help="size_class:threads,persistent,xcd_remap (repeatable; skips the autotuner)")
-    ap.add_argument("--surrogate-epochs", type=int, default=8,
+    ap.add_argument("--surrogate-epochs", type=int, default=12,
                     help="training epochs of the surrogate comparison (rs15 only; 0 = skip)")
-    ap.add_argument("--surrogate-targets", type=int, default=8,
+    ap.add_argument("--surrogate-targets", type=int, default=16,
                     help="rollouts averaged into each training target")
     ap.add_argument("--surrogate-leaves", type=int, default=2048,
                     help="training leaves of 100 scenarios each (x 20 actions = pairs / 2000)")
@@ -319,10 +319,13 @@ def surrogate_section(ctx, args):
 
     # search at equal budget
     runs = {}
-    for name, sur in (("rollouts", None), ("surrogate", net)) if args.search_seconds > 0 else ():
+    # the second rollout run (another random-number key) measures how much
+    # the root value of two equal searches differs by itself
+    plan = (("rollouts", None, 3), ("surrogate", net, 3), ("rollouts_key4", None, 4))
+    for name, sur, key in plan if args.search_seconds > 0 else ():
         r = ctx.search(m, W.rocksample_belief(desc), K=500, n_threads=8, max_depth=90, batch_leaves=8,
                        time_budget_s=args.search_seconds, rollout=rcfg, surrogate=sur, surrogate_horizon=90,
-                       surrogate_judge_every=16 if sur is not None else 0, seed=3)
+                       surrogate_judge_every=16 if sur is not None else 0, seed=key)
         runs[name] = dict(trials_per_s=round(r["trials"] / r["elapsed_s"], 1),
                           expansions_per_s=round(r["expansions"] / r["elapsed_s"], 1),
                           l_root=round(r["l_root"], 5), u_root=round(r["u_root"], 5),
@@ -361,29 +364,52 @@ def surrogate_section(ctx, args):
                          child_l0_p90_one_rollout=round(float(np.percentile(ce_one, 90)), 5),
                          child_l0_p90_surrogate=round(float(np.percentile(ce_sur, 90)), 5))),
         search=dict(threads=8, leaf_batch=8, budget_s=args.search_seconds, runs=runs,
-                    root_value_rel_err=round(abs(ls_ - lf_) / max(abs(lf_), 1e-9), 5)))
+                    root_value_rel_err=round(abs(ls_ - lf_) / max(abs(lf_), 1e-9), 5),
+                    root_value_rel_diff_two_rollout_runs=round(
+                        abs(runs["rollouts_key4"]["l_root"] - lf_) / max(abs(lf_), 1e-9), 5) if runs else None))
 
 
 def cpu_baseline(items, seconds):
-    """The oracle as it stands, single-threaded, over leaves of the same
-    batch until the time budget is spent."""
+    """The oracle as it stands over leaves of the same batch: first on one
+    thread until the time budget is spent, then on one thread per host core
+    (the oracle is reentrant C; ctypes releases the interpreter lock during
+    each call) over the whole batch, repeated for at least two seconds."""
+    import concurrent.futures as cf
+
     import numpy as np
 
     import oracle
-    steps = 0
-    done = 0
-    t0 = time.perf_counter()
-    for d, lf, seed, cfg in items:
+
+    def one(it):
+        d, lf, seed, cfg = it
         par = oracle.parent_states(d, lf)
         res = oracle.expand_leaf(d, oracle.cfg(*cfg), par, lf["ids"].astype(np.uint32), lf["idx"],
                                  lf["depth"], lf["last_action"], seed, 0)
-        steps += res["expand_steps"] + res["rollout_steps"]
+        return int(res["expand_steps"]) + int(res["rollout_steps"])
+
+    steps = done = 0
+    t0 = time.perf_counter()
+    for it in items:
+        steps += one(it)
         done += 1
         if time.perf_counter() - t0 > seconds:
             break
-    dt = time.perf_counter() - t0
-    return dict(value=steps / dt, unit="scenario-steps/s", cores=1, kind="oracle",
-                sample="first %d of %d leaves of the same batch, %.1f s, single thread" % (done, len(items), dt))
+    dt1 = time.perf_counter() - t0
+    single = steps / dt1
+    cores = min(16, len(os.sched_getaffinity(0)))
+    msteps = passes = 0
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+        while True:
+            msteps += sum(ex.map(one, items, chunksize=8))
+            passes += 1
+            if time.perf_counter() - t0 >= 2.0:
+                break
+    dtm = time.perf_counter() - t0
+    return dict(value=msteps / dtm, unit="scenario-steps/s", cores=cores, kind="oracle",
+                single_thread_value=round(single, 1),
+                sample="whole batch (%d leaves) %d time(s) on %d threads in %.1f s; single thread: first %d "
+                       "leaves in %.1f s" % (len(items), passes, cores, dtm, done, dt1))
 
 
 def main():
