@@ -119,26 +119,52 @@ hdx_states rec_states(const hdx_model_desc &d, const Rec &r) {
     return s;
 }
 
-// Per-thread scratch of the surrogate judge: a record for the largest leaf
-// and its head block on the host.
-struct Judge {
-    Rec rec;
-    char *head = nullptr;
+// A thread's head block in pinned host memory mapped into the device's
+// address space: the expansion kernels write a leaf's child tables there
+// directly, so the host reads them after the stream synchronises, with no
+// copy call.  Sized for the largest record.
+struct HeadBuf {
+    char *host = nullptr;
+    char *dev = nullptr;
+    bool alloc(size_t bytes) {
+        if (hipHostMalloc((void **)&host, bytes, hipHostMallocMapped) != hipSuccess) {
+            host = nullptr;
+            return false;
+        }
+        if (hipHostGetDevicePointer((void **)&dev, host, 0) != hipSuccess) {
+            hipHostFree(host);
+            host = dev = nullptr;
+            return false;
+        }
+        return true;
+    }
+    void release() {
+        if (host) hipHostFree(host);
+        host = dev = nullptr;
+    }
 };
 
-// Points a leaf's outputs at a record's arrays.
-void fill_outputs(const hdx_model_desc &d, hdx_leaf &L, const Rec &r) {
+// Per-thread scratch of the surrogate judge: a record for the largest leaf
+// and its head block.
+struct Judge {
+    Rec rec;
+    HeadBuf head;
+};
+
+// Points a leaf's outputs at a record's arrays, its head block at `head`
+// (a mapped host block laid out like the record's head).
+void fill_outputs(const hdx_model_desc &d, hdx_leaf &L, const Rec &r, char *head) {
     L.states_out = rec_states(d, r);
     L.ids_out = (uint32_t *)(r.dev + r.L.ids);
     L.perm = (int32_t *)(r.dev + r.L.perm);
-    L.n_children = (int32_t *)(r.dev + r.L.n_children);
-    L.child_z = (uint64_t *)(r.dev + r.L.child_z);
-    L.child_n = (int32_t *)(r.dev + r.L.child_n);
-    L.child_off = (int32_t *)(r.dev + r.L.child_off);
-    L.child_u0 = (float *)(r.dev + r.L.child_u0);
-    L.child_l0 = (float *)(r.dev + r.L.child_l0);
-    L.r_mean = (float *)(r.dev + r.L.r_mean);
-    L.steps = (int64_t *)(r.dev + r.L.steps);
+    L.n_children = (int32_t *)(head + r.L.n_children);
+    L.child_z = (uint64_t *)(head + r.L.child_z);
+    L.child_n = (int32_t *)(head + r.L.child_n);
+    L.child_off = (int32_t *)(head + r.L.child_off);
+    L.child_u0 = (float *)(head + r.L.child_u0);
+    L.child_l0 = (float *)(head + r.L.child_l0);
+    L.r_mean = (float *)(head + r.L.r_mean);
+    L.steps = (int64_t *)(head + r.L.steps);
 }
 
 
@@ -249,7 +275,7 @@ struct Search {
         return best;
     }
 
-    bool expand(int node_id, hipStream_t stream, char *head_host, Judge *J);
+    bool expand(int node_id, hipStream_t stream, const HeadBuf &hb, Judge *J);
     void judge_leaf(const hdx_leaf &L0, const Rec &r, const char *head_host, Judge &J, hipStream_t stream);
     bool use_surrogate() const { return cfg.surrogate != nullptr && !surrogate_off.load(); }
 
@@ -298,21 +324,30 @@ struct Search {
 // when the accumulated relative error exceeds the configured bound.
 void Search::judge_leaf(const hdx_leaf &L0, const Rec &r, const char *head_host, Judge &J, hipStream_t stream) {
     hdx_leaf L = L0;
-    fill_outputs(d, L, J.rec);
+    // the judge's record has room for the largest leaf; its head block takes
+    // this leaf's layout (the offsets of r)
+    fill_outputs(d, L, J.rec, J.head.dev);
+    L.n_children = (int32_t *)(J.head.dev + r.L.n_children);
+    L.child_z = (uint64_t *)(J.head.dev + r.L.child_z);
+    L.child_n = (int32_t *)(J.head.dev + r.L.child_n);
+    L.child_off = (int32_t *)(J.head.dev + r.L.child_off);
+    L.child_u0 = (float *)(J.head.dev + r.L.child_u0);
+    L.child_l0 = (float *)(J.head.dev + r.L.child_l0);
+    L.r_mean = (float *)(J.head.dev + r.L.r_mean);
+    L.steps = (int64_t *)(J.head.dev + r.L.steps);
     hdx_status st = hdx_expand_leaf_surrogate(ctx, &L, 1, cfg.surrogate, cfg.surrogate_horizon, stream);
     if (st != HDX_OK) {
         fail(st, "judge expansion");
         return;
     }
-    if (hipMemcpyAsync(J.head, J.rec.dev, J.rec.L.head, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-        hipStreamSynchronize(stream) != hipSuccess) {
-        fail(HDX_E_DEVICE, "judge head copy");
+    if (hipStreamSynchronize(stream) != hipSuccess) {
+        fail(HDX_E_DEVICE, "judge expansion wait");
         return;
     }
     const int cap = L0.cap;
     const int32_t *nch = (const int32_t *)(head_host + r.L.n_children);
     const float *lf = (const float *)(head_host + r.L.child_l0);
-    const float *ls = (const float *)(J.head + J.rec.L.child_l0);
+    const float *ls = (const float *)(J.head.host + r.L.child_l0);
     double e = 0.0, ref = 0.0;
     int64_t nc = 0;
     for (int a = 0; a < A; ++a)
@@ -330,7 +365,8 @@ void Search::judge_leaf(const hdx_leaf &L0, const Rec &r, const char *head_host,
         surrogate_off = true;
 }
 
-bool Search::expand(int node_id, hipStream_t stream, char *head_host, Judge *J) {
+bool Search::expand(int node_id, hipStream_t stream, const HeadBuf &hb, Judge *J) {
+    char *head_host = hb.host;
     // builds the leaf descriptor; the caller holds no lock
     Node b;
     {
@@ -357,7 +393,7 @@ bool Search::expand(int node_id, hipStream_t stream, char *head_host, Judge *J) 
     L.depth = b.depth;
     L.last_action = b.action;
     L.cap = cap_for(b.n);
-    fill_outputs(d, L, r);
+    fill_outputs(d, L, r, hb.dev);
     hdx_status st = HDX_OK;
     const bool sur = use_surrogate();
     const bool judge = sur && J != nullptr && cfg.surrogate_judge_every > 0 &&
@@ -389,14 +425,13 @@ bool Search::expand(int node_id, hipStream_t stream, char *head_host, Judge *J) 
         if (st != HDX_OK) {
             fail(st, "expand_leaf");
         } else {
-            hipError_t e = hipMemcpyAsync(head_host, r.dev, r.L.head, hipMemcpyDeviceToHost, stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            const hipError_t e = hipStreamSynchronize(stream);  // the head block is then on the host
             if (e != hipSuccess) {
                 st = HDX_E_DEVICE;
                 std::lock_guard<std::mutex> g(emu);
                 if (error == HDX_OK) {
                     error = st;
-                    error_msg = std::string("head copy: ") + hipGetErrorString(e);
+                    error_msg = std::string("expansion wait: ") + hipGetErrorString(e);
                 }
                 stop = true;
             }
@@ -435,10 +470,7 @@ void batcher_loop(Search *S, hipStream_t stream) {
                                                                      S->cfg.surrogate_horizon, stream)
                                          : hdx_expand_leaf(S->ctx, leaves.data(), nl, stream);
         if (st != HDX_OK) S->fail(st, "batched expand_leaf");
-        for (Request *q : batch)
-            if (st == HDX_OK &&
-                hipMemcpyAsync(q->head_host, q->rec->dev, q->rec->L.head, hipMemcpyDeviceToHost, stream) != hipSuccess)
-                st = HDX_E_DEVICE;
+        // every leaf's head block is mapped host memory: one wait delivers all
         if (st == HDX_OK && hipStreamSynchronize(stream) != hipSuccess) st = HDX_E_DEVICE;
         S->launches++;
         {
@@ -455,12 +487,16 @@ void batcher_loop(Search *S, hipStream_t stream) {
 void worker(Search *S, int tid, size_t head_bytes) {
     hipStream_t stream = nullptr;
     hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
-    char *head_host = nullptr;
-    hipHostMalloc((void **)&head_host, head_bytes);
+    HeadBuf hb;
+    if (!hb.alloc(head_bytes)) {
+        S->fail(HDX_E_NOMEM, "head block");
+        hipStreamDestroy(stream);
+        return;
+    }
     Judge judge;
     Judge *J = nullptr;
     if (S->cfg.surrogate && S->cfg.surrogate_judge_every > 0 && S->alloc_rec(S->cfg.K, &judge.rec) &&
-        hipHostMalloc((void **)&judge.head, judge.rec.L.head) == hipSuccess)
+        judge.head.alloc(head_bytes))
         J = &judge;
     std::vector<int> path;
     const double K = (double)S->cfg.K;
@@ -513,7 +549,7 @@ void worker(Search *S, int tid, size_t head_bytes) {
         }
         bool ok = true;
         if (leaf >= 0) {
-            ok = S->expand(leaf, stream, head_host, J);
+            ok = S->expand(leaf, stream, hb, J);
             if (!ok) {
                 std::lock_guard<std::mutex> g(S->mu);
                 S->nodes[leaf].state = 0;
@@ -536,8 +572,8 @@ void worker(Search *S, int tid, size_t head_bytes) {
             std::this_thread::yield();
         }
     }
-    hipHostFree(head_host);
-    if (judge.head) hipHostFree(judge.head);
+    hb.release();
+    judge.head.release();
     hipStreamDestroy(stream);
 }
 
