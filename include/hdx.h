@@ -326,6 +326,11 @@ hdx_status hdx_mlp_destroy(hdx_ctx *ctx, hdx_mlp *mlp);
 /* Copy the FP32 parameters to / from host memory (set resets Adam). */
 hdx_status hdx_mlp_get_params(hdx_ctx *ctx, const hdx_mlp *mlp, float *host_params);
 hdx_status hdx_mlp_set_params(hdx_ctx *ctx, hdx_mlp *mlp, const float *host_params);
+/* Checkpoint: save writes the FP32 parameters, the Adam moments and step to
+ * a file (after the device is idle); load restores them (E_SHAPE for a file
+ * that is not such a checkpoint, E_INVALID if it cannot be opened). */
+hdx_status hdx_mlp_save(hdx_ctx *ctx, hdx_mlp *mlp, const char *path);
+hdx_status hdx_mlp_load(hdx_ctx *ctx, hdx_mlp *mlp, const char *path);
 /* y[i] = MLP(X[i]) for n rows (device arrays). */
 hdx_status hdx_mlp_forward(hdx_ctx *ctx, hdx_mlp *mlp, const uint16_t *X, int64_t n, float *y, hdx_stream stream);
 /* Gradients of mean((MLP(X) - t)^2) over a batch (a multiple of 64, at

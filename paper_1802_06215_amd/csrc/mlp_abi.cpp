@@ -1,6 +1,7 @@
 // C ABI of the rollout-value surrogate: create, parameters, forward,
 // gradients, training step (Adam) and state features.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <mutex>
@@ -162,6 +163,53 @@ hdx_status hdx_mlp_set_params(hdx_ctx *ctx, hdx_mlp *m, const float *host) {
         mlp_refresh_bf16(m->P, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
         return HDX_E_DEVICE;
     m->step = 0;
+    return HDX_OK;
+}
+
+// Checkpoint file: magic, parameter count, Adam step, then the FP32
+// parameters and the two Adam moments (little-endian, as in memory).
+static const char kMlpMagic[8] = {'H', 'D', 'X', 'M', 'L', 'P', '0', '1'};
+
+hdx_status hdx_mlp_save(hdx_ctx *ctx, hdx_mlp *m, const char *path) {
+    if (!ctx || !m || !path) return HDX_E_INVALID;
+    std::lock_guard<std::mutex> g(m->mu);
+    const size_t n = kMlpParams;
+    std::vector<float> buf(3 * n);
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(buf.data(), m->P.p, n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(buf.data() + n, m->P.m, n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(buf.data() + 2 * n, m->P.v, n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+        return HDX_E_DEVICE;
+    FILE *f = fopen(path, "wb");
+    if (!f) return HDX_E_INVALID;
+    const int64_t count = (int64_t)n, step = m->step;
+    const bool ok = fwrite(kMlpMagic, 1, 8, f) == 8 && fwrite(&count, sizeof(count), 1, f) == 1 &&
+                    fwrite(&step, sizeof(step), 1, f) == 1 && fwrite(buf.data(), sizeof(float), 3 * n, f) == 3 * n;
+    return (fclose(f) == 0 && ok) ? HDX_OK : HDX_E_INVALID;
+}
+
+hdx_status hdx_mlp_load(hdx_ctx *ctx, hdx_mlp *m, const char *path) {
+    if (!ctx || !m || !path) return HDX_E_INVALID;
+    FILE *f = fopen(path, "rb");
+    if (!f) return HDX_E_INVALID;
+    char magic[8];
+    int64_t count = 0, step = 0;
+    const size_t n = kMlpParams;
+    std::vector<float> buf(3 * n);
+    const bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kMlpMagic, 8) == 0 &&
+                    fread(&count, sizeof(count), 1, f) == 1 && count == (int64_t)n &&
+                    fread(&step, sizeof(step), 1, f) == 1 && step >= 0 && step < (1ll << 31) &&
+                    fread(buf.data(), sizeof(float), 3 * n, f) == 3 * n;
+    fclose(f);
+    if (!ok) return HDX_E_SHAPE;
+    std::lock_guard<std::mutex> g(m->mu);
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(m->P.p, buf.data(), n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->P.m, buf.data() + n, n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->P.v, buf.data() + 2 * n, n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        mlp_refresh_bf16(m->P, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        return HDX_E_DEVICE;
+    m->step = (int)step;
     return HDX_OK;
 }
 

@@ -103,7 +103,7 @@ EXPORTS = ["hdx_version", "hdx_init", "hdx_fini", "hdx_last_error", "hdx_upload_
            "hdx_batch_set_class_schedule", "hdx_batch_get_class_schedule",
            "hdx_batch_launch", "hdx_batch_autotune", "hdx_search", "hdx_mlp_create", "hdx_mlp_destroy",
            "hdx_mlp_get_params", "hdx_mlp_set_params", "hdx_mlp_forward", "hdx_mlp_gradients",
-           "hdx_mlp_train_step", "hdx_features", "hdx_expand_leaf_surrogate",
+           "hdx_mlp_train_step", "hdx_features", "hdx_expand_leaf_surrogate", "hdx_mlp_save", "hdx_mlp_load",
            "hdx_tree_create", "hdx_tree_destroy", "hdx_tree_add_children", "hdx_backup",
            "hdx_tree_bounds", "hdx_tree_size"]
 
@@ -156,6 +156,8 @@ def load_library():
     L.hdx_mlp_train_step.argtypes = [P, P, P, P, I32, C.c_float, P, P]
     L.hdx_features.argtypes = [P, P, States, P, I64, I32, P, P]
     L.hdx_expand_leaf_surrogate.argtypes = [P, P, I32, P, I32, P]
+    L.hdx_mlp_save.argtypes = [P, P, C.c_char_p]
+    L.hdx_mlp_load.argtypes = [P, P, C.c_char_p]
     L.hdx_tree_create.argtypes = [I32, C.c_double, I32, C.c_double, C.c_double, C.POINTER(P)]
     L.hdx_tree_destroy.argtypes = [P]
     L.hdx_tree_add_children.argtypes = [P, I64, P, P, P, P, P, P, I32, C.POINTER(I64)]
@@ -538,6 +540,12 @@ class Mlp:
         p = np.ascontiguousarray(p, dtype=np.float32)
         assert p.shape == (MLP_PARAMS,)
         self.ctx._check(self.lib.hdx_mlp_set_params(self.ctx.handle, self.handle, p.ctypes.data))
+
+    def save(self, path: str) -> None:
+        self.ctx._check(self.lib.hdx_mlp_save(self.ctx.handle, self.handle, os.fsencode(path)))
+
+    def load(self, path: str) -> None:
+        self.ctx._check(self.lib.hdx_mlp_load(self.ctx.handle, self.handle, os.fsencode(path)))
 
     def forward(self, X: torch.Tensor, stream=None) -> torch.Tensor:
         """X: int16/uint16 BF16 bits [n, 64] on the device."""

@@ -140,3 +140,31 @@ def test_features_match_definition(ctx):
     got = X.cpu().numpy().view(np.uint16)
     want = (ref.bf16_round(ref.rocksample_features(desc, st["w"], depths, 90)).view(np.uint32) >> 16).astype(np.uint16)
     assert np.array_equal(got, want)
+
+
+def test_checkpoint_roundtrip(ctx, tmp_path):
+    """save/load restores the parameters, the Adam moments and step: the next
+    training step from a loaded copy equals the original's bit for bit."""
+    from paper_1802_06215_amd import Mlp
+    from paper_1802_06215_amd.hdx import HdxError
+    rng = np.random.default_rng(3)
+    X = device_bf16(rng.normal(0, 1, (1024, 64)).astype(np.float32))
+    t = torch.from_numpy(rng.normal(0, 1, 1024).astype(np.float32)).cuda()
+    a = Mlp(ctx, seed=7)
+    for _ in range(3):
+        a.train_step(X, t, 1e-3)
+    path = str(tmp_path / "net.ckpt")
+    a.save(path)
+    b = Mlp(ctx, seed=99)
+    b.load(path)
+    assert np.array_equal(a.params().view(np.uint32), b.params().view(np.uint32))
+    a.train_step(X, t, 1e-3)
+    b.train_step(X, t, 1e-3)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.params().view(np.uint32), b.params().view(np.uint32))
+    bad = tmp_path / "bad.ckpt"
+    bad.write_bytes(b"not a checkpoint")
+    with pytest.raises(HdxError):
+        b.load(str(bad))
+    a.close()
+    b.close()
