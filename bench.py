@@ -73,7 +73,7 @@ def parse():
                     "(skips the autotuner)")
     ap.add_argument("--class-schedule", action="append", default=[],
                     help="size_class:threads,persistent,xcd_remap (repeatable; skips the autotuner)")
-    ap.add_argument("--surrogate-epochs", type=int, default=12,
+    ap.add_argument("--surrogate-epochs", type=int, default=24,
                     help="training epochs of the surrogate comparison (rs15 only; 0 = skip)")
     ap.add_argument("--surrogate-targets", type=int, default=16,
                     help="rollouts averaged into each training target")
@@ -258,7 +258,7 @@ def surrogate_section(ctx, args):
     net = Mlp(ctx, seed=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    hist = S.fit(net, X, t, epochs=args.surrogate_epochs, batch=4096, lr=1e-3)
+    hist = S.fit(net, X, t, epochs=args.surrogate_epochs, batch=4096, lr=2e-3, lr_final=1e-4)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     samples = (X.shape[0] // 4096) * 4096 * args.surrogate_epochs
@@ -299,13 +299,14 @@ def surrogate_section(ctx, args):
             acc += o.L[:, :o.n]
     ctx.expand_leaf_surrogate(descs, net, 90)
     torch.cuda.synchronize()
-    pe_one, pe_sur, ce_one, ce_sur = [], [], [], []
+    pe_one, pe_sur, ce_one, ce_sur, pb_sur, cb_sur = [], [], [], [], [], []
     for (o, _), acc, (l_one, perm, coff, cn, nch, l0_one) in zip(outs, ref_sum, one):
         truth = (acc / R).cpu().numpy().astype(np.float64)
         l_sur = o.L[:, :o.n].cpu().numpy().astype(np.float64)
         l_one = l_one.cpu().numpy().astype(np.float64)
         pe_one.append(np.abs(l_one - truth).ravel())
         pe_sur.append(np.abs(l_sur - truth).ravel())
+        pb_sur.append((l_sur - truth).ravel())
         l0_sur = o.child_l0.cpu().numpy()
         for a in range(len(nch)):
             for c in range(nch[a]):
@@ -313,18 +314,27 @@ def surrogate_section(ctx, args):
                 t0_ = truth[a, seg].mean()
                 ce_one.append(abs(l0_one[a, c] - t0_))
                 ce_sur.append(abs(l0_sur[a, c] - t0_))
-    pe_one, pe_sur = np.concatenate(pe_one), np.concatenate(pe_sur)
-    ce_one, ce_sur = np.asarray(ce_one), np.asarray(ce_sur)
+                cb_sur.append(l0_sur[a, c] - t0_)
+    pe_one, pe_sur, pb_sur = np.concatenate(pe_one), np.concatenate(pe_sur), np.concatenate(pb_sur)
+    ce_one, ce_sur, cb_sur = np.asarray(ce_one), np.asarray(ce_sur), np.asarray(cb_sur)
     del descs, outs, keep, one, ref_sum
 
     # search at equal budget
     runs = {}
-    # the second rollout run (another random-number key) measures how much
-    # the root value of two equal searches differs by itself
-    plan = (("rollouts", None, 3), ("surrogate", net, 3), ("rollouts_key4", None, 4))
-    for name, sur, key in plan if args.search_seconds > 0 else ():
+    # each form under three random-number keys: the root value of equal
+    # searches varies with the key, so the forms are compared by their means
+    # (equal time, then an equal number of trials: the lower bound of the
+    # root grows as the tree grows, so the equal-trials runs isolate the
+    # accuracy of the leaf values from the speed of the search)
+    keys = (3, 4, 5)
+    EQ_TRIALS = 8000
+    plan = [("%s_key%d" % (nm, k), sur, k, 0) for k in keys for nm, sur in (("rollouts", None), ("surrogate", net))]
+    plan += [("%s_trials_key%d" % (nm, k), sur, k, EQ_TRIALS)
+             for k in keys for nm, sur in (("rollouts", None), ("surrogate", net))]
+    for name, sur, key, max_trials in plan if args.search_seconds > 0 else ():
         r = ctx.search(m, W.rocksample_belief(desc), K=500, n_threads=8, max_depth=90, batch_leaves=8,
-                       time_budget_s=args.search_seconds, rollout=rcfg, surrogate=sur, surrogate_horizon=90,
+                       time_budget_s=args.search_seconds if max_trials == 0 else 10.0, max_trials=max_trials,
+                       rollout=rcfg, surrogate=sur, surrogate_horizon=90,
                        surrogate_judge_every=16 if sur is not None else 0, seed=key)
         runs[name] = dict(trials_per_s=round(r["trials"] / r["elapsed_s"], 1),
                           expansions_per_s=round(r["expansions"] / r["elapsed_s"], 1),
@@ -334,8 +344,17 @@ def surrogate_section(ctx, args):
             runs[name].update(judged_leaves=r["judged_leaves"], judge_child_l0_mae=round(r["judge_mae"], 5),
                               judge_rel_err=round(r["judge_rel_err"], 5), fell_back=bool(r["surrogate_off"]))
         log("search", name, runs[name])
-    lf_ = runs["rollouts"]["l_root"] if runs else 0.0
-    ls_ = runs["surrogate"]["l_root"] if runs else 0.0
+    def stats(form):
+        v = np.array([runs["%s_key%d" % (form, k)]["l_root"] for k in keys])
+        t = np.array([runs["%s_key%d" % (form, k)]["trials_per_s"] for k in keys])
+        return v.mean(), v.std(ddof=1) / np.sqrt(len(v)), t.mean()
+    if runs:
+        lf_, lf_se, tf_ = stats("rollouts")
+        ls_, ls_se, ts_ = stats("surrogate")
+        ef_, ef_se, _ = stats("rollouts_trials")
+        es_, es_se, _ = stats("surrogate_trials")
+        per_key = [abs(runs["surrogate_trials_key%d" % k]["l_root"] - runs["rollouts_trials_key%d" % k]["l_root"]) /
+                   max(abs(runs["rollouts_trials_key%d" % k]["l_root"]), 1e-9) for k in keys]
     net.close()
     return dict(
         config="RockSample 15x15, 15 rocks, uniform-random rollouts of depth 90; MLP 64-256-256-256-1 "
@@ -359,14 +378,24 @@ def surrogate_section(ctx, args):
                      vs_mean_of_16_rollouts=dict(
                          pair_mae_one_rollout=round(float(pe_one.mean()), 5),
                          pair_mae_surrogate=round(float(pe_sur.mean()), 5),
+                         pair_bias_surrogate=round(float(pb_sur.mean()), 5),
+                         child_l0_bias_surrogate=round(float(cb_sur.mean()), 5),
                          child_l0_mae_one_rollout=round(float(ce_one.mean()), 5),
                          child_l0_mae_surrogate=round(float(ce_sur.mean()), 5),
                          child_l0_p90_one_rollout=round(float(np.percentile(ce_one, 90)), 5),
                          child_l0_p90_surrogate=round(float(np.percentile(ce_sur, 90)), 5))),
         search=dict(threads=8, leaf_batch=8, budget_s=args.search_seconds, runs=runs,
-                    root_value_rel_err=round(abs(ls_ - lf_) / max(abs(lf_), 1e-9), 5),
-                    root_value_rel_diff_two_rollout_runs=round(
-                        abs(runs["rollouts_key4"]["l_root"] - lf_) / max(abs(lf_), 1e-9), 5) if runs else None))
+                    summary=dict(keys=list(keys), rollouts_trials_per_s=round(tf_, 1),
+                                 surrogate_trials_per_s=round(ts_, 1), trials_ratio=round(ts_ / tf_, 3),
+                                 l_root_rollouts=round(lf_, 5), l_root_rollouts_se=round(lf_se, 5),
+                                 l_root_surrogate=round(ls_, 5), l_root_surrogate_se=round(ls_se, 5),
+                                 root_value_rel_err=round(abs(ls_ - lf_) / max(abs(lf_), 1e-9), 5),
+                                 rollout_key_spread_rel=round(lf_se * np.sqrt(len(keys)) / max(abs(lf_), 1e-9), 5),
+                                 equal_trials=EQ_TRIALS, l_root_rollouts_eq=round(ef_, 5),
+                                 l_root_surrogate_eq=round(es_, 5),
+                                 root_value_rel_err_eq=round(abs(es_ - ef_) / max(abs(ef_), 1e-9), 5),
+                                 root_value_rel_err_eq_per_key=[round(v, 5) for v in per_key])
+                    if runs else None))
 
 
 def cpu_baseline(items, seconds):

@@ -9,6 +9,8 @@ the shuffling gather and the bookkeeping here are plain tensor plumbing.
 """
 from __future__ import annotations
 
+import math
+
 import torch
 
 from . import hdx as H
@@ -31,10 +33,11 @@ def leaf_pairs(ctx: "H.Context", model: "H.Model", out: "H.LeafBuffers", depth: 
 
 
 def fit(mlp: "H.Mlp", X: torch.Tensor, t: torch.Tensor, epochs: int, batch: int = 4096, lr: float = 1e-3,
-        seed: int = 0) -> list:
+        seed: int = 0, lr_final: float | None = None) -> list:
     """Adam on mean squared error over `epochs` passes of shuffled
     minibatches of `batch` rows (a multiple of 64; a ragged last batch is
-    dropped).  Returns the mean training loss of each epoch."""
+    dropped); with lr_final the rate follows a cosine from lr down to
+    lr_final over the epochs.  Returns the mean training loss of each epoch."""
     if batch % 64 or batch <= 0:
         raise ValueError("batch must be a positive multiple of 64")
     N = X.shape[0]
@@ -46,12 +49,15 @@ def fit(mlp: "H.Mlp", X: torch.Tensor, t: torch.Tensor, epochs: int, batch: int 
     loss = torch.zeros(1, dtype=torch.float32, device=X.device)
     acc = torch.zeros(1, dtype=torch.float32, device=X.device)
     hist = []
-    for _ in range(epochs):
+    for e in range(epochs):
+        rate = lr
+        if lr_final is not None and epochs > 1:
+            rate = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * e / (epochs - 1)))
         perm = torch.randperm(N, generator=g, device=X.device)
         Xs, ts = X[perm], t[perm]
         acc.zero_()
         for i in range(steps):
-            mlp.train_step(Xs[i * batch:(i + 1) * batch], ts[i * batch:(i + 1) * batch], lr, loss)
+            mlp.train_step(Xs[i * batch:(i + 1) * batch], ts[i * batch:(i + 1) * batch], rate, loss)
             acc += loss
         hist.append(float(acc) / steps)
     return hist
