@@ -233,18 +233,25 @@ hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *batch, const hdx_leaf *
 /* Launch schedule: workgroup size (multiple of 64; capped at 512 for
  * RockSample-only batches and 256 otherwise, and at what a size class's
  * leaves need), persistent workgroups per CU (0 = one workgroup per tile),
- * and the XCD-contiguous tile mapping.  Tiles launch per size class of their
- * leaf (class c holds leaves of 64*2^(c-1) < n <= 64*2^c scenarios, c =
- * 0..5); set_schedule applies to every class, set_class_schedule to one.
- * get_schedule reports the class with the most tiles.  Results are
- * bit-identical under every schedule. */
+ * and the XCD-contiguous tile mapping.  Tiles launch in groups of one model
+ * variant (0 RockSample; 1, 2, 3 driving with up to 8, 16, 32 pedestrians)
+ * and one size class of their leaf (class c holds leaves of 64*2^(c-1) < n
+ * <= 64*2^c scenarios, c = 0..5): group = variant * HDX_SIZE_CLASSES +
+ * class.  set_schedule applies to every group, set_class_schedule to the
+ * groups of one size class; get_group_schedule reports one group (and its
+ * tile count), get_class_schedule the class's group with the most tiles,
+ * get_schedule the group with the most tiles.  Results are bit-identical
+ * under every schedule. */
 #define HDX_SIZE_CLASSES 6
+#define HDX_LAUNCH_GROUPS 24
 hdx_status hdx_batch_set_schedule(hdx_ctx *ctx, hdx_batch *batch, int32_t threads, int32_t persistent,
                                   int32_t xcd_remap);
 hdx_status hdx_batch_set_class_schedule(hdx_ctx *ctx, hdx_batch *batch, int32_t size_class, int32_t threads,
                                         int32_t persistent, int32_t xcd_remap);
 hdx_status hdx_batch_get_class_schedule(const hdx_batch *batch, int32_t size_class, int32_t *threads,
                                         int32_t *persistent, int32_t *xcd_remap, int64_t *tiles);
+hdx_status hdx_batch_get_group_schedule(const hdx_batch *batch, int32_t group, int32_t *threads, int32_t *persistent,
+                                        int32_t *xcd_remap, int64_t *tiles);
 hdx_status hdx_batch_get_schedule(const hdx_batch *batch, int32_t *threads, int32_t *persistent,
                                   int32_t *xcd_remap);
 /* Launch through a captured HIP graph (captured on first use and again
@@ -252,11 +259,11 @@ hdx_status hdx_batch_get_schedule(const hdx_batch *batch, int32_t *threads, int3
 hdx_status hdx_batch_use_graph(hdx_ctx *ctx, hdx_batch *batch, int32_t enable);
 /* Expand every staged leaf: one kernel launch (or graph replay), no copies. */
 hdx_status hdx_batch_launch(hdx_ctx *ctx, hdx_batch *batch, hdx_stream stream);
-/* Autotuner (an internal stream; blocks until done): per size class, time
- * each candidate schedule `reps` times on that class's staged tiles alone;
- * then, as the classes run side by side, refine each class's schedule once
+/* Autotuner (an internal stream; blocks until done): per launch group, time
+ * each candidate schedule `reps` times on that group's staged tiles alone;
+ * then, as the groups run side by side, refine each group's schedule once
  * more against the whole launch.  *best_ms is the mean time of the chosen
- * whole launch (of the single class when there is one).  Outputs are
+ * whole launch (of the single group when there is one).  Outputs are
  * rewritten with identical values. */
 hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *batch, int32_t reps, float *best_ms);
 

@@ -173,30 +173,43 @@ int32_t variant_max_threads(const Variant &v);
 hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queue, int32_t n_tiles,
                          const Variant &v, const Schedule &sch, int32_t n_cu, hipStream_t stream);
 
-// Tiles are launched by size class of their leaf (n <= 64, 128, 256, 512,
-// 1024, 2048): each class gets an LDS carve-up and a workgroup size for its
-// own largest leaf, so small leaves do not pay for the largest one's
-// footprint (LDS is what limits resident workgroups per CU).  The tile
-// array is ordered by class; class c owns tiles [begin[c], begin[c] +
-// count[c]) and the queue d_queues[c].
+// Tiles are launched in groups of one model variant and one size class of
+// their leaf (n <= 64, 128, 256, 512, 1024, 2048).  A group gets the kernel
+// of its own model (RockSample tiles never run in the register budget of the
+// driving model) and an LDS carve-up and workgroup size for its own largest
+// leaf, so small leaves do not pay for the largest one's footprint (LDS is
+// what limits resident workgroups per CU).  Model variants: 0 RockSample,
+// 1-3 driving with up to 8, 16, 32 pedestrians.  Group g = variant *
+// kSizeClasses + size class; the tile array is ordered by group; group g
+// owns tiles [begin[g], begin[g] + count[g]) and the queue d_queues[g].
 constexpr int kSizeClasses = 6;
+constexpr int kModelVariants = 4;
+constexpr int kGroups = kModelVariants * kSizeClasses;
 __host__ __device__ inline int size_class(int32_t n) {
     int c = 0;
     while (c < kSizeClasses - 1 && n > (64 << c)) ++c;
     return c;
 }
+inline int model_variant(int32_t kind, int32_t n_peds) {
+    return kind == HDX_ROCKSAMPLE ? 0 : n_peds <= 8 ? 1 : n_peds <= 16 ? 2 : 3;
+}
+inline Variant group_variant(int g) {
+    const int v = g / kSizeClasses;
+    return v == 0 ? Variant{0, 1, 1} : Variant{1, v == 1 ? 8 : v == 2 ? 16 : 32, 1};
+}
 struct ClassPlan {
-    int64_t begin[kSizeClasses], count[kSizeClasses];
-    int32_t n_max[kSizeClasses];
+    int64_t begin[kGroups], count[kGroups];
+    int32_t n_max[kGroups];
 };
-// Stable reorder of tiles[0, n_tiles) by class; fills plan.
-void plan_classes(const LeafTask *tasks, Tile *tiles, int64_t n_tiles, ClassPlan *plan);
-// One launch per non-empty class in mask (bit c = class c); lds_n[c] sizes
-// class c's LDS (>= its n_max); sch[c] is its schedule (its width capped at
-// what the class's leaves need).
+// Stable reorder of tiles[0, n_tiles) by group (variant[leaf] is the leaf's
+// model variant); fills plan.
+void plan_classes(const LeafTask *tasks, const int8_t *variant, Tile *tiles, int64_t n_tiles, ClassPlan *plan);
+// One launch per non-empty group in mask (bit g = group g); lds_n[g] sizes
+// group g's LDS (>= its n_max); sch[g] is its schedule (its width capped at
+// what the group's leaves and model need).
 hipError_t launch_classes(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queues, const ClassPlan &plan,
-                          const Variant &v, const int32_t *lds_n, const Schedule *sch, int32_t n_cu,
-                          hipStream_t stream, uint32_t mask = 0xffffffffu);
+                          const int32_t *lds_n, const Schedule *sch, int32_t n_cu, hipStream_t stream,
+                          uint32_t mask = 0xffffffffu);
 // Default schedule of a class whose largest leaf has n_max scenarios: two
 // scenarios per lane up to 256 lanes, one workgroup per tile, XCD-contiguous.
 Schedule class_default_schedule(int32_t n_max, int32_t max_threads);

@@ -23,13 +23,13 @@ struct Slot {
     TileQueue *h_queue = nullptr, *d_queue = nullptr;
     int64_t cap_tasks = 0, cap_tiles = 0;
     hipEvent_t done = nullptr;
-    hipEvent_t fork = nullptr, join[kSizeClasses] = {};  // size classes run side by side
+    hipEvent_t fork = nullptr, join[kGroups] = {};  // launch groups run side by side
     bool used = false;
 };
 
 bool create_events(hipEvent_t *fork, hipEvent_t *join) {
     if (hipEventCreateWithFlags(fork, hipEventDisableTiming) != hipSuccess) return false;
-    for (int c = 0; c < kSizeClasses; ++c)
+    for (int c = 0; c < kGroups; ++c)
         if (hipEventCreateWithFlags(&join[c], hipEventDisableTiming) != hipSuccess) return false;
     return true;
 }
@@ -37,7 +37,7 @@ bool create_events(hipEvent_t *fork, hipEvent_t *join) {
 void destroy_events(hipEvent_t *fork, hipEvent_t *join) {
     if (*fork) hipEventDestroy(*fork);
     *fork = nullptr;
-    for (int c = 0; c < kSizeClasses; ++c) {
+    for (int c = 0; c < kGroups; ++c) {
         if (join[c]) hipEventDestroy(join[c]);
         join[c] = nullptr;
     }
@@ -58,7 +58,7 @@ struct hdx_ctx {
     std::mutex mu;
     Slot slots[kSlots];
     int next_slot = 0;
-    hipStream_t cls_stream[kSizeClasses] = {};  // one stream per size class (default priority)
+    hipStream_t cls_stream[kGroups] = {};  // one stream per launch group (default priority)
     Schedule sched{256, 0, 1};
     bool sched_fixed = false;
 };
@@ -92,7 +92,7 @@ hdx_status hdx_init(int32_t device, hdx_ctx **out) {
     hdx_ctx *ctx = new hdx_ctx();
     ctx->device = device;
     ctx->n_cu = prop.multiProcessorCount;
-    for (int c = 0; c < kSizeClasses; ++c)
+    for (int c = 0; c < kGroups; ++c)
         if (hipStreamCreateWithFlags(&ctx->cls_stream[c], hipStreamNonBlocking) != hipSuccess) {
             hdx_fini(ctx);
             return HDX_E_DEVICE;
@@ -102,9 +102,9 @@ hdx_status hdx_init(int32_t device, hdx_ctx **out) {
             hdx_fini(ctx);
             return HDX_E_DEVICE;
         }
-        if (hipMalloc(&s.d_queue, kSizeClasses * sizeof(TileQueue)) != hipSuccess ||
-            hipHostMalloc(&s.h_queue, kSizeClasses * sizeof(TileQueue)) != hipSuccess ||
-            hipMemset(s.d_queue, 0, kSizeClasses * sizeof(TileQueue)) != hipSuccess) {
+        if (hipMalloc(&s.d_queue, kGroups * sizeof(TileQueue)) != hipSuccess ||
+            hipHostMalloc(&s.h_queue, kGroups * sizeof(TileQueue)) != hipSuccess ||
+            hipMemset(s.d_queue, 0, kGroups * sizeof(TileQueue)) != hipSuccess) {
             hdx_fini(ctx);
             return HDX_E_NOMEM;
         }
@@ -131,7 +131,7 @@ hdx_status hdx_fini(hdx_ctx *ctx) {
         if (s.done) hipEventDestroy(s.done);
         destroy_events(&s.fork, s.join);
     }
-    for (int c = 0; c < kSizeClasses; ++c)
+    for (int c = 0; c < kGroups; ++c)
         if (ctx->cls_stream[c]) hipStreamDestroy(ctx->cls_stream[c]);
     delete ctx;
     return HDX_OK;
@@ -437,29 +437,29 @@ void pack_leaves(const hdx_leaf *leaves, int32_t n_leaves, LeafTask *tasks, Tile
 // one workgroup per tile, consecutive tiles kept on one XCD.
 }  // namespace
 
-void hdx::plan_classes(const LeafTask *tasks, Tile *tiles, int64_t n_tiles, ClassPlan *plan) {
-    int64_t cnt[kSizeClasses] = {0};
-    for (int c = 0; c < kSizeClasses; ++c) plan->n_max[c] = 0;
+void hdx::plan_classes(const LeafTask *tasks, const int8_t *variant, Tile *tiles, int64_t n_tiles,
+                       ClassPlan *plan) {
+    auto group = [&](const Tile &t) { return variant[t.leaf] * kSizeClasses + size_class(tasks[t.leaf].n); };
+    int64_t cnt[kGroups] = {0};
+    for (int g = 0; g < kGroups; ++g) plan->n_max[g] = 0;
     for (int64_t t = 0; t < n_tiles; ++t) {
-        const int32_t n = tasks[tiles[t].leaf].n;
-        const int c = size_class(n);
-        cnt[c]++;
-        if (n > plan->n_max[c]) plan->n_max[c] = n;
+        const int g = group(tiles[t]);
+        cnt[g]++;
+        plan->n_max[g] = std::max(plan->n_max[g], tasks[tiles[t].leaf].n);
     }
     int64_t at = 0;
-    for (int c = 0; c < kSizeClasses; ++c) {
-        plan->begin[c] = at;
-        plan->count[c] = cnt[c];
-        at += cnt[c];
+    for (int g = 0; g < kGroups; ++g) {
+        plan->begin[g] = at;
+        plan->count[g] = cnt[g];
+        at += cnt[g];
     }
     bool sorted = true;
-    for (int64_t t = 1; t < n_tiles && sorted; ++t)
-        sorted = size_class(tasks[tiles[t - 1].leaf].n) <= size_class(tasks[tiles[t].leaf].n);
+    for (int64_t t = 1; t < n_tiles && sorted; ++t) sorted = group(tiles[t - 1]) <= group(tiles[t]);
     if (sorted) return;
     std::vector<Tile> tmp(tiles, tiles + n_tiles);
-    int64_t pos[kSizeClasses];
-    for (int c = 0; c < kSizeClasses; ++c) pos[c] = plan->begin[c];
-    for (const Tile &t : tmp) tiles[pos[size_class(tasks[t.leaf].n)]++] = t;
+    int64_t pos[kGroups];
+    for (int g = 0; g < kGroups; ++g) pos[g] = plan->begin[g];
+    for (const Tile &t : tmp) tiles[pos[group(t)]++] = t;
 }
 
 Schedule hdx::class_default_schedule(int32_t n_max, int32_t max_threads) {
@@ -471,17 +471,17 @@ Schedule hdx::class_default_schedule(int32_t n_max, int32_t max_threads) {
 }
 
 hipError_t hdx::launch_classes(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queues,
-                               const ClassPlan &plan, const Variant &v, const int32_t *lds_n, const Schedule *sch,
-                               int32_t n_cu, hipStream_t stream, uint32_t mask) {
-    for (int c = 0; c < kSizeClasses; ++c) {
-        if (plan.count[c] == 0 || !(mask & (1u << c))) continue;
-        Variant vc = v;
-        vc.n_max = std::max(lds_n[c], plan.n_max[c]);
-        // a workgroup no wider than the class's leaves need
-        const int need = std::max(64, pow2_at_least(std::max(vc.n_max, 1)));
-        Schedule sc = sch[c];
+                               const ClassPlan &plan, const int32_t *lds_n, const Schedule *sch, int32_t n_cu,
+                               hipStream_t stream, uint32_t mask) {
+    for (int g = 0; g < kGroups; ++g) {
+        if (plan.count[g] == 0 || !(mask & (1u << g))) continue;
+        Variant vg = group_variant(g);
+        vg.n_max = std::max(lds_n[g], plan.n_max[g]);
+        // a workgroup no wider than the group's leaves need
+        const int need = std::min(variant_max_threads(vg), std::max(64, pow2_at_least(std::max(vg.n_max, 1))));
+        Schedule sc = sch[g];
         if (sc.threads > need) sc.threads = need;
-        const hipError_t e = launch_expand(d_tasks, d_tiles + plan.begin[c], d_queues + c, (int32_t)plan.count[c], vc,
+        const hipError_t e = launch_expand(d_tasks, d_tiles + plan.begin[g], d_queues + g, (int32_t)plan.count[g], vg,
                                            sc, n_cu, stream);
         if (e != hipSuccess) return e;
     }
@@ -490,30 +490,39 @@ hipError_t hdx::launch_classes(const LeafTask *d_tasks, const Tile *d_tiles, Til
 
 namespace {
 
-// Each non-empty class of `mask` on its own stream, forked from `st` and
-// joined back into it (inside a stream capture this becomes parallel graph
-// branches), so one class's slow tail overlaps the others; a single class
-// launches on `st` directly.
+// Each non-empty group of `mask` on a stream of its own, forked from `st`
+// and joined back into it (inside a stream capture this becomes parallel
+// graph branches), so one group's slow tail overlaps the others; a single
+// group launches on `st` directly.
 hipError_t launch_classes_forked(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queues,
-                                 const ClassPlan &plan, const Variant &v, const int32_t *lds_n, const Schedule *sch,
-                                 int32_t n_cu, hipStream_t st, const hipStream_t *cls, hipEvent_t fork,
-                                 const hipEvent_t *join, uint32_t mask = 0xffffffffu) {
+                                 const ClassPlan &plan, const int32_t *lds_n, const Schedule *sch, int32_t n_cu,
+                                 hipStream_t st, const hipStream_t *cls, hipEvent_t fork, const hipEvent_t *join,
+                                 uint32_t mask = 0xffffffffu) {
     int active = 0;
-    for (int c = 0; c < kSizeClasses; ++c)
-        if (plan.count[c] > 0 && (mask & (1u << c))) ++active;
-    if (active <= 1) return launch_classes(d_tasks, d_tiles, d_queues, plan, v, lds_n, sch, n_cu, st, mask);
+    for (int g = 0; g < kGroups; ++g)
+        if (plan.count[g] > 0 && (mask & (1u << g))) ++active;
+    if (active <= 1) return launch_classes(d_tasks, d_tiles, d_queues, plan, lds_n, sch, n_cu, st, mask);
     hipError_t e = hipEventRecord(fork, st);
-    // largest class first: its tail is the longest
-    for (int c = kSizeClasses - 1; c >= 0 && e == hipSuccess; --c) {
-        if (plan.count[c] == 0 || !(mask & (1u << c))) continue;
-        e = hipStreamWaitEvent(cls[c], fork, 0);
-        if (e == hipSuccess) e = launch_classes(d_tasks, d_tiles, d_queues, plan, v, lds_n, sch, n_cu, cls[c], 1u << c);
-        if (e == hipSuccess) e = hipEventRecord(join[c], cls[c]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, join[c], 0);
-    }
+    // largest leaves first: their tails are the longest
+    for (int c = kSizeClasses - 1; c >= 0 && e == hipSuccess; --c)
+        for (int v = kModelVariants - 1; v >= 0 && e == hipSuccess; --v) {
+            const int g = v * kSizeClasses + c;
+            if (plan.count[g] == 0 || !(mask & (1u << g))) continue;
+            e = hipStreamWaitEvent(cls[g], fork, 0);
+            if (e == hipSuccess) e = launch_classes(d_tasks, d_tiles, d_queues, plan, lds_n, sch, n_cu, cls[g], 1u << g);
+            if (e == hipSuccess) e = hipEventRecord(join[g], cls[g]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, join[g], 0);
+        }
     return e;
 }
 
+// Model variant of each leaf (its launch-group row).
+void leaf_variants(const hdx_leaf *leaves, int32_t n_leaves, int8_t *out) {
+    for (int32_t i = 0; i < n_leaves; ++i) {
+        const hdx_model_desc &d = *hdx_internal_desc(leaves[i].model);
+        out[i] = (int8_t)model_variant(d.kind, d.n_peds);
+    }
+}
 
 hdx_status grow_pinned(hdx_ctx *ctx, LeafTask **h_tasks, LeafTask **d_tasks, int64_t *cap_tasks, Tile **h_tiles,
                        Tile **d_tiles, int64_t *cap_tiles, int64_t need_tasks, int64_t need_tiles) {
@@ -577,21 +586,23 @@ hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
                      sh.n_tiles);
     if (st != HDX_OK) return st;
     pack_leaves(leaves, n_leaves, s.h_tasks, s.h_tiles);
+    std::vector<int8_t> var(n_leaves);
+    leaf_variants(leaves, n_leaves, var.data());
     ClassPlan plan;
-    plan_classes(s.h_tasks, s.h_tiles, sh.n_tiles, &plan);
-    for (int c = 0; c < kSizeClasses; ++c) s.h_queue[c] = TileQueue{0, 0, (int32_t)plan.count[c], 0};
+    plan_classes(s.h_tasks, var.data(), s.h_tiles, sh.n_tiles, &plan);
+    for (int g = 0; g < kGroups; ++g) s.h_queue[g] = TileQueue{0, 0, (int32_t)plan.count[g], 0};
     hipStream_t hs = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(s.d_tasks, s.h_tasks, n_leaves * sizeof(LeafTask), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(s.d_tiles, s.h_tiles, sh.n_tiles * sizeof(Tile), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(s.d_queue, s.h_queue, kSizeClasses * sizeof(TileQueue), hipMemcpyHostToDevice, hs);
+        e = hipMemcpyAsync(s.d_queue, s.h_queue, kGroups * sizeof(TileQueue), hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return hip_fail(ctx, e, "descriptor copy");
-    const Variant v = pick_variant(sh.has_rs, sh.has_ped, sh.ped_max, sh.n_max);
-    const int32_t no_lds[kSizeClasses] = {0, 0, 0, 0, 0, 0};
-    Schedule sch[kSizeClasses];
-    for (int c = 0; c < kSizeClasses; ++c)
-        sch[c] = ctx->sched_fixed ? ctx->sched : class_default_schedule(plan.n_max[c], variant_max_threads(v));
-    e = launch_classes_forked(s.d_tasks, s.d_tiles, s.d_queue, plan, v, no_lds, sch, ctx->n_cu, hs, ctx->cls_stream,
+    int32_t no_lds[kGroups] = {};
+    Schedule sch[kGroups];
+    for (int g = 0; g < kGroups; ++g)
+        sch[g] = ctx->sched_fixed ? ctx->sched
+                                  : class_default_schedule(plan.n_max[g], variant_max_threads(group_variant(g)));
+    e = launch_classes_forked(s.d_tasks, s.d_tiles, s.d_queue, plan, no_lds, sch, ctx->n_cu, hs, ctx->cls_stream,
                               s.fork, s.join);
     if (e != hipSuccess) return hip_fail(ctx, e, "expand launch");
     e = hipEventRecord(s.done, hs);
@@ -609,39 +620,36 @@ struct hdx_batch {
     int64_t max_leaves = 0, max_tiles = 0;  // capacity the caller asked for
     int32_t n_leaves = 0;
     int64_t n_tiles = 0;
-    Variant var{0, 1, 1};
-    int32_t lds_n = 1;  // largest leaf seen
     ClassPlan plan{};
-    int32_t lds_c[kSizeClasses] = {0, 0, 0, 0, 0, 0};  // per class: largest leaf seen
+    int32_t lds_c[kGroups] = {};  // per launch group: largest leaf seen
     ClassPlan g_plan{};
-    int32_t g_lds[kSizeClasses] = {0, 0, 0, 0, 0, 0};
-    Schedule sched[kSizeClasses];  // per size class
-    bool sched_set[kSizeClasses] = {false, false, false, false, false, false};
-    hipStream_t work = nullptr;  // capture and tuning stream
-    hipStream_t cls[kSizeClasses] = {};  // size classes side by side
-    hipEvent_t fork = nullptr, join[kSizeClasses] = {};
+    int32_t g_lds[kGroups] = {};
+    Schedule sched[kGroups];  // per launch group
+    bool sched_set[kGroups] = {};
+    hipStream_t work = nullptr;      // capture and tuning stream
+    hipStream_t cls[kGroups] = {};  // launch groups side by side
+    hipEvent_t fork = nullptr, join[kGroups] = {};
     hipEvent_t staged = nullptr, t0 = nullptr, t1 = nullptr;
     bool staged_used = false;
     bool graph_on = false, graph_ok = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    Variant g_var{0, 1, 1};
-    Schedule g_sched[kSizeClasses];
+    Schedule g_sched[kGroups];
     int64_t g_tiles = 0;
 };
 
 namespace {
 
-Variant batch_variant(const hdx_batch *b) {
-    Variant v = b->var;
-    v.n_max = b->lds_n;
-    return v;
-}
-
 hipError_t batch_direct_launch(hdx_ctx *ctx, hdx_batch *b, const Schedule *s, hipStream_t st,
                                uint32_t mask = 0xffffffffu) {
-    return launch_classes_forked(b->d_tasks, b->d_tiles, b->d_queue, b->plan, b->var, b->lds_c, s, ctx->n_cu, st,
-                                 b->cls, b->fork, b->join, mask);
+    return launch_classes_forked(b->d_tasks, b->d_tiles, b->d_queue, b->plan, b->lds_c, s, ctx->n_cu, st, b->cls,
+                                 b->fork, b->join, mask);
+}
+
+// Widest workgroup group g can use: its model's cap and its leaves' need.
+int32_t group_width_cap(const hdx_batch *b, int g) {
+    const int32_t n_max = std::max(b->lds_c[g], b->plan.n_max[g]);
+    return std::min(variant_max_threads(group_variant(g)), std::max(64, pow2_at_least(std::max(n_max, 1))));
 }
 
 bool same_schedule(const Schedule &a, const Schedule &b) {
@@ -669,14 +677,14 @@ hdx_status hdx_batch_create(hdx_ctx *ctx, int32_t max_leaves, int64_t max_tiles,
     hdx_status st = grow_pinned(ctx, &b->h_tasks, &b->d_tasks, &b->cap_tasks, &b->h_tiles, &b->d_tiles, &b->cap_tiles,
                                 max_leaves, max_tiles);
     if (st == HDX_OK &&
-        (hipHostMalloc(&b->h_queue, kSizeClasses * sizeof(TileQueue)) != hipSuccess ||
-         hipMalloc(&b->d_queue, kSizeClasses * sizeof(TileQueue)) != hipSuccess ||
-         hipMemset(b->d_queue, 0, kSizeClasses * sizeof(TileQueue)) != hipSuccess ||
+        (hipHostMalloc(&b->h_queue, kGroups * sizeof(TileQueue)) != hipSuccess ||
+         hipMalloc(&b->d_queue, kGroups * sizeof(TileQueue)) != hipSuccess ||
+         hipMemset(b->d_queue, 0, kGroups * sizeof(TileQueue)) != hipSuccess ||
          hipStreamCreateWithFlags(&b->work, hipStreamNonBlocking) != hipSuccess || !create_events(&b->fork, b->join) ||
          hipEventCreate(&b->staged) != hipSuccess || hipEventCreate(&b->t0) != hipSuccess ||
          hipEventCreate(&b->t1) != hipSuccess))
         st = fail(ctx, HDX_E_NOMEM, "batch allocation");
-    for (int c = 0; c < kSizeClasses && st == HDX_OK; ++c)
+    for (int c = 0; c < kGroups && st == HDX_OK; ++c)
         if (hipStreamCreateWithFlags(&b->cls[c], hipStreamNonBlocking) != hipSuccess)
             st = fail(ctx, HDX_E_NOMEM, "batch streams");
     if (st == HDX_OK && hipDeviceSynchronize() != hipSuccess) st = fail(ctx, HDX_E_DEVICE, "batch allocation");
@@ -700,7 +708,7 @@ hdx_status hdx_batch_destroy(hdx_ctx *ctx, hdx_batch *b) {
     if (b->d_tiles) hipFree(b->d_tiles);
     if (b->d_queue) hipFree(b->d_queue);
     if (b->work) hipStreamDestroy(b->work);
-    for (int c = 0; c < kSizeClasses; ++c)
+    for (int c = 0; c < kGroups; ++c)
         if (b->cls[c]) hipStreamDestroy(b->cls[c]);
     destroy_events(&b->fork, b->join);
     if (b->staged) hipEventDestroy(b->staged);
@@ -723,11 +731,13 @@ hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *b, const hdx_leaf *leav
         if (e != hipSuccess) return hip_fail(ctx, e, "staging wait");
     }
     pack_leaves(leaves, n_leaves, b->h_tasks, b->h_tiles);
-    plan_classes(b->h_tasks, b->h_tiles, sh.n_tiles, &b->plan);
-    for (int c = 0; c < kSizeClasses; ++c) {
-        b->h_queue[c] = TileQueue{0, 0, (int32_t)b->plan.count[c], 0};
-        // LDS sized for the largest leaf a class has seen, so graphs survive smaller batches
-        b->lds_c[c] = std::max(b->lds_c[c], b->plan.n_max[c]);
+    std::vector<int8_t> var(std::max(n_leaves, 1));
+    leaf_variants(leaves, n_leaves, var.data());
+    plan_classes(b->h_tasks, var.data(), b->h_tiles, sh.n_tiles, &b->plan);
+    for (int g = 0; g < kGroups; ++g) {
+        b->h_queue[g] = TileQueue{0, 0, (int32_t)b->plan.count[g], 0};
+        // LDS sized for the largest leaf a group has seen, so graphs survive smaller batches
+        b->lds_c[g] = std::max(b->lds_c[g], b->plan.n_max[g]);
     }
     hipStream_t hs = (hipStream_t)stream;
     hipError_t e = hipSuccess;
@@ -735,17 +745,15 @@ hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *b, const hdx_leaf *leav
     if (e == hipSuccess && sh.n_tiles > 0)
         e = hipMemcpyAsync(b->d_tiles, b->h_tiles, sh.n_tiles * sizeof(Tile), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_queue, b->h_queue, kSizeClasses * sizeof(TileQueue), hipMemcpyHostToDevice, hs);
+        e = hipMemcpyAsync(b->d_queue, b->h_queue, kGroups * sizeof(TileQueue), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipEventRecord(b->staged, hs);
     if (e != hipSuccess) return hip_fail(ctx, e, "batch descriptor copy");
     b->staged_used = true;
     b->n_leaves = n_leaves;
     b->n_tiles = sh.n_tiles;
-    b->var = pick_variant(sh.has_rs, sh.has_ped, sh.ped_max, sh.n_max);
-    if (sh.n_max > b->lds_n) b->lds_n = sh.n_max;
-    for (int c = 0; c < kSizeClasses; ++c)
-        if (!b->sched_set[c])
-            b->sched[c] = class_default_schedule(std::max(b->lds_c[c], 1), variant_max_threads(b->var));
+    for (int g = 0; g < kGroups; ++g)
+        if (!b->sched_set[g])
+            b->sched[g] = class_default_schedule(std::max(b->lds_c[g], 1), variant_max_threads(group_variant(g)));
     return HDX_OK;
 }
 
@@ -754,9 +762,9 @@ hdx_status hdx_batch_set_schedule(hdx_ctx *ctx, hdx_batch *b, int32_t threads, i
     if (!ctx || !b) return HDX_E_INVALID;
     if (threads < 64 || threads > 1024 || threads % 64 != 0 || persistent < 0 || persistent > 64)
         return fail(ctx, HDX_E_INVALID, "schedule");
-    for (int c = 0; c < kSizeClasses; ++c) {
-        b->sched[c] = Schedule{threads, persistent, xcd_remap ? 1 : 0};
-        b->sched_set[c] = true;
+    for (int g = 0; g < kGroups; ++g) {
+        b->sched[g] = Schedule{threads, persistent, xcd_remap ? 1 : 0};
+        b->sched_set[g] = true;
     }
     return HDX_OK;
 }
@@ -767,31 +775,47 @@ hdx_status hdx_batch_set_class_schedule(hdx_ctx *ctx, hdx_batch *b, int32_t cls,
     if (cls < 0 || cls >= kSizeClasses || threads < 64 || threads > 1024 || threads % 64 != 0 || persistent < 0 ||
         persistent > 64)
         return fail(ctx, HDX_E_INVALID, "schedule");
-    b->sched[cls] = Schedule{threads, persistent, xcd_remap ? 1 : 0};
-    b->sched_set[cls] = true;
+    for (int v = 0; v < kModelVariants; ++v) {
+        b->sched[v * kSizeClasses + cls] = Schedule{threads, persistent, xcd_remap ? 1 : 0};
+        b->sched_set[v * kSizeClasses + cls] = true;
+    }
+    return HDX_OK;
+}
+
+hdx_status hdx_batch_get_group_schedule(const hdx_batch *b, int32_t group, int32_t *threads, int32_t *persistent,
+                                        int32_t *xcd_remap, int64_t *tiles) {
+    if (!b || !threads || !persistent || !xcd_remap || group < 0 || group >= kGroups) return HDX_E_INVALID;
+    const Schedule &s = b->sched[group];
+    const int32_t cap = group_width_cap(b, group);
+    *threads = s.threads > cap ? cap : s.threads;
+    *persistent = s.persistent;
+    *xcd_remap = s.xcd_remap;
+    if (tiles) *tiles = b->plan.count[group];
     return HDX_OK;
 }
 
 hdx_status hdx_batch_get_class_schedule(const hdx_batch *b, int32_t cls, int32_t *threads, int32_t *persistent,
                                         int32_t *xcd_remap, int64_t *tiles) {
     if (!b || !threads || !persistent || !xcd_remap || cls < 0 || cls >= kSizeClasses) return HDX_E_INVALID;
-    const Schedule &s = b->sched[cls];
-    const int32_t n_max = std::max(b->lds_c[cls], b->plan.n_max[cls]);
-    const int32_t need = std::max(64, pow2_at_least(std::max(n_max, 1)));
-    const int32_t cap = std::min(need, variant_max_threads(b->var));
-    *threads = s.threads > cap ? cap : s.threads;
-    *persistent = s.persistent;
-    *xcd_remap = s.xcd_remap;
-    if (tiles) *tiles = b->plan.count[cls];
-    return HDX_OK;
+    // the class's group with the most tiles
+    int best = cls;
+    int64_t total = 0;
+    for (int v = 0; v < kModelVariants; ++v) {
+        const int g = v * kSizeClasses + cls;
+        total += b->plan.count[g];
+        if (b->plan.count[g] > b->plan.count[best]) best = g;
+    }
+    const hdx_status st = hdx_batch_get_group_schedule(b, best, threads, persistent, xcd_remap, nullptr);
+    if (tiles) *tiles = total;
+    return st;
 }
 
 hdx_status hdx_batch_get_schedule(const hdx_batch *b, int32_t *threads, int32_t *persistent, int32_t *xcd_remap) {
     if (!b || !threads || !persistent || !xcd_remap) return HDX_E_INVALID;
     int big = 0;
-    for (int c = 1; c < kSizeClasses; ++c)
-        if (b->plan.count[c] > b->plan.count[big]) big = c;
-    return hdx_batch_get_class_schedule(b, big, threads, persistent, xcd_remap, nullptr);
+    for (int g = 1; g < kGroups; ++g)
+        if (b->plan.count[g] > b->plan.count[big]) big = g;
+    return hdx_batch_get_group_schedule(b, big, threads, persistent, xcd_remap, nullptr);
 }
 
 hdx_status hdx_batch_use_graph(hdx_ctx *ctx, hdx_batch *b, int32_t enable) {
@@ -810,16 +834,14 @@ hdx_status hdx_batch_launch(hdx_ctx *ctx, hdx_batch *b, hdx_stream stream) {
         e = batch_direct_launch(ctx, b, b->sched, hs);
         return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "batch launch");
     }
-    const Variant v = batch_variant(b);
-    // the graph bakes in each class's tile offset, LDS size and (non-persistent) grid
-    bool classes_same = true;
-    for (int c = 0; c < kSizeClasses; ++c)
-        classes_same = classes_same && b->plan.begin[c] == b->g_plan.begin[c] && b->lds_c[c] == b->g_lds[c] &&
-                       same_schedule(b->sched[c], b->g_sched[c]) &&
-                       (b->sched[c].persistent > 0 ? (b->plan.count[c] > 0) == (b->g_plan.count[c] > 0)
-                                                   : b->plan.count[c] == b->g_plan.count[c]);
-    const bool same = b->graph_ok && classes_same && v.mode == b->g_var.mode && v.pm == b->g_var.pm &&
-                      v.n_max == b->g_var.n_max;
+    // the graph bakes in each group's tile offset, LDS size and (non-persistent) grid
+    bool groups_same = true;
+    for (int g = 0; g < kGroups; ++g)
+        groups_same = groups_same && b->plan.begin[g] == b->g_plan.begin[g] && b->lds_c[g] == b->g_lds[g] &&
+                      same_schedule(b->sched[g], b->g_sched[g]) &&
+                      (b->sched[g].persistent > 0 ? (b->plan.count[g] > 0) == (b->g_plan.count[g] > 0)
+                                                  : b->plan.count[g] == b->g_plan.count[g]);
+    const bool same = b->graph_ok && groups_same;
     if (!same) {
         drop_graph(b);
         e = hipStreamBeginCapture(b->work, hipStreamCaptureModeThreadLocal);
@@ -834,12 +856,11 @@ hdx_status hdx_batch_launch(hdx_ctx *ctx, hdx_batch *b, hdx_stream stream) {
             return hip_fail(ctx, e, "graph instantiate");
         }
         b->graph_ok = true;
-        b->g_var = v;
         b->g_tiles = b->n_tiles;
         b->g_plan = b->plan;
-        for (int c = 0; c < kSizeClasses; ++c) {
-            b->g_lds[c] = b->lds_c[c];
-            b->g_sched[c] = b->sched[c];
+        for (int g = 0; g < kGroups; ++g) {
+            b->g_lds[g] = b->lds_c[g];
+            b->g_sched[g] = b->sched[g];
         }
     }
     e = hipGraphLaunch(b->exec, hs);
@@ -851,11 +872,8 @@ hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *b, int32_t reps, float *b
     if (b->n_tiles == 0) return HDX_OK;
     hipSetDevice(ctx->device);
     if (b->staged_used) hipEventSynchronize(b->staged);
-    const Variant v = batch_variant(b);
-    const int tmax = variant_max_threads(v);
     auto candidates = [&](int c) {
-        const int32_t n_max = std::max(b->lds_c[c], b->plan.n_max[c]);
-        const int cap = std::min(tmax, std::max(64, pow2_at_least(std::max(n_max, 1))));
+        const int cap = group_width_cap(b, c);
         std::vector<Schedule> cand;
         for (int th = 64; th <= cap; th *= 2) {
             cand.push_back(Schedule{th, 0, 0});
@@ -876,12 +894,12 @@ hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *b, int32_t reps, float *b
         return e;
     };
     int active = 0;
-    for (int c = 0; c < kSizeClasses; ++c) active += b->plan.count[c] > 0;
-    // 1: each size class on its own launch
-    Schedule trial[kSizeClasses];
-    for (int k = 0; k < kSizeClasses; ++k) trial[k] = b->sched[k];
+    for (int c = 0; c < kGroups; ++c) active += b->plan.count[c] > 0;
+    // 1: each launch group on its own launch
+    Schedule trial[kGroups];
+    for (int k = 0; k < kGroups; ++k) trial[k] = b->sched[k];
     float total = 0.0f;
-    for (int c = 0; c < kSizeClasses; ++c) {
+    for (int c = 0; c < kGroups; ++c) {
         if (b->plan.count[c] == 0) continue;
         float best = 1e30f;
         Schedule best_s = b->sched[c];
@@ -898,13 +916,13 @@ hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *b, int32_t reps, float *b
         trial[c] = best_s;
         total += best;
     }
-    // 2: the classes run side by side, so each class's schedule is refined
+    // 2: the groups run side by side, so each group's schedule is refined
     // once more against the whole launch with the others at their choice
     if (active > 1) {
         float best = 0.0f;
         hipError_t e = time_launch(trial, 0xffffffffu, &best);
         if (e != hipSuccess) return hip_fail(ctx, e, "autotune launch");
-        for (int c = kSizeClasses - 1; c >= 0; --c) {
+        for (int c = kGroups - 1; c >= 0; --c) {
             if (b->plan.count[c] == 0) continue;
             const Schedule keep = trial[c];
             Schedule best_s = keep;
@@ -923,7 +941,7 @@ hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *b, int32_t reps, float *b
         }
         total = best;
     }
-    for (int c = 0; c < kSizeClasses; ++c)
+    for (int c = 0; c < kGroups; ++c)
         if (b->plan.count[c] > 0) {
             b->sched[c] = trial[c];
             b->sched_set[c] = true;

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libhdx.so")
 ROCKSAMPLE, PEDNAV = 0, 1
 POLICY_DEFAULT, POLICY_CONST, POLICY_RANDOM = 0, 1, 2
 SIZE_CLASSES = 6
+LAUNCH_GROUPS = 24  # model variant (RockSample; driving <= 8, 16, 32 pedestrians) x size class
 MAX_LEAF_SCENARIOS = 2048
 MAX_HORIZON = 4096
 
@@ -100,7 +101,7 @@ EXPORTS = ["hdx_version", "hdx_init", "hdx_fini", "hdx_last_error", "hdx_upload_
            "hdx_sample_scenarios", "hdx_expand_leaf", "hdx_rollout_bounds", "hdx_philox",
            "hdx_fp32_selftest", "hdx_batch_create", "hdx_batch_destroy", "hdx_batch_set_leaves",
            "hdx_batch_set_schedule", "hdx_batch_get_schedule", "hdx_batch_use_graph",
-           "hdx_batch_set_class_schedule", "hdx_batch_get_class_schedule",
+           "hdx_batch_set_class_schedule", "hdx_batch_get_class_schedule", "hdx_batch_get_group_schedule",
            "hdx_batch_launch", "hdx_batch_autotune", "hdx_search", "hdx_mlp_create", "hdx_mlp_destroy",
            "hdx_mlp_get_params", "hdx_mlp_set_params", "hdx_mlp_forward", "hdx_mlp_gradients",
            "hdx_mlp_train_step", "hdx_features", "hdx_expand_leaf_surrogate", "hdx_mlp_save", "hdx_mlp_load",
@@ -142,6 +143,8 @@ def load_library():
     L.hdx_batch_get_schedule.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]
     L.hdx_batch_set_class_schedule.argtypes = [P, P, I32, I32, I32, I32]
     L.hdx_batch_get_class_schedule.argtypes = [P, I32, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32),
+                                               C.POINTER(I64)]
+    L.hdx_batch_get_group_schedule.argtypes = [P, I32, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32),
                                                C.POINTER(I64)]
     L.hdx_batch_use_graph.argtypes = [P, P, I32]
     L.hdx_batch_launch.argtypes = [P, P, P]
@@ -500,6 +503,17 @@ class Batch:
                                                                   C.byref(n)))
             if n.value:
                 out.append((c, t.value, p.value, x.value, n.value))
+        return out
+
+    def group_schedules(self) -> list:
+        """[(model_variant, size_class, threads, persistent, xcd_remap, tiles)] of the non-empty groups."""
+        out = []
+        for g in range(LAUNCH_GROUPS):
+            t, p, x, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+            self.ctx._check(self.lib.hdx_batch_get_group_schedule(self.handle, g, C.byref(t), C.byref(p), C.byref(x),
+                                                                  C.byref(n)))
+            if n.value:
+                out.append((g // SIZE_CLASSES, g % SIZE_CLASSES, t.value, p.value, x.value, n.value))
         return out
 
     def use_graph(self, enable: bool = True):
