@@ -564,10 +564,9 @@ def main():
                        "%d synthetic leaves",
                  mix64="MIX64: 64 planner instances (RockSample 7..20 / driving, K in {100,200,500}); "
                        "%d leaves in one launch")
-    t, p, x = batch.schedule()
     variants = ("rocksample", "driving<=8", "driving<=16", "driving<=32")
-    per_class = [dict(model=variants[v], max_n=64 << c, tiles=n, threads=ct, persistent=cp, xcd_remap=cx)
-                 for v, c, ct, cp, cx, n in batch.group_schedules()]
+    per_class = [dict(model=variants[v], max_n=64 << c, tiles=n, threads=ct, persistent=cp, xcd_remap=cx, span=cs)
+                 for v, c, ct, cp, cx, cs, n in batch.group_schedules()]
     out = dict(metric=METRIC, value=round(value, 1), unit="scenario-steps/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(wall * 1e3 / args.steps, 4), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="int32+fp32", data="synthetic",

@@ -232,8 +232,13 @@ hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *batch, const hdx_leaf *
                                 hdx_stream stream);
 /* Launch schedule: workgroup size (multiple of 64; capped at 512 for
  * RockSample-only batches and 256 otherwise, and at what a size class's
- * leaves need), persistent workgroups per CU (0 = one workgroup per tile),
- * and the XCD-contiguous tile mapping.  Tiles launch in groups of one model
+ * leaves need), persistent workgroups per CU (0 = one workgroup per span),
+ * the XCD-contiguous tile mapping, and the span: how many consecutive tiles
+ * (1..32) a workgroup takes at once.  The tiles of a leaf are consecutive,
+ * and a RockSample workgroup that takes several of them gathers and updates
+ * the leaf's scenarios and draws their sensor words once for all of them
+ * (the persistent form takes whole spans while many tiles remain, then
+ * single tiles).  Tiles launch in groups of one model
  * variant (0 RockSample; 1, 2, 3 driving with up to 8, 16, 32 pedestrians)
  * and one size class of their leaf (class c holds leaves of 64*2^(c-1) < n
  * <= 64*2^c scenarios, c = 0..5): group = variant * HDX_SIZE_CLASSES +
@@ -245,15 +250,16 @@ hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *batch, const hdx_leaf *
 #define HDX_SIZE_CLASSES 6
 #define HDX_LAUNCH_GROUPS 24
 hdx_status hdx_batch_set_schedule(hdx_ctx *ctx, hdx_batch *batch, int32_t threads, int32_t persistent,
-                                  int32_t xcd_remap);
+                                  int32_t xcd_remap, int32_t span);
 hdx_status hdx_batch_set_class_schedule(hdx_ctx *ctx, hdx_batch *batch, int32_t size_class, int32_t threads,
-                                        int32_t persistent, int32_t xcd_remap);
+                                        int32_t persistent, int32_t xcd_remap, int32_t span);
+/* span and tiles may be NULL. */
 hdx_status hdx_batch_get_class_schedule(const hdx_batch *batch, int32_t size_class, int32_t *threads,
-                                        int32_t *persistent, int32_t *xcd_remap, int64_t *tiles);
+                                        int32_t *persistent, int32_t *xcd_remap, int32_t *span, int64_t *tiles);
 hdx_status hdx_batch_get_group_schedule(const hdx_batch *batch, int32_t group, int32_t *threads, int32_t *persistent,
-                                        int32_t *xcd_remap, int64_t *tiles);
+                                        int32_t *xcd_remap, int32_t *span, int64_t *tiles);
 hdx_status hdx_batch_get_schedule(const hdx_batch *batch, int32_t *threads, int32_t *persistent,
-                                  int32_t *xcd_remap);
+                                  int32_t *xcd_remap, int32_t *span);
 /* Launch through a captured HIP graph (captured on first use and again
  * when the kernel variant or schedule changes). */
 hdx_status hdx_batch_use_graph(hdx_ctx *ctx, hdx_batch *batch, int32_t enable);

@@ -93,9 +93,11 @@ struct TileQueue {
 // Launch schedule of the expansion kernel; results never depend on it.
 struct Schedule {
     int32_t threads;     // workgroup size, a multiple of 64
-    int32_t persistent;  // 0: one workgroup per tile; >0: that many workgroups per CU
+    int32_t persistent;  // 0: one workgroup per span of tiles; >0: that many workgroups per CU
     int32_t xcd_remap;   // keep consecutive tiles (one leaf) on one XCD
+    int32_t span;        // consecutive tiles a workgroup takes at once (1..kMaxSpan)
 };
+constexpr int kMaxSpan = 32;
 
 // LDS carve-up of one tile, the same on host (for the launch size) and
 // device.  Regions live in phases and are reused:
@@ -108,8 +110,10 @@ struct Schedule {
 //   child         child index of each scenario (bits 0-15) and its rank
 //                 inside its 64-scenario chunk (bits 16-23)
 //   perm          grouped order (or the bitonic keys of the fallback path)
+//   cache         (small carve-up) the leaf's updated states, scenario ids
+//                 and sensor words, kept across the tiles of one leaf
 struct LdsLayout {
-    uint32_t zkey, tab, dslot, off, ubuf, lbuf, child, perm, misc, gpow, total;
+    uint32_t zkey, tab, dslot, off, ubuf, lbuf, child, perm, misc, gpow, cache, total;
     int32_t np, p2, h, table_cap;
     int32_t small;  // small-alphabet carve-up: no hash table, chunk counts in tab
 };
@@ -155,6 +159,7 @@ __host__ __device__ inline LdsLayout make_layout(int32_t np, bool small = false)
     L.perm = take(4u * L.p2);
     L.misc = take(64 + 4u * 64);
     L.gpow = small ? L.misc : take(4u * (kGpowLds + 2 * kMaxGoals));
+    L.cache = small ? take(12u * np) : 0;
     L.total = o;
     return L;
 }

@@ -25,6 +25,24 @@ namespace {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// Sum of v over the 64 lanes (all active), in one fixed order: inclusive
+// prefix sums inside each row of 16 lanes (row shifts by 1, 2, 4, 8), then
+// the row totals carried by the row broadcasts of lanes 15 and 31; the total
+// is lane 63's prefix.  Lanes without a source add +0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_src(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, true));
+}
+__device__ __forceinline__ float wave_total(float v) {
+    v = v + dpp_src<0x111, 0xf>(v);  // row_shr:1
+    v = v + dpp_src<0x112, 0xf>(v);  // row_shr:2
+    v = v + dpp_src<0x114, 0xf>(v);  // row_shr:4
+    v = v + dpp_src<0x118, 0xf>(v);  // row_shr:8
+    v = v + dpp_src<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v = v + dpp_src<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 __device__ __forceinline__ uint64_t mix_key(uint64_t z) {
     return (z * 0x9E3779B97F4A7C15ull) >> 32;
 }
@@ -147,9 +165,21 @@ __device__ void block_exclusive_scan(int32_t *a, int len, int32_t *scratch) {
 
 __device__ __forceinline__ bool has_states(const StatesPtr &S) { return S.w != nullptr || S.s != nullptr; }
 
-// One (leaf, action) tile.
+// Leaf cache flags carried from one tile of a workgroup to the next tile of
+// the same leaf: the cache is in use; it holds the leaf's updated states and
+// scenario ids; it holds the sensor words of the leaf's depth.
+enum : int { kCacheOn = 4, kCacheStates = 1, kCacheWords = 2 };
+
+// One (leaf, action) tile.  `cache` holds the leaf cache flags on entry; the
+// flags valid for the next tile of the same leaf are returned.  The updated
+// leaf states and the sensor words do not depend on the tile's action, so a
+// workgroup that takes several tiles of one leaf gathers and updates the
+// scenarios once and draws each scenario's sensor word once; every lane
+// keeps its own scenarios (k = tid + i * blockDim), so the cache needs no
+// barrier of its own.
 template <class Ops>
-__device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char *lds, const LdsLayout &Ly) {
+__device__ int run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char *lds, const LdsLayout &Ly,
+                        int cache) {
     float *gpow_lds = (float *)(lds + Ly.gpow);
     const MView M = make_view(T->model, gpow_lds);
     const int n = T->n;
@@ -172,11 +202,20 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
     float *chunk_r = (float *)(misc + 8);                          // per-chunk reward sums (<= 32)
     int32_t *scan_scratch = misc + 48;
     const int H = Ly.h;
+    // small observation alphabet (keys below 32): per 64-scenario chunk t and
+    // key v, the scenario count and the U and L sums (entry t * 32 + v, over
+    // zkey), the chunk's key mask (over dslot), and per key the child offset
+    // and child index (over off)
+    const int kchunks = (Ly.np + 63) >> 6;
+    int32_t *kc = (int32_t *)(lds + Ly.zkey);
+    float *ku = (float *)(kc + 32 * kchunks);
+    float *kl = ku + 32 * kchunks;
+    uint32_t *kmask = (uint32_t *)(lds + Ly.dslot);
+    int32_t *koff = (int32_t *)(lds + Ly.off);
+    int32_t *kci = koff + 32;
 
     if constexpr (!Ops::kSmallObs)
         for (int h = tid; h < H; h += nt) tab[h] = kEmptyKey;
-    if (Ly.small)
-        for (int i = tid; i < Ly.table_cap; i += nt) cnt[i] = 0;
     if (tid == 0) {
         misc[0] = 0;
         misc[1] = 0;
@@ -201,6 +240,12 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
     const StatesPtr sprime = load_states(&T->sprime);
     const bool write_leaf = (a == 0);
     const bool pair_out = has_states(sprime);
+    const bool use_cache = Ops::kLeafCache && (cache & kCacheOn) != 0;
+    const bool have_states = use_cache && (cache & kCacheStates) != 0;
+    const bool have_words = use_cache && (cache & kCacheWords) != 0;
+    int32_t *c_w = (int32_t *)(lds + Ly.cache);
+    uint32_t *c_id = (uint32_t *)(c_w + Ly.np);
+    uint32_t *c_word = c_id + Ly.np;
 
     // -- gather + update + expand + bounds + rollouts (Eq. 10, 12, 13) ------
     // Every lane of a wavefront runs the same number of rounds, so the
@@ -214,7 +259,7 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
         uint32_t id = 0;
         typename Ops::State st;
         // gather + update + expansion step of one scenario
-        auto expand_one = [&]() {
+        auto gather_update = [&]() {
             const int p = T->idx[k];
             id = T->parent_ids[p];
             Ops::load(M, parent, p, st);
@@ -223,11 +268,41 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
                 uint64_t z0;
                 Ops::template step<false>(M, st, last_action, id, (uint32_t)(depth - 1), RP.k0, RP.k1, r0, z0);
             }
+        };
+        auto expand_one = [&]() {
+            if constexpr (Ops::kLeafCache) {
+                if (have_states) {
+                    st.w = c_w[k];
+                    id = c_id[k];
+                } else {
+                    gather_update();
+                    if (use_cache) {
+                        c_w[k] = st.w;
+                        c_id[k] = id;
+                    }
+                }
+            } else {
+                gather_update();
+            }
             if (write_leaf) {
                 Ops::store(M, leaf_out, k, st);
                 T->ids_out[k] = id;
             }
             my_exp += Ops::terminal(st) ? 0 : 1;
+            if constexpr (Ops::kLeafCache) {
+                if (use_cache) {
+                    Ops::template step_with<true>(
+                        M, st, a,
+                        [&]() {
+                            if (have_words) return c_word[k];
+                            const uint32_t u = Ops::sense_word(id, (uint32_t)depth, RP.k0, RP.k1);
+                            c_word[k] = u;
+                            return u;
+                        },
+                        r, z);
+                    return;
+                }
+            }
             Ops::template step<true>(M, st, a, id, (uint32_t)depth, RP.k0, RP.k1, r, z);
         };
         float U = 0.0f;
@@ -241,27 +316,56 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
             expand_one();
             U = Ops::upper(M, st);
         }
+        float L = 0.0f;
         if (valid) {
             const int64_t pk = (int64_t)a * n + k;
             if (pair_out) Ops::store(M, sprime, pk, st);
             int ns = 0;
-            const float L = rollout<Ops>(M, RP, st, id, depth + 1, ns);
+            L = rollout<Ops>(M, RP, st, id, depth + 1, ns);
             my_roll += ns;
-            zk[k] = z;
-            ub[k] = U;
-            lb[k] = L;
+            if constexpr (!Ops::kSmallObs) {
+                zk[k] = z;
+                ub[k] = U;
+                lb[k] = L;
+            }
             if (T->r) T->r[pk] = r;
             if (T->z) T->z[pk] = z;
             if (T->U) T->U[pk] = U;
             if (T->L) T->L[pk] = L;
         }
-        // mean step reward: plain sum of this 64-scenario chunk in k order
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const float o = __shfl_up(r, d, 64);
-            if (lane >= d) r = o + r;
+        const bool chunk_live = base + wid * 64 < n;  // wavefront-uniform
+        if constexpr (Ops::kSmallObs) {
+            // this chunk's scenarios by key: counts, ranks, and the U and L
+            // sums of each key present (keys in order of first appearance)
+            if (chunk_live) {
+                const int t = (base >> 6) + wid;
+                const uint32_t key = valid ? (uint32_t)z : 0xFFFFFFFFu;
+                uint64_t rem = __ballot(valid);
+                uint32_t present = 0;
+                int rank = 0;
+                while (rem) {
+                    const int leader = __ffsll((unsigned long long)rem) - 1;
+                    const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
+                    const bool mine = key == v;
+                    const uint64_t bv = __ballot(mine);
+                    if (mine) rank = __popcll(bv & __lanemask_lt());
+                    const float su = wave_total(mine ? U : 0.0f);
+                    const float sl = wave_total(mine ? L : 0.0f);
+                    if (lane == 0) {
+                        kc[t * 32 + v] = __popcll(bv);
+                        ku[t * 32 + v] = su;
+                        kl[t * 32 + v] = sl;
+                    }
+                    present |= 1u << v;
+                    rem &= ~bv;
+                }
+                if (lane == 0) kmask[t] = present;
+                if (valid) child[k] = (int32_t)(key | ((uint32_t)rank << 16));
+            }
         }
-        if (lane == 63 && base + wid * 64 < n) chunk_r[(base >> 6) + wid] = r;
+        // mean step reward: sum of this 64-scenario chunk (lanes past n add 0)
+        const float r_chunk = wave_total(r);
+        if (lane == 0 && chunk_live) chunk_r[(base >> 6) + wid] = r_chunk;
     }
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) {
@@ -275,29 +379,73 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
 
     int D;
     if constexpr (Ops::kSmallObs) {
-        // -- small observation alphabet (every key below 32) ---------------------
-        // presence mask by wavefront OR plus one LDS atomic per wavefront; the
-        // child of a key is the rank of its bit, which is ascending key order
-        uint32_t m = 0;
-        for (int k = tid; k < n; k += nt) m |= 1u << (uint32_t)zk[k];
+        // -- small observation alphabet: children from the per-chunk key tables --
+        // Lane v of wavefront 0 owns key v: its scenario count (turning the
+        // per-chunk counts into prefixes over chunks) and its U and L sums,
+        // chunk partials added in chunk order.  A present key's child index
+        // is the number of present keys below it (ascending observation).
+        __syncthreads();
+        const int nch = (n + 63) >> 6;
+        if (wid == 0) {
+            const uint32_t v = (uint32_t)lane;
+            int run = 0;
+            float tu = 0.0f, tl = 0.0f;
+            for (int t = 0; t < nch; ++t) {
+                const uint32_t km = kmask[t];
+                if (lane < 32 && ((km >> v) & 1u)) {
+                    const int c = kc[t * 32 + v];
+                    kc[t * 32 + v] = run;
+                    run += c;
+                    tu = tu + ku[t * 32 + v];
+                    tl = tl + kl[t * 32 + v];
+                }
+            }
+            const bool present = run > 0;
+            const uint32_t mask = (uint32_t)__ballot(present);
+            D = __popc(mask);
+            const int ci = lane < 32 ? __popc(mask & ((1u << v) - 1u)) : 0;
+            int incl = run;
 #pragma unroll
-        for (int d = 32; d > 0; d >>= 1) m |= (uint32_t)__shfl_xor((int)m, d, 64);
-        if (lane == 0 && m) atomicOr((unsigned int *)&misc[2], m);
-        __syncthreads();
-        const uint32_t mask = (uint32_t)misc[2];
-        D = __popc(mask);
-        for (int i = tid; i < D && i < cap; i += nt) {
-            uint32_t mm = mask;
-            for (int q = 0; q < i; ++q) mm &= mm - 1u;  // drop the i lowest keys
-            T->child_z[(int64_t)a * cap + i] = (uint64_t)(__ffs(mm) - 1);
+            for (int d = 1; d < 32; d <<= 1) {
+                const int o = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += o;
+            }
+            const int off_v = incl - run;
+            if (lane < 32) {
+                koff[v] = off_v;
+                kci[v] = ci;
+            }
+            if (present && ci < cap) {
+                const int64_t o = (int64_t)a * cap + ci;
+                T->child_z[o] = (uint64_t)v;
+                T->child_n[o] = run;
+                T->child_off[o] = off_v;
+                T->child_u0[o] = tu / (float)run;
+                T->child_l0[o] = tl / (float)run;
+            }
+            if (lane == 0) {
+                T->n_children[a] = D;
+                float tr = 0.0f;
+                for (int t = 0; t < nch; ++t) tr = tr + chunk_r[t];
+                T->r_mean[a] = n > 0 ? tr / (float)n : 0.0f;
+                T->steps[2 * a + 0] = (int64_t)stepc[0];
+                T->steps[2 * a + 1] = (int64_t)stepc[1];
+            }
         }
-        if (tid == 0) T->n_children[a] = D;
+        __syncthreads();
+        // grouped order: a scenario's place is its child's offset, plus the
+        // key's count in earlier chunks, plus its rank inside its chunk
         for (int k = tid; k < n; k += nt) {
-            const int c = __popc(mask & ((1u << (uint32_t)zk[k]) - 1u));
-            child[k] = c;
-            if (T->child_of) T->child_of[(int64_t)a * n + k] = c;
+            const int32_t cw = child[k];
+            const int v = cw & 0xFFFF;
+            T->perm[(int64_t)a * n + koff[v] + kc[(k >> 6) * 32 + v] + (cw >> 16)] = k;
+            if (T->child_of) T->child_of[(int64_t)a * n + k] = kci[v];
         }
-        __syncthreads();
+        __syncthreads();  // LDS is reused by the next tile
+        if constexpr (Ops::kLeafCache) {
+            if (use_cache) return cache | kCacheStates | (Ops::draws_word(a) ? kCacheWords : 0);
+        }
+        return 0;
     } else {
         // -- LDS hash of the observations ----------------------------------------
         for (int k = tid; k < n; k += nt) {
@@ -501,11 +649,15 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
         T->steps[2 * a + 1] = (int64_t)stepc[1];
     }
     __syncthreads();  // LDS is reused by the next tile
+    if constexpr (Ops::kLeafCache) {
+        if (use_cache) return cache | kCacheStates | (Ops::draws_word(a) ? kCacheWords : 0);
+    }
+    return 0;
 }
 
 template <int PM>
 __device__ __forceinline__ void run_ped(const HDX_CONST LeafTask *T, int a, unsigned char *lds, const LdsLayout &Ly) {
-    run_tile<PedOps<PM>>(T, a, lds, Ly);
+    run_tile<PedOps<PM>>(T, a, lds, Ly, 0);
 }
 
 __device__ __forceinline__ int remap_xcd(int b, int grid) {
@@ -520,36 +672,60 @@ __device__ __forceinline__ int remap_xcd(int b, int grid) {
 // in registers.
 template <int MODE>
 constexpr int max_threads() { return MODE == 0 ? 512 : 256; }
+// RockSample tiles: keep 7 wavefronts per SIMD resident (at most 72 VGPRs,
+// no spills); the driving model's register state decides its own.
+template <int MODE>
+constexpr int min_waves() { return MODE == 0 ? 7 : 1; }
 
+// A workgroup takes `span` consecutive tiles at a time (tiles of one leaf
+// are consecutive, in action order), so RockSample tiles after the first of
+// a leaf reuse the leaf cache.  The persistent form pops whole spans while
+// many tiles remain and single tiles at the tail.
 template <int MODE, int PM>
-__global__ __launch_bounds__(max_threads<MODE>()) void expand_tiles(const LeafTask *tasks, const Tile *tiles,
+__global__ __launch_bounds__(max_threads<MODE>(), min_waves<MODE>()) void expand_tiles(const LeafTask *tasks, const Tile *tiles,
                                                                     TileQueue *queue, int32_t n_max,
-                                                                    int32_t persistent, int32_t xcd_remap) {
+                                                                    int32_t persistent, int32_t xcd_remap,
+                                                                    int32_t span) {
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ int32_t s_tile;
+    __shared__ int32_t s_tile, s_count;
     const LdsLayout Ly = make_layout(n_max, MODE == 0);
     const int32_t n_tiles = __builtin_amdgcn_readfirstlane(queue->n_tiles);
+    const int cache_on = (MODE == 0 && (span > 1 || persistent)) ? kCacheOn : 0;
+    int cached_leaf = -1, flags = 0;
     int iter = 0;
     for (;;) {
-        int t;
+        int t0, count;
         if (persistent) {
-            if (threadIdx.x == 0) s_tile = atomicAdd(&queue->next, 1);
+            if (threadIdx.x == 0) {
+                const int seen = __hip_atomic_load(&queue->next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int want = (n_tiles - seen > 2 * span * (int)gridDim.x) ? span : 1;
+                s_tile = atomicAdd(&queue->next, want);
+                s_count = want;
+            }
             __syncthreads();
-            t = __builtin_amdgcn_readfirstlane(s_tile);
+            t0 = __builtin_amdgcn_readfirstlane(s_tile);
+            count = __builtin_amdgcn_readfirstlane(s_count);
             __syncthreads();
         } else {
             if (iter > 0) break;
-            t = xcd_remap ? remap_xcd((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+            t0 = (xcd_remap ? remap_xcd((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x) * span;
+            count = span;
         }
         ++iter;
-        if (t >= n_tiles) break;
-        const HDX_CONST Tile *tile = (const HDX_CONST Tile *)(tiles + t);
-        const HDX_CONST LeafTask *T = (const HDX_CONST LeafTask *)(tasks + tile->leaf);
-        const int a = tile->action;
-        if (MODE == 0 || (MODE == 2 && T->kind == HDX_ROCKSAMPLE)) {
-            run_tile<RsOps>(T, a, lds, Ly);
-        } else if (MODE != 0) {
-            run_ped<PM>(T, a, lds, Ly);
+        if (t0 >= n_tiles) break;
+        const int t1 = min(t0 + count, n_tiles);
+        for (int t = t0; t < t1; ++t) {
+            const HDX_CONST Tile *tile = (const HDX_CONST Tile *)(tiles + t);
+            const int leaf = tile->leaf;
+            const HDX_CONST LeafTask *T = (const HDX_CONST LeafTask *)(tasks + leaf);
+            const int a = tile->action;
+            if (leaf != cached_leaf) flags = cache_on;
+            cached_leaf = leaf;
+            if (MODE == 0 || (MODE == 2 && T->kind == HDX_ROCKSAMPLE)) {
+                flags = run_tile<RsOps>(T, a, lds, Ly, flags);
+            } else if (MODE != 0) {
+                run_ped<PM>(T, a, lds, Ly);
+            }
         }
     }
     if (persistent && threadIdx.x == 0) {
@@ -583,7 +759,7 @@ __global__ __launch_bounds__(max_threads<MODE>()) void expand_args(const ArgPack
     const HDX_CONST LeafTask *T = &P->t[i];
     const int a = t - P->tile_begin[i];
     if (MODE == 0 || (MODE == 2 && T->kind == HDX_ROCKSAMPLE)) {
-        run_tile<RsOps>(T, a, lds, Ly);
+        run_tile<RsOps>(T, a, lds, Ly, 0);
     } else if (MODE != 0) {
         run_ped<PM>(T, a, lds, Ly);
     }
@@ -614,11 +790,12 @@ hipError_t launch_expand_t(const LeafTask *d_tasks, const Tile *d_tiles, TileQue
     const LdsLayout Ly = make_layout(n_max, MODE == 0);
     // persistent: a fixed grid that drains the tile queue, so a captured
     // graph stays valid for any tile count
-    const int grid = sch.persistent > 0 ? n_cu * sch.persistent : n_tiles;
+    const int span = sch.span < 1 ? 1 : sch.span > kMaxSpan ? kMaxSpan : sch.span;
+    const int grid = sch.persistent > 0 ? n_cu * sch.persistent : (n_tiles + span - 1) / span;
     if (grid < 1) return hipSuccess;
     const int threads = sch.threads > max_threads<MODE>() ? max_threads<MODE>() : sch.threads;
     hipLaunchKernelGGL((expand_tiles<MODE, PM>), dim3(grid), dim3(threads), Ly.total, stream, d_tasks, d_tiles,
-                       d_queue, n_max, sch.persistent > 0 ? 1 : 0, sch.xcd_remap);
+                       d_queue, n_max, sch.persistent > 0 ? 1 : 0, sch.xcd_remap, span);
     return hipGetLastError();
 }
 

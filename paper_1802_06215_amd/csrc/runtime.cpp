@@ -59,7 +59,7 @@ struct hdx_ctx {
     Slot slots[kSlots];
     int next_slot = 0;
     hipStream_t cls_stream[kGroups] = {};  // one stream per launch group (default priority)
-    Schedule sched{256, 0, 1};
+    Schedule sched{256, 0, 1, 1};
     bool sched_fixed = false;
 };
 
@@ -467,6 +467,7 @@ Schedule hdx::class_default_schedule(int32_t n_max, int32_t max_threads) {
     s.threads = std::min(std::max(64, pow2_at_least(std::max(n_max, 1)) / 2), std::min(256, max_threads));
     s.persistent = 0;
     s.xcd_remap = 1;
+    s.span = 1;
     return s;
 }
 
@@ -653,7 +654,7 @@ int32_t group_width_cap(const hdx_batch *b, int g) {
 }
 
 bool same_schedule(const Schedule &a, const Schedule &b) {
-    return a.threads == b.threads && a.persistent == b.persistent && a.xcd_remap == b.xcd_remap;
+    return a.threads == b.threads && a.persistent == b.persistent && a.xcd_remap == b.xcd_remap && a.span == b.span;
 }
 
 void drop_graph(hdx_batch *b) {
@@ -758,44 +759,46 @@ hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *b, const hdx_leaf *leav
 }
 
 hdx_status hdx_batch_set_schedule(hdx_ctx *ctx, hdx_batch *b, int32_t threads, int32_t persistent,
-                                  int32_t xcd_remap) {
+                                  int32_t xcd_remap, int32_t span) {
     if (!ctx || !b) return HDX_E_INVALID;
-    if (threads < 64 || threads > 1024 || threads % 64 != 0 || persistent < 0 || persistent > 64)
+    if (threads < 64 || threads > 1024 || threads % 64 != 0 || persistent < 0 || persistent > 64 || span < 1 ||
+        span > kMaxSpan)
         return fail(ctx, HDX_E_INVALID, "schedule");
     for (int g = 0; g < kGroups; ++g) {
-        b->sched[g] = Schedule{threads, persistent, xcd_remap ? 1 : 0};
+        b->sched[g] = Schedule{threads, persistent, xcd_remap ? 1 : 0, span};
         b->sched_set[g] = true;
     }
     return HDX_OK;
 }
 
 hdx_status hdx_batch_set_class_schedule(hdx_ctx *ctx, hdx_batch *b, int32_t cls, int32_t threads, int32_t persistent,
-                                        int32_t xcd_remap) {
+                                        int32_t xcd_remap, int32_t span) {
     if (!ctx || !b) return HDX_E_INVALID;
     if (cls < 0 || cls >= kSizeClasses || threads < 64 || threads > 1024 || threads % 64 != 0 || persistent < 0 ||
-        persistent > 64)
+        persistent > 64 || span < 1 || span > kMaxSpan)
         return fail(ctx, HDX_E_INVALID, "schedule");
     for (int v = 0; v < kModelVariants; ++v) {
-        b->sched[v * kSizeClasses + cls] = Schedule{threads, persistent, xcd_remap ? 1 : 0};
+        b->sched[v * kSizeClasses + cls] = Schedule{threads, persistent, xcd_remap ? 1 : 0, span};
         b->sched_set[v * kSizeClasses + cls] = true;
     }
     return HDX_OK;
 }
 
 hdx_status hdx_batch_get_group_schedule(const hdx_batch *b, int32_t group, int32_t *threads, int32_t *persistent,
-                                        int32_t *xcd_remap, int64_t *tiles) {
+                                        int32_t *xcd_remap, int32_t *span, int64_t *tiles) {
     if (!b || !threads || !persistent || !xcd_remap || group < 0 || group >= kGroups) return HDX_E_INVALID;
     const Schedule &s = b->sched[group];
     const int32_t cap = group_width_cap(b, group);
     *threads = s.threads > cap ? cap : s.threads;
     *persistent = s.persistent;
     *xcd_remap = s.xcd_remap;
+    if (span) *span = s.span;
     if (tiles) *tiles = b->plan.count[group];
     return HDX_OK;
 }
 
 hdx_status hdx_batch_get_class_schedule(const hdx_batch *b, int32_t cls, int32_t *threads, int32_t *persistent,
-                                        int32_t *xcd_remap, int64_t *tiles) {
+                                        int32_t *xcd_remap, int32_t *span, int64_t *tiles) {
     if (!b || !threads || !persistent || !xcd_remap || cls < 0 || cls >= kSizeClasses) return HDX_E_INVALID;
     // the class's group with the most tiles
     int best = cls;
@@ -805,17 +808,18 @@ hdx_status hdx_batch_get_class_schedule(const hdx_batch *b, int32_t cls, int32_t
         total += b->plan.count[g];
         if (b->plan.count[g] > b->plan.count[best]) best = g;
     }
-    const hdx_status st = hdx_batch_get_group_schedule(b, best, threads, persistent, xcd_remap, nullptr);
+    const hdx_status st = hdx_batch_get_group_schedule(b, best, threads, persistent, xcd_remap, span, nullptr);
     if (tiles) *tiles = total;
     return st;
 }
 
-hdx_status hdx_batch_get_schedule(const hdx_batch *b, int32_t *threads, int32_t *persistent, int32_t *xcd_remap) {
+hdx_status hdx_batch_get_schedule(const hdx_batch *b, int32_t *threads, int32_t *persistent, int32_t *xcd_remap,
+                                  int32_t *span) {
     if (!b || !threads || !persistent || !xcd_remap) return HDX_E_INVALID;
     int big = 0;
     for (int g = 1; g < kGroups; ++g)
         if (b->plan.count[g] > b->plan.count[big]) big = g;
-    return hdx_batch_get_group_schedule(b, big, threads, persistent, xcd_remap, nullptr);
+    return hdx_batch_get_group_schedule(b, big, threads, persistent, xcd_remap, span, nullptr);
 }
 
 hdx_status hdx_batch_use_graph(hdx_ctx *ctx, hdx_batch *b, int32_t enable) {
@@ -874,11 +878,18 @@ hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *b, int32_t reps, float *b
     if (b->staged_used) hipEventSynchronize(b->staged);
     auto candidates = [&](int c) {
         const int cap = group_width_cap(b, c);
+        // spans only where the leaf cache makes them pay (RockSample groups)
+        const bool spans = group_variant(c).mode == 0;
         std::vector<Schedule> cand;
         for (int th = 64; th <= cap; th *= 2) {
-            cand.push_back(Schedule{th, 0, 0});
-            cand.push_back(Schedule{th, 0, 1});
-            for (int p : {1, 2, 4, 8}) cand.push_back(Schedule{th, p, 0});
+            cand.push_back(Schedule{th, 0, 0, 1});
+            cand.push_back(Schedule{th, 0, 1, 1});
+            for (int p : {1, 2, 4, 8}) cand.push_back(Schedule{th, p, 0, 1});
+            if (!spans) continue;
+            for (int sp : {2, 4}) {
+                cand.push_back(Schedule{th, 0, 1, sp});
+                for (int p : {2, 4}) cand.push_back(Schedule{th, p, 0, sp});
+            }
         }
         return cand;
     };

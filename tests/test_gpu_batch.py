@@ -82,10 +82,11 @@ def test_batch_equals_per_instance_under_every_schedule(ctx):
     b.set_leaves([it["leaf"] for it in items])
     torch.cuda.synchronize()
     for threads in (64, 128, 256):
-        for persistent, xcd in ((0, 0), (0, 1), (1, 0), (3, 0), (8, 0)):
-            print("schedule", threads, persistent, xcd, flush=True)
+        for persistent, xcd, span in ((0, 0, 1), (0, 1, 1), (1, 0, 1), (3, 0, 1), (8, 0, 1), (0, 1, 3), (0, 0, 7),
+                                      (2, 0, 4), (1, 0, 32)):
+            print("schedule", threads, persistent, xcd, span, flush=True)
             clear(items)
-            b.set_schedule(threads, persistent, xcd)
+            b.set_schedule(threads, persistent, xcd, span)
             b.launch()
             torch.cuda.synchronize()
             assert_same(snapshot(items), ref)
@@ -145,8 +146,8 @@ def test_autotune_keeps_results(ctx):
     b.set_leaves([it["leaf"] for it in items])
     ms = b.autotune(2)
     assert ms > 0
-    threads, persistent, xcd = b.schedule()
-    assert threads in (64, 128, 256, 512)
+    threads, persistent, xcd, span = b.schedule()
+    assert threads in (64, 128, 256, 512) and 1 <= span <= 32
     clear(items)
     b.launch()
     torch.cuda.synchronize()
@@ -162,3 +163,57 @@ def test_batch_capacity_error(ctx):
         b.set_leaves([it["leaf"] for it in items])
     assert e.value.code == -5
     b.close()
+
+
+def test_leaf_cache_spans_match_single_tiles(ctx):
+    """RockSample workgroups that take several tiles of one leaf gather and
+    update its scenarios once and draw each sensor word once (the leaf
+    cache); every output, per-pair ones included, must equal a launch that
+    takes one tile per workgroup, under spans that split leaves at any
+    action and persistent pops."""
+    from paper_1802_06215_amd import Batch
+    desc = W.rocksample_model(15, 15, 3)
+    m = ctx.upload_model(desc)
+    items = []
+    for i, n in enumerate((500, 250, 125, 62, 31, 7, 1, 300, 499, 64, 65, 200)):
+        lf = W.rocksample_leaf(desc, 500, n, 900 + i, p_term=0.1, depth=1 + (7 * i) % 40)
+        # a sense action before the leaf exercises the update step's no-draw path
+        if i % 3 == 0:
+            lf["last_action"] = 5 + i % desc["m"]
+        par_np = oracle.parent_states(desc, lf)
+        par, pids = to_dev(par_np), ids_dev(lf["ids"])
+        cfgs = cfg_pair(0, 1 << 30, 90)
+        leaf, out, idx = gpu_leaf_desc(m, par, pids, lf["idx"], lf["depth"], lf["last_action"], 77 + i, 3,
+                                       cfgs[1], True)
+        items.append(dict(desc=desc, m=m, lf=lf, par_np=par_np, leaf=leaf, out=out, cfgs=cfgs,
+                          keep=(par, pids, idx)))
+    for it in items:  # one leaf per call: one tile per workgroup, no cache
+        ctx.expand_leaf([it["leaf"]])
+    torch.cuda.synchronize()
+    ref = snapshot(items)
+    b = Batch(ctx, len(items), len(items) * desc["n_actions"])
+    b.set_leaves([it["leaf"] for it in items])
+    torch.cuda.synchronize()
+    for threads, persistent, xcd, span in ((64, 0, 1, 2), (256, 0, 0, 3), (128, 0, 1, 20), (256, 0, 1, 32),
+                                           (64, 2, 0, 4), (256, 1, 0, 7), (512, 4, 0, 20)):
+        print("span schedule", threads, persistent, xcd, span, flush=True)
+        clear(items)
+        for it in items:
+            for t in (it["out"].r, it["out"].z, it["out"].U, it["out"].L):
+                t.fill_(-3)
+        b.set_schedule(threads, persistent, xcd, span)
+        b.launch()
+        torch.cuda.synchronize()
+        got = snapshot(items)
+        assert_same(got, ref)
+        for x, y in zip(got, ref):
+            for key in ("r", "U", "L"):
+                assert np.array_equal(x[key].view(np.uint32), y[key].view(np.uint32)), key
+            assert np.array_equal(x["z"], y["z"])
+            assert np.array_equal(x["sprime"]["w"], y["sprime"]["w"])
+    b.close()
+    for it in items[::4]:
+        lf = it["lf"]
+        want = oracle.expand_leaf(desc, it["cfgs"][0], it["par_np"], lf["ids"].astype(np.uint32), lf["idx"],
+                                  lf["depth"], lf["last_action"], it["leaf"].seed, 3, per_pair=True)
+        compare_leaf(desc, collect(m, it["out"]), want, len(lf["idx"]))
