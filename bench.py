@@ -73,6 +73,8 @@ def parse():
                     "(skips the autotuner)")
     ap.add_argument("--class-schedule", action="append", default=[],
                     help="size_class:threads,persistent,xcd_remap (repeatable; skips the autotuner)")
+    ap.add_argument("--split", action="store_true",
+                    help="one launch group per size class (with --schedule / --class-schedule)")
     ap.add_argument("--surrogate-epochs", type=int, default=24,
                     help="training epochs of the surrogate comparison (rs15 only; 0 = skip)")
     ap.add_argument("--surrogate-targets", type=int, default=16,
@@ -478,6 +480,7 @@ def main():
     log("leaves %d tiles %d" % (len(leaves), n_tiles))
     tuned_ms = None
     if args.schedule or args.class_schedule:
+        batch.set_split(args.split)
         if args.schedule:
             batch.set_schedule(*[int(v) for v in args.schedule.split(",")])
         for cs in args.class_schedule:
@@ -565,14 +568,14 @@ def main():
                  mix64="MIX64: 64 planner instances (RockSample 7..20 / driving, K in {100,200,500}); "
                        "%d leaves in one launch")
     variants = ("rocksample", "driving<=8", "driving<=16", "driving<=32")
-    per_class = [dict(model=variants[v], max_n=64 << c, tiles=n, threads=ct, persistent=cp, xcd_remap=cx, span=cs)
-                 for v, c, ct, cp, cx, cs, n in batch.group_schedules()]
+    per_class = [dict(model=variants[v], max_n=64 << c, tiles=n, threads=ct, persistent=cp, xcd_remap=cx)
+                 for v, c, ct, cp, cx, n in batch.group_schedules()]
     out = dict(metric=METRIC, value=round(value, 1), unit="scenario-steps/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(wall * 1e3 / args.steps, 4), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="int32+fp32", data="synthetic",
                config=dict(workload=names[args.workload] % len(leaves), leaves=len(leaves), tiles=n_tiles,
                            scenario_steps_per_step=steps_per_launch, expand_steps=exp_steps,
-                           rollout_steps=roll_steps, schedule=per_class,
+                           rollout_steps=roll_steps, split_by_size_class=batch.split(), schedule=per_class,
                            hip_graph=True, autotune_ms=tuned_ms),
                roofline=roofline, cpu_baseline=cpu,
                search=dict(config="RockSample 15x15, 15 rocks, K=500, max depth 90, %.1f s planning step"

@@ -230,47 +230,49 @@ hdx_status hdx_batch_destroy(hdx_ctx *ctx, hdx_batch *batch);
  * copy to device memory is enqueued on `stream`. */
 hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *batch, const hdx_leaf *leaves, int32_t n_leaves,
                                 hdx_stream stream);
-/* Launch schedule: workgroup size (multiple of 64; capped at 512 for
- * RockSample-only batches and 256 otherwise, and at what a size class's
- * leaves need), persistent workgroups per CU (0 = one workgroup per span),
- * the XCD-contiguous tile mapping, and the span: how many consecutive tiles
- * (1..32) a workgroup takes at once.  The tiles of a leaf are consecutive,
- * and a RockSample workgroup that takes several of them gathers and updates
- * the leaf's scenarios and draws their sensor words once for all of them
- * (the persistent form takes whole spans while many tiles remain, then
- * single tiles).  Tiles launch in groups of one model
- * variant (0 RockSample; 1, 2, 3 driving with up to 8, 16, 32 pedestrians)
- * and one size class of their leaf (class c holds leaves of 64*2^(c-1) < n
- * <= 64*2^c scenarios, c = 0..5): group = variant * HDX_SIZE_CLASSES +
- * class.  set_schedule applies to every group, set_class_schedule to the
+/* Launch plan and schedule.  Tiles launch in groups of one model variant
+ * (0 RockSample; 1, 2, 3 driving with up to 8, 16, 32 pedestrians), each
+ * group one dispatch with an LDS carve-up and workgroup size for its
+ * largest leaf, tiles ordered largest leaf first.  Unsplit (the default):
+ * one group per variant, filed under the size class of its largest leaf.
+ * Split: one group per variant and size class of leaf (class c holds leaves
+ * of 64*2^(c-1) < n <= 64*2^c scenarios, c = 0..5), the groups launched side
+ * by side.  Group = variant * HDX_SIZE_CLASSES + class.  set_split re-plans
+ * the staged leaves (and later ones).  A group's schedule: workgroup size
+ * (multiple of 64; capped at 512 for RockSample and 256 for driving, and at
+ * what the group's leaves need), persistent workgroups per CU (0 = one
+ * workgroup per tile), and the XCD-contiguous tile mapping.  set_schedule applies to every group, set_class_schedule to the
  * groups of one size class; get_group_schedule reports one group (and its
  * tile count), get_class_schedule the class's group with the most tiles,
  * get_schedule the group with the most tiles.  Results are bit-identical
  * under every schedule. */
 #define HDX_SIZE_CLASSES 6
 #define HDX_LAUNCH_GROUPS 24
+hdx_status hdx_batch_set_split(hdx_ctx *ctx, hdx_batch *batch, int32_t split);
+hdx_status hdx_batch_get_split(const hdx_batch *batch, int32_t *split);
 hdx_status hdx_batch_set_schedule(hdx_ctx *ctx, hdx_batch *batch, int32_t threads, int32_t persistent,
-                                  int32_t xcd_remap, int32_t span);
+                                  int32_t xcd_remap);
 hdx_status hdx_batch_set_class_schedule(hdx_ctx *ctx, hdx_batch *batch, int32_t size_class, int32_t threads,
-                                        int32_t persistent, int32_t xcd_remap, int32_t span);
-/* span and tiles may be NULL. */
+                                        int32_t persistent, int32_t xcd_remap);
+/* tiles may be NULL. */
 hdx_status hdx_batch_get_class_schedule(const hdx_batch *batch, int32_t size_class, int32_t *threads,
-                                        int32_t *persistent, int32_t *xcd_remap, int32_t *span, int64_t *tiles);
+                                        int32_t *persistent, int32_t *xcd_remap, int64_t *tiles);
 hdx_status hdx_batch_get_group_schedule(const hdx_batch *batch, int32_t group, int32_t *threads, int32_t *persistent,
-                                        int32_t *xcd_remap, int32_t *span, int64_t *tiles);
+                                        int32_t *xcd_remap, int64_t *tiles);
 hdx_status hdx_batch_get_schedule(const hdx_batch *batch, int32_t *threads, int32_t *persistent,
-                                  int32_t *xcd_remap, int32_t *span);
+                                  int32_t *xcd_remap);
 /* Launch through a captured HIP graph (captured on first use and again
  * when the kernel variant or schedule changes). */
 hdx_status hdx_batch_use_graph(hdx_ctx *ctx, hdx_batch *batch, int32_t enable);
 /* Expand every staged leaf: one kernel launch (or graph replay), no copies. */
 hdx_status hdx_batch_launch(hdx_ctx *ctx, hdx_batch *batch, hdx_stream stream);
-/* Autotuner (an internal stream; blocks until done): per launch group, time
- * each candidate schedule `reps` times on that group's staged tiles alone;
- * then, as the groups run side by side, refine each group's schedule once
- * more against the whole launch.  *best_ms is the mean time of the chosen
- * whole launch (of the single group when there is one).  Outputs are
- * rewritten with identical values. */
+/* Autotuner (an internal stream; blocks until done), for the unsplit and
+ * the split plan in turn: per launch group, time each candidate schedule
+ * `reps` times on that group's staged tiles alone; then, as the groups run
+ * side by side, refine each group's schedule once more against the whole
+ * launch.  The faster plan and its schedules are kept.  *best_ms is the mean
+ * time of the chosen whole launch (of the single group when there is one).
+ * Outputs are rewritten with identical values. */
 hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *batch, int32_t reps, float *best_ms);
 
 /* rollout_bounds (Eq. 12, 13 per scenario): for each of n states (device),

@@ -93,14 +93,13 @@ struct TileQueue {
 // Launch schedule of the expansion kernel; results never depend on it.
 struct Schedule {
     int32_t threads;     // workgroup size, a multiple of 64
-    int32_t persistent;  // 0: one workgroup per span of tiles; >0: that many workgroups per CU
+    int32_t persistent;  // 0: one workgroup per tile; >0: that many workgroups per CU
     int32_t xcd_remap;   // keep consecutive tiles (one leaf) on one XCD
-    int32_t span;        // consecutive tiles a workgroup takes at once (1..kMaxSpan)
 };
-constexpr int kMaxSpan = 32;
 
 // LDS carve-up of one tile, the same on host (for the launch size) and
-// device.  Regions live in phases and are reused:
+// device.  General carve-up (any model); regions live in phases and are
+// reused:
 //   zkey | tab    observations, then the open-addressing hash; after the
 //                 children are ranked the pair holds the chunk count table
 //                 (cnt), and later the grouped per-scenario sums (su, sl)
@@ -110,12 +109,17 @@ constexpr int kMaxSpan = 32;
 //   child         child index of each scenario (bits 0-15) and its rank
 //                 inside its 64-scenario chunk (bits 16-23)
 //   perm          grouped order (or the bitonic keys of the fallback path)
-//   cache         (small carve-up) the leaf's updated states, scenario ids
-//                 and sensor words, kept across the tiles of one leaf
+// Small carve-up (RockSample-only launches: every observation key is below
+// 32, no model table staged):
+//   zkey          per 64-scenario chunk and key: count, U sum, L sum
+//   dslot         per chunk: mask of the keys present
+//   off           per key: child offset and child index
+//   child         key of each scenario (bits 0-15) and its rank inside its
+//                 chunk among the scenarios of that key (bits 16-23)
 struct LdsLayout {
-    uint32_t zkey, tab, dslot, off, ubuf, lbuf, child, perm, misc, gpow, cache, total;
+    uint32_t zkey, tab, dslot, off, ubuf, lbuf, child, perm, misc, gpow, total;
     int32_t np, p2, h, table_cap;
-    int32_t small;  // small-alphabet carve-up: no hash table, chunk counts in tab
+    int32_t small;
 };
 
 __host__ __device__ inline int32_t pow2_at_least(int32_t v) {
@@ -124,10 +128,6 @@ __host__ __device__ inline int32_t pow2_at_least(int32_t v) {
     return p;
 }
 
-// small: every observation key is below 32 and no model table is staged
-// (RockSample-only launches): no hash table; the per-chunk child counts get
-// a region of their own (32 per 64-scenario chunk) and the child sizes one
-// of 32 entries, so the tile needs about 60% of the general carve-up.
 __host__ __device__ inline LdsLayout make_layout(int32_t np, bool small = false) {
     LdsLayout L;
     if (np < 1) np = 1;
@@ -141,25 +141,31 @@ __host__ __device__ inline LdsLayout make_layout(int32_t np, bool small = false)
         o += (bytes + 15u) & ~15u;
         return at;
     };
-    L.zkey = take(8u * L.p2);
     if (small) {
         const uint32_t chunks = (uint32_t)((np + 63) / 64);
-        L.tab = take(4u * 32u * chunks);
-        L.table_cap = (int32_t)(32u * chunks);
-        L.dslot = take(4u * 32u);
-    } else {
-        L.tab = take(8u * L.h + 16u);
-        L.table_cap = (int32_t)((8u * L.p2 + 8u * L.h + 16u) / 4u);
-        L.dslot = take(4u * L.p2);
+        L.zkey = take(3u * 4u * 32u * chunks);
+        L.tab = L.zkey;
+        L.table_cap = 0;
+        L.dslot = take(4u * chunks);
+        L.off = take(4u * 64u);
+        L.ubuf = L.lbuf = L.perm = L.off;  // not used by the small path
+        L.child = take(4u * np);
+        L.misc = take(64 + 4u * 64);
+        L.gpow = L.misc;
+        L.total = o;
+        return L;
     }
+    L.zkey = take(8u * L.p2);
+    L.tab = take(8u * L.h + 16u);
+    L.table_cap = (int32_t)((8u * L.p2 + 8u * L.h + 16u) / 4u);
+    L.dslot = take(4u * L.p2);
     L.off = take(4u * L.p2);
     L.ubuf = take(4u * np);
     L.lbuf = take(4u * np);
     L.child = take(4u * np);
     L.perm = take(4u * L.p2);
     L.misc = take(64 + 4u * 64);
-    L.gpow = small ? L.misc : take(4u * (kGpowLds + 2 * kMaxGoals));
-    L.cache = small ? take(12u * np) : 0;
+    L.gpow = take(4u * (kGpowLds + 2 * kMaxGoals));
     L.total = o;
     return L;
 }
@@ -178,13 +184,17 @@ int32_t variant_max_threads(const Variant &v);
 hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queue, int32_t n_tiles,
                          const Variant &v, const Schedule &sch, int32_t n_cu, hipStream_t stream);
 
-// Tiles are launched in groups of one model variant and one size class of
-// their leaf (n <= 64, 128, 256, 512, 1024, 2048).  A group gets the kernel
-// of its own model (RockSample tiles never run in the register budget of the
-// driving model) and an LDS carve-up and workgroup size for its own largest
-// leaf, so small leaves do not pay for the largest one's footprint (LDS is
-// what limits resident workgroups per CU).  Model variants: 0 RockSample,
-// 1-3 driving with up to 8, 16, 32 pedestrians.  Group g = variant *
+// Tiles are launched in groups.  A group holds tiles of one model variant
+// (0 RockSample, 1-3 driving with up to 8, 16, 32 pedestrians), so
+// RockSample tiles never run in the register budget of the driving model,
+// and gets an LDS carve-up and workgroup size for its own largest leaf.  By
+// default all leaves of a variant form one group (one dispatch, no fork and
+// join between dispatches), filed under the size class of its largest leaf;
+// split plans give each size class of leaf (n <= 64, 128, 256, 512, 1024,
+// 2048) a group of its own, so small leaves do not pay for the largest one's
+// footprint, and launch the groups side by side.  Inside a group the tiles
+// are ordered largest leaf first (long tiles start early, short ones fill
+// the tail), a leaf's tiles in action order.  Group g = variant *
 // kSizeClasses + size class; the tile array is ordered by group; group g
 // owns tiles [begin[g], begin[g] + count[g]) and the queue d_queues[g].
 constexpr int kSizeClasses = 6;
@@ -206,18 +216,23 @@ struct ClassPlan {
     int64_t begin[kGroups], count[kGroups];
     int32_t n_max[kGroups];
 };
-// Stable reorder of tiles[0, n_tiles) by group (variant[leaf] is the leaf's
-// model variant); fills plan.
-void plan_classes(const LeafTask *tasks, const int8_t *variant, Tile *tiles, int64_t n_tiles, ClassPlan *plan);
+// Reorder tiles[0, n_tiles) by group, largest leaf first inside a group
+// (variant[leaf] is the leaf's model variant); fills plan.
+void plan_classes(const LeafTask *tasks, const int8_t *variant, Tile *tiles, int64_t n_tiles, ClassPlan *plan,
+                  bool split);
 // One launch per non-empty group in mask (bit g = group g); lds_n[g] sizes
 // group g's LDS (>= its n_max); sch[g] is its schedule (its width capped at
 // what the group's leaves and model need).
 hipError_t launch_classes(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queues, const ClassPlan &plan,
                           const int32_t *lds_n, const Schedule *sch, int32_t n_cu, hipStream_t stream,
                           uint32_t mask = 0xffffffffu);
-// Default schedule of a class whose largest leaf has n_max scenarios: two
-// scenarios per lane up to 256 lanes, one workgroup per tile, XCD-contiguous.
-Schedule class_default_schedule(int32_t n_max, int32_t max_threads);
+// Default schedule of a group whose largest leaf has n_max scenarios.
+// Latency form (a few leaves, split groups): two scenarios per lane up to
+// 256 lanes, one workgroup per tile, XCD-contiguous.  Throughput form (one
+// group per model): RockSample one wavefront per tile (the most tiles in
+// flight, barriers of a single wavefront), driving as the latency form;
+// workgroups in tile order (largest first spreads over the XCDs).
+Schedule class_default_schedule(int32_t n_max, int32_t max_threads, int32_t mode = -1);
 hipError_t configure_expand_kernels();
 
 // Up to kArgLeaves leaves passed by value in the kernel arguments.

@@ -165,21 +165,9 @@ __device__ void block_exclusive_scan(int32_t *a, int len, int32_t *scratch) {
 
 __device__ __forceinline__ bool has_states(const StatesPtr &S) { return S.w != nullptr || S.s != nullptr; }
 
-// Leaf cache flags carried from one tile of a workgroup to the next tile of
-// the same leaf: the cache is in use; it holds the leaf's updated states and
-// scenario ids; it holds the sensor words of the leaf's depth.
-enum : int { kCacheOn = 4, kCacheStates = 1, kCacheWords = 2 };
-
-// One (leaf, action) tile.  `cache` holds the leaf cache flags on entry; the
-// flags valid for the next tile of the same leaf are returned.  The updated
-// leaf states and the sensor words do not depend on the tile's action, so a
-// workgroup that takes several tiles of one leaf gathers and updates the
-// scenarios once and draws each scenario's sensor word once; every lane
-// keeps its own scenarios (k = tid + i * blockDim), so the cache needs no
-// barrier of its own.
+// One (leaf, action) tile.
 template <class Ops>
-__device__ int run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char *lds, const LdsLayout &Ly,
-                        int cache) {
+__device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char *lds, const LdsLayout &Ly) {
     float *gpow_lds = (float *)(lds + Ly.gpow);
     const MView M = make_view(T->model, gpow_lds);
     const int n = T->n;
@@ -194,9 +182,8 @@ __device__ int run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char 
     float *lb = (float *)(lds + Ly.lbuf);
     int32_t *child = (int32_t *)(lds + Ly.child);
     int32_t *permb = (int32_t *)(lds + Ly.perm);
-    // per-chunk child counts: over zkey and tab (contiguous), or tab alone in
-    // the small carve-up, where they are cleared with the tile's other state
-    int32_t *cnt = (int32_t *)(lds + (Ly.small ? Ly.tab : Ly.zkey));
+    // per-chunk child counts: over zkey and tab (contiguous)
+    int32_t *cnt = (int32_t *)(lds + Ly.zkey);
     int32_t *misc = (int32_t *)(lds + Ly.misc);                   // [0] distinct count, [1] sentinel seen
     unsigned long long *stepc = (unsigned long long *)(misc + 4);  // expansion, rollout steps
     float *chunk_r = (float *)(misc + 8);                          // per-chunk reward sums (<= 32)
@@ -240,12 +227,6 @@ __device__ int run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char 
     const StatesPtr sprime = load_states(&T->sprime);
     const bool write_leaf = (a == 0);
     const bool pair_out = has_states(sprime);
-    const bool use_cache = Ops::kLeafCache && (cache & kCacheOn) != 0;
-    const bool have_states = use_cache && (cache & kCacheStates) != 0;
-    const bool have_words = use_cache && (cache & kCacheWords) != 0;
-    int32_t *c_w = (int32_t *)(lds + Ly.cache);
-    uint32_t *c_id = (uint32_t *)(c_w + Ly.np);
-    uint32_t *c_word = c_id + Ly.np;
 
     // -- gather + update + expand + bounds + rollouts (Eq. 10, 12, 13) ------
     // Every lane of a wavefront runs the same number of rounds, so the
@@ -259,7 +240,8 @@ __device__ int run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char 
         uint32_t id = 0;
         typename Ops::State st;
         // gather + update + expansion step of one scenario
-        auto gather_update = [&]() {
+        // gather + update + expansion step of one scenario
+        auto expand_one = [&]() {
             const int p = T->idx[k];
             id = T->parent_ids[p];
             Ops::load(M, parent, p, st);
@@ -268,41 +250,11 @@ __device__ int run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char 
                 uint64_t z0;
                 Ops::template step<false>(M, st, last_action, id, (uint32_t)(depth - 1), RP.k0, RP.k1, r0, z0);
             }
-        };
-        auto expand_one = [&]() {
-            if constexpr (Ops::kLeafCache) {
-                if (have_states) {
-                    st.w = c_w[k];
-                    id = c_id[k];
-                } else {
-                    gather_update();
-                    if (use_cache) {
-                        c_w[k] = st.w;
-                        c_id[k] = id;
-                    }
-                }
-            } else {
-                gather_update();
-            }
             if (write_leaf) {
                 Ops::store(M, leaf_out, k, st);
                 T->ids_out[k] = id;
             }
             my_exp += Ops::terminal(st) ? 0 : 1;
-            if constexpr (Ops::kLeafCache) {
-                if (use_cache) {
-                    Ops::template step_with<true>(
-                        M, st, a,
-                        [&]() {
-                            if (have_words) return c_word[k];
-                            const uint32_t u = Ops::sense_word(id, (uint32_t)depth, RP.k0, RP.k1);
-                            c_word[k] = u;
-                            return u;
-                        },
-                        r, z);
-                    return;
-                }
-            }
             Ops::template step<true>(M, st, a, id, (uint32_t)depth, RP.k0, RP.k1, r, z);
         };
         float U = 0.0f;
@@ -442,10 +394,7 @@ __device__ int run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char 
             if (T->child_of) T->child_of[(int64_t)a * n + k] = kci[v];
         }
         __syncthreads();  // LDS is reused by the next tile
-        if constexpr (Ops::kLeafCache) {
-            if (use_cache) return cache | kCacheStates | (Ops::draws_word(a) ? kCacheWords : 0);
-        }
-        return 0;
+        return;
     } else {
         // -- LDS hash of the observations ----------------------------------------
         for (int k = tid; k < n; k += nt) {
@@ -513,10 +462,8 @@ __device__ int run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char 
     // -- stable grouping: position of each scenario in perm --------------------
     const int nchunks = (n + 63) >> 6;
     if ((int64_t)nchunks * D <= Ly.table_cap) {
-        if (!Ly.small) {
-            for (int i = tid; i < nchunks * D; i += nt) cnt[i] = 0;
-            __syncthreads();
-        }
+        for (int i = tid; i < nchunks * D; i += nt) cnt[i] = 0;
+        __syncthreads();
         for (int t = wid; t < nchunks; t += nw) {
             const int k = t * 64 + lane;
             const bool valid = k < n;
@@ -649,15 +596,11 @@ __device__ int run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char 
         T->steps[2 * a + 1] = (int64_t)stepc[1];
     }
     __syncthreads();  // LDS is reused by the next tile
-    if constexpr (Ops::kLeafCache) {
-        if (use_cache) return cache | kCacheStates | (Ops::draws_word(a) ? kCacheWords : 0);
-    }
-    return 0;
 }
 
 template <int PM>
 __device__ __forceinline__ void run_ped(const HDX_CONST LeafTask *T, int a, unsigned char *lds, const LdsLayout &Ly) {
-    run_tile<PedOps<PM>>(T, a, lds, Ly, 0);
+    run_tile<PedOps<PM>>(T, a, lds, Ly);
 }
 
 __device__ __forceinline__ int remap_xcd(int b, int grid) {
@@ -677,55 +620,38 @@ constexpr int max_threads() { return MODE == 0 ? 512 : 256; }
 template <int MODE>
 constexpr int min_waves() { return MODE == 0 ? 7 : 1; }
 
-// A workgroup takes `span` consecutive tiles at a time (tiles of one leaf
-// are consecutive, in action order), so RockSample tiles after the first of
-// a leaf reuse the leaf cache.  The persistent form pops whole spans while
-// many tiles remain and single tiles at the tail.
 template <int MODE, int PM>
-__global__ __launch_bounds__(max_threads<MODE>(), min_waves<MODE>()) void expand_tiles(const LeafTask *tasks, const Tile *tiles,
-                                                                    TileQueue *queue, int32_t n_max,
-                                                                    int32_t persistent, int32_t xcd_remap,
-                                                                    int32_t span) {
+__global__ __launch_bounds__(max_threads<MODE>(), min_waves<MODE>()) void expand_tiles(const LeafTask *tasks,
+                                                                                       const Tile *tiles,
+                                                                                       TileQueue *queue,
+                                                                                       int32_t n_max,
+                                                                                       int32_t persistent,
+                                                                                       int32_t xcd_remap) {
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ int32_t s_tile, s_count;
+    __shared__ int32_t s_tile;
     const LdsLayout Ly = make_layout(n_max, MODE == 0);
     const int32_t n_tiles = __builtin_amdgcn_readfirstlane(queue->n_tiles);
-    const int cache_on = (MODE == 0 && (span > 1 || persistent)) ? kCacheOn : 0;
-    int cached_leaf = -1, flags = 0;
     int iter = 0;
     for (;;) {
-        int t0, count;
+        int t;
         if (persistent) {
-            if (threadIdx.x == 0) {
-                const int seen = __hip_atomic_load(&queue->next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const int want = (n_tiles - seen > 2 * span * (int)gridDim.x) ? span : 1;
-                s_tile = atomicAdd(&queue->next, want);
-                s_count = want;
-            }
+            if (threadIdx.x == 0) s_tile = atomicAdd(&queue->next, 1);
             __syncthreads();
-            t0 = __builtin_amdgcn_readfirstlane(s_tile);
-            count = __builtin_amdgcn_readfirstlane(s_count);
+            t = __builtin_amdgcn_readfirstlane(s_tile);
             __syncthreads();
         } else {
             if (iter > 0) break;
-            t0 = (xcd_remap ? remap_xcd((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x) * span;
-            count = span;
+            t = xcd_remap ? remap_xcd((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
         }
         ++iter;
-        if (t0 >= n_tiles) break;
-        const int t1 = min(t0 + count, n_tiles);
-        for (int t = t0; t < t1; ++t) {
-            const HDX_CONST Tile *tile = (const HDX_CONST Tile *)(tiles + t);
-            const int leaf = tile->leaf;
-            const HDX_CONST LeafTask *T = (const HDX_CONST LeafTask *)(tasks + leaf);
-            const int a = tile->action;
-            if (leaf != cached_leaf) flags = cache_on;
-            cached_leaf = leaf;
-            if (MODE == 0 || (MODE == 2 && T->kind == HDX_ROCKSAMPLE)) {
-                flags = run_tile<RsOps>(T, a, lds, Ly, flags);
-            } else if (MODE != 0) {
-                run_ped<PM>(T, a, lds, Ly);
-            }
+        if (t >= n_tiles) break;
+        const HDX_CONST Tile *tile = (const HDX_CONST Tile *)(tiles + t);
+        const HDX_CONST LeafTask *T = (const HDX_CONST LeafTask *)(tasks + tile->leaf);
+        const int a = tile->action;
+        if (MODE == 0 || (MODE == 2 && T->kind == HDX_ROCKSAMPLE)) {
+            run_tile<RsOps>(T, a, lds, Ly);
+        } else if (MODE != 0) {
+            run_ped<PM>(T, a, lds, Ly);
         }
     }
     if (persistent && threadIdx.x == 0) {
@@ -759,7 +685,7 @@ __global__ __launch_bounds__(max_threads<MODE>()) void expand_args(const ArgPack
     const HDX_CONST LeafTask *T = &P->t[i];
     const int a = t - P->tile_begin[i];
     if (MODE == 0 || (MODE == 2 && T->kind == HDX_ROCKSAMPLE)) {
-        run_tile<RsOps>(T, a, lds, Ly, 0);
+        run_tile<RsOps>(T, a, lds, Ly);
     } else if (MODE != 0) {
         run_ped<PM>(T, a, lds, Ly);
     }
@@ -790,12 +716,11 @@ hipError_t launch_expand_t(const LeafTask *d_tasks, const Tile *d_tiles, TileQue
     const LdsLayout Ly = make_layout(n_max, MODE == 0);
     // persistent: a fixed grid that drains the tile queue, so a captured
     // graph stays valid for any tile count
-    const int span = sch.span < 1 ? 1 : sch.span > kMaxSpan ? kMaxSpan : sch.span;
-    const int grid = sch.persistent > 0 ? n_cu * sch.persistent : (n_tiles + span - 1) / span;
+    const int grid = sch.persistent > 0 ? n_cu * sch.persistent : n_tiles;
     if (grid < 1) return hipSuccess;
     const int threads = sch.threads > max_threads<MODE>() ? max_threads<MODE>() : sch.threads;
     hipLaunchKernelGGL((expand_tiles<MODE, PM>), dim3(grid), dim3(threads), Ly.total, stream, d_tasks, d_tiles,
-                       d_queue, n_max, sch.persistent > 0 ? 1 : 0, sch.xcd_remap, span);
+                       d_queue, n_max, sch.persistent > 0 ? 1 : 0, sch.xcd_remap);
     return hipGetLastError();
 }
 

@@ -113,31 +113,15 @@ struct RsOps {
     static constexpr bool kSmallObs = true;       // observations 0 (none), 1, 2 (sensor readings)
     static constexpr bool kLdsModel = false;      // expansion reads no per-lane table from LDS
     static constexpr bool kWaveUpper = true;      // upper bound evaluated by whole wavefronts
-    static constexpr bool kLeafCache = true;      // leaf states and sensor words reusable across actions
 
     __device__ static void load(const MView &, const StatesPtr &S, int64_t p, State &st) { st.w = S.w[p]; }
     __device__ static void make_terminal(State &st) { st.w = 1 << 30; }
     __device__ static void store(const MView &, const StatesPtr &S, int64_t p, const State &st) { S.w[p] = st.w; }
     __device__ static bool terminal(const State &st) { return (st.w >> 30) & 1; }
 
-    // The uniform word a sensor reading draws: it depends on the scenario and
-    // the depth only, so every sense action at one depth reads the same one.
-    __device__ static uint32_t sense_word(uint32_t id, uint32_t depth, uint32_t k0, uint32_t k1) {
-        return philox(id, depth, 0, kTagStep, k0, k1).x;
-    }
-    // whether action a's step draws the sensor word of every live scenario
-    __device__ static bool draws_word(int a) { return a >= 5; }
-
     template <bool kObs>
     __device__ static void step(const MView &M, State &st, int a, uint32_t id, uint32_t depth, uint32_t k0,
                                 uint32_t k1, float &r, uint64_t &z) {
-        step_with<kObs>(M, st, a, [&]() { return sense_word(id, depth, k0, k1); }, r, z);
-    }
-
-    // The step with the sensor's uniform word supplied by word() (called only
-    // when an observation is drawn).
-    template <bool kObs, class Word>
-    __device__ static void step_with(const MView &M, State &st, int a, Word word, float &r, uint64_t &z) {
         int32_t w = st.w;
         r = 0.0f;
         z = 0;
@@ -175,7 +159,7 @@ struct RsOps {
             // drawn when the observation is wanted
             const int i = a - 5;
             const int dx = x - M.h->rock_x[i], dy = y - M.h->rock_y[i];
-            const uint32_t u = word();
+            const uint32_t u = philox(id, depth, 0, kTagStep, k0, k1).x;
             const int correct = u <= M.thr[dx * dx + dy * dy];
             const int truth = (w >> (10 + i)) & 1;
             z = (correct ? truth : !truth) ? 1 : 2;
@@ -256,7 +240,6 @@ struct PedOps {
     static constexpr bool kSmallObs = false;      // 64-bit hashed observations
     static constexpr bool kLdsModel = true;       // discount powers and goal points staged in LDS
     static constexpr bool kWaveUpper = false;     // per-lane upper bound
-    static constexpr bool kLeafCache = false;     // state too large to keep per scenario in LDS
 
     __device__ static void load(const MView &M, const StatesPtr &S, int64_t p, State &st) {
         st.s = S.s[p];

@@ -59,7 +59,7 @@ struct hdx_ctx {
     Slot slots[kSlots];
     int next_slot = 0;
     hipStream_t cls_stream[kGroups] = {};  // one stream per launch group (default priority)
-    Schedule sched{256, 0, 1, 1};
+    Schedule sched{256, 0, 1};
     bool sched_fixed = false;
 };
 
@@ -438,8 +438,15 @@ void pack_leaves(const hdx_leaf *leaves, int32_t n_leaves, LeafTask *tasks, Tile
 }  // namespace
 
 void hdx::plan_classes(const LeafTask *tasks, const int8_t *variant, Tile *tiles, int64_t n_tiles,
-                       ClassPlan *plan) {
-    auto group = [&](const Tile &t) { return variant[t.leaf] * kSizeClasses + size_class(tasks[t.leaf].n); };
+                       ClassPlan *plan, bool split) {
+    int32_t vmax[kModelVariants] = {0};
+    if (!split)
+        for (int64_t t = 0; t < n_tiles; ++t)
+            vmax[variant[tiles[t].leaf]] = std::max(vmax[variant[tiles[t].leaf]], tasks[tiles[t].leaf].n);
+    auto group = [&](const Tile &t) {
+        const int v = variant[t.leaf];
+        return v * kSizeClasses + size_class(split ? tasks[t.leaf].n : vmax[v]);
+    };
     int64_t cnt[kGroups] = {0};
     for (int g = 0; g < kGroups; ++g) plan->n_max[g] = 0;
     for (int64_t t = 0; t < n_tiles; ++t) {
@@ -453,21 +460,19 @@ void hdx::plan_classes(const LeafTask *tasks, const int8_t *variant, Tile *tiles
         plan->count[g] = cnt[g];
         at += cnt[g];
     }
-    bool sorted = true;
-    for (int64_t t = 1; t < n_tiles && sorted; ++t) sorted = group(tiles[t - 1]) <= group(tiles[t]);
-    if (sorted) return;
-    std::vector<Tile> tmp(tiles, tiles + n_tiles);
-    int64_t pos[kGroups];
-    for (int g = 0; g < kGroups; ++g) pos[g] = plan->begin[g];
-    for (const Tile &t : tmp) tiles[pos[group(t)]++] = t;
+    std::stable_sort(tiles, tiles + n_tiles, [&](const Tile &x, const Tile &y) {
+        const int gx = group(x), gy = group(y);
+        if (gx != gy) return gx < gy;
+        return tasks[x.leaf].n > tasks[y.leaf].n;
+    });
 }
 
-Schedule hdx::class_default_schedule(int32_t n_max, int32_t max_threads) {
+Schedule hdx::class_default_schedule(int32_t n_max, int32_t max_threads, int32_t mode) {
     Schedule s;
     s.threads = std::min(std::max(64, pow2_at_least(std::max(n_max, 1)) / 2), std::min(256, max_threads));
     s.persistent = 0;
-    s.xcd_remap = 1;
-    s.span = 1;
+    s.xcd_remap = mode < 0 ? 1 : 0;
+    if (mode == 0) s.threads = 64;
     return s;
 }
 
@@ -590,7 +595,7 @@ hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
     std::vector<int8_t> var(n_leaves);
     leaf_variants(leaves, n_leaves, var.data());
     ClassPlan plan;
-    plan_classes(s.h_tasks, var.data(), s.h_tiles, sh.n_tiles, &plan);
+    plan_classes(s.h_tasks, var.data(), s.h_tiles, sh.n_tiles, &plan, false);
     for (int g = 0; g < kGroups; ++g) s.h_queue[g] = TileQueue{0, 0, (int32_t)plan.count[g], 0};
     hipStream_t hs = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(s.d_tasks, s.h_tasks, n_leaves * sizeof(LeafTask), hipMemcpyHostToDevice, hs);
@@ -602,7 +607,8 @@ hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
     Schedule sch[kGroups];
     for (int g = 0; g < kGroups; ++g)
         sch[g] = ctx->sched_fixed ? ctx->sched
-                                  : class_default_schedule(plan.n_max[g], variant_max_threads(group_variant(g)));
+                                  : class_default_schedule(plan.n_max[g], variant_max_threads(group_variant(g)),
+                                                           group_variant(g).mode);
     e = launch_classes_forked(s.d_tasks, s.d_tiles, s.d_queue, plan, no_lds, sch, ctx->n_cu, hs, ctx->cls_stream,
                               s.fork, s.join);
     if (e != hipSuccess) return hip_fail(ctx, e, "expand launch");
@@ -637,6 +643,8 @@ struct hdx_batch {
     hipGraphExec_t exec = nullptr;
     Schedule g_sched[kGroups];
     int64_t g_tiles = 0;
+    bool split = false;         // one launch group per (model variant, size class)
+    std::vector<int8_t> var;    // model variant of each staged leaf
 };
 
 namespace {
@@ -654,7 +662,29 @@ int32_t group_width_cap(const hdx_batch *b, int g) {
 }
 
 bool same_schedule(const Schedule &a, const Schedule &b) {
-    return a.threads == b.threads && a.persistent == b.persistent && a.xcd_remap == b.xcd_remap && a.span == b.span;
+    return a.threads == b.threads && a.persistent == b.persistent && a.xcd_remap == b.xcd_remap;
+}
+
+// Default schedule of every group that has none set.
+void default_schedules(hdx_batch *b) {
+    for (int g = 0; g < kGroups; ++g)
+        if (!b->sched_set[g])
+            b->sched[g] = class_default_schedule(std::max(b->lds_c[g], 1), variant_max_threads(group_variant(g)),
+                                                 group_variant(g).mode);
+}
+
+// Plan the staged tiles (split or merged groups) and copy tiles and queues
+// to the device on `st`.
+hipError_t replan(hdx_batch *b, hipStream_t st) {
+    plan_classes(b->h_tasks, b->var.data(), b->h_tiles, b->n_tiles, &b->plan, b->split);
+    for (int g = 0; g < kGroups; ++g) {
+        b->h_queue[g] = TileQueue{0, 0, (int32_t)b->plan.count[g], 0};
+        b->lds_c[g] = std::max(b->lds_c[g], b->plan.n_max[g]);
+    }
+    hipError_t e = hipSuccess;
+    if (b->n_tiles > 0) e = hipMemcpyAsync(b->d_tiles, b->h_tiles, b->n_tiles * sizeof(Tile), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_queue, b->h_queue, kGroups * sizeof(TileQueue), hipMemcpyHostToDevice, st);
+    return e;
 }
 
 void drop_graph(hdx_batch *b) {
@@ -732,73 +762,85 @@ hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *b, const hdx_leaf *leav
         if (e != hipSuccess) return hip_fail(ctx, e, "staging wait");
     }
     pack_leaves(leaves, n_leaves, b->h_tasks, b->h_tiles);
-    std::vector<int8_t> var(std::max(n_leaves, 1));
-    leaf_variants(leaves, n_leaves, var.data());
-    plan_classes(b->h_tasks, var.data(), b->h_tiles, sh.n_tiles, &b->plan);
-    for (int g = 0; g < kGroups; ++g) {
-        b->h_queue[g] = TileQueue{0, 0, (int32_t)b->plan.count[g], 0};
-        // LDS sized for the largest leaf a group has seen, so graphs survive smaller batches
-        b->lds_c[g] = std::max(b->lds_c[g], b->plan.n_max[g]);
-    }
+    b->var.assign(std::max(n_leaves, 1), 0);
+    leaf_variants(leaves, n_leaves, b->var.data());
+    b->n_leaves = n_leaves;
+    b->n_tiles = sh.n_tiles;
+    // LDS sized for the largest leaf a group has seen, so graphs survive smaller batches
     hipStream_t hs = (hipStream_t)stream;
     hipError_t e = hipSuccess;
     if (n_leaves > 0) e = hipMemcpyAsync(b->d_tasks, b->h_tasks, n_leaves * sizeof(LeafTask), hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess && sh.n_tiles > 0)
-        e = hipMemcpyAsync(b->d_tiles, b->h_tiles, sh.n_tiles * sizeof(Tile), hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_queue, b->h_queue, kGroups * sizeof(TileQueue), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = replan(b, hs);
     if (e == hipSuccess) e = hipEventRecord(b->staged, hs);
     if (e != hipSuccess) return hip_fail(ctx, e, "batch descriptor copy");
     b->staged_used = true;
-    b->n_leaves = n_leaves;
-    b->n_tiles = sh.n_tiles;
-    for (int g = 0; g < kGroups; ++g)
-        if (!b->sched_set[g])
-            b->sched[g] = class_default_schedule(std::max(b->lds_c[g], 1), variant_max_threads(group_variant(g)));
+    default_schedules(b);
+    return HDX_OK;
+}
+
+hdx_status hdx_batch_set_split(hdx_ctx *ctx, hdx_batch *b, int32_t split) {
+    if (!ctx || !b) return HDX_E_INVALID;
+    if ((split != 0) == b->split) return HDX_OK;
+    hipSetDevice(ctx->device);
+    if (b->staged_used) {
+        hipError_t e = hipEventSynchronize(b->staged);
+        if (e != hipSuccess) return hip_fail(ctx, e, "staging wait");
+    }
+    hipDeviceSynchronize();  // no launch may still read the tiles
+    b->split = split != 0;
+    drop_graph(b);
+    hipError_t e = replan(b, b->work);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->work);
+    if (e != hipSuccess) return hip_fail(ctx, e, "replan");
+    default_schedules(b);
+    return HDX_OK;
+}
+
+hdx_status hdx_batch_get_split(const hdx_batch *b, int32_t *split) {
+    if (!b || !split) return HDX_E_INVALID;
+    *split = b->split ? 1 : 0;
     return HDX_OK;
 }
 
 hdx_status hdx_batch_set_schedule(hdx_ctx *ctx, hdx_batch *b, int32_t threads, int32_t persistent,
-                                  int32_t xcd_remap, int32_t span) {
+                                  int32_t xcd_remap) {
     if (!ctx || !b) return HDX_E_INVALID;
-    if (threads < 64 || threads > 1024 || threads % 64 != 0 || persistent < 0 || persistent > 64 || span < 1 ||
-        span > kMaxSpan)
+    if (threads < 64 || threads > 1024 || threads % 64 != 0 || persistent < 0 || persistent > 64)
         return fail(ctx, HDX_E_INVALID, "schedule");
     for (int g = 0; g < kGroups; ++g) {
-        b->sched[g] = Schedule{threads, persistent, xcd_remap ? 1 : 0, span};
+        b->sched[g] = Schedule{threads, persistent, xcd_remap ? 1 : 0};
         b->sched_set[g] = true;
     }
     return HDX_OK;
 }
 
 hdx_status hdx_batch_set_class_schedule(hdx_ctx *ctx, hdx_batch *b, int32_t cls, int32_t threads, int32_t persistent,
-                                        int32_t xcd_remap, int32_t span) {
+                                        int32_t xcd_remap) {
     if (!ctx || !b) return HDX_E_INVALID;
     if (cls < 0 || cls >= kSizeClasses || threads < 64 || threads > 1024 || threads % 64 != 0 || persistent < 0 ||
-        persistent > 64 || span < 1 || span > kMaxSpan)
+        persistent > 64)
         return fail(ctx, HDX_E_INVALID, "schedule");
     for (int v = 0; v < kModelVariants; ++v) {
-        b->sched[v * kSizeClasses + cls] = Schedule{threads, persistent, xcd_remap ? 1 : 0, span};
+        b->sched[v * kSizeClasses + cls] = Schedule{threads, persistent, xcd_remap ? 1 : 0};
         b->sched_set[v * kSizeClasses + cls] = true;
     }
     return HDX_OK;
 }
 
 hdx_status hdx_batch_get_group_schedule(const hdx_batch *b, int32_t group, int32_t *threads, int32_t *persistent,
-                                        int32_t *xcd_remap, int32_t *span, int64_t *tiles) {
+                                        int32_t *xcd_remap, int64_t *tiles) {
     if (!b || !threads || !persistent || !xcd_remap || group < 0 || group >= kGroups) return HDX_E_INVALID;
     const Schedule &s = b->sched[group];
     const int32_t cap = group_width_cap(b, group);
     *threads = s.threads > cap ? cap : s.threads;
     *persistent = s.persistent;
     *xcd_remap = s.xcd_remap;
-    if (span) *span = s.span;
     if (tiles) *tiles = b->plan.count[group];
     return HDX_OK;
 }
 
 hdx_status hdx_batch_get_class_schedule(const hdx_batch *b, int32_t cls, int32_t *threads, int32_t *persistent,
-                                        int32_t *xcd_remap, int32_t *span, int64_t *tiles) {
+                                        int32_t *xcd_remap, int64_t *tiles) {
     if (!b || !threads || !persistent || !xcd_remap || cls < 0 || cls >= kSizeClasses) return HDX_E_INVALID;
     // the class's group with the most tiles
     int best = cls;
@@ -808,18 +850,17 @@ hdx_status hdx_batch_get_class_schedule(const hdx_batch *b, int32_t cls, int32_t
         total += b->plan.count[g];
         if (b->plan.count[g] > b->plan.count[best]) best = g;
     }
-    const hdx_status st = hdx_batch_get_group_schedule(b, best, threads, persistent, xcd_remap, span, nullptr);
+    const hdx_status st = hdx_batch_get_group_schedule(b, best, threads, persistent, xcd_remap, nullptr);
     if (tiles) *tiles = total;
     return st;
 }
 
-hdx_status hdx_batch_get_schedule(const hdx_batch *b, int32_t *threads, int32_t *persistent, int32_t *xcd_remap,
-                                  int32_t *span) {
+hdx_status hdx_batch_get_schedule(const hdx_batch *b, int32_t *threads, int32_t *persistent, int32_t *xcd_remap) {
     if (!b || !threads || !persistent || !xcd_remap) return HDX_E_INVALID;
     int big = 0;
     for (int g = 1; g < kGroups; ++g)
         if (b->plan.count[g] > b->plan.count[big]) big = g;
-    return hdx_batch_get_group_schedule(b, big, threads, persistent, xcd_remap, span, nullptr);
+    return hdx_batch_get_group_schedule(b, big, threads, persistent, xcd_remap, nullptr);
 }
 
 hdx_status hdx_batch_use_graph(hdx_ctx *ctx, hdx_batch *b, int32_t enable) {
@@ -878,22 +919,15 @@ hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *b, int32_t reps, float *b
     if (b->staged_used) hipEventSynchronize(b->staged);
     auto candidates = [&](int c) {
         const int cap = group_width_cap(b, c);
-        // spans only where the leaf cache makes them pay (RockSample groups)
-        const bool spans = group_variant(c).mode == 0;
         std::vector<Schedule> cand;
         for (int th = 64; th <= cap; th *= 2) {
-            cand.push_back(Schedule{th, 0, 0, 1});
-            cand.push_back(Schedule{th, 0, 1, 1});
-            for (int p : {1, 2, 4, 8}) cand.push_back(Schedule{th, p, 0, 1});
-            if (!spans) continue;
-            for (int sp : {2, 4}) {
-                cand.push_back(Schedule{th, 0, 1, sp});
-                for (int p : {2, 4}) cand.push_back(Schedule{th, p, 0, sp});
-            }
+            cand.push_back(Schedule{th, 0, 0});
+            cand.push_back(Schedule{th, 0, 1});
+            for (int p : {1, 2, 4, 8}) cand.push_back(Schedule{th, p, 0});
         }
         return cand;
     };
-    // mean ms of `reps` launches of the classes in mask under schedules s
+    // mean ms of `reps` launches of the groups in mask under schedules s
     auto time_launch = [&](const Schedule *s, uint32_t mask, float *ms) -> hipError_t {
         hipError_t e = batch_direct_launch(ctx, b, s, b->work, mask);  // warm-up
         if (e == hipSuccess) e = hipEventRecord(b->t0, b->work);
@@ -904,60 +938,89 @@ hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *b, int32_t reps, float *b
         *ms /= (float)reps;
         return e;
     };
-    int active = 0;
-    for (int c = 0; c < kGroups; ++c) active += b->plan.count[c] > 0;
-    // 1: each launch group on its own launch
-    Schedule trial[kGroups];
-    for (int k = 0; k < kGroups; ++k) trial[k] = b->sched[k];
-    float total = 0.0f;
-    for (int c = 0; c < kGroups; ++c) {
-        if (b->plan.count[c] == 0) continue;
-        float best = 1e30f;
-        Schedule best_s = b->sched[c];
-        for (const Schedule &s : candidates(c)) {
-            trial[c] = s;
-            float ms = 0.0f;
-            const hipError_t e = time_launch(trial, 1u << c, &ms);
-            if (e != hipSuccess) return hip_fail(ctx, e, "autotune launch");
-            if (ms < best) {
-                best = ms;
-                best_s = s;
-            }
-        }
-        trial[c] = best_s;
-        total += best;
-    }
-    // 2: the groups run side by side, so each group's schedule is refined
-    // once more against the whole launch with the others at their choice
-    if (active > 1) {
-        float best = 0.0f;
-        hipError_t e = time_launch(trial, 0xffffffffu, &best);
-        if (e != hipSuccess) return hip_fail(ctx, e, "autotune launch");
-        for (int c = kGroups - 1; c >= 0; --c) {
+    // schedules of the current plan's groups: 1, each group on its own
+    // launch; 2, as the groups run side by side, each group's schedule once
+    // more against the whole launch with the others at their choice
+    auto tune_plan = [&](Schedule *trial, float *total) -> hipError_t {
+        int active = 0;
+        for (int c = 0; c < kGroups; ++c) active += b->plan.count[c] > 0;
+        for (int k = 0; k < kGroups; ++k) trial[k] = b->sched[k];
+        *total = 0.0f;
+        for (int c = 0; c < kGroups; ++c) {
             if (b->plan.count[c] == 0) continue;
-            const Schedule keep = trial[c];
-            Schedule best_s = keep;
+            float best = 1e30f;
+            Schedule best_s = b->sched[c];
             for (const Schedule &s : candidates(c)) {
-                if (same_schedule(s, keep)) continue;
                 trial[c] = s;
                 float ms = 0.0f;
-                e = time_launch(trial, 0xffffffffu, &ms);
-                if (e != hipSuccess) return hip_fail(ctx, e, "autotune launch");
+                const hipError_t e = time_launch(trial, 1u << c, &ms);
+                if (e != hipSuccess) return e;
                 if (ms < best) {
                     best = ms;
                     best_s = s;
                 }
             }
             trial[c] = best_s;
+            *total += best;
         }
-        total = best;
+        if (active > 1) {
+            float best = 0.0f;
+            hipError_t e = time_launch(trial, 0xffffffffu, &best);
+            if (e != hipSuccess) return e;
+            for (int c = kGroups - 1; c >= 0; --c) {
+                if (b->plan.count[c] == 0) continue;
+                const Schedule keep = trial[c];
+                Schedule best_s = keep;
+                for (const Schedule &s : candidates(c)) {
+                    if (same_schedule(s, keep)) continue;
+                    trial[c] = s;
+                    float ms = 0.0f;
+                    e = time_launch(trial, 0xffffffffu, &ms);
+                    if (e != hipSuccess) return e;
+                    if (ms < best) {
+                        best = ms;
+                        best_s = s;
+                    }
+                }
+                trial[c] = best_s;
+            }
+            *total = best;
+        }
+        return hipSuccess;
+    };
+    // both plans (one group per model, or per model and size class); the
+    // faster one is kept
+    hipDeviceSynchronize();
+    drop_graph(b);
+    const bool first = b->split;
+    Schedule sa[kGroups], sb[kGroups];
+    float ta = 0.0f, tb = 0.0f;
+    hipError_t e = tune_plan(sa, &ta);
+    if (e == hipSuccess) {
+        b->split = !first;
+        e = replan(b, b->work);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->work);
+        if (e == hipSuccess) {
+            default_schedules(b);
+            e = tune_plan(sb, &tb);
+        }
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "autotune launch");
+    const Schedule *chosen = sb;
+    float total = tb;
+    if (ta <= tb) {
+        b->split = first;
+        e = replan(b, b->work);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->work);
+        if (e != hipSuccess) return hip_fail(ctx, e, "replan");
+        chosen = sa;
+        total = ta;
     }
     for (int c = 0; c < kGroups; ++c)
         if (b->plan.count[c] > 0) {
-            b->sched[c] = trial[c];
+            b->sched[c] = chosen[c];
             b->sched_set[c] = true;
         }
-    drop_graph(b);
     if (best_ms) *best_ms = total;
     return HDX_OK;
 }

@@ -101,6 +101,7 @@ EXPORTS = ["hdx_version", "hdx_init", "hdx_fini", "hdx_last_error", "hdx_upload_
            "hdx_sample_scenarios", "hdx_expand_leaf", "hdx_rollout_bounds", "hdx_philox",
            "hdx_fp32_selftest", "hdx_batch_create", "hdx_batch_destroy", "hdx_batch_set_leaves",
            "hdx_batch_set_schedule", "hdx_batch_get_schedule", "hdx_batch_use_graph",
+           "hdx_batch_set_split", "hdx_batch_get_split",
            "hdx_batch_set_class_schedule", "hdx_batch_get_class_schedule", "hdx_batch_get_group_schedule",
            "hdx_batch_launch", "hdx_batch_autotune", "hdx_search", "hdx_mlp_create", "hdx_mlp_destroy",
            "hdx_mlp_get_params", "hdx_mlp_set_params", "hdx_mlp_forward", "hdx_mlp_gradients",
@@ -139,13 +140,15 @@ def load_library():
     L.hdx_batch_create.argtypes = [P, I32, I64, C.POINTER(P)]
     L.hdx_batch_destroy.argtypes = [P, P]
     L.hdx_batch_set_leaves.argtypes = [P, P, P, I32, P]
-    L.hdx_batch_set_schedule.argtypes = [P, P, I32, I32, I32, I32]
-    L.hdx_batch_get_schedule.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]
-    L.hdx_batch_set_class_schedule.argtypes = [P, P, I32, I32, I32, I32, I32]
+    L.hdx_batch_set_split.argtypes = [P, P, I32]
+    L.hdx_batch_get_split.argtypes = [P, C.POINTER(I32)]
+    L.hdx_batch_set_schedule.argtypes = [P, P, I32, I32, I32]
+    L.hdx_batch_get_schedule.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]
+    L.hdx_batch_set_class_schedule.argtypes = [P, P, I32, I32, I32, I32]
     L.hdx_batch_get_class_schedule.argtypes = [P, I32, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32),
-                                               C.POINTER(I32), C.POINTER(I64)]
+                                               C.POINTER(I64)]
     L.hdx_batch_get_group_schedule.argtypes = [P, I32, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32),
-                                               C.POINTER(I32), C.POINTER(I64)]
+                                               C.POINTER(I64)]
     L.hdx_batch_use_graph.argtypes = [P, P, I32]
     L.hdx_batch_launch.argtypes = [P, P, P]
     L.hdx_batch_autotune.argtypes = [P, P, I32, C.POINTER(C.c_float)]
@@ -481,41 +484,50 @@ class Batch:
         self.ctx._check(self.lib.hdx_batch_set_leaves(self.ctx.handle, self.handle, C.cast(arr, C.c_void_p),
                                                       len(leaves), _stream(stream)))
 
-    def set_schedule(self, threads: int, persistent: int, xcd_remap: int, span: int = 1):
+    def set_split(self, split: bool):
+        """One launch group per model variant (False, the default) or per
+        model variant and size class (True); re-plans the staged leaves."""
+        self.ctx._check(self.lib.hdx_batch_set_split(self.ctx.handle, self.handle, int(split)))
+
+    def split(self) -> bool:
+        v = C.c_int32()
+        self.ctx._check(self.lib.hdx_batch_get_split(self.handle, C.byref(v)))
+        return bool(v.value)
+
+    def set_schedule(self, threads: int, persistent: int, xcd_remap: int):
         self.ctx._check(self.lib.hdx_batch_set_schedule(self.ctx.handle, self.handle, threads, persistent,
-                                                        xcd_remap, span))
+                                                        xcd_remap))
 
     def schedule(self):
-        """(threads, persistent, xcd_remap, span) of the group with the most tiles."""
-        t, p, x, sp = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
-        self.ctx._check(self.lib.hdx_batch_get_schedule(self.handle, C.byref(t), C.byref(p), C.byref(x),
-                                                        C.byref(sp)))
-        return t.value, p.value, x.value, sp.value
+        """(threads, persistent, xcd_remap) of the group with the most tiles."""
+        t, p, x = C.c_int32(), C.c_int32(), C.c_int32()
+        self.ctx._check(self.lib.hdx_batch_get_schedule(self.handle, C.byref(t), C.byref(p), C.byref(x)))
+        return t.value, p.value, x.value
 
-    def set_class_schedule(self, size_class: int, threads: int, persistent: int, xcd_remap: int, span: int = 1):
+    def set_class_schedule(self, size_class: int, threads: int, persistent: int, xcd_remap: int):
         self.ctx._check(self.lib.hdx_batch_set_class_schedule(self.ctx.handle, self.handle, size_class, threads,
-                                                              persistent, xcd_remap, span))
+                                                              persistent, xcd_remap))
 
     def class_schedules(self) -> list:
-        """[(size_class, threads, persistent, xcd_remap, span, tiles)] of the non-empty classes."""
+        """[(size_class, threads, persistent, xcd_remap, tiles)] of the non-empty classes."""
         out = []
         for c in range(SIZE_CLASSES):
-            t, p, x, sp, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+            t, p, x, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
             self.ctx._check(self.lib.hdx_batch_get_class_schedule(self.handle, c, C.byref(t), C.byref(p), C.byref(x),
-                                                                  C.byref(sp), C.byref(n)))
+                                                                  C.byref(n)))
             if n.value:
-                out.append((c, t.value, p.value, x.value, sp.value, n.value))
+                out.append((c, t.value, p.value, x.value, n.value))
         return out
 
     def group_schedules(self) -> list:
-        """[(model_variant, size_class, threads, persistent, xcd_remap, span, tiles)] of the non-empty groups."""
+        """[(model_variant, size_class, threads, persistent, xcd_remap, tiles)] of the non-empty groups."""
         out = []
         for g in range(LAUNCH_GROUPS):
-            t, p, x, sp, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+            t, p, x, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
             self.ctx._check(self.lib.hdx_batch_get_group_schedule(self.handle, g, C.byref(t), C.byref(p), C.byref(x),
-                                                                  C.byref(sp), C.byref(n)))
+                                                                  C.byref(n)))
             if n.value:
-                out.append((g // SIZE_CLASSES, g % SIZE_CLASSES, t.value, p.value, x.value, sp.value, n.value))
+                out.append((g // SIZE_CLASSES, g % SIZE_CLASSES, t.value, p.value, x.value, n.value))
         return out
 
     def use_graph(self, enable: bool = True):

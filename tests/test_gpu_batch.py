@@ -81,15 +81,17 @@ def test_batch_equals_per_instance_under_every_schedule(ctx):
     b = Batch(ctx, 64, 64 * 25)
     b.set_leaves([it["leaf"] for it in items])
     torch.cuda.synchronize()
-    for threads in (64, 128, 256):
-        for persistent, xcd, span in ((0, 0, 1), (0, 1, 1), (1, 0, 1), (3, 0, 1), (8, 0, 1), (0, 1, 3), (0, 0, 7),
-                                      (2, 0, 4), (1, 0, 32)):
-            print("schedule", threads, persistent, xcd, span, flush=True)
-            clear(items)
-            b.set_schedule(threads, persistent, xcd, span)
-            b.launch()
-            torch.cuda.synchronize()
-            assert_same(snapshot(items), ref)
+    for split in (False, True):
+        b.set_split(split)
+        assert b.split() == split
+        for threads in (64, 128, 256):
+            for persistent, xcd in ((0, 0), (0, 1), (1, 0), (3, 0), (8, 0)):
+                print("plan split=%d schedule" % split, threads, persistent, xcd, flush=True)
+                clear(items)
+                b.set_schedule(threads, persistent, xcd)
+                b.launch()
+                torch.cuda.synchronize()
+                assert_same(snapshot(items), ref)
     b.close()
 
 
@@ -146,8 +148,8 @@ def test_autotune_keeps_results(ctx):
     b.set_leaves([it["leaf"] for it in items])
     ms = b.autotune(2)
     assert ms > 0
-    threads, persistent, xcd, span = b.schedule()
-    assert threads in (64, 128, 256, 512) and 1 <= span <= 32
+    threads, persistent, xcd = b.schedule()
+    assert threads in (64, 128, 256, 512)
     clear(items)
     b.launch()
     torch.cuda.synchronize()
@@ -165,12 +167,12 @@ def test_batch_capacity_error(ctx):
     b.close()
 
 
-def test_leaf_cache_spans_match_single_tiles(ctx):
-    """RockSample workgroups that take several tiles of one leaf gather and
-    update its scenarios once and draw each sensor word once (the leaf
-    cache); every output, per-pair ones included, must equal a launch that
-    takes one tile per workgroup, under spans that split leaves at any
-    action and persistent pops."""
+def test_rocksample_plans_match_single_leaf_calls(ctx):
+    """RockSample leaves of every size class (terminal scenarios, a sense
+    action before the leaf) in one batch: under the unsplit plan (all sizes
+    in one dispatch, largest first, one wavefront or more per tile) and the
+    split plan, every output, per-pair ones included, must equal one-leaf
+    calls, and sampled leaves must match the oracle."""
     from paper_1802_06215_amd import Batch
     desc = W.rocksample_model(15, 15, 3)
     m = ctx.upload_model(desc)
@@ -194,14 +196,15 @@ def test_leaf_cache_spans_match_single_tiles(ctx):
     b = Batch(ctx, len(items), len(items) * desc["n_actions"])
     b.set_leaves([it["leaf"] for it in items])
     torch.cuda.synchronize()
-    for threads, persistent, xcd, span in ((64, 0, 1, 2), (256, 0, 0, 3), (128, 0, 1, 20), (256, 0, 1, 32),
-                                           (64, 2, 0, 4), (256, 1, 0, 7), (512, 4, 0, 20)):
-        print("span schedule", threads, persistent, xcd, span, flush=True)
+    for split, threads, persistent, xcd in ((False, 64, 0, 0), (False, 64, 0, 1), (False, 256, 0, 0),
+                                            (False, 512, 2, 0), (True, 64, 0, 1), (True, 128, 1, 0)):
+        print("plan split=%d schedule" % split, threads, persistent, xcd, flush=True)
         clear(items)
         for it in items:
             for t in (it["out"].r, it["out"].z, it["out"].U, it["out"].L):
                 t.fill_(-3)
-        b.set_schedule(threads, persistent, xcd, span)
+        b.set_split(split)
+        b.set_schedule(threads, persistent, xcd)
         b.launch()
         torch.cuda.synchronize()
         got = snapshot(items)
