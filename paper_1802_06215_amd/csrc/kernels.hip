@@ -232,6 +232,7 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
     // Every lane of a wavefront runs the same number of rounds, so the
     // reward of a 64-scenario chunk can be summed with shuffles right here.
     int my_exp = 0, my_roll = 0;
+    typename Ops::WaveUpper wave_upper;
     for (int base = 0; base < n; base += nt) {
         const int k = base + tid;
         const bool valid = k < n;
@@ -263,7 +264,7 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
             // per-rock terms across lanes); lanes past n stay terminal
             Ops::make_terminal(st);
             if (valid) expand_one();
-            U = Ops::upper_wave(M, st);
+            U = Ops::upper_wave(M, st, wave_upper);
         } else if (valid) {
             expand_one();
             U = Ops::upper(M, st);

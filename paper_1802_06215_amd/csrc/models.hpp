@@ -176,12 +176,21 @@ struct RsOps {
         return u + 10.0f * M.gpow_lane(M.h->grid - 1 - x);
     }
 
+    // Per-rock terms of the last common cell, kept across the rounds of a
+    // tile (wavefront-uniform except ci, which lane i holds for rock i).
+    struct WaveUpper {
+        int x = -1, y = -1;
+        float ci = 0.0f, exit = 0.0f;
+    };
+
     // The same value, bit for bit.  Robot cells are deterministic, so the
-    // live scenarios of a tile usually share one cell: then lane i computes
-    // rock i's discounted reward once for the wavefront and every lane only
-    // selects the terms of its good rocks (adding +0 for the others leaves
-    // the sum unchanged).  Called by all 64 lanes of a wavefront.
-    __device__ static float upper_wave(const MView &M, const State &st) {
+    // live scenarios of a tile usually share one cell: then lane i holds
+    // rock i's discounted reward for the wavefront (recomputed only when the
+    // cell changes) and every lane adds the terms of its good rocks, masking
+    // the others to +0 (which leaves the sum unchanged): a sign-extended bit
+    // field, an and, an add and a lane read per rock.  Called by all 64
+    // lanes of a wavefront.
+    __device__ static float upper_wave(const MView &M, const State &st, WaveUpper &wu) {
         const bool live = !((st.w >> 30) & 1);
         const int x = st.w & 31, y = (st.w >> 5) & 31;
         const uint64_t lv = __ballot(live);
@@ -199,15 +208,20 @@ struct RsOps {
         }
         const int xs = __builtin_amdgcn_readfirstlane(x0), ys = __builtin_amdgcn_readfirstlane(y0);
         const int nr = M.h->n_rocks;
-        const int lane = (int)__lane_id();
-        float ci = 0.0f;
-        if (lane < nr) ci = 10.0f * M.gg[abs(xs - M.h->rock_x[lane]) + abs(ys - M.h->rock_y[lane])];
+        if (xs != wu.x || ys != wu.y) {
+            const int lane = (int)__lane_id();
+            wu.ci = lane < nr ? 10.0f * M.gg[abs(xs - M.h->rock_x[lane]) + abs(ys - M.h->rock_y[lane])] : 0.0f;
+            wu.exit = 10.0f * M.gpow_uniform(M.h->grid - 1 - xs);
+            wu.x = xs;
+            wu.y = ys;
+        }
         float u = 0.0f;
         for (int i = 0; i < nr; ++i) {
-            const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ci), i));
-            u += ((st.w >> (10 + i)) & 1) ? c : 0.0f;
+            const int c = __builtin_amdgcn_readlane(__float_as_int(wu.ci), i);
+            const int keep = __builtin_amdgcn_sbfe(st.w, 10 + i, 1);  // all ones if rock i is good
+            u = u + __int_as_float(keep & c);
         }
-        u = u + 10.0f * M.gpow_uniform(M.h->grid - 1 - xs);
+        u = u + wu.exit;
         return live ? u : 0.0f;
     }
 
@@ -240,6 +254,7 @@ struct PedOps {
     static constexpr bool kSmallObs = false;      // 64-bit hashed observations
     static constexpr bool kLdsModel = true;       // discount powers and goal points staged in LDS
     static constexpr bool kWaveUpper = false;     // per-lane upper bound
+    struct WaveUpper {};
 
     __device__ static void load(const MView &M, const StatesPtr &S, int64_t p, State &st) {
         st.s = S.s[p];
