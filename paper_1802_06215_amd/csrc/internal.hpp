@@ -194,10 +194,12 @@ hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue
 // 2048) a group of its own, so small leaves do not pay for the largest one's
 // footprint, and launch the groups side by side.  Inside a group the tiles
 // are ordered largest leaf first (long tiles start early, short ones fill
-// the tail), a leaf's tiles in action order.  Group g = variant *
+// the tail), a leaf's tiles in action order, and interleaved so that the
+// tiles of one leaf go to one XCD.  Group g = variant *
 // kSizeClasses + size class; the tile array is ordered by group; group g
 // owns tiles [begin[g], begin[g] + count[g]) and the queue d_queues[g].
 constexpr int kSizeClasses = 6;
+constexpr int kXcds = 8;  // accelerator dies, each with its own L2
 constexpr int kModelVariants = 4;
 constexpr int kGroups = kModelVariants * kSizeClasses;
 __host__ __device__ inline int size_class(int32_t n) {

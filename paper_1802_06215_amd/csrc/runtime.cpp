@@ -465,6 +465,32 @@ void hdx::plan_classes(const LeafTask *tasks, const int8_t *variant, Tile *tiles
         if (gx != gy) return gx < gy;
         return tasks[x.leaf].n > tasks[y.leaf].n;
     });
+    // Workgroups are dealt to the 8 XCDs round-robin (workgroup b to XCD
+    // b mod 8), each XCD with its own L2.  Inside a group, deal the leaves
+    // (largest first) to the XCDs in turn and interleave the XCDs' tile
+    // lists, so every tile of a leaf runs where its parent data is cached
+    // while each XCD still sees the sizes largest first.
+    std::vector<Tile> lists[kXcds];
+    for (int g = 0; g < kGroups; ++g) {
+        Tile *t = tiles + plan->begin[g];
+        const int64_t count = plan->count[g];
+        if (count < 2 * kXcds) continue;
+        for (auto &l : lists) l.clear();
+        int32_t prev = -1;
+        int64_t rank = -1;
+        for (int64_t i = 0; i < count; ++i) {
+            if (t[i].leaf != prev) {
+                prev = t[i].leaf;
+                ++rank;
+            }
+            lists[rank % kXcds].push_back(t[i]);
+        }
+        size_t pos[kXcds] = {};
+        int64_t o = 0;
+        while (o < count)
+            for (int x = 0; x < kXcds; ++x)
+                if (pos[x] < lists[x].size()) t[o++] = lists[x][pos[x]++];
+    }
 }
 
 Schedule hdx::class_default_schedule(int32_t n_max, int32_t max_threads, int32_t mode) {
