@@ -301,7 +301,10 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
                     const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
                     const bool mine = key == v;
                     const uint64_t bv = __ballot(mine);
-                    if (mine) rank = __popcll(bv & __lanemask_lt());
+                    // lanes below this one with the same key
+                    const int below = (int)__builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(bv >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bv, 0u));
+                    if (mine) rank = below;
                     const float su = wave_total(mine ? U : 0.0f);
                     const float sl = wave_total(mine ? L : 0.0f);
                     if (lane == 0) {
