@@ -30,10 +30,11 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE (scaled by a plain copy of known size), recorded with a hash of
 # the kernel's sources: reported only while those sources are unchanged.
 PROFILED_TRAFFIC = {
-    "rs15": dict(bytes=52.317e6, sha="03a79afef7fb6d81", summary="profiles/expand_tiles_rs15.md"),
+    "rs15": dict(bytes=53.46e6, sha="2e834922e7f3b015", summary="profiles/expand_tiles_rs15.md"),
 }
+# the kernel and the host code that orders its tiles (the order decides L2 reuse)
 KERNEL_SOURCES = ("paper_1802_06215_amd/csrc/kernels.hip", "paper_1802_06215_amd/csrc/models.hpp",
-                  "paper_1802_06215_amd/csrc/internal.hpp")
+                  "paper_1802_06215_amd/csrc/internal.hpp", "paper_1802_06215_amd/csrc/runtime.cpp")
 
 
 def kernel_sha() -> str:
