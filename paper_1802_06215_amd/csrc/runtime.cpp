@@ -631,10 +631,15 @@ hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
     if (e != hipSuccess) return hip_fail(ctx, e, "descriptor copy");
     int32_t no_lds[kGroups] = {};
     Schedule sch[kGroups];
-    for (int g = 0; g < kGroups; ++g)
+    // a launch far smaller than the GPU (a search's leaf batch) is latency
+    // bound: wider workgroups finish each tile sooner
+    const bool few = sh.n_tiles < 8 * (int64_t)ctx->n_cu;
+    for (int g = 0; g < kGroups; ++g) {
         sch[g] = ctx->sched_fixed ? ctx->sched
                                   : class_default_schedule(plan.n_max[g], variant_max_threads(group_variant(g)),
-                                                           group_variant(g).mode);
+                                                           few ? -1 : group_variant(g).mode);
+        if (few) sch[g].xcd_remap = 0;
+    }
     e = launch_classes_forked(s.d_tasks, s.d_tiles, s.d_queue, plan, no_lds, sch, ctx->n_cu, hs, ctx->cls_stream,
                               s.fork, s.join);
     if (e != hipSuccess) return hip_fail(ctx, e, "expand launch");
