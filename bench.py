@@ -323,6 +323,21 @@ def surrogate_section(ctx, args):
     ce_one, ce_sur, cb_sur = np.asarray(ce_one), np.asarray(ce_sur), np.asarray(cb_sur)
     del descs, outs, keep, one, ref_sum
 
+    # the same tree, three frontier values: for each key, the root and the
+    # children it reaches are expanded (that fixes a two-level tree) and the
+    # depth-2 frontier is valued by single rollouts, by the mean of 32
+    # independent rollouts (the reference) and by the surrogate
+    same_tree = []
+    for key in range(1, 9):
+        root = ctx.sample_scenarios(m, W.rocksample_belief(desc), 500, 40 + key, 0)
+        same_tree.append(S.root_values_same_tree(ctx, m, desc["gamma"], root, 500, rcfg, key, net, 90))
+        log("same tree", key, same_tree[-1])
+    rel = lambda v, ref: abs(v - ref) / max(abs(ref), 1e-9)
+    st_sur = [rel(t_["surrogate"], t_["reference"]) for t_ in same_tree]
+    st_one = [rel(t_["rollout"], t_["reference"]) for t_ in same_tree]
+    st_abs_sur = [abs(t_["surrogate"] - t_["reference"]) for t_ in same_tree]
+    st_abs_one = [abs(t_["rollout"] - t_["reference"]) for t_ in same_tree]
+
     # search at equal budget
     runs = {}
     # each form under three random-number keys: the root value of equal
@@ -388,6 +403,21 @@ def surrogate_section(ctx, args):
                          child_l0_mae_surrogate=round(float(ce_sur.mean()), 5),
                          child_l0_p90_one_rollout=round(float(np.percentile(ce_one, 90)), 5),
                          child_l0_p90_surrogate=round(float(np.percentile(ce_sur, 90)), 5))),
+        same_tree=dict(trees=len(same_tree), depth1_nodes=[t_["depth1_nodes"] for t_ in same_tree],
+                       frontier_pairs=[t_["frontier_pairs"] for t_ in same_tree],
+                       reference_rollouts_per_pair=32,
+                       l_root_reference=[round(t_["reference"], 5) for t_ in same_tree],
+                       l_root_rollout=[round(t_["rollout"], 5) for t_ in same_tree],
+                       l_root_surrogate=[round(t_["surrogate"], 5) for t_ in same_tree],
+                       root_rel_err_surrogate_mean=round(float(np.mean(st_sur)), 5),
+                       root_rel_err_surrogate_max=round(float(np.max(st_sur)), 5),
+                       root_rel_err_one_rollout_mean=round(float(np.mean(st_one)), 5),
+                       root_rel_err_one_rollout_max=round(float(np.max(st_one)), 5),
+                       root_abs_err_surrogate_mean=round(float(np.mean(st_abs_sur)), 5),
+                       root_abs_err_one_rollout_mean=round(float(np.mean(st_abs_one)), 5),
+                       rel_err_of_mean_root_surrogate=round(
+                           rel(np.mean([t_["surrogate"] for t_ in same_tree]),
+                               np.mean([t_["reference"] for t_ in same_tree])), 5)),
         search=dict(threads=8, leaf_batch=8, budget_s=args.search_seconds, runs=runs,
                     summary=dict(keys=list(keys), rollouts_trials_per_s=round(tf_, 1),
                                  surrogate_trials_per_s=round(ts_, 1), trials_ratio=round(ts_ / tf_, 3),
