@@ -81,8 +81,11 @@ def parse():
                     help="training epochs of the surrogate comparison (rs15 only; 0 = skip)")
     ap.add_argument("--surrogate-targets", type=int, default=16,
                     help="rollouts averaged into each training target")
-    ap.add_argument("--surrogate-leaves", type=int, default=2048,
-                    help="training leaves of 100 scenarios each (x 20 actions = pairs / 2000)")
+    ap.add_argument("--surrogate-leaves", type=int, default=1024,
+                    help="synthetic training leaves of 100 scenarios each (x 20 actions = pairs / 2000)")
+    ap.add_argument("--surrogate-planner-seeds", type=int, default=6,
+                    help="planner trees (root from the start belief, 8 levels of up to 32 nodes) "
+                         "that add training pairs")
     return ap.parse_args()
 
 
@@ -245,20 +248,35 @@ def surrogate_section(ctx, args):
         return e0.elapsed_time(e1) * 1e-3 / reps
 
     # training set: expansions with full rollouts, per-pair outputs kept
-    specs = [(50000 + i, 100, 1 + (7 * i) % 89) for i in range(args.surrogate_leaves)]
-    descs, outs, keep = leafset(specs, True)
-    gen_s = timed(lambda: ctx.expand_leaf(descs), 1)
-    pairs = [S.leaf_pairs(ctx, m, o, d, 90) for o, d in outs]
-    X = torch.cat([p[0] for p in pairs])
-    # targets: mean of several rollouts per pair (the stepped states do not
-    # depend on the key; only the random rollout actions do)
-    acc = [torch.zeros_like(o.L[:, :o.n]) for o, _ in outs]
-    for r in range(args.surrogate_targets):
-        ctx.expand_leaf(reseed(keep, 700000 + r))
-        for a_, (o, _) in zip(acc, outs):
-            a_ += o.L[:, :o.n]
-    t = torch.cat([(a_ / args.surrogate_targets).reshape(-1) for a_ in acc])
-    del pairs, outs, descs, keep, acc
+    gen_s = 0.0
+    X = torch.empty((0, H.MLP_IN), dtype=torch.int16, device="cuda")
+    t = torch.empty(0, dtype=torch.float32, device="cuda")
+    if args.surrogate_leaves > 0:
+        specs = [(50000 + i, 100, 1 + (7 * i) % 89) for i in range(args.surrogate_leaves)]
+        descs, outs, keep = leafset(specs, True)
+        gen_s = timed(lambda: ctx.expand_leaf(descs), 1)
+        pairs = [S.leaf_pairs(ctx, m, o, d, 90) for o, d in outs]
+        X = torch.cat([p[0] for p in pairs])
+        # targets: mean of several rollouts per pair (the stepped states do not
+        # depend on the key; only the random rollout actions do)
+        acc = [torch.zeros_like(o.L[:, :o.n]) for o, _ in outs]
+        for r in range(args.surrogate_targets):
+            ctx.expand_leaf(reseed(keep, 700000 + r))
+            for a_, (o, _) in zip(acc, outs):
+                a_ += o.L[:, :o.n]
+        t = torch.cat([(a_ / args.surrogate_targets).reshape(-1) for a_ in acc])
+        del pairs, outs, descs, keep, acc
+    # and pairs from the planner's own trees: roots sampled from the start
+    # belief, expanded level by level (states at the depths a search reaches)
+    n_synth = int(X.shape[0])
+    t0 = time.perf_counter()
+    Xp, tp = S.planner_pairs(ctx, m, lambda sd: ctx.sample_scenarios(m, W.rocksample_belief(desc), 500, sd, 0),
+                             500, rcfg, range(100, 100 + args.surrogate_planner_seeds), levels=8,
+                             nodes_per_level=32, horizon=90, ref_keys=args.surrogate_targets)
+    torch.cuda.synchronize()
+    gen_s += time.perf_counter() - t0
+    X, t = torch.cat([X, Xp]), torch.cat([t, tp])
+    del Xp, tp
     net = Mlp(ctx, seed=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -378,7 +396,9 @@ def surrogate_section(ctx, args):
     return dict(
         config="RockSample 15x15, 15 rocks, uniform-random rollouts of depth 90; MLP 64-256-256-256-1 "
                "(BF16 MFMA, FP32 accumulate)",
-        train=dict(pairs=n_pairs, leaves=args.surrogate_leaves, rollouts_per_target=args.surrogate_targets,
+        train=dict(pairs=n_pairs, synthetic_pairs=n_synth, planner_pairs=n_pairs - n_synth,
+                   leaves=args.surrogate_leaves, planner_trees=args.surrogate_planner_seeds,
+                   rollouts_per_target=args.surrogate_targets,
                    data_gen_s=round(gen_s, 3), epochs=args.surrogate_epochs,
                    fit_s=round(train_s, 3), samples_per_s=round(samples / train_s, 1),
                    tflops=round(S.FLOPS_TRAIN * samples / train_s / 1e12, 2), losses=[round(h, 4) for h in hist]),
@@ -415,6 +435,14 @@ def surrogate_section(ctx, args):
                        root_rel_err_one_rollout_max=round(float(np.max(st_one)), 5),
                        root_abs_err_surrogate_mean=round(float(np.mean(st_abs_sur)), 5),
                        root_abs_err_one_rollout_mean=round(float(np.mean(st_abs_one)), 5),
+                       frontier_mean_reference=round(float(np.mean([t_["frontier_mean_reference"]
+                                                                     for t_ in same_tree])), 5),
+                       frontier_bias_surrogate=round(float(np.mean([t_["frontier_bias_surrogate"]
+                                                                    for t_ in same_tree])), 5),
+                       frontier_mae_surrogate=round(float(np.mean([t_["frontier_mae_surrogate"]
+                                                                   for t_ in same_tree])), 5),
+                       frontier_mae_one_rollout=round(float(np.mean([t_["frontier_mae_rollout"]
+                                                                     for t_ in same_tree])), 5),
                        rel_err_of_mean_root_surrogate=round(
                            rel(np.mean([t_["surrogate"] for t_ in same_tree]),
                                np.mean([t_["reference"] for t_ in same_tree])), 5)),

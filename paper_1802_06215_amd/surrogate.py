@@ -138,7 +138,69 @@ def root_values_same_tree(ctx: "H.Context", model: "H.Model", gamma: float, root
             tree.backup(first + i)
         return tree.bounds(0)[1]
 
-    return dict(rollout=root_value(v_one.cpu().numpy().astype(np.float64)),
-                reference=root_value(v_ref.cpu().numpy()),
-                surrogate=root_value(v_sur.cpu().numpy().astype(np.float64)),
-                depth1_nodes=len(nodes), frontier_pairs=int(fids.numel()))
+    ref = v_ref.cpu().numpy()
+    sur = v_sur.cpu().numpy().astype(np.float64)
+    one = v_one.cpu().numpy().astype(np.float64)
+    return dict(rollout=root_value(one), reference=root_value(ref), surrogate=root_value(sur),
+                depth1_nodes=len(nodes), frontier_pairs=int(fids.numel()),
+                frontier_mean_reference=float(ref.mean()), frontier_bias_surrogate=float((sur - ref).mean()),
+                frontier_mae_surrogate=float(np.abs(sur - ref).mean()),
+                frontier_mae_rollout=float(np.abs(one - ref).mean()))
+
+
+def planner_pairs(ctx: "H.Context", model: "H.Model", root_states, K: int, cfg: "H.RolloutCfg",
+                  seeds, levels: int, nodes_per_level: int, horizon: int, ref_keys: int,
+                  ref_seed: int = 1 << 21):
+    """Training pairs from the planner's own trees: for each seed, a root of
+    K scenarios (`root_states(seed)`) is expanded, then up to
+    `nodes_per_level` of the children reached at each depth (drawn from the
+    seed) are expanded in turn, down to `levels` levels; every (action,
+    scenario) pair of every expanded node contributes its stepped state at
+    its depth, with the mean of `ref_keys` independent default-policy
+    rollouts from it as the target.  Returns (features [N, 64] BF16 bits,
+    targets [N] f32)."""
+    A = model.n_actions
+    feats, targets = [], []
+    for seed in seeds:
+        gen = np.random.default_rng(np.random.SeedSequence([0x504C4E, seed]))
+        root = root_states(seed)
+        dev = root[next(iter(root))].device
+        ids = torch.arange(K, dtype=torch.int32, device=dev)
+        level = [(root, ids, torch.arange(K, dtype=torch.int32, device=dev), 0, -1)]
+        keep = []
+        for _ in range(levels):
+            outs = [H.LeafBuffers(model, int(idx.numel()), per_pair=True) for _, _, idx, _, _ in level]
+            ctx.expand_leaf([H.make_leaf(model, par, pid, idx, d, la, o, seed, 0, cfg)
+                             for (par, pid, idx, d, la), o in zip(level, outs)])
+            torch.cuda.synchronize()
+            front = _cat_states([{k: v[..., :A * o.n] for k, v in o.sprime.items()} for o in outs])
+            fids = torch.cat([o.ids[:o.n].repeat(A) for o in outs])
+            depths = torch.cat([torch.full((A * o.n,), d + 1, dtype=torch.int32, device=dev)
+                                for (_, _, _, d, _), o in zip(level, outs)])
+            acc = torch.zeros(fids.numel(), dtype=torch.float64, device=dev)
+            for r in range(ref_keys):
+                _, L, _ = ctx.rollout_bounds(model, cfg, front, fids, depths, ref_seed + 1000 * seed + r, 0)
+                acc += L.double()
+            feats.append(H.features(ctx, model, front, depths, horizon))
+            targets.append((acc / ref_keys).float())
+            # next level: children with at least one scenario, a random subset
+            cands = []
+            for (_, _, _, d, _), o in zip(level, outs):
+                nc, off, cn = o.n_children.cpu().numpy(), o.child_off.cpu().numpy(), o.child_n.cpu().numpy()
+                for a in range(A):
+                    for c in range(int(nc[a])):
+                        if cn[a, c] > 0:
+                            cands.append((o, a, int(off[a, c]), int(cn[a, c]), d + 1))
+            if not cands:
+                break
+            pick = gen.choice(len(cands), size=min(nodes_per_level, len(cands)), replace=False)
+            level = []
+            for i in sorted(pick):
+                o, a, off, cn, d = cands[i]
+                states = {k: v[..., :o.n].contiguous() for k, v in o.states.items()}
+                level.append((states, o.ids[:o.n], o.perm[a, off:off + cn].contiguous(), d, a))
+            keep.append(outs)
+    if not feats:
+        return (torch.empty((0, H.MLP_IN), dtype=torch.int16, device="cuda"),
+                torch.empty(0, dtype=torch.float32, device="cuda"))
+    return torch.cat(feats), torch.cat(targets)
