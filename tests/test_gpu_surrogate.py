@@ -262,3 +262,73 @@ def test_search_surrogate_judge_and_fallback(ctx, net, threads, batch):
     print(r["judged_leaves"], r["judge_rel_err"], r["surrogate_off"], flush=True)
     assert r["judged_leaves"] >= 8
     assert r["surrogate_off"] == (1 if r["judge_rel_err"] > 1e-12 else 0)
+
+
+def _oracle_two_level_root(desc, ocfg, root_np, K, key):
+    """Root lower bound of the two-level tree, every node expanded by the
+    oracle (FP64) and backed up by the oracle's Eq. 4."""
+    ids = np.arange(K, dtype=np.uint32)
+    res0 = oracle.expand_leaf(desc, ocfg, root_np, ids, np.arange(K, dtype=np.int32), 0, -1, key, 0)
+    root = oracle.Node(None, K, 0.0, 0.0)
+    oracle.attach_children(desc, root, res0)
+    for a in range(desc["n_actions"]):
+        for c in range(int(res0["n_children"][a])):
+            off, n = int(res0["child_off"][a, c]), int(res0["child_n"][a, c])
+            res = oracle.expand_leaf(desc, ocfg, root_np, ids, res0["perm"][a, off:off + n], 1, a, key, 0)
+            node = root.actions[a][1][c]
+            oracle.attach_children(desc, node, res)
+            oracle.backup(node, desc["gamma"])
+    return root.l
+
+
+def test_same_tree_root_values_match_oracle(ctx, net):
+    """The plain-rollout root value of the two-level comparison tree equals
+    the oracle's tree built from its own expansions (1e-5 relative); the
+    reference and surrogate variants are finite; the frontier holds every
+    (action, scenario) pair of every depth-1 node."""
+    from paper_1802_06215_amd import hdx as H, surrogate as S
+    desc = W.rocksample_model(7, 8, 1)
+    m = ctx.upload_model(desc)
+    K = 48
+    cfg = H.rollout_cfg(H.POLICY_RANDOM, 1 << 30, 30)
+    for key in (1, 2):
+        root = ctx.sample_scenarios(m, W.rocksample_belief(desc), K, 10 + key, 0)
+        torch.cuda.synchronize()
+        root_np = dict(w=root["w"].cpu().numpy().astype(np.int32))
+        got = S.root_values_same_tree(ctx, m, desc["gamma"], root, K, cfg, key, net, 30, ref_keys=2)
+        want = _oracle_two_level_root(desc, oracle.cfg(2, 1 << 30, 30), root_np, K, key)
+        print("key", key, got, want, flush=True)
+        assert abs(got["rollout"] - want) <= 1e-5 * max(1.0, abs(want)), (got["rollout"], want)
+        assert np.isfinite(got["reference"]) and np.isfinite(got["surrogate"])
+        # every depth-1 node holds a share of the K scenarios per action
+        assert got["frontier_pairs"] == desc["n_actions"] * desc["n_actions"] * K
+
+
+def test_planner_pairs_first_level(ctx):
+    """Training pairs from planner trees: the first level is the root's
+    expansion, rows a*K + k in order; its targets are the mean of the
+    rollout values under the reference keys, recomputed here from an
+    independent expansion of the same root."""
+    from paper_1802_06215_amd import hdx as H, surrogate as S
+    desc = W.rocksample_model(7, 8, 1)
+    m = ctx.upload_model(desc)
+    K, A, R = 64, desc["n_actions"], 3
+    cfg = H.rollout_cfg(H.POLICY_RANDOM, 1 << 30, 30)
+    root_of = lambda sd: ctx.sample_scenarios(m, W.rocksample_belief(desc), K, sd, 0)
+    X, t = S.planner_pairs(ctx, m, root_of, K, cfg, [5], levels=3, nodes_per_level=4, horizon=30, ref_keys=R,
+                           ref_seed=777)
+    assert X.shape[1] == 64 and X.shape[0] == t.shape[0] and X.shape[0] > A * K
+    assert torch.isfinite(t).all()
+    root = root_of(5)
+    out = H.LeafBuffers(m, K, per_pair=True)
+    ids = torch.arange(K, dtype=torch.int32, device="cuda")
+    ctx.expand_leaf([H.make_leaf(m, root, ids, ids.clone(), 0, -1, out, 5, 0, cfg)])
+    sp = {k: v[..., :A * K].contiguous() for k, v in out.sprime.items()}
+    fids = out.ids[:K].repeat(A)
+    depths = torch.ones(A * K, dtype=torch.int32, device="cuda")
+    acc = torch.zeros(A * K, dtype=torch.float64, device="cuda")
+    for r in range(R):
+        _, L, _ = ctx.rollout_bounds(m, cfg, sp, fids, depths, 777 + 1000 * 5 + r, 0)
+        acc += L.double()
+    assert torch.equal(t[:A * K], (acc / R).float())
+    assert torch.equal(X[:A * K], H.features(ctx, m, sp, depths, 30))
