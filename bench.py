@@ -503,6 +503,66 @@ def cpu_baseline(items, seconds):
                        "leaves in %.1f s" % (len(items), passes, cores, dtm, done, dt1))
 
 
+def despot_analogue(desc, seconds, K=500, seed=3, max_depth=90, xi=0.95):
+    """The paper's DESPOT baseline as it stands here: one host thread, trials
+    by Eq. 5 (the action of largest upper bound) and Eq. 7 (the child of
+    largest weighted excess uncertainty), every expansion and Eq. 4 backup
+    done by the oracle (FP64 values), default move-east rollouts.  Returns
+    the tree size it builds within `seconds` (the paper's speedup metric
+    counts tree size within the planning time)."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+
+    rc = oracle.cfg(0, 1 << 30, max_depth)
+    gamma = desc["gamma"]
+    root_states = oracle.sample_scenarios(desc, W.rocksample_belief(desc), K, seed, 0)
+    ids = np.arange(K, dtype=np.uint32)
+    U, L, _ = oracle.rollout_bounds(desc, rc, root_states, ids, np.zeros(K, np.int32), seed, 0)
+    root = oracle.Node(None, K, U.mean(), L.mean())
+    pending = {id(root): (root_states, ids, np.arange(K, dtype=np.int32), 0, -1)}
+    nodes, trials, expansions, steps = 1, 0, 0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        gap0 = root.u - root.l
+        if gap0 <= 0.0:
+            break
+        b, depth = root, 0
+        while b is not None and b.actions is not None:
+            best_a, best_v = 0, -np.inf
+            for a, (r, kids) in enumerate(b.actions):
+                v = r + gamma * sum(k.n / b.n * k.u for k in kids)
+                if v > best_v:
+                    best_a, best_v = a, v
+            best, best_e = None, -np.inf
+            for k in b.actions[best_a][1]:
+                e = (k.u - k.l) - k.n / K * xi * gap0
+                if e > best_e:
+                    best, best_e = k, e
+            b = best if best is not None and best_e > 0.0 else None
+            depth += 1
+        trials += 1
+        if b is None:  # no positive excess uncertainty below the root: one thread stays here
+            break
+        if depth >= max_depth or b.n == 0:
+            continue
+        par, pids, idx, d, la = pending.pop(id(b))
+        res = oracle.expand_leaf(desc, rc, par, pids, idx, d, la, seed, 0)
+        expansions += 1
+        steps += int(res["expand_steps"]) + int(res["rollout_steps"])
+        oracle.attach_children(desc, b, res)
+        for a, (_, kids) in enumerate(b.actions):
+            for c, k in enumerate(kids):
+                off, cnt = int(res["child_off"][a, c]), int(res["child_n"][a, c])
+                pending[id(k)] = (res["states"], res["ids"], res["perm"][a, off:off + cnt], d + 1, a)
+                nodes += 1
+        oracle.backup(b, gamma)
+    dt = time.perf_counter() - t0
+    return dict(nodes=nodes, trials=trials, expansions=expansions, elapsed_s=round(dt, 3),
+                scenario_steps_per_s=round(steps / dt, 1), l_root=round(root.l, 5), u_root=round(root.u, 5))
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -594,10 +654,13 @@ def main():
         desc = items[0][0]
         m = wl["models"][id(desc)]
         search = []
-        for threads, nb in ((4, 0), (8, 0), (8, 8), (16, 16)):
+        # one thread with plain DESPOT choices (c_a = c_o = 0) is the
+        # GPU-DESPOT analogue; several threads with Eq. 8-9 the HyP-DESPOT one
+        for threads, nb in ((1, 0), (4, 0), (8, 0), (8, 8), (16, 16)):
+            extra = dict(c_a=0.0, c_o=0.0) if threads == 1 else {}
             res = ctx.search(m, W.rocksample_belief(desc), K=500, n_threads=threads, max_depth=90,
                              batch_leaves=nb, time_budget_s=args.search_seconds,
-                             rollout=H.rollout_cfg(0, 1 << 30, 90), seed=3)
+                             rollout=H.rollout_cfg(0, 1 << 30, 90), seed=3, **extra)
             search.append(dict(threads=threads, leaf_batcher=nb > 0,
                                trials_per_s=round(res["trials"] / res["elapsed_s"], 1),
                                expanding_trials_per_s=round(res["expansions"] / res["elapsed_s"], 1),
@@ -618,6 +681,17 @@ def main():
         log("cpu baseline (oracle)...")
         cpu = cpu_baseline(items, args.cpu_seconds)
         cpu["value"] = round(cpu["value"], 1)
+        if search:
+            # the paper's metric: tree size built within the planning time,
+            # relative to DESPOT (here its one-thread host analogue)
+            desp = despot_analogue(items[0][0], args.search_seconds)
+            log("despot analogue", desp)
+            best = max(search, key=lambda r: r["nodes"])
+            one = next(r for r in search if r["threads"] == 1)
+            cpu["despot_analogue"] = dict(desp, planning_s=args.search_seconds,
+                                          speedup_gpu_despot=round(one["nodes"] / desp["nodes"], 1),
+                                          speedup_hyp_despot=round(best["nodes"] / desp["nodes"], 1),
+                                          hyp_config=dict(threads=best["threads"], leaf_batcher=best["leaf_batcher"]))
 
     names = dict(rs15="RS15 leaf expansion: RockSample 15x15, 15 rocks, |A|=20, K=500, horizon 90, move-east "
                       "rollouts; %d synthetic leaves (n in {500,250,125,63,32}, depth 1..30)",
