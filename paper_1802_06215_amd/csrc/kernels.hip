@@ -319,8 +319,9 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
                 if (valid) child[k] = (int32_t)(key | ((uint32_t)rank << 16));
             }
         }
-        // mean step reward: sum of this 64-scenario chunk (lanes past n add 0)
-        const float r_chunk = wave_total(r);
+        // mean step reward: sum of this 64-scenario chunk (lanes past n add 0;
+        // a chunk without a reward sums to +0 without the reduction)
+        const float r_chunk = __ballot(r != 0.0f) ? wave_total(r) : 0.0f;
         if (lane == 0 && chunk_live) chunk_r[(base >> 6) + wid] = r_chunk;
     }
 #pragma unroll

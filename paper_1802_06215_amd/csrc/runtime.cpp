@@ -499,6 +499,8 @@ Schedule hdx::class_default_schedule(int32_t n_max, int32_t max_threads, int32_t
     s.persistent = 0;
     s.xcd_remap = mode < 0 ? 1 : 0;
     if (mode == 0) s.threads = 64;
+    // latency form: one scenario per lane where the model's width allows
+    if (mode == -2) s.threads = std::min(std::max(64, pow2_at_least(std::max(n_max, 1))), max_threads);
     return s;
 }
 
@@ -602,7 +604,7 @@ hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
         pack.n_leaves = n_leaves;
         pack.n_max = v0.n_max;
         const Schedule sch =
-            ctx->sched_fixed ? ctx->sched : class_default_schedule(v0.n_max, variant_max_threads(v0));
+            ctx->sched_fixed ? ctx->sched : class_default_schedule(v0.n_max, variant_max_threads(v0), -2);
         pack.xcd_remap = sch.xcd_remap;
         hipError_t e = launch_expand_args(pack, v0, sch, (hipStream_t)stream);
         return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "expand launch");
@@ -637,7 +639,7 @@ hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
     for (int g = 0; g < kGroups; ++g) {
         sch[g] = ctx->sched_fixed ? ctx->sched
                                   : class_default_schedule(plan.n_max[g], variant_max_threads(group_variant(g)),
-                                                           few ? -1 : group_variant(g).mode);
+                                                           few ? -2 : group_variant(g).mode);
         if (few) sch[g].xcd_remap = 0;
     }
     e = launch_classes_forked(s.d_tasks, s.d_tiles, s.d_queue, plan, no_lds, sch, ctx->n_cu, hs, ctx->cls_stream,
