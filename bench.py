@@ -567,9 +567,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: the leaf-expansion path is measured on one MI355X; "
-              "multi-GPU runs are not part of this build (got --gpus %d, WORLD_SIZE %d)" % (args.gpus, world),
-              file=sys.stderr)
+        print("bench.py runs on one GPU only: the leaf-expansion path is measured on one MI355X and has no "
+              "multi-GPU form (got --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
