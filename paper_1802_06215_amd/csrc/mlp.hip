@@ -110,25 +110,26 @@ __global__ __launch_bounds__(256) void gemm_bf16(int M, int N, int K, const uint
 }
 
 // ---- fused forward --------------------------------------------------------
-// One workgroup of eight wavefronts takes kFR = 128 rows.  The layer input
-// (X, then H1, H2) sits in LDS; wavefront w computes rows [64 (w / 4), +64)
-// x columns [64 (w % 4), +64) with 16x16x32 BF16 MFMAs, its weight
-// fragments read straight from the transposed BF16 weights.  The MFMA is
+// One workgroup of four wavefronts takes kFR = 128 rows.  The layer input
+// (X, then H1, H2) sits in LDS; wavefront w computes all 128 rows x columns
+// [64 w, +64) with 16x16x32 BF16 MFMAs (8 x 4 accumulator tiles), its weight
+// fragments read straight from the transposed BF16 weights, each fragment
+// feeding eight row tiles.  The MFMA is
 // fed (weights, activations), i.e. it produces the transposed tile, so a
 // lane ends up holding four consecutive output columns of one row: the
 // epilogue (bias, ReLU, BF16) writes them as one 8-byte LDS store.  The
 // output layer sums each row's 256 products over a lane's 16 columns, the
 // four lanes of the row, then the four column wavefronts, in a fixed order,
 // so a row's value does not depend on the other rows.
-constexpr int kFR = 128, kHP = kMlpHidden + 8, kFwdThreads = 512;
+constexpr int kFR = 128, kHP = kMlpHidden + 8, kFwdThreads = 256, kMI = kFR / 16;
 
-// acc[i][j][r] = output (row rb + 16 i + q, column nb + 16 j + 4 g + r)
+// acc[i][j][r] = output (row 16 i + q, column nb + 16 j + 4 g + r)
 template <int K>
-__device__ __forceinline__ void fused_layer(const uint16_t (*Hs)[kHP], const uint16_t *__restrict__ wt, int rb,
-                                            int nb, int lane, f32x4 (&acc)[4][4]) {
+__device__ __forceinline__ void fused_layer(const uint16_t (*Hs)[kHP], const uint16_t *__restrict__ wt, int nb,
+                                            int lane, f32x4 (&acc)[kMI][4]) {
     const int g = lane >> 4, q = lane & 15;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < kMI; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const uint16_t *wrow = wt + (size_t)(nb + q) * K + g * 8;
@@ -138,37 +139,38 @@ __device__ __forceinline__ void fused_layer(const uint16_t (*Hs)[kHP], const uin
 #pragma unroll
         for (int j = 0; j < 4; ++j) b[j] = *(const bf16x8 *)(wrow + (size_t)j * 16 * K + k0);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const bf16x8 a = *(const bf16x8 *)&Hs[rb + i * 16 + q][k0 + g * 8];
+        for (int i = 0; i < kMI; ++i) {
+            const bf16x8 a = *(const bf16x8 *)&Hs[i * 16 + q][k0 + g * 8];
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], a, acc[i][j], 0, 0, 0);
         }
     }
 }
 
-// BF16 of a finite or infinite non-negative value (post-ReLU), nearest even
-__device__ __forceinline__ uint32_t f2bf_pos(float f) {
-    const uint32_t u = __float_as_uint(f);
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+// Two FP32 values rounded to BF16 (nearest even) and packed, lo in bits
+// 0-15: one v_cvt_pk_bf16_f32 on gfx950.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+    const f32x2_t v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
 }
 
 // h = bf16(relu(acc + bias)) into LDS (and, when STORE, to Hout)
 template <bool STORE>
-__device__ __forceinline__ void fused_store(uint16_t (*Hs)[kHP], const f32x4 (&acc)[4][4], const float *__restrict__ bias,
-                                            int rb, int nb, int lane, uint16_t *Hout, int64_t r0, int64_t n) {
+__device__ __forceinline__ void fused_store(uint16_t (*Hs)[kHP], const f32x4 (&acc)[kMI][4],
+                                            const float *__restrict__ bias, int nb, int lane, uint16_t *Hout,
+                                            int64_t r0, int64_t n) {
     const int g = lane >> 4, q = lane & 15;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int col = nb + j * 16 + g * 4;
         const float4 bv = *(const float4 *)(bias + col);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = rb + i * 16 + q;
-            const uint32_t h0 = f2bf_pos(fmaxf(acc[i][j][0] + bv.x, 0.f));
-            const uint32_t h1 = f2bf_pos(fmaxf(acc[i][j][1] + bv.y, 0.f));
-            const uint32_t h2 = f2bf_pos(fmaxf(acc[i][j][2] + bv.z, 0.f));
-            const uint32_t h3 = f2bf_pos(fmaxf(acc[i][j][3] + bv.w, 0.f));
-            const uint2 v = make_uint2(h0 | (h1 << 16), h2 | (h3 << 16));
+        for (int i = 0; i < kMI; ++i) {
+            const int row = i * 16 + q;
+            const uint2 v = make_uint2(pack_bf16(fmaxf(acc[i][j][0] + bv.x, 0.f), fmaxf(acc[i][j][1] + bv.y, 0.f)),
+                                       pack_bf16(fmaxf(acc[i][j][2] + bv.z, 0.f), fmaxf(acc[i][j][3] + bv.w, 0.f)));
             *(uint2 *)&Hs[row][col] = v;
             if (STORE && r0 + row < n) *(uint2 *)(Hout + (r0 + row) * kMlpHidden + col) = v;
         }
@@ -177,7 +179,7 @@ __device__ __forceinline__ void fused_store(uint16_t (*Hs)[kHP], const f32x4 (&a
 
 // STORE: also write H1..H3 (training); the inference form writes only y.
 template <bool STORE>
-__global__ __launch_bounds__(kFwdThreads, 4) void mlp_fused_fwd(const uint16_t *__restrict__ X, int64_t n,
+__global__ __launch_bounds__(kFwdThreads, 2) void mlp_fused_fwd(const uint16_t *__restrict__ X, int64_t n,
                                                              const MlpDev P, float *__restrict__ y, uint16_t *H1,
                                                              uint16_t *H2, uint16_t *H3) {
     __shared__ __align__(16) uint16_t Hs[kFR][kHP];
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(kFwdThreads, 4) void mlp_fused_fwd(const uint16_t *
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, q = lane & 15;
     const int64_t r0 = (int64_t)blockIdx.x * kFR;
-    const int rb = (wave >> 2) * 64, cw = wave & 3, nb = cw * 64;
+    const int cw = wave, nb = cw * 64;
     constexpr int kV = kMlpIn / 8;  // uint4 per input row
     for (int i = tid; i < kFR * kV; i += kFwdThreads) {
         const int r = i / kV, c = (i % kV) * 8;
@@ -194,18 +196,20 @@ __global__ __launch_bounds__(kFwdThreads, 4) void mlp_fused_fwd(const uint16_t *
         *(uint4 *)&Hs[r][c] = v;
     }
     __syncthreads();
-    f32x4 acc[4][4];
-    fused_layer<kMlpIn>(Hs, P.w1t, rb, nb, lane, acc);
+    f32x4 acc[kMI][4];
+    fused_layer<kMlpIn>(Hs, P.w1t, nb, lane, acc);
     __syncthreads();
-    fused_store<STORE>(Hs, acc, P.b1, rb, nb, lane, H1, r0, n);
+    fused_store<STORE>(Hs, acc, P.b1, nb, lane, H1, r0, n);
     __syncthreads();
-    fused_layer<kMlpHidden>(Hs, P.w2t, rb, nb, lane, acc);
+    fused_layer<kMlpHidden>(Hs, P.w2t, nb, lane, acc);
     __syncthreads();
-    fused_store<STORE>(Hs, acc, P.b2, rb, nb, lane, H2, r0, n);
+    fused_store<STORE>(Hs, acc, P.b2, nb, lane, H2, r0, n);
     __syncthreads();
-    fused_layer<kMlpHidden>(Hs, P.w3t, rb, nb, lane, acc);
+    fused_layer<kMlpHidden>(Hs, P.w3t, nb, lane, acc);
     // output layer: y = bf16(h3) . bf16(w4) + b4
-    float rowsum[4] = {0.f, 0.f, 0.f, 0.f};
+    float rowsum[kMI];
+#pragma unroll
+    for (int i = 0; i < kMI; ++i) rowsum[i] = 0.f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int col = nb + j * 16 + g * 4;
@@ -214,28 +218,25 @@ __global__ __launch_bounds__(kFwdThreads, 4) void mlp_fused_fwd(const uint16_t *
         const float w0 = __uint_as_float(wv.x << 16), w1 = __uint_as_float(wv.x & 0xffff0000u);
         const float w2 = __uint_as_float(wv.y << 16), w3 = __uint_as_float(wv.y & 0xffff0000u);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = rb + i * 16 + q;
-            const uint32_t h0 = f2bf_pos(fmaxf(acc[i][j][0] + bv.x, 0.f));
-            const uint32_t h1 = f2bf_pos(fmaxf(acc[i][j][1] + bv.y, 0.f));
-            const uint32_t h2 = f2bf_pos(fmaxf(acc[i][j][2] + bv.z, 0.f));
-            const uint32_t h3 = f2bf_pos(fmaxf(acc[i][j][3] + bv.w, 0.f));
-            if (STORE && r0 + row < n)
-                *(uint2 *)(H3 + (r0 + row) * kMlpHidden + col) = make_uint2(h0 | (h1 << 16), h2 | (h3 << 16));
+        for (int i = 0; i < kMI; ++i) {
+            const int row = i * 16 + q;
+            const uint32_t h01 = pack_bf16(fmaxf(acc[i][j][0] + bv.x, 0.f), fmaxf(acc[i][j][1] + bv.y, 0.f));
+            const uint32_t h23 = pack_bf16(fmaxf(acc[i][j][2] + bv.z, 0.f), fmaxf(acc[i][j][3] + bv.w, 0.f));
+            if (STORE && r0 + row < n) *(uint2 *)(H3 + (r0 + row) * kMlpHidden + col) = make_uint2(h01, h23);
             float s = rowsum[i];
-            s += __uint_as_float(h0 << 16) * w0;
-            s += __uint_as_float(h1 << 16) * w1;
-            s += __uint_as_float(h2 << 16) * w2;
-            s += __uint_as_float(h3 << 16) * w3;
+            s += __uint_as_float(h01 << 16) * w0;
+            s += __uint_as_float(h01 & 0xffff0000u) * w1;
+            s += __uint_as_float(h23 << 16) * w2;
+            s += __uint_as_float(h23 & 0xffff0000u) * w3;
             rowsum[i] = s;
         }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < kMI; ++i) {
         float s = rowsum[i];
         s += __shfl_xor(s, 16, 64);
         s += __shfl_xor(s, 32, 64);
-        if (g == 0) yp[cw][rb + i * 16 + q] = s;
+        if (g == 0) yp[cw][i * 16 + q] = s;
     }
     __syncthreads();
     if (tid < kFR && r0 + tid < n) y[r0 + tid] = (((yp[0][tid] + yp[1][tid]) + yp[2][tid]) + yp[3][tid]) + P.b4[0];
