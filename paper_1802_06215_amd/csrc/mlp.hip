@@ -581,24 +581,38 @@ __global__ void sum_parts(const float *part, int n, float *out) {
 namespace {
 // Surrogate lower bounds of the children of pack entry blockIdx.z: for
 // action a (blockIdx.y) and child c, l0 = mean of the surrogate values of
-// the child's scenarios, summed in grouped order; per-scenario values
-// copied out on request.
-__global__ void surrogate_reduce(const SurPack P) {
+// the child's scenarios; per-scenario values copied out on request.  With
+// few children (RockSample: at most three) the wavefront takes one child at
+// a time, lane l summing the child's grouped positions l, l + 64, ... in
+// order and a fixed butterfly adding the lanes; with many small children
+// (hashed observations) each lane sums one child in grouped order.
+__global__ __launch_bounds__(64) void surrogate_reduce(const SurPack P) {
     const SurArgs &A = P.a[blockIdx.z];
     const int a = blockIdx.y;
     if (a >= A.n_actions) return;
-    const int n = A.n;
+    const int n = A.n, lane = threadIdx.x;
     const float *v = A.values + (int64_t)a * n;
-    const int nch = A.n_children[a];
+    const int nch = min(A.n_children[a], A.cap);
     const int32_t *perm = A.perm + (int64_t)a * n;
-    for (int c = threadIdx.x; c < nch && c < A.cap; c += blockDim.x) {
-        const int off = A.child_off[a * A.cap + c], cnt = A.child_n[a * A.cap + c];
-        float sum = 0.f;
-        for (int i = 0; i < cnt; ++i) sum = sum + v[perm[off + i]];
-        A.child_l0[a * A.cap + c] = sum / (float)cnt;
+    if (nch <= 16) {
+        for (int c = 0; c < nch; ++c) {
+            const int off = A.child_off[a * A.cap + c], cnt = A.child_n[a * A.cap + c];
+            float sum = 0.f;
+            for (int i = lane; i < cnt; i += 64) sum = sum + v[perm[off + i]];
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) sum = sum + __shfl_xor(sum, d, 64);
+            if (lane == 0) A.child_l0[a * A.cap + c] = sum / (float)cnt;
+        }
+    } else {
+        for (int c = lane; c < nch; c += 64) {
+            const int off = A.child_off[a * A.cap + c], cnt = A.child_n[a * A.cap + c];
+            float sum = 0.f;
+            for (int i = 0; i < cnt; ++i) sum = sum + v[perm[off + i]];
+            A.child_l0[a * A.cap + c] = sum / (float)cnt;
+        }
     }
     if (A.L_out)
-        for (int k = threadIdx.x; k < n; k += blockDim.x) A.L_out[(int64_t)a * n + k] = v[k];
+        for (int k = lane; k < n; k += 64) A.L_out[(int64_t)a * n + k] = v[k];
 }
 }  // namespace
 
