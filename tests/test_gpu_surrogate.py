@@ -63,7 +63,7 @@ def run_surrogate(ctx, net, m, lf, seed, step, hcfg):
     leaf, out, keep = gpu_leaf_desc(m, parent, pids, lf["idx"], lf["depth"], lf["last_action"], seed, step, hcfg)
     ctx.expand_leaf_surrogate([leaf], net, HORIZON)
     torch.cuda.synchronize()
-    return collect(m, out)
+    return collect(m, out), out
 
 
 def check(ctx, net, desc, lf, seed, step, cfgs):
@@ -71,7 +71,7 @@ def check(ctx, net, desc, lf, seed, step, cfgs):
     m = ctx.upload_model(desc)
     n = len(lf["idx"])
     print("surrogate leaf: kind=%d n=%d depth=%d seed=%d" % (desc["kind"], n, lf["depth"], seed), flush=True)
-    gpu = run_surrogate(ctx, net, m, lf, seed, step, hcfg)
+    gpu, out = run_surrogate(ctx, net, m, lf, seed, step, hcfg)
     want = oracle.expand_leaf(desc, ocfg, oracle.parent_states(desc, lf), np.asarray(lf["ids"], np.uint32),
                               lf["idx"], lf["depth"], lf["last_action"], seed, step, per_pair=True)
     A = desc["n_actions"]
@@ -83,6 +83,14 @@ def check(ctx, net, desc, lf, seed, step, cfgs):
     assert np.array_equal(gpu["z"], want["z"])
     assert int(gpu["steps"][:, 0].sum()) == want["expand_steps"]
     assert int(gpu["steps"][:, 1].sum()) == 0
+    if n:
+        # the forward that forms features from the states equals the features
+        # kernel followed by the forward, bit for bit
+        from paper_1802_06215_amd import hdx as H
+        sp = {k: v[..., :A * n].contiguous() for k, v in out.sprime.items()}
+        depths = torch.full((A * n,), lf["depth"] + 1, dtype=torch.int32, device="cuda")
+        y = net.forward(H.features(ctx, m, sp, depths, HORIZON))
+        assert np.array_equal(bits(gpu["L"].reshape(-1)), bits(y.cpu().numpy()))
     vals = reference_values(desc, net, want["sprime"], lf["depth"])
     scale = (np.abs(vals).mean() if n else 0.0) + 1e-3
     err = np.max(np.abs(gpu["L"] - vals)) if n else 0.0
@@ -136,7 +144,7 @@ def test_surrogate_batch_matches_single_calls(ctx, net):
         gen = W.rocksample_leaf if desc["kind"] == W.ROCKSAMPLE else W.pednav_leaf
         lf = gen(desc, 500, n, 10 + i, p_term=0.05)
         hcfg = H.rollout_cfg(0, 1 << 30, HORIZON)
-        singles.append(run_surrogate(ctx, net, m, lf, 10 + i, 3, hcfg))
+        singles.append(run_surrogate(ctx, net, m, lf, 10 + i, 3, hcfg)[0])
         parent = to_dev(oracle.parent_states(desc, lf))
         pids = ids_dev(lf["ids"])
         leaf, out, k = gpu_leaf_desc(m, parent, pids, lf["idx"], lf["depth"], lf["last_action"], 10 + i, 3, hcfg)
