@@ -7,15 +7,20 @@
 // k = tid, tid + T, ...: it gathers the parent state (struct-of-arrays,
 // coalesced along k), applies the last action, steps the tile's action,
 // evaluates the upper-bound heuristic and runs the default-policy rollout in
-// registers.  Observations are then grouped in LDS: an open-addressing hash
-// collects the distinct observations, which are sorted (one wavefront
-// bitonic network, or an LDS bitonic network past 64 keys) to give the
-// children their canonical order; scenario positions inside each child
-// come from wavefront ballots per 64-scenario chunk and a prefix over
-// chunks (a segmented sort of the scenarios by child, stable in scenario
-// order).  Per-child sums of U and L are wavefront segmented scans (shuffle
-// based) over 64-aligned chunks of the grouped order, then chunk partials
-// in order, so the floating-point order depends only on the data, never on
+// registers.  Then the scenarios are grouped by observation, two ways:
+//  - observation alphabets below 32 keys (RockSample): in registers, per
+//    64-scenario chunk one ballot per key present gives counts and ranks
+//    and DPP row reductions the key's U and L sums; one wavefront turns the
+//    per-chunk tables into children (ascending key), offsets and means,
+//    chunk partials added in chunk order;
+//  - hashed observations (driving): an open-addressing LDS hash collects
+//    the distinct observations, which are sorted (one wavefront bitonic
+//    network, or an LDS bitonic network past 64 keys); scenario positions
+//    inside each child come from wavefront ballots per 64-scenario chunk
+//    and a prefix over chunks, and the per-child sums of U and L from
+//    segmented wavefront scans over 64-aligned chunks of the grouped order,
+//    chunk partials added in order.
+// Either way the floating-point order depends only on the data, never on
 // the workgroup size or the schedule.
 #include "models.hpp"
 
@@ -206,7 +211,6 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
     if (tid == 0) {
         misc[0] = 0;
         misc[1] = 0;
-        misc[2] = 0;
         stepc[0] = 0;
         stepc[1] = 0;
     }
@@ -229,8 +233,9 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
     const bool pair_out = has_states(sprime);
 
     // -- gather + update + expand + bounds + rollouts (Eq. 10, 12, 13) ------
-    // Every lane of a wavefront runs the same number of rounds, so the
-    // reward of a 64-scenario chunk can be summed with shuffles right here.
+    // Every lane of a wavefront runs the same number of rounds, so a
+    // 64-scenario chunk's reward (and, for small alphabets, its per-key
+    // tables) are reduced by the whole wavefront right here.
     int my_exp = 0, my_roll = 0;
     typename Ops::WaveUpper wave_upper;
     for (int base = 0; base < n; base += nt) {
@@ -240,7 +245,6 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
         uint64_t z = 0;
         uint32_t id = 0;
         typename Ops::State st;
-        // gather + update + expansion step of one scenario
         // gather + update + expansion step of one scenario
         auto expand_one = [&]() {
             const int p = T->idx[k];

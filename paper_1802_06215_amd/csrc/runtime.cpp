@@ -433,8 +433,6 @@ void pack_leaves(const hdx_leaf *leaves, int32_t n_leaves, LeafTask *tasks, Tile
     }
 }
 
-// Default schedule: one scenario per lane up to the variant's workgroup cap,
-// one workgroup per tile, consecutive tiles kept on one XCD.
 }  // namespace
 
 void hdx::plan_classes(const LeafTask *tasks, const int8_t *variant, Tile *tiles, int64_t n_tiles,
