@@ -11,7 +11,10 @@ in Python.  States use the library's documented struct-of-arrays layout:
 * RockSample: ``{"w": int32[n]}`` with x in bits 0-4, y in bits 5-9, rock i's
   quality in bit 10+i and the terminal flag in bit 30;
 * crowd driving: ``{"s": f32[n], "car": int32[n] (speed level | terminal<<8),
-  "px": f32[P, n], "py": f32[P, n], "goal": u8[P, n]}``.
+  "px": f32[P, n], "py": f32[P, n], "goal": u8[P, n]}``;
+* multi-agent RockSample: ``{"w": int32[2, n]}``, row 0 the robots (robot 1's
+  x, y in bits 0-4, 5-9, robot 2's in bits 10-14, 15-19, robot j gone in bit
+  20+j, terminal in bit 30), row 1 the rocks (rock i's quality in bit i).
 
 Parity pins for every function here live in ``tests/test_oracle_*.py``.
 """
@@ -128,10 +131,36 @@ def rs_unpack(w) -> dict:
     return dict(x=w & 31, y=(w >> 5) & 31, rocks=(w >> 10) & 0xFFFFF, term=(w >> 30) & 1)
 
 
+def mars_pack(pos, rocks, term=None) -> np.ndarray:
+    """Multi-agent RockSample states [2, n] from fields: pos = (x1, y1, x2,
+    y2, gone1, gone2), each a scalar or an [n] array; rocks: bool [n, m];
+    term defaults to both robots gone."""
+    rocks = np.asarray(rocks, dtype=bool)
+    n = rocks.shape[0]
+    x1, y1, x2, y2, g1, g2 = (np.broadcast_to(np.asarray(f, dtype=np.int64), (n,)) for f in pos)
+    if term is None:
+        term = g1 & g2
+    row0 = x1 | (y1 << 5) | (x2 << 10) | (y2 << 15) | (g1 << 20) | (g2 << 21)
+    row0 = row0 | (np.asarray(term, dtype=np.int64) << 30)
+    row1 = np.zeros(n, dtype=np.int64)
+    for i in range(rocks.shape[1]):
+        row1 |= rocks[:, i].astype(np.int64) << i
+    return np.stack([row0, row1]).astype(np.int32)
+
+
+def mars_unpack(w) -> dict:
+    w = np.asarray(w, dtype=np.int64)
+    r0 = w[0]
+    return dict(x1=r0 & 31, y1=(r0 >> 5) & 31, x2=(r0 >> 10) & 31, y2=(r0 >> 15) & 31,
+                gone1=(r0 >> 20) & 1, gone2=(r0 >> 21) & 1, term=(r0 >> 30) & 1, rocks=w[1])
+
+
 def parent_states(desc: dict, leaf: dict) -> dict:
     """States dict for a synthetic leaf's parent (fields from ``workloads``)."""
     if desc["kind"] == 0:
         return dict(w=rs_pack(leaf["x"], leaf["y"], leaf["rocks"], leaf["term"]))
+    if desc["kind"] == 2:
+        return dict(w=mars_pack(leaf["pos"], leaf["rocks"], leaf["term"]))
     car = leaf["level"].astype(np.int32) | (leaf["term"].astype(np.int32) << 8)
     return dict(s=np.ascontiguousarray(leaf["s"], dtype=np.float32), car=car.astype(np.int32),
                 px=np.ascontiguousarray(leaf["px"], dtype=np.float32),
@@ -142,6 +171,8 @@ def parent_states(desc: dict, leaf: dict) -> dict:
 def empty_states(desc: dict, n: int) -> dict:
     if desc["kind"] == 0:
         return dict(w=np.zeros(n, np.int32))
+    if desc["kind"] == 2:
+        return dict(w=np.zeros((2, n), np.int32))
     P = desc["n_peds"]
     return dict(s=np.zeros(n, np.float32), car=np.zeros(n, np.int32),
                 px=np.zeros((P, n), np.float32), py=np.zeros((P, n), np.float32),
@@ -152,7 +183,7 @@ def _soa(desc: dict, st: dict | None, n: int) -> _Soa:
     v = _Soa()
     if st is None:
         return v
-    if desc["kind"] == 0:
+    if desc["kind"] in (0, 2):
         v.w = _ptr(st["w"])
     else:
         v.s, v.car = _ptr(st["s"]), _ptr(st["car"])
@@ -165,6 +196,9 @@ def _check_states(desc, st):
     if desc["kind"] == 0:
         assert st["w"].dtype == np.int32 and st["w"].flags.c_contiguous
         return st["w"].shape[0]
+    if desc["kind"] == 2:
+        assert st["w"].dtype == np.int32 and st["w"].flags.c_contiguous and st["w"].shape[0] == 2
+        return st["w"].shape[1]
     n = st["s"].shape[0]
     P = desc["n_peds"]
     assert st["px"].shape == (P, n) and st["goal"].dtype == np.uint8
@@ -178,7 +212,7 @@ def model(desc: dict) -> _Model:
     m.kind = desc["kind"]
     m.n_actions = desc["n_actions"]
     m.gamma = desc["gamma"]
-    if desc["kind"] == 0:
+    if desc["kind"] in (0, 2):
         m.n, m.m = desc["n"], desc["m"]
         for i in range(desc["m"]):
             m.rock_x[i] = int(desc["rock_x"][i])
@@ -198,7 +232,8 @@ def model(desc: dict) -> _Model:
 def cfg(policy: int = 0, max_steps: int = 1 << 30, max_depth: int = -1,
         const_action: int = 0) -> _Cfg:
     """Rollout configuration: policy 0 = model default (RockSample: move
-    east; crowd driving: brake for a pedestrian ahead, else accelerate),
+    east; multi-agent RockSample: both robots move east; crowd driving: brake
+    for a pedestrian ahead, else accelerate),
     1 = constant action, 2 = uniform random action per step."""
     c = _Cfg()
     c.policy, c.const_action, c.max_steps, c.max_depth = policy, const_action, max_steps, max_depth
@@ -227,6 +262,11 @@ def sample_scenarios(desc, belief, K, seed, step_idx):
     if desc["kind"] == 0:
         p = np.ascontiguousarray(belief["p"], dtype=np.float64)
         lib().or_sample_scenarios(C.byref(M), K, seed, step_idx, belief["x"], belief["y"], _ptr(p),
+                                  0.0, 0, None, None, None, C.byref(_soa(desc, out, K)))
+    elif desc["kind"] == 2:
+        p = np.ascontiguousarray(belief["p"], dtype=np.float64)
+        row0 = int(mars_pack(belief["pos"], np.zeros((1, 0), bool))[0, 0])
+        lib().or_sample_scenarios(C.byref(M), K, seed, step_idx, row0, 0, _ptr(p),
                                   0.0, 0, None, None, None, C.byref(_soa(desc, out, K)))
     else:
         px = np.ascontiguousarray(belief["px"], dtype=np.float32)
@@ -259,7 +299,10 @@ def rollout_bounds(desc, rcfg, states, ids, depths, seed, step_idx, with_abs: bo
 
 def max_children(desc: dict, n: int) -> int:
     """Most children one action can have: RockSample observations take 3
-    values; crowd-driving observations are hashes, so up to one per scenario."""
+    values, multi-agent ones 9; crowd-driving observations are hashes, so up
+    to one per scenario."""
+    if desc["kind"] == 2:
+        return min(n, 9)
     return min(n, 3) if desc["kind"] == 0 else n
 
 
@@ -305,6 +348,8 @@ def expand_leaf(desc, rcfg, parent, parent_ids, idx, depth, last_action, seed, s
         sp = res["sprime"]
         if desc["kind"] == 0:
             sp["w"] = sp["w"].reshape(A, n)
+        elif desc["kind"] == 2:
+            sp["w"] = sp["w"].reshape(2, A, n)
         else:
             P = desc["n_peds"]
             sp["s"], sp["car"] = sp["s"].reshape(A, n), sp["car"].reshape(A, n)
@@ -322,6 +367,8 @@ def take_states(desc: dict, st: dict, positions) -> dict:
     positions = np.asarray(positions, dtype=np.int64)
     if desc["kind"] == 0:
         return dict(w=np.ascontiguousarray(st["w"][positions]))
+    if desc["kind"] == 2:
+        return dict(w=np.ascontiguousarray(st["w"][:, positions]))
     return dict(s=np.ascontiguousarray(st["s"][positions]),
                 car=np.ascontiguousarray(st["car"][positions]),
                 px=np.ascontiguousarray(st["px"][:, positions]),

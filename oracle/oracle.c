@@ -95,7 +95,7 @@ static uint64_t prob_threshold(double p)
 #define OR_MAX_GOALS 8
 
 typedef struct {
-    int32_t kind; /* 0: RockSample, 1: crowd driving */
+    int32_t kind; /* 0: RockSample, 1: crowd driving, 2: multi-agent RockSample */
     int32_t n_actions;
     double gamma;
     /* RockSample */
@@ -118,7 +118,8 @@ typedef struct {
 
 /* One scenario's state, in a form the plain loops can copy freely. */
 typedef struct {
-    int32_t w; /* RockSample: packed word */
+    int32_t w;  /* RockSample: packed word; multi-agent: the robots' row */
+    int32_t w2; /* multi-agent RockSample: the rocks' row */
     float s;   /* crowd driving: car position along the path */
     int32_t level;
     int32_t term;
@@ -128,7 +129,7 @@ typedef struct {
 
 /* Struct-of-arrays views, in the library's documented state layout. */
 typedef struct {
-    int32_t *w;     /* RockSample word per scenario */
+    int32_t *w;     /* RockSample word per scenario; multi-agent: [2][stride] */
     float *s;       /* car position */
     int32_t *car;   /* speed level in bits 0-7, terminal in bit 8 */
     float *px, *py; /* [ped][scenario] */
@@ -141,6 +142,10 @@ static void load_state(const or_model *M, const or_soa *A, int64_t k, or_state *
     memset(st, 0, sizeof(*st));
     if (M->kind == 0) {
         st->w = A->w[k];
+        st->term = (st->w >> 30) & 1;
+    } else if (M->kind == 2) {
+        st->w = A->w[k];
+        st->w2 = A->w[A->stride + k];
         st->term = (st->w >> 30) & 1;
     } else {
         st->s = A->s[k];
@@ -158,6 +163,9 @@ static void store_state(const or_model *M, const or_soa *A, int64_t k, const or_
 {
     if (M->kind == 0) {
         A->w[k] = st->w;
+    } else if (M->kind == 2) {
+        A->w[k] = st->w;
+        A->w[A->stride + k] = st->w2;
     } else {
         A->s[k] = st->s;
         A->car[k] = (st->level & 0xff) | (st->term ? 0x100 : 0);
@@ -246,6 +254,111 @@ static double rs_upper(const or_model *M, const or_state *st)
         if (rs_good(st->w, i))
             u += 10.0 * pow(M->gamma, abs(x - M->rock_x[i]) + abs(y - M->rock_y[i]));
     u += 10.0 * pow(M->gamma, M->n - 1 - x);
+    return u;
+}
+
+/* --- Multi-agent RockSample (Sec. IV-A): two robots on one n x n grid
+ *     share the m rocks; each robot moves to a neighbouring cell, senses a
+ *     rock or samples the rock it stands on, and earns +10 when it leaves
+ *     through the east border; the world ends when both have left.
+ *     State, two rows: robots' row = robot 1's cell (x bits 0-4, y bits
+ *     5-9), robot 2's cell (x bits 10-14, y bits 15-19), robot j gone in bit
+ *     20+j, terminal (both gone) in bit 30; rocks' row = quality of rock i in
+ *     bit i.  Joint action a = a1 (5+m) + a2, each robot's own action
+ *     numbered as in RockSample.  Readings: robot 1 acts first and robot 2
+ *     then acts on the rocks robot 1 left (a rock both sample in one step
+ *     pays +10 then -10); a robot that has left does nothing; robot j's
+ *     sensor reads word j of the step block; the joint observation is
+ *     3 z1 + z2. */
+#define MARS_GONE0 20
+#define MARS_TERM 30
+
+static void mars_robot(const or_model *M, or_state *st, int j, int b, uint32_t word, float *r, int *zj)
+{
+    int32_t w = st->w;
+    *r = 0.0f;
+    *zj = OBS_NONE;
+    if ((w >> (MARS_GONE0 + j)) & 1) return; /* this robot has left the map */
+    int sh = 10 * j, n = M->n;
+    int x = (w >> sh) & 31, y = (w >> (sh + 5)) & 31;
+    if (b == RS_NORTH) {
+        if (y + 1 < n) y = y + 1;
+    } else if (b == RS_SOUTH) {
+        if (y > 0) y = y - 1;
+    } else if (b == RS_WEST) {
+        if (x > 0) x = x - 1;
+    } else if (b == RS_EAST) {
+        if (x + 1 == n) {
+            *r = 10.0f;
+            w |= 1 << (MARS_GONE0 + j);
+        } else {
+            x = x + 1;
+        }
+    } else if (b == RS_SAMPLE) {
+        for (int i = 0; i < M->m; i++) {
+            if (M->rock_x[i] == x && M->rock_y[i] == y) {
+                if ((st->w2 >> i) & 1) {
+                    *r = 10.0f;
+                    st->w2 &= ~(1 << i);
+                } else {
+                    *r = -10.0f;
+                }
+            }
+        }
+    } else {
+        int i = b - RS_SENSE0;
+        int dx = x - M->rock_x[i], dy = y - M->rock_y[i];
+        int correct = (uint64_t)word < rs_sense_threshold(dx * dx + dy * dy);
+        int truth = (st->w2 >> i) & 1;
+        int reading = correct ? truth : !truth;
+        *zj = reading ? OBS_GOOD : OBS_BAD;
+    }
+    w = (w & ~(0x3ff << sh)) | ((x | (y << 5)) << sh);
+    st->w = w;
+}
+
+static void mars_step(const or_model *M, or_state *st, int a, uint32_t seed, uint32_t step,
+                      uint32_t id, uint32_t depth, float *r, uint64_t *z)
+{
+    *r = 0.0f;
+    *z = OBS_NONE;
+    if (st->term) return; /* terminal states are absorbing */
+    int per = 5 + M->m;
+    uint32_t u[4];
+    draw_block(seed, step, id, depth, 0, TAG_STEP, u);
+    float r1, r2;
+    int z1, z2;
+    mars_robot(M, st, 0, a / per, u[0], &r1, &z1);
+    mars_robot(M, st, 1, a % per, u[1], &r2, &z2);
+    *r = r1 + r2;
+    *z = (uint64_t)(3 * z1 + z2);
+    if (((st->w >> MARS_GONE0) & 3) == 3) {
+        st->term = 1;
+        st->w |= 1 << MARS_TERM;
+    }
+}
+
+/* Optimistic value: every good rock sampled by the nearer robot still on
+ * the map on arrival at the shortest path length, plus each such robot's
+ * exit reward at its shortest exit time. */
+static double mars_upper(const or_model *M, const or_state *st)
+{
+    if (st->term) return 0.0;
+    double u = 0.0;
+    for (int i = 0; i < M->m; i++) {
+        if (!((st->w2 >> i) & 1)) continue;
+        int best = -1;
+        for (int j = 0; j < 2; j++) {
+            if ((st->w >> (MARS_GONE0 + j)) & 1) continue;
+            int x = (st->w >> (10 * j)) & 31, y = (st->w >> (10 * j + 5)) & 31;
+            int d = abs(x - M->rock_x[i]) + abs(y - M->rock_y[i]);
+            if (best < 0 || d < best) best = d;
+        }
+        u += 10.0 * pow(M->gamma, best);
+    }
+    for (int j = 0; j < 2; j++)
+        if (!((st->w >> (MARS_GONE0 + j)) & 1))
+            u += 10.0 * pow(M->gamma, M->n - 1 - ((st->w >> (10 * j)) & 31));
     return u;
 }
 
@@ -386,12 +499,15 @@ static void model_step(const or_model *M, or_state *st, int a, uint32_t seed, ui
 {
     if (M->kind == 0)
         rs_step(M, st, a, seed, step, id, depth, r, z);
+    else if (M->kind == 2)
+        mars_step(M, st, a, seed, step, id, depth, r, z);
     else
         ped_step(M, st, a, seed, step, id, depth, r, z);
 }
 
 static double model_upper(const or_model *M, const or_state *st)
 {
+    if (M->kind == 2) return mars_upper(M, st);
     return M->kind == 0 ? rs_upper(M, st) : ped_upper(M, st);
 }
 
@@ -404,6 +520,7 @@ static int policy_action(const or_model *M, const or_rollout_cfg *C, const or_st
         draw_block(seed, step, id, depth, 0, TAG_POLICY, u);
         return (int)(u[0] % (uint32_t)M->n_actions);
     }
+    if (M->kind == 2) return RS_EAST * (5 + M->m) + RS_EAST; /* both robots move east */
     return M->kind == 0 ? RS_EAST : ped_default_action(M, st);
 }
 
@@ -450,7 +567,8 @@ void or_step_batch(const or_model *M, const or_soa *in, const uint32_t *ids, int
 
 /* Draw K start states from the belief (Sec. III-A): scenario k uses counter
  * (k, 0, block, INIT).  RockSample: known cell, rock i good with
- * probability p[i] (word i%4 of block i/4).  Crowd driving: known car and
+ * probability p[i] (word i%4 of block i/4).  Multi-agent RockSample: x0 is
+ * the known robots' row, the rocks drawn as for RockSample.  Crowd driving: known car and
  * pedestrian positions, pedestrian j's goal drawn from goal_p[j][.]. */
 void or_sample_scenarios(const or_model *M, int32_t K, uint32_t seed, uint32_t step,
                          int32_t x0, int32_t y0, const double *p_good,
@@ -468,6 +586,14 @@ void or_sample_scenarios(const or_model *M, int32_t K, uint32_t seed, uint32_t s
                 if ((uint64_t)u[i % 4] < prob_threshold(p_good[i])) w |= 1 << (10 + i);
             }
             st.w = w;
+        } else if (M->kind == 2) {
+            st.w = x0;
+            st.term = (x0 >> MARS_TERM) & 1;
+            for (int i = 0; i < M->m; i++) {
+                uint32_t u[4];
+                draw_block(seed, step, (uint32_t)k, 0, (uint32_t)(i / 4), TAG_INIT, u);
+                if ((uint64_t)u[i % 4] < prob_threshold(p_good[i])) st.w2 |= 1 << i;
+            }
         } else {
             st.s = s0;
             st.level = level0;

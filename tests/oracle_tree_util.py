@@ -19,3 +19,24 @@ def grow(desc, rc, parent, parent_ids, idx, depth, last_action, seed, step, hori
     node.u = oracle.node_value(node, desc["gamma"], "u")
     node.l = oracle.node_value(node, desc["gamma"], "l")
     return node
+
+
+def brute_force(desc, rc, st, ids, depth, h, seed, step, which):
+    """Scenario-determinised expectimax, grouping by a dictionary."""
+    n = len(ids)
+    if h == 0:
+        U, L, _ = oracle.rollout_bounds(desc, rc, st, ids, depth, seed, step)
+        return float(np.mean(U if which == "u" else L))
+    best = -np.inf
+    for a in range(desc["n_actions"]):
+        nxt, r, z = oracle.step(desc, st, ids, a, depth, seed, step)
+        groups = {}
+        for k in range(n):
+            groups.setdefault(int(z[k]), []).append(k)
+        q = float(np.sum(r.astype(np.float64))) / n
+        for zz, ks in groups.items():
+            sub = oracle.take_states(desc, nxt, ks)
+            q += desc["gamma"] * len(ks) / n * brute_force(desc, rc, sub, ids[ks], depth + 1, h - 1,
+                                                           seed, step, which)
+        best = max(best, q)
+    return best

@@ -16,7 +16,7 @@ import pytest
 
 import oracle
 import workloads as W
-from oracle_tree_util import grow
+from oracle_tree_util import brute_force, grow
 
 
 def rs_model(n, rocks):
@@ -39,27 +39,6 @@ def test_no_rocks_depth_closed_form(n, x0):
     deep = grow(d, rc, st, np.arange(K), np.arange(K), 0, -1, 1, 0, need)
     assert abs(deep.l - exact) < 1e-12
     assert abs(deep.u - exact) < 1e-12  # the heuristic is tight with no rocks
-
-
-def brute_force(desc, rc, st, ids, depth, h, seed, step, which):
-    """Scenario-determinised expectimax, grouping by a dictionary."""
-    n = len(ids)
-    if h == 0:
-        U, L, _ = oracle.rollout_bounds(desc, rc, st, ids, depth, seed, step)
-        return float(np.mean(U if which == "u" else L))
-    best = -np.inf
-    for a in range(desc["n_actions"]):
-        nxt, r, z = oracle.step(desc, st, ids, a, depth, seed, step)
-        groups = {}
-        for k in range(n):
-            groups.setdefault(int(z[k]), []).append(k)
-        q = float(np.sum(r.astype(np.float64))) / n
-        for zz, ks in groups.items():
-            sub = oracle.take_states(desc, nxt, ks)
-            q += desc["gamma"] * len(ks) / n * brute_force(desc, rc, sub, ids[ks], depth + 1, h - 1,
-                                                           seed, step, which)
-        best = max(best, q)
-    return best
 
 
 @pytest.mark.parametrize("case", range(4))

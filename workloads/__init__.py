@@ -16,6 +16,7 @@ import numpy as np
 
 ROCKSAMPLE = 0
 PEDNAV = 1
+MARS = 2
 
 
 def rocksample_model(n: int, m: int, seed: int, gamma: float = 0.95) -> dict:
@@ -45,6 +46,38 @@ def rocksample_belief(model: dict, p_good: float = 0.5, x=None, y=None) -> dict:
     return dict(x=model["start_x"] if x is None else x,
                 y=model["start_y"] if y is None else y,
                 p=np.full(m, p_good, dtype=np.float64))
+
+
+def mars_model(n: int, m: int, seed: int, gamma: float = 0.95) -> dict:
+    """Multi-agent RockSample(n, m): two robots on an n x n grid with m rocks
+    on distinct seeded cells (Sec. IV-A).
+
+    Robot 1 starts at column 0, row n // 2, robot 2 at column 0, row
+    n // 2 - 1; no rock lies on a start cell.  Each robot has 5 + m actions
+    (four moves, sample, one sense per rock), so the joint action count is
+    (5 + m)^2: 256, 400 and 625 for (11, 11), (15, 15) and (20, 20).
+    """
+    if not (2 <= n <= 31) or not (0 <= m <= 20):
+        raise ValueError("need 2 <= n <= 31 and 0 <= m <= 20")
+    rng = np.random.default_rng(np.random.SeedSequence([0x4D4152, n, m, seed]))
+    starts = [(0, n // 2), (0, n // 2 - 1)]
+    cells = [c for c in range(n * n) if (c % n, c // n) not in starts]
+    if m > len(cells):
+        raise ValueError("too many rocks for the grid")
+    pick = rng.permutation(len(cells))[:m]
+    rx = np.array([cells[i] % n for i in pick], dtype=np.int32)
+    ry = np.array([cells[i] // n for i in pick], dtype=np.int32)
+    return dict(kind=MARS, n=n, m=m, rock_x=rx, rock_y=ry, gamma=gamma,
+                start=(starts[0][0], starts[0][1], starts[1][0], starts[1][1]),
+                n_actions=(5 + m) ** 2)
+
+
+def mars_belief(model: dict, p_good: float = 0.5, pos=None) -> dict:
+    """Initial belief: known robot cells (pos = (x1, y1, x2, y2, gone1,
+    gone2)), independent rock qualities."""
+    if pos is None:
+        pos = (*model["start"], 0, 0)
+    return dict(pos=tuple(int(v) for v in pos), p=np.full(model["m"], p_good, dtype=np.float64))
 
 
 def pednav_model(n_peds: int, n_goals: int, seed: int, gamma: float = 0.98,
@@ -96,6 +129,36 @@ def rocksample_leaf(model: dict, n_parent: int, n_leaf: int, seed: int,
     return dict(x=int(rng.integers(0, n)), y=int(rng.integers(0, n)),
                 rocks=rng.random((n_parent, m)) < 0.5,
                 term=rng.random(n_parent) < p_term,
+                ids=_sorted_subset(rng, k_root, n_parent),
+                idx=_sorted_subset(rng, n_parent, n_leaf),
+                depth=int(rng.integers(1, 16)) if depth is None else depth,
+                last_action=int(rng.integers(0, model["n_actions"])))
+
+
+def mars_leaf(model: dict, n_parent: int, n_leaf: int, seed: int,
+              k_root: int | None = None, p_term: float = 0.02,
+              depth: int | None = None, shared_cells: bool = True) -> dict:
+    """A synthetic multi-agent RockSample leaf.
+
+    Robot cells are deterministic in the model, so by default the parent's
+    scenarios share both cells (and a robot that has left, with probability
+    0.2 each); with shared_cells=False every scenario draws its own cells.
+    A few scenarios are terminal (both robots gone).
+    """
+    rng = np.random.default_rng(np.random.SeedSequence([0x4D4C46, n_parent, n_leaf, seed]))
+    n, m = model["n"], model["m"]
+    k_root = max(k_root or n_parent, n_parent)
+    size = 1 if shared_cells else n_parent
+    cells = [rng.integers(0, n, size) for _ in range(4)]
+    gone = [(rng.random(size) < 0.2).astype(np.int64) for _ in range(2)]
+    both = gone[0] & gone[1]
+    gone[1] = gone[1] & ~both  # at most one robot gone unless terminal
+    term = rng.random(n_parent) < p_term
+    g1 = np.broadcast_to(gone[0], (n_parent,)) | term
+    g2 = np.broadcast_to(gone[1], (n_parent,)) | term
+    pos = tuple(np.broadcast_to(c, (n_parent,)).astype(np.int64) for c in cells) + (g1.astype(np.int64),
+                                                                                   g2.astype(np.int64))
+    return dict(pos=pos, rocks=rng.random((n_parent, m)) < 0.5, term=term.astype(np.int64),
                 ids=_sorted_subset(rng, k_root, n_parent),
                 idx=_sorted_subset(rng, n_parent, n_leaf),
                 depth=int(rng.integers(1, 16)) if depth is None else depth,
