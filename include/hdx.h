@@ -56,8 +56,10 @@ typedef int32_t hdx_status;
 
 #define HDX_ROCKSAMPLE 0
 #define HDX_PEDNAV 1
+#define HDX_MARS 2 /* multi-agent RockSample */
 
 #define HDX_MAX_ROCKS 20
+#define HDX_MAX_ACTIONS 625 /* (5 + HDX_MAX_ROCKS)^2, the multi-agent model's largest */
 #define HDX_MAX_GRID 31
 #define HDX_MAX_PEDS 32
 #define HDX_MAX_GOALS 8
@@ -78,13 +80,20 @@ typedef void *hdx_stream; /* hipStream_t */
  * (rock_x[i], rock_y[i]); actions 0 north (y+1), 1 south, 2 east (x+1),
  * 3 west, 4 sample, 5+i sense rock i; rewards +10 good sample, -10 bad
  * sample, +10 exit east (terminal); sensor accuracy 0.5 + 0.5 2^(-d/20).
+ * Multi-agent RockSample (Sec. IV-A): the same grid and rocks with two
+ * robots; joint action a = a1 (5 + n_rocks) + a2, each robot's own action
+ * numbered as above, so n_actions = (5 + n_rocks)^2 (625 for 20 rocks);
+ * robot 1 acts first, then robot 2 on the rocks robot 1 left; each robot
+ * earns +10 on leaving through the east border and then does nothing; the
+ * world ends when both have left; robot j (0, 1) reads word j of its step's
+ * random block for a sense; observation 3 z1 + z2 (9 values); grid >= 2.
  * Crowd driving (Sec. IV-A): straight path of path_len metres, n_levels
  * speed levels, pedestrians walking at ped_speed to one of n_goals goal
  * points with Gaussian heading noise sigma_h; actions 0 accelerate,
  * 1 maintain, 2 decelerate, failing with probability p_fail. */
 typedef struct {
-    int32_t kind;     /* HDX_ROCKSAMPLE or HDX_PEDNAV */
-    int32_t n_actions;/* 5 + n_rocks, or 3 */
+    int32_t kind;     /* HDX_ROCKSAMPLE, HDX_PEDNAV or HDX_MARS */
+    int32_t n_actions;/* 5 + n_rocks, 3, or (5 + n_rocks)^2 */
     double gamma;     /* discount */
     int32_t grid, n_rocks;
     int32_t rock_x[HDX_MAX_ROCKS], rock_y[HDX_MAX_ROCKS];
@@ -103,6 +112,8 @@ typedef struct {
     int32_t level;         /* driving: speed level */
     const float *px, *py;  /* driving: [n_peds] pedestrian positions */
     const double *goal_p;  /* driving: [n_peds][n_goals] goal probabilities */
+    int32_t x2, y2;        /* multi-agent: robot 2's cell (x, y is robot 1's) */
+    int32_t gone;          /* multi-agent: bit j set if robot j+1 has left */
 } hdx_belief;
 
 /* Rollout configuration for the lower bound (Eq. 13).  A rollout from depth
@@ -115,6 +126,12 @@ typedef struct {
     int32_t max_depth;
 } hdx_rollout_cfg;
 
+/* Scenario states, struct of arrays (device pointers).  RockSample: w[k],
+ * the packed word.  Multi-agent RockSample: w[k] the robots' row (robot 1's
+ * x, y in bits 0-4, 5-9, robot 2's in bits 10-14, 15-19, robot j gone in
+ * bit 20+j, terminal in bit 30) and w[stride + k] the rocks' row (rock i's
+ * quality in bit i).  Driving: s[k], car[k] (speed level | terminal << 8)
+ * and px, py, goal [n_peds][stride]. */
 typedef struct {
     int32_t *w;
     float *s;
@@ -231,7 +248,8 @@ hdx_status hdx_batch_destroy(hdx_ctx *ctx, hdx_batch *batch);
 hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *batch, const hdx_leaf *leaves, int32_t n_leaves,
                                 hdx_stream stream);
 /* Launch plan and schedule.  Tiles launch in groups of one model variant
- * (0 RockSample; 1, 2, 3 driving with up to 8, 16, 32 pedestrians), each
+ * (0 RockSample; 1, 2, 3 driving with up to 8, 16, 32 pedestrians; 4
+ * multi-agent RockSample), each
  * group one dispatch with an LDS carve-up and workgroup size for its
  * largest leaf, tiles ordered largest leaf first.  Unsplit (the default):
  * one group per variant, filed under the size class of its largest leaf.
@@ -239,7 +257,8 @@ hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *batch, const hdx_leaf *
  * of 64*2^(c-1) < n <= 64*2^c scenarios, c = 0..5), the groups launched side
  * by side.  Group = variant * HDX_SIZE_CLASSES + class.  set_split re-plans
  * the staged leaves (and later ones).  A group's schedule: workgroup size
- * (multiple of 64; capped at 512 for RockSample and 256 for driving, and at
+ * (multiple of 64; capped at 512 for both RockSample models and 256 for
+ * driving, and at
  * what the group's leaves need), persistent workgroups per CU (0 = one
  * workgroup per tile), and the XCD-contiguous tile mapping.  set_schedule applies to every group, set_class_schedule to the
  * groups of one size class; get_group_schedule reports one group (and its
@@ -247,7 +266,7 @@ hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *batch, const hdx_leaf *
  * get_schedule the group with the most tiles.  Results are bit-identical
  * under every schedule. */
 #define HDX_SIZE_CLASSES 6
-#define HDX_LAUNCH_GROUPS 24
+#define HDX_LAUNCH_GROUPS 30
 hdx_status hdx_batch_set_split(hdx_ctx *ctx, hdx_batch *batch, int32_t split);
 hdx_status hdx_batch_get_split(const hdx_batch *batch, int32_t *split);
 hdx_status hdx_batch_set_schedule(hdx_ctx *ctx, hdx_batch *batch, int32_t threads, int32_t persistent,
@@ -359,7 +378,8 @@ hdx_status hdx_mlp_train_step(hdx_ctx *ctx, hdx_mlp *mlp, const uint16_t *X, con
 /* Surrogate input features of n states (device): RockSample x/n, y/n,
  * terminal, (horizon - depth)/100, rock qualities, rock offsets dx/n and
  * dy/n; driving s/L, speed level, terminal, (horizon - depth)/100, then per
- * pedestrian (px - s)/10, py/10, goal/n_goals; zero padding to 64. */
+ * pedestrian (px - s)/10, py/10, goal/n_goals; zero padding to 64.
+ * HDX_E_UNSUPPORTED for the multi-agent model (no features defined). */
 hdx_status hdx_features(hdx_ctx *ctx, const hdx_model *model, hdx_states states, const int32_t *depths, int64_t n,
                         int32_t horizon, uint16_t *X, hdx_stream stream);
 
@@ -369,7 +389,7 @@ hdx_status hdx_features(hdx_ctx *ctx, const hdx_model *model, hdx_states states,
  * the given horizon), steps[a][1] is 0, and L (if given) receives the
  * surrogate value per (action, scenario).  Scratch for the stepped states,
  * features and values belongs to the MLP handle (grown on demand); calls
- * on one handle are serialised. */
+ * on one handle are serialised.  HDX_E_UNSUPPORTED for a multi-agent leaf. */
 hdx_status hdx_expand_leaf_surrogate(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves, hdx_mlp *mlp,
                                      int32_t horizon, hdx_stream stream);
 
@@ -428,8 +448,8 @@ typedef struct {
     int32_t max_depth_reached;
     int32_t arena_full;             /* 1 if the device arena ran out */
     double elapsed_s;
-    double action_l[HDX_MAX_ROCKS + 5]; /* per-action lower bounds at the root (first n_actions) */
-    double action_u[HDX_MAX_ROCKS + 5];
+    double action_l[HDX_MAX_ACTIONS]; /* per-action lower bounds at the root (first n_actions) */
+    double action_u[HDX_MAX_ACTIONS];
     int64_t judged_leaves, judged_children; /* surrogate judge: leaves and children compared */
     double judge_mae;                       /* mean |l0_sur - l0_rollout| per judged child */
     double judge_rel_err;                   /* sum |l0_sur - l0_rollout| / sum |l0_rollout| */

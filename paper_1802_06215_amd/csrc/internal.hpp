@@ -176,7 +176,7 @@ __host__ __device__ inline LdsLayout make_layout(int32_t np, bool small = false)
 struct Variant {
     int32_t mode, pm, n_max;
 };
-Variant pick_variant(int32_t has_rs, int32_t has_ped, int32_t ped_max, int32_t n_max);
+Variant pick_variant(int32_t has_rs, int32_t has_ped, int32_t ped_max, int32_t n_max, int32_t has_mars);
 int32_t variant_max_threads(const Variant &v);
 
 // Kernel launchers (kernels.hip).  The expansion kernel reads the tile
@@ -185,7 +185,8 @@ hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue
                          const Variant &v, const Schedule &sch, int32_t n_cu, hipStream_t stream);
 
 // Tiles are launched in groups.  A group holds tiles of one model variant
-// (0 RockSample, 1-3 driving with up to 8, 16, 32 pedestrians), so
+// (0 RockSample, 1-3 driving with up to 8, 16, 32 pedestrians, 4
+// multi-agent RockSample), so
 // RockSample tiles never run in the register budget of the driving model,
 // and gets an LDS carve-up and workgroup size for its own largest leaf.  By
 // default all leaves of a variant form one group (one dispatch, no fork and
@@ -200,7 +201,7 @@ hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue
 // owns tiles [begin[g], begin[g] + count[g]) and the queue d_queues[g].
 constexpr int kSizeClasses = 6;
 constexpr int kXcds = 8;  // accelerator dies, each with its own L2
-constexpr int kModelVariants = 4;
+constexpr int kModelVariants = 5;
 constexpr int kGroups = kModelVariants * kSizeClasses;
 __host__ __device__ inline int size_class(int32_t n) {
     int c = 0;
@@ -208,10 +209,11 @@ __host__ __device__ inline int size_class(int32_t n) {
     return c;
 }
 inline int model_variant(int32_t kind, int32_t n_peds) {
-    return kind == HDX_ROCKSAMPLE ? 0 : n_peds <= 8 ? 1 : n_peds <= 16 ? 2 : 3;
+    return kind == HDX_ROCKSAMPLE ? 0 : kind == HDX_MARS ? 4 : n_peds <= 8 ? 1 : n_peds <= 16 ? 2 : 3;
 }
 inline Variant group_variant(int g) {
     const int v = g / kSizeClasses;
+    if (v == 4) return Variant{3, 1, 1};
     return v == 0 ? Variant{0, 1, 1} : Variant{1, v == 1 ? 8 : v == 2 ? 16 : 32, 1};
 }
 struct ClassPlan {
@@ -250,7 +252,7 @@ struct SampleArgs {
     const DevModel *model;
     uint32_t k0, k1;
     int32_t K;
-    int32_t x0, y0;
+    int32_t x0, y0;  // RockSample: robot cell; multi-agent: x0 is the robots' row
     uint64_t rock_thr[kMaxRocks];
     float s0;
     int32_t level0;

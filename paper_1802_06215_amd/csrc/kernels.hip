@@ -619,15 +619,28 @@ __device__ __forceinline__ int remap_xcd(int b, int grid) {
     return x * base + min(x, extra) + slot;
 }
 
-// MODE 0: RockSample only; 1: crowd driving only; 2: both.  Workgroups of
-// the driving model are capped at 256 lanes so its per-lane state can stay
-// in registers.
+// MODE 0: RockSample only; 1: crowd driving only; 2: both; 3: multi-agent
+// RockSample only.  Workgroups of the driving model are capped at 256 lanes
+// so its per-lane state can stay in registers.
 template <int MODE>
-constexpr int max_threads() { return MODE == 0 ? 512 : 256; }
+constexpr bool small_obs_mode() { return MODE == 0 || MODE == 3; }
+template <int MODE>
+constexpr int max_threads() { return small_obs_mode<MODE>() ? 512 : 256; }
 // RockSample tiles: keep 7 wavefronts per SIMD resident (at most 72 VGPRs,
 // no spills); the driving model's register state decides its own.
 template <int MODE>
-constexpr int min_waves() { return MODE == 0 ? 7 : 1; }
+constexpr int min_waves() { return small_obs_mode<MODE>() ? 7 : 1; }
+
+template <int MODE, int PM>
+__device__ __forceinline__ void run_mode(const HDX_CONST LeafTask *T, int a, unsigned char *lds, const LdsLayout &Ly) {
+    if (MODE == 3) {
+        run_tile<MarsOps>(T, a, lds, Ly);
+    } else if (MODE == 0 || (MODE == 2 && T->kind == HDX_ROCKSAMPLE)) {
+        run_tile<RsOps>(T, a, lds, Ly);
+    } else {
+        run_ped<PM>(T, a, lds, Ly);
+    }
+}
 
 template <int MODE, int PM>
 __global__ __launch_bounds__(max_threads<MODE>(), min_waves<MODE>()) void expand_tiles(const LeafTask *tasks,
@@ -638,7 +651,7 @@ __global__ __launch_bounds__(max_threads<MODE>(), min_waves<MODE>()) void expand
                                                                                        int32_t xcd_remap) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ int32_t s_tile;
-    const LdsLayout Ly = make_layout(n_max, MODE == 0);
+    const LdsLayout Ly = make_layout(n_max, small_obs_mode<MODE>());
     const int32_t n_tiles = __builtin_amdgcn_readfirstlane(queue->n_tiles);
     int iter = 0;
     for (;;) {
@@ -656,12 +669,7 @@ __global__ __launch_bounds__(max_threads<MODE>(), min_waves<MODE>()) void expand
         if (t >= n_tiles) break;
         const HDX_CONST Tile *tile = (const HDX_CONST Tile *)(tiles + t);
         const HDX_CONST LeafTask *T = (const HDX_CONST LeafTask *)(tasks + tile->leaf);
-        const int a = tile->action;
-        if (MODE == 0 || (MODE == 2 && T->kind == HDX_ROCKSAMPLE)) {
-            run_tile<RsOps>(T, a, lds, Ly);
-        } else if (MODE != 0) {
-            run_ped<PM>(T, a, lds, Ly);
-        }
+        run_mode<MODE, PM>(T, tile->action, lds, Ly);
     }
     if (persistent && threadIdx.x == 0) {
         __threadfence();
@@ -684,7 +692,7 @@ __global__ __launch_bounds__(max_threads<MODE>()) void expand_args(const ArgPack
 #else
     const ArgPack *P = &pack;
 #endif
-    const LdsLayout Ly = make_layout(P->n_max, MODE == 0);
+    const LdsLayout Ly = make_layout(P->n_max, small_obs_mode<MODE>());
     const int n_leaves = P->n_leaves;
     const int n_tiles = P->tile_begin[n_leaves];
     const int t = P->xcd_remap ? remap_xcd((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
@@ -692,12 +700,7 @@ __global__ __launch_bounds__(max_threads<MODE>()) void expand_args(const ArgPack
     int i = 0;
     while (i + 1 < n_leaves && t >= P->tile_begin[i + 1]) ++i;
     const HDX_CONST LeafTask *T = &P->t[i];
-    const int a = t - P->tile_begin[i];
-    if (MODE == 0 || (MODE == 2 && T->kind == HDX_ROCKSAMPLE)) {
-        run_tile<RsOps>(T, a, lds, Ly);
-    } else if (MODE != 0) {
-        run_ped<PM>(T, a, lds, Ly);
-    }
+    run_mode<MODE, PM>(T, t - P->tile_begin[i], lds, Ly);
 }
 
 template <int MODE, int PM>
@@ -711,7 +714,7 @@ hipError_t configure_t() {
 
 template <int MODE, int PM>
 hipError_t launch_args_t(const ArgPack &pack, const Schedule &sch, hipStream_t stream) {
-    const LdsLayout Ly = make_layout(pack.n_max, MODE == 0);
+    const LdsLayout Ly = make_layout(pack.n_max, small_obs_mode<MODE>());
     const int grid = pack.tile_begin[pack.n_leaves];
     if (grid < 1) return hipSuccess;
     const int threads = sch.threads > max_threads<MODE>() ? max_threads<MODE>() : sch.threads;
@@ -722,7 +725,7 @@ hipError_t launch_args_t(const ArgPack &pack, const Schedule &sch, hipStream_t s
 template <int MODE, int PM>
 hipError_t launch_expand_t(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queue, int32_t n_tiles,
                            int32_t n_max, const Schedule &sch, int32_t n_cu, hipStream_t stream) {
-    const LdsLayout Ly = make_layout(n_max, MODE == 0);
+    const LdsLayout Ly = make_layout(n_max, small_obs_mode<MODE>());
     // persistent: a fixed grid that drains the tile queue, so a captured
     // graph stays valid for any tile count
     const int grid = sch.persistent > 0 ? n_cu * sch.persistent : n_tiles;
@@ -750,6 +753,17 @@ __global__ void sample_kernel(const SampleArgs A) {
             if ((uint64_t)word < A.rock_thr[i]) w |= 1 << (10 + i);
         }
         S.w[k] = w;
+    } else if (M->kind == HDX_MARS) {
+        // the robots' row is known; rock i good as for RockSample
+        int32_t rk = 0;
+        uint4 u = make_uint4(0, 0, 0, 0);
+        for (int i = 0; i < M->n_rocks; ++i) {
+            if ((i & 3) == 0) u = philox((uint32_t)k, 0, (uint32_t)(i >> 2), kTagInit, A.k0, A.k1);
+            const uint32_t word = (i & 3) == 0 ? u.x : (i & 3) == 1 ? u.y : (i & 3) == 2 ? u.z : u.w;
+            if ((uint64_t)word < A.rock_thr[i]) rk |= 1 << i;
+        }
+        S.w[k] = A.x0;
+        S.w[S.stride + k] = rk;
     } else {
         S.s[k] = A.s0;
         S.car[k] = A.level0 & 0xff;
@@ -829,15 +843,17 @@ hipError_t launch_fp32_selftest(const float *a, const float *b, const float *c, 
 
 int32_t max_dynamic_lds() { return 160 * 1024 - 256; }
 
-Variant pick_variant(int32_t has_rs, int32_t has_ped, int32_t ped_max, int32_t n_max) {
+Variant pick_variant(int32_t has_rs, int32_t has_ped, int32_t ped_max, int32_t n_max, int32_t has_mars) {
     Variant v;
-    v.mode = !has_ped ? 0 : (has_rs ? 2 : 1);
+    v.mode = has_mars ? 3 : !has_ped ? 0 : (has_rs ? 2 : 1);
     v.pm = !has_ped ? 1 : ped_max <= 8 ? 8 : ped_max <= 16 ? 16 : 32;
     v.n_max = n_max < 1 ? 1 : n_max;
     return v;
 }
 
-int32_t variant_max_threads(const Variant &v) { return v.mode == 0 ? max_threads<0>() : max_threads<1>(); }
+int32_t variant_max_threads(const Variant &v) {
+    return v.mode == 0 ? max_threads<0>() : v.mode == 3 ? max_threads<3>() : max_threads<1>();
+}
 
 hipError_t configure_expand_kernels() {
     hipError_t e = configure_t<0, 1>();
@@ -847,6 +863,7 @@ hipError_t configure_expand_kernels() {
     if (e == hipSuccess) e = configure_t<2, 8>();
     if (e == hipSuccess) e = configure_t<2, 16>();
     if (e == hipSuccess) e = configure_t<2, 32>();
+    if (e == hipSuccess) e = configure_t<3, 1>();
     return e;
 }
 
@@ -854,6 +871,7 @@ hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue
                          const Variant &v, const Schedule &sch, int32_t n_cu, hipStream_t stream) {
 #define HDX_LAUNCH(M, P) launch_expand_t<M, P>(d_tasks, d_tiles, d_queue, n_tiles, v.n_max, sch, n_cu, stream)
     if (v.mode == 0) return HDX_LAUNCH(0, 1);
+    if (v.mode == 3) return HDX_LAUNCH(3, 1);
     if (v.mode == 1) return v.pm == 8 ? HDX_LAUNCH(1, 8) : v.pm == 16 ? HDX_LAUNCH(1, 16) : HDX_LAUNCH(1, 32);
     return v.pm == 8 ? HDX_LAUNCH(2, 8) : v.pm == 16 ? HDX_LAUNCH(2, 16) : HDX_LAUNCH(2, 32);
 #undef HDX_LAUNCH
@@ -862,6 +880,7 @@ hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue
 hipError_t launch_expand_args(const ArgPack &pack, const Variant &v, const Schedule &sch, hipStream_t stream) {
 #define HDX_LAUNCH(M, P) launch_args_t<M, P>(pack, sch, stream)
     if (v.mode == 0) return HDX_LAUNCH(0, 1);
+    if (v.mode == 3) return HDX_LAUNCH(3, 1);
     if (v.mode == 1) return v.pm == 8 ? HDX_LAUNCH(1, 8) : v.pm == 16 ? HDX_LAUNCH(1, 16) : HDX_LAUNCH(1, 32);
     return v.pm == 8 ? HDX_LAUNCH(2, 8) : v.pm == 16 ? HDX_LAUNCH(2, 16) : HDX_LAUNCH(2, 32);
 #undef HDX_LAUNCH
@@ -880,6 +899,8 @@ hipError_t launch_bounds(const BoundsArgs &args, int32_t kind, int32_t n_peds, h
     if (blocks == 0) return hipSuccess;
     if (kind == HDX_ROCKSAMPLE) {
         hipLaunchKernelGGL(bounds_kernel<RsOps>, dim3((unsigned)blocks), dim3(threads), 0, stream, args);
+    } else if (kind == HDX_MARS) {
+        hipLaunchKernelGGL(bounds_kernel<MarsOps>, dim3((unsigned)blocks), dim3(threads), 0, stream, args);
     } else if (n_peds <= 8) {
         hipLaunchKernelGGL(bounds_kernel<PedOps<8>>, dim3((unsigned)blocks), dim3(threads), 0, stream, args);
     } else if (n_peds <= 16) {

@@ -229,6 +229,174 @@ struct RsOps {
 };
 
 // ---------------------------------------------------------------------------
+// Multi-agent RockSample: two robots share the rocks.  Two int32 rows per
+// scenario: the robots' row (robot 1's cell in bits 0-9, robot 2's in bits
+// 10-19, x in the low five bits of each; robot j gone in bit 20+j; terminal
+// in bit 30) and the rocks' row (rock i's quality in bit i), at w[k] and
+// w[stride + k].  Joint action a = a1 (5+m) + a2; robot 1 acts first, then
+// robot 2 on the rocks robot 1 left; robot j's sensor reads word j of the
+// step block; the joint observation is 3 z1 + z2.
+// ---------------------------------------------------------------------------
+struct MarsOps {
+    struct State {
+        int32_t p, rk;
+    };
+    static constexpr bool kHashObs = false;
+    static constexpr bool kSplitRollout = true;
+    static constexpr bool kSmallObs = true;  // 9 joint observations
+    static constexpr bool kLdsModel = false;
+    static constexpr bool kWaveUpper = true;
+    static constexpr int kGone0 = 20, kTerm = 30;
+    static constexpr int kFar = 62;  // beyond any Manhattan distance on a 31 x 31 grid
+
+    __device__ static void load(const MView &, const StatesPtr &S, int64_t p, State &st) {
+        st.p = S.w[p];
+        st.rk = S.w[S.stride + p];
+    }
+    __device__ static void make_terminal(State &st) {
+        st.p = (1 << kTerm) | (3 << kGone0);
+        st.rk = 0;
+    }
+    __device__ static void store(const MView &, const StatesPtr &S, int64_t p, const State &st) {
+        S.w[p] = st.p;
+        S.w[S.stride + p] = st.rk;
+    }
+    __device__ static bool terminal(const State &st) { return (st.p >> kTerm) & 1; }
+
+    // Robot J's own action b (numbered as in RockSample); returns its reward.
+    template <int J, bool kObs>
+    __device__ static float act(const MView &M, State &st, int b, uint32_t word, int &zj) {
+        zj = 0;
+        int32_t p = st.p;
+        if ((p >> (kGone0 + J)) & 1) return 0.0f;  // this robot has left the map
+        constexpr int sh = 10 * J;
+        int x = (p >> sh) & 31, y = (p >> (sh + 5)) & 31;
+        const int n = M.h->grid;
+        float r = 0.0f;
+        if (b == 0) {
+            if (y + 1 < n) ++y;
+        } else if (b == 1) {
+            if (y > 0) --y;
+        } else if (b == 2) {
+            if (x + 1 == n) {
+                r = 10.0f;
+                p |= 1 << (kGone0 + J);
+            } else {
+                ++x;
+            }
+        } else if (b == 3) {
+            if (x > 0) --x;
+        } else if (b == 4) {
+            int i = -1;
+            for (int q = 0; q < M.h->n_rocks; ++q)
+                if (M.h->rock_x[q] == x && M.h->rock_y[q] == y) i = q;
+            if (i >= 0) {
+                if ((st.rk >> i) & 1) {
+                    r = 10.0f;
+                    st.rk &= ~(1 << i);
+                } else {
+                    r = -10.0f;
+                }
+            }
+        } else if (kObs) {
+            const int i = b - 5;
+            const int dx = x - M.h->rock_x[i], dy = y - M.h->rock_y[i];
+            const int correct = word <= M.thr[dx * dx + dy * dy];
+            const int truth = (st.rk >> i) & 1;
+            zj = (correct ? truth : !truth) ? 1 : 2;
+        }
+        st.p = (p & ~(0x3ff << sh)) | ((x | (y << 5)) << sh);
+        return r;
+    }
+
+    template <bool kObs>
+    __device__ static void step(const MView &M, State &st, int a, uint32_t id, uint32_t depth, uint32_t k0,
+                                uint32_t k1, float &r, uint64_t &z) {
+        r = 0.0f;
+        z = 0;
+        if ((st.p >> kTerm) & 1) return;  // absorbing
+        const int per = 5 + M.h->n_rocks;
+        const int a1 = a / per, a2 = a - a1 * per;
+        uint32_t w0 = 0, w1 = 0;
+        if (kObs && (a1 >= 5 || a2 >= 5)) {
+            // a sense's reading is only drawn when the observation is wanted
+            const uint4 u = philox(id, depth, 0, kTagStep, k0, k1);
+            w0 = u.x;
+            w1 = u.y;
+        }
+        int z1, z2;
+        const float r1 = act<0, kObs>(M, st, a1, w0, z1);
+        const float r2 = act<1, kObs>(M, st, a2, w1, z2);
+        r = r1 + r2;
+        z = (uint64_t)(3 * z1 + z2);
+        if (((st.p >> kGone0) & 3) == 3) st.p |= 1 << kTerm;
+    }
+
+    // Distance from the nearer robot still on the map to cell (rx, ry).
+    __device__ static int near(int32_t p, int rx, int ry) {
+        const int d0 = ((p >> kGone0) & 1) ? kFar : abs((p & 31) - rx) + abs(((p >> 5) & 31) - ry);
+        const int d1 = ((p >> (kGone0 + 1)) & 1) ? kFar : abs(((p >> 10) & 31) - rx) + abs(((p >> 15) & 31) - ry);
+        return d0 < d1 ? d0 : d1;
+    }
+
+    // Every good rock sampled by the nearer robot on arrival, plus each
+    // robot's exit reward at its shortest exit time (rocks in index order,
+    // then robot 1's exit, then robot 2's).
+    __device__ static float upper(const MView &M, const State &st) {
+        if ((st.p >> kTerm) & 1) return 0.0f;
+        float u = 0.0f;
+        for (int i = 0; i < M.h->n_rocks; ++i)
+            if ((st.rk >> i) & 1) u += 10.0f * M.gg[near(st.p, M.h->rock_x[i], M.h->rock_y[i])];
+        const int n1 = M.h->grid - 1;
+        if (!((st.p >> kGone0) & 1)) u += 10.0f * M.gg[n1 - (st.p & 31)];
+        if (!((st.p >> (kGone0 + 1)) & 1)) u += 10.0f * M.gg[n1 - ((st.p >> 10) & 31)];
+        return u;
+    }
+
+    struct WaveUpper {
+        int32_t p = -1;
+        float ci = 0.0f, e0 = 0.0f, e1 = 0.0f;
+    };
+
+    // The same value, bit for bit.  Robot cells are deterministic, so the
+    // live scenarios of a tile usually share the robots' row: then lane i
+    // holds rock i's term for the wavefront and every lane masks the terms
+    // of its bad rocks to +0, as RockSample's bound does; a robot that has
+    // left adds +0 for its exit.  Called by all 64 lanes of a wavefront.
+    __device__ static float upper_wave(const MView &M, const State &st, WaveUpper &wu) {
+        const bool live = !((st.p >> kTerm) & 1);
+        const uint64_t lv = __ballot(live);
+        if (lv == 0) return 0.0f;
+        const int leader = __ffsll((unsigned long long)lv) - 1;
+        const int32_t p0 = __shfl(st.p, leader, 64);
+        if (__ballot(live && st.p != p0) != 0) return upper(M, st);
+        const int32_t ps = __builtin_amdgcn_readfirstlane(p0);
+        const int nr = M.h->n_rocks;
+        if (ps != wu.p) {
+            const int lane = (int)__lane_id();
+            wu.ci = lane < nr ? 10.0f * M.gg[near(ps, M.h->rock_x[lane], M.h->rock_y[lane])] : 0.0f;
+            const int n1 = M.h->grid - 1;
+            wu.e0 = ((ps >> kGone0) & 1) ? 0.0f : 10.0f * M.gpow_uniform(n1 - (ps & 31));
+            wu.e1 = ((ps >> (kGone0 + 1)) & 1) ? 0.0f : 10.0f * M.gpow_uniform(n1 - ((ps >> 10) & 31));
+            wu.p = ps;
+        }
+        float u = 0.0f;
+        for (int i = 0; i < nr; ++i) {
+            const int c = __builtin_amdgcn_readlane(__float_as_int(wu.ci), i);
+            const int keep = __builtin_amdgcn_sbfe(st.rk, i, 1);  // all ones if rock i is good
+            u = u + __int_as_float(keep & c);
+        }
+        u = u + wu.e0;
+        u = u + wu.e1;
+        return live ? u : 0.0f;
+    }
+
+    __device__ static int default_action(const MView &M, const State &) {
+        return 2 * (5 + M.h->n_rocks) + 2;  // both robots move east
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Crowd driving: car (position, speed level, terminal) and up to PM
 // pedestrians held in registers.
 // ---------------------------------------------------------------------------

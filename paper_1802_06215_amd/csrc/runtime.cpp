@@ -147,12 +147,13 @@ hdx_status hdx_upload_model(hdx_ctx *ctx, const hdx_model_desc *d, hdx_model **o
     memset(dm, 0, sizeof(DevModel));
     ModelHdr *h = &dm->h;
     h->kind = d->kind;
-    if (d->kind == HDX_ROCKSAMPLE) {
-        if (d->grid < 1 || d->grid > kMaxGrid || d->n_rocks < 0 || d->n_rocks > kMaxRocks) {
+    if (d->kind == HDX_ROCKSAMPLE || d->kind == HDX_MARS) {
+        const int g_min = d->kind == HDX_MARS ? 2 : 1;
+        if (d->grid < g_min || d->grid > kMaxGrid || d->n_rocks < 0 || d->n_rocks > kMaxRocks) {
             delete dm;
-            return fail(ctx, HDX_E_SHAPE, "grid must be 1..31 and rocks 0..20");
+            return fail(ctx, HDX_E_SHAPE, "grid must be 1..31 (2..31 for two robots) and rocks 0..20");
         }
-        h->n_actions = 5 + d->n_rocks;
+        h->n_actions = d->kind == HDX_MARS ? (5 + d->n_rocks) * (5 + d->n_rocks) : 5 + d->n_rocks;
         h->grid = d->grid;
         h->n_rocks = d->n_rocks;
         std::vector<int8_t> rock_at(kMaxGrid * kMaxGrid, -1);
@@ -265,6 +266,7 @@ extern "C" {
 int32_t hdx_model_max_children(const hdx_model *m, int32_t n) {
     if (!m || n < 0) return -1;
     if (m->desc.kind == HDX_ROCKSAMPLE) return n < 3 ? n : 3;  // none, good, bad
+    if (m->desc.kind == HDX_MARS) return n < 9 ? n : 9;        // one reading per robot
     return n;                                                  // hashed observations
 }
 
@@ -282,6 +284,7 @@ static StatesPtr to_ptr(const hdx_states &s) {
 
 static bool states_ok(const hdx_model *m, const hdx_states &s, int64_t n) {
     if (m->desc.kind == HDX_ROCKSAMPLE) return s.w != nullptr;
+    if (m->desc.kind == HDX_MARS) return s.w != nullptr && s.stride >= n;
     if (!s.s || !s.car) return false;
     if (m->desc.n_peds > 0 && (!s.px || !s.py || !s.goal || s.stride < n)) return false;
     return true;
@@ -305,6 +308,13 @@ hdx_status hdx_sample_scenarios(hdx_ctx *ctx, const hdx_model *m, const hdx_beli
         if (d.n_rocks > 0 && !b->p_good) return fail(ctx, HDX_E_INVALID, "p_good is null");
         A.x0 = b->x;
         A.y0 = b->y;
+        for (int i = 0; i < d.n_rocks; ++i) A.rock_thr[i] = prob_threshold(b->p_good[i]);
+    } else if (d.kind == HDX_MARS) {
+        if (b->x < 0 || b->x >= d.grid || b->y < 0 || b->y >= d.grid || b->x2 < 0 || b->x2 >= d.grid ||
+            b->y2 < 0 || b->y2 >= d.grid || b->gone < 0 || b->gone > 3)
+            return fail(ctx, HDX_E_INVALID, "robot cells");
+        if (d.n_rocks > 0 && !b->p_good) return fail(ctx, HDX_E_INVALID, "p_good is null");
+        A.x0 = b->x | (b->y << 5) | (b->x2 << 10) | (b->y2 << 15) | (b->gone << 20) | (b->gone == 3 ? 1 << 30 : 0);
         for (int i = 0; i < d.n_rocks; ++i) A.rock_thr[i] = prob_threshold(b->p_good[i]);
     } else {
         if (d.n_peds > 0 && (!b->px || !b->py || !b->goal_p)) return fail(ctx, HDX_E_INVALID, "belief arrays");
@@ -346,7 +356,7 @@ namespace {
 
 struct Shape {
     int64_t n_tiles = 0;
-    int32_t n_max = 1, has_rs = 0, has_ped = 0, ped_max = 0;
+    int32_t n_max = 1, has_rs = 0, has_ped = 0, ped_max = 0, has_mars = 0;
 };
 
 hdx_status validate_leaves(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves, Shape *sh) {
@@ -381,6 +391,8 @@ hdx_status validate_leaves(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
         if (d.kind == HDX_PEDNAV) {
             s.has_ped = 1;
             if (d.n_peds > s.ped_max) s.ped_max = d.n_peds;
+        } else if (d.kind == HDX_MARS) {
+            s.has_mars = 1;
         } else {
             s.has_rs = 1;
         }
@@ -429,7 +441,8 @@ void pack_leaves(const hdx_leaf *leaves, int32_t n_leaves, LeafTask *tasks, Tile
         T.U = L.U;
         T.L = L.L;
         T.child_of = L.child_of;
-        for (int a = 0; a < T.n_actions; ++a) tiles[t++] = Tile{i, a};
+        if (tiles)
+            for (int a = 0; a < T.n_actions; ++a) tiles[t++] = Tile{i, a};
     }
 }
 
@@ -496,7 +509,7 @@ Schedule hdx::class_default_schedule(int32_t n_max, int32_t max_threads, int32_t
     s.threads = std::min(std::max(64, pow2_at_least(std::max(n_max, 1)) / 2), std::min(256, max_threads));
     s.persistent = 0;
     s.xcd_remap = mode < 0 ? 1 : 0;
-    if (mode == 0) s.threads = 64;
+    if (mode == 0 || mode == 3) s.threads = 64;
     // latency form: one scenario per lane where the model's width allows
     if (mode == -2) s.threads = std::min(std::max(64, pow2_at_least(std::max(n_max, 1))), max_threads);
     return s;
@@ -589,14 +602,14 @@ hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
     hdx_status st = validate_leaves(ctx, leaves, n_leaves, &sh);
     if (st != HDX_OK || n_leaves == 0) return st;
     hipSetDevice(ctx->device);
-    const Variant v0 = pick_variant(sh.has_rs, sh.has_ped, sh.ped_max, sh.n_max);
-    if (n_leaves <= kArgLeaves) {
-        // small calls carry their descriptors in the kernel arguments
+    const Variant v0 = pick_variant(sh.has_rs, sh.has_ped, sh.ped_max, sh.n_max, sh.has_mars);
+    if (n_leaves <= kArgLeaves && !(sh.has_mars && (sh.has_rs || sh.has_ped))) {
+        // small calls of one kernel variant carry their descriptors in the
+        // kernel arguments (the multi-agent model has a kernel of its own)
         static_assert(sizeof(ArgPack) <= 4096, "kernel argument pack too large");
         ArgPack pack;
         memset(&pack, 0, sizeof(pack));
-        Tile tiles[kArgLeaves * (kMaxRocks + 5)];
-        pack_leaves(leaves, n_leaves, pack.t, tiles);
+        pack_leaves(leaves, n_leaves, pack.t, nullptr);
         pack.tile_begin[0] = 0;
         for (int32_t i = 0; i < n_leaves; ++i) pack.tile_begin[i + 1] = pack.tile_begin[i] + pack.t[i].n_actions;
         pack.n_leaves = n_leaves;

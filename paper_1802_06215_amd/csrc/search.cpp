@@ -57,6 +57,8 @@ RecLayout rec_layout(const hdx_model_desc &d, int n, int cap) {
     L.w = L.s = L.car = L.px = L.py = L.goal = 0;
     if (d.kind == HDX_ROCKSAMPLE) {
         L.w = take(4ull * n);
+    } else if (d.kind == HDX_MARS) {
+        L.w = take(8ull * n);  // robots' row, then rocks' row
     } else {
         L.s = take(4ull * n);
         L.car = take(4ull * n);
@@ -106,7 +108,7 @@ struct Request {
 hdx_states rec_states(const hdx_model_desc &d, const Rec &r) {
     hdx_states s;
     memset(&s, 0, sizeof(s));
-    if (d.kind == HDX_ROCKSAMPLE) {
+    if (d.kind == HDX_ROCKSAMPLE || d.kind == HDX_MARS) {
         s.w = (int32_t *)(r.dev + r.L.w);
     } else {
         s.s = (float *)(r.dev + r.L.s);
@@ -584,7 +586,7 @@ extern "C" hdx_status hdx_search(hdx_ctx *ctx, const hdx_model *model, const hdx
     if (!ctx || !model || !belief || !cfg || !out) return HDX_E_INVALID;
     const int A = hdx_model_actions(model);
     if (cfg->K < 1 || cfg->K > HDX_MAX_LEAF_SCENARIOS || cfg->n_threads < 1 || cfg->n_threads > 64 ||
-        cfg->max_depth < 1 || cfg->arena_bytes < (1 << 20) || A > HDX_MAX_ROCKS + 5)
+        cfg->max_depth < 1 || cfg->arena_bytes < (1 << 20) || A > HDX_MAX_ACTIONS)
         return HDX_E_INVALID;
     Search S;
     S.ctx = ctx;

@@ -16,10 +16,11 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libhdx.so")
 
-ROCKSAMPLE, PEDNAV = 0, 1
+ROCKSAMPLE, PEDNAV, MARS = 0, 1, 2
+MAX_ACTIONS = 625  # HDX_MAX_ACTIONS
 POLICY_DEFAULT, POLICY_CONST, POLICY_RANDOM = 0, 1, 2
 SIZE_CLASSES = 6
-LAUNCH_GROUPS = 24  # model variant (RockSample; driving <= 8, 16, 32 pedestrians) x size class
+LAUNCH_GROUPS = 30  # model variant (RockSample; driving <= 8, 16, 32 pedestrians; multi-agent) x size class
 MAX_LEAF_SCENARIOS = 2048
 MAX_HORIZON = 4096
 
@@ -49,7 +50,7 @@ class ModelDesc(C.Structure):
 class Belief(C.Structure):
     _fields_ = [("x", C.c_int32), ("y", C.c_int32), ("p_good", C.c_void_p),
                 ("s", C.c_float), ("level", C.c_int32), ("px", C.c_void_p), ("py", C.c_void_p),
-                ("goal_p", C.c_void_p)]
+                ("goal_p", C.c_void_p), ("x2", C.c_int32), ("y2", C.c_int32), ("gone", C.c_int32)]
 
 
 class RolloutCfg(C.Structure):
@@ -78,7 +79,7 @@ class SearchResult(C.Structure):
                 ("idle_trials", C.c_int64),
                 ("expansions", C.c_int64), ("nodes", C.c_int64), ("scenario_steps", C.c_int64),
                 ("launches", C.c_int64), ("max_depth_reached", C.c_int32), ("arena_full", C.c_int32),
-                ("elapsed_s", C.c_double), ("action_l", C.c_double * 25), ("action_u", C.c_double * 25),
+                ("elapsed_s", C.c_double), ("action_l", C.c_double * MAX_ACTIONS), ("action_u", C.c_double * MAX_ACTIONS),
                 ("judged_leaves", C.c_int64), ("judged_children", C.c_int64), ("judge_mae", C.c_double),
                 ("judge_rel_err", C.c_double), ("surrogate_off", C.c_int32)]
 
@@ -192,7 +193,7 @@ def model_desc(d: dict) -> ModelDesc:
     m.kind = d["kind"]
     m.n_actions = d["n_actions"]
     m.gamma = d["gamma"]
-    if d["kind"] == ROCKSAMPLE:
+    if d["kind"] in (ROCKSAMPLE, MARS):
         m.grid, m.n_rocks = d["n"], d["m"]
         for i in range(d["m"]):
             m.rock_x[i], m.rock_y[i] = int(d["rock_x"][i]), int(d["rock_y"][i])
@@ -230,6 +231,11 @@ def states_view(model: Model, st: dict) -> States:
     if model.kind == ROCKSAMPLE:
         v.w = _dp(st["w"])
         v.stride = st["w"].shape[-1]
+    elif model.kind == MARS:
+        # rows of [2, n]: the robots' row, then the rocks' row
+        assert st["w"].dim() == 2 and st["w"].shape[0] == 2 and st["w"].stride(1) == 1
+        v.w = _dp(st["w"])
+        v.stride = st["w"].stride(0)
     else:
         v.s, v.car = _dp(st["s"]), _dp(st["car"])
         if model.n_peds > 0:
@@ -243,6 +249,8 @@ def states_view(model: Model, st: dict) -> States:
 def empty_states(model: Model, n: int, device="cuda") -> dict:
     if model.kind == ROCKSAMPLE:
         return dict(w=torch.empty(n, dtype=torch.int32, device=device))
+    if model.kind == MARS:
+        return dict(w=torch.empty((2, n), dtype=torch.int32, device=device))
     P = model.n_peds
     return dict(s=torch.empty(n, dtype=torch.float32, device=device),
                 car=torch.empty(n, dtype=torch.int32, device=device),
@@ -303,6 +311,8 @@ def leaf_buffer_slab(model: Model, count: int, n_max: int, device="cuda") -> lis
                  steps=torch.empty((count, A, 2), dtype=torch.int64, device=device))
     if model.kind == ROCKSAMPLE:
         st = dict(w=torch.empty((count, n1), dtype=i32, device=device))
+    elif model.kind == MARS:
+        st = dict(w=torch.empty((count, 2, n1), dtype=i32, device=device))
     else:
         P = model.n_peds
         st = dict(s=torch.empty((count, n1), dtype=f32, device=device),
@@ -329,6 +339,20 @@ def rocksample_states(x, y, rocks, term, device="cuda") -> dict:
     w |= (rocks.astype(np.int64) << (10 + np.arange(rocks.shape[1]))).sum(1) if rocks.shape[1] else 0
     w |= np.asarray(term, dtype=np.int64) << 30
     return dict(w=torch.from_numpy(w.astype(np.int32)).to(device))
+
+
+def mars_states(pos, rocks, term, device="cuda") -> dict:
+    """Pack multi-agent RockSample fields (pos = (x1, y1, x2, y2, gone1,
+    gone2), each a scalar or per scenario; rock qualities [n, m]; terminal
+    flags) into the library's two-row layout, on the device."""
+    rocks = np.asarray(rocks, dtype=bool)
+    n = rocks.shape[0]
+    x1, y1, x2, y2, g1, g2 = (np.broadcast_to(np.asarray(f, dtype=np.int64), (n,)) for f in pos)
+    row0 = x1 | (y1 << 5) | (x2 << 10) | (y2 << 15) | (g1 << 20) | (g2 << 21)
+    row0 = row0 | (np.asarray(term, dtype=np.int64) << 30)
+    row1 = (rocks.astype(np.int64) << np.arange(rocks.shape[1])).sum(1) if rocks.shape[1] else np.zeros(n, np.int64)
+    w = np.stack([row0, row1]).astype(np.int32)
+    return dict(w=torch.from_numpy(w).to(device))
 
 
 def pednav_states(s, level, term, px, py, goal, device="cuda") -> dict:
@@ -450,6 +474,11 @@ class Context:
             p = np.ascontiguousarray(belief["p"], dtype=np.float64)
             keep.append(p)
             b.x, b.y, b.p_good = belief["x"], belief["y"], p.ctypes.data
+        elif model.kind == MARS:
+            p = np.ascontiguousarray(belief["p"], dtype=np.float64)
+            keep.append(p)
+            x1, y1, x2, y2, g1, g2 = (int(v) for v in belief["pos"])
+            b.x, b.y, b.x2, b.y2, b.gone, b.p_good = x1, y1, x2, y2, g1 | (g2 << 1), p.ctypes.data
         else:
             px = np.ascontiguousarray(belief["px"], dtype=np.float32)
             py = np.ascontiguousarray(belief["py"], dtype=np.float32)
