@@ -15,6 +15,9 @@ Workloads (all synthetic, seeded; see workloads/):
   rs7   RockSample 7x7, 8 rocks, |A|=13, K=100, rollouts of depth 30
   ped16 crowd driving, 16 pedestrians, 5 goals, |A|=3, K=500, rollouts 50
   mix64 64 planner instances (RockSample 7..20 / driving, K in 100..500)
+  mars11, mars15, mars20  multi-agent RockSample (n, n) with n rocks,
+        |A| = 256, 400, 625, K=500, horizon 90, both robots move east in
+        rollouts; 128 leaves with n in {500,250,125,63,32}, depth 1..30
 """
 import argparse
 import json
@@ -30,8 +33,9 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE (scaled by a plain copy of known size), recorded with a hash of
 # the kernel's sources: reported only while those sources are unchanged.
 PROFILED_TRAFFIC = {
-    "rs15": dict(bytes=53.46e6, sha="676abc530adf48eb", summary="profiles/expand_tiles_rs15.md"),
-    "ped16": dict(bytes=75.68e6, sha="676abc530adf48eb", summary="profiles/expand_tiles_ped16.md"),
+    "rs15": dict(bytes=53.46e6, sha="4b960a9e693293ad", summary="profiles/expand_tiles_rs15.md"),
+    "ped16": dict(bytes=75.69e6, sha="4b960a9e693293ad", summary="profiles/expand_tiles_ped16.md"),
+    "mars20": dict(bytes=87.69e6, sha="4b960a9e693293ad", summary="profiles/expand_tiles_mars20.md"),
 }
 # the kernel and the host code that orders its tiles (the order decides L2 reuse)
 KERNEL_SOURCES = ("paper_1802_06215_amd/csrc/kernels.hip", "paper_1802_06215_amd/csrc/models.hpp",
@@ -60,7 +64,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rs15", choices=["rs15", "rs7", "ped16", "mix64"])
+    ap.add_argument("--workload", default="rs15", choices=["rs15", "rs7", "ped16", "mix64", "mars11", "mars15", "mars20"])
     ap.add_argument("--leaves", type=int, default=0, help="leaves per batch (0 = workload default)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -70,7 +74,7 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (x3), to scale HBM byte counters")
     ap.add_argument("--search-seconds", type=float, default=1.0,
-                    help="planning budget of each search measurement (rs15 only; 0 = skip)")
+                    help="planning budget of each search measurement (rs15 and marsNN; 0 = skip)")
     ap.add_argument("--schedule", default="", help="threads,persistent,xcd_remap for every size class "
                     "(skips the autotuner)")
     ap.add_argument("--class-schedule", action="append", default=[],
@@ -101,6 +105,11 @@ def rs_ops(m):
     return dict(step=step, sense_extra=PHILOX_OPS + 6, upper=3 + 6 * m, group=12, reduce=3)
 
 
+def mars_ops(m):
+    step = 2 * 8 + 4                          # joint-action decode, then each robot as in RockSample
+    return dict(step=step, sense_extra=PHILOX_OPS + 2 * 6, upper=3 + 6 * m, group=12, reduce=3)
+
+
 def ped_ops(P):
     ped = 30                                  # Irwin-Hall, heading, sqrt, 2 div, rotation, update
     step = (P + 1) * PHILOX_OPS + 6 + P * ped + 5 * P + 3
@@ -111,9 +120,10 @@ def ped_ops(P):
 def algorithmic_ops(desc, n, A, expand_steps, rollout_steps):
     """ALU work of one leaf: update + expansion + bounds + grouping + sums."""
     pairs = n * A
-    if desc["kind"] == 0:
-        c = rs_ops(desc["m"])
-        sense_pairs = n * desc["m"]
+    if desc["kind"] in (0, 2):
+        c = rs_ops(desc["m"]) if desc["kind"] == 0 else mars_ops(desc["m"])
+        # pairs whose action senses (a joint action senses unless both robots move or sample)
+        sense_pairs = n * (desc["m"] if desc["kind"] == 0 else A - 25)
         return (n * c["step"] * A                # update step recomputed per action tile
                 + pairs * (c["step"] + c["upper"] + c["group"] + c["reduce"])
                 + sense_pairs * c["sense_extra"] + rollout_steps * c["step"])
@@ -143,6 +153,14 @@ def build(ctx, args):
             n_leaf = max(1, K >> (i % 5))
             lf = W.rocksample_leaf(desc, K, n_leaf, 1000 + i, depth=1 + i % 30)
             items.append((desc, lf, 7, cfg))
+    elif wl.startswith("mars"):
+        size = int(wl[4:])
+        B = args.leaves or 128
+        desc = W.mars_model(size, size, 1)
+        for i in range(B):
+            n_leaf = max(1, 500 >> (i % 5))
+            lf = W.mars_leaf(desc, 500, n_leaf, 1000 + i, depth=1 + i % 30)
+            items.append((desc, lf, 7, (0, 1 << 30, 90)))
     elif wl == "ped16":
         B = args.leaves or 512
         desc = W.pednav_model(16, 5, 1)
@@ -186,6 +204,8 @@ def build(ctx, args):
             _, lf, seed, cfg = items[k]
             if d["kind"] == 0:
                 par = H.rocksample_states(lf["x"], lf["y"], lf["rocks"], lf["term"])
+            elif d["kind"] == 2:
+                par = H.mars_states(lf["pos"], lf["rocks"], lf["term"])
             else:
                 par = H.pednav_states(lf["s"], lf["level"], lf["term"], lf["px"], lf["py"], lf["goal"])
             pids = torch.from_numpy(lf["ids"].astype(np.int32)).cuda()
@@ -517,7 +537,8 @@ def despot_analogue(desc, seconds, K=500, seed=3, max_depth=90, xi=0.95):
 
     rc = oracle.cfg(0, 1 << 30, max_depth)
     gamma = desc["gamma"]
-    root_states = oracle.sample_scenarios(desc, W.rocksample_belief(desc), K, seed, 0)
+    belief = W.mars_belief(desc) if desc["kind"] == 2 else W.rocksample_belief(desc)
+    root_states = oracle.sample_scenarios(desc, belief, K, seed, 0)
     ids = np.arange(K, dtype=np.uint32)
     U, L, _ = oracle.rollout_bounds(desc, rc, root_states, ids, np.zeros(K, np.int32), seed, 0)
     root = oracle.Node(None, K, U.mean(), L.mean())
@@ -648,18 +669,22 @@ def main():
                     ops_per_launch=int(ops), kernel_ms=round(kernel_ms, 4))
 
     search = None
-    if args.workload == "rs15" and args.search_seconds > 0:
+    if (args.workload == "rs15" or args.workload.startswith("mars")) and args.search_seconds > 0:
         import workloads as W
         desc = items[0][0]
         m = wl["models"][id(desc)]
+        belief = W.mars_belief(desc) if desc["kind"] == 2 else W.rocksample_belief(desc)
+        # node records of 625-action trees hold a 1.25 MB grouping each at
+        # K = 500: give those searches room for a full planning step
+        arena = (48 << 30) if desc["kind"] == 2 else (8 << 30)
         search = []
         # one thread with plain DESPOT choices (c_a = c_o = 0) is the
         # GPU-DESPOT analogue; several threads with Eq. 8-9 the HyP-DESPOT one
         for threads, nb in ((1, 0), (4, 0), (8, 0), (8, 8), (16, 16)):
             extra = dict(c_a=0.0, c_o=0.0) if threads == 1 else {}
-            res = ctx.search(m, W.rocksample_belief(desc), K=500, n_threads=threads, max_depth=90,
+            res = ctx.search(m, belief, K=500, n_threads=threads, max_depth=90,
                              batch_leaves=nb, time_budget_s=args.search_seconds,
-                             rollout=H.rollout_cfg(0, 1 << 30, 90), seed=3, **extra)
+                             rollout=H.rollout_cfg(0, 1 << 30, 90), seed=3, arena_bytes=arena, **extra)
             search.append(dict(threads=threads, leaf_batcher=nb > 0,
                                trials_per_s=round(res["trials"] / res["elapsed_s"], 1),
                                expanding_trials_per_s=round(res["expansions"] / res["elapsed_s"], 1),
@@ -667,7 +692,8 @@ def main():
                                expansions=res["expansions"], launches=res["launches"],
                                scenario_steps_per_s=round(res["scenario_steps"] / res["elapsed_s"], 1),
                                nodes=res["nodes"], depth=res["max_depth_reached"],
-                               root_gap=round(res["u_root"] - res["l_root"], 4)))
+                               root_gap=round(res["u_root"] - res["l_root"], 4),
+                               elapsed_s=round(res["elapsed_s"], 3), arena_full=res["arena_full"]))
             log("search", search[-1])
 
     sur = None
@@ -700,7 +726,12 @@ def main():
                        "%d synthetic leaves",
                  mix64="MIX64: 64 planner instances (RockSample 7..20 / driving, K in {100,200,500}); "
                        "%d leaves in one launch")
-    variants = ("rocksample", "driving<=8", "driving<=16", "driving<=32")
+    for size in (11, 15, 20):
+        names["mars%d" % size] = ("MARS%d leaf expansion: multi-agent RockSample %dx%d, %d rocks, |A|=%d, K=500, "
+                                  "horizon 90, both robots move east in rollouts; %%d synthetic leaves "
+                                  "(n in {500,250,125,63,32}, depth 1..30)" % (size, size, size, size,
+                                                                               (5 + size) ** 2))
+    variants = ("rocksample", "driving<=8", "driving<=16", "driving<=32", "multi-agent rocksample")
     per_class = [dict(model=variants[v], max_n=64 << c, tiles=n, threads=ct, persistent=cp, xcd_remap=cx)
                  for v, c, ct, cp, cx, n in batch.group_schedules()]
     out = dict(metric=METRIC, value=round(value, 1), unit="scenario-steps/s", n_gpus=1, steps=args.steps,
@@ -711,8 +742,10 @@ def main():
                            rollout_steps=roll_steps, split_by_size_class=batch.split(), schedule=per_class,
                            hip_graph=True, autotune_ms=tuned_ms),
                roofline=roofline, cpu_baseline=cpu,
-               search=dict(config="RockSample 15x15, 15 rocks, K=500, max depth 90, %.1f s planning step"
-                           % args.search_seconds, runs=search) if search else None,
+               search=dict(config="%s %dx%d, %d rocks, K=500, max depth 90, %.1f s planning step"
+                           % ("multi-agent RockSample" if items[0][0]["kind"] == 2 else "RockSample",
+                              items[0][0]["n"], items[0][0]["n"], items[0][0]["m"], args.search_seconds),
+                           runs=search) if search else None,
                surrogate=sur)
     print(json.dumps(out), flush=True)
     batch.close()
