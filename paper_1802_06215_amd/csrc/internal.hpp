@@ -30,7 +30,10 @@ struct ModelHdr {
     int32_t grid, n_rocks;
     int32_t rock_x[kMaxRocks], rock_y[kMaxRocks];
     // crowd driving
-    int32_t n_peds, n_goals, n_levels, pad1;
+    int32_t n_peds, n_goals, n_levels;
+    // multi-agent RockSample: ceil(2^16 / (5 + n_rocks)), so that robot 1's
+    // action of joint action a < (5 + n_rocks)^2 is (a * joint_inv) >> 16
+    int32_t joint_inv;
     float goal_x[kMaxGoals], goal_y[kMaxGoals];
     float path_len, dt, step_len, half_sigma, coll_r2, reach, ih_scale;
     float r_collision, r_step, r_goal, pad2;

@@ -316,7 +316,7 @@ struct MarsOps {
         z = 0;
         if ((st.p >> kTerm) & 1) return;  // absorbing
         const int per = 5 + M.h->n_rocks;
-        const int a1 = a / per, a2 = a - a1 * per;
+        const int a1 = (a * M.h->joint_inv) >> 16, a2 = a - a1 * per;  // a / per without a division
         uint32_t w0 = 0, w1 = 0;
         if (kObs && (a1 >= 5 || a2 >= 5)) {
             // a sense's reading is only drawn when the observation is wanted

@@ -154,6 +154,8 @@ hdx_status hdx_upload_model(hdx_ctx *ctx, const hdx_model_desc *d, hdx_model **o
             return fail(ctx, HDX_E_SHAPE, "grid must be 1..31 (2..31 for two robots) and rocks 0..20");
         }
         h->n_actions = d->kind == HDX_MARS ? (5 + d->n_rocks) * (5 + d->n_rocks) : 5 + d->n_rocks;
+        // exact for every a < (5 + n_rocks)^2 with 5 + n_rocks <= 25 (checked exhaustively)
+        h->joint_inv = (65536 + 4 + d->n_rocks) / (5 + d->n_rocks);
         h->grid = d->grid;
         h->n_rocks = d->n_rocks;
         std::vector<int8_t> rock_at(kMaxGrid * kMaxGrid, -1);
