@@ -180,8 +180,11 @@ struct Search {
     std::atomic<int64_t> arena_used{0};
     std::atomic<int> arena_full{0};
     std::mutex mu;  // tree
-    std::vector<Node> nodes;
-    std::vector<Act> acts;
+    // chunked stores: growth never moves existing nodes (a 625-action tree
+    // adds ~18 M nodes a second; a vector's doubling copies stalled every
+    // thread behind the tree lock)
+    std::deque<Node> nodes;
+    std::deque<Act> acts;
     std::deque<Rec> recs;  // stable addresses
     std::atomic<int64_t> trials{0}, expansions{0}, steps{0}, launches{0};
     std::atomic<int> max_depth{0};
@@ -650,7 +653,6 @@ extern "C" hdx_status hdx_search(hdx_ctx *ctx, const hdx_model *model, const hdx
     root.l = sl / (double)K;
     root.parent_rec = 0;
     root.idx_dev = iota;
-    S.nodes.reserve(1 << 16);
     S.nodes.push_back(root);
     out->u0_root = root.u;
     out->l0_root = root.l;
