@@ -16,6 +16,7 @@
 #include <condition_variable>
 #include <deque>
 #include <limits>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -90,6 +91,25 @@ struct Node {
     int32_t visits = 0, vloss = 0;
     int32_t act_begin = -1;
     int32_t rec = -1;
+};
+
+// Append-only store in chunks of 2^16 elements: growth never moves an
+// element (a 625-action tree adds ~20 M nodes a second, and a vector's
+// doubling copies stalled every thread behind the tree lock), and an index
+// costs one shift and one mask.  Guarded by the tree lock like the tree.
+template <class T>
+struct ChunkStore {
+    static constexpr int kShift = 16;
+    static constexpr size_t kMask = (size_t(1) << kShift) - 1;
+    std::vector<std::unique_ptr<T[]>> chunks;
+    size_t n = 0;
+    T &operator[](size_t i) { return chunks[i >> kShift][i & kMask]; }
+    const T &operator[](size_t i) const { return chunks[i >> kShift][i & kMask]; }
+    size_t size() const { return n; }
+    void push_back(const T &v) {
+        if ((n >> kShift) == chunks.size()) chunks.emplace_back(new T[size_t(1) << kShift]);
+        (*this)[n++] = v;
+    }
 };
 
 struct Act {
@@ -180,11 +200,8 @@ struct Search {
     std::atomic<int64_t> arena_used{0};
     std::atomic<int> arena_full{0};
     std::mutex mu;  // tree
-    // chunked stores: growth never moves existing nodes (a 625-action tree
-    // adds ~18 M nodes a second; a vector's doubling copies stalled every
-    // thread behind the tree lock)
-    std::deque<Node> nodes;
-    std::deque<Act> acts;
+    ChunkStore<Node> nodes;
+    ChunkStore<Act> acts;
     std::deque<Rec> recs;  // stable addresses
     std::atomic<int64_t> trials{0}, expansions{0}, steps{0}, launches{0};
     std::atomic<int> max_depth{0};
