@@ -14,7 +14,10 @@ in Python.  States use the library's documented struct-of-arrays layout:
   "px": f32[P, n], "py": f32[P, n], "goal": u8[P, n]}``;
 * multi-agent RockSample: ``{"w": int32[2, n]}``, row 0 the robots (robot 1's
   x, y in bits 0-4, 5-9, robot 2's in bits 10-14, 15-19, robot j gone in bit
-  20+j, terminal in bit 30), row 1 the rocks (rock i's quality in bit i).
+  20+j, terminal in bit 30), row 1 the rocks (rock i's quality in bit i);
+* navigation: ``{"w": int32[5, n]}``, row 0 the robot (x bits 0-3, y bits 4-7,
+  terminal bit 30), rows 1-4 the unknown cells' occupancy (cell i in bit i%32
+  of row 1 + i//32).
 
 Parity pins for every function here live in ``tests/test_oracle_*.py``.
 """
@@ -52,7 +55,9 @@ class _Model(C.Structure):
                 ("path_len", C.c_float), ("dt", C.c_float), ("ped_speed", C.c_float),
                 ("sigma_h", C.c_float), ("coll_radius", C.c_float),
                 ("r_collision", C.c_float), ("r_step", C.c_float), ("r_goal", C.c_float),
-                ("p_fail", C.c_double)]
+                ("p_fail", C.c_double),
+                ("nav_goal_x", C.c_int32), ("nav_wall", C.c_int32), ("nav_gate_x", C.c_int32 * 2),
+                ("nav_cell", C.c_int16 * 256), ("p_err", C.c_double)]
 
 
 class _Cfg(C.Structure):
@@ -155,12 +160,34 @@ def mars_unpack(w) -> dict:
                 gone1=(r0 >> 20) & 1, gone2=(r0 >> 21) & 1, term=(r0 >> 30) & 1, rocks=w[1])
 
 
+def nav_pack(x, y, cells, term) -> np.ndarray:
+    """Navigation states [5, n] from fields: robot x, y (scalars or [n]),
+    unknown-cell occupancy bool [n, U] (U <= 128), terminal flags."""
+    cells = np.asarray(cells, dtype=bool)
+    n = cells.shape[0]
+    out = np.zeros((5, n), dtype=np.int64)
+    out[0] = (np.broadcast_to(np.asarray(x, np.int64), (n,)) | (np.broadcast_to(np.asarray(y, np.int64), (n,)) << 4)
+              | (np.asarray(term, dtype=np.int64) << 30))
+    for i in range(cells.shape[1]):
+        out[1 + i // 32] |= cells[:, i].astype(np.int64) << (i % 32)
+    return out.astype(np.uint32).view(np.int32)
+
+
+def nav_unpack(w) -> dict:
+    w = np.asarray(w).view(np.uint32).astype(np.int64)
+    U = 128
+    cells = np.stack([(w[1 + i // 32] >> (i % 32)) & 1 for i in range(U)], axis=-1).astype(bool)
+    return dict(x=w[0] & 15, y=(w[0] >> 4) & 15, term=(w[0] >> 30) & 1, cells=cells)
+
+
 def parent_states(desc: dict, leaf: dict) -> dict:
     """States dict for a synthetic leaf's parent (fields from ``workloads``)."""
     if desc["kind"] == 0:
         return dict(w=rs_pack(leaf["x"], leaf["y"], leaf["rocks"], leaf["term"]))
     if desc["kind"] == 2:
         return dict(w=mars_pack(leaf["pos"], leaf["rocks"], leaf["term"]))
+    if desc["kind"] == 3:
+        return dict(w=nav_pack(leaf["x"], leaf["y"], leaf["cells"], leaf["term"]))
     car = leaf["level"].astype(np.int32) | (leaf["term"].astype(np.int32) << 8)
     return dict(s=np.ascontiguousarray(leaf["s"], dtype=np.float32), car=car.astype(np.int32),
                 px=np.ascontiguousarray(leaf["px"], dtype=np.float32),
@@ -173,6 +200,8 @@ def empty_states(desc: dict, n: int) -> dict:
         return dict(w=np.zeros(n, np.int32))
     if desc["kind"] == 2:
         return dict(w=np.zeros((2, n), np.int32))
+    if desc["kind"] == 3:
+        return dict(w=np.zeros((5, n), np.int32))
     P = desc["n_peds"]
     return dict(s=np.zeros(n, np.float32), car=np.zeros(n, np.int32),
                 px=np.zeros((P, n), np.float32), py=np.zeros((P, n), np.float32),
@@ -183,7 +212,7 @@ def _soa(desc: dict, st: dict | None, n: int) -> _Soa:
     v = _Soa()
     if st is None:
         return v
-    if desc["kind"] in (0, 2):
+    if desc["kind"] in (0, 2, 3):
         v.w = _ptr(st["w"])
     else:
         v.s, v.car = _ptr(st["s"]), _ptr(st["car"])
@@ -196,8 +225,9 @@ def _check_states(desc, st):
     if desc["kind"] == 0:
         assert st["w"].dtype == np.int32 and st["w"].flags.c_contiguous
         return st["w"].shape[0]
-    if desc["kind"] == 2:
-        assert st["w"].dtype == np.int32 and st["w"].flags.c_contiguous and st["w"].shape[0] == 2
+    if desc["kind"] in (2, 3):
+        assert st["w"].dtype == np.int32 and st["w"].flags.c_contiguous
+        assert st["w"].shape[0] == (2 if desc["kind"] == 2 else 5)
         return st["w"].shape[1]
     n = st["s"].shape[0]
     P = desc["n_peds"]
@@ -212,7 +242,15 @@ def model(desc: dict) -> _Model:
     m.kind = desc["kind"]
     m.n_actions = desc["n_actions"]
     m.gamma = desc["gamma"]
-    if desc["kind"] in (0, 2):
+    if desc["kind"] == 3:
+        m.n = desc["n"]
+        m.p_fail, m.p_err = desc["p_fail"], desc["p_err"]
+        m.nav_goal_x, m.nav_wall = desc["goal_x"], desc["wall"]
+        m.nav_gate_x[0], m.nav_gate_x[1] = int(desc["gate_x"][0]), int(desc["gate_x"][1])
+        cell = np.asarray(desc["cell"], np.int64).reshape(-1)
+        for c in range(cell.shape[0]):
+            m.nav_cell[c] = int(cell[c])
+    elif desc["kind"] in (0, 2):
         m.n, m.m = desc["n"], desc["m"]
         for i in range(desc["m"]):
             m.rock_x[i] = int(desc["rock_x"][i])
@@ -263,6 +301,10 @@ def sample_scenarios(desc, belief, K, seed, step_idx):
         p = np.ascontiguousarray(belief["p"], dtype=np.float64)
         lib().or_sample_scenarios(C.byref(M), K, seed, step_idx, belief["x"], belief["y"], _ptr(p),
                                   0.0, 0, None, None, None, C.byref(_soa(desc, out, K)))
+    elif desc["kind"] == 3:
+        p = np.ascontiguousarray(belief["p"], dtype=np.float64)
+        lib().or_sample_scenarios(C.byref(M), K, seed, step_idx, 0, 0, _ptr(p),
+                                  0.0, 0, None, None, None, C.byref(_soa(desc, out, K)))
     elif desc["kind"] == 2:
         p = np.ascontiguousarray(belief["p"], dtype=np.float64)
         row0 = int(mars_pack(belief["pos"], np.zeros((1, 0), bool))[0, 0])
@@ -303,6 +345,8 @@ def max_children(desc: dict, n: int) -> int:
     to one per scenario."""
     if desc["kind"] == 2:
         return min(n, 9)
+    if desc["kind"] == 3:
+        return min(n, 257)  # eight neighbour bits, or the terminal reading
     return min(n, 3) if desc["kind"] == 0 else n
 
 
@@ -348,8 +392,8 @@ def expand_leaf(desc, rcfg, parent, parent_ids, idx, depth, last_action, seed, s
         sp = res["sprime"]
         if desc["kind"] == 0:
             sp["w"] = sp["w"].reshape(A, n)
-        elif desc["kind"] == 2:
-            sp["w"] = sp["w"].reshape(2, A, n)
+        elif desc["kind"] in (2, 3):
+            sp["w"] = sp["w"].reshape(sp["w"].shape[0], A, n)
         else:
             P = desc["n_peds"]
             sp["s"], sp["car"] = sp["s"].reshape(A, n), sp["car"].reshape(A, n)
@@ -367,7 +411,7 @@ def take_states(desc: dict, st: dict, positions) -> dict:
     positions = np.asarray(positions, dtype=np.int64)
     if desc["kind"] == 0:
         return dict(w=np.ascontiguousarray(st["w"][positions]))
-    if desc["kind"] == 2:
+    if desc["kind"] in (2, 3):
         return dict(w=np.ascontiguousarray(st["w"][:, positions]))
     return dict(s=np.ascontiguousarray(st["s"][positions]),
                 car=np.ascontiguousarray(st["car"][positions]),

@@ -95,7 +95,7 @@ static uint64_t prob_threshold(double p)
 #define OR_MAX_GOALS 8
 
 typedef struct {
-    int32_t kind; /* 0: RockSample, 1: crowd driving, 2: multi-agent RockSample */
+    int32_t kind; /* 0: RockSample, 1: crowd driving, 2: multi-agent RockSample, 3: navigation */
     int32_t n_actions;
     double gamma;
     /* RockSample */
@@ -107,6 +107,10 @@ typedef struct {
     float path_len, dt, ped_speed, sigma_h, coll_radius;
     float r_collision, r_step, r_goal;
     double p_fail;
+    /* navigation (also uses n, gamma, p_fail) */
+    int32_t nav_goal_x, nav_wall, nav_gate_x[2];
+    int16_t nav_cell[256]; /* [y * n + x]: -1 known free, -2 known wall, >= 0 unknown cell index */
+    double p_err;          /* per-neighbour sensor error */
 } or_model;
 
 typedef struct {
@@ -120,6 +124,7 @@ typedef struct {
 typedef struct {
     int32_t w;  /* RockSample: packed word; multi-agent: the robots' row */
     int32_t w2; /* multi-agent RockSample: the rocks' row */
+    int32_t nw[4]; /* navigation: unknown cells' occupancy, cell i in bit i%32 of nw[i/32] */
     float s;   /* crowd driving: car position along the path */
     int32_t level;
     int32_t term;
@@ -147,6 +152,10 @@ static void load_state(const or_model *M, const or_soa *A, int64_t k, or_state *
         st->w = A->w[k];
         st->w2 = A->w[A->stride + k];
         st->term = (st->w >> 30) & 1;
+    } else if (M->kind == 3) {
+        st->w = A->w[k];
+        for (int j = 0; j < 4; j++) st->nw[j] = A->w[(1 + j) * A->stride + k];
+        st->term = (st->w >> 30) & 1;
     } else {
         st->s = A->s[k];
         st->level = A->car[k] & 0xff;
@@ -166,6 +175,9 @@ static void store_state(const or_model *M, const or_soa *A, int64_t k, const or_
     } else if (M->kind == 2) {
         A->w[k] = st->w;
         A->w[A->stride + k] = st->w2;
+    } else if (M->kind == 3) {
+        A->w[k] = st->w;
+        for (int j = 0; j < 4; j++) A->w[(1 + j) * A->stride + k] = st->nw[j];
     } else {
         A->s[k] = st->s;
         A->car[k] = (st->level & 0xff) | (st->term ? 0x100 : 0);
@@ -362,6 +374,117 @@ static double mars_upper(const or_model *M, const or_state *st)
     return u;
 }
 
+/* --- Navigation in a partially known map (Sec. IV-A): an n x n grid
+ *     (13 x 13 in the paper), row 0 at the top.  Cells are known free,
+ *     known walls, or unknown (occupied or not in each scenario; the two
+ *     gates of the middle wall are unknown cells of which exactly one is
+ *     open).  State: robot row word = x in bits 0-3, y in bits 4-7,
+ *     terminal in bit 30; then four words of unknown-cell occupancy.
+ *     Actions: 0 stay, 1-8 move to a neighbour N, NE, E, SE, S, SW, W, NW
+ *     (y grows downwards).  Readings: a move fails (the robot stays) when
+ *     word 0 of step block 0 is below the failure threshold, and still
+ *     costs the motion cost; moving into a wall, an occupied cell or off
+ *     the map is a crash (robot stays, -1); entering the goal pays +20
+ *     instead of the motion cost and ends the episode; staying costs -0.2;
+ *     every other move -0.1.  Observation: one bit per neighbour (in action
+ *     order) after the step, 1 = occupied (off the map reads occupied),
+ *     neighbour j's bit flipped when word j%4 of step block 1 + j/4 is below
+ *     the sensor-error threshold; a terminal state observes 256. */
+#define NAV_TERM 30
+#define NAV_OBS_TERMINAL 256u
+static const int NAV_DX[9] = {0, 0, 1, 1, 1, 0, -1, -1, -1};
+static const int NAV_DY[9] = {0, -1, -1, 0, 1, 1, 1, 0, -1};
+
+/* Occupied in this scenario (off the map counts as occupied). */
+static int nav_occupied(const or_model *M, const or_state *st, int x, int y)
+{
+    if (x < 0 || y < 0 || x >= M->n || y >= M->n) return 1;
+    int c = M->nav_cell[y * M->n + x];
+    if (c == -1) return 0;
+    if (c == -2) return 1;
+    return (st->nw[c / 32] >> (c % 32)) & 1;
+}
+
+static void nav_step(const or_model *M, or_state *st, int a, uint32_t seed, uint32_t step,
+                     uint32_t id, uint32_t depth, float *r, uint64_t *z)
+{
+    *r = 0.0f;
+    *z = NAV_OBS_TERMINAL;
+    if (st->term) return; /* terminal states are absorbing */
+    int x = st->w & 15, y = (st->w >> 4) & 15;
+    uint32_t u[4];
+    draw_block(seed, step, id, depth, 0, TAG_STEP, u);
+    if (a == 0) {
+        *r = -0.2f;
+    } else if ((uint64_t)u[0] < prob_threshold(M->p_fail)) {
+        *r = -0.1f; /* the move fails: the robot stays */
+    } else {
+        int tx = x + NAV_DX[a], ty = y + NAV_DY[a];
+        if (nav_occupied(M, st, tx, ty)) {
+            *r = -1.0f; /* crash: the robot stays */
+        } else {
+            x = tx;
+            y = ty;
+            if (x == M->nav_goal_x && y == M->n - 1) {
+                *r = 20.0f;
+                st->term = 1;
+            } else {
+                *r = -0.1f;
+            }
+        }
+    }
+    st->w = x | (y << 4) | (st->term ? 1 << NAV_TERM : 0);
+    if (st->term) return; /* the world ends: no reading */
+    uint32_t v[8];
+    draw_block(seed, step, id, depth, 1, TAG_STEP, v);
+    draw_block(seed, step, id, depth, 2, TAG_STEP, v + 4);
+    uint64_t obs = 0;
+    for (int j = 0; j < 8; j++) {
+        int bit = nav_occupied(M, st, x + NAV_DX[j + 1], y + NAV_DY[j + 1]);
+        if ((uint64_t)v[j] < prob_threshold(M->p_err)) bit = !bit;
+        obs |= (uint64_t)bit << j;
+    }
+    *z = obs;
+}
+
+/* Optimistic value: the goal reward on the shortest path (Chebyshev
+ * distance d in 8-connected moves, reward on the d-th move, at step d-1),
+ * no costs. */
+static double nav_upper(const or_model *M, const or_state *st)
+{
+    if (st->term) return 0.0;
+    int x = st->w & 15, y = (st->w >> 4) & 15;
+    int dx = abs(x - M->nav_goal_x), dy = abs(y - (M->n - 1));
+    int d = dx > dy ? dx : dy;
+    return 20.0 * pow(M->gamma, d - 1);
+}
+
+/* Default policy: head for the open gate while above the wall, then for the
+ * goal; take the diagonal step towards the target, else its vertical, else
+ * its horizontal part, whichever lands on a free cell; else stay. */
+static int nav_default_action(const or_model *M, const or_state *st)
+{
+    int x = st->w & 15, y = (st->w >> 4) & 15;
+    int tx = M->nav_goal_x, ty = M->n - 1;
+    if (y < M->nav_wall) {
+        int g = ((st->nw[0] >> 0) & 1) == 0 ? 0 : (((st->nw[0] >> 1) & 1) == 0 ? 1 : -1);
+        if (g >= 0) {
+            tx = M->nav_gate_x[g];
+            ty = M->nav_wall;
+        }
+    }
+    int sx = tx > x ? 1 : (tx < x ? -1 : 0), sy = ty > y ? 1 : (ty < y ? -1 : 0);
+    int cand[3][2] = {{sx, sy}, {0, sy}, {sx, 0}};
+    for (int c = 0; c < 3; c++) {
+        int dx = cand[c][0], dy = cand[c][1];
+        if (dx == 0 && dy == 0) continue;
+        if (nav_occupied(M, st, x + dx, y + dy)) continue;
+        for (int a = 1; a < 9; a++)
+            if (NAV_DX[a] == dx && NAV_DY[a] == dy) return a;
+    }
+    return 0;
+}
+
 /* --- Crowd driving: a car along a straight path among pedestrians walking
  *     to hidden goals with noisy headings; accelerate/decelerate fail with a
  *     small probability (Sec. IV-A).  Actions 0 accelerate, 1 maintain,
@@ -501,6 +624,8 @@ static void model_step(const or_model *M, or_state *st, int a, uint32_t seed, ui
         rs_step(M, st, a, seed, step, id, depth, r, z);
     else if (M->kind == 2)
         mars_step(M, st, a, seed, step, id, depth, r, z);
+    else if (M->kind == 3)
+        nav_step(M, st, a, seed, step, id, depth, r, z);
     else
         ped_step(M, st, a, seed, step, id, depth, r, z);
 }
@@ -508,6 +633,7 @@ static void model_step(const or_model *M, or_state *st, int a, uint32_t seed, ui
 static double model_upper(const or_model *M, const or_state *st)
 {
     if (M->kind == 2) return mars_upper(M, st);
+    if (M->kind == 3) return nav_upper(M, st);
     return M->kind == 0 ? rs_upper(M, st) : ped_upper(M, st);
 }
 
@@ -521,6 +647,7 @@ static int policy_action(const or_model *M, const or_rollout_cfg *C, const or_st
         return (int)(u[0] % (uint32_t)M->n_actions);
     }
     if (M->kind == 2) return RS_EAST * (5 + M->m) + RS_EAST; /* both robots move east */
+    if (M->kind == 3) return nav_default_action(M, st);
     return M->kind == 0 ? RS_EAST : ped_default_action(M, st);
 }
 
@@ -568,7 +695,11 @@ void or_step_batch(const or_model *M, const or_soa *in, const uint32_t *ids, int
 /* Draw K start states from the belief (Sec. III-A): scenario k uses counter
  * (k, 0, block, INIT).  RockSample: known cell, rock i good with
  * probability p[i] (word i%4 of block i/4).  Multi-agent RockSample: x0 is
- * the known robots' row, the rocks drawn as for RockSample.  Crowd driving: known car and
+ * the known robots' row, the rocks drawn as for RockSample.  Navigation:
+ * draw k = word k%4 of block k/4; the robot on row 0 at column
+ * floor(draw0 * n / 2^32); gate 0 open (unknown cell 0 free, cell 1
+ * occupied) iff draw1 < 2^31, else the reverse; unknown cell i >= 2
+ * occupied iff draw i is below the threshold of p[i].  Crowd driving: known car and
  * pedestrian positions, pedestrian j's goal drawn from goal_p[j][.]. */
 void or_sample_scenarios(const or_model *M, int32_t K, uint32_t seed, uint32_t step,
                          int32_t x0, int32_t y0, const double *p_good,
@@ -586,6 +717,22 @@ void or_sample_scenarios(const or_model *M, int32_t K, uint32_t seed, uint32_t s
                 if ((uint64_t)u[i % 4] < prob_threshold(p_good[i])) w |= 1 << (10 + i);
             }
             st.w = w;
+        } else if (M->kind == 3) {
+            uint32_t u[4];
+            int nu = 0;
+            for (int c = 0; c < M->n * M->n; c++)
+                if (M->nav_cell[c] >= 0) nu++;
+            draw_block(seed, step, (uint32_t)k, 0, 0, TAG_INIT, u);
+            int x = (int)(((uint64_t)u[0] * (uint64_t)M->n) >> 32);
+            st.w = x;
+            if (u[1] < 0x80000000u)
+                st.nw[0] |= 2; /* gate 0 open, gate 1 closed */
+            else
+                st.nw[0] |= 1;
+            for (int i = 2; i < nu; i++) {
+                if (i % 4 == 0) draw_block(seed, step, (uint32_t)k, 0, (uint32_t)(i / 4), TAG_INIT, u);
+                if ((uint64_t)u[i % 4] < prob_threshold(p_good[i])) st.nw[i / 32] |= 1 << (i % 32);
+            }
         } else if (M->kind == 2) {
             st.w = x0;
             st.term = (x0 >> MARS_TERM) & 1;

@@ -17,6 +17,7 @@ import numpy as np
 ROCKSAMPLE = 0
 PEDNAV = 1
 MARS = 2
+NAV = 3
 
 
 def rocksample_model(n: int, m: int, seed: int, gamma: float = 0.95) -> dict:
@@ -78,6 +79,52 @@ def mars_belief(model: dict, p_good: float = 0.5, pos=None) -> dict:
     if pos is None:
         pos = (*model["start"], 0, 0)
     return dict(pos=tuple(int(v) for v in pos), p=np.full(model["m"], p_good, dtype=np.float64))
+
+
+def nav_model(seed: int, n: int = 13, n_landmarks: int = 8, p_occ: float = 0.1,
+              gamma: float = 0.95) -> dict:
+    """Navigation in a partially known n x n map (Sec. IV-A; 13 x 13 in the paper).
+
+    Row 0 (the top border, where the robot starts at a random column) and
+    row n-1 (the goal's row, goal column seeded) are known free.  The middle
+    row is a known wall except two seeded gate columns, which are unknown
+    cells 0 and 1 (exactly one open).  Of the remaining cells, n_landmarks
+    seeded ones are known walls and the rest are unknown, each occupied with
+    probability p_occ: at n = 13 that is 2 + 122 = 124 unknown cells, the
+    paper's 169 x 2^124 states.  Nine actions (stay, eight neighbours).
+    """
+    if not (5 <= n <= 16):
+        raise ValueError("need 5 <= n <= 16")
+    rng = np.random.default_rng(np.random.SeedSequence([0x4E4156, n, seed]))
+    wall = n // 2
+    cell = np.full((n, n), -1, dtype=np.int64)  # [y][x]
+    cell[wall, :] = -2
+    gates = np.sort(rng.choice(np.arange(1, n - 1), size=2, replace=False))
+    for i, gx in enumerate(gates):
+        cell[wall, gx] = i
+    mid = [(x, y) for y in range(1, n - 1) if y != wall for x in range(n)]
+    order = rng.permutation(len(mid))
+    for j in order[:n_landmarks]:
+        x, y = mid[j]
+        cell[y, x] = -2
+    u = 2
+    for j in np.sort(order[n_landmarks:]):
+        x, y = mid[j]
+        cell[y, x] = u
+        u += 1
+    if u > 128:
+        raise ValueError("more than 128 unknown cells")
+    return dict(kind=NAV, n=n, cell=cell, wall=wall, gate_x=gates.astype(np.int32),
+                goal_x=int(rng.integers(0, n)), n_unknown=u, p_occ=p_occ, gamma=gamma,
+                p_fail=0.03, p_err=0.03, n_actions=9)
+
+
+def nav_belief(model: dict) -> dict:
+    """Initial belief: robot somewhere on the top row, one gate open (1/2
+    each), every other unknown cell occupied with probability p_occ."""
+    p = np.full(model["n_unknown"], model["p_occ"], dtype=np.float64)
+    p[:2] = 0.5
+    return dict(p=p)
 
 
 def pednav_model(n_peds: int, n_goals: int, seed: int, gamma: float = 0.98,
@@ -163,6 +210,39 @@ def mars_leaf(model: dict, n_parent: int, n_leaf: int, seed: int,
                 idx=_sorted_subset(rng, n_parent, n_leaf),
                 depth=int(rng.integers(1, 16)) if depth is None else depth,
                 last_action=int(rng.integers(0, model["n_actions"])))
+
+
+def nav_leaf(model: dict, n_parent: int, n_leaf: int, seed: int, k_root: int | None = None,
+             p_term: float = 0.02, depth: int | None = None, shared_cell: bool = False) -> dict:
+    """A synthetic navigation leaf: robot cells near one another (moves can
+    fail, so a node's scenarios spread out), maps drawn from the prior."""
+    rng = np.random.default_rng(np.random.SeedSequence([0x4E4C46, n_parent, n_leaf, seed]))
+    n, U = model["n"], model["n_unknown"]
+    k_root = max(k_root or n_parent, n_parent)
+    free = [(x, y) for y in range(n) for x in range(n) if model["cell"][y, x] != -2]
+    cx, cy = free[int(rng.integers(0, len(free)))]
+    if shared_cell:
+        x = np.full(n_parent, cx, np.int64)
+        y = np.full(n_parent, cy, np.int64)
+    else:
+        x = np.clip(cx + rng.integers(-1, 2, n_parent), 0, n - 1)
+        y = np.clip(cy + rng.integers(-1, 2, n_parent), 0, n - 1)
+    cells = rng.random((n_parent, U)) < model["p_occ"]
+    g = rng.random(n_parent) < 0.5
+    cells[:, 0], cells[:, 1] = ~g, g
+    # a robot never stands in an occupied cell
+    for k in range(n_parent):
+        c = model["cell"][y[k], x[k]]
+        if c == -2:
+            x[k], y[k] = cx, cy
+            c = model["cell"][cy, cx]
+        if c >= 0:
+            cells[k, c] = False
+    return dict(x=x, y=y, cells=cells, term=rng.random(n_parent) < p_term,
+                ids=_sorted_subset(rng, k_root, n_parent),
+                idx=_sorted_subset(rng, n_parent, n_leaf),
+                depth=int(rng.integers(1, 30)) if depth is None else depth,
+                last_action=int(rng.integers(0, 9)))
 
 
 def pednav_leaf(model: dict, n_parent: int, n_leaf: int, seed: int,
