@@ -57,6 +57,9 @@ typedef int32_t hdx_status;
 #define HDX_ROCKSAMPLE 0
 #define HDX_PEDNAV 1
 #define HDX_MARS 2 /* multi-agent RockSample */
+#define HDX_NAV 3  /* navigation in a partially known map */
+#define HDX_MAX_NAV_GRID 16
+#define HDX_MAX_NAV_UNKNOWN 128
 
 #define HDX_MAX_ROCKS 20
 #define HDX_MAX_ACTIONS 625 /* (5 + HDX_MAX_ROCKS)^2, the multi-agent model's largest */
@@ -87,13 +90,23 @@ typedef void *hdx_stream; /* hipStream_t */
  * earns +10 on leaving through the east border and then does nothing; the
  * world ends when both have left; robot j (0, 1) reads word j of its step's
  * random block for a sense; observation 3 z1 + z2 (9 values); grid >= 2.
+ * Navigation (Sec. IV-A): a grid x grid map (5..16; 13 in the paper), row 0
+ * at the top; nav_cell[y * grid + x] = -1 known free, -2 known wall, or the
+ * index (0..127) of an unknown cell; unknown cells 0 and 1 are the gates of
+ * the wall on row nav_wall (columns nav_gate_x); the goal is
+ * (nav_goal_x, grid - 1).  Actions 0 stay (-0.2), 1-8 move N, NE, E, SE, S,
+ * SW, W, NW (-0.1; y grows downwards); a move fails with p_fail (the robot
+ * stays, still -0.1); a move into a wall, an occupied unknown cell or off
+ * the map is a crash (-1, the robot stays); entering the goal pays +20 and
+ * ends the episode.  Observation: bit j = neighbour j+1 occupied (off the
+ * map reads occupied), each flipped with p_err; 256 once terminal.
  * Crowd driving (Sec. IV-A): straight path of path_len metres, n_levels
  * speed levels, pedestrians walking at ped_speed to one of n_goals goal
  * points with Gaussian heading noise sigma_h; actions 0 accelerate,
  * 1 maintain, 2 decelerate, failing with probability p_fail. */
 typedef struct {
-    int32_t kind;     /* HDX_ROCKSAMPLE, HDX_PEDNAV or HDX_MARS */
-    int32_t n_actions;/* 5 + n_rocks, 3, or (5 + n_rocks)^2 */
+    int32_t kind;     /* HDX_ROCKSAMPLE, HDX_PEDNAV, HDX_MARS or HDX_NAV */
+    int32_t n_actions;/* 5 + n_rocks, 3, (5 + n_rocks)^2, or 9 */
     double gamma;     /* discount */
     int32_t grid, n_rocks;
     int32_t rock_x[HDX_MAX_ROCKS], rock_y[HDX_MAX_ROCKS];
@@ -101,13 +114,19 @@ typedef struct {
     float goal_x[HDX_MAX_GOALS], goal_y[HDX_MAX_GOALS];
     float path_len, dt, ped_speed, sigma_h, coll_radius;
     float r_collision, r_step, r_goal;
-    double p_fail;
+    double p_fail;    /* driving: action failure; navigation: move failure */
+    int32_t nav_goal_x, nav_wall, nav_gate_x[2];
+    int16_t nav_cell[HDX_MAX_NAV_GRID * HDX_MAX_NAV_GRID];
+    double p_err;     /* navigation: per-neighbour reading error */
 } hdx_model_desc;
 
 /* Belief to sample start states from (host memory). */
 typedef struct {
     int32_t x, y;          /* RockSample: known robot cell */
-    const double *p_good;  /* RockSample: [n_rocks] P(rock i good) */
+    const double *p_good;  /* RockSample: [n_rocks] P(rock i good); navigation: [unknown cells]
+                              P(cell occupied), entries 0 and 1 (the gates, one open with
+                              probability 1/2 each) ignored; the robot starts on row 0 at a
+                              uniformly drawn column */
     float s;               /* driving: car position */
     int32_t level;         /* driving: speed level */
     const float *px, *py;  /* driving: [n_peds] pedestrian positions */
@@ -130,7 +149,9 @@ typedef struct {
  * the packed word.  Multi-agent RockSample: w[k] the robots' row (robot 1's
  * x, y in bits 0-4, 5-9, robot 2's in bits 10-14, 15-19, robot j gone in
  * bit 20+j, terminal in bit 30) and w[stride + k] the rocks' row (rock i's
- * quality in bit i).  Driving: s[k], car[k] (speed level | terminal << 8)
+ * quality in bit i).  Navigation: w[k] the robot (x bits 0-3, y bits 4-7,
+ * terminal bit 30), then w[(1 + j) * stride + k], j = 0..3, unknown cell i
+ * occupied in bit i % 32 of row 1 + i / 32.  Driving: s[k], car[k] (speed level | terminal << 8)
  * and px, py, goal [n_peds][stride]. */
 typedef struct {
     int32_t *w;
@@ -249,7 +270,7 @@ hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *batch, const hdx_leaf *
                                 hdx_stream stream);
 /* Launch plan and schedule.  Tiles launch in groups of one model variant
  * (0 RockSample; 1, 2, 3 driving with up to 8, 16, 32 pedestrians; 4
- * multi-agent RockSample), each
+ * multi-agent RockSample; 5 navigation), each
  * group one dispatch with an LDS carve-up and workgroup size for its
  * largest leaf, tiles ordered largest leaf first.  Unsplit (the default):
  * one group per variant, filed under the size class of its largest leaf.
@@ -266,7 +287,7 @@ hdx_status hdx_batch_set_leaves(hdx_ctx *ctx, hdx_batch *batch, const hdx_leaf *
  * get_schedule the group with the most tiles.  Results are bit-identical
  * under every schedule. */
 #define HDX_SIZE_CLASSES 6
-#define HDX_LAUNCH_GROUPS 30
+#define HDX_LAUNCH_GROUPS 36
 hdx_status hdx_batch_set_split(hdx_ctx *ctx, hdx_batch *batch, int32_t split);
 hdx_status hdx_batch_get_split(const hdx_batch *batch, int32_t *split);
 hdx_status hdx_batch_set_schedule(hdx_ctx *ctx, hdx_batch *batch, int32_t threads, int32_t persistent,
@@ -379,7 +400,7 @@ hdx_status hdx_mlp_train_step(hdx_ctx *ctx, hdx_mlp *mlp, const uint16_t *X, con
  * terminal, (horizon - depth)/100, rock qualities, rock offsets dx/n and
  * dy/n; driving s/L, speed level, terminal, (horizon - depth)/100, then per
  * pedestrian (px - s)/10, py/10, goal/n_goals; zero padding to 64.
- * HDX_E_UNSUPPORTED for the multi-agent model (no features defined). */
+ * HDX_E_UNSUPPORTED for the multi-agent and navigation models (no features defined). */
 hdx_status hdx_features(hdx_ctx *ctx, const hdx_model *model, hdx_states states, const int32_t *depths, int64_t n,
                         int32_t horizon, uint16_t *X, hdx_stream stream);
 
@@ -389,7 +410,7 @@ hdx_status hdx_features(hdx_ctx *ctx, const hdx_model *model, hdx_states states,
  * the given horizon), steps[a][1] is 0, and L (if given) receives the
  * surrogate value per (action, scenario).  Scratch for the stepped states,
  * features and values belongs to the MLP handle (grown on demand); calls
- * on one handle are serialised.  HDX_E_UNSUPPORTED for a multi-agent leaf. */
+ * on one handle are serialised.  HDX_E_UNSUPPORTED for a multi-agent or navigation leaf. */
 hdx_status hdx_expand_leaf_surrogate(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves, hdx_mlp *mlp,
                                      int32_t horizon, hdx_stream stream);
 

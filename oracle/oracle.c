@@ -456,7 +456,7 @@ static double nav_upper(const or_model *M, const or_state *st)
     int x = st->w & 15, y = (st->w >> 4) & 15;
     int dx = abs(x - M->nav_goal_x), dy = abs(y - (M->n - 1));
     int d = dx > dy ? dx : dy;
-    return 20.0 * pow(M->gamma, d - 1);
+    return 20.0 * pow(M->gamma, d > 0 ? d - 1 : 0); /* d = 0 (on the goal yet not terminal) is unreachable */
 }
 
 /* Default policy: head for the open gate while above the wall, then for the

@@ -37,7 +37,13 @@ struct ModelHdr {
     float goal_x[kMaxGoals], goal_y[kMaxGoals];
     float path_len, dt, step_len, half_sigma, coll_r2, reach, ih_scale;
     float r_collision, r_step, r_goal, pad2;
-    uint64_t fail_thr;  // action fails iff word < fail_thr
+    uint64_t fail_thr;  // action fails iff word < fail_thr (driving, navigation)
+    // navigation: goal column (on the bottom row), wall row, gate columns,
+    // per cell -1 known free / -2 known wall / unknown cell index, and the
+    // reading error (a neighbour's bit flips iff word < err_thr)
+    int32_t nav_goal_x, nav_wall, nav_gate_x[2];
+    int16_t nav_cell[HDX_MAX_NAV_GRID * HDX_MAX_NAV_GRID];
+    uint64_t err_thr;
 };
 
 constexpr int kGpowLds = 256;
@@ -179,7 +185,8 @@ __host__ __device__ inline LdsLayout make_layout(int32_t np, bool small = false)
 struct Variant {
     int32_t mode, pm, n_max;
 };
-Variant pick_variant(int32_t has_rs, int32_t has_ped, int32_t ped_max, int32_t n_max, int32_t has_mars);
+Variant pick_variant(int32_t has_rs, int32_t has_ped, int32_t ped_max, int32_t n_max, int32_t has_mars,
+                     int32_t has_nav);
 int32_t variant_max_threads(const Variant &v);
 
 // Kernel launchers (kernels.hip).  The expansion kernel reads the tile
@@ -189,7 +196,7 @@ hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue
 
 // Tiles are launched in groups.  A group holds tiles of one model variant
 // (0 RockSample, 1-3 driving with up to 8, 16, 32 pedestrians, 4
-// multi-agent RockSample), so
+// multi-agent RockSample, 5 navigation), so
 // RockSample tiles never run in the register budget of the driving model,
 // and gets an LDS carve-up and workgroup size for its own largest leaf.  By
 // default all leaves of a variant form one group (one dispatch, no fork and
@@ -204,7 +211,7 @@ hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue
 // owns tiles [begin[g], begin[g] + count[g]) and the queue d_queues[g].
 constexpr int kSizeClasses = 6;
 constexpr int kXcds = 8;  // accelerator dies, each with its own L2
-constexpr int kModelVariants = 5;
+constexpr int kModelVariants = 6;
 constexpr int kGroups = kModelVariants * kSizeClasses;
 __host__ __device__ inline int size_class(int32_t n) {
     int c = 0;
@@ -212,11 +219,12 @@ __host__ __device__ inline int size_class(int32_t n) {
     return c;
 }
 inline int model_variant(int32_t kind, int32_t n_peds) {
-    return kind == HDX_ROCKSAMPLE ? 0 : kind == HDX_MARS ? 4 : n_peds <= 8 ? 1 : n_peds <= 16 ? 2 : 3;
+    return kind == HDX_ROCKSAMPLE ? 0 : kind == HDX_MARS ? 4 : kind == HDX_NAV ? 5 : n_peds <= 8 ? 1 : n_peds <= 16 ? 2 : 3;
 }
 inline Variant group_variant(int g) {
     const int v = g / kSizeClasses;
     if (v == 4) return Variant{3, 1, 1};
+    if (v == 5) return Variant{4, 1, 1};
     return v == 0 ? Variant{0, 1, 1} : Variant{1, v == 1 ? 8 : v == 2 ? 16 : 32, 1};
 }
 struct ClassPlan {
@@ -232,7 +240,7 @@ void plan_classes(const LeafTask *tasks, const int8_t *variant, Tile *tiles, int
 // what the group's leaves and model need).
 hipError_t launch_classes(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queues, const ClassPlan &plan,
                           const int32_t *lds_n, const Schedule *sch, int32_t n_cu, hipStream_t stream,
-                          uint32_t mask = 0xffffffffu);
+                          uint64_t mask = ~0ull);
 // Default schedule of a group whose largest leaf has n_max scenarios.
 // Latency form (a few leaves, split groups): two scenarios per lane up to
 // 256 lanes, one workgroup per tile, XCD-contiguous.  Throughput form (one
@@ -261,8 +269,11 @@ struct SampleArgs {
     int32_t level0;
     float px0[kMaxPeds], py0[kMaxPeds];
     uint64_t goal_thr[kMaxPeds][kMaxGoals];  // cumulative thresholds
+    int32_t n_unknown;                       // navigation: unknown cells
+    uint64_t cell_thr[HDX_MAX_NAV_UNKNOWN];  // navigation: P(occupied) thresholds
     StatesPtr out;
 };
+static_assert(sizeof(SampleArgs) <= 4096, "sample kernel arguments too large");
 hipError_t launch_sample(const SampleArgs &args, hipStream_t stream);
 
 struct BoundsArgs {

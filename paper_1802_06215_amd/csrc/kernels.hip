@@ -620,8 +620,9 @@ __device__ __forceinline__ int remap_xcd(int b, int grid) {
 }
 
 // MODE 0: RockSample only; 1: crowd driving only; 2: both; 3: multi-agent
-// RockSample only.  Workgroups of the driving model are capped at 256 lanes
-// so its per-lane state can stay in registers.
+// RockSample only; 4: navigation only.  Workgroups of the driving and
+// navigation models are capped at 256 lanes (register state, hashed
+// observations).
 template <int MODE>
 constexpr bool small_obs_mode() { return MODE == 0 || MODE == 3; }
 template <int MODE>
@@ -635,6 +636,8 @@ template <int MODE, int PM>
 __device__ __forceinline__ void run_mode(const HDX_CONST LeafTask *T, int a, unsigned char *lds, const LdsLayout &Ly) {
     if (MODE == 3) {
         run_tile<MarsOps>(T, a, lds, Ly);
+    } else if (MODE == 4) {
+        run_tile<NavOps>(T, a, lds, Ly);
     } else if (MODE == 0 || (MODE == 2 && T->kind == HDX_ROCKSAMPLE)) {
         run_tile<RsOps>(T, a, lds, Ly);
     } else {
@@ -764,6 +767,28 @@ __global__ void sample_kernel(const SampleArgs A) {
         }
         S.w[k] = A.x0;
         S.w[S.stride + k] = rk;
+    } else if (M->kind == HDX_NAV) {
+        // robot on row 0 at a uniform column; one gate open; other unknown
+        // cells occupied at their prior (draw i = word i % 4 of block i / 4)
+        uint4 u = philox((uint32_t)k, 0, 0, kTagInit, A.k0, A.k1);
+        const int x = (int)(((uint64_t)u.x * (uint64_t)M->grid) >> 32);
+        uint32_t m0 = u.y < 0x80000000u ? 2u : 1u, m1 = 0, m2 = 0, m3 = 0;
+        for (int i = 2; i < A.n_unknown; ++i) {
+            if ((i & 3) == 0) u = philox((uint32_t)k, 0, (uint32_t)(i >> 2), kTagInit, A.k0, A.k1);
+            const uint32_t word = (i & 3) == 0 ? u.x : (i & 3) == 1 ? u.y : (i & 3) == 2 ? u.z : u.w;
+            if ((uint64_t)word < A.cell_thr[i]) {
+                const uint32_t bit = 1u << (i & 31);
+                if (i < 32) m0 |= bit;
+                else if (i < 64) m1 |= bit;
+                else if (i < 96) m2 |= bit;
+                else m3 |= bit;
+            }
+        }
+        S.w[k] = x;
+        S.w[S.stride + k] = (int32_t)m0;
+        S.w[2 * S.stride + k] = (int32_t)m1;
+        S.w[3 * S.stride + k] = (int32_t)m2;
+        S.w[4 * S.stride + k] = (int32_t)m3;
     } else {
         S.s[k] = A.s0;
         S.car[k] = A.level0 & 0xff;
@@ -843,16 +868,18 @@ hipError_t launch_fp32_selftest(const float *a, const float *b, const float *c, 
 
 int32_t max_dynamic_lds() { return 160 * 1024 - 256; }
 
-Variant pick_variant(int32_t has_rs, int32_t has_ped, int32_t ped_max, int32_t n_max, int32_t has_mars) {
+Variant pick_variant(int32_t has_rs, int32_t has_ped, int32_t ped_max, int32_t n_max, int32_t has_mars,
+                     int32_t has_nav) {
     Variant v;
-    v.mode = has_mars ? 3 : !has_ped ? 0 : (has_rs ? 2 : 1);
+    v.mode = has_nav ? 4 : has_mars ? 3 : !has_ped ? 0 : (has_rs ? 2 : 1);
     v.pm = !has_ped ? 1 : ped_max <= 8 ? 8 : ped_max <= 16 ? 16 : 32;
     v.n_max = n_max < 1 ? 1 : n_max;
     return v;
 }
 
 int32_t variant_max_threads(const Variant &v) {
-    return v.mode == 0 ? max_threads<0>() : v.mode == 3 ? max_threads<3>() : max_threads<1>();
+    return v.mode == 0 ? max_threads<0>() : v.mode == 3 ? max_threads<3>() : v.mode == 4 ? max_threads<4>()
+                                                                            : max_threads<1>();
 }
 
 hipError_t configure_expand_kernels() {
@@ -864,6 +891,7 @@ hipError_t configure_expand_kernels() {
     if (e == hipSuccess) e = configure_t<2, 16>();
     if (e == hipSuccess) e = configure_t<2, 32>();
     if (e == hipSuccess) e = configure_t<3, 1>();
+    if (e == hipSuccess) e = configure_t<4, 1>();
     return e;
 }
 
@@ -872,6 +900,7 @@ hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue
 #define HDX_LAUNCH(M, P) launch_expand_t<M, P>(d_tasks, d_tiles, d_queue, n_tiles, v.n_max, sch, n_cu, stream)
     if (v.mode == 0) return HDX_LAUNCH(0, 1);
     if (v.mode == 3) return HDX_LAUNCH(3, 1);
+    if (v.mode == 4) return HDX_LAUNCH(4, 1);
     if (v.mode == 1) return v.pm == 8 ? HDX_LAUNCH(1, 8) : v.pm == 16 ? HDX_LAUNCH(1, 16) : HDX_LAUNCH(1, 32);
     return v.pm == 8 ? HDX_LAUNCH(2, 8) : v.pm == 16 ? HDX_LAUNCH(2, 16) : HDX_LAUNCH(2, 32);
 #undef HDX_LAUNCH
@@ -881,6 +910,7 @@ hipError_t launch_expand_args(const ArgPack &pack, const Variant &v, const Sched
 #define HDX_LAUNCH(M, P) launch_args_t<M, P>(pack, sch, stream)
     if (v.mode == 0) return HDX_LAUNCH(0, 1);
     if (v.mode == 3) return HDX_LAUNCH(3, 1);
+    if (v.mode == 4) return HDX_LAUNCH(4, 1);
     if (v.mode == 1) return v.pm == 8 ? HDX_LAUNCH(1, 8) : v.pm == 16 ? HDX_LAUNCH(1, 16) : HDX_LAUNCH(1, 32);
     return v.pm == 8 ? HDX_LAUNCH(2, 8) : v.pm == 16 ? HDX_LAUNCH(2, 16) : HDX_LAUNCH(2, 32);
 #undef HDX_LAUNCH
@@ -901,6 +931,8 @@ hipError_t launch_bounds(const BoundsArgs &args, int32_t kind, int32_t n_peds, h
         hipLaunchKernelGGL(bounds_kernel<RsOps>, dim3((unsigned)blocks), dim3(threads), 0, stream, args);
     } else if (kind == HDX_MARS) {
         hipLaunchKernelGGL(bounds_kernel<MarsOps>, dim3((unsigned)blocks), dim3(threads), 0, stream, args);
+    } else if (kind == HDX_NAV) {
+        hipLaunchKernelGGL(bounds_kernel<NavOps>, dim3((unsigned)blocks), dim3(threads), 0, stream, args);
     } else if (n_peds <= 8) {
         hipLaunchKernelGGL(bounds_kernel<PedOps<8>>, dim3((unsigned)blocks), dim3(threads), 0, stream, args);
     } else if (n_peds <= 16) {

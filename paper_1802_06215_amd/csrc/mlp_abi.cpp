@@ -252,8 +252,8 @@ hdx_status hdx_mlp_train_step(hdx_ctx *ctx, hdx_mlp *m, const uint16_t *X, const
 hdx_status hdx_features(hdx_ctx *ctx, const hdx_model *model, hdx_states states, const int32_t *depths, int64_t n,
                         int32_t horizon, uint16_t *X, hdx_stream stream) {
     if (!ctx || !model || n < 0 || (n > 0 && (!depths || !X))) return HDX_E_INVALID;
-    if (hdx_internal_desc(model)->kind == HDX_MARS) {
-        hdx_internal_set_error(ctx, "no surrogate features for the multi-agent model");
+    if (hdx_internal_desc(model)->kind == HDX_MARS || hdx_internal_desc(model)->kind == HDX_NAV) {
+        hdx_internal_set_error(ctx, "no surrogate features for this model");
         return HDX_E_UNSUPPORTED;
     }
     if (n == 0) return HDX_OK;
@@ -279,8 +279,8 @@ hdx_status hdx_expand_leaf_surrogate(hdx_ctx *ctx, const hdx_leaf *leaves, int32
     for (int32_t i = 0; i < n_leaves; ++i) {
         if (!leaves[i].model) return HDX_E_INVALID;
         const hdx_model_desc &d = *hdx_internal_desc(leaves[i].model);
-        if (d.kind == HDX_MARS) {
-            hdx_internal_set_error(ctx, "no surrogate features for the multi-agent model");
+        if (d.kind == HDX_MARS || d.kind == HDX_NAV) {
+            hdx_internal_set_error(ctx, "no surrogate features for this model");
             return HDX_E_UNSUPPORTED;
         }
         const int64_t np = (int64_t)d.n_actions * (leaves[i].n > 0 ? leaves[i].n : 0);

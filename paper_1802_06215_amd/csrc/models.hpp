@@ -397,6 +397,153 @@ struct MarsOps {
 };
 
 // ---------------------------------------------------------------------------
+// Navigation in a partially known map.  Five int32 rows per scenario: the
+// robot (x bits 0-3, y bits 4-7, terminal bit 30) at w[k], then the unknown
+// cells' occupancy (cell i in bit i % 32 of row 1 + i / 32) at
+// w[(1 + j) * stride + k].  Actions 0 stay, 1-8 move N, NE, E, SE, S, SW, W,
+// NW (y grows downwards).  A move draws word 0 of step block 0 (failure);
+// a reading draws step blocks 1 and 2 (one word per neighbour).
+// ---------------------------------------------------------------------------
+constexpr int nav_dx_of(int a) { return (a == 0 || a == 1 || a == 5) ? 0 : (a >= 2 && a <= 4) ? 1 : -1; }
+constexpr int nav_dy_of(int a) { return (a == 0 || a == 3 || a == 7) ? 0 : (a == 1 || a == 2 || a == 8) ? -1 : 1; }
+// dx + 1 and dy + 1 of each action in two bits; the action of each (dx, dy)
+// in four bits at (dy + 1) * 3 + dx + 1
+constexpr uint32_t nav_pack_dir(bool y) {
+    uint32_t v = 0;
+    for (int a = 0; a < 9; ++a) v |= (uint32_t)((y ? nav_dy_of(a) : nav_dx_of(a)) + 1) << (2 * a);
+    return v;
+}
+constexpr uint64_t nav_action_table() {
+    uint64_t t = 0;
+    for (int a = 0; a < 9; ++a) t |= (uint64_t)a << (4 * ((nav_dy_of(a) + 1) * 3 + nav_dx_of(a) + 1));
+    return t;
+}
+
+struct NavOps {
+    struct State {
+        int32_t p;
+        uint32_t m0, m1, m2, m3;
+    };
+    static constexpr bool kHashObs = true;
+    static constexpr bool kSplitRollout = true;
+    static constexpr bool kSmallObs = false;  // 8 reading bits: 256 observations
+    static constexpr bool kLdsModel = true;   // discount powers staged in LDS
+    static constexpr bool kWaveUpper = false;
+    struct WaveUpper {};
+    static constexpr uint32_t kDx = nav_pack_dir(false), kDy = nav_pack_dir(true);
+    static constexpr uint64_t kAction = nav_action_table();
+    static constexpr uint64_t kTerminalObs = 256;
+
+    __device__ static int dx(int a) { return (int)((kDx >> (2 * a)) & 3u) - 1; }
+    __device__ static int dy(int a) { return (int)((kDy >> (2 * a)) & 3u) - 1; }
+
+    __device__ static void load(const MView &, const StatesPtr &S, int64_t p, State &st) {
+        st.p = S.w[p];
+        st.m0 = (uint32_t)S.w[S.stride + p];
+        st.m1 = (uint32_t)S.w[2 * S.stride + p];
+        st.m2 = (uint32_t)S.w[3 * S.stride + p];
+        st.m3 = (uint32_t)S.w[4 * S.stride + p];
+    }
+    __device__ static void make_terminal(State &st) {
+        st.p = 1 << 30;
+        st.m0 = st.m1 = st.m2 = st.m3 = 0;
+    }
+    __device__ static void store(const MView &, const StatesPtr &S, int64_t p, const State &st) {
+        S.w[p] = st.p;
+        S.w[S.stride + p] = (int32_t)st.m0;
+        S.w[2 * S.stride + p] = (int32_t)st.m1;
+        S.w[3 * S.stride + p] = (int32_t)st.m2;
+        S.w[4 * S.stride + p] = (int32_t)st.m3;
+    }
+    __device__ static bool terminal(const State &st) { return (st.p >> 30) & 1; }
+
+    // Occupied in this scenario; off the map counts as occupied.
+    __device__ static int occupied(const MView &M, const State &st, int x, int y) {
+        const int n = M.h->grid;
+        if (x < 0 || y < 0 || x >= n || y >= n) return 1;
+        const int c = M.h->nav_cell[y * n + x];
+        if (c < 0) return c == -2 ? 1 : 0;
+        const uint32_t w = c < 32 ? st.m0 : c < 64 ? st.m1 : c < 96 ? st.m2 : st.m3;
+        return (int)((w >> (c & 31)) & 1u);
+    }
+
+    template <bool kObs>
+    __device__ static void step(const MView &M, State &st, int a, uint32_t id, uint32_t depth, uint32_t k0,
+                                uint32_t k1, float &r, uint64_t &z) {
+        r = 0.0f;
+        z = kTerminalObs;
+        if ((st.p >> 30) & 1) return;  // absorbing
+        int x = st.p & 15, y = (st.p >> 4) & 15;
+        int term = 0;
+        if (a == 0) {
+            r = -0.2f;
+        } else if ((uint64_t)philox(id, depth, 0, kTagStep, k0, k1).x < M.h->fail_thr) {
+            r = -0.1f;  // the move fails: the robot stays
+        } else {
+            const int tx = x + dx(a), ty = y + dy(a);
+            if (occupied(M, st, tx, ty)) {
+                r = -1.0f;  // crash: the robot stays
+            } else {
+                x = tx;
+                y = ty;
+                if (x == M.h->nav_goal_x && y == M.h->grid - 1) {
+                    r = 20.0f;
+                    term = 1;
+                } else {
+                    r = -0.1f;
+                }
+            }
+        }
+        st.p = x | (y << 4) | (term << 30);
+        if (!kObs || term) return;
+        const uint4 b1 = philox(id, depth, 1, kTagStep, k0, k1);
+        const uint4 b2 = philox(id, depth, 2, kTagStep, k0, k1);
+        const uint32_t words[8] = {b1.x, b1.y, b1.z, b1.w, b2.x, b2.y, b2.z, b2.w};
+        uint64_t obs = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            int bit = occupied(M, st, x + dx(j + 1), y + dy(j + 1));
+            if ((uint64_t)words[j] < M.h->err_thr) bit ^= 1;
+            obs |= (uint64_t)bit << j;
+        }
+        z = obs;
+    }
+
+    // The goal reward on the shortest 8-connected path, no costs.
+    __device__ static float upper(const MView &M, const State &st) {
+        if ((st.p >> 30) & 1) return 0.0f;
+        const int ax = abs((st.p & 15) - M.h->nav_goal_x), ay = abs(((st.p >> 4) & 15) - (M.h->grid - 1));
+        const int d = ax > ay ? ax : ay;
+        return 20.0f * M.gpow_lane(d > 0 ? d - 1 : 0);
+    }
+    __device__ static float upper_wave(const MView &M, const State &st, WaveUpper &) { return upper(M, st); }
+
+    // Head for the open gate while above the wall, then for the goal: the
+    // diagonal step towards the target, else its vertical part, else its
+    // horizontal part, the first that lands on a free cell; else stay.
+    __device__ static int default_action(const MView &M, const State &st) {
+        const int x = st.p & 15, y = (st.p >> 4) & 15;
+        int tx = M.h->nav_goal_x, ty = M.h->grid - 1;
+        if (y < M.h->nav_wall) {
+            const int g = !(st.m0 & 1u) ? 0 : (!(st.m0 & 2u) ? 1 : -1);
+            if (g >= 0) {
+                tx = M.h->nav_gate_x[g];
+                ty = M.h->nav_wall;
+            }
+        }
+        const int sx = tx > x ? 1 : (tx < x ? -1 : 0), sy = ty > y ? 1 : (ty < y ? -1 : 0);
+        const int cx[3] = {sx, 0, sx}, cy[3] = {sy, sy, 0};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (cx[c] == 0 && cy[c] == 0) continue;
+            if (occupied(M, st, x + cx[c], y + cy[c])) continue;
+            return (int)((kAction >> (4 * ((cy[c] + 1) * 3 + cx[c] + 1))) & 15u);
+        }
+        return 0;
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Crowd driving: car (position, speed level, terminal) and up to PM
 // pedestrians held in registers.
 // ---------------------------------------------------------------------------

@@ -174,6 +174,39 @@ hdx_status hdx_upload_model(hdx_ctx *ctx, const hdx_model_desc *d, hdx_model **o
             const double acc = 0.5 + 0.5 * pow(2.0, -sqrt((double)d2) / 20.0);
             dm->sense_thr_m1[d2] = (uint32_t)(prob_threshold(acc) - 1);
         }
+    } else if (d->kind == HDX_NAV) {
+        const int n = d->grid;
+        if (n < 5 || n > HDX_MAX_NAV_GRID) {
+            delete dm;
+            return fail(ctx, HDX_E_SHAPE, "navigation grid must be 5..16");
+        }
+        int n_unknown = 0;
+        bool ok = d->nav_wall >= 1 && d->nav_wall <= n - 2 && d->nav_goal_x >= 0 && d->nav_goal_x < n &&
+                  d->nav_gate_x[0] >= 0 && d->nav_gate_x[0] < n && d->nav_gate_x[1] >= 0 && d->nav_gate_x[1] < n &&
+                  d->p_fail >= 0.0 && d->p_fail < 1.0 && d->p_err >= 0.0 && d->p_err < 1.0;
+        std::vector<int> seen(HDX_MAX_NAV_UNKNOWN, 0);
+        for (int c = 0; ok && c < n * n; ++c) {
+            const int v = d->nav_cell[c];
+            if (v >= HDX_MAX_NAV_UNKNOWN || v < -2 || (v >= 0 && seen[v]++)) ok = false;
+            else if (v >= 0) ++n_unknown;
+        }
+        // unknown cells are numbered 0..n_unknown-1; 0 and 1 are the gates; the goal is known free
+        for (int v = 0; ok && v < n_unknown; ++v) ok = seen[v] == 1;
+        ok = ok && n_unknown >= 2 && d->nav_cell[d->nav_wall * n + d->nav_gate_x[0]] == 0 &&
+             d->nav_cell[d->nav_wall * n + d->nav_gate_x[1]] == 1 && d->nav_cell[(n - 1) * n + d->nav_goal_x] == -1;
+        if (!ok) {
+            delete dm;
+            return fail(ctx, HDX_E_INVALID, "navigation map, gates, goal or probabilities");
+        }
+        h->n_actions = 9;
+        h->grid = n;
+        h->nav_goal_x = d->nav_goal_x;
+        h->nav_wall = d->nav_wall;
+        h->nav_gate_x[0] = d->nav_gate_x[0];
+        h->nav_gate_x[1] = d->nav_gate_x[1];
+        for (int c = 0; c < HDX_MAX_NAV_GRID * HDX_MAX_NAV_GRID; ++c) h->nav_cell[c] = c < n * n ? d->nav_cell[c] : -2;
+        h->fail_thr = prob_threshold(d->p_fail);
+        h->err_thr = prob_threshold(d->p_err);
     } else if (d->kind == HDX_PEDNAV) {
         if (d->n_peds < 0 || d->n_peds > kMaxPeds || d->n_goals < 1 || d->n_goals > kMaxGoals ||
             d->n_levels < 1 || d->n_levels > 255) {
@@ -269,6 +302,7 @@ int32_t hdx_model_max_children(const hdx_model *m, int32_t n) {
     if (!m || n < 0) return -1;
     if (m->desc.kind == HDX_ROCKSAMPLE) return n < 3 ? n : 3;  // none, good, bad
     if (m->desc.kind == HDX_MARS) return n < 9 ? n : 9;        // one reading per robot
+    if (m->desc.kind == HDX_NAV) return n < 257 ? n : 257;     // eight reading bits, or terminal
     return n;                                                  // hashed observations
 }
 
@@ -286,7 +320,7 @@ static StatesPtr to_ptr(const hdx_states &s) {
 
 static bool states_ok(const hdx_model *m, const hdx_states &s, int64_t n) {
     if (m->desc.kind == HDX_ROCKSAMPLE) return s.w != nullptr;
-    if (m->desc.kind == HDX_MARS) return s.w != nullptr && s.stride >= n;
+    if (m->desc.kind == HDX_MARS || m->desc.kind == HDX_NAV) return s.w != nullptr && s.stride >= n;
     if (!s.s || !s.car) return false;
     if (m->desc.n_peds > 0 && (!s.px || !s.py || !s.goal || s.stride < n)) return false;
     return true;
@@ -318,6 +352,13 @@ hdx_status hdx_sample_scenarios(hdx_ctx *ctx, const hdx_model *m, const hdx_beli
         if (d.n_rocks > 0 && !b->p_good) return fail(ctx, HDX_E_INVALID, "p_good is null");
         A.x0 = b->x | (b->y << 5) | (b->x2 << 10) | (b->y2 << 15) | (b->gone << 20) | (b->gone == 3 ? 1 << 30 : 0);
         for (int i = 0; i < d.n_rocks; ++i) A.rock_thr[i] = prob_threshold(b->p_good[i]);
+    } else if (d.kind == HDX_NAV) {
+        int nu = 0;
+        for (int c = 0; c < d.grid * d.grid; ++c)
+            if (d.nav_cell[c] >= 0) ++nu;
+        if (nu > 2 && !b->p_good) return fail(ctx, HDX_E_INVALID, "p_good is null");
+        A.n_unknown = nu;
+        for (int i = 2; i < nu; ++i) A.cell_thr[i] = prob_threshold(b->p_good[i]);
     } else {
         if (d.n_peds > 0 && (!b->px || !b->py || !b->goal_p)) return fail(ctx, HDX_E_INVALID, "belief arrays");
         if (b->level < 0 || b->level >= d.n_levels) return fail(ctx, HDX_E_INVALID, "speed level");
@@ -358,7 +399,7 @@ namespace {
 
 struct Shape {
     int64_t n_tiles = 0;
-    int32_t n_max = 1, has_rs = 0, has_ped = 0, ped_max = 0, has_mars = 0;
+    int32_t n_max = 1, has_rs = 0, has_ped = 0, ped_max = 0, has_mars = 0, has_nav = 0;
 };
 
 hdx_status validate_leaves(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves, Shape *sh) {
@@ -395,6 +436,8 @@ hdx_status validate_leaves(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
             if (d.n_peds > s.ped_max) s.ped_max = d.n_peds;
         } else if (d.kind == HDX_MARS) {
             s.has_mars = 1;
+        } else if (d.kind == HDX_NAV) {
+            s.has_nav = 1;
         } else {
             s.has_rs = 1;
         }
@@ -519,9 +562,9 @@ Schedule hdx::class_default_schedule(int32_t n_max, int32_t max_threads, int32_t
 
 hipError_t hdx::launch_classes(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queues,
                                const ClassPlan &plan, const int32_t *lds_n, const Schedule *sch, int32_t n_cu,
-                               hipStream_t stream, uint32_t mask) {
+                               hipStream_t stream, uint64_t mask) {
     for (int g = 0; g < kGroups; ++g) {
-        if (plan.count[g] == 0 || !(mask & (1u << g))) continue;
+        if (plan.count[g] == 0 || !(mask & (1ull << g))) continue;
         Variant vg = group_variant(g);
         vg.n_max = std::max(lds_n[g], plan.n_max[g]);
         // a workgroup no wider than the group's leaves need
@@ -544,19 +587,19 @@ namespace {
 hipError_t launch_classes_forked(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queues,
                                  const ClassPlan &plan, const int32_t *lds_n, const Schedule *sch, int32_t n_cu,
                                  hipStream_t st, const hipStream_t *cls, hipEvent_t fork, const hipEvent_t *join,
-                                 uint32_t mask = 0xffffffffu) {
+                                 uint64_t mask = ~0ull) {
     int active = 0;
     for (int g = 0; g < kGroups; ++g)
-        if (plan.count[g] > 0 && (mask & (1u << g))) ++active;
+        if (plan.count[g] > 0 && (mask & (1ull << g))) ++active;
     if (active <= 1) return launch_classes(d_tasks, d_tiles, d_queues, plan, lds_n, sch, n_cu, st, mask);
     hipError_t e = hipEventRecord(fork, st);
     // largest leaves first: their tails are the longest
     for (int c = kSizeClasses - 1; c >= 0 && e == hipSuccess; --c)
         for (int v = kModelVariants - 1; v >= 0 && e == hipSuccess; --v) {
             const int g = v * kSizeClasses + c;
-            if (plan.count[g] == 0 || !(mask & (1u << g))) continue;
+            if (plan.count[g] == 0 || !(mask & (1ull << g))) continue;
             e = hipStreamWaitEvent(cls[g], fork, 0);
-            if (e == hipSuccess) e = launch_classes(d_tasks, d_tiles, d_queues, plan, lds_n, sch, n_cu, cls[g], 1u << g);
+            if (e == hipSuccess) e = launch_classes(d_tasks, d_tiles, d_queues, plan, lds_n, sch, n_cu, cls[g], 1ull << g);
             if (e == hipSuccess) e = hipEventRecord(join[g], cls[g]);
             if (e == hipSuccess) e = hipStreamWaitEvent(st, join[g], 0);
         }
@@ -604,10 +647,12 @@ hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
     hdx_status st = validate_leaves(ctx, leaves, n_leaves, &sh);
     if (st != HDX_OK || n_leaves == 0) return st;
     hipSetDevice(ctx->device);
-    const Variant v0 = pick_variant(sh.has_rs, sh.has_ped, sh.ped_max, sh.n_max, sh.has_mars);
-    if (n_leaves <= kArgLeaves && !(sh.has_mars && (sh.has_rs || sh.has_ped))) {
-        // small calls of one kernel variant carry their descriptors in the
-        // kernel arguments (the multi-agent model has a kernel of its own)
+    const Variant v0 = pick_variant(sh.has_rs, sh.has_ped, sh.ped_max, sh.n_max, sh.has_mars, sh.has_nav);
+    const int kernels = (sh.has_rs || sh.has_ped ? 1 : 0) + sh.has_mars + sh.has_nav;
+    if (n_leaves <= kArgLeaves && kernels <= 1) {
+        // small calls of one kernel carry their descriptors in the kernel
+        // arguments (the multi-agent and navigation models have kernels of
+        // their own; RockSample and driving share one)
         static_assert(sizeof(ArgPack) <= 4096, "kernel argument pack too large");
         ArgPack pack;
         memset(&pack, 0, sizeof(pack));
@@ -696,7 +741,7 @@ struct hdx_batch {
 namespace {
 
 hipError_t batch_direct_launch(hdx_ctx *ctx, hdx_batch *b, const Schedule *s, hipStream_t st,
-                               uint32_t mask = 0xffffffffu) {
+                               uint64_t mask = ~0ull) {
     return launch_classes_forked(b->d_tasks, b->d_tiles, b->d_queue, b->plan, b->lds_c, s, ctx->n_cu, st, b->cls,
                                  b->fork, b->join, mask);
 }
@@ -974,7 +1019,7 @@ hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *b, int32_t reps, float *b
         return cand;
     };
     // mean ms of `reps` launches of the groups in mask under schedules s
-    auto time_launch = [&](const Schedule *s, uint32_t mask, float *ms) -> hipError_t {
+    auto time_launch = [&](const Schedule *s, uint64_t mask, float *ms) -> hipError_t {
         hipError_t e = batch_direct_launch(ctx, b, s, b->work, mask);  // warm-up
         if (e == hipSuccess) e = hipEventRecord(b->t0, b->work);
         for (int r = 0; r < reps && e == hipSuccess; ++r) e = batch_direct_launch(ctx, b, s, b->work, mask);
@@ -999,7 +1044,7 @@ hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *b, int32_t reps, float *b
             for (const Schedule &s : candidates(c)) {
                 trial[c] = s;
                 float ms = 0.0f;
-                const hipError_t e = time_launch(trial, 1u << c, &ms);
+                const hipError_t e = time_launch(trial, 1ull << c, &ms);
                 if (e != hipSuccess) return e;
                 if (ms < best) {
                     best = ms;
@@ -1011,7 +1056,7 @@ hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *b, int32_t reps, float *b
         }
         if (active > 1) {
             float best = 0.0f;
-            hipError_t e = time_launch(trial, 0xffffffffu, &best);
+            hipError_t e = time_launch(trial, ~0ull, &best);
             if (e != hipSuccess) return e;
             for (int c = kGroups - 1; c >= 0; --c) {
                 if (b->plan.count[c] == 0) continue;
@@ -1021,7 +1066,7 @@ hdx_status hdx_batch_autotune(hdx_ctx *ctx, hdx_batch *b, int32_t reps, float *b
                     if (same_schedule(s, keep)) continue;
                     trial[c] = s;
                     float ms = 0.0f;
-                    e = time_launch(trial, 0xffffffffu, &ms);
+                    e = time_launch(trial, ~0ull, &ms);
                     if (e != hipSuccess) return e;
                     if (ms < best) {
                         best = ms;

@@ -60,6 +60,8 @@ RecLayout rec_layout(const hdx_model_desc &d, int n, int cap) {
         L.w = take(4ull * n);
     } else if (d.kind == HDX_MARS) {
         L.w = take(8ull * n);  // robots' row, then rocks' row
+    } else if (d.kind == HDX_NAV) {
+        L.w = take(20ull * n);  // robot row, then four rows of unknown cells
     } else {
         L.s = take(4ull * n);
         L.car = take(4ull * n);
@@ -128,7 +130,7 @@ struct Request {
 hdx_states rec_states(const hdx_model_desc &d, const Rec &r) {
     hdx_states s;
     memset(&s, 0, sizeof(s));
-    if (d.kind == HDX_ROCKSAMPLE || d.kind == HDX_MARS) {
+    if (d.kind == HDX_ROCKSAMPLE || d.kind == HDX_MARS || d.kind == HDX_NAV) {
         s.w = (int32_t *)(r.dev + r.L.w);
     } else {
         s.s = (float *)(r.dev + r.L.s);

@@ -16,11 +16,11 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libhdx.so")
 
-ROCKSAMPLE, PEDNAV, MARS = 0, 1, 2
+ROCKSAMPLE, PEDNAV, MARS, NAV = 0, 1, 2, 3
 MAX_ACTIONS = 625  # HDX_MAX_ACTIONS
 POLICY_DEFAULT, POLICY_CONST, POLICY_RANDOM = 0, 1, 2
 SIZE_CLASSES = 6
-LAUNCH_GROUPS = 30  # model variant (RockSample; driving <= 8, 16, 32 pedestrians; multi-agent) x size class
+LAUNCH_GROUPS = 36  # model variant (RockSample; driving <= 8, 16, 32 pedestrians; multi-agent; navigation) x size class
 MAX_LEAF_SCENARIOS = 2048
 MAX_HORIZON = 4096
 
@@ -44,7 +44,9 @@ class ModelDesc(C.Structure):
                 ("path_len", C.c_float), ("dt", C.c_float), ("ped_speed", C.c_float),
                 ("sigma_h", C.c_float), ("coll_radius", C.c_float),
                 ("r_collision", C.c_float), ("r_step", C.c_float), ("r_goal", C.c_float),
-                ("p_fail", C.c_double)]
+                ("p_fail", C.c_double),
+                ("nav_goal_x", C.c_int32), ("nav_wall", C.c_int32), ("nav_gate_x", C.c_int32 * 2),
+                ("nav_cell", C.c_int16 * 256), ("p_err", C.c_double)]
 
 
 class Belief(C.Structure):
@@ -193,7 +195,15 @@ def model_desc(d: dict) -> ModelDesc:
     m.kind = d["kind"]
     m.n_actions = d["n_actions"]
     m.gamma = d["gamma"]
-    if d["kind"] in (ROCKSAMPLE, MARS):
+    if d["kind"] == NAV:
+        m.grid = d["n"]
+        m.nav_goal_x, m.nav_wall = int(d["goal_x"]), int(d["wall"])
+        m.nav_gate_x[0], m.nav_gate_x[1] = int(d["gate_x"][0]), int(d["gate_x"][1])
+        cell = np.asarray(d["cell"], np.int64).reshape(-1)
+        for c in range(cell.shape[0]):
+            m.nav_cell[c] = int(cell[c])
+        m.p_fail, m.p_err = d["p_fail"], d["p_err"]
+    elif d["kind"] in (ROCKSAMPLE, MARS):
         m.grid, m.n_rocks = d["n"], d["m"]
         for i in range(d["m"]):
             m.rock_x[i], m.rock_y[i] = int(d["rock_x"][i]), int(d["rock_y"][i])
@@ -231,9 +241,10 @@ def states_view(model: Model, st: dict) -> States:
     if model.kind == ROCKSAMPLE:
         v.w = _dp(st["w"])
         v.stride = st["w"].shape[-1]
-    elif model.kind == MARS:
-        # rows of [2, n]: the robots' row, then the rocks' row
-        assert st["w"].dim() == 2 and st["w"].shape[0] == 2 and st["w"].stride(1) == 1
+    elif model.kind in (MARS, NAV):
+        # rows of [2, n] (robots, rocks) or [5, n] (robot, four rows of unknown cells)
+        assert st["w"].dim() == 2 and st["w"].shape[0] == (2 if model.kind == MARS else 5)
+        assert st["w"].stride(1) == 1
         v.w = _dp(st["w"])
         v.stride = st["w"].stride(0)
     else:
@@ -249,8 +260,8 @@ def states_view(model: Model, st: dict) -> States:
 def empty_states(model: Model, n: int, device="cuda") -> dict:
     if model.kind == ROCKSAMPLE:
         return dict(w=torch.empty(n, dtype=torch.int32, device=device))
-    if model.kind == MARS:
-        return dict(w=torch.empty((2, n), dtype=torch.int32, device=device))
+    if model.kind in (MARS, NAV):
+        return dict(w=torch.empty((2 if model.kind == MARS else 5, n), dtype=torch.int32, device=device))
     P = model.n_peds
     return dict(s=torch.empty(n, dtype=torch.float32, device=device),
                 car=torch.empty(n, dtype=torch.int32, device=device),
@@ -311,8 +322,8 @@ def leaf_buffer_slab(model: Model, count: int, n_max: int, device="cuda") -> lis
                  steps=torch.empty((count, A, 2), dtype=torch.int64, device=device))
     if model.kind == ROCKSAMPLE:
         st = dict(w=torch.empty((count, n1), dtype=i32, device=device))
-    elif model.kind == MARS:
-        st = dict(w=torch.empty((count, 2, n1), dtype=i32, device=device))
+    elif model.kind in (MARS, NAV):
+        st = dict(w=torch.empty((count, 2 if model.kind == MARS else 5, n1), dtype=i32, device=device))
     else:
         P = model.n_peds
         st = dict(s=torch.empty((count, n1), dtype=f32, device=device),
@@ -353,6 +364,20 @@ def mars_states(pos, rocks, term, device="cuda") -> dict:
     row1 = (rocks.astype(np.int64) << np.arange(rocks.shape[1])).sum(1) if rocks.shape[1] else np.zeros(n, np.int64)
     w = np.stack([row0, row1]).astype(np.int32)
     return dict(w=torch.from_numpy(w).to(device))
+
+
+def nav_states(x, y, cells, term, device="cuda") -> dict:
+    """Pack navigation fields (robot x, y, scalars or per scenario; unknown
+    cells occupied, bool [n, U <= 128]; terminal flags) into the library's
+    five-row layout, on the device."""
+    cells = np.asarray(cells, dtype=bool)
+    n = cells.shape[0]
+    w = np.zeros((5, n), dtype=np.int64)
+    w[0] = (np.broadcast_to(np.asarray(x, np.int64), (n,)) | (np.broadcast_to(np.asarray(y, np.int64), (n,)) << 4)
+            | (np.asarray(term, dtype=np.int64) << 30))
+    for i in range(cells.shape[1]):
+        w[1 + i // 32] |= cells[:, i].astype(np.int64) << (i % 32)
+    return dict(w=torch.from_numpy(w.astype(np.uint32).view(np.int32)).to(device))
 
 
 def pednav_states(s, level, term, px, py, goal, device="cuda") -> dict:
@@ -474,6 +499,10 @@ class Context:
             p = np.ascontiguousarray(belief["p"], dtype=np.float64)
             keep.append(p)
             b.x, b.y, b.p_good = belief["x"], belief["y"], p.ctypes.data
+        elif model.kind == NAV:
+            p = np.ascontiguousarray(belief["p"], dtype=np.float64)
+            keep.append(p)
+            b.p_good = p.ctypes.data
         elif model.kind == MARS:
             p = np.ascontiguousarray(belief["p"], dtype=np.float64)
             keep.append(p)

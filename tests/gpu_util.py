@@ -52,8 +52,8 @@ def collect(model, out: H.LeafBuffers) -> dict:
         sp = {k: host(v)[..., :A * n] for k, v in out.sprime.items()}
         if model.kind == H.ROCKSAMPLE:
             sp["w"] = sp["w"].reshape(A, n)
-        elif model.kind == H.MARS:
-            sp["w"] = sp["w"].reshape(2, A, n)
+        elif model.kind in (H.MARS, H.NAV):
+            sp["w"] = sp["w"].reshape(sp["w"].shape[0], A, n)
         else:
             sp["s"], sp["car"] = sp["s"].reshape(A, n), sp["car"].reshape(A, n)
             for f in ("px", "py", "goal"):
