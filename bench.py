@@ -18,6 +18,9 @@ Workloads (all synthetic, seeded; see workloads/):
   mars11, mars15, mars20  multi-agent RockSample (n, n) with n rocks,
         |A| = 256, 400, 625, K=500, horizon 90, both robots move east in
         rollouts; 128 leaves with n in {500,250,125,63,32}, depth 1..30
+  nav13 navigation in a partially known 13x13 map (124 unknown cells), |A|=9,
+        horizon 90, gate-then-goal rollouts; 1024 leaves with n in
+        {2000,1000,500,250,125}; search at K = 100, 500, 1000, 2000
 """
 import argparse
 import json
@@ -64,7 +67,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rs15", choices=["rs15", "rs7", "ped16", "mix64", "mars11", "mars15", "mars20"])
+    ap.add_argument("--workload", default="rs15", choices=["rs15", "rs7", "ped16", "mix64", "mars11", "mars15", "mars20", "nav13"])
     ap.add_argument("--leaves", type=int, default=0, help="leaves per batch (0 = workload default)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -110,6 +113,12 @@ def mars_ops(m):
     return dict(step=step, sense_extra=PHILOX_OPS + 2 * 6, upper=3 + 6 * m, group=12, reduce=3)
 
 
+def nav_ops():
+    occ = 8                                   # bounds test, cell table, unknown-bit select
+    step = PHILOX_OPS + 6 + occ + 6           # failure draw, move, occupancy, reward
+    return dict(step=step, policy=3 * occ + 12, obs=2 * PHILOX_OPS + 8 * (occ + 4), upper=8, group=12, reduce=3)
+
+
 def ped_ops(P):
     ped = 30                                  # Irwin-Hall, heading, sqrt, 2 div, rotation, update
     step = (P + 1) * PHILOX_OPS + 6 + P * ped + 5 * P + 3
@@ -127,6 +136,10 @@ def algorithmic_ops(desc, n, A, expand_steps, rollout_steps):
         return (n * c["step"] * A                # update step recomputed per action tile
                 + pairs * (c["step"] + c["upper"] + c["group"] + c["reduce"])
                 + sense_pairs * c["sense_extra"] + rollout_steps * c["step"])
+    if desc["kind"] == 3:
+        c = nav_ops()
+        return (n * c["step"] * A + pairs * (c["step"] + c["obs"] + c["upper"] + c["group"] + c["reduce"])
+                + rollout_steps * (c["step"] + c["policy"]))
     c = ped_ops(desc["n_peds"])
     return (n * c["step"] * A + pairs * (c["step"] + c["obs"] + c["upper"] + c["group"] + c["reduce"])
             + rollout_steps * c["step"])
@@ -160,6 +173,13 @@ def build(ctx, args):
         for i in range(B):
             n_leaf = max(1, 500 >> (i % 5))
             lf = W.mars_leaf(desc, 500, n_leaf, 1000 + i, depth=1 + i % 30)
+            items.append((desc, lf, 7, (0, 1 << 30, 90)))
+    elif wl == "nav13":
+        B = args.leaves or 1024
+        desc = W.nav_model(1)
+        for i in range(B):
+            n_leaf = max(1, 2000 >> (i % 5))
+            lf = W.nav_leaf(desc, 2000, n_leaf, 1000 + i, depth=1 + i % 30)
             items.append((desc, lf, 7, (0, 1 << 30, 90)))
     elif wl == "ped16":
         B = args.leaves or 512
@@ -206,6 +226,8 @@ def build(ctx, args):
                 par = H.rocksample_states(lf["x"], lf["y"], lf["rocks"], lf["term"])
             elif d["kind"] == 2:
                 par = H.mars_states(lf["pos"], lf["rocks"], lf["term"])
+            elif d["kind"] == 3:
+                par = H.nav_states(lf["x"], lf["y"], lf["cells"], lf["term"])
             else:
                 par = H.pednav_states(lf["s"], lf["level"], lf["term"], lf["px"], lf["py"], lf["goal"])
             pids = torch.from_numpy(lf["ids"].astype(np.int32)).cuda()
@@ -537,7 +559,8 @@ def despot_analogue(desc, seconds, K=500, seed=3, max_depth=90, xi=0.95):
 
     rc = oracle.cfg(0, 1 << 30, max_depth)
     gamma = desc["gamma"]
-    belief = W.mars_belief(desc) if desc["kind"] == 2 else W.rocksample_belief(desc)
+    belief = (W.mars_belief(desc) if desc["kind"] == 2 else W.nav_belief(desc) if desc["kind"] == 3
+              else W.rocksample_belief(desc))
     root_states = oracle.sample_scenarios(desc, belief, K, seed, 0)
     ids = np.arange(K, dtype=np.uint32)
     U, L, _ = oracle.rollout_bounds(desc, rc, root_states, ids, np.zeros(K, np.int32), seed, 0)
@@ -582,6 +605,14 @@ def despot_analogue(desc, seconds, K=500, seed=3, max_depth=90, xi=0.95):
     dt = time.perf_counter() - t0
     return dict(nodes=nodes, trials=trials, expansions=expansions, elapsed_s=round(dt, 3),
                 scenario_steps_per_s=round(steps / dt, 1), l_root=round(root.l, 5), u_root=round(root.u, 5))
+
+
+def search_config(desc, seconds):
+    if desc["kind"] == 3:
+        return ("navigation %dx%d, %d unknown cells, K in {100, 500, 1000, 2000}, max depth 90, %.1f s planning "
+                "step" % (desc["n"], desc["n"], desc["n_unknown"], seconds))
+    return "%s %dx%d, %d rocks, K=500, max depth 90, %.1f s planning step" % (
+        "multi-agent RockSample" if desc["kind"] == 2 else "RockSample", desc["n"], desc["n"], desc["m"], seconds)
 
 
 def main():
@@ -696,6 +727,34 @@ def main():
                                elapsed_s=round(res["elapsed_s"], 3), arena_full=res["arena_full"]))
             log("search", search[-1])
 
+    if args.workload == "nav13" and args.search_seconds > 0:
+        # the scenario-count study: tree size within the planning time at
+        # K = 100 .. 2000, one search thread (GPU-DESPOT analogue) and eight
+        # with the leaf batcher (HyP analogue), against the DESPOT analogue
+        import workloads as W
+        desc = items[0][0]
+        m = wl["models"][id(desc)]
+        search = []
+        for K in (100, 500, 1000, 2000):
+            row = dict(K=K)
+            for name, threads, nb in (("gpu_despot", 1, 0), ("hyp", 8, 8)):
+                extra = dict(c_a=0.0, c_o=0.0) if threads == 1 else {}
+                res = ctx.search(m, W.nav_belief(desc), K=K, n_threads=threads, max_depth=90, batch_leaves=nb,
+                                 time_budget_s=args.search_seconds, rollout=H.rollout_cfg(0, 1 << 30, 90), seed=3,
+                                 arena_bytes=32 << 30, **extra)
+                row[name] = dict(threads=threads, leaf_batcher=nb > 0,
+                                 trials_per_s=round(res["trials"] / res["elapsed_s"], 1),
+                                 expansions=res["expansions"], nodes=res["nodes"], depth=res["max_depth_reached"],
+                                 root_gap=round(res["u_root"] - res["l_root"], 4),
+                                 elapsed_s=round(res["elapsed_s"], 3), arena_full=res["arena_full"])
+            if not args.no_cpu_baseline:
+                desp = despot_analogue(desc, args.search_seconds, K=K)
+                row["despot_analogue"] = desp
+                row["speedup_gpu_despot"] = round(row["gpu_despot"]["nodes"] / desp["nodes"], 1)
+                row["speedup_hyp_despot"] = round(row["hyp"]["nodes"] / desp["nodes"], 1)
+            log("search", row)
+            search.append(row)
+
     sur = None
     if args.workload == "rs15" and args.surrogate_epochs > 0:
         log("surrogate comparison...")
@@ -706,7 +765,7 @@ def main():
         log("cpu baseline (oracle)...")
         cpu = cpu_baseline(items, args.cpu_seconds)
         cpu["value"] = round(cpu["value"], 1)
-        if search:
+        if search and items[0][0]["kind"] != 3:  # navigation's study carries its own comparison
             # the paper's metric: tree size built within the planning time,
             # relative to DESPOT (here its one-thread host analogue)
             desp = despot_analogue(items[0][0], args.search_seconds)
@@ -726,12 +785,15 @@ def main():
                        "%d synthetic leaves",
                  mix64="MIX64: 64 planner instances (RockSample 7..20 / driving, K in {100,200,500}); "
                        "%d leaves in one launch")
+    names["nav13"] = ("NAV13 leaf expansion: navigation in a partially known 13x13 map, 124 unknown cells, |A|=9, "
+                      "horizon 90, gate-then-goal rollouts; %d synthetic leaves (n in {2000,1000,500,250,125}, "
+                      "depth 1..30)")
     for size in (11, 15, 20):
         names["mars%d" % size] = ("MARS%d leaf expansion: multi-agent RockSample %dx%d, %d rocks, |A|=%d, K=500, "
                                   "horizon 90, both robots move east in rollouts; %%d synthetic leaves "
                                   "(n in {500,250,125,63,32}, depth 1..30)" % (size, size, size, size,
                                                                                (5 + size) ** 2))
-    variants = ("rocksample", "driving<=8", "driving<=16", "driving<=32", "multi-agent rocksample")
+    variants = ("rocksample", "driving<=8", "driving<=16", "driving<=32", "multi-agent rocksample", "navigation")
     per_class = [dict(model=variants[v], max_n=64 << c, tiles=n, threads=ct, persistent=cp, xcd_remap=cx)
                  for v, c, ct, cp, cx, n in batch.group_schedules()]
     out = dict(metric=METRIC, value=round(value, 1), unit="scenario-steps/s", n_gpus=1, steps=args.steps,
@@ -742,10 +804,7 @@ def main():
                            rollout_steps=roll_steps, split_by_size_class=batch.split(), schedule=per_class,
                            hip_graph=True, autotune_ms=tuned_ms),
                roofline=roofline, cpu_baseline=cpu,
-               search=dict(config="%s %dx%d, %d rocks, K=500, max depth 90, %.1f s planning step"
-                           % ("multi-agent RockSample" if items[0][0]["kind"] == 2 else "RockSample",
-                              items[0][0]["n"], items[0][0]["n"], items[0][0]["m"], args.search_seconds),
-                           runs=search) if search else None,
+               search=dict(config=search_config(items[0][0], args.search_seconds), runs=search) if search else None,
                surrogate=sur)
     print(json.dumps(out), flush=True)
     batch.close()

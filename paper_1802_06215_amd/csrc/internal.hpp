@@ -243,10 +243,11 @@ hipError_t launch_classes(const LeafTask *d_tasks, const Tile *d_tiles, TileQueu
                           uint64_t mask = ~0ull);
 // Default schedule of a group whose largest leaf has n_max scenarios.
 // Latency form (a few leaves, split groups): two scenarios per lane up to
-// 256 lanes, one workgroup per tile, XCD-contiguous.  Throughput form (one
-// group per model): RockSample one wavefront per tile (the most tiles in
-// flight, barriers of a single wavefront), driving as the latency form;
-// workgroups in tile order (largest first spreads over the XCDs).
+// 256 lanes (navigation: 1024), one workgroup per tile, XCD-contiguous.
+// Throughput form (one group per model): both RockSample models one
+// wavefront per tile (the most tiles in flight, barriers of a single
+// wavefront), driving and navigation as the latency form; workgroups in
+// tile order (largest first spreads over the XCDs).
 Schedule class_default_schedule(int32_t n_max, int32_t max_threads, int32_t mode = -1);
 hipError_t configure_expand_kernels();
 

@@ -620,13 +620,14 @@ __device__ __forceinline__ int remap_xcd(int b, int grid) {
 }
 
 // MODE 0: RockSample only; 1: crowd driving only; 2: both; 3: multi-agent
-// RockSample only; 4: navigation only.  Workgroups of the driving and
-// navigation models are capped at 256 lanes (register state, hashed
-// observations).
+// RockSample only; 4: navigation only.  Workgroups of the driving model are
+// capped at 256 lanes so its per-lane state can stay in registers;
+// navigation (83 registers) takes up to 1024, because one large leaf's LDS
+// carve-up leaves room for one workgroup per CU.
 template <int MODE>
 constexpr bool small_obs_mode() { return MODE == 0 || MODE == 3; }
 template <int MODE>
-constexpr int max_threads() { return small_obs_mode<MODE>() ? 512 : 256; }
+constexpr int max_threads() { return small_obs_mode<MODE>() ? 512 : MODE == 4 ? 1024 : 256; }
 // RockSample tiles: keep 7 wavefronts per SIMD resident (at most 72 VGPRs,
 // no spills); the driving model's register state decides its own.
 template <int MODE>

@@ -551,7 +551,7 @@ void hdx::plan_classes(const LeafTask *tasks, const int8_t *variant, Tile *tiles
 
 Schedule hdx::class_default_schedule(int32_t n_max, int32_t max_threads, int32_t mode) {
     Schedule s;
-    s.threads = std::min(std::max(64, pow2_at_least(std::max(n_max, 1)) / 2), std::min(256, max_threads));
+    s.threads = std::min(std::max(64, pow2_at_least(std::max(n_max, 1)) / 2), std::min(mode == 4 ? 1024 : 256, max_threads));
     s.persistent = 0;
     s.xcd_remap = mode < 0 ? 1 : 0;
     if (mode == 0 || mode == 3) s.threads = 64;

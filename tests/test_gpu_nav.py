@@ -177,7 +177,8 @@ def test_mixed_batches_match_single_leaves_and_oracle(ctx):
     b = Batch(ctx, len(items), sum(it["desc"]["n_actions"] for it in items))
     b.set_leaves([it["leaf"] for it in items])
     torch.cuda.synchronize()
-    for split, threads, persistent, xcd in ((False, 256, 0, 0), (True, 64, 0, 1), (True, 128, 2, 0)):
+    for split, threads, persistent, xcd in ((False, 256, 0, 0), (False, 1024, 0, 0), (True, 64, 0, 1),
+                                            (True, 512, 2, 0)):
         print("mixed batch split=%d schedule" % split, threads, persistent, xcd, flush=True)
         wipe(items)
         b.set_split(split)
