@@ -463,8 +463,12 @@ struct NavOps {
         if (x < 0 || y < 0 || x >= n || y >= n) return 1;
         const int c = M.h->nav_cell[y * n + x];
         if (c < 0) return c == -2 ? 1 : 0;
-        const uint32_t w = c < 32 ? st.m0 : c < 64 ? st.m1 : c < 96 ? st.m2 : st.m3;
-        return (int)((w >> (c & 31)) & 1u);
+        // two 64-bit halves and a select: a four-way select chain becomes a
+        // private array indexed by c / 32 (scratch memory)
+        const uint64_t lo = (uint64_t)st.m0 | ((uint64_t)st.m1 << 32);
+        const uint64_t hi = (uint64_t)st.m2 | ((uint64_t)st.m3 << 32);
+        const uint64_t half = c < 64 ? lo : hi;
+        return (int)((half >> (c & 63)) & 1u);
     }
 
     template <bool kObs>
