@@ -222,3 +222,29 @@ def test_nav_search(ctx, threads, batch, K):
     tol = 1e-4 * max(1.0, abs(res["u0_root"]))
     assert res["l0_root"] - tol <= res["l_root"] <= res["u_root"] + tol <= res["u0_root"] + 2 * tol
     assert res["best_action"] == int(np.argmax(res["action_l"]))
+
+
+def test_upload_rejects_bad_maps(ctx):
+    from paper_1802_06215_amd import HdxError
+    good = W.nav_model(1)
+    ctx.upload_model(good)
+    bad = []
+    d = dict(good, cell=good["cell"].copy())
+    d["cell"][good["wall"], good["gate_x"][0]] = -2  # a gate that is not unknown cell 0
+    bad.append((d, -1))
+    d = dict(good, cell=good["cell"].copy())
+    d["cell"][12, good["goal_x"]] = -2  # the goal on a wall
+    bad.append((d, -1))
+    d = dict(good, cell=good["cell"].copy())
+    ys, xs = np.nonzero(d["cell"] >= 2)
+    d["cell"][ys[1], xs[1]] = d["cell"][ys[0], xs[0]]  # one unknown index used twice
+    bad.append((d, -1))
+    bad.append((dict(good, p_err=1.0), -1))
+    bad.append((dict(good, n=4, cell=np.full((4, 4), -1)), -4))  # grids of 5..16 only
+    for desc, code in bad:
+        with pytest.raises(HdxError) as e:
+            ctx.upload_model(desc)
+        assert e.value.code == code
+    with pytest.raises(HdxError) as e:
+        ctx.upload_model(dict(W.mars_model(7, 8, 1), n=1))  # two robots need a grid of 2 or more
+    assert e.value.code == -4
