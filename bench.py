@@ -13,7 +13,8 @@ Workloads (all synthetic, seeded; see workloads/):
   rs15  RockSample 15x15, 15 rocks, |A|=20, K=500, horizon 90, move-east
         rollouts; 2048 leaves with n in {500,250,125,63,32}, depth 1..30
   rs7   RockSample 7x7, 8 rocks, |A|=13, K=100, rollouts of depth 30
-  ped16 crowd driving, 16 pedestrians, 5 goals, |A|=3, K=500, rollouts 50
+  ped16 crowd driving, 16 pedestrians, 5 goals, |A|=3, K=500, rollouts 50;
+        search with 6, 12 and 20 pedestrians (the element-count study)
   mix64 64 planner instances (RockSample 7..20 / driving, K in 100..500)
   mars11, mars15, mars20  multi-agent RockSample (n, n) with n rocks,
         |A| = 256, 400, 625, K=500, horizon 90, both robots move east in
@@ -558,10 +559,10 @@ def despot_analogue(desc, seconds, K=500, seed=3, max_depth=90, xi=0.95):
     import oracle
     import workloads as W
 
-    rc = oracle.cfg(0, 1 << 30, max_depth)
+    rc = oracle.cfg(0, 50, max_depth) if desc["kind"] == 1 else oracle.cfg(0, 1 << 30, max_depth)
     gamma = desc["gamma"]
     belief = (W.mars_belief(desc) if desc["kind"] == 2 else W.nav_belief(desc) if desc["kind"] == 3
-              else W.rocksample_belief(desc))
+              else W.pednav_belief(desc) if desc["kind"] == 1 else W.rocksample_belief(desc))
     root_states = oracle.sample_scenarios(desc, belief, K, seed, 0)
     ids = np.arange(K, dtype=np.uint32)
     U, L, _ = oracle.rollout_bounds(desc, rc, root_states, ids, np.zeros(K, np.int32), seed, 0)
@@ -609,6 +610,9 @@ def despot_analogue(desc, seconds, K=500, seed=3, max_depth=90, xi=0.95):
 
 
 def search_config(desc, seconds):
+    if desc["kind"] == 1:
+        return ("crowd driving with 6, 12 and 20 pedestrians, 5 goals, K=500, rollouts of 50, max depth 50, "
+                "%.1f s planning step" % seconds)
     if desc["kind"] == 3:
         return ("navigation %dx%d, %d unknown cells, K in {100, 500, 1000, 2000}, max depth 90, %.1f s planning "
                 "step" % (desc["n"], desc["n"], desc["n_unknown"], seconds))
@@ -728,6 +732,34 @@ def main():
                                elapsed_s=round(res["elapsed_s"], 3), arena_full=res["arena_full"]))
             log("search", search[-1])
 
+    if args.workload == "ped16" and args.search_seconds > 0:
+        # the element-count study: the same search with 6, 12 and 20
+        # pedestrians (K = 500, rollouts of 50, depth 50) against the DESPOT
+        # analogue on the same model
+        import workloads as W
+        search = []
+        for P in (6, 12, 20):
+            dp = W.pednav_model(P, 5, 1)
+            mp = ctx.upload_model(dp)
+            row = dict(peds=P)
+            for name, threads, nb in (("gpu_despot", 1, 0), ("hyp", 8, 8)):
+                extra = dict(c_a=0.0, c_o=0.0) if threads == 1 else {}
+                res = ctx.search(mp, W.pednav_belief(dp), K=500, n_threads=threads, max_depth=50, batch_leaves=nb,
+                                 time_budget_s=args.search_seconds, rollout=H.rollout_cfg(0, 50), seed=3,
+                                 arena_bytes=8 << 30, **extra)
+                row[name] = dict(threads=threads, leaf_batcher=nb > 0,
+                                 trials_per_s=round(res["trials"] / res["elapsed_s"], 1),
+                                 expansions=res["expansions"], nodes=res["nodes"], depth=res["max_depth_reached"],
+                                 root_gap=round(res["u_root"] - res["l_root"], 4),
+                                 elapsed_s=round(res["elapsed_s"], 3), arena_full=res["arena_full"])
+            if not args.no_cpu_baseline:
+                desp = despot_analogue(dp, args.search_seconds, K=500, max_depth=50)
+                row["despot_analogue"] = desp
+                row["speedup_gpu_despot"] = round(row["gpu_despot"]["nodes"] / desp["nodes"], 1)
+                row["speedup_hyp_despot"] = round(row["hyp"]["nodes"] / desp["nodes"], 1)
+            log("search", row)
+            search.append(row)
+
     if args.workload == "nav13" and args.search_seconds > 0:
         # the scenario-count study: tree size within the planning time at
         # K = 100 .. 2000, one search thread (GPU-DESPOT analogue) and eight
@@ -766,7 +798,7 @@ def main():
         log("cpu baseline (oracle)...")
         cpu = cpu_baseline(items, args.cpu_seconds)
         cpu["value"] = round(cpu["value"], 1)
-        if search and items[0][0]["kind"] != 3:  # navigation's study carries its own comparison
+        if search and items[0][0]["kind"] in (0, 2):  # the driving and navigation studies carry their own
             # the paper's metric: tree size built within the planning time,
             # relative to DESPOT (here its one-thread host analogue)
             desp = despot_analogue(items[0][0], args.search_seconds)

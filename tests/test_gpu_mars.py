@@ -257,3 +257,21 @@ def test_surrogate_rejects_mars(ctx):
     with pytest.raises(HdxError) as e:
         H.features(ctx, m, st, torch.zeros(4, dtype=torch.int32, device="cuda"), 90)
     assert e.value.code == -6
+
+
+def test_no_rocks_search_finds_both_exits(ctx):
+    """No rocks and no rollouts: expansions and Eq. 4 backups alone must find
+    the two robots' exit value 10 gamma^(n-1-x1) + 10 gamma^(n-1-x2), and the
+    first joint action moves both robots east."""
+    from paper_1802_06215_amd import hdx as H
+    n = 3
+    desc = dict(kind=2, n=n, m=0, rock_x=np.zeros(0, np.int32), rock_y=np.zeros(0, np.int32), gamma=0.95,
+                start=(0, 1, 0, 0), n_actions=25)
+    m = ctx.upload_model(desc)
+    belief = dict(pos=(0, 1, 1, 0, 0, 0), p=np.zeros(0))
+    res = ctx.search(m, belief, K=4, n_threads=1, max_depth=6, time_budget_s=20.0, max_trials=4000,
+                     gap_epsilon=1e-9, rollout=H.rollout_cfg(0, 0), arena_bytes=256 << 20)
+    exact = 10 * 0.95 ** 2 + 10 * 0.95 ** 1
+    assert abs(res["u0_root"] - exact) < 1e-5 and res["l0_root"] == 0.0
+    assert abs(res["l_root"] - exact) < 1e-5 and abs(res["u_root"] - exact) < 1e-5
+    assert res["best_action"] == 2 * 5 + 2
