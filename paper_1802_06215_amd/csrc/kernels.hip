@@ -171,7 +171,10 @@ __device__ void block_exclusive_scan(int32_t *a, int len, int32_t *scratch) {
 __device__ __forceinline__ bool has_states(const StatesPtr &S) { return S.w != nullptr || S.s != nullptr; }
 
 // One (leaf, action) tile.
-template <class Ops>
+// kGroup: compile the element-level rollout of small leaves in (the
+// few-leaf launch a search thread makes; the batched launch leaves it out,
+// since its registers would cost the driving model a wavefront per SIMD).
+template <class Ops, bool kGroup = false>
 __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char *lds, const LdsLayout &Ly) {
     float *gpow_lds = (float *)(lds + Ly.gpow);
     const MView M = make_view(T->model, gpow_lds);
@@ -231,6 +234,13 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
     const StatesPtr sprime = load_states(&T->sprime);
     const bool write_leaf = (a == 0);
     const bool pair_out = has_states(sprime);
+    // element-level rollouts when the leaf is small enough for every
+    // scenario to get a group of lanes of wavefront 0 (tile-uniform)
+    int group_lanes = 0;
+    if constexpr (Ops::kGroupRollout && kGroup) {
+        const int G = pow2_at_least(M.h->n_peds > 0 ? M.h->n_peds : 1);
+        if (n * G <= 64) group_lanes = G;
+    }
 
     // -- gather + update + expand + bounds + rollouts (Eq. 10, 12, 13) ------
     // Every lane of a wavefront runs the same number of rounds, so a
@@ -274,12 +284,26 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
             U = Ops::upper(M, st);
         }
         float L = 0.0f;
+        bool rolled = false;
+        if constexpr (Ops::kGroupRollout && kGroup) {
+            if (group_lanes > 0) {
+                // n <= 64: one round, every scenario in wavefront 0; the
+                // stepped state is stored first (the rollout works on a copy)
+                if (valid && pair_out) Ops::store(M, sprime, (int64_t)a * n + k, st);
+                int ns = 0;
+                if (wid == 0) L = Ops::group_rollout(M, RP, st, id, depth + 1, n, group_lanes, ns);
+                if (valid) my_roll += ns;
+                rolled = true;
+            }
+        }
         if (valid) {
             const int64_t pk = (int64_t)a * n + k;
-            if (pair_out) Ops::store(M, sprime, pk, st);
-            int ns = 0;
-            L = rollout<Ops>(M, RP, st, id, depth + 1, ns);
-            my_roll += ns;
+            if (!rolled) {
+                if (pair_out) Ops::store(M, sprime, pk, st);
+                int ns = 0;
+                L = rollout<Ops>(M, RP, st, id, depth + 1, ns);
+                my_roll += ns;
+            }
             if constexpr (!Ops::kSmallObs) {
                 zk[k] = z;
                 ub[k] = U;
@@ -607,9 +631,9 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
     __syncthreads();  // LDS is reused by the next tile
 }
 
-template <int PM>
+template <int PM, bool kGroup>
 __device__ __forceinline__ void run_ped(const HDX_CONST LeafTask *T, int a, unsigned char *lds, const LdsLayout &Ly) {
-    run_tile<PedOps<PM>>(T, a, lds, Ly);
+    run_tile<PedOps<PM>, kGroup>(T, a, lds, Ly);
 }
 
 __device__ __forceinline__ int remap_xcd(int b, int grid) {
@@ -633,7 +657,7 @@ constexpr int max_threads() { return small_obs_mode<MODE>() ? 512 : MODE == 4 ? 
 template <int MODE>
 constexpr int min_waves() { return small_obs_mode<MODE>() ? 7 : 1; }
 
-template <int MODE, int PM>
+template <int MODE, int PM, bool kGroup = false>
 __device__ __forceinline__ void run_mode(const HDX_CONST LeafTask *T, int a, unsigned char *lds, const LdsLayout &Ly) {
     if (MODE == 3) {
         run_tile<MarsOps>(T, a, lds, Ly);
@@ -642,7 +666,7 @@ __device__ __forceinline__ void run_mode(const HDX_CONST LeafTask *T, int a, uns
     } else if (MODE == 0 || (MODE == 2 && T->kind == HDX_ROCKSAMPLE)) {
         run_tile<RsOps>(T, a, lds, Ly);
     } else {
-        run_ped<PM>(T, a, lds, Ly);
+        run_ped<PM, kGroup>(T, a, lds, Ly);
     }
 }
 
@@ -704,7 +728,7 @@ __global__ __launch_bounds__(max_threads<MODE>()) void expand_args(const ArgPack
     int i = 0;
     while (i + 1 < n_leaves && t >= P->tile_begin[i + 1]) ++i;
     const HDX_CONST LeafTask *T = &P->t[i];
-    run_mode<MODE, PM>(T, t - P->tile_begin[i], lds, Ly);
+    run_mode<MODE, PM, true>(T, t - P->tile_begin[i], lds, Ly);
 }
 
 template <int MODE, int PM>

@@ -101,6 +101,11 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     return make_uint4(c0, c1, c2, c3);
 }
 
+struct RolloutParams {
+    uint32_t k0, k1;
+    int32_t policy, const_action, max_steps, max_depth, n_actions;
+};
+
 // ---------------------------------------------------------------------------
 // RockSample: one packed int32 word per scenario.
 // ---------------------------------------------------------------------------
@@ -113,6 +118,7 @@ struct RsOps {
     static constexpr bool kSmallObs = true;       // observations 0 (none), 1, 2 (sensor readings)
     static constexpr bool kLdsModel = false;      // expansion reads no per-lane table from LDS
     static constexpr bool kWaveUpper = true;      // upper bound evaluated by whole wavefronts
+    static constexpr bool kGroupRollout = false;  // one lane per scenario in rollouts
 
     __device__ static void load(const MView &, const StatesPtr &S, int64_t p, State &st) { st.w = S.w[p]; }
     __device__ static void make_terminal(State &st) { st.w = 1 << 30; }
@@ -246,6 +252,7 @@ struct MarsOps {
     static constexpr bool kSmallObs = true;  // 9 joint observations
     static constexpr bool kLdsModel = false;
     static constexpr bool kWaveUpper = true;
+    static constexpr bool kGroupRollout = false;
     static constexpr int kGone0 = 20, kTerm = 30;
     static constexpr int kFar = 62;  // beyond any Manhattan distance on a 31 x 31 grid
 
@@ -429,6 +436,7 @@ struct NavOps {
     static constexpr bool kSmallObs = false;  // 8 reading bits: 256 observations
     static constexpr bool kLdsModel = true;   // discount powers staged in LDS
     static constexpr bool kWaveUpper = false;
+    static constexpr bool kGroupRollout = false;
     struct WaveUpper {};
     static constexpr uint32_t kDx = nav_pack_dir(false), kDy = nav_pack_dir(true);
     static constexpr uint64_t kAction = nav_action_table();
@@ -573,7 +581,36 @@ struct PedOps {
     static constexpr bool kSmallObs = false;      // 64-bit hashed observations
     static constexpr bool kLdsModel = true;       // discount powers and goal points staged in LDS
     static constexpr bool kWaveUpper = false;     // per-lane upper bound
+    static constexpr bool kGroupRollout = true;   // small leaves: one lane per pedestrian in rollouts
     struct WaveUpper {};
+
+    // One pedestrian's walk towards its goal with heading noise from the
+    // four words of its block (shared by the one-lane step and the
+    // element-level rollout, so both take the same operations).
+    __device__ static void move_ped(const MView &M, const uint4 &u, int goal, float &px, float &py) {
+        const int32_t sum = (int32_t)((u.x >> 8) + (u.y >> 8) + (u.z >> 8) + (u.w >> 8));
+        const float noise = (float)(sum - 33554430) * M.h->ih_scale;
+        const float gx = M.goal_x(goal), gy = M.goal_y(goal);
+        const float dx = gx - px;
+        const float dy = gy - py;
+        const float dist = __builtin_sqrtf(dx * dx + dy * dy);
+        const float step_len = M.h->step_len;
+        if (dist <= step_len) {
+            px = gx;
+            py = gy;
+        } else {
+            const float ux = dx / dist, uy = dy / dist;
+            const float t = M.h->half_sigma * noise;
+            const float t2 = t * t;
+            const float den = 1.0f + t2;
+            const float c = (1.0f - t2) / den;
+            const float sn = (2.0f * t) / den;
+            const float rx = ux * c - uy * sn;
+            const float ry = ux * sn + uy * c;
+            px = px + step_len * rx;
+            py = py + step_len * ry;
+        }
+    }
 
     __device__ static void load(const MView &M, const StatesPtr &S, int64_t p, State &st) {
         st.s = S.s[p];
@@ -622,32 +659,11 @@ struct PedOps {
         if (a == 2 && !failed && level > 0) level = level - 1;
         const float v = 0.5f * (float)level;
         const float s_next = st.s + v * M.h->dt;
-        const float step_len = M.h->step_len, half_sigma = M.h->half_sigma;
 #pragma unroll
         for (int j = 0; j < PM; ++j) {
             if (j < M.h->n_peds) {
                 const uint4 u = philox(id, depth, (uint32_t)(j + 1), kTagStep, k0, k1);
-                const int32_t sum = (int32_t)((u.x >> 8) + (u.y >> 8) + (u.z >> 8) + (u.w >> 8));
-                const float noise = (float)(sum - 33554430) * M.h->ih_scale;
-                const float gx = M.goal_x(st.goal[j]), gy = M.goal_y(st.goal[j]);
-                const float dx = gx - st.px[j];
-                const float dy = gy - st.py[j];
-                const float dist = __builtin_sqrtf(dx * dx + dy * dy);
-                if (dist <= step_len) {
-                    st.px[j] = gx;
-                    st.py[j] = gy;
-                } else {
-                    const float ux = dx / dist, uy = dy / dist;
-                    const float t = half_sigma * noise;
-                    const float t2 = t * t;
-                    const float den = 1.0f + t2;
-                    const float c = (1.0f - t2) / den;
-                    const float sn = (2.0f * t) / den;
-                    const float rx = ux * c - uy * sn;
-                    const float ry = ux * sn + uy * c;
-                    st.px[j] = st.px[j] + step_len * rx;
-                    st.py[j] = st.py[j] + step_len * ry;
-                }
+                move_ped(M, u, st.goal[j], st.px[j], st.py[j]);
             }
         }
         bool collided = false;
@@ -713,11 +729,93 @@ struct PedOps {
         }
         return brake ? 2 : 0;
     }
-};
 
-struct RolloutParams {
-    uint32_t k0, k1;
-    int32_t policy, const_action, max_steps, max_depth, n_actions;
+    // Element-level rollouts of a small leaf (Sec. III-D: the parallelism
+    // inside one step of a scenario): scenario g of the wavefront's first n
+    // lanes runs on lanes [g*G, g*G + G), lane g*G + j stepping pedestrian
+    // j; every lane of a group computes the car, the reward and the value,
+    // and collisions and the braking rule are ORs of the group's ballot
+    // bits.  The operations and their order are those of the one-lane
+    // rollout, so the results are the same bits.  Called by all 64 lanes of
+    // a wavefront (n * G <= 64, G a power of two >= the pedestrian count);
+    // lane k < n receives scenario k's value and step count.
+    __device__ static float group_rollout(const MView &M, const RolloutParams &P, const State &st, uint32_t id,
+                                          int d0, int n, int G, int &nsteps) {
+        const int lane = (int)__lane_id();
+        const int g = lane / G, j = lane - g * G;
+        const bool active = g < n;
+        const int src = active ? g : 0;
+        float s = __shfl(st.s, src, 64);
+        int level = __shfl(st.level, src, 64);
+        int term = __shfl(st.term, src, 64);
+        const uint32_t sid = (uint32_t)__shfl((int)id, src, 64);
+        float px = 0.0f, py = 0.0f;
+        int goal = 0;
+#pragma unroll
+        for (int q = 0; q < PM; ++q) {
+            const float vx = __shfl(st.px[q], src, 64);
+            const float vy = __shfl(st.py[q], src, 64);
+            const int vg = __shfl(st.goal[q], src, 64);
+            if (j == q) {
+                px = vx;
+                py = vy;
+                goal = vg;
+            }
+        }
+        const bool ped = active && j < M.h->n_peds;
+        if (!active) term = 1;
+        const uint64_t gmask = (G >= 64 ? ~0ull : ((1ull << G) - 1ull)) << (g * G);
+        int n_roll = P.max_steps;
+        if (P.max_depth >= 0 && P.max_depth - d0 < n_roll) n_roll = P.max_depth - d0;
+        if (n_roll > kHorizon) n_roll = kHorizon;
+        float value = 0.0f;
+        int steps = 0;
+        for (int t = 0; t < n_roll; ++t) {
+            if (term) break;
+            const uint32_t depth = (uint32_t)(d0 + t);
+            int a;
+            if (P.policy == HDX_POLICY_CONST) {
+                a = P.const_action;
+            } else if (P.policy == HDX_POLICY_RANDOM) {
+                a = (int)(philox(sid, depth, 0, kTagPolicy, P.k0, P.k1).x % (uint32_t)P.n_actions);
+            } else {
+                const float ahead = px - s;
+                const bool b = ped && ahead >= 0.0f && ahead <= 3.0f && fabsf(py) < 1.5f;
+                a = (__ballot(b) & gmask) ? 2 : 0;
+            }
+            const uint4 u0 = philox(sid, depth, 0, kTagStep, P.k0, P.k1);
+            const bool failed = (uint64_t)u0.x < M.h->fail_thr;
+            if (a == 0 && !failed && level < M.h->n_levels - 1) level = level + 1;
+            if (a == 2 && !failed && level > 0) level = level - 1;
+            const float v = 0.5f * (float)level;
+            const float s_next = s + v * M.h->dt;
+            if (ped) {
+                const uint4 u = philox(sid, depth, (uint32_t)(j + 1), kTagStep, P.k0, P.k1);
+                move_ped(M, u, goal, px, py);
+            }
+            bool hit = false;
+            if (level > 0 && ped) {
+                const float ddx = px - s_next;
+                const float d2 = ddx * ddx + py * py;
+                hit = d2 < M.h->coll_r2;
+            }
+            const bool collided = (__ballot(hit) & gmask) != 0;
+            float reward = M.h->r_step;
+            if (collided) {
+                reward = M.h->r_step + M.h->r_collision;
+                term = 1;
+            } else if (s_next >= M.h->path_len) {
+                reward = M.h->r_step + M.h->r_goal;
+                term = 1;
+            }
+            s = s_next;
+            value += M.gpow_uniform(t) * reward;
+            ++steps;
+        }
+        const int from = (lane < n ? lane : 0) * G;
+        nsteps = __shfl(steps, from, 64);
+        return __shfl(value, from, 64);
+    }
 };
 
 // Default-policy rollout from depth d0 (Eq. 13): discounted from d0, stops
