@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (x3), to scale HBM byte counters")
     ap.add_argument("--search-seconds", type=float, default=1.0,
-                    help="planning budget of each search measurement (rs15 and marsNN; 0 = skip)")
+                    help="planning budget of each search measurement (rs15, marsNN, nav13, ped16; 0 = skip)")
     ap.add_argument("--schedule", default="", help="threads,persistent,xcd_remap for every size class "
                     "(skips the autotuner)")
     ap.add_argument("--class-schedule", action="append", default=[],
