@@ -117,6 +117,10 @@ struct ChunkStore {
 struct Act {
     double r;
     int32_t child_begin, n_children, visits;
+    // sum over the children of n_child / n_parent times their u and l, in
+    // child order; recomputed whenever a child's bounds change, so Eq. 4 and
+    // Eq. 8 read one value per action instead of visiting every child
+    double su = 0.0, sl = 0.0;
 };
 
 struct Request {
@@ -252,23 +256,34 @@ struct Search {
 
     double root_gap() const { return std::max(nodes[0].u - nodes[0].l, 0.0); }
 
-    // Eq. 4 for one expanded node
+    // The weighted child sums of one action (the inner sums of Eq. 4).
+    void refresh(Act &x, int32_t parent_n) {
+        double su = 0.0, sl = 0.0;
+        for (int c = 0; c < x.n_children; ++c) {
+            const Node &k = nodes[x.child_begin + c];
+            const double w = (double)k.n / (double)parent_n;
+            su += w * k.u;
+            sl += w * k.l;
+        }
+        x.su = su;
+        x.sl = sl;
+    }
+
+    // Eq. 4 for one expanded node; its new bounds go into its parent
+    // action's sums
     void bellman(Node &b) {
         double bu = -std::numeric_limits<double>::infinity(), bl = bu;
         for (int a = 0; a < A; ++a) {
             const Act &x = acts[b.act_begin + a];
-            double su = 0.0, sl = 0.0;
-            for (int c = 0; c < x.n_children; ++c) {
-                const Node &k = nodes[x.child_begin + c];
-                const double w = (double)k.n / (double)b.n;
-                su += w * k.u;
-                sl += w * k.l;
-            }
-            bu = std::max(bu, x.r + d.gamma * su);
-            bl = std::max(bl, x.r + d.gamma * sl);
+            bu = std::max(bu, x.r + d.gamma * x.su);
+            bl = std::max(bl, x.r + d.gamma * x.sl);
         }
         b.u = bu;
         b.l = bl;
+        if (b.parent >= 0) {
+            const Node &p = nodes[b.parent];
+            refresh(acts[p.act_begin + b.action], p.n);
+        }
     }
 
     // Action bound of Eq. 8: u(b,a) plus the scenario-based exploration bonus
@@ -278,12 +293,7 @@ struct Search {
         const double nb = (double)b.n * (double)std::max(b.visits, 1);
         for (int a = 0; a < A; ++a) {
             const Act &x = acts[b.act_begin + a];
-            double su = 0.0;
-            for (int c = 0; c < x.n_children; ++c) {
-                const Node &k = nodes[x.child_begin + c];
-                su += (double)k.n / (double)b.n * k.u;
-            }
-            double v = x.r + d.gamma * su;
+            double v = x.r + d.gamma * x.su;
             if (c_a_abs > 0.0) {
                 if (x.visits == 0) {
                     v = std::numeric_limits<double>::infinity();
@@ -321,6 +331,7 @@ struct Search {
         const int parent_n = b.n;
         nodes[node_id].act_begin = (int32_t)acts.size();
         for (int a = 0; a < A; ++a) {
+            const size_t ai = acts.size();
             acts.push_back(Act{(double)rm[a], (int32_t)nodes.size(), nch[a], 0});
             for (int c = 0; c < nch[a]; ++c) {
                 Node k;
@@ -334,6 +345,7 @@ struct Search {
                 k.idx_dev = (const int32_t *)(r.dev + r.L.perm) + (size_t)a * parent_n + co[a * cap + c];
                 nodes.push_back(k);
             }
+            refresh(acts[ai], parent_n);
         }
         nodes[node_id].state = 2;
         int md = parent_depth + 1;
