@@ -182,20 +182,23 @@ struct RsOps {
         return u + 10.0f * M.gpow_lane(M.h->grid - 1 - x);
     }
 
-    // Per-rock terms of the last common cell, kept across the rounds of a
-    // tile (wavefront-uniform except ci, which lane i holds for rock i).
+    // Partial sums of the last common cell, kept across the rounds of a
+    // tile: entry 16 g + m (lane of tab0, or of tab1 past 63) is the sum of
+    // the terms of the good rocks of group g (rocks 4g .. 4g+3) when their
+    // qualities read m.
     struct WaveUpper {
         int x = -1, y = -1;
-        float ci = 0.0f, exit = 0.0f;
+        float tab0 = 0.0f, tab1 = 0.0f, exit = 0.0f;
     };
 
-    // The same value, bit for bit.  Robot cells are deterministic, so the
-    // live scenarios of a tile usually share one cell: then lane i holds
-    // rock i's discounted reward for the wavefront (recomputed only when the
-    // cell changes) and every lane adds the terms of its good rocks, masking
-    // the others to +0 (which leaves the sum unchanged): a sign-extended bit
-    // field, an and, an add and a lane read per rock.  Called by all 64
-    // lanes of a wavefront.
+    // The same value, bit for bit, whichever way it is computed: the good
+    // rocks' terms 10 gamma^d are summed within groups of four rocks in
+    // index order, the group sums added in group order, then the exit term.
+    // Robot cells are deterministic, so the live scenarios of a tile usually
+    // share one cell: then the wavefront tabulates every group's sum for all
+    // 16 quality patterns (rebuilt only when the cell changes) and each lane
+    // adds one table entry per group of four rocks (a bit-field extract, a
+    // cross-lane read and an add).  Called by all 64 lanes of a wavefront.
     __device__ static float upper_wave(const MView &M, const State &st, WaveUpper &wu) {
         const bool live = !((st.w >> 30) & 1);
         const int x = st.w & 31, y = (st.w >> 5) & 31;
@@ -203,29 +206,46 @@ struct RsOps {
         if (lv == 0) return 0.0f;
         const int leader = __ffsll((unsigned long long)lv) - 1;
         const int x0 = __shfl(x, leader, 64), y0 = __shfl(y, leader, 64);
+        const int nr = M.h->n_rocks;
+        const int ng = (nr + 3) >> 2;
         if (__ballot(live && (x != x0 || y != y0)) != 0) {
             // cells differ: per-lane terms, discount powers read from the model table
             if (!live) return 0.0f;
             float u = 0.0f;
-            for (int i = 0; i < M.h->n_rocks; ++i)
-                if ((st.w >> (10 + i)) & 1)
-                    u += 10.0f * M.gg[abs(x - M.h->rock_x[i]) + abs(y - M.h->rock_y[i])];
+            for (int g = 0; g < ng; ++g) {
+                float p = 0.0f;
+                for (int i = 4 * g; i < 4 * g + 4 && i < nr; ++i)
+                    if ((st.w >> (10 + i)) & 1)
+                        p = p + 10.0f * M.gg[abs(x - M.h->rock_x[i]) + abs(y - M.h->rock_y[i])];
+                u = u + p;
+            }
             return u + 10.0f * M.gg[M.h->grid - 1 - x];
         }
         const int xs = __builtin_amdgcn_readfirstlane(x0), ys = __builtin_amdgcn_readfirstlane(y0);
-        const int nr = M.h->n_rocks;
         if (xs != wu.x || ys != wu.y) {
             const int lane = (int)__lane_id();
-            wu.ci = lane < nr ? 10.0f * M.gg[abs(xs - M.h->rock_x[lane]) + abs(ys - M.h->rock_y[lane])] : 0.0f;
+            const float ci = lane < nr ? 10.0f * M.gg[abs(xs - M.h->rock_x[lane]) + abs(ys - M.h->rock_y[lane])] : 0.0f;
+            // entry e = 16 g + m: group g's good rocks under pattern m, in index order
+            float t0 = 0.0f, t1 = 0.0f;
+            const int g0 = lane >> 4, g1 = 4 + (lane >> 4), m = lane & 15;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const float c0 = __shfl(ci, (4 * g0 + b) & 63, 64);
+                const float c1 = __shfl(ci, (4 * g1 + b) & 63, 64);
+                if (((m >> b) & 1) && 4 * g0 + b < nr) t0 = t0 + c0;
+                if (((m >> b) & 1) && 4 * g1 + b < nr) t1 = t1 + c1;
+            }
+            wu.tab0 = t0;
+            wu.tab1 = t1;
             wu.exit = 10.0f * M.gpow_uniform(M.h->grid - 1 - xs);
             wu.x = xs;
             wu.y = ys;
         }
         float u = 0.0f;
-        for (int i = 0; i < nr; ++i) {
-            const int c = __builtin_amdgcn_readlane(__float_as_int(wu.ci), i);
-            const int keep = __builtin_amdgcn_sbfe(st.w, 10 + i, 1);  // all ones if rock i is good
-            u = u + __int_as_float(keep & c);
+        for (int g = 0; g < ng; ++g) {
+            const int pat = (int)__builtin_amdgcn_ubfe((uint32_t)st.w, 10 + 4 * g, 4);
+            const float t = g < 4 ? __shfl(wu.tab0, 16 * g + pat, 64) : __shfl(wu.tab1, 16 * (g - 4) + pat, 64);
+            u = u + t;
         }
         u = u + wu.exit;
         return live ? u : 0.0f;
@@ -347,13 +367,19 @@ struct MarsOps {
     }
 
     // Every good rock sampled by the nearer robot on arrival, plus each
-    // robot's exit reward at its shortest exit time (rocks in index order,
-    // then robot 1's exit, then robot 2's).
+    // robot's exit reward at its shortest exit time (rocks summed within
+    // groups of four in index order, the group sums in group order, then
+    // robot 1's exit, then robot 2's).
     __device__ static float upper(const MView &M, const State &st) {
         if ((st.p >> kTerm) & 1) return 0.0f;
         float u = 0.0f;
-        for (int i = 0; i < M.h->n_rocks; ++i)
-            if ((st.rk >> i) & 1) u += 10.0f * M.gg[near(st.p, M.h->rock_x[i], M.h->rock_y[i])];
+        const int nr = M.h->n_rocks;
+        for (int g = 0; g < (nr + 3) >> 2; ++g) {
+            float p = 0.0f;
+            for (int i = 4 * g; i < 4 * g + 4 && i < nr; ++i)
+                if ((st.rk >> i) & 1) p = p + 10.0f * M.gg[near(st.p, M.h->rock_x[i], M.h->rock_y[i])];
+            u = u + p;
+        }
         const int n1 = M.h->grid - 1;
         if (!((st.p >> kGone0) & 1)) u += 10.0f * M.gg[n1 - (st.p & 31)];
         if (!((st.p >> (kGone0 + 1)) & 1)) u += 10.0f * M.gg[n1 - ((st.p >> 10) & 31)];
@@ -362,14 +388,15 @@ struct MarsOps {
 
     struct WaveUpper {
         int32_t p = -1;
-        float ci = 0.0f, e0 = 0.0f, e1 = 0.0f;
+        float tab0 = 0.0f, tab1 = 0.0f, e0 = 0.0f, e1 = 0.0f;
     };
 
     // The same value, bit for bit.  Robot cells are deterministic, so the
-    // live scenarios of a tile usually share the robots' row: then lane i
-    // holds rock i's term for the wavefront and every lane masks the terms
-    // of its bad rocks to +0, as RockSample's bound does; a robot that has
-    // left adds +0 for its exit.  Called by all 64 lanes of a wavefront.
+    // live scenarios of a tile usually share the robots' row: then the
+    // wavefront tabulates each group of four rocks' sum for all 16 quality
+    // patterns, as RockSample's bound does, and each lane adds one entry per
+    // group; a robot that has left adds +0 for its exit.  Called by all 64
+    // lanes of a wavefront.
     __device__ static float upper_wave(const MView &M, const State &st, WaveUpper &wu) {
         const bool live = !((st.p >> kTerm) & 1);
         const uint64_t lv = __ballot(live);
@@ -379,19 +406,31 @@ struct MarsOps {
         if (__ballot(live && st.p != p0) != 0) return upper(M, st);
         const int32_t ps = __builtin_amdgcn_readfirstlane(p0);
         const int nr = M.h->n_rocks;
+        const int ng = (nr + 3) >> 2;
         if (ps != wu.p) {
             const int lane = (int)__lane_id();
-            wu.ci = lane < nr ? 10.0f * M.gg[near(ps, M.h->rock_x[lane], M.h->rock_y[lane])] : 0.0f;
+            const float ci = lane < nr ? 10.0f * M.gg[near(ps, M.h->rock_x[lane], M.h->rock_y[lane])] : 0.0f;
+            float t0 = 0.0f, t1 = 0.0f;
+            const int g0 = lane >> 4, g1 = 4 + (lane >> 4), m = lane & 15;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const float c0 = __shfl(ci, (4 * g0 + b) & 63, 64);
+                const float c1 = __shfl(ci, (4 * g1 + b) & 63, 64);
+                if (((m >> b) & 1) && 4 * g0 + b < nr) t0 = t0 + c0;
+                if (((m >> b) & 1) && 4 * g1 + b < nr) t1 = t1 + c1;
+            }
+            wu.tab0 = t0;
+            wu.tab1 = t1;
             const int n1 = M.h->grid - 1;
             wu.e0 = ((ps >> kGone0) & 1) ? 0.0f : 10.0f * M.gpow_uniform(n1 - (ps & 31));
             wu.e1 = ((ps >> (kGone0 + 1)) & 1) ? 0.0f : 10.0f * M.gpow_uniform(n1 - ((ps >> 10) & 31));
             wu.p = ps;
         }
         float u = 0.0f;
-        for (int i = 0; i < nr; ++i) {
-            const int c = __builtin_amdgcn_readlane(__float_as_int(wu.ci), i);
-            const int keep = __builtin_amdgcn_sbfe(st.rk, i, 1);  // all ones if rock i is good
-            u = u + __int_as_float(keep & c);
+        for (int g = 0; g < ng; ++g) {
+            const int pat = (int)__builtin_amdgcn_ubfe((uint32_t)st.rk, 4 * g, 4);
+            const float t = g < 4 ? __shfl(wu.tab0, 16 * g + pat, 64) : __shfl(wu.tab1, 16 * (g - 4) + pat, 64);
+            u = u + t;
         }
         u = u + wu.e0;
         u = u + wu.e1;
