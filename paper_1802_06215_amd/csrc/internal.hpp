@@ -174,7 +174,8 @@ __host__ __device__ inline LdsLayout make_layout(int32_t np, bool small = false)
     L.child = take(4u * np);
     L.perm = take(4u * L.p2);
     L.misc = take(64 + 4u * 64);
-    L.gpow = take(4u * (kGpowLds + 2 * kMaxGoals));
+    // discount powers, goal points, and the navigation cell table (int16)
+    L.gpow = take(4u * (kGpowLds + 2 * kMaxGoals) + 2u * HDX_MAX_NAV_GRID * HDX_MAX_NAV_GRID);
     L.total = o;
     return L;
 }

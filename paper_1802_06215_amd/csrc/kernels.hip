@@ -22,6 +22,8 @@
 //    chunk partials added in order.
 // Either way the floating-point order depends only on the data, never on
 // the workgroup size or the schedule.
+#include <type_traits>
+
 #include "models.hpp"
 
 namespace hdx {
@@ -218,6 +220,7 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
         stepc[1] = 0;
     }
     if constexpr (Ops::kLdsModel) stage_gpow(T->model, gpow_lds);
+    if constexpr (std::is_same<Ops, NavOps>::value) stage_cells(T->model, gpow_lds);
     __syncthreads();
 
     RolloutParams RP;
@@ -842,6 +845,7 @@ template <class Ops>
 __global__ __launch_bounds__(256) void bounds_kernel(const BoundsArgs A) {
     __shared__ float gpow_lds[kModelLdsFloats];
     stage_gpow(A.model, gpow_lds);
+    if constexpr (std::is_same<Ops, NavOps>::value) stage_cells(A.model, gpow_lds);
     __syncthreads();
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= A.n) return;

@@ -33,6 +33,7 @@ struct MView {
     const HDX_CONST uint32_t *thr;
     const HDX_CONST float *gg;
     const float *gl;
+    const int16_t *cl;  // navigation cell table, staged in LDS after the goal points
     __device__ float gpow_uniform(int j) const { return gg[j]; }
     __device__ float gpow_lane(int j) const { return j < kGpowLds ? gl[j] : gg[j]; }
     // goal point coordinates, staged in LDS after the discount powers
@@ -46,6 +47,7 @@ __device__ __forceinline__ MView make_view(const DevModel *gm, const float *gpow
     v.thr = (const HDX_CONST uint32_t *)gm->sense_thr_m1;
     v.gg = (const HDX_CONST float *)gm->gpow;
     v.gl = gpow_lds;
+    v.cl = (const int16_t *)(gpow_lds + kGpowLds + 2 * kMaxGoals);
     return v;
 }
 
@@ -62,18 +64,26 @@ __device__ __forceinline__ StatesPtr load_states(const HDX_CONST StatesPtr *s) {
 }
 
 // Stage the first kGpowLds discount powers and the goal points of a model
-// into LDS (kModelLdsFloats floats; the caller synchronises afterwards).
-constexpr int kModelLdsFloats = kGpowLds + 2 * kMaxGoals;
+// into LDS, and for navigation its cell table after them (kModelLdsFloats
+// floats in all; the caller synchronises afterwards).
+constexpr int kNavCells = HDX_MAX_NAV_GRID * HDX_MAX_NAV_GRID;
+constexpr int kModelLdsFloats = kGpowLds + 2 * kMaxGoals + kNavCells / 2;
 __device__ __forceinline__ void stage_gpow(const DevModel *gm, float *gpow_lds) {
     const HDX_CONST float *g = (const HDX_CONST float *)gm->gpow;
     const HDX_CONST ModelHdr *h = (const HDX_CONST ModelHdr *)&gm->h;
-    for (int j = threadIdx.x; j < kModelLdsFloats; j += blockDim.x) {
+    for (int j = threadIdx.x; j < kGpowLds + 2 * kMaxGoals; j += blockDim.x) {
         float v;
         if (j < kGpowLds) v = g[j];
         else if (j < kGpowLds + kMaxGoals) v = h->goal_x[j - kGpowLds];
         else v = h->goal_y[j - kGpowLds - kMaxGoals];
         gpow_lds[j] = v;
     }
+}
+// The navigation cell table, after the goal points (navigation kernels only).
+__device__ __forceinline__ void stage_cells(const DevModel *gm, float *gpow_lds) {
+    const HDX_CONST ModelHdr *h = (const HDX_CONST ModelHdr *)&gm->h;
+    int16_t *cells = (int16_t *)(gpow_lds + kGpowLds + 2 * kMaxGoals);
+    for (int c = threadIdx.x; c < kNavCells; c += blockDim.x) cells[c] = h->nav_cell[c];
 }
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
@@ -508,7 +518,7 @@ struct NavOps {
     __device__ static int occupied(const MView &M, const State &st, int x, int y) {
         const int n = M.h->grid;
         if (x < 0 || y < 0 || x >= n || y >= n) return 1;
-        const int c = M.h->nav_cell[y * n + x];
+        const int c = M.cl[y * n + x];
         if (c < 0) return c == -2 ? 1 : 0;
         // two 64-bit halves and a select: a four-way select chain becomes a
         // private array indexed by c / 32 (scratch memory)
