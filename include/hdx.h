@@ -25,6 +25,8 @@
  * Scenario states: struct of arrays ("hdx_states"), one element per scenario
  *  - RockSample: w[k] packs x in bits 0-4, y in bits 5-9, rock i's quality
  *    (1 = good) in bit 10+i, terminal in bit 30.
+ *  - Multi-agent RockSample: two rows of w (robots, rocks); navigation: five
+ *    rows of w (robot, then the unknown cells' occupancy); see hdx_states.
  *  - Crowd driving: s[k] car position (m) along the path; car[k] = speed
  *    level (bits 0-7, speed 0.5 m/s per level) | terminal (bit 8);
  *    px/py/goal are [pedestrian][stride] arrays (FP32 metres and the index
