@@ -158,7 +158,7 @@ __host__ __device__ inline LdsLayout make_layout(int32_t np, bool small = false)
         L.dslot = take(4u * chunks);
         L.off = take(4u * 64u);
         L.ubuf = L.lbuf = L.perm = L.off;  // not used by the small path
-        L.child = take(4u * np);
+        L.child = take(2u * np);  // per scenario: key | rank << 5 (int16)
         L.misc = take(64 + 4u * 64);
         L.gpow = L.misc;
         L.total = o;

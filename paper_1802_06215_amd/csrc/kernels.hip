@@ -191,6 +191,7 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
     float *ub = (float *)(lds + Ly.ubuf);
     float *lb = (float *)(lds + Ly.lbuf);
     int32_t *child = (int32_t *)(lds + Ly.child);
+    int16_t *kchild = (int16_t *)(lds + Ly.child);  // small alphabets: key | rank << 5
     int32_t *permb = (int32_t *)(lds + Ly.perm);
     // per-chunk child counts: over zkey and tab (contiguous)
     int32_t *cnt = (int32_t *)(lds + Ly.zkey);
@@ -347,7 +348,7 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
                     rem &= ~bv;
                 }
                 if (lane == 0) kmask[t] = present;
-                if (valid) child[k] = (int32_t)(key | ((uint32_t)rank << 16));
+                if (valid) kchild[k] = (int16_t)(key | ((uint32_t)rank << 5));
             }
         }
         // mean step reward: sum of this 64-scenario chunk (lanes past n add 0;
@@ -424,9 +425,9 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
         // grouped order: a scenario's place is its child's offset, plus the
         // key's count in earlier chunks, plus its rank inside its chunk
         for (int k = tid; k < n; k += nt) {
-            const int32_t cw = child[k];
-            const int v = cw & 0xFFFF;
-            T->perm[(int64_t)a * n + koff[v] + kc[(k >> 6) * 32 + v] + (cw >> 16)] = k;
+            const int32_t cw = kchild[k];
+            const int v = cw & 31;
+            T->perm[(int64_t)a * n + koff[v] + kc[(k >> 6) * 32 + v] + (cw >> 5)] = k;
             if (T->child_of) T->child_of[(int64_t)a * n + k] = kci[v];
         }
         __syncthreads();  // LDS is reused by the next tile
