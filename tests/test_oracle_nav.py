@@ -181,3 +181,18 @@ def test_leaf_invariants():
     sub = oracle.take_states(d, par, leaf["idx"])
     st, _, _ = oracle.step(d, sub, leaf["ids"][leaf["idx"]], leaf["last_action"], leaf["depth"] - 1, 4, 1)
     assert np.array_equal(st["w"], res["states"]["w"])
+
+
+@pytest.mark.parametrize("x,y,d", [(2, 3, 1), (1, 3, 1), (4, 3, 2), (0, 1, 3), (2, 0, 4), (4, 0, 4)])
+def test_upper_bound_by_distance(x, y, d):
+    """One move per cell of Chebyshev distance d to the goal (2, 4); the
+    bound collects +20 on the d-th move, discounted d - 1 times."""
+    dm = small_map()
+    U, _, _ = oracle.rollout_bounds(dm, oracle.cfg(0, 100), state(x, y, [1, 0, 0, 0]), np.arange(1), 0, 1, 0)
+    assert abs(U[0] - 20 * G ** (d - 1)) < 1e-12
+
+
+def test_upper_bound_terminal_is_zero():
+    dm = small_map()
+    U, L, _ = oracle.rollout_bounds(dm, oracle.cfg(0, 100), state(2, 4, [1, 0, 0, 0], term=1), np.arange(1), 0, 1, 0)
+    assert U[0] == 0.0 and L[0] == 0.0
