@@ -77,7 +77,7 @@ class _Out(C.Structure):
                 ("Labs", C.c_void_p), ("child_of", C.c_void_p), ("perm", C.c_void_p), ("n_children", C.c_void_p),
                 ("child_z", C.c_void_p), ("child_n", C.c_void_p), ("child_off", C.c_void_p),
                 ("child_u0", C.c_void_p), ("child_l0", C.c_void_p), ("r_mean", C.c_void_p),
-                ("expand_steps", C.c_void_p), ("rollout_steps", C.c_void_p)]
+                ("expand_steps", C.c_void_p), ("rollout_steps", C.c_void_p), ("steps", C.c_void_p)]
 
 
 _lib = None
@@ -100,6 +100,8 @@ def lib():
         L.or_expand_leaf.restype = C.c_int
         L.or_rs_sense_threshold.argtypes = [C.c_int32]
         L.or_rs_sense_threshold.restype = C.c_uint64
+        L.or_mix64.argtypes = [C.c_uint64]
+        L.or_mix64.restype = C.c_uint64
         _lib = L
     return _lib
 
@@ -124,7 +126,7 @@ def rs_pack(x, y, rocks, term) -> np.ndarray:
     """RockSample state words from fields (rocks: bool [n, m])."""
     rocks = np.asarray(rocks, dtype=bool)
     n = rocks.shape[0]
-    w = np.full(n, int(x) | (int(y) << 5), dtype=np.int64)
+    w = np.broadcast_to(np.asarray(x, np.int64) | (np.asarray(y, np.int64) << 5), (n,)).copy()
     for i in range(rocks.shape[1]):
         w |= rocks[:, i].astype(np.int64) << (10 + i)
     w |= np.asarray(term, dtype=np.int64) << 30
@@ -367,7 +369,7 @@ def expand_leaf(desc, rcfg, parent, parent_ids, idx, depth, last_action, seed, s
                child_n=np.zeros((A, capc), np.int32), child_off=np.zeros((A, capc), np.int32),
                child_u0=np.zeros((A, capc)), child_l0=np.zeros((A, capc)),
                r_mean=np.zeros(A), expand_steps=np.zeros(1, np.int64),
-               rollout_steps=np.zeros(1, np.int64))
+               rollout_steps=np.zeros(1, np.int64), steps=np.zeros((A, 2), np.int64))
     o = _Out()
     o.states = _soa(desc, res["states"], n)
     if per_pair:
@@ -378,7 +380,7 @@ def expand_leaf(desc, rcfg, parent, parent_ids, idx, depth, last_action, seed, s
         o.r, o.z, o.U, o.L = _ptr(res["r"]), _ptr(res["z"]), _ptr(res["U"]), _ptr(res["L"])
         o.Labs = _ptr(res["Labs"])
     for f in ("ids", "child_of", "perm", "n_children", "child_z", "child_n", "child_off",
-              "child_u0", "child_l0", "r_mean", "expand_steps", "rollout_steps"):
+              "child_u0", "child_l0", "r_mean", "expand_steps", "rollout_steps", "steps"):
         setattr(o, f, _ptr(res[f]))
     M = model(desc)
     rc = lib().or_expand_leaf(C.byref(M), C.byref(rcfg), seed, step_idx,
@@ -461,3 +463,8 @@ def backup(node: Node, gamma: float) -> None:
             node.u = node_value(node, gamma, "u")
             node.l = node_value(node, gamma, "l")
         node = node.parent
+
+
+def mix64(x: int) -> int:
+    """The observation hash's 64-bit mixing function (splitmix64's output step)."""
+    return int(lib().or_mix64(x & 0xFFFFFFFFFFFFFFFF))

@@ -456,7 +456,10 @@ static double nav_upper(const or_model *M, const or_state *st)
     int x = st->w & 15, y = (st->w >> 4) & 15;
     int dx = abs(x - M->nav_goal_x), dy = abs(y - (M->n - 1));
     int d = dx > dy ? dx : dy;
-    return 20.0 * pow(M->gamma, d > 0 ? d - 1 : 0); /* d = 0 (on the goal yet not terminal) is unreachable */
+    /* +20 is paid on entering the goal: from the goal cell itself (a state no
+     * step produces, since entering is terminal) the soonest is to leave and
+     * re-enter, two moves, so the bound is 20 gamma there */
+    return 20.0 * pow(M->gamma, d > 0 ? d - 1 : 1);
 }
 
 /* Default policy: head for the open gate while above the wall, then for the
@@ -809,6 +812,7 @@ typedef struct {
     double *child_u0, *child_l0;  /* [A][cap] */
     double *r_mean;     /* [A] */
     int64_t *expand_steps, *rollout_steps; /* scalars */
+    int64_t *steps;     /* [A][2] per action: expansion steps, rollout steps */
 } or_expand_out;
 
 /* Leaf expansion (Sec. III-D): gather the leaf's scenarios from its parent by
@@ -851,16 +855,17 @@ int or_expand_leaf(const or_model *M, const or_rollout_cfg *C, uint32_t seed, ui
 
     for (int a = 0; a < A; a++) {
         double r_sum = 0.0;
+        int64_t a_exp = 0, a_roll = 0;
         for (int32_t k = 0; k < n; k++) {
             or_state st = leaf[k];
             float r;
             uint64_t z;
-            if (!leaf[k].term) exp_steps += 1;
+            if (!leaf[k].term) a_exp += 1;
             model_step(M, &st, a, seed, step, ids[k], (uint32_t)depth, &r, &z);
             r_sum += (double)r;
             U[k] = model_upper(M, &st);
             double mag = 0.0;
-            L[k] = rollout(M, C, st, seed, step, ids[k], depth + 1, &roll_steps, &mag);
+            L[k] = rollout(M, C, st, seed, step, ids[k], depth + 1, &a_roll, &mag);
             pairs[k].z = z;
             pairs[k].k = k;
             int64_t pk = (int64_t)a * n + k;
@@ -872,6 +877,13 @@ int or_expand_leaf(const or_model *M, const or_rollout_cfg *C, uint32_t seed, ui
             if (out->Labs) out->Labs[pk] = mag;
         }
         if (out->r_mean) out->r_mean[a] = n > 0 ? r_sum / n : 0.0;
+        /* step counts (model steps on non-terminal states) of this action */
+        exp_steps += a_exp;
+        roll_steps += a_roll;
+        if (out->steps) {
+            out->steps[2 * a] = a_exp;
+            out->steps[2 * a + 1] = a_roll;
+        }
 
         /* Eq. 11: one child per distinct observation; a stable sort keeps
          * each child's scenarios in ascending leaf position. */
@@ -920,6 +932,10 @@ int or_expand_leaf(const or_model *M, const or_rollout_cfg *C, uint32_t seed, ui
     free(ch_l);
     return status;
 }
+
+/* The observation hash's mixing function, exposed so the tests can check it
+ * against the published splitmix64 generator. */
+uint64_t or_mix64(uint64_t x) { return mix64(x); }
 
 /* Sensor threshold table, exposed so the tests can check the accuracy law. */
 uint64_t or_rs_sense_threshold(int32_t d2) { return rs_sense_threshold(d2); }

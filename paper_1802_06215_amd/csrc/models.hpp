@@ -570,12 +570,14 @@ struct NavOps {
         z = obs;
     }
 
-    // The goal reward on the shortest 8-connected path, no costs.
+    // The goal reward on the shortest 8-connected path, no costs; it is paid
+    // on entering the goal, so a robot standing on it must leave and re-enter
+    // (two moves).
     __device__ static float upper(const MView &M, const State &st) {
         if ((st.p >> 30) & 1) return 0.0f;
         const int ax = abs((st.p & 15) - M.h->nav_goal_x), ay = abs(((st.p >> 4) & 15) - (M.h->grid - 1));
         const int d = ax > ay ? ax : ay;
-        return 20.0f * M.gpow_lane(d > 0 ? d - 1 : 0);
+        return 20.0f * M.gpow_lane(d > 0 ? d - 1 : 1);
     }
     __device__ static float upper_wave(const MView &M, const State &st, WaveUpper &) { return upper(M, st); }
 

@@ -99,8 +99,8 @@ def compare_leaf(desc, gpu: dict, ref: dict, n: int):
     assert_states_equal(gpu["states"], ref["states"])
     assert np.array_equal(gpu["ids"], ref["ids"])
     assert np.array_equal(gpu["n_children"], ref["n_children"])
-    assert int(gpu["steps"][:, 0].sum()) == ref["expand_steps"]
-    assert int(gpu["steps"][:, 1].sum()) == ref["rollout_steps"]
+    # per action: (expansion steps, rollout steps), element by element
+    assert np.array_equal(gpu["steps"], ref["steps"]), "per-action step counts differ"
     assert np.array_equal(gpu["perm"], ref["perm"])
     for a in range(A):
         nc = int(ref["n_children"][a])

@@ -89,6 +89,7 @@ def test_rs7_root_parity_and_closed_form(ctx, model_seed):
         nc = gpu["n_children"][a]
         assert np.allclose(gpu["child_l0"][a, :nc], want, rtol=1e-6)
     assert int(gpu["steps"][:, 1].sum()) == 9000
+    assert gpu["steps"].tolist() == [[100, 600] if a == 2 else [100, 700] for a in range(desc["n_actions"])]
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3, 4])

@@ -196,3 +196,26 @@ def test_upper_bound_terminal_is_zero():
     dm = small_map()
     U, L, _ = oracle.rollout_bounds(dm, oracle.cfg(0, 100), state(2, 4, [1, 0, 0, 0], term=1), np.arange(1), 0, 1, 0)
     assert U[0] == 0.0 and L[0] == 0.0
+
+
+def test_upper_bound_on_the_goal_cell():
+    """A robot standing on the goal without the episode having ended (no step
+    produces it: entering the goal is terminal) collects +20 soonest by
+    leaving and re-entering, two moves: the bound is 20 gamma.  It must be
+    admissible -- at least the best return, which with the noise off is
+    -0.1 (leave) + gamma 20 (re-enter) -- and consistent, u(s) >= r + gamma u(s')
+    for every action."""
+    dm = small_map()
+    on_goal = state(2, 4, [1, 0, 0, 0])
+    U, _, _ = oracle.rollout_bounds(dm, oracle.cfg(0, 100), on_goal, np.arange(1), 0, 1, 0)
+    assert abs(U[0] - 20 * G) < 1e-12
+    best = float(np.float32(-0.1)) + G * 20.0
+    assert U[0] >= best
+    for a in range(9):
+        nxt, r, _ = oracle.step(dm, on_goal, np.arange(1), a, 0, 1, 0)
+        Un, _, _ = oracle.rollout_bounds(dm, oracle.cfg(0, 100), nxt, np.arange(1), 1, 1, 0)
+        assert U[0] >= float(r[0]) + G * Un[0] - 1e-12, a
+    # the brute-force optimum over three steps from the goal cell is the
+    # leave-and-re-enter return, and the bound is above it
+    v = brute_force(dm, oracle.cfg(1, 0), on_goal, np.arange(1), 0, 3, 1, 0, "l")
+    assert abs(v - best) < 1e-6 and U[0] >= v

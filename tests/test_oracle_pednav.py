@@ -189,3 +189,16 @@ def test_sample_scenarios_goal_prior():
         freq = np.bincount(st["goal"][j], minlength=3) / K
         sd = np.sqrt(gp[j] * (1 - gp[j]) / K) + 1e-12
         assert np.all(np.abs(freq - gp[j]) <= 5 * sd)
+
+
+def test_observation_mixer_is_splitmix64():
+    """The observation hash's mixing step is splitmix64's output function:
+    driven as the generator (state += the golden-ratio increment), it gives
+    the generator's published first outputs from state 0."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "splitmix64_seed0.json")))
+    inc, st = int(g["increment"], 16), 0
+    for want in g["outputs"]:
+        st = (st + inc) & 0xFFFFFFFFFFFFFFFF
+        assert oracle.mix64(st) == int(want, 16)

@@ -144,6 +144,9 @@ def test_rs7_root_closed_form():
             assert res["r_mean"][a] == 0.0
         assert res["rollout_steps"] == g["root_rollout_steps"]
         assert res["expand_steps"] == g["root_expand_steps"]
+        for a in range(A):
+            want = g["root_steps_east_action"] if a == 2 else g["root_steps_other_action"]
+            assert res["steps"][a].tolist() == want
         root = oracle.Node(None, 100, 0.0, 0.0)
         oracle.attach_children(d, root, res)
         oracle.backup(root, d["gamma"])

@@ -84,6 +84,12 @@ def _leaf(kind, seed, n_parent=200, n_leaf=150):
     return d, lf, rc
 
 
+def _action_states(d, sp, a):
+    if d["kind"] == 0:
+        return dict(w=np.ascontiguousarray(sp["w"][a]))
+    return {f: np.ascontiguousarray(sp[f][a] if f in ("s", "car") else sp[f][:, a]) for f in sp}
+
+
 @pytest.mark.parametrize("kind,seed", [(0, 1), (0, 2), (1, 1), (1, 2)])
 def test_expansion_invariants(kind, seed):
     d, lf, rc = _leaf(kind, seed)
@@ -124,6 +130,14 @@ def test_expansion_invariants(kind, seed):
         assert np.all(res["r"][a][term == 1] == 0)
     # expansion steps count the non-terminal scenarios once per action
     assert res["expand_steps"] == A * int((term == 0).sum())
+    assert np.all(res["steps"][:, 0] == int((term == 0).sum()))
+    # each action's rollout steps are those of rollouts from its own stepped
+    # states at depth + 1 (a count credited to another action fails here)
+    for a in range(A):
+        sp_a = _action_states(d, res["sprime"], a)
+        _, _, st = oracle.rollout_bounds(d, rc, sp_a, res["ids"], lf["depth"] + 1, 7, 1)
+        assert res["steps"][a, 1] == int(np.sum(st))
+    assert res["steps"][:, 1].sum() == res["rollout_steps"]
 
 
 @pytest.mark.parametrize("kind", [0, 1])

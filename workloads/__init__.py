@@ -163,23 +163,29 @@ def _sorted_subset(rng, universe: int, size: int) -> np.ndarray:
 
 def rocksample_leaf(model: dict, n_parent: int, n_leaf: int, seed: int,
                     k_root: int | None = None, p_term: float = 0.02,
-                    depth: int | None = None) -> dict:
+                    depth: int | None = None, shared_cell: bool = True) -> dict:
     """A synthetic RockSample leaf with the shape of one deep in a DESPOT tree.
 
     The parent holds ``n_parent`` scenarios sharing one robot cell (position
     is deterministic in RockSample), random rock qualities and a few terminal
-    scenarios; the leaf is an ascending subset of ``n_leaf`` of them.
+    scenarios; the leaf is an ascending subset of ``n_leaf`` of them.  With
+    shared_cell=False every scenario draws its own cell (states the model
+    never produces from one root, but valid inputs of an expansion).
     """
     rng = np.random.default_rng(np.random.SeedSequence([0x4C4541, n_parent, n_leaf, seed]))
     n, m = model["n"], model["m"]
     k_root = max(k_root or n_parent, n_parent)
-    return dict(x=int(rng.integers(0, n)), y=int(rng.integers(0, n)),
+    leaf = dict(x=int(rng.integers(0, n)), y=int(rng.integers(0, n)),
                 rocks=rng.random((n_parent, m)) < 0.5,
                 term=rng.random(n_parent) < p_term,
                 ids=_sorted_subset(rng, k_root, n_parent),
                 idx=_sorted_subset(rng, n_parent, n_leaf),
                 depth=int(rng.integers(1, 16)) if depth is None else depth,
                 last_action=int(rng.integers(0, model["n_actions"])))
+    if not shared_cell:
+        leaf["x"] = rng.integers(0, n, n_parent)
+        leaf["y"] = rng.integers(0, n, n_parent)
+    return leaf
 
 
 def mars_leaf(model: dict, n_parent: int, n_leaf: int, seed: int,
