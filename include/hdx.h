@@ -252,6 +252,32 @@ hdx_status hdx_sample_scenarios(hdx_ctx *ctx, const hdx_model *model, const hdx_
 hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves,
                            hdx_stream stream);
 
+/* ---- Expansion that allocates nothing ---------------------------------- */
+
+/* For callers that cannot allocate device or host memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * hdx_expand_leaf_noalloc expands leaves exactly as hdx_expand_leaf does
+ * (same arguments, outputs, validation and errors; results bit-identical),
+ * but the call's own device buffers -- the leaf descriptors, the (leaf,
+ * action) tile list and the tile-queue heads -- live in a fixed array of
+ * the library, HDX_NOALLOC_SCRATCH_BYTES on each GPU it runs on, held until
+ * the process ends, and the host staging it copies them from is set up by
+ * hdx_init.  The call itself allocates nothing: no hipMalloc, hipFree or
+ * other allocating routine, host or device.
+ * Limits: at most HDX_NOALLOC_MAX_LEAVES leaves and HDX_NOALLOC_MAX_TILES
+ * tiles (the sum of the leaves' action counts) per call; beyond them the
+ * call returns HDX_E_CAPACITY and launches nothing.
+ * Sharing: every call on a GPU uses that GPU's one array, which keeps the
+ * last call's contents (the queue heads are rewritten by every call).  Calls
+ * on one stream are ordered; calls that overlap on one GPU -- on other
+ * streams, from other threads or other contexts -- race and must not be
+ * made.  Up to four leaves of one kernel travel in the kernel arguments, as
+ * in hdx_expand_leaf, and leave the array untouched. */
+#define HDX_NOALLOC_MAX_LEAVES 512
+#define HDX_NOALLOC_MAX_TILES 65536
+#define HDX_NOALLOC_SCRATCH_BYTES (1 << 20)
+hdx_status hdx_expand_leaf_noalloc(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves, hdx_stream stream);
+
 /* ---- Batched form: many leaves, many instances, one launch ------------- */
 
 /* A reusable batch of leaves (node-level parallelism of Sec. III-D, leaves

@@ -1,6 +1,7 @@
 // Host runtime behind the C ABI: context, model upload (device tables),
 // argument validation, descriptor staging and kernel launches.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -51,6 +52,41 @@ uint64_t prob_threshold(double p) {
 
 }  // namespace
 
+// ---- Fixed scratch of the expansion entry point that allocates nothing ----
+// Leaf descriptors, the tile list and the tile queues of one call, at fixed
+// offsets.  Each GPU the library runs on holds its own copy until the process
+// ends.  In host code `scratch` names a host-side stand-in, never the device
+// memory: host code uses only the per-device address that
+// hipGetSymbolAddress returns (kept in g_scratch_addr).
+namespace {
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t kNaTasksOff = 0;
+constexpr size_t kNaTilesOff = align256((size_t)HDX_NOALLOC_MAX_LEAVES * sizeof(LeafTask));
+constexpr size_t kNaQueueOff = kNaTilesOff + align256((size_t)HDX_NOALLOC_MAX_TILES * sizeof(Tile));
+constexpr size_t kNaBytes = kNaQueueOff + align256((size_t)kGroups * sizeof(TileQueue));
+static_assert(kNaBytes <= HDX_NOALLOC_SCRATCH_BYTES, "no-allocation scratch larger than documented");
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+// Device address of this device's scratch copy; call with `device` current.
+static hipError_t scratch_address(int device, unsigned char **out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_addr[device] = (unsigned char *)ptr;
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
+}
+
 struct hdx_ctx {
     int32_t device = 0;
     int32_t n_cu = 256;
@@ -61,6 +97,17 @@ struct hdx_ctx {
     hipStream_t cls_stream[kGroups] = {};  // one stream per launch group (default priority)
     Schedule sched{256, 0, 1};
     bool sched_fixed = false;
+    // expansion without allocation: the device's fixed scratch array (its
+    // address from hipGetSymbolAddress), pinned host staging and events made
+    // here at set-up, and fixed host arrays for planning
+    unsigned char *na_scratch = nullptr;
+    LeafTask *na_h_tasks = nullptr;
+    Tile *na_h_tiles = nullptr;
+    TileQueue *na_h_queue = nullptr;
+    hipEvent_t na_done = nullptr, na_fork = nullptr, na_join[kGroups] = {};
+    bool na_used = false;
+    int8_t na_var[HDX_NOALLOC_MAX_LEAVES];
+    int32_t na_order[HDX_NOALLOC_MAX_LEAVES];
 };
 
 struct hdx_model {
@@ -68,13 +115,19 @@ struct hdx_model {
     DevModel *d_model = nullptr;
 };
 
-static hdx_status fail(hdx_ctx *ctx, hdx_status code, const std::string &msg) {
-    if (ctx) ctx->err = msg;
+// Error texts go into a string whose capacity hdx_init reserves, so
+// reporting an error allocates nothing.
+constexpr size_t kErrCap = 512;
+
+static hdx_status fail(hdx_ctx *ctx, hdx_status code, const char *msg) {
+    if (ctx) ctx->err.assign(msg, strnlen(msg, kErrCap - 1));
     return code;
 }
 
 static hdx_status hip_fail(hdx_ctx *ctx, hipError_t e, const char *what) {
-    return fail(ctx, HDX_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    char buf[kErrCap];
+    snprintf(buf, sizeof(buf), "%s: %s", what, hipGetErrorString(e));
+    return fail(ctx, HDX_E_DEVICE, buf);
 }
 
 extern "C" {
@@ -113,6 +166,24 @@ hdx_status hdx_init(int32_t device, hdx_ctx **out) {
         hdx_fini(ctx);
         return HDX_E_DEVICE;
     }
+    // set-up of hdx_expand_leaf_noalloc: the scratch's device address, host
+    // staging and events, so that the call itself allocates nothing
+    ctx->err.reserve(kErrCap);
+    if (scratch_address(device, &ctx->na_scratch) != hipSuccess) {
+        hdx_fini(ctx);
+        return HDX_E_DEVICE;
+    }
+    if (hipHostMalloc((void **)&ctx->na_h_tasks, HDX_NOALLOC_MAX_LEAVES * sizeof(LeafTask)) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->na_h_tiles, HDX_NOALLOC_MAX_TILES * sizeof(Tile)) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->na_h_queue, kGroups * sizeof(TileQueue)) != hipSuccess) {
+        hdx_fini(ctx);
+        return HDX_E_NOMEM;
+    }
+    if (hipEventCreateWithFlags(&ctx->na_done, hipEventDisableTiming) != hipSuccess ||
+        !create_events(&ctx->na_fork, ctx->na_join)) {
+        hdx_fini(ctx);
+        return HDX_E_DEVICE;
+    }
     *out = ctx;
     return HDX_OK;
 }
@@ -131,6 +202,14 @@ hdx_status hdx_fini(hdx_ctx *ctx) {
         if (s.done) hipEventDestroy(s.done);
         destroy_events(&s.fork, s.join);
     }
+    if (ctx->na_done) {
+        hipEventSynchronize(ctx->na_done);
+        hipEventDestroy(ctx->na_done);
+    }
+    destroy_events(&ctx->na_fork, ctx->na_join);
+    if (ctx->na_h_tasks) hipHostFree(ctx->na_h_tasks);
+    if (ctx->na_h_tiles) hipHostFree(ctx->na_h_tiles);
+    if (ctx->na_h_queue) hipHostFree(ctx->na_h_queue);
     for (int c = 0; c < kGroups; ++c)
         if (ctx->cls_stream[c]) hipStreamDestroy(ctx->cls_stream[c]);
     delete ctx;
@@ -639,6 +718,137 @@ hdx_status grow_pinned(hdx_ctx *ctx, LeafTask **h_tasks, LeafTask **d_tasks, int
 
 }  // namespace
 
+namespace {
+
+// Small calls of one kernel carry their descriptors in the kernel arguments
+// (the multi-agent and navigation models have kernels of their own;
+// RockSample and driving share one).  Returns false if the call is not such
+// a call; otherwise launches and sets *st.
+bool launch_in_args(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves, const Shape &sh, hipStream_t stream,
+                    hdx_status *st) {
+    const int kernels = (sh.has_rs || sh.has_ped ? 1 : 0) + sh.has_mars + sh.has_nav;
+    if (n_leaves > kArgLeaves || kernels > 1) return false;
+    const Variant v0 = pick_variant(sh.has_rs, sh.has_ped, sh.ped_max, sh.n_max, sh.has_mars, sh.has_nav);
+    static_assert(sizeof(ArgPack) <= 4096, "kernel argument pack too large");
+    ArgPack pack;
+    memset(&pack, 0, sizeof(pack));
+    pack_leaves(leaves, n_leaves, pack.t, nullptr);
+    pack.tile_begin[0] = 0;
+    for (int32_t i = 0; i < n_leaves; ++i) pack.tile_begin[i + 1] = pack.tile_begin[i] + pack.t[i].n_actions;
+    pack.n_leaves = n_leaves;
+    pack.n_max = v0.n_max;
+    const Schedule sch =
+        ctx->sched_fixed ? ctx->sched : class_default_schedule(v0.n_max, variant_max_threads(v0), -2);
+    pack.xcd_remap = sch.xcd_remap;
+    const hipError_t e = launch_expand_args(pack, v0, sch, stream);
+    *st = e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "expand launch");
+    return true;
+}
+
+// Copy a planned call's descriptors, tiles and queue heads from host staging
+// to their device buffers on `hs`, launch its groups, and record `done`
+// after the launch (the host staging may be rewritten once it has fired).
+hdx_status launch_staged(hdx_ctx *ctx, const LeafTask *h_tasks, const Tile *h_tiles, TileQueue *h_queue,
+                         LeafTask *d_tasks, Tile *d_tiles, TileQueue *d_queue, int32_t n_leaves, int64_t n_tiles,
+                         const ClassPlan &plan, hipStream_t hs, hipEvent_t fork, const hipEvent_t *join,
+                         hipEvent_t done) {
+    for (int g = 0; g < kGroups; ++g) h_queue[g] = TileQueue{0, 0, (int32_t)plan.count[g], 0};
+    hipError_t e = hipMemcpyAsync(d_tasks, h_tasks, n_leaves * sizeof(LeafTask), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_tiles, h_tiles, n_tiles * sizeof(Tile), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_queue, h_queue, kGroups * sizeof(TileQueue), hipMemcpyHostToDevice, hs);
+    if (e != hipSuccess) return hip_fail(ctx, e, "descriptor copy");
+    int32_t no_lds[kGroups] = {};
+    Schedule sch[kGroups];
+    // a launch far smaller than the GPU (a search's leaf batch) is latency
+    // bound: wider workgroups finish each tile sooner
+    const bool few = n_tiles < 8 * (int64_t)ctx->n_cu;
+    for (int g = 0; g < kGroups; ++g) {
+        sch[g] = ctx->sched_fixed ? ctx->sched
+                                  : class_default_schedule(plan.n_max[g], variant_max_threads(group_variant(g)),
+                                                           few ? -2 : group_variant(g).mode);
+        if (few) sch[g].xcd_remap = 0;
+    }
+    e = launch_classes_forked(d_tasks, d_tiles, d_queue, plan, no_lds, sch, ctx->n_cu, hs, ctx->cls_stream, fork,
+                              join);
+    if (e != hipSuccess) return hip_fail(ctx, e, "expand launch");
+    e = hipEventRecord(done, hs);
+    return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "event record");
+}
+
+// The unsplit plan of plan_classes (one group per model variant, filed
+// under its largest leaf's size class; largest leaf first, a leaf's tiles in
+// action order; leaves dealt to the XCDs in turn and their tile lists
+// interleaved), built from the leaf descriptors with fixed arrays only:
+// order[] holds n_leaves leaf indices, tiles[] receives every tile.
+void plan_fixed(const LeafTask *tasks, const int8_t *variant, int32_t n_leaves, Tile *tiles, int32_t *order,
+                ClassPlan *plan) {
+    int32_t vmax[kModelVariants] = {0};
+    for (int32_t i = 0; i < n_leaves; ++i) vmax[variant[i]] = std::max(vmax[variant[i]], tasks[i].n);
+    auto group = [&](int32_t i) { return variant[i] * kSizeClasses + size_class(vmax[variant[i]]); };
+    for (int g = 0; g < kGroups; ++g) {
+        plan->count[g] = 0;
+        plan->n_max[g] = 0;
+    }
+    for (int32_t i = 0; i < n_leaves; ++i) {
+        plan->count[group(i)] += tasks[i].n_actions;
+        plan->n_max[group(i)] = std::max(plan->n_max[group(i)], tasks[i].n);
+    }
+    int64_t at = 0;
+    for (int g = 0; g < kGroups; ++g) {
+        plan->begin[g] = at;
+        at += plan->count[g];
+    }
+    // leaves by (group, size descending, index): insertion sort
+    auto before = [&](int32_t x, int32_t y) {
+        const int gx = group(x), gy = group(y);
+        if (gx != gy) return gx < gy;
+        if (tasks[x].n != tasks[y].n) return tasks[x].n > tasks[y].n;
+        return x < y;
+    };
+    for (int32_t i = 0; i < n_leaves; ++i) {
+        int32_t j = i;
+        while (j > 0 && before(i, order[j - 1])) {
+            order[j] = order[j - 1];
+            --j;
+        }
+        order[j] = i;
+    }
+    int32_t lo = 0;
+    for (int g = 0; g < kGroups; ++g) {
+        int32_t hi = lo;
+        while (hi < n_leaves && group(order[hi]) == g) ++hi;
+        Tile *t = tiles + plan->begin[g];
+        const int64_t count = plan->count[g];
+        int64_t o = 0;
+        if (count < 2 * kXcds) {
+            for (int32_t r = lo; r < hi; ++r)
+                for (int a = 0; a < tasks[order[r]].n_actions; ++a) t[o++] = Tile{order[r], a};
+        } else {
+            // XCD x takes the leaves of rank x, x + 8, ...; one tile from
+            // each XCD's list in turn
+            int32_t rank[kXcds], act[kXcds];
+            for (int x = 0; x < kXcds; ++x) {
+                rank[x] = x;
+                act[x] = 0;
+            }
+            const int32_t nl = hi - lo;
+            while (o < count)
+                for (int x = 0; x < kXcds; ++x) {
+                    if (rank[x] >= nl) continue;
+                    const int32_t leaf = order[lo + rank[x]];
+                    t[o++] = Tile{leaf, act[x]};
+                    if (++act[x] == tasks[leaf].n_actions) {
+                        act[x] = 0;
+                        rank[x] += kXcds;
+                    }
+                }
+        }
+        lo = hi;
+    }
+}
+
+}  // namespace
+
 extern "C" {
 
 hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves, hdx_stream stream) {
@@ -647,26 +857,7 @@ hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
     hdx_status st = validate_leaves(ctx, leaves, n_leaves, &sh);
     if (st != HDX_OK || n_leaves == 0) return st;
     hipSetDevice(ctx->device);
-    const Variant v0 = pick_variant(sh.has_rs, sh.has_ped, sh.ped_max, sh.n_max, sh.has_mars, sh.has_nav);
-    const int kernels = (sh.has_rs || sh.has_ped ? 1 : 0) + sh.has_mars + sh.has_nav;
-    if (n_leaves <= kArgLeaves && kernels <= 1) {
-        // small calls of one kernel carry their descriptors in the kernel
-        // arguments (the multi-agent and navigation models have kernels of
-        // their own; RockSample and driving share one)
-        static_assert(sizeof(ArgPack) <= 4096, "kernel argument pack too large");
-        ArgPack pack;
-        memset(&pack, 0, sizeof(pack));
-        pack_leaves(leaves, n_leaves, pack.t, nullptr);
-        pack.tile_begin[0] = 0;
-        for (int32_t i = 0; i < n_leaves; ++i) pack.tile_begin[i + 1] = pack.tile_begin[i] + pack.t[i].n_actions;
-        pack.n_leaves = n_leaves;
-        pack.n_max = v0.n_max;
-        const Schedule sch =
-            ctx->sched_fixed ? ctx->sched : class_default_schedule(v0.n_max, variant_max_threads(v0), -2);
-        pack.xcd_remap = sch.xcd_remap;
-        hipError_t e = launch_expand_args(pack, v0, sch, (hipStream_t)stream);
-        return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "expand launch");
-    }
+    if (launch_in_args(ctx, leaves, n_leaves, sh, (hipStream_t)stream, &st)) return st;
     std::lock_guard<std::mutex> lock(ctx->mu);
     Slot &s = ctx->slots[ctx->next_slot];
     ctx->next_slot = (ctx->next_slot + 1) % kSlots;
@@ -682,30 +873,40 @@ hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
     leaf_variants(leaves, n_leaves, var.data());
     ClassPlan plan;
     plan_classes(s.h_tasks, var.data(), s.h_tiles, sh.n_tiles, &plan, false);
-    for (int g = 0; g < kGroups; ++g) s.h_queue[g] = TileQueue{0, 0, (int32_t)plan.count[g], 0};
-    hipStream_t hs = (hipStream_t)stream;
-    hipError_t e = hipMemcpyAsync(s.d_tasks, s.h_tasks, n_leaves * sizeof(LeafTask), hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess) e = hipMemcpyAsync(s.d_tiles, s.h_tiles, sh.n_tiles * sizeof(Tile), hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(s.d_queue, s.h_queue, kGroups * sizeof(TileQueue), hipMemcpyHostToDevice, hs);
-    if (e != hipSuccess) return hip_fail(ctx, e, "descriptor copy");
-    int32_t no_lds[kGroups] = {};
-    Schedule sch[kGroups];
-    // a launch far smaller than the GPU (a search's leaf batch) is latency
-    // bound: wider workgroups finish each tile sooner
-    const bool few = sh.n_tiles < 8 * (int64_t)ctx->n_cu;
-    for (int g = 0; g < kGroups; ++g) {
-        sch[g] = ctx->sched_fixed ? ctx->sched
-                                  : class_default_schedule(plan.n_max[g], variant_max_threads(group_variant(g)),
-                                                           few ? -2 : group_variant(g).mode);
-        if (few) sch[g].xcd_remap = 0;
+    st = launch_staged(ctx, s.h_tasks, s.h_tiles, s.h_queue, s.d_tasks, s.d_tiles, s.d_queue, n_leaves, sh.n_tiles,
+                       plan, (hipStream_t)stream, s.fork, s.join, s.done);
+    if (st == HDX_OK) s.used = true;
+    return st;
+}
+
+hdx_status hdx_expand_leaf_noalloc(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves, hdx_stream stream) {
+    if (!ctx) return HDX_E_INVALID;
+    Shape sh;
+    hdx_status st = validate_leaves(ctx, leaves, n_leaves, &sh);
+    if (st != HDX_OK || n_leaves == 0) return st;
+    if (n_leaves > HDX_NOALLOC_MAX_LEAVES) return fail(ctx, HDX_E_CAPACITY, "more than HDX_NOALLOC_MAX_LEAVES leaves");
+    if (sh.n_tiles > HDX_NOALLOC_MAX_TILES)
+        return fail(ctx, HDX_E_CAPACITY, "more than HDX_NOALLOC_MAX_TILES (leaf, action) tiles");
+    if (!ctx->na_scratch) return fail(ctx, HDX_E_DEVICE, "no-allocation scratch not set up");
+    hipSetDevice(ctx->device);
+    if (launch_in_args(ctx, leaves, n_leaves, sh, (hipStream_t)stream, &st)) return st;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (ctx->na_used) {
+        // the previous call's copies must have left the host staging
+        const hipError_t e = hipEventSynchronize(ctx->na_done);
+        if (e != hipSuccess) return hip_fail(ctx, e, "staging wait");
     }
-    e = launch_classes_forked(s.d_tasks, s.d_tiles, s.d_queue, plan, no_lds, sch, ctx->n_cu, hs, ctx->cls_stream,
-                              s.fork, s.join);
-    if (e != hipSuccess) return hip_fail(ctx, e, "expand launch");
-    e = hipEventRecord(s.done, hs);
-    s.used = true;
-    return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "event record");
+    pack_leaves(leaves, n_leaves, ctx->na_h_tasks, nullptr);
+    leaf_variants(leaves, n_leaves, ctx->na_var);
+    ClassPlan plan;
+    plan_fixed(ctx->na_h_tasks, ctx->na_var, n_leaves, ctx->na_h_tiles, ctx->na_order, &plan);
+    LeafTask *d_tasks = (LeafTask *)(ctx->na_scratch + kNaTasksOff);
+    Tile *d_tiles = (Tile *)(ctx->na_scratch + kNaTilesOff);
+    TileQueue *d_queue = (TileQueue *)(ctx->na_scratch + kNaQueueOff);
+    st = launch_staged(ctx, ctx->na_h_tasks, ctx->na_h_tiles, ctx->na_h_queue, d_tasks, d_tiles, d_queue, n_leaves,
+                       sh.n_tiles, plan, (hipStream_t)stream, ctx->na_fork, ctx->na_join, ctx->na_done);
+    if (st == HDX_OK) ctx->na_used = true;
+    return st;
 }
 
 }  // extern "C"

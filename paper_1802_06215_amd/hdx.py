@@ -23,6 +23,8 @@ SIZE_CLASSES = 6
 LAUNCH_GROUPS = 36  # model variant (RockSample; driving <= 8, 16, 32 pedestrians; multi-agent; navigation) x size class
 MAX_LEAF_SCENARIOS = 2048
 MAX_HORIZON = 4096
+NOALLOC_MAX_LEAVES = 512  # HDX_NOALLOC_MAX_LEAVES
+NOALLOC_MAX_TILES = 65536  # HDX_NOALLOC_MAX_TILES
 
 STATUS = {0: "HDX_OK", -1: "HDX_E_INVALID", -2: "HDX_E_DEVICE", -3: "HDX_E_NOMEM", -4: "HDX_E_SHAPE",
           -5: "HDX_E_CAPACITY", -6: "HDX_E_UNSUPPORTED"}
@@ -110,7 +112,7 @@ EXPORTS = ["hdx_version", "hdx_init", "hdx_fini", "hdx_last_error", "hdx_upload_
            "hdx_mlp_get_params", "hdx_mlp_set_params", "hdx_mlp_forward", "hdx_mlp_gradients",
            "hdx_mlp_train_step", "hdx_features", "hdx_expand_leaf_surrogate", "hdx_mlp_save", "hdx_mlp_load",
            "hdx_tree_create", "hdx_tree_destroy", "hdx_tree_add_children", "hdx_backup",
-           "hdx_tree_bounds", "hdx_tree_size"]
+           "hdx_tree_bounds", "hdx_tree_size", "hdx_expand_leaf_noalloc"]
 
 _lib = None
 
@@ -136,6 +138,7 @@ def load_library():
     L.hdx_model_max_children.argtypes = [P, I32]
     L.hdx_sample_scenarios.argtypes = [P, P, C.POINTER(Belief), I32, U32, U32, States, P]
     L.hdx_expand_leaf.argtypes = [P, P, I32, P]
+    L.hdx_expand_leaf_noalloc.argtypes = [P, P, I32, P]
     L.hdx_rollout_bounds.argtypes = [P, P, C.POINTER(RolloutCfg), U32, U32, States, P, P, I64,
                                      P, P, P, P]
     L.hdx_philox.argtypes = [P, P, I64, U32, U32, P, P]
@@ -454,6 +457,12 @@ class Context:
         arr = (Leaf * len(leaves))(*leaves)
         self._check(self.lib.hdx_expand_leaf(self.handle, C.cast(arr, C.c_void_p), len(leaves),
                                              _stream(stream)))
+
+    def expand_leaf_noalloc(self, leaves, stream=None) -> None:
+        leaves = list(leaves)
+        arr = (Leaf * len(leaves))(*leaves)
+        self._check(self.lib.hdx_expand_leaf_noalloc(self.handle, C.cast(arr, C.c_void_p), len(leaves),
+                                                     _stream(stream)))
 
     def expand_leaf_surrogate(self, leaves, mlp: "Mlp", horizon: int, stream=None) -> None:
         leaves = list(leaves)
