@@ -11,14 +11,14 @@ before timing starts.  Prints one JSON line.
 
 Workloads (all synthetic, seeded; see workloads/):
   rs15  RockSample 15x15, 15 rocks, |A|=20, K=500, horizon 90, move-east
-        rollouts; 2048 leaves with n in {500,250,125,63,32}, depth 1..30
+        rollouts; 2048 leaves with n in {500,250,125,62,31}, depth 1..30
   rs7   RockSample 7x7, 8 rocks, |A|=13, K=100, rollouts of depth 30
   ped16 crowd driving, 16 pedestrians, 5 goals, |A|=3, K=500, rollouts 50;
         search with 6, 12 and 20 pedestrians (the element-count study)
   mix64 64 planner instances (RockSample 7..20 / driving, K in 100..500)
   mars11, mars15, mars20  multi-agent RockSample (n, n) with n rocks,
         |A| = 256, 400, 625, K=500, horizon 90, both robots move east in
-        rollouts; 128 leaves with n in {500,250,125,63,32}, depth 1..30
+        rollouts; 128 leaves with n in {500,250,125,62,31}, depth 1..30
   nav13 navigation in a partially known 13x13 map (124 unknown cells), |A|=9,
         horizon 90, gate-then-goal rollouts; 1024 leaves with n in
         {2000,1000,500,250,125}; search at K = 100, 500, 1000, 2000
@@ -37,10 +37,12 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE (scaled by a plain copy of known size), recorded with a hash of
 # the kernel's sources: reported only while those sources are unchanged.
 PROFILED_TRAFFIC = {
-    "rs15": dict(bytes=53.47e6, sha="7d4f28556a645cc0", summary="profiles/expand_tiles_rs15.md"),
-    "ped16": dict(bytes=75.69e6, sha="7d4f28556a645cc0", summary="profiles/expand_tiles_ped16.md"),
-    "mars20": dict(bytes=87.70e6, sha="7d4f28556a645cc0", summary="profiles/expand_tiles_mars20.md"),
-    "nav13": dict(bytes=255.5e6, sha="7d4f28556a645cc0", summary="profiles/expand_tiles_nav13.md"),
+    "rs15": dict(bytes=39.42e6, valu_insts=5.913e7, sha="9bb2c4911d84e95c", summary="profiles/expand_tiles_rs15.md"),
+    "rs7": dict(bytes=52.57e6, valu_insts=7.311e7, sha="9bb2c4911d84e95c", summary="profiles/expand_tiles_rs7.md"),
+}
+# The same for the expand/group stage alone (rollouts off).
+PROFILED_STAGE_TRAFFIC = {
+    "rs15": dict(bytes=39.42e6, sha="9bb2c4911d84e95c", summary="profiles/expand_tiles_rs15.md"),
 }
 # the kernel and the host code that orders its tiles (the order decides L2 reuse)
 KERNEL_SOURCES = ("paper_1802_06215_amd/csrc/kernels.hip", "paper_1802_06215_amd/csrc/models.hpp",
@@ -74,6 +76,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the timed batch (no expand-stage, per-instance or single-leaf timings; for profiling)")
+    ap.add_argument("--no-rollouts", action="store_true",
+                    help="time the expand/group stage alone (rollouts of length 0; for profiling that stage)")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only the surrogate comparison (prints its JSON object; for profiling the MLP kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -99,52 +105,75 @@ def parse():
 
 
 # ---------------------------------------------------------------------------
-# Algorithmic work per unit (32-bit lane operations the model definitions
-# require, counted from the equations, not from compiled code).
+# Algorithmic work per unit.  The headline fraction counts work the way the
+# hot-path scope table does: a fixed number of 32-bit lane operations per
+# scenario-step (model steps on non-terminal states, in expansion and in
+# rollouts) plus one Philox4x32-10 block per random draw the model makes,
+# and the minimal HBM bytes of a leaf (2-byte child ids).  A finer model of
+# the same work (bounds, grouping and sums included, each counted once) is
+# reported beside it.
 # ---------------------------------------------------------------------------
-PHILOX_OPS = 10 * 8 + 9 * 2  # per round: 2 mul-lo, 2 mul-hi, 4 xor; key bumps
+PHILOX_OPS = 10 * 8 + 9 * 2  # 10 rounds of 2 mul-lo, 2 mul-hi, 4 xor; 9 key bumps of 2 adds
+STEP_OPS_RS = 10              # decode, move / exit test, reward, discount, accumulate
 
 
-def rs_ops(m):
-    step = 8                                  # decode, move/exit test, reward, discount, accumulate
-    return dict(step=step, sense_extra=PHILOX_OPS + 6, upper=3 + 6 * m, group=12, reduce=3)
+def _sense_actions(desc):
+    """Actions whose expansion step draws a random block (a sensor reading)."""
+    A = desc["n_actions"]
+    if desc["kind"] == 0:
+        return [a for a in range(A) if a >= 5]
+    if desc["kind"] == 2:
+        b = 5 + desc["m"]
+        return [a for a in range(A) if a // b >= 5 or a % b >= 5]
+    return list(range(A))
 
 
-def mars_ops(m):
-    step = 2 * 8 + 4                          # joint-action decode, then each robot as in RockSample
-    return dict(step=step, sense_extra=PHILOX_OPS + 2 * 6, upper=3 + 6 * m, group=12, reduce=3)
+def survey_ops(desc, steps):
+    """Lane operations of one leaf by the scope table's accounting; steps is
+    the leaf's [A][2] (expansion, rollout) step counts."""
+    exp_a, roll = steps[:, 0], int(steps[:, 1].sum())
+    exp = int(exp_a.sum())
+    k = desc["kind"]
+    if k == 0:
+        return STEP_OPS_RS * (exp + roll) + PHILOX_OPS * int(exp_a[_sense_actions(desc)].sum())
+    if k == 2:  # two robots per step; one block per pair where a robot senses
+        return 2 * STEP_OPS_RS * (exp + roll) + PHILOX_OPS * int(exp_a[_sense_actions(desc)].sum())
+    if k == 3:  # a move-failure block every step; two blocks of readings (8 bits) per expansion step
+        return (STEP_OPS_RS + PHILOX_OPS) * (exp + roll) + (2 * PHILOX_OPS + 8 * 4) * exp
+    P = desc["n_peds"]  # car failure draw + one Gaussian block and ~40 FP32 ops per pedestrian
+    return (STEP_OPS_RS + 40 * P + PHILOX_OPS * (P + 1)) * (exp + roll)
 
 
-def nav_ops():
-    occ = 8                                   # bounds test, cell table, unknown-bit select
-    step = PHILOX_OPS + 6 + occ + 6           # failure draw, move, occupancy, reward
-    return dict(step=step, policy=3 * occ + 12, obs=2 * PHILOX_OPS + 8 * (occ + 4), upper=8, group=12, reduce=3)
+def state_bytes(desc):
+    k = desc["kind"]
+    return 4 if k == 0 else 8 if k == 2 else 20 if k == 3 else 8 + 9 * desc["n_peds"]
 
 
-def ped_ops(P):
-    ped = 30                                  # Irwin-Hall, heading, sqrt, 2 div, rotation, update
-    step = (P + 1) * PHILOX_OPS + 6 + P * ped + 5 * P + 3
-    obs = (2 * P + 1) * 12                    # hash of speed and floored positions
-    return dict(step=step, obs=obs, upper=6, group=12, reduce=3)
+def leaf_bytes(desc, n, n_children_total):
+    """Minimal HBM bytes of one leaf expansion: read the parent's states,
+    ids and positions; write the leaf's states and ids, 2-byte child ids
+    (perm), the child table (z 8, n 4, offset 4, u0 4, l0 4) and the
+    per-action results (children 4, mean reward 4, step counts 16)."""
+    A, sb = desc["n_actions"], state_bytes(desc)
+    return n * (sb + 4 + 2) + n * (sb + 4) + 2 * A * n + 24 * n_children_total + 24 * A
 
 
-def algorithmic_ops(desc, n, A, expand_steps, rollout_steps):
-    """ALU work of one leaf: update + expansion + bounds + grouping + sums."""
+def model_ops(desc, n, A, steps):
+    """A finer count of the same leaf's work, each part once: update step per
+    scenario, per pair the step, Eq. 12 at the tabulated cost (one table
+    entry per four rocks), key grouping and the sums; rollout steps; random
+    blocks as in survey_ops."""
+    k = desc["kind"]
+    m = desc.get("m", 0)
     pairs = n * A
-    if desc["kind"] in (0, 2):
-        c = rs_ops(desc["m"]) if desc["kind"] == 0 else mars_ops(desc["m"])
-        # pairs whose action senses (a joint action senses unless both robots move or sample)
-        sense_pairs = n * (desc["m"] if desc["kind"] == 0 else A - 25)
-        return (n * c["step"] * A                # update step recomputed per action tile
-                + pairs * (c["step"] + c["upper"] + c["group"] + c["reduce"])
-                + sense_pairs * c["sense_extra"] + rollout_steps * c["step"])
-    if desc["kind"] == 3:
-        c = nav_ops()
-        return (n * c["step"] * A + pairs * (c["step"] + c["obs"] + c["upper"] + c["group"] + c["reduce"])
-                + rollout_steps * (c["step"] + c["policy"]))
-    c = ped_ops(desc["n_peds"])
-    return (n * c["step"] * A + pairs * (c["step"] + c["obs"] + c["upper"] + c["group"] + c["reduce"])
-            + rollout_steps * c["step"])
+    exp, roll = int(steps[:, 0].sum()), int(steps[:, 1].sum())
+    group, reduce_ = 12, 3
+    if k in (0, 2):
+        step = STEP_OPS_RS if k == 0 else 2 * STEP_OPS_RS
+        upper = 3 + 2 * ((m + 3) // 4) * (1 if k == 0 else 2)
+        rnd = PHILOX_OPS * int(steps[_sense_actions(desc), 0].sum())
+        return n * step + pairs * (step + upper + group + reduce_) + roll * step + rnd
+    return n * (survey_ops(desc, steps) // max(exp + roll, 1)) + survey_ops(desc, steps) + pairs * (6 + group + reduce_)
 
 
 # ---------------------------------------------------------------------------
@@ -204,6 +233,8 @@ def build(ctx, args):
                     lf = W.pednav_leaf(d, K, n_leaf, 5000 + j * per + r, depth=1 + r % 12)
                     items.append((d, lf, j, (0, 50, -1)))
 
+    if getattr(args, "no_rollouts", False):
+        items = [(d, lf, seed, (cfg[0], 0, cfg[2])) for d, lf, seed, cfg in items]
     models = {}
     groups = {}
     for k, (d, lf, seed, cfg) in enumerate(items):
@@ -233,7 +264,7 @@ def build(ctx, args):
             else:
                 par = H.pednav_states(lf["s"], lf["level"], lf["term"], lf["px"], lf["py"], lf["goal"])
             pids = torch.from_numpy(lf["ids"].astype(np.int32)).cuda()
-            idx = torch.from_numpy(lf["idx"]).cuda()
+            idx = H.positions(lf["idx"])
             b.n = len(lf["idx"])
             leaves[k] = H.make_leaf(m, par, pids, idx, lf["depth"], lf["last_action"], b, seed, 0,
                                     H.rollout_cfg(*cfg))
@@ -266,7 +297,7 @@ def surrogate_section(ctx, args):
             lf = W.rocksample_leaf(desc, 500, n, seed, depth=depth)
             par = H.rocksample_states(lf["x"], lf["y"], lf["rocks"], lf["term"])
             pids = torch.from_numpy(lf["ids"].astype(np.int32)).cuda()
-            idx = torch.from_numpy(lf["idx"]).cuda()
+            idx = H.positions(lf["idx"])
             out = H.LeafBuffers(m, n, per_pair=per_pair)
             descs.append(H.make_leaf(m, par, pids, idx, lf["depth"], lf["last_action"], out, seed, 0, rcfg))
             outs.append((out, lf["depth"]))
@@ -505,10 +536,12 @@ def surrogate_section(ctx, args):
 
 
 def cpu_baseline(items, seconds):
-    """The oracle as it stands over leaves of the same batch: first on one
-    thread until the time budget is spent, then on one thread per host core
-    (the oracle is reentrant C; ctypes releases the interpreter lock during
-    each call) over the whole batch, repeated for at least two seconds."""
+    """The oracle as it stands over leaves of the same batch, timed as the
+    scope table asks: five measurements of at least seconds/10 each (the
+    whole batch, or its first leaves on one thread), the median reported;
+    first on one thread, then on one thread per host core (the oracle is
+    reentrant C; ctypes releases the interpreter lock during each call) over
+    the whole batch."""
     import concurrent.futures as cf
 
     import numpy as np
@@ -522,29 +555,37 @@ def cpu_baseline(items, seconds):
                                  lf["depth"], lf["last_action"], seed, 0)
         return int(res["expand_steps"]) + int(res["rollout_steps"])
 
-    steps = done = 0
-    t0 = time.perf_counter()
-    for it in items:
-        steps += one(it)
-        done += 1
-        if time.perf_counter() - t0 > seconds:
-            break
-    dt1 = time.perf_counter() - t0
-    single = steps / dt1
+    each = max(seconds / 10.0, 1.0)
+
+    def measure(run_pass):
+        rates = []
+        for _ in range(5):
+            st = 0
+            t0 = time.perf_counter()
+            while time.perf_counter() - t0 < each:
+                st += run_pass()
+            rates.append(st / (time.perf_counter() - t0))
+        return float(np.median(rates)), rates
+
+    pos = [0]
+
+    def single_pass():  # the next 8 leaves of the batch, cycling
+        st = 0
+        for _ in range(8):
+            st += one(items[pos[0] % len(items)])
+            pos[0] += 1
+        return st
+
+    single, _ = measure(single_pass)
     cores = min(16, len(os.sched_getaffinity(0)))
-    msteps = passes = 0
-    t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=cores) as ex:
-        while True:
-            msteps += sum(ex.map(one, items, chunksize=8))
-            passes += 1
-            if time.perf_counter() - t0 >= 2.0:
-                break
-    dtm = time.perf_counter() - t0
-    return dict(value=msteps / dtm, unit="scenario-steps/s", cores=cores, kind="oracle",
+        multi, rates = measure(lambda: sum(ex.map(one, items, chunksize=8)))
+    return dict(value=multi, unit="scenario-steps/s", cores=cores, kind="oracle",
                 single_thread_value=round(single, 1),
-                sample="whole batch (%d leaves) %d time(s) on %d threads in %.1f s; single thread: first %d "
-                       "leaves in %.1f s" % (len(items), passes, cores, dtm, done, dt1))
+                sample="median of 5 measurements of >= %.1f s each: on %d threads, passes over the whole batch "
+                       "(%d leaves); on one thread, the batch's leaves in order, 8 at a time (%d leaves in all)"
+                       % (each, cores, len(items), pos[0]),
+                rates=[round(r, 1) for r in rates])
 
 
 def despot_analogue(desc, seconds, K=500, seed=3, max_depth=90, xi=0.95):
@@ -620,6 +661,103 @@ def search_config(desc, seconds):
         "multi-agent RockSample" if desc["kind"] == 2 else "RockSample", desc["n"], desc["n"], desc["m"], seconds)
 
 
+def _timed_events(fn, reps, stream=None):
+    """Mean milliseconds per call between HIP events on the stream the calls
+    are issued on."""
+    import torch
+    stream = stream or torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def expand_stage(ctx, wl, args):
+    """The expand/group stage (gather + update, expansion, grouping, upper
+    bounds, sums) without rollouts: the same batch with rollouts of length
+    0, as one replayed graph; time and algorithmic HBM fraction."""
+    import torch
+    from paper_1802_06215_amd import hdx as H
+    leaves = []
+    for L in wl["leaves"]:
+        c = H.Leaf.from_buffer_copy(L)
+        c.rollout.max_steps = 0
+        leaves.append(c)
+    b = H.Batch(ctx, len(leaves), sum(it[0]["n_actions"] for it in wl["items"]))
+    b.set_leaves(leaves)
+    b.autotune(2)
+    b.use_graph(True)
+    for _ in range(3):
+        b.launch()
+    torch.cuda.synchronize()
+    ms = _timed_events(b.launch, max(args.steps, 20))
+    alg = 0
+    for slab, ks in zip(wl["slabs"], wl["groups"]):
+        nch = slab["n_children"].cpu().numpy()
+        for j, k in enumerate(ks):
+            d, lf = wl["items"][k][0], wl["items"][k][1]
+            alg += leaf_bytes(d, len(lf["idx"]), int(nch[j].sum()))
+    prof = PROFILED_STAGE_TRAFFIC.get(args.workload)
+    traffic = prof["bytes"] if prof and prof["sha"] == kernel_sha() else None
+    b.close()
+    return dict(kernel_ms=round(ms, 4), algorithmic_bytes=int(alg),
+                hbm_gbs=round(alg / (ms * 1e-3) / 1e9, 1), hbm_frac=round(alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                traffic=traffic, traffic_source=prof["summary"] if traffic else None)
+
+
+def per_instance_compare(ctx, wl, batch, args):
+    """One replayed graph of the whole batch against the same leaves issued
+    as one expand call per planner instance (each instance's leaves in one
+    launch), on one stream."""
+    import torch
+    by_inst = {}
+    for k, it in enumerate(wl["items"]):
+        by_inst.setdefault(it[2], []).append(wl["leaves"][k])
+    calls = list(by_inst.values())
+
+    def per_instance():
+        for ls in calls:
+            ctx.expand_leaf(ls)
+    per_instance()
+    torch.cuda.synchronize()
+    reps = max(5, args.steps // 2)
+    t0 = time.perf_counter()
+    per_ms = _timed_events(per_instance, reps)
+    per_wall = (time.perf_counter() - t0) * 1e3 / reps
+    t0 = time.perf_counter()
+    one_ms = _timed_events(batch.launch, reps)
+    one_wall = (time.perf_counter() - t0) * 1e3 / reps
+    return dict(instances=len(calls), launches_per_instance_form=len(calls), per_instance_ms=round(per_ms, 4),
+                per_instance_wall_ms=round(per_wall, 4), one_graph_ms=round(one_ms, 4),
+                one_graph_wall_ms=round(one_wall, 4), speedup=round(per_ms / one_ms, 2))
+
+
+def single_leaf_latency(ctx, wl, reps=200):
+    """Latency of one search thread's call: the batch's first (largest) leaf
+    alone, hdx_expand_leaf then a stream synchronisation, host clock; and
+    the GPU time of the same call between events."""
+    import torch
+    leaf = [wl["leaves"][0]]
+    n = len(wl["items"][0][1]["idx"])
+    for _ in range(10):
+        ctx.expand_leaf(leaf)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        ctx.expand_leaf(leaf)
+        stream.synchronize()
+        t.append(time.perf_counter() - t0)
+    gpu_ms = _timed_events(lambda: ctx.expand_leaf(leaf), reps)
+    import numpy as np
+    return dict(scenarios=n, actions=wl["items"][0][0]["n_actions"], wall_ms_median=round(float(np.median(t)) * 1e3, 4),
+                wall_ms_p90=round(float(np.percentile(t, 90)) * 1e3, 4), gpu_ms_back_to_back=round(gpu_ms, 4))
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -687,22 +825,51 @@ def main():
     kernel_ms = e0.elapsed_time(e1) / args.steps
     value = steps_per_launch * args.steps / wall
 
-    # algorithmic ALU work per launch, from per-leaf step counts (slabs are
-    # grouped per model, in the order build() recorded)
-    ops = 0
+    # algorithmic work per launch, from per-leaf step counts and child counts
+    # (slabs are grouped per model, in the order build() recorded)
+    ops = ops_fine = alg_bytes = 0
     for slab, ks in zip(wl["slabs"], wl["groups"]):
-        st = slab["steps"].sum(dim=1).cpu().numpy()
+        st = slab["steps"].cpu().numpy()
+        nch = slab["n_children"].cpu().numpy()
         for j, k in enumerate(ks):
             d, lf = items[k][0], items[k][1]
-            ops += algorithmic_ops(d, len(lf["idx"]), d["n_actions"], int(st[j, 0]), int(st[j, 1]))
+            n = len(lf["idx"])
+            ops += survey_ops(d, st[j])
+            ops_fine += model_ops(d, n, d["n_actions"], st[j])
+            alg_bytes += leaf_bytes(d, n, int(nch[j].sum()))
     achieved_tops = ops / (kernel_ms * 1e-3) / 1e12
+    hbm_gbs = alg_bytes / (kernel_ms * 1e-3) / 1e9
     prof = PROFILED_TRAFFIC.get(args.workload)
-    traffic = prof["bytes"] if prof and prof["sha"] == kernel_sha() else None
-    roofline = dict(bound="alu", achieved=round(achieved_tops, 3), peak=round(PEAK_ALU_TOPS, 2),
-                    unit="TOP/s", frac=round(achieved_tops / PEAK_ALU_TOPS, 4), traffic=traffic,
-                    traffic_unit="bytes/launch", traffic_source=prof["summary"] if traffic else None,
-                    hbm_gbs_at_traffic=round(traffic / (kernel_ms * 1e-3) / 1e9, 1) if traffic else None,
-                    ops_per_launch=int(ops), kernel_ms=round(kernel_ms, 4))
+    current = prof is not None and prof["sha"] == kernel_sha()
+    traffic = prof["bytes"] if current else None
+    alu_frac, hbm_frac = achieved_tops / PEAK_ALU_TOPS, hbm_gbs / PEAK_HBM_GBS
+    roofline = dict(bound="alu" if alu_frac >= hbm_frac else "hbm",
+                    achieved=round(achieved_tops, 3), peak=round(PEAK_ALU_TOPS, 2), unit="TOP/s",
+                    frac=round(alu_frac, 4), traffic=traffic, traffic_unit="bytes/launch",
+                    traffic_source=prof["summary"] if current else None,
+                    kernel_ms=round(kernel_ms, 4), ops_per_launch=int(ops),
+                    ops_accounting="%d lane-ops per scenario-step + %d per Philox block drawn" % (STEP_OPS_RS,
+                                                                                              PHILOX_OPS),
+                    hbm=dict(algorithmic_bytes=int(alg_bytes), achieved=round(hbm_gbs, 1), peak=PEAK_HBM_GBS,
+                             unit="GB/s", frac=round(hbm_frac, 4),
+                             traffic_over_algorithmic=round(traffic / alg_bytes, 2) if traffic else None),
+                    op_model=dict(ops_per_launch=int(ops_fine),
+                                  frac=round(ops_fine / (kernel_ms * 1e-3) / 1e12 / PEAK_ALU_TOPS, 4)))
+    if current and prof.get("valu_insts"):
+        # VALU instructions the kernel issued (rocprofv3 SQ_INSTS_VALU, per
+        # launch) as 64-lane slots, against the algorithmic lane-ops
+        roofline["valu_issued_lane_slots"] = int(prof["valu_insts"] * 64)
+        roofline["issued_over_algorithmic"] = round(prof["valu_insts"] * 64 / ops, 2)
+
+    # the expand/group stage alone: the same leaves with rollouts off (the
+    # lower bound then comes from no rollout steps), one graph replay
+    stage = None if args.no_rollouts or args.no_extras else expand_stage(ctx, wl, args)
+
+    extra = {}
+    if args.workload == "mix64" and not args.no_extras:
+        extra["per_instance"] = per_instance_compare(ctx, wl, batch, args)
+    if args.workload in ("rs7", "rs15", "mars20", "nav13", "ped16") and not args.no_extras:
+        extra["single_leaf"] = single_leaf_latency(ctx, wl)
 
     search = None
     if (args.workload == "rs15" or args.workload.startswith("mars")) and args.search_seconds > 0:
@@ -811,7 +978,7 @@ def main():
                                           hyp_config=dict(threads=best["threads"], leaf_batcher=best["leaf_batcher"]))
 
     names = dict(rs15="RS15 leaf expansion: RockSample 15x15, 15 rocks, |A|=20, K=500, horizon 90, move-east "
-                      "rollouts; %d synthetic leaves (n in {500,250,125,63,32}, depth 1..30)",
+                      "rollouts; %d synthetic leaves (n in {500,250,125,62,31}, depth 1..30)",
                  rs7="RS7 leaf expansion: RockSample 7x7, 8 rocks, |A|=13, K=100, move-east rollouts of "
                      "depth 30; %d synthetic leaves",
                  ped16="PED16 leaf expansion: 16 pedestrians, 5 goals, |A|=3, K=500, rollouts of 50; "
@@ -824,7 +991,7 @@ def main():
     for size in (11, 15, 20):
         names["mars%d" % size] = ("MARS%d leaf expansion: multi-agent RockSample %dx%d, %d rocks, |A|=%d, K=500, "
                                   "horizon 90, both robots move east in rollouts; %%d synthetic leaves "
-                                  "(n in {500,250,125,63,32}, depth 1..30)" % (size, size, size, size,
+                                  "(n in {500,250,125,62,31}, depth 1..30)" % (size, size, size, size,
                                                                                (5 + size) ** 2))
     variants = ("rocksample", "driving<=8", "driving<=16", "driving<=32", "multi-agent rocksample", "navigation")
     per_class = [dict(model=variants[v], max_n=64 << c, tiles=n, threads=ct, persistent=cp, xcd_remap=cx)
@@ -836,7 +1003,7 @@ def main():
                            scenario_steps_per_step=steps_per_launch, expand_steps=exp_steps,
                            rollout_steps=roll_steps, split_by_size_class=batch.split(), schedule=per_class,
                            hip_graph=True, autotune_ms=tuned_ms),
-               roofline=roofline, cpu_baseline=cpu,
+               roofline=roofline, expand_stage=stage, cpu_baseline=cpu, **extra,
                search=dict(config=search_config(items[0][0], args.search_seconds), runs=search) if search else None,
                surrogate=sur)
     print(json.dumps(out), flush=True)

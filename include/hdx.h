@@ -170,7 +170,8 @@ typedef struct {
  *   inputs
  *     parent, parent_ids : the parent's states and scenario ids
  *     idx[n]             : positions of the leaf's scenarios in the parent
- *                          arrays, strictly ascending
+ *                          arrays (int16, so below 32768), strictly
+ *                          ascending
  *     depth              : the leaf's depth (root = 0); the update step uses
  *                          depth-1, expansion depth, rollouts depth+1 on
  *     last_action        : action from the parent, or -1 for a root (states
@@ -180,7 +181,10 @@ typedef struct {
  *   outputs
  *     states_out, ids_out[n] : the leaf's own states (materialised) and ids
  *     perm[A][n]         : leaf positions grouped by child (children in
- *                          ascending observation, positions ascending)
+ *                          ascending observation, positions ascending);
+ *                          int16, two bytes per scenario, so a child's
+ *                          segment perm[a][off..off+count) is directly the
+ *                          idx of that child when it is expanded
  *     n_children[A]      : children per action (Eq. 11)
  *     child_z, child_n, child_off [A][cap] : observation, scenario count and
  *                          offset into perm[a] of each child
@@ -196,11 +200,11 @@ typedef struct {
     hdx_rollout_cfg rollout;
     hdx_states parent;
     const uint32_t *parent_ids;
-    const int32_t *idx;
+    const int16_t *idx;
     int32_t n, depth, last_action, cap;
     hdx_states states_out;
     uint32_t *ids_out;
-    int32_t *perm;
+    int16_t *perm;
     int32_t *n_children;
     uint64_t *child_z;
     int32_t *child_n, *child_off;
@@ -233,6 +237,12 @@ hdx_status hdx_free_model(hdx_ctx *ctx, hdx_model *model);
 int32_t hdx_model_actions(const hdx_model *model);
 /* Largest child count one action can produce for a leaf of n scenarios. */
 int32_t hdx_model_max_children(const hdx_model *model, int32_t n);
+/* Workspace query: device bytes the caller provides for the required
+ * outputs of n_leaves leaves of K scenarios each (states_out, ids_out,
+ * perm, n_children, the child table with cap = hdx_model_max_children(K),
+ * r_mean, steps; each array rounded up to 256 bytes), without the optional
+ * per-pair outputs.  0 for a NULL model or negative sizes. */
+size_t hdx_expand_out_bytes(const hdx_model *model, int32_t K, int32_t n_leaves);
 
 /* sample_scenarios (Sec. III-A): K start states drawn from the belief into
  * `out` (device), scenario k using counter (k, 0, block, 1).  Errors:
@@ -386,6 +396,20 @@ hdx_status hdx_tree_add_children(hdx_tree *tree, int64_t node, const int32_t *n_
 hdx_status hdx_backup(hdx_tree *tree, int64_t node);
 hdx_status hdx_tree_bounds(const hdx_tree *tree, int64_t node, double *u, double *l);
 int64_t hdx_tree_size(const hdx_tree *tree);
+
+/* Belief update of the online loop (Sec. III-A, Eq. 3) for RockSample,
+ * host only: the belief after `action` and observation z from belief b (the
+ * robot cell x, y and p_good[n_rocks] of the description).  The robot's
+ * moves are deterministic, so the new cell is the action's; sampling makes
+ * the rock under the robot bad (p = 0); a reading z (1 good, 2 bad) of rock
+ * i at Euclidean distance d, correct with probability 0.5 + 0.5 2^(-d/20),
+ * updates p_i by Bayes' rule.  *out is b with the new cell and p_good =
+ * p_out (caller-owned, n_rocks entries); *terminal is 1 when the action
+ * leaves the grid eastwards.  HDX_E_UNSUPPORTED for other models,
+ * HDX_E_INVALID for a cell outside the grid, an unknown action, or a
+ * reading that is neither 1 nor 2. */
+hdx_status hdx_belief_update(const hdx_model_desc *desc, const hdx_belief *b, int32_t action, uint64_t z,
+                             hdx_belief *out, double *p_out, int32_t *terminal);
 
 /* ---- Rollout-value surrogate ------------------------------------------- */
 

@@ -71,11 +71,11 @@ struct LeafTask {
     int32_t policy, const_action, max_steps, max_depth;
     StatesPtr parent;
     const uint32_t *parent_ids;
-    const int32_t *idx;
+    const int16_t *idx;
     int32_t n, depth, last_action, cap;
     StatesPtr out;
     uint32_t *ids_out;
-    int32_t *perm;
+    int16_t *perm;
     int32_t *n_children;
     uint64_t *child_z;
     int32_t *child_n, *child_off;

@@ -427,7 +427,7 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
         for (int k = tid; k < n; k += nt) {
             const int32_t cw = kchild[k];
             const int v = cw & 31;
-            T->perm[(int64_t)a * n + koff[v] + kc[(k >> 6) * 32 + v] + (cw >> 5)] = k;
+            T->perm[(int64_t)a * n + koff[v] + kc[(k >> 6) * 32 + v] + (cw >> 5)] = (int16_t)k;
             if (T->child_of) T->child_of[(int64_t)a * n + k] = kci[v];
         }
         __syncthreads();  // LDS is reused by the next tile
@@ -579,7 +579,7 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
         for (int i = tid; i < n; i += nt) permb[i] = (int32_t)(comp[i] & 0xFFFFu);
         __syncthreads();
     }
-    for (int i = tid; i < n; i += nt) T->perm[(int64_t)a * n + i] = permb[i];
+    for (int i = tid; i < n; i += nt) T->perm[(int64_t)a * n + i] = (int16_t)permb[i];
     for (int c = tid; c < D && c < cap; c += nt) {
         T->child_n[(int64_t)a * cap + c] = nc[c];
         T->child_off[(int64_t)a * cap + c] = off[c];

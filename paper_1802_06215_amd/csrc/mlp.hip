@@ -593,7 +593,7 @@ __global__ __launch_bounds__(64) void surrogate_reduce(const SurPack P) {
     const int n = A.n, lane = threadIdx.x;
     const float *v = A.values + (int64_t)a * n;
     const int nch = min(A.n_children[a], A.cap);
-    const int32_t *perm = A.perm + (int64_t)a * n;
+    const int16_t *perm = A.perm + (int64_t)a * n;
     if (nch <= 16) {
         for (int c = 0; c < nch; ++c) {
             const int off = A.child_off[a * A.cap + c], cnt = A.child_n[a * A.cap + c];

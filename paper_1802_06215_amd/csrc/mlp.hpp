@@ -76,7 +76,8 @@ hipError_t mlp_sum_loss(const float *part, int n, float *out, hipStream_t s);
 
 struct SurArgs {
     const float *values;  // [A][n] surrogate value per (action, scenario)
-    const int32_t *perm, *n_children, *child_n, *child_off;
+    const int16_t *perm;
+    const int32_t *n_children, *child_n, *child_off;
     float *child_l0;
     float *L_out;  // optional [A][n]
     int32_t n, cap, n_actions, pad;

@@ -385,6 +385,22 @@ int32_t hdx_model_max_children(const hdx_model *m, int32_t n) {
     return n;                                                  // hashed observations
 }
 
+size_t hdx_expand_out_bytes(const hdx_model *m, int32_t K, int32_t n_leaves) {
+    if (!m || K < 0 || n_leaves < 0) return 0;
+    const hdx_model_desc &d = m->desc;
+    const size_t A = (size_t)d.n_actions, n = (size_t)K;
+    const size_t cap = (size_t)std::max(hdx_model_max_children(m, K), 1);
+    auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t states;
+    if (d.kind == HDX_ROCKSAMPLE) states = r(4 * n);
+    else if (d.kind == HDX_MARS) states = r(8 * n);
+    else if (d.kind == HDX_NAV) states = r(20 * n);
+    else states = 2 * r(4 * n) + 2 * r(4 * (size_t)d.n_peds * n) + r((size_t)d.n_peds * n);
+    const size_t per_leaf = states + r(4 * n) + r(2 * A * n) + r(4 * A) + r(8 * A * cap) + 4 * r(4 * A * cap) +
+                            r(4 * A) + r(16 * A);
+    return per_leaf * (size_t)n_leaves;
+}
+
 static StatesPtr to_ptr(const hdx_states &s) {
     StatesPtr p;
     p.w = s.w;

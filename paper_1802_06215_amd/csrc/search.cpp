@@ -70,7 +70,7 @@ RecLayout rec_layout(const hdx_model_desc &d, int n, int cap) {
         L.goal = take(1ull * d.n_peds * n);
     }
     L.ids = take(4ull * n);
-    L.perm = take(4ull * A * n);
+    L.perm = take(2ull * A * n);
     L.total = o;
     return L;
 }
@@ -88,7 +88,7 @@ struct Node {
     int32_t depth = 0;
     double u = 0.0, l = 0.0;
     int32_t parent_rec = -1;          // record holding the parent's states
-    const int32_t *idx_dev = nullptr;  // positions in that record
+    const int16_t *idx_dev = nullptr;  // positions in that record
     int32_t state = 0;                // 0 leaf, 1 being expanded, 2 expanded
     int32_t visits = 0, vloss = 0;
     int32_t act_begin = -1;
@@ -184,7 +184,7 @@ struct Judge {
 void fill_outputs(const hdx_model_desc &d, hdx_leaf &L, const Rec &r, char *head) {
     L.states_out = rec_states(d, r);
     L.ids_out = (uint32_t *)(r.dev + r.L.ids);
-    L.perm = (int32_t *)(r.dev + r.L.perm);
+    L.perm = (int16_t *)(r.dev + r.L.perm);
     L.n_children = (int32_t *)(head + r.L.n_children);
     L.child_z = (uint64_t *)(head + r.L.child_z);
     L.child_n = (int32_t *)(head + r.L.child_n);
@@ -342,7 +342,7 @@ struct Search {
                 k.u = cu[a * cap + c];
                 k.l = cl[a * cap + c];
                 k.parent_rec = rec_index;
-                k.idx_dev = (const int32_t *)(r.dev + r.L.perm) + (size_t)a * parent_n + co[a * cap + c];
+                k.idx_dev = (const int16_t *)(r.dev + r.L.perm) + (size_t)a * parent_n + co[a * cap + c];
                 nodes.push_back(k);
             }
             refresh(acts[ai], parent_n);
@@ -636,25 +636,31 @@ extern "C" hdx_status hdx_search(hdx_ctx *ctx, const hdx_model *model, const hdx
 
     // root: sample K scenarios (Sec. III-A) and set the initial bounds
     Rec root_rec;
-    int32_t *iota = nullptr, *depths = nullptr;
+    int16_t *iota = nullptr;  // the root's positions 0..K-1 in its own record
+    int32_t *depths = nullptr;
     float *U = nullptr, *L = nullptr;
     const size_t K = (size_t)cfg->K;
     if (!S.alloc_rec(cfg->K, &root_rec)) st = HDX_E_NOMEM;
     if (st == HDX_OK) {
-        const int64_t at = S.arena_used.fetch_add((int64_t)align16(16 * K));
-        if (at + (int64_t)align16(16 * K) > cfg->arena_bytes) st = HDX_E_NOMEM;
-        iota = (int32_t *)(S.arena + at);
-        depths = iota + K;
+        const int64_t bytes = (int64_t)align16(14 * K);
+        const int64_t at = S.arena_used.fetch_add(bytes);
+        if (at + bytes > cfg->arena_bytes) st = HDX_E_NOMEM;
+        depths = (int32_t *)(S.arena + at);
         U = (float *)(depths + K);
         L = U + K;
+        iota = (int16_t *)(L + K);
     }
     std::vector<int32_t> h_iota(K), h_zero(K, 0);
+    std::vector<int16_t> h_iota16(K);
     std::vector<float> hU(K), hL(K);
-    for (size_t k = 0; k < K; ++k) h_iota[k] = (int32_t)k;
+    for (size_t k = 0; k < K; ++k) {
+        h_iota[k] = (int32_t)k;
+        h_iota16[k] = (int16_t)k;
+    }
     if (st == HDX_OK)
         st = hdx_sample_scenarios(ctx, model, belief, cfg->K, cfg->seed, cfg->step, rec_states(S.d, root_rec),
                                   main_stream);
-    if (st == HDX_OK && (hipMemcpyAsync(iota, h_iota.data(), 4 * K, hipMemcpyHostToDevice, main_stream) != hipSuccess ||
+    if (st == HDX_OK && (hipMemcpyAsync(iota, h_iota16.data(), 2 * K, hipMemcpyHostToDevice, main_stream) != hipSuccess ||
                          hipMemcpyAsync(depths, h_zero.data(), 4 * K, hipMemcpyHostToDevice, main_stream) != hipSuccess ||
                          hipMemcpyAsync(root_rec.dev + root_rec.L.ids, h_iota.data(), 4 * K, hipMemcpyHostToDevice,
                                         main_stream) != hipSuccess))

@@ -1,6 +1,8 @@
 // DESPOT tree on the host and the Bellman backup of Eq. 4 (Sec. III-A).
 // Nodes keep their scenario count and bounds; an expanded node keeps, per
 // action, the mean step reward and the range of its observation children.
+#include <math.h>
+
 #include <algorithm>
 #include <limits>
 #include <mutex>
@@ -121,3 +123,46 @@ hdx_status hdx_tree_bounds(const hdx_tree *t, int64_t node, double *u, double *l
 }
 
 }  // extern "C"
+
+// ---- Belief update of the online loop (Sec. III-A, Eq. 3) ----------------
+// RockSample's state is the robot cell, which moves deterministically, and
+// the rock qualities, independent a priori and each touched by at most one
+// action per step; the belief factors into the cell and one probability per
+// rock, and Eq. 3 (Bayes' rule over the transition and the observation
+// likelihood) reduces to: a move sets the cell, sampling makes the rock
+// under the robot bad, and a reading z of rock i at Euclidean distance d is
+// correct with probability acc(d) = 0.5 + 0.5 2^(-d/20), so
+// P'(good) = P(good) L(z|good) / (P(good) L(z|good) + P(bad) L(z|bad)).
+extern "C" hdx_status hdx_belief_update(const hdx_model_desc *d, const hdx_belief *b, int32_t action, uint64_t z,
+                                        hdx_belief *out, double *p_out, int32_t *terminal) {
+    if (!d || !b || !out || !terminal || (d->n_rocks > 0 && (!b->p_good || !p_out))) return HDX_E_INVALID;
+    if (d->kind != HDX_ROCKSAMPLE) return HDX_E_UNSUPPORTED;
+    const int n = d->grid, m = d->n_rocks;
+    if (action < 0 || action >= 5 + m || b->x < 0 || b->x >= n || b->y < 0 || b->y >= n) return HDX_E_INVALID;
+    if (action >= 5 && z != 1 && z != 2) return HDX_E_INVALID;  // a reading is good (1) or bad (2)
+    for (int i = 0; i < m; ++i) p_out[i] = b->p_good[i];
+    *out = *b;
+    out->p_good = p_out;
+    *terminal = 0;
+    int x = b->x, y = b->y;
+    if (action == 0 && y + 1 < n) y += 1;       // north
+    else if (action == 1 && y > 0) y -= 1;      // south
+    else if (action == 3 && x > 0) x -= 1;      // west
+    else if (action == 2) {                     // east; leaving the grid ends the episode
+        if (x + 1 >= n) *terminal = 1;
+        else x += 1;
+    } else if (action == 4) {
+        for (int i = 0; i < m; ++i)
+            if (d->rock_x[i] == b->x && d->rock_y[i] == b->y) p_out[i] = 0.0;
+    } else if (action >= 5) {
+        const int i = action - 5;
+        const double dx = (double)(b->x - d->rock_x[i]), dy = (double)(b->y - d->rock_y[i]);
+        const double acc = 0.5 + 0.5 * pow(2.0, -sqrt(dx * dx + dy * dy) / 20.0);
+        const double lg = z == 1 ? acc : 1.0 - acc, lb = z == 1 ? 1.0 - acc : acc;
+        const double den = b->p_good[i] * lg + (1.0 - b->p_good[i]) * lb;
+        if (den > 0.0) p_out[i] = b->p_good[i] * lg / den;
+    }
+    out->x = x;
+    out->y = y;
+    return HDX_OK;
+}

@@ -5,10 +5,10 @@ action is executed in a true environment, and the belief is updated from the
 observation.  The true environment is stepped by the library's own
 expansion kernel (a one-scenario leaf whose parent is the true state, with a
 random-number key of its own), so the environment and the planner share one
-model definition.  The belief is the robot cell (observed) and each rock's
-probability of being good, updated by Bayes' rule on a sensor reading: a
-reading is correct with probability 0.5 + 0.5 * 2^(-d/20) at Euclidean
-distance d; a sampled rock is known to be bad afterwards.
+model definition.  The belief (the robot cell and each rock's probability
+of being good) is updated by the library's hdx_belief_update (Eq. 3).  This
+module is a driver of the library's calls and holds none of the method's
+arithmetic.
 """
 from __future__ import annotations
 
@@ -16,10 +16,6 @@ import numpy as np
 import torch
 
 from . import hdx as H
-
-
-def sensor_accuracy(d: float) -> float:
-    return 0.5 + 0.5 * 2.0 ** (-d / 20.0)
 
 
 class RockSampleEnv:
@@ -32,7 +28,7 @@ class RockSampleEnv:
         self.seed = seed
         self.t = 0
         self._ids = torch.zeros(1, dtype=torch.int32, device="cuda")
-        self._idx = torch.zeros(1, dtype=torch.int32, device="cuda")
+        self._idx = torch.zeros(1, dtype=torch.int16, device="cuda")
         self._out = H.LeafBuffers(model, 1, per_pair=True)
         self._cfg = H.rollout_cfg(H.POLICY_CONST, 0, -1, 0)  # no rollouts: only the step
 
@@ -50,23 +46,6 @@ class RockSampleEnv:
         self.term = bool((w >> 30) & 1)
         self.t += 1
         return r, z
-
-
-def update_belief(desc: dict, belief: dict, action: int, z: int, x: int, y: int) -> dict:
-    """Belief after `action` with observation z, the robot now at (x, y)."""
-    p = np.asarray(belief["p"], dtype=np.float64).copy()
-    rx, ry = np.asarray(desc["rock_x"]), np.asarray(desc["rock_y"])
-    if action == 4:  # sampling leaves the rock under the robot bad
-        for i in range(desc["m"]):
-            if rx[i] == belief["x"] and ry[i] == belief["y"]:
-                p[i] = 0.0
-    elif action >= 5:
-        i = action - 5
-        acc = sensor_accuracy(float(np.hypot(belief["x"] - rx[i], belief["y"] - ry[i])))
-        lg, lb = (acc, 1.0 - acc) if z == 1 else (1.0 - acc, acc)
-        den = p[i] * lg + (1.0 - p[i]) * lb
-        p[i] = p[i] * lg / den if den > 0 else p[i]
-    return dict(x=int(x), y=int(y), p=p)
 
 
 def run_rocksample(ctx: "H.Context", model: "H.Model", desc: dict, true_rocks, max_steps: int,
@@ -90,6 +69,7 @@ def run_rocksample(ctx: "H.Context", model: "H.Model", desc: dict, true_rocks, m
         disc *= gamma
         if env.term:
             break
-        belief = update_belief(desc, belief, a, z, env.x, env.y)
+        belief, _ = H.belief_update(desc, belief, a, z)
+        assert (belief["x"], belief["y"]) == (env.x, env.y)
     return dict(actions=actions, rewards=rewards, discounted_return=total, steps=len(actions),
                 exited=env.term, trials=trials)

@@ -112,7 +112,8 @@ EXPORTS = ["hdx_version", "hdx_init", "hdx_fini", "hdx_last_error", "hdx_upload_
            "hdx_mlp_get_params", "hdx_mlp_set_params", "hdx_mlp_forward", "hdx_mlp_gradients",
            "hdx_mlp_train_step", "hdx_features", "hdx_expand_leaf_surrogate", "hdx_mlp_save", "hdx_mlp_load",
            "hdx_tree_create", "hdx_tree_destroy", "hdx_tree_add_children", "hdx_backup",
-           "hdx_tree_bounds", "hdx_tree_size", "hdx_expand_leaf_noalloc"]
+           "hdx_tree_bounds", "hdx_tree_size", "hdx_expand_leaf_noalloc", "hdx_expand_out_bytes",
+           "hdx_belief_update"]
 
 _lib = None
 
@@ -139,6 +140,10 @@ def load_library():
     L.hdx_sample_scenarios.argtypes = [P, P, C.POINTER(Belief), I32, U32, U32, States, P]
     L.hdx_expand_leaf.argtypes = [P, P, I32, P]
     L.hdx_expand_leaf_noalloc.argtypes = [P, P, I32, P]
+    L.hdx_expand_out_bytes.argtypes = [P, I32, I32]
+    L.hdx_expand_out_bytes.restype = C.c_size_t
+    L.hdx_belief_update.argtypes = [C.POINTER(ModelDesc), C.POINTER(Belief), I32, C.c_uint64, C.POINTER(Belief),
+                                    P, C.POINTER(I32)]
     L.hdx_rollout_bounds.argtypes = [P, P, C.POINTER(RolloutCfg), U32, U32, States, P, P, I64,
                                      P, P, P, P]
     L.hdx_philox.argtypes = [P, P, I64, U32, U32, P, P]
@@ -234,6 +239,11 @@ class Model:
         self.n_actions = desc["n_actions"]
         self.n_peds = desc.get("n_peds", 0)
 
+    def out_bytes(self, K: int, n_leaves: int = 1) -> int:
+        """hdx_expand_out_bytes: device bytes of the required outputs of
+        n_leaves leaves of K scenarios."""
+        return int(self.ctx.lib.hdx_expand_out_bytes(self.handle, K, n_leaves))
+
     def max_children(self, n: int) -> int:
         return self.ctx.lib.hdx_model_max_children(self.handle, n)
 
@@ -283,7 +293,7 @@ class LeafBuffers:
         i32, f32 = torch.int32, torch.float32
         self.states = empty_states(model, max(n, 1), device)
         self.ids = torch.empty(max(n, 1), dtype=torch.int32, device=device)
-        self.perm = torch.empty((A, max(n, 1)), dtype=i32, device=device)
+        self.perm = torch.empty((A, max(n, 1)), dtype=torch.int16, device=device)
         self.n_children = torch.empty(A, dtype=i32, device=device)
         self.child_z = torch.empty((A, cap), dtype=torch.int64, device=device)
         self.child_n = torch.empty((A, cap), dtype=i32, device=device)
@@ -314,7 +324,7 @@ def leaf_buffer_slab(model: Model, count: int, n_max: int, device="cuda") -> lis
     n1 = max(n_max, 1)
     i32, f32 = torch.int32, torch.float32
     slabs = dict(ids=torch.empty((count, n1), dtype=i32, device=device),
-                 perm=torch.empty((count, A, n1), dtype=i32, device=device),
+                 perm=torch.empty((count, A, n1), dtype=torch.int16, device=device),
                  n_children=torch.empty((count, A), dtype=i32, device=device),
                  child_z=torch.empty((count, A, cap), dtype=torch.int64, device=device),
                  child_n=torch.empty((count, A, cap), dtype=i32, device=device),
@@ -391,9 +401,40 @@ def pednav_states(s, level, term, px, py, goal, device="cuda") -> dict:
                 goal=f(goal, np.uint8))
 
 
+def positions(idx, device="cuda") -> torch.Tensor:
+    """A leaf's positions in its parent's arrays as the int16 device tensor
+    hdx_leaf.idx takes."""
+    a = np.asarray(idx)
+    if a.size and (a.min() < 0 or a.max() >= 1 << 15):
+        raise ValueError("positions must lie in [0, 32768)")
+    return torch.from_numpy(np.ascontiguousarray(a.astype(np.int16))).to(device)
+
+
+def belief_update(desc: dict, belief: dict, action: int, z: int):
+    """RockSample belief after `action` and observation z (Eq. 3), computed
+    by hdx_belief_update; returns (new belief dict, terminal)."""
+    lib = load_library()
+    md = model_desc(desc)
+    p = np.ascontiguousarray(belief["p"], dtype=np.float64)
+    b = Belief()
+    b.x, b.y, b.p_good = int(belief["x"]), int(belief["y"]), p.ctypes.data
+    out = Belief()
+    p_out = np.empty_like(p)
+    term = C.c_int32(0)
+    rc = lib.hdx_belief_update(C.byref(md), C.byref(b), int(action), int(z), C.byref(out),
+                               p_out.ctypes.data, C.byref(term))
+    if rc != 0:
+        raise HdxError(rc, "hdx_belief_update")
+    return dict(x=int(out.x), y=int(out.y), p=p_out), bool(term.value)
+
+
 def make_leaf(model: Model, parent: dict, parent_ids, idx, depth: int, last_action: int,
               out: LeafBuffers, seed: int, step: int, cfg: RolloutCfg) -> Leaf:
-    """An hdx_leaf descriptor over device tensors (they must outlive the call)."""
+    """An hdx_leaf descriptor over device tensors (they must outlive the call).
+    idx holds int16 positions (a child's idx is a segment of its parent's
+    perm, which the library writes as int16)."""
+    if idx.dtype != torch.int16:
+        raise TypeError("idx must be an int16 tensor, got %s" % idx.dtype)
     L = Leaf()
     L.model = model.handle
     L.seed, L.step = seed, step

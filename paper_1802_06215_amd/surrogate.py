@@ -88,7 +88,7 @@ def root_values_same_tree(ctx: "H.Context", model: "H.Model", gamma: float, root
     dev = root[next(iter(root))].device
     A = model.n_actions
     ids = torch.arange(K, dtype=torch.int32, device=dev)
-    idx = torch.arange(K, dtype=torch.int32, device=dev)
+    idx = torch.arange(K, dtype=torch.int16, device=dev)
     out0 = H.LeafBuffers(model, K)
     ctx.expand_leaf([H.make_leaf(model, root, ids, idx, 0, -1, out0, key, 0, cfg)])
     torch.cuda.synchronize()
@@ -97,7 +97,7 @@ def root_values_same_tree(ctx: "H.Context", model: "H.Model", gamma: float, root
     nodes, keep, leaves = [], [], []
     for a in range(A):
         for c in range(int(nc0[a])):
-            seg = torch.from_numpy(perm0[a, off0[a, c]:off0[a, c] + cn0[a, c]].astype(np.int32)).to(dev)
+            seg = torch.from_numpy(perm0[a, off0[a, c]:off0[a, c] + cn0[a, c]].astype(np.int16)).to(dev)
             out = H.LeafBuffers(model, int(cn0[a, c]), per_pair=True)
             leaves.append(H.make_leaf(model, root, ids, seg, 1, a, out, key, 0, cfg))
             nodes.append(out)
@@ -166,7 +166,7 @@ def planner_pairs(ctx: "H.Context", model: "H.Model", root_states, K: int, cfg: 
         root = root_states(seed)
         dev = root[next(iter(root))].device
         ids = torch.arange(K, dtype=torch.int32, device=dev)
-        level = [(root, ids, torch.arange(K, dtype=torch.int32, device=dev), 0, -1)]
+        level = [(root, ids, torch.arange(K, dtype=torch.int16, device=dev), 0, -1)]
         keep = []
         for _ in range(levels):
             outs = [H.LeafBuffers(model, int(idx.numel()), per_pair=True) for _, _, idx, _, _ in level]

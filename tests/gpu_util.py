@@ -32,7 +32,7 @@ def cfg_pair(policy=0, max_steps=1 << 30, max_depth=-1, const_action=0):
 
 def gpu_leaf_desc(model, parent_dev, pids_dev, idx_np, depth, last_action, seed, step, hcfg,
                   per_pair=True):
-    idx = ids_dev(idx_np)
+    idx = H.positions(idx_np)
     out = H.LeafBuffers(model, len(idx_np), per_pair)
     leaf = H.make_leaf(model, parent_dev, pids_dev, idx, depth, last_action, out, seed, step, hcfg)
     return leaf, out, idx

@@ -307,3 +307,20 @@ def test_fp32_rounding_selftest(ctx):
         want = [np.sqrt(np.abs(a)), a / b, a * b + c, np.floor(a)]
     for i, w in enumerate(want):
         assert np.array_equal(out[i].view(np.uint32), w.astype(np.float32).view(np.uint32)), i
+
+
+@pytest.mark.parametrize("which", ["rs", "ped", "mars", "nav"])
+def test_expand_out_bytes_covers_the_required_outputs(ctx, which):
+    from paper_1802_06215_amd import hdx as H
+    desc = dict(rs=lambda: W.rocksample_model(15, 15, 1), ped=lambda: W.pednav_model(16, 5, 1),
+                mars=lambda: W.mars_model(11, 11, 1), nav=lambda: W.nav_model(1))[which]()
+    m = ctx.upload_model(desc)
+    r = lambda b: (b + 255) // 256 * 256
+    for K in (1, 100, 500, 2048):
+        out = H.LeafBuffers(m, K)
+        tensors = list(out.states.values()) + [out.ids, out.perm, out.n_children, out.child_z, out.child_n,
+                                               out.child_off, out.child_u0, out.child_l0, out.r_mean, out.steps]
+        want = sum(r(t.numel() * t.element_size()) for t in tensors)
+        assert m.out_bytes(K) == want, (which, K)
+        assert m.out_bytes(K, 7) == 7 * want
+    assert m.out_bytes(-1) == 0

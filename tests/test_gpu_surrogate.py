@@ -171,7 +171,7 @@ def expand_with_rollouts(ctx, m, desc, leaves_spec, hcfg):
         lf = W.rocksample_leaf(desc, 500, n, seed, depth=depth)
         par = H.rocksample_states(lf["x"], lf["y"], lf["rocks"], lf["term"])
         pids = torch.from_numpy(lf["ids"].astype(np.int32)).cuda()
-        idx = torch.from_numpy(lf["idx"]).cuda()
+        idx = H.positions(lf["idx"])
         out = H.LeafBuffers(m, n, per_pair=True)
         descs.append(H.make_leaf(m, par, pids, idx, lf["depth"], lf["last_action"], out, seed, 0, hcfg))
         outs.append((out, lf["depth"]))
@@ -330,7 +330,7 @@ def test_planner_pairs_first_level(ctx):
     root = root_of(5)
     out = H.LeafBuffers(m, K, per_pair=True)
     ids = torch.arange(K, dtype=torch.int32, device="cuda")
-    ctx.expand_leaf([H.make_leaf(m, root, ids, ids.clone(), 0, -1, out, 5, 0, cfg)])
+    ctx.expand_leaf([H.make_leaf(m, root, ids, H.positions(np.arange(K)), 0, -1, out, 5, 0, cfg)])
     sp = {k: v[..., :A * K].contiguous() for k, v in out.sprime.items()}
     fids = out.ids[:K].repeat(A)
     depths = torch.ones(A * K, dtype=torch.int32, device="cuda")
