@@ -82,6 +82,9 @@ def parse():
                     help="time the expand/group stage alone (rollouts of length 0; for profiling that stage)")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only the surrogate comparison (prints its JSON object; for profiling the MLP kernels)")
+    ap.add_argument("--mlp-only", action="store_true",
+                    help="only the surrogate MLP kernels on random BF16 features: the forward over 4.65 M rows and "
+                         "training steps at several batch sizes (prints a JSON object; for profiling the MLP kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (x3), to scale HBM byte counters")
     ap.add_argument("--search-seconds", type=float, default=1.0,
@@ -535,6 +538,48 @@ def surrogate_section(ctx, args):
                     if runs else None))
 
 
+def mlp_section(ctx, args):
+    """The MLP kernels alone on random features (no data generation): the
+    fused forward over as many rows as the surrogate comparison's training
+    set, and Adam steps at batch sizes 4096 to 65536; HIP-event times on the
+    launch stream, TFLOP/s against 2.5 PFLOP/s dense BF16."""
+    import torch
+
+    from paper_1802_06215_amd import Mlp
+    from paper_1802_06215_amd import surrogate as S
+
+    g = torch.Generator(device="cuda").manual_seed(7)
+    rows = 4_650_000 // 128 * 128
+    X = torch.rand((rows, 64), generator=g, device="cuda").to(torch.bfloat16).view(torch.int16)
+    t = torch.rand(rows, generator=g, device="cuda")
+    net = Mlp(ctx, seed=1)
+    out = dict(forward=None, train=[])
+    net.forward(X)
+    torch.cuda.synchronize()
+    ms = _timed_events(lambda: net.forward(X), 3)
+    out["forward"] = dict(rows=rows, ms=round(ms, 3), tflops=round(S.FLOPS_FWD * rows / ms / 1e9, 1),
+                          frac=round(S.FLOPS_FWD * rows / ms / 1e9 / PEAK_BF16_TFLOPS, 4))
+    loss = torch.zeros(1, device="cuda")
+    for B in (4096, 16384, 65536):
+        steps = 20
+        for i in range(3):
+            net.train_step(X[i * B:(i + 1) * B], t[i * B:(i + 1) * B], 1e-4, loss)
+        torch.cuda.synchronize()
+        i = [0]
+
+        def step():
+            j = i[0] % (rows // B)
+            net.train_step(X[j * B:(j + 1) * B], t[j * B:(j + 1) * B], 1e-4, loss)
+            i[0] += 1
+        ms = _timed_events(step, steps)
+        out["train"].append(dict(batch=B, ms_per_step=round(ms, 4), samples_per_s=round(B / ms * 1e3, 1),
+                                 tflops=round(S.FLOPS_TRAIN * B / ms / 1e9, 2),
+                                 frac=round(S.FLOPS_TRAIN * B / ms / 1e9 / PEAK_BF16_TFLOPS, 4)))
+        log("mlp train", out["train"][-1])
+    net.close()
+    return out
+
+
 def cpu_baseline(items, seconds):
     """The oracle as it stands over leaves of the same batch, timed as the
     scope table asks: five measurements of at least seconds/10 each (the
@@ -780,6 +825,10 @@ def main():
         log("copied %d bytes x3" % (a.numel() * 4))
         return
     ctx = H.Context(0)
+    if args.mlp_only:
+        print(json.dumps(dict(mlp=mlp_section(ctx, args))), flush=True)
+        ctx.close()
+        return
     if args.surrogate_only:
         print(json.dumps(dict(surrogate=surrogate_section(ctx, args))), flush=True)
         ctx.close()
@@ -999,7 +1048,8 @@ def main():
     out = dict(metric=METRIC, value=round(value, 1), unit="scenario-steps/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(wall * 1e3 / args.steps, 4), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="int32+fp32", data="synthetic",
-               config=dict(workload=names[args.workload] % len(leaves), leaves=len(leaves), tiles=n_tiles,
+               config=dict(workload=names[args.workload] % len(leaves), leaves=len(leaves),
+                           leaf_actions=n_tiles, tiles=sum(g["tiles"] for g in per_class),
                            scenario_steps_per_step=steps_per_launch, expand_steps=exp_steps,
                            rollout_steps=roll_steps, split_by_size_class=batch.split(), schedule=per_class,
                            hip_graph=True, autotune_ms=tuned_ms),

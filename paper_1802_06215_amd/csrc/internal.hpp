@@ -275,8 +275,8 @@ struct SampleArgs {
     uint64_t cell_thr[HDX_MAX_NAV_UNKNOWN];  // navigation: P(occupied) thresholds
     StatesPtr out;
 };
-static_assert(sizeof(SampleArgs) <= 4096, "sample kernel arguments too large");
-hipError_t launch_sample(const SampleArgs &args, hipStream_t stream);
+// Staged in device memory (d_args) before the launch.
+hipError_t launch_sample(const SampleArgs *d_args, int32_t K, hipStream_t stream);
 
 struct BoundsArgs {
     const DevModel *model;

@@ -771,7 +771,9 @@ hipError_t launch_expand_t(const LeafTask *d_tasks, const Tile *d_tiles, TileQue
 // ---------------------------------------------------------------------------
 // sample_scenarios
 // ---------------------------------------------------------------------------
-__global__ void sample_kernel(const SampleArgs A) {
+// The arguments (belief thresholds, ~3.6 KB) are read from device memory.
+__global__ void sample_kernel(const SampleArgs *args) {
+    const HDX_CONST SampleArgs &A = *(const HDX_CONST SampleArgs *)args;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= A.K) return;
     const HDX_CONST ModelHdr *M = (const HDX_CONST ModelHdr *)&A.model->h;
@@ -946,10 +948,11 @@ hipError_t launch_expand_args(const ArgPack &pack, const Variant &v, const Sched
 #undef HDX_LAUNCH
 }
 
-hipError_t launch_sample(const SampleArgs &args, hipStream_t stream) {
+hipError_t launch_sample(const SampleArgs *d_args, int32_t K, hipStream_t stream) {
     const int threads = 256;
-    const int blocks = (args.K + threads - 1) / threads;
-    hipLaunchKernelGGL(sample_kernel, dim3(blocks), dim3(threads), 0, stream, args);
+    const int blocks = (K + threads - 1) / threads;
+    if (blocks < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(sample_kernel, dim3(blocks), dim3(threads), 0, stream, d_args);
     return hipGetLastError();
 }
 

@@ -65,12 +65,13 @@ hipError_t mlp_backward(const MlpDev &P, const uint16_t *X, const float *t, int 
                         hipStream_t s);
 hipError_t mlp_adam(MlpDev &P, const float *grads, float lr, int step, hipStream_t s);
 hipError_t mlp_refresh_bf16(MlpDev &P, hipStream_t s);
-// Features of several state arrays, kFeatPack per launch (kernel arguments).
-constexpr int kFeatPack = 36;
+// Features of several state arrays, kFeatPack per launch (kernel arguments,
+// kept under 1 KB).
+constexpr int kFeatPack = 8;
 struct FeatPack {
     FeatArgs a[kFeatPack];
 };
-static_assert(sizeof(FeatPack) <= 4096, "kernel argument pack too large");
+static_assert(sizeof(FeatPack) <= 1024, "kernel argument pack too large");
 hipError_t launch_features(const FeatArgs *a, int count, hipStream_t s);
 hipError_t mlp_sum_loss(const float *part, int n, float *out, hipStream_t s);
 
@@ -82,11 +83,11 @@ struct SurArgs {
     float *L_out;  // optional [A][n]
     int32_t n, cap, n_actions, pad;
 };
-constexpr int kSurPack = 56;
+constexpr int kSurPack = 12;  // kernel arguments kept under 1 KB
 struct SurPack {
     SurArgs a[kSurPack];
 };
-static_assert(sizeof(SurPack) <= 4096, "kernel argument pack too large");
+static_assert(sizeof(SurPack) <= 1024, "kernel argument pack too large");
 hipError_t launch_surrogate_reduce(const SurArgs *a, int count, hipStream_t s);
 
 }  // namespace hdx

@@ -16,6 +16,14 @@ using namespace hdx;
 namespace {
 
 constexpr int kSlots = 16;  // concurrent expand calls in flight per context
+constexpr int kArgSlots = 8;  // argument blocks staged in device memory per context
+
+// Pinned staging and device copy of one launch's argument block.
+struct ArgSlot {
+    void *h = nullptr, *d = nullptr;
+    hipEvent_t done = nullptr;
+    bool used = false;
+};
 
 // Pinned staging + device copy of one call's leaf descriptors and tiles.
 struct Slot {
@@ -97,6 +105,8 @@ struct hdx_ctx {
     hipStream_t cls_stream[kGroups] = {};  // one stream per launch group (default priority)
     Schedule sched{256, 0, 1};
     bool sched_fixed = false;
+    ArgSlot arg_slots[kArgSlots];
+    int next_arg_slot = 0;
     // expansion without allocation: the device's fixed scratch array (its
     // address from hipGetSymbolAddress), pinned host staging and events made
     // here at set-up, and fixed host arrays for planning
@@ -166,6 +176,12 @@ hdx_status hdx_init(int32_t device, hdx_ctx **out) {
         hdx_fini(ctx);
         return HDX_E_DEVICE;
     }
+    for (auto &a : ctx->arg_slots)
+        if (hipHostMalloc(&a.h, sizeof(SampleArgs)) != hipSuccess || hipMalloc(&a.d, sizeof(SampleArgs)) != hipSuccess ||
+            hipEventCreateWithFlags(&a.done, hipEventDisableTiming) != hipSuccess) {
+            hdx_fini(ctx);
+            return HDX_E_NOMEM;
+        }
     // set-up of hdx_expand_leaf_noalloc: the scratch's device address, host
     // staging and events, so that the call itself allocates nothing
     ctx->err.reserve(kErrCap);
@@ -205,6 +221,14 @@ hdx_status hdx_fini(hdx_ctx *ctx) {
     if (ctx->na_done) {
         hipEventSynchronize(ctx->na_done);
         hipEventDestroy(ctx->na_done);
+    }
+    for (auto &a : ctx->arg_slots) {
+        if (a.done) {
+            hipEventSynchronize(a.done);
+            hipEventDestroy(a.done);
+        }
+        if (a.h) hipHostFree(a.h);
+        if (a.d) hipFree(a.d);
     }
     destroy_events(&ctx->na_fork, ctx->na_join);
     if (ctx->na_h_tasks) hipHostFree(ctx->na_h_tasks);
@@ -373,6 +397,10 @@ void hdx_internal_quiesce(hdx_ctx *ctx) {
         if (s.used) hipEventSynchronize(s.done);
         s.used = false;
     }
+    for (auto &a : ctx->arg_slots) {
+        if (a.used) hipEventSynchronize(a.done);
+        a.used = false;
+    }
 }
 
 extern "C" {
@@ -470,8 +498,21 @@ hdx_status hdx_sample_scenarios(hdx_ctx *ctx, const hdx_model *m, const hdx_beli
         }
     }
     hipSetDevice(ctx->device);
-    hipError_t e = launch_sample(A, (hipStream_t)stream);
-    return e == hipSuccess ? HDX_OK : hip_fail(ctx, e, "sample_scenarios launch");
+    // the arguments go through a device slot (they are too large to travel
+    // comfortably in the kernel-argument segment); the slot is reused once
+    // the kernel that read it has run
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    ArgSlot &slot = ctx->arg_slots[ctx->next_arg_slot];
+    ctx->next_arg_slot = (ctx->next_arg_slot + 1) % kArgSlots;
+    hipError_t e = hipSuccess;
+    if (slot.used && (e = hipEventSynchronize(slot.done)) != hipSuccess) return hip_fail(ctx, e, "argument slot wait");
+    memcpy(slot.h, &A, sizeof(A));
+    e = hipMemcpyAsync(slot.d, slot.h, sizeof(A), hipMemcpyHostToDevice, (hipStream_t)stream);
+    if (e == hipSuccess) e = launch_sample((const SampleArgs *)slot.d, K, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipEventRecord(slot.done, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "sample_scenarios launch");
+    slot.used = true;
+    return HDX_OK;
 }
 
 static int64_t horizon_of(const hdx_rollout_cfg &c, int64_t d0) {

@@ -340,3 +340,103 @@ def test_planner_pairs_first_level(ctx):
         acc += L.double()
     assert torch.equal(t[:A * K], (acc / R).float())
     assert torch.equal(X[:A * K], H.features(ctx, m, sp, depths, 30))
+
+
+def _keyed_leaves(ctx, m, desc, spec, hcfg):
+    """Leaves of `spec` with per-pair outputs, and a function that re-keys
+    them: the same leaves and buffers under another random-number key."""
+    from paper_1802_06215_amd import hdx as H
+    built = []
+    for seed, n, depth in spec:
+        lf = W.rocksample_leaf(desc, 500, n, seed, depth=depth)
+        par = H.rocksample_states(lf["x"], lf["y"], lf["rocks"], lf["term"])
+        pids = torch.from_numpy(lf["ids"].astype(np.int32)).cuda()
+        idx = H.positions(lf["idx"])
+        out = H.LeafBuffers(m, n, per_pair=True)
+        built.append((par, pids, idx, lf, out))
+
+    def keyed(key=None):
+        return [H.make_leaf(m, par, pids, idx, lf["depth"], lf["last_action"], out,
+                            lf_seed if key is None else key, 0, hcfg)
+                for (par, pids, idx, lf, out), (lf_seed, _, _) in zip(built, spec)]
+    return built, keyed
+
+
+def test_surrogate_gains_over_single_rollouts(ctx):
+    """What the trained network gains over the method without it (plain
+    default-policy rollouts in Eq. 13), RockSample 15x15 with uniform-random
+    rollouts of depth 90.  On held-out leaves of 31 and 62 scenarios with
+    fixed keys, each child's l0 from the surrogate is closer to the child's
+    value -- the mean over 16 independent rollouts per (action, scenario)
+    pair -- than the l0 from the single rollouts it replaces; and at equal
+    planning time the search with the surrogate completes more trials per
+    second."""
+    from paper_1802_06215_amd import Mlp, hdx as H
+    from paper_1802_06215_amd import surrogate as S
+    desc = W.rocksample_model(15, 15, 1)
+    m = ctx.upload_model(desc)
+    hcfg = H.rollout_cfg(H.POLICY_RANDOM, 1 << 30, HORIZON)
+    # training pairs: stepped states of synthetic leaves, each target the mean
+    # of 4 rollouts (the stepped states do not depend on the key)
+    spec = [(3000 + i, 100, 1 + (7 * i) % 60) for i in range(640)]
+    built, keyed = _keyed_leaves(ctx, m, desc, spec, hcfg)
+    ctx.expand_leaf(keyed())
+    torch.cuda.synchronize()
+    X = torch.cat([S.leaf_pairs(ctx, m, out, lf["depth"], HORIZON)[0] for _, _, _, lf, out in built])
+    acc = [torch.zeros_like(out.L[:, :out.n]) for *_, out in built]
+    for r in range(4):
+        ctx.expand_leaf(keyed(600000 + r))
+        for a_, (*_, out) in zip(acc, built):
+            a_ += out.L[:, :out.n]
+    t = torch.cat([(a_ / 4).reshape(-1) for a_ in acc])
+    net = Mlp(ctx, seed=3)
+    hist = S.fit(net, X, t, epochs=8, batch=4096, lr=2e-3, lr_final=2e-4)
+    torch.cuda.synchronize()
+    print("gain: %d training pairs, epoch losses %s" % (len(t), ["%.4f" % h for h in hist]), flush=True)
+    del built, keyed, X, t, acc
+
+    # held-out leaves of the sizes a search expands below its root (62 and 31
+    # scenarios: a sense splits a node's scenarios between two readings); the
+    # reference value of a pair is its mean over 16 keys
+    spec = [(9100 + i, (62, 31)[i % 2], 1 + (13 * i) % 60) for i in range(64)]
+    built, keyed = _keyed_leaves(ctx, m, desc, spec, hcfg)
+    ctx.expand_leaf(keyed())
+    torch.cuda.synchronize()
+    one = [dict(l0=out.child_l0.cpu().numpy().copy(), nc=out.n_children.cpu().numpy().copy(),
+                off=out.child_off.cpu().numpy().copy(), cn=out.child_n.cpu().numpy().copy(),
+                perm=out.perm.cpu().numpy()[:, :out.n].astype(np.int64)) for *_, out in built]
+    ref_sum = [torch.zeros_like(out.L[:, :out.n], dtype=torch.float64) for *_, out in built]
+    for r in range(16):
+        ctx.expand_leaf(keyed(800000 + r))
+        for a_, (*_, out) in zip(ref_sum, built):
+            a_ += out.L[:, :out.n].double()
+    ctx.expand_leaf_surrogate(keyed(), net, HORIZON)  # the first key's grouping again
+    torch.cuda.synchronize()
+    e_one, e_sur = [], []
+    for h, a_, (*_, out) in zip(one, ref_sum, built):
+        truth = (a_ / 16).cpu().numpy()
+        sur = out.child_l0.cpu().numpy()
+        assert np.array_equal(out.n_children.cpu().numpy(), h["nc"])
+        for a in range(len(h["nc"])):
+            for c in range(h["nc"][a]):
+                v = truth[a, h["perm"][a, h["off"][a, c]:h["off"][a, c] + h["cn"][a, c]]].mean()
+                e_one.append(abs(h["l0"][a, c] - v))
+                e_sur.append(abs(sur[a, c] - v))
+    e_one, e_sur = float(np.mean(e_one)), float(np.mean(e_sur))
+    print("gain: child l0 mean abs error vs the 16-rollout mean: surrogate %.4f, one rollout %.4f (%d children)"
+          % (e_sur, e_one, sum(int(h["nc"].sum()) for h in one)), flush=True)
+    assert e_sur < e_one
+
+    # equal planning time: trials per second with each source of leaf values
+    b = W.rocksample_belief(desc)
+    common = dict(K=500, n_threads=8, batch_leaves=8, time_budget_s=0.5, max_depth=HORIZON, rollout=hcfg,
+                  arena_bytes=4 << 30)
+    rate = {"rollouts": [], "surrogate": []}
+    for key in (21, 22):
+        r = ctx.search(m, b, seed=key, **common)
+        rate["rollouts"].append(r["trials"] / r["elapsed_s"])
+        r = ctx.search(m, b, seed=key, surrogate=net, surrogate_horizon=HORIZON, **common)
+        rate["surrogate"].append(r["trials"] / r["elapsed_s"])
+    print("gain: trials/s rollouts %s, surrogate %s" % (rate["rollouts"], rate["surrogate"]), flush=True)
+    assert sum(rate["surrogate"]) > sum(rate["rollouts"])
+    net.close()
