@@ -471,6 +471,7 @@ def surrogate_section(ctx, args):
         per_key = [abs(runs["surrogate_trials_key%d" % k]["l_root"] - runs["rollouts_trials_key%d" % k]["l_root"]) /
                    max(abs(runs["rollouts_trials_key%d" % k]["l_root"]), 1e-9) for k in keys]
     net.close()
+    kernels = mlp_section(ctx, args)
     return dict(
         config="RockSample 15x15, 15 rocks, uniform-random rollouts of depth 90; MLP 64-256-256-256-1 "
                "(BF16 MFMA, FP32 accumulate)",
@@ -480,6 +481,8 @@ def surrogate_section(ctx, args):
                    data_gen_s=round(gen_s, 3), epochs=args.surrogate_epochs,
                    fit_s=round(train_s, 3), samples_per_s=round(samples / train_s, 1),
                    tflops=round(S.FLOPS_TRAIN * samples / train_s / 1e12, 2), losses=[round(h, 4) for h in hist]),
+        kernels=dict(note="the MLP kernels alone on random features (bench.py --mlp-only): forward over 4.65 M rows, "
+                          "Adam steps at batch 4096, 16384 and 65536", **kernels),
         forward=dict(rows=n_pairs, ms=round(fwd_s * 1e3, 3),
                      roofline=dict(bound="mfma", kernel="mlp_fused_fwd",
                                    achieved=round(S.FLOPS_FWD * n_pairs / fwd_s / 1e12, 2), peak=PEAK_BF16_TFLOPS,

@@ -25,90 +25,6 @@ __device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even; N
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// C[M x N] = op(A)[M x K] * op(B)[K x N], BF16 inputs, FP32 accumulation.
-// A is [M][K] (lda) or, if a_t, [K][M]; B is [K][N] (ldb) or, if b_t, [N][K].
-// N must be a multiple of 64 and K of 32; rows m >= M are zero / not stored.
-// blockIdx.z selects the k range [z kslice, (z + 1) kslice) (split K); with
-// EPI_F32 slice z writes its partial product at out_f + z M ldo.
-enum { EPI_BIAS_RELU_BF16 = 0, EPI_MASK_BF16 = 1, EPI_F32 = 2 };
-
-constexpr int TM = 64, TN = 64, TK = 32, KP = TK + 8;  // LDS row pad against bank conflicts
-
-__global__ __launch_bounds__(256) void gemm_bf16(int M, int N, int K, const uint16_t *__restrict__ A, int lda,
-                                                 int a_t, const uint16_t *__restrict__ B, int ldb, int b_t,
-                                                 int epi, const float *__restrict__ bias,
-                                                 const uint16_t *__restrict__ mask, int ldm, uint16_t *out_bf,
-                                                 float *out_f, int ldo, int kslice) {
-    __shared__ __align__(16) uint16_t As[TM][KP];
-    __shared__ __align__(16) uint16_t Bs[TN][KP];  // n-major: Bs[n][k]
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    f32x4 acc[2][2];
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int kbeg = blockIdx.z * kslice, kend = min(K, kbeg + kslice);
-    if (epi == EPI_F32) out_f += (size_t)blockIdx.z * M * ldo;
-    for (int k0 = kbeg; k0 < kend; k0 += TK) {
-        // A tile: 64 x 32 -> As[m][k]; 256 threads x 8 elements
-        if (!a_t) {
-            const int r = tid >> 2, c = (tid & 3) * 8;
-            const int m = m0 + r;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (m < M) v = *(const uint4 *)(A + (size_t)m * lda + k0 + c);
-            *(uint4 *)&As[r][c] = v;
-        } else {
-            const int k = tid >> 3, c = (tid & 7) * 8;  // 32 k rows x 64 m
-            const int m = m0 + c;
-            const uint16_t *src = A + (size_t)(k0 + k) * lda + m;
-            if (m + 8 <= M) {
-                const uint4 v = *(const uint4 *)src;
-                const uint16_t *e = (const uint16_t *)&v;
-                for (int i = 0; i < 8; ++i) As[c + i][k] = e[i];
-            } else {
-                for (int i = 0; i < 8; ++i) As[c + i][k] = (m + i < M) ? src[i] : (uint16_t)0;
-            }
-        }
-        // B tile: 32 x 64 -> Bs[n][k]
-        if (b_t) {
-            const int r = tid >> 2, c = (tid & 3) * 8;  // B stored [N][K]
-            *(uint4 *)&Bs[r][c] = *(const uint4 *)(B + (size_t)(n0 + r) * ldb + k0 + c);
-        } else {
-            const int k = tid >> 3, c = (tid & 7) * 8;  // B stored [K][N]
-            const uint4 v = *(const uint4 *)(B + (size_t)(k0 + k) * ldb + n0 + c);
-            const uint16_t *e = (const uint16_t *)&v;
-            for (int i = 0; i < 8; ++i) Bs[c + i][k] = e[i];
-        }
-        __syncthreads();
-        const int g = lane >> 4, q = lane & 15;
-        bf16x8 a[2], b[2];
-        for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8 *)&As[wm + i * 16 + q][g * 8];
-        for (int j = 0; j < 2; ++j) b[j] = *(const bf16x8 *)&Bs[wn + j * 16 + q][g * 8];
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-        __syncthreads();
-    }
-    // D layout: lane holds rows 4*(lane/16)+r, column lane%16 of each 16x16 tile
-    const int g = lane >> 4, q = lane & 15;
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j)
-            for (int r = 0; r < 4; ++r) {
-                const int m = m0 + wm + i * 16 + g * 4 + r;
-                const int n = n0 + wn + j * 16 + q;
-                if (m >= M) continue;
-                const float v = acc[i][j][r];
-                if (epi == EPI_BIAS_RELU_BF16) {
-                    const float z = v + bias[n];
-                    out_bf[(size_t)m * ldo + n] = f2bf(z > 0.f ? z : 0.f);
-                } else if (epi == EPI_MASK_BF16) {
-                    const bool on = mask[(size_t)m * ldm + n] != 0 && !(mask[(size_t)m * ldm + n] & 0x8000);
-                    out_bf[(size_t)m * ldo + n] = f2bf(on ? v : 0.f);
-                } else {
-                    out_f[(size_t)m * ldo + n] = v;
-                }
-            }
-}
-
 // ---- fused forward --------------------------------------------------------
 // One workgroup of four wavefronts takes kFR = 128 rows.  The layer input
 // (X, then H1, H2) sits in LDS; wavefront w computes all 128 rows x columns
@@ -177,7 +93,18 @@ __device__ __forceinline__ void fused_store(uint16_t (*Hs)[kHP], const f32x4 (&a
     }
 }
 
-// STORE: also write H1..H3 (training); the inference form writes only y.
+// A block's 128 rows of Hs out to H (rows below n), 16 bytes per thread
+// per store: whole rows, coalesced.
+__device__ __forceinline__ void copy_rows_out(const uint16_t (*Hs)[kHP], uint16_t *H, int64_t r0, int64_t n) {
+    constexpr int kV = kMlpHidden / 8;
+    for (int i = threadIdx.x; i < kFR * kV; i += kFwdThreads) {
+        const int r = i / kV, c = (i % kV) * 8;
+        if (r0 + r < n) *(uint4 *)(H + (r0 + r) * kMlpHidden + c) = *(const uint4 *)&Hs[r][c];
+    }
+}
+
+// STORE: also write H1..H3 (training), through LDS as whole rows; the
+// inference form writes only y.
 template <bool STORE>
 __global__ __launch_bounds__(kFwdThreads, 2) void mlp_fused_fwd(const uint16_t *__restrict__ X, int64_t n,
                                                              const MlpDev P, float *__restrict__ y, uint16_t *H1,
@@ -199,13 +126,16 @@ __global__ __launch_bounds__(kFwdThreads, 2) void mlp_fused_fwd(const uint16_t *
     f32x4 acc[kMI][4];
     fused_layer<kMlpIn>(Hs, P.w1t, nb, lane, acc);
     __syncthreads();
-    fused_store<STORE>(Hs, acc, P.b1, nb, lane, H1, r0, n);
+    fused_store<false>(Hs, acc, P.b1, nb, lane, nullptr, r0, n);
     __syncthreads();
+    if (STORE) copy_rows_out(Hs, H1, r0, n);
     fused_layer<kMlpHidden>(Hs, P.w2t, nb, lane, acc);
     __syncthreads();
-    fused_store<STORE>(Hs, acc, P.b2, nb, lane, H2, r0, n);
+    fused_store<false>(Hs, acc, P.b2, nb, lane, nullptr, r0, n);
     __syncthreads();
+    if (STORE) copy_rows_out(Hs, H2, r0, n);
     fused_layer<kMlpHidden>(Hs, P.w3t, nb, lane, acc);
+    if (STORE) __syncthreads();  // H3 goes through Hs once every wavefront has read H2
     // output layer: y = bf16(h3) . bf16(w4) + b4
     float rowsum[kMI];
 #pragma unroll
@@ -222,7 +152,7 @@ __global__ __launch_bounds__(kFwdThreads, 2) void mlp_fused_fwd(const uint16_t *
             const int row = i * 16 + q;
             const uint32_t h01 = pack_bf16(fmaxf(acc[i][j][0] + bv.x, 0.f), fmaxf(acc[i][j][1] + bv.y, 0.f));
             const uint32_t h23 = pack_bf16(fmaxf(acc[i][j][2] + bv.z, 0.f), fmaxf(acc[i][j][3] + bv.w, 0.f));
-            if (STORE && r0 + row < n) *(uint2 *)(H3 + (r0 + row) * kMlpHidden + col) = make_uint2(h01, h23);
+            if (STORE) *(uint2 *)&Hs[row][col] = make_uint2(h01, h23);
             float s = rowsum[i];
             s += __uint_as_float(h01 << 16) * w0;
             s += __uint_as_float(h01 & 0xffff0000u) * w1;
@@ -239,7 +169,347 @@ __global__ __launch_bounds__(kFwdThreads, 2) void mlp_fused_fwd(const uint16_t *
         if (g == 0) yp[cw][i * 16 + q] = s;
     }
     __syncthreads();
+    if (STORE) copy_rows_out(Hs, H3, r0, n);
     if (tid < kFR && r0 + tid < n) y[r0 + tid] = (((yp[0][tid] + yp[1][tid]) + yp[2][tid]) + yp[3][tid]) + P.b4[0];
+}
+
+// ---- training step: fused backward, weight gradients, reductions --------
+// Backward of one 128-row block, laid out as the fused forward: dy, then
+// G3 = dy w4 [H3 > 0], G2 = (G3 W3^T) [H2 > 0] and G1 = (G2 W2^T) [H1 > 0]
+// with 16x16x32 BF16 MFMAs (a row of W_l as stored, [in][out], holds an
+// output column's products contiguously), each G rounded to BF16 and written
+// out for the weight gradients; the block's column sums of G1..G3 (bias
+// gradients), of dy H3 (dw4), of dy (db4) and its share of the loss go to
+// its row of `part`, each sum in a fixed order.
+constexpr int kBwdPart = kMlpBwdPart;  // db1, db2, db3, dw4 | db4, loss
+
+__device__ __forceinline__ bool bf_on(uint32_t h) { return (h & 0xffffu) != 0 && !(h & 0x8000u); }
+
+// A block's 128 rows of H (rows below B; zeros past them) into Hs, whole
+// rows, 16 bytes per thread per load.
+__device__ __forceinline__ void copy_rows_in(uint16_t (*Hs)[kHP], const uint16_t *H, int64_t r0, int64_t B) {
+    constexpr int kV = kMlpHidden / 8;
+    for (int i = threadIdx.x; i < kFR * kV; i += kFwdThreads) {
+        const int r = i / kV, c = (i % kV) * 8;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (r0 + r < B) v = *(const uint4 *)(H + (r0 + r) * kMlpHidden + c);
+        *(uint4 *)&Hs[r][c] = v;
+    }
+}
+
+// One layer's G: the accumulators masked where H > 0 and rounded to BF16,
+// H read from Hs (staged there by the caller), G written back into Hs; the
+// block's column sums into colsum[col].  Hs is read, then (after a
+// barrier) rewritten.
+__device__ __forceinline__ void bwd_mask(uint16_t (*Hs)[kHP], const f32x4 (&acc)[kMI][4], int nb, int lane,
+                                         float *colsum) {
+    const int g = lane >> 4, q = lane & 15;
+    uint2 gv[kMI][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = nb + j * 16 + g * 4;
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+#pragma unroll
+        for (int i = 0; i < kMI; ++i) {
+            const uint2 hv = *(const uint2 *)&Hs[i * 16 + q][col];
+            const uint32_t lo = pack_bf16(bf_on(hv.x) ? acc[i][j][0] : 0.f, bf_on(hv.x >> 16) ? acc[i][j][1] : 0.f);
+            const uint32_t hi = pack_bf16(bf_on(hv.y) ? acc[i][j][2] : 0.f, bf_on(hv.y >> 16) ? acc[i][j][3] : 0.f);
+            gv[i][j] = make_uint2(lo, hi);
+            s0 += __uint_as_float(lo << 16);
+            s1 += __uint_as_float(lo & 0xffff0000u);
+            s2 += __uint_as_float(hi << 16);
+            s3 += __uint_as_float(hi & 0xffff0000u);
+        }
+        // the 16 lanes of this column group hold the 128 rows: fixed butterfly
+#pragma unroll
+        for (int d = 1; d < 16; d <<= 1) {
+            s0 += __shfl_xor(s0, d, 64);
+            s1 += __shfl_xor(s1, d, 64);
+            s2 += __shfl_xor(s2, d, 64);
+            s3 += __shfl_xor(s3, d, 64);
+        }
+        if (q == 0) *(float4 *)(colsum + col) = make_float4(s0, s1, s2, s3);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < kMI; ++i) *(uint2 *)&Hs[i * 16 + q][nb + j * 16 + g * 4] = gv[i][j];
+}
+
+__global__ __launch_bounds__(kFwdThreads, 2) void mlp_fused_bwd(const float *__restrict__ y,
+                                                             const float *__restrict__ t, int B,
+                                                             const uint16_t *H1, const uint16_t *H2,
+                                                             const uint16_t *H3, const MlpDev P, uint16_t *G1,
+                                                             uint16_t *G2, uint16_t *G3, float *part) {
+    __shared__ __align__(16) uint16_t Gs[kFR][kHP];
+    __shared__ float dys[kFR];
+    __shared__ float red[8][kMlpHidden];
+    __shared__ float wred[2][2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * kFR;
+    float *pb = part + (size_t)blockIdx.x * kBwdPart;
+    // dy = 2 (y - t) / B; this block's db4 and loss
+    if (tid < kFR) {
+        const int64_t row = r0 + tid;
+        float d = 0.f, l = 0.f;
+        if (row < B) {
+            const float e = y[row] - t[row];
+            d = 2.f * e / (float)B;
+            l = e * e / (float)B;
+        }
+        dys[tid] = d;
+#pragma unroll
+        for (int s = 32; s > 0; s >>= 1) {
+            d += __shfl_xor(d, s, 64);
+            l += __shfl_xor(l, s, 64);
+        }
+        if (lane == 0) {
+            wred[wave][0] = d;
+            wred[wave][1] = l;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        pb[4 * kMlpHidden] = wred[0][0] + wred[1][0];
+        pb[4 * kMlpHidden + 1] = wred[0][1] + wred[1][1];
+    }
+    // G3 = bf16(dy w4) where H3 > 0: thread (row group rg of 16 rows, 8 columns c8)
+    {
+        const int c8 = (tid & 31) * 8, rg = tid >> 5;
+        float w4[8];
+        const uint4 wv = *(const uint4 *)(P.w4b + c8);
+        const uint32_t wvw[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            w4[2 * e] = __uint_as_float(wvw[e] << 16);
+            w4[2 * e + 1] = __uint_as_float(wvw[e] & 0xffff0000u);
+        }
+        float s3[8], s4[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s3[e] = s4[e] = 0.f;
+        for (int rr = 0; rr < 16; ++rr) {
+            const int row = rg * 16 + rr;
+            const int64_t grow = r0 + row;
+            uint4 hv = make_uint4(0u, 0u, 0u, 0u);
+            if (grow < B) hv = *(const uint4 *)(H3 + grow * kMlpHidden + c8);
+            const uint32_t hw[4] = {hv.x, hv.y, hv.z, hv.w};
+            const float d = dys[row];
+            uint32_t gw[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t h0 = hw[e] & 0xffffu, h1 = hw[e] >> 16;
+                gw[e] = pack_bf16(bf_on(h0) ? d * w4[2 * e] : 0.f, bf_on(h1) ? d * w4[2 * e + 1] : 0.f);
+                s3[2 * e] += __uint_as_float(gw[e] << 16);
+                s3[2 * e + 1] += __uint_as_float(gw[e] & 0xffff0000u);
+                s4[2 * e] += __uint_as_float(h0 << 16) * d;
+                s4[2 * e + 1] += __uint_as_float(h1 << 16) * d;
+            }
+            const uint4 gv = make_uint4(gw[0], gw[1], gw[2], gw[3]);
+            *(uint4 *)&Gs[row][c8] = gv;
+            if (grow < B) *(uint4 *)(G3 + grow * kMlpHidden + c8) = gv;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) red[rg][c8 + e] = s3[e];
+        __syncthreads();
+        {
+            float s = 0.f;
+            for (int r = 0; r < 8; ++r) s += red[r][tid];
+            pb[2 * kMlpHidden + tid] = s;  // db3
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 8; ++e) red[rg][c8 + e] = s4[e];
+        __syncthreads();
+        {
+            float s = 0.f;
+            for (int r = 0; r < 8; ++r) s += red[r][tid];
+            pb[3 * kMlpHidden + tid] = s;  // dw4
+        }
+    }
+    const int nb = wave * 64;
+    f32x4 acc[kMI][4];
+    __syncthreads();
+    // G2 = (G3 W3^T) [H2 > 0]
+    fused_layer<kMlpHidden>(Gs, P.w3b, nb, lane, acc);
+    __syncthreads();
+    copy_rows_in(Gs, H2, r0, B);
+    __syncthreads();
+    bwd_mask(Gs, acc, nb, lane, pb + kMlpHidden);
+    __syncthreads();
+    copy_rows_out(Gs, G2, r0, B);
+    // G1 = (G2 W2^T) [H1 > 0]
+    fused_layer<kMlpHidden>(Gs, P.w2b, nb, lane, acc);
+    __syncthreads();
+    copy_rows_in(Gs, H1, r0, B);
+    __syncthreads();
+    bwd_mask(Gs, acc, nb, lane, pb);
+    __syncthreads();
+    copy_rows_out(Gs, G1, r0, B);
+}
+
+// Weight gradients dW_l[M][256] = A_l^T G_l over the batch rows, split into
+// row slices: workgroup (m tile of 64 rows of dW, slice, layer) accumulates
+// its 64 x 256 tile over its slice with 16x16x32 BF16 MFMAs, wavefront w
+// owning columns [64 w, 64 w + 64).  Per step of 32 batch rows the A and G
+// tiles are staged in LDS transposed (k contiguous), two batch rows packed
+// per 32-bit store.  Each slice writes its partial product; the slices are
+// summed in order afterwards.
+struct WgradArgs {
+    const uint16_t *A[3];
+    const uint16_t *G[3];
+    float *out[3];
+    int32_t M[3];
+    int32_t B, kslice, slices;
+};
+constexpr int kWK = 32, kWP = kWK + 8;
+
+// Tiles in a 1-D grid: the four m tiles of a slice of dW3, then of dW2, then
+// dW1's one tile per slice.  Workgroup b runs on XCD b mod 8, each XCD with
+// its own L2; consecutive tiles are dealt to one XCD so the m tiles of a
+// slice read its G rows through one L2.
+__global__ __launch_bounds__(256, 2) void wgrad_bf16(const WgradArgs W) {
+    __shared__ __align__(16) uint16_t As[64][kWP];
+    __shared__ __align__(16) uint16_t Gt[kMlpHidden][kWP];
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    const int x8 = b & 7, base = nb >> 3, extra = nb & 7;
+    const int J = x8 * base + min(x8, extra) + (b >> 3);
+    const int S = W.slices;
+    int layer, slice, mt;
+    if (J < 8 * S) {
+        layer = 2 - J / (4 * S);
+        slice = (J % (4 * S)) >> 2;
+        mt = J & 3;
+    } else {
+        layer = 0;
+        slice = J - 8 * S;
+        mt = 0;
+    }
+    const int M = W.M[layer], m0 = mt * 64;
+    const uint16_t *A = W.A[layer], *G = W.G[layer];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, q = lane & 15;
+    const int kbeg = slice * W.kslice, kend = min(W.B, kbeg + W.kslice);
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // this thread's loads of one step: A (threads below 128: a row pair and a
+    // chunk of 8 columns), G (two units of a row pair and a chunk)
+    const int pa = tid & 15, ca = tid >> 4;
+    uint4 ra[2], rg[2][2];
+    auto load = [&](int k0) {
+        const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+        ra[0] = ra[1] = z;
+        if (tid < 128) {
+            const int r = k0 + 2 * pa;
+            if (r < kend) ra[0] = *(const uint4 *)(A + (size_t)r * M + m0 + ca * 8);
+            if (r + 1 < kend) ra[1] = *(const uint4 *)(A + (size_t)(r + 1) * M + m0 + ca * 8);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int u = tid + 256 * h, r = k0 + 2 * (u & 15), ch = u >> 4;
+            rg[h][0] = rg[h][1] = z;
+            if (r < kend) rg[h][0] = *(const uint4 *)(G + (size_t)r * kMlpHidden + ch * 8);
+            if (r + 1 < kend) rg[h][1] = *(const uint4 *)(G + (size_t)(r + 1) * kMlpHidden + ch * 8);
+        }
+    };
+    // two batch rows of 8 columns into 8 LDS rows (k contiguous), packed
+    auto stash = [](uint16_t (*T)[kWP], int row0, int pr, const uint4 &v0, const uint4 &v1) {
+        const uint32_t a0[4] = {v0.x, v0.y, v0.z, v0.w}, a1[4] = {v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            *(uint32_t *)&T[row0 + 2 * e][2 * pr] = (a0[e] & 0xffffu) | (a1[e] << 16);
+            *(uint32_t *)&T[row0 + 2 * e + 1][2 * pr] = (a0[e] >> 16) | (a1[e] & 0xffff0000u);
+        }
+    };
+    if (kbeg < kend) load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += kWK) {
+        if (tid < 128) stash(As, ca * 8, pa, ra[0], ra[1]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int u = tid + 256 * h;
+            stash(Gt, (u >> 4) * 8, u & 15, rg[h][0], rg[h][1]);
+        }
+        __syncthreads();
+        if (k0 + kWK < kend) load(k0 + kWK);  // the next step's loads fly during this step's products
+        bf16x8 a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8 *)&As[i * 16 + q][g * 8];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = *(const bf16x8 *)&Gt[wave * 64 + j * 16 + q][g * 8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // D: lane holds rows 4 g + r of each 16 x 16 tile, column q
+    float *out = W.out[layer] + (size_t)slice * M * kMlpHidden;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                out[(size_t)(m0 + i * 16 + g * 4 + r) * kMlpHidden + wave * 64 + j * 16 + q] = acc[i][j][r];
+}
+
+// The gradient vector from the partials, each sum in a fixed order.
+// Weight matrices: element by element over the row slices, in slice order.
+__global__ void reduce_wgrads(const float *__restrict__ wpart0, const float *__restrict__ wpart1,
+                              const float *__restrict__ wpart2, int slices, float *__restrict__ grads) {
+    constexpr int64_t n0 = (int64_t)kMlpIn * kMlpHidden, n1 = (int64_t)kMlpHidden * kMlpHidden;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n0 + 2 * n1) return;
+    const float *wp;
+    int64_t o, n, dst;
+    if (i < n0) {
+        wp = wpart0, o = i, n = n0, dst = kOffW1 + i;
+    } else if (i < n0 + n1) {
+        wp = wpart1, o = i - n0, n = n1, dst = kOffW2 + o;
+    } else {
+        wp = wpart2, o = i - n0 - n1, n = n1, dst = kOffW3 + o;
+    }
+    // loads issued eight slices ahead; the sum stays in slice order
+    float s = 0.f;
+    int z = 0;
+    for (; z + 8 <= slices; z += 8) {
+        float t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = wp[(size_t)(z + u) * n + o];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += t[u];
+    }
+    for (; z < slices; ++z) s += wp[(size_t)z * n + o];
+    grads[dst] = s;
+}
+
+// Biases, w4, b4 and the loss over the blocks' partial rows: workgroup x
+// takes 16 entries of a row, its 64 segments of consecutive blocks are
+// summed in block order, then the segment sums in segment order.
+constexpr int kRedSeg = 64, kRedCols = 16;
+__global__ __launch_bounds__(kRedCols * kRedSeg) void reduce_bias(const float *__restrict__ bpart, int blocks,
+                                                                   float *__restrict__ grads, float *loss) {
+    __shared__ float seg[kRedSeg][kRedCols];
+    const int c = threadIdx.x % kRedCols, sg = threadIdx.x / kRedCols;
+    const int e = blockIdx.x * kRedCols + c;  // entry of a partial row
+    const int per = (blocks + kRedSeg - 1) / kRedSeg;
+    float s = 0.f;
+    if (e < 4 * kMlpHidden + 2)
+        for (int b = sg * per; b < min(blocks, (sg + 1) * per); ++b) s += bpart[(size_t)b * kBwdPart + e];
+    seg[sg][c] = s;
+    __syncthreads();
+    if (sg == 0 && e < 4 * kMlpHidden + 2) {
+        float t = 0.f;
+        for (int k = 0; k < kRedSeg; ++k) t += seg[k][c];
+        if (e < kMlpHidden) grads[kOffB1 + e] = t;
+        else if (e < 2 * kMlpHidden) grads[kOffB2 + e - kMlpHidden] = t;
+        else if (e < 3 * kMlpHidden) grads[kOffB3 + e - 2 * kMlpHidden] = t;
+        else if (e < 4 * kMlpHidden) grads[kOffW4 + e - 3 * kMlpHidden] = t;
+        else if (e == 4 * kMlpHidden) grads[kOffB4] = t;
+        else if (loss) *loss = t;
+    }
 }
 
 // W1..W3 transposed to [out][in] (BF16), for the fused forward
@@ -262,66 +532,29 @@ __global__ void transpose_weights(const uint16_t *__restrict__ pb, uint16_t *__r
     pt[i] = pb[base + k * kMlpHidden + col];
 }
 
-// dy = 2 (y - t) / B; per-block partial losses
-__global__ void loss_grad(const float *y, const float *t, int B, float *dy, float *loss_part) {
-    __shared__ float part[4];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    float l = 0.f;
-    if (i < B) {
-        const float e = y[i] - t[i];
-        dy[i] = 2.f * e / (float)B;
-        l = e * e / (float)B;
+// Place of packed parameter i (an element of W1..W3) in the transposed
+// BF16 weights ([out][in]), or -1 for the other parameters.
+__device__ __forceinline__ int64_t transposed_at(int64_t i) {
+    constexpr int64_t n1 = (int64_t)kMlpIn * kMlpHidden, n2 = (int64_t)kMlpHidden * kMlpHidden;
+    int64_t o, base;
+    int K;
+    if (i >= kOffW1 && i < kOffB1) {
+        o = i - kOffW1, base = 0, K = kMlpIn;
+    } else if (i >= kOffW2 && i < kOffB2) {
+        o = i - kOffW2, base = n1, K = kMlpHidden;
+    } else if (i >= kOffW3 && i < kOffB3) {
+        o = i - kOffW3, base = n1 + n2, K = kMlpHidden;
+    } else {
+        return -1;
     }
-    for (int d = 32; d > 0; d >>= 1) l += __shfl_xor(l, d, 64);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = l;
-    __syncthreads();
-    if (threadIdx.x == 0) loss_part[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+    const int64_t k = o / kMlpHidden, col = o % kMlpHidden;  // W[k][col]
+    return base + col * K + k;
 }
 
-// G3[b][j] = dy[b] w4[j] [H3[b][j] > 0]  (bf16)
-__global__ void out_layer_back(const float *dy, const uint16_t *w4, const uint16_t *H, int B, uint16_t *G) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)B * kMlpHidden) return;
-    const int64_t b = i / kMlpHidden;
-    const int j = (int)(i % kMlpHidden);
-    const uint16_t h = H[i];
-    const bool on = h != 0 && !(h & 0x8000);
-    G[i] = f2bf(on ? dy[b] * bf2f(w4[j]) : 0.f);
-}
-
-// Partial weighted column sums over kMlpColRows-row slices:
-// part[slice][j] = sum_b v(b, j) w(b), v = bf16 M[b][j] (1 without M),
-// w = w[b] (1 without w); 64 columns x 4 row groups per block, fixed order.
-__global__ __launch_bounds__(256) void wcolsum_part(const uint16_t *__restrict__ Mx, const float *__restrict__ w,
-                                                    int B, int N, float *__restrict__ part) {
-    __shared__ float red[4][64];
-    const int tid = threadIdx.x, l = tid & 63, rg = tid >> 6;
-    const int c = blockIdx.x * 64 + l;
-    const int b0 = blockIdx.y * kMlpColRows, b1 = min(B, b0 + kMlpColRows);
-    float s = 0.f;
-    if (c < N)
-        for (int b = b0 + rg; b < b1; b += 4) {
-            float v = Mx ? bf2f(Mx[(size_t)b * N + c]) : 1.f;
-            if (w) v *= w[b];
-            s += v;
-        }
-    red[rg][l] = s;
-    __syncthreads();
-    if (rg == 0 && c < N) part[(size_t)blockIdx.y * N + c] = ((red[0][l] + red[1][l]) + red[2][l]) + red[3][l];
-}
-
-// out[i] = sum over slices z of part[z n + i], in slice order
-__global__ void sum_slices(const float *__restrict__ part, int S, int64_t n, float *__restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float s = 0.f;
-    for (int z = 0; z < S; ++z) s += part[(size_t)z * n + i];
-    out[i] = s;
-}
-
-// Adam on FP32 master weights; refresh the BF16 copy of weight matrices
+// Adam on FP32 master weights; the BF16 copy and its transpose refreshed in
+// the same pass
 __global__ void adam_step(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
-                          float eps, float c1, float c2, const int64_t *bf_ranges, uint16_t *pbf) {
+                          float eps, float c1, float c2, uint16_t *pbf, uint16_t *pt) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float gi = g[i];
@@ -332,7 +565,10 @@ __global__ void adam_step(float *p, const float *g, float *m, float *v, int64_t 
     const float upd = lr * (mi / c1) / (sqrtf(vi / c2) + eps);
     const float np = p[i] - upd;
     p[i] = np;
-    pbf[i] = f2bf(np);
+    const uint16_t b = f2bf(np);
+    pbf[i] = b;
+    const int64_t ti = transposed_at(i);
+    if (ti >= 0) pt[ti] = b;
 }
 
 __global__ void to_bf16(const float *src, int64_t n, uint16_t *dst) {
@@ -443,48 +679,6 @@ inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
 
-hipError_t mlp_gemm(int M, int N, int K, const uint16_t *A, int lda, int a_t, const uint16_t *B, int ldb, int b_t,
-                    int epi, const float *bias, const uint16_t *mask, int ldm, uint16_t *out_bf, float *out_f, int ldo,
-                    hipStream_t s, int slices) {
-    if (M <= 0) return hipSuccess;
-    if (slices < 1 || epi != EPI_F32) slices = 1;
-    const int kslice = ((K + slices - 1) / slices + TK - 1) / TK * TK;
-    slices = (K + kslice - 1) / kslice;
-    dim3 grid(N / TN, (M + TM - 1) / TM, slices);
-    hipLaunchKernelGGL(gemm_bf16, grid, dim3(256), 0, s, M, N, K, A, lda, a_t, B, ldb, b_t, epi, bias, mask, ldm,
-                       out_bf, out_f, ldo, kslice);
-    return hipGetLastError();
-}
-
-namespace {
-
-// dW[M x 256] = A^T G over B rows (A [B][M], G [B][256]), split over K
-// into slices summed in a fixed order.
-hipError_t weight_grad(int M, int B, const uint16_t *A, const uint16_t *G, float *out, float *part, hipStream_t s) {
-    const int slices = std::max(1, std::min(kMlpMaxSlices, B / 512));
-    if (slices == 1)
-        return mlp_gemm(M, kMlpHidden, B, A, M, 1, G, kMlpHidden, 0, EPI_F32, nullptr, nullptr, 0, nullptr, out,
-                        kMlpHidden, s, 1);
-    hipError_t e = mlp_gemm(M, kMlpHidden, B, A, M, 1, G, kMlpHidden, 0, EPI_F32, nullptr, nullptr, 0, nullptr, part,
-                            kMlpHidden, s, slices);
-    if (e != hipSuccess) return e;
-    const int kslice = ((B + slices - 1) / slices + TK - 1) / TK * TK;
-    const int used = (B + kslice - 1) / kslice;
-    const int64_t n = (int64_t)M * kMlpHidden;
-    hipLaunchKernelGGL(sum_slices, dim3(blocks_for(n, 256)), dim3(256), 0, s, part, used, n, out);
-    return hipGetLastError();
-}
-
-// out[j] = sum_b v(b, j) w(b) (see wcolsum_part), two passes, fixed order
-hipError_t col_sum(const uint16_t *Mx, const float *w, int B, int N, float *out, float *part, hipStream_t s) {
-    const int S = (B + kMlpColRows - 1) / kMlpColRows;
-    hipLaunchKernelGGL(wcolsum_part, dim3((N + 63) / 64, S), dim3(256), 0, s, Mx, w, B, N, part);
-    hipLaunchKernelGGL(sum_slices, dim3(blocks_for(N, 256)), dim3(256), 0, s, part, S, (int64_t)N, out);
-    return hipGetLastError();
-}
-
-}  // namespace
-
 // Forward pass of n rows: the fused kernel, 128 rows per workgroup.
 hipError_t mlp_forward(const MlpDev &P, const uint16_t *X, int64_t n, uint16_t *H1, uint16_t *H2, uint16_t *H3,
                        float *y, hipStream_t s) {
@@ -500,42 +694,48 @@ hipError_t mlp_forward(const MlpDev &P, const uint16_t *X, int64_t n, uint16_t *
     return hipGetLastError();
 }
 
-// Gradients of the mean squared error for one batch (B a multiple of 64).
+// Gradients of the mean squared error for one batch (B a multiple of 64):
+// the fused forward storing H1..H3, the fused backward (G1..G3 and the
+// per-block column sums), the split-K weight gradients of all three layers
+// in one launch, and one pass summing every partial in a fixed order; the
+// loss (when wanted) with it.
 hipError_t mlp_backward(const MlpDev &P, const uint16_t *X, const float *t, int B, MlpScratch &S, float *grads,
-                        hipStream_t s) {
-    const int H = kMlpHidden;
+                        float *loss, hipStream_t s) {
     hipError_t e = mlp_forward(P, X, B, S.h1, S.h2, S.h3, S.y, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(loss_grad, dim3(blocks_for(B, 256)), dim3(256), 0, s, S.y, t, B, S.dy, S.loss_part);
-    float *gw1 = grads + kOffW1, *gb1 = grads + kOffB1, *gw2 = grads + kOffW2, *gb2 = grads + kOffB2;
-    float *gw3 = grads + kOffW3, *gb3 = grads + kOffB3, *gw4 = grads + kOffW4, *gb4 = grads + kOffB4;
-    float *part = S.part, *cpart = S.part + (int64_t)kMlpMaxSlices * H * H;
-    hipLaunchKernelGGL(out_layer_back, dim3(blocks_for((int64_t)B * H, 256)), dim3(256), 0, s, S.dy, P.w4b, S.h3, B,
-                       S.g3);
-    // output layer: dw4 = H3^T dy, db4 = sum dy
-    if ((e = col_sum(S.h3, S.dy, B, H, gw4, cpart, s)) != hipSuccess) return e;
-    if ((e = col_sum(nullptr, S.dy, B, 1, gb4, cpart, s)) != hipSuccess) return e;
-    // layer 3: dW3 = H2^T G3, db3 = colsum G3, G2 = (G3 W3^T) [H2 > 0]
-    if ((e = weight_grad(H, B, S.h2, S.g3, gw3, part, s)) != hipSuccess) return e;
-    if ((e = col_sum(S.g3, nullptr, B, H, gb3, cpart, s)) != hipSuccess) return e;
-    e = mlp_gemm(B, H, H, S.g3, H, 0, P.w3b, H, 1, EPI_MASK_BF16, nullptr, S.h2, H, S.g2, nullptr, H, s, 1);
-    if (e != hipSuccess) return e;
-    // layer 2
-    if ((e = weight_grad(H, B, S.h1, S.g2, gw2, part, s)) != hipSuccess) return e;
-    if ((e = col_sum(S.g2, nullptr, B, H, gb2, cpart, s)) != hipSuccess) return e;
-    e = mlp_gemm(B, H, H, S.g2, H, 0, P.w2b, H, 1, EPI_MASK_BF16, nullptr, S.h1, H, S.g1, nullptr, H, s, 1);
-    if (e != hipSuccess) return e;
-    // layer 1
-    if ((e = weight_grad(kMlpIn, B, X, S.g1, gw1, part, s)) != hipSuccess) return e;
-    return col_sum(S.g1, nullptr, B, H, gb1, cpart, s);
+    const int blocks = (B + kFR - 1) / kFR;
+    float *wpart0 = S.part;
+    int slices = std::max(1, std::min(kMlpMaxSlices, B / 1024));
+    const int kslice = ((B + slices - 1) / slices + kWK - 1) / kWK * kWK;
+    slices = (B + kslice - 1) / kslice;
+    float *wpart1 = wpart0 + (size_t)slices * kMlpIn * kMlpHidden;
+    float *wpart2 = wpart1 + (size_t)slices * kMlpHidden * kMlpHidden;
+    float *bpart = wpart2 + (size_t)slices * kMlpHidden * kMlpHidden;
+    hipLaunchKernelGGL(mlp_fused_bwd, dim3(blocks), dim3(kFwdThreads), 0, s, S.y, t, B, S.h1, S.h2, S.h3, P, S.g1,
+                       S.g2, S.g3, bpart);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    WgradArgs W;
+    W.A[0] = X, W.A[1] = S.h1, W.A[2] = S.h2;
+    W.G[0] = S.g1, W.G[1] = S.g2, W.G[2] = S.g3;
+    W.out[0] = wpart0, W.out[1] = wpart1, W.out[2] = wpart2;
+    W.M[0] = kMlpIn, W.M[1] = kMlpHidden, W.M[2] = kMlpHidden;
+    W.B = B;
+    W.kslice = kslice;
+    W.slices = slices;
+    hipLaunchKernelGGL(wgrad_bf16, dim3(9 * slices), dim3(256), 0, s, W);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_wgrads, dim3(blocks_for((int64_t)(kMlpIn + 2 * kMlpHidden) * kMlpHidden, 256)),
+                       dim3(256), 0, s, wpart0, wpart1, wpart2, slices, grads);
+    hipLaunchKernelGGL(reduce_bias, dim3((4 * kMlpHidden + 2 + kRedCols - 1) / kRedCols), dim3(kRedCols * kRedSeg), 0,
+                       s, bpart, blocks, grads, loss);
+    return hipGetLastError();
 }
 
 hipError_t mlp_adam(MlpDev &P, const float *grads, float lr, int step, hipStream_t s) {
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
     hipLaunchKernelGGL(adam_step, dim3(blocks_for(kMlpParams, 256)), dim3(256), 0, s, P.p, grads, P.m, P.v,
-                       (int64_t)kMlpParams, lr, b1, b2, eps, c1, c2, nullptr, P.pb);
-    hipLaunchKernelGGL(transpose_weights, dim3(blocks_for(kMlpWtElems, 256)), dim3(256), 0, s, P.pb, P.pt);
+                       (int64_t)kMlpParams, lr, b1, b2, eps, c1, c2, P.pb, P.pt);
     return hipGetLastError();
 }
 
@@ -564,19 +764,6 @@ hipError_t launch_features(const FeatArgs *a, int count, hipStream_t s) {
     }
     return hipSuccess;
 }
-
-}  // namespace hdx
-
-namespace hdx {
-namespace {
-__global__ void sum_parts(const float *part, int n, float *out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        float s = 0.f;
-        for (int i = 0; i < n; ++i) s += part[i];
-        out[0] = s;
-    }
-}
-}  // namespace
 
 namespace {
 // Surrogate lower bounds of the children of pack entry blockIdx.z: for
@@ -634,8 +821,4 @@ hipError_t launch_surrogate_reduce(const SurArgs *a, int count, hipStream_t s) {
     return hipSuccess;
 }
 
-hipError_t mlp_sum_loss(const float *part, int n, float *out, hipStream_t s) {
-    hipLaunchKernelGGL(sum_parts, dim3(1), dim3(64), 0, s, part, n, out);
-    return hipGetLastError();
-}
 }  // namespace hdx

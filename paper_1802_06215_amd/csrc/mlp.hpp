@@ -21,11 +21,13 @@ constexpr int64_t kMlpParams = kOffB4 + 1;
 static_assert(kMlpParams == HDX_MLP_PARAMS, "parameter count");
 
 constexpr int64_t kMlpWtElems = (int64_t)kMlpHidden * kMlpIn + 2 * (int64_t)kMlpHidden * kMlpHidden;
-// split-K partial sums of the weight gradients: at most kMlpMaxSlices slices
-constexpr int kMlpMaxSlices = 32;
-constexpr int kMlpColRows = 256;  // rows per partial of a column sum
+// partials of one training step: the weight gradients of the three layers
+// over at most kMlpMaxSlices row slices, then the backward's per-block
+// column sums (kMlpBwdPart floats per 128-row block)
+constexpr int kMlpMaxSlices = 64;
+constexpr int kMlpBwdPart = 4 * kMlpHidden + 8;
 constexpr int64_t kMlpPartFloats =
-    (int64_t)kMlpMaxSlices * kMlpHidden * kMlpHidden + (kMlpChunkRows / kMlpColRows) * (int64_t)(kMlpHidden + 1);
+    (int64_t)kMlpMaxSlices * (kMlpIn + 2 * kMlpHidden) * kMlpHidden + (kMlpChunkRows / 128) * (int64_t)kMlpBwdPart;
 
 struct MlpDev {
     float *p;      // FP32 master parameters
@@ -41,7 +43,7 @@ struct MlpDev {
 struct MlpScratch {
     int64_t rows = 0;
     uint16_t *h1 = nullptr, *h2 = nullptr, *h3 = nullptr, *g1 = nullptr, *g2 = nullptr, *g3 = nullptr;
-    float *y = nullptr, *dy = nullptr, *loss_part = nullptr;
+    float *y = nullptr;
     float *part = nullptr;  // kMlpPartFloats
 };
 
@@ -54,15 +56,12 @@ struct FeatArgs {
     uint16_t *X;
 };
 
-hipError_t mlp_gemm(int M, int N, int K, const uint16_t *A, int lda, int a_t, const uint16_t *B, int ldb, int b_t,
-                    int epi, const float *bias, const uint16_t *mask, int ldm, uint16_t *out_bf, float *out_f, int ldo,
-                    hipStream_t s, int slices);
 // y = MLP(X) for n rows; H1..H3 (row stride 256) receive the activations
 // when non-NULL (then they hold n rows).
 hipError_t mlp_forward(const MlpDev &P, const uint16_t *X, int64_t n, uint16_t *H1, uint16_t *H2, uint16_t *H3,
                        float *y, hipStream_t s);
 hipError_t mlp_backward(const MlpDev &P, const uint16_t *X, const float *t, int B, MlpScratch &S, float *grads,
-                        hipStream_t s);
+                        float *loss, hipStream_t s);
 hipError_t mlp_adam(MlpDev &P, const float *grads, float lr, int step, hipStream_t s);
 hipError_t mlp_refresh_bf16(MlpDev &P, hipStream_t s);
 // Features of several state arrays, kFeatPack per launch (kernel arguments,
@@ -73,7 +72,6 @@ struct FeatPack {
 };
 static_assert(sizeof(FeatPack) <= 1024, "kernel argument pack too large");
 hipError_t launch_features(const FeatArgs *a, int count, hipStream_t s);
-hipError_t mlp_sum_loss(const float *part, int n, float *out, hipStream_t s);
 
 struct SurArgs {
     const float *values;  // [A][n] surrogate value per (action, scenario)

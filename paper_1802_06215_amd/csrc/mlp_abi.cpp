@@ -48,14 +48,13 @@ void init_params(uint32_t seed, std::vector<float> &p) {
 bool grow_scratch(MlpScratch &S, int64_t rows) {
     if (S.rows >= rows) return true;
     for (void *ptr : {(void *)S.h1, (void *)S.h2, (void *)S.h3, (void *)S.g1, (void *)S.g2, (void *)S.g3,
-                      (void *)S.y, (void *)S.dy, (void *)S.loss_part, (void *)S.part})
+                      (void *)S.y, (void *)S.part})
         if (ptr) hipFree(ptr);
     S = MlpScratch();
     const size_t hb = (size_t)rows * kMlpHidden * sizeof(uint16_t);
     if (hipMalloc(&S.h1, hb) != hipSuccess || hipMalloc(&S.h2, hb) != hipSuccess || hipMalloc(&S.h3, hb) != hipSuccess ||
         hipMalloc(&S.g1, hb) != hipSuccess || hipMalloc(&S.g2, hb) != hipSuccess || hipMalloc(&S.g3, hb) != hipSuccess ||
-        hipMalloc(&S.y, rows * sizeof(float)) != hipSuccess || hipMalloc(&S.dy, rows * sizeof(float)) != hipSuccess ||
-        hipMalloc(&S.loss_part, ((rows + 255) / 256) * sizeof(float)) != hipSuccess ||
+        hipMalloc(&S.y, rows * sizeof(float)) != hipSuccess ||
         hipMalloc(&S.part, kMlpPartFloats * sizeof(float)) != hipSuccess)
         return false;
     S.rows = rows;
@@ -143,7 +142,7 @@ hdx_status hdx_mlp_destroy(hdx_ctx *ctx, hdx_mlp *m) {
         if (ptr) hipFree(ptr);
     if (m->last) hipEventDestroy(m->last);
     for (void *ptr : {(void *)m->S.h1, (void *)m->S.h2, (void *)m->S.h3, (void *)m->S.g1, (void *)m->S.g2,
-                      (void *)m->S.g3, (void *)m->S.y, (void *)m->S.dy, (void *)m->S.loss_part, (void *)m->S.part})
+                      (void *)m->S.g3, (void *)m->S.y, (void *)m->S.part})
         if (ptr) hipFree(ptr);
     delete m;
     return HDX_OK;
@@ -230,9 +229,7 @@ hdx_status hdx_mlp_gradients(hdx_ctx *ctx, hdx_mlp *m, const uint16_t *X, const 
     if (!grow_scratch(m->S, batch)) return HDX_E_NOMEM;
     hipStream_t s = (hipStream_t)stream;
     Ordered o(m, s);
-    if (mlp_backward(m->P, X, t, batch, m->S, grads, s) != hipSuccess) return HDX_E_DEVICE;
-    if (loss && mlp_sum_loss(m->S.loss_part, (batch + 255) / 256, loss, s) != hipSuccess) return HDX_E_DEVICE;
-    return HDX_OK;
+    return mlp_backward(m->P, X, t, batch, m->S, grads, loss, s) == hipSuccess ? HDX_OK : HDX_E_DEVICE;
 }
 
 hdx_status hdx_mlp_train_step(hdx_ctx *ctx, hdx_mlp *m, const uint16_t *X, const float *t, int32_t batch, float lr,
@@ -243,8 +240,7 @@ hdx_status hdx_mlp_train_step(hdx_ctx *ctx, hdx_mlp *m, const uint16_t *X, const
     if (!grow_scratch(m->S, batch)) return HDX_E_NOMEM;
     hipStream_t s = (hipStream_t)stream;
     Ordered o(m, s);
-    if (mlp_backward(m->P, X, t, batch, m->S, m->grads, s) != hipSuccess) return HDX_E_DEVICE;
-    if (loss && mlp_sum_loss(m->S.loss_part, (batch + 255) / 256, loss, s) != hipSuccess) return HDX_E_DEVICE;
+    if (mlp_backward(m->P, X, t, batch, m->S, m->grads, loss, s) != hipSuccess) return HDX_E_DEVICE;
     m->step += 1;
     return mlp_adam(m->P, m->grads, lr, m->step, s) == hipSuccess ? HDX_OK : HDX_E_DEVICE;
 }
