@@ -636,66 +636,28 @@ def cpu_baseline(items, seconds):
                 rates=[round(r, 1) for r in rates])
 
 
-def despot_analogue(desc, seconds, K=500, seed=3, max_depth=90, xi=0.95):
-    """The paper's DESPOT baseline as it stands here: one host thread, trials
-    by Eq. 5 (the action of largest upper bound) and Eq. 7 (the child of
-    largest weighted excess uncertainty), every expansion and Eq. 4 backup
-    done by the oracle (FP64 values), default move-east rollouts.  Returns
-    the tree size it builds within `seconds` (the paper's speedup metric
-    counts tree size within the planning time)."""
+def despot_analogue(desc, seconds, K=500, seed=3, max_depth=90, xi=0.95, repeats=5):
+    """The paper's DESPOT baseline as it stands here: the oracle's one-thread
+    C trial loop (Eq. 5 and 7 to descend, the oracle's leaf expansion with
+    FP64 values, Eq. 4 back up), default rollouts.  The paper's speedup
+    metric counts tree size within the planning time: the median tree size
+    of `repeats` runs of `seconds` each is reported."""
     import numpy as np
 
     import oracle
     import workloads as W
 
     rc = oracle.cfg(0, 50, max_depth) if desc["kind"] == 1 else oracle.cfg(0, 1 << 30, max_depth)
-    gamma = desc["gamma"]
     belief = (W.mars_belief(desc) if desc["kind"] == 2 else W.nav_belief(desc) if desc["kind"] == 3
               else W.pednav_belief(desc) if desc["kind"] == 1 else W.rocksample_belief(desc))
-    root_states = oracle.sample_scenarios(desc, belief, K, seed, 0)
-    ids = np.arange(K, dtype=np.uint32)
-    U, L, _ = oracle.rollout_bounds(desc, rc, root_states, ids, np.zeros(K, np.int32), seed, 0)
-    root = oracle.Node(None, K, U.mean(), L.mean())
-    pending = {id(root): (root_states, ids, np.arange(K, dtype=np.int32), 0, -1)}
-    nodes, trials, expansions, steps = 1, 0, 0, 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        gap0 = root.u - root.l
-        if gap0 <= 0.0:
-            break
-        b, depth = root, 0
-        while b is not None and b.actions is not None:
-            best_a, best_v = 0, -np.inf
-            for a, (r, kids) in enumerate(b.actions):
-                v = r + gamma * sum(k.n / b.n * k.u for k in kids)
-                if v > best_v:
-                    best_a, best_v = a, v
-            best, best_e = None, -np.inf
-            for k in b.actions[best_a][1]:
-                e = (k.u - k.l) - k.n / K * xi * gap0
-                if e > best_e:
-                    best, best_e = k, e
-            b = best if best is not None and best_e > 0.0 else None
-            depth += 1
-        trials += 1
-        if b is None:  # no positive excess uncertainty below the root: one thread stays here
-            break
-        if depth >= max_depth or b.n == 0:
-            continue
-        par, pids, idx, d, la = pending.pop(id(b))
-        res = oracle.expand_leaf(desc, rc, par, pids, idx, d, la, seed, 0)
-        expansions += 1
-        steps += int(res["expand_steps"]) + int(res["rollout_steps"])
-        oracle.attach_children(desc, b, res)
-        for a, (_, kids) in enumerate(b.actions):
-            for c, k in enumerate(kids):
-                off, cnt = int(res["child_off"][a, c]), int(res["child_n"][a, c])
-                pending[id(k)] = (res["states"], res["ids"], res["perm"][a, off:off + cnt], d + 1, a)
-                nodes += 1
-        oracle.backup(b, gamma)
-    dt = time.perf_counter() - t0
-    return dict(nodes=nodes, trials=trials, expansions=expansions, elapsed_s=round(dt, 3),
-                scenario_steps_per_s=round(steps / dt, 1), l_root=round(root.l, 5), u_root=round(root.u, 5))
+    root = oracle.sample_scenarios(desc, belief, K, seed, 0)
+    runs = [oracle.despot(desc, rc, root, K, seed, 0, max_depth, xi, seconds) for _ in range(repeats)]
+    med = sorted(runs, key=lambda r: r["nodes"])[len(runs) // 2]
+    return dict(nodes=med["nodes"], trials=med["trials"], expansions=med["expansions"],
+                elapsed_s=round(med["elapsed_s"], 3),
+                scenario_steps_per_s=round(med["scenario_steps"] / med["elapsed_s"], 1),
+                l_root=round(med["l_root"], 5), u_root=round(med["u_root"], 5), runs=repeats,
+                nodes_per_run=[r["nodes"] for r in runs])
 
 
 def search_config(desc, seconds):

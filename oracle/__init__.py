@@ -102,6 +102,9 @@ def lib():
         L.or_rs_sense_threshold.restype = C.c_uint64
         L.or_mix64.argtypes = [C.c_uint64]
         L.or_mix64.restype = C.c_uint64
+        L.or_despot.argtypes = [P, P, C.c_uint32, C.c_uint32, P, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                C.c_int64, P]
+        L.or_despot.restype = C.c_int
         _lib = L
     return _lib
 
@@ -402,6 +405,27 @@ def expand_leaf(desc, rcfg, parent, parent_ids, idx, depth, last_action, seed, s
             for f in ("px", "py", "goal"):
                 sp[f] = sp[f].reshape(P, A, n)
     return res
+
+
+class _DespotResult(C.Structure):
+    _fields_ = [("nodes", C.c_int64), ("trials", C.c_int64), ("expansions", C.c_int64),
+                ("scenario_steps", C.c_int64), ("u_root", C.c_double), ("l_root", C.c_double),
+                ("elapsed_s", C.c_double), ("max_depth_reached", C.c_int32), ("near_ties", C.c_int32)]
+
+
+def despot(desc, rcfg, root_states, K, seed, step_idx, max_depth, xi=0.95, seconds=1.0, max_trials=0) -> dict:
+    """One planning step of the plain DESPOT trial loop on one host thread
+    (Sec. III-A; Eq. 5 and 7 to descend, the oracle's expansion, Eq. 4 back
+    up) from the root scenarios `root_states` (ids 0..K-1)."""
+    n = _check_states(desc, root_states)
+    assert n == K
+    res = _DespotResult()
+    M = model(desc)
+    rc = lib().or_despot(C.byref(M), C.byref(rcfg), seed, step_idx, C.byref(_soa(desc, root_states, K)), K,
+                         max_depth, xi, seconds, max_trials, C.byref(res))
+    if rc != 0:
+        raise MemoryError("or_despot ran out of memory")
+    return {f: getattr(res, f) for f, _ in _DespotResult._fields_}
 
 
 def rs_sense_threshold(d2: int) -> int:

@@ -22,10 +22,12 @@
  * model definitions, bound heuristics, child order) follow the project's
  * model specification; each is named where it is used.
  */
+#define _POSIX_C_SOURCE 200809L
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10: Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as   */
@@ -939,3 +941,314 @@ uint64_t or_mix64(uint64_t x) { return mix64(x); }
 
 /* Sensor threshold table, exposed so the tests can check the accuracy law. */
 uint64_t or_rs_sense_threshold(int32_t d2) { return rs_sense_threshold(d2); }
+
+/* ------------------------------------------------------------------------ */
+/* The DESPOT trial loop on one host thread (Sec. III-A), the baseline the  */
+/* paper's speedups are quoted against, built on the expansion above: each   */
+/* trial descends from the root taking the action of largest upper bound    */
+/* (Eq. 5) and the observation child of largest weighted excess uncertainty */
+/* E = (u - l) - (|Phi_c| / K) xi (u(b0) - l(b0)) (Eq. 6, 7), stops where E  */
+/* is not positive, expands the leaf it reaches above the depth limit and   */
+/* backs the path up (Eq. 4).  Ties go to the lowest action index and the   */
+/* first child in observation order.  Values FP64.                          */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t parent, action, n, depth;
+    double u, l;
+    int32_t src;           /* record whose states and ids this node's positions index */
+    const int32_t *pos;    /* [n] positions in that record */
+    int32_t act_begin;     /* first action branch; -1 until expanded */
+} dn_node;
+
+typedef struct {
+    double r;
+    int32_t child_begin, n_children;
+} dn_act;
+
+typedef struct {
+    or_soa states;
+    uint32_t *ids;
+    int32_t *perm; /* [A][n] */
+    void *buf;     /* the record's one allocation */
+} dn_rec;
+
+typedef struct {
+    int64_t nodes, trials, expansions, scenario_steps;
+    double u_root, l_root, elapsed_s;
+    int32_t max_depth_reached;
+    int32_t near_ties; /* choices whose runner-up was within 1e-6 (relative) but not equal */
+} or_despot_result;
+
+/* a choice decided by less than FP32 resolution of the values compared */
+static int dn_near(double best, double second)
+{
+    if (!(second > -INFINITY) || best == second) return 0;
+    return best - second <= 1e-6 * fmax(fabs(best), 1.0);
+}
+
+static double dn_now(void)
+{
+    struct timespec t;
+    clock_gettime(CLOCK_MONOTONIC, &t);
+    return (double)t.tv_sec + 1e-9 * (double)t.tv_nsec;
+}
+
+/* A record of n scenarios: states in the library's layout, ids, grouped order. */
+static int dn_rec_alloc(const or_model *M, int32_t n, dn_rec *r)
+{
+    const int64_t A = M->n_actions, nn = n > 0 ? n : 1;
+    int64_t words = 0, fl = 0, bytes8 = 0;
+    if (M->kind == 0) words = nn;
+    else if (M->kind == 2) words = 2 * nn;
+    else if (M->kind == 3) words = 5 * nn;
+    else {
+        words = nn;                      /* car */
+        fl = nn * (1 + 2 * M->n_peds);   /* s, px, py */
+        bytes8 = nn * M->n_peds;         /* goal */
+    }
+    size_t total = sizeof(int32_t) * (size_t)(words + nn + A * nn) + sizeof(float) * (size_t)fl + (size_t)bytes8 + 64;
+    char *b = (char *)calloc(1, total);
+    if (!b) return -1;
+    memset(r, 0, sizeof(*r));
+    r->buf = b;
+    int32_t *wp = (int32_t *)b;
+    r->ids = (uint32_t *)(wp + words);
+    r->perm = (int32_t *)(r->ids + nn);
+    float *fp = (float *)(r->perm + A * nn);
+    if (M->kind == 1) {
+        r->states.car = wp;
+        r->states.s = fp;
+        r->states.px = fp + nn;
+        r->states.py = fp + nn + nn * M->n_peds;
+        r->states.goal = (uint8_t *)(fp + fl);
+    } else {
+        r->states.w = wp;
+    }
+    r->states.stride = n;
+    return 0;
+}
+
+#define DN_GROW(ptr, cnt, cap, type)                                              \
+    do {                                                                           \
+        if ((cnt) >= (cap)) {                                                      \
+            int64_t nc_ = (cap) ? 2 * (cap) : 1024;                                \
+            type *np_ = (type *)realloc((ptr), sizeof(type) * (size_t)nc_);        \
+            if (!np_) { status = -1; goto done; }                                  \
+            (ptr) = np_;                                                           \
+            (cap) = nc_;                                                           \
+        }                                                                          \
+    } while (0)
+
+/* Eq. 4 at one expanded node from its branches and children */
+static void dn_bellman(const or_model *M, dn_node *nodes, const dn_act *acts, int32_t b)
+{
+    double bu = -INFINITY, bl = -INFINITY;
+    for (int a = 0; a < M->n_actions; a++) {
+        const dn_act *x = &acts[nodes[b].act_begin + a];
+        double su = 0.0, sl = 0.0;
+        for (int c = 0; c < x->n_children; c++) {
+            const dn_node *k = &nodes[x->child_begin + c];
+            const double w = (double)k->n / (double)nodes[b].n;
+            su += w * k->u;
+            sl += w * k->l;
+        }
+        if (x->r + M->gamma * su > bu) bu = x->r + M->gamma * su;
+        if (x->r + M->gamma * sl > bl) bl = x->r + M->gamma * sl;
+    }
+    nodes[b].u = bu;
+    nodes[b].l = bl;
+}
+
+/* One planning step from K root scenarios (states `root`, ids 0..K-1): trials
+ * until `seconds` of wall time pass, max_trials trials (if > 0), or the
+ * root's gap closes.  Returns 0, or -1 when memory runs out. */
+int or_despot(const or_model *M, const or_rollout_cfg *C, uint32_t seed, uint32_t step, const or_soa *root,
+              int32_t K, int32_t max_depth, double xi, double seconds, int64_t max_trials, or_despot_result *res)
+{
+    const int A = M->n_actions;
+    int status = 0;
+    dn_node *nodes = NULL;
+    dn_act *acts = NULL;
+    dn_rec *recs = NULL;
+    int32_t *path = NULL, *iota = NULL;
+    int64_t n_nodes = 0, cap_nodes = 0, n_acts = 0, cap_acts = 0, n_recs = 0, cap_recs = 0, cap_path = 0;
+    double *U = NULL, *L = NULL, *cu = NULL, *cl = NULL, *rm = NULL;
+    int64_t *st = NULL, *steps = NULL;
+    int32_t *depths = NULL, *nch = NULL, *cn = NULL, *coff = NULL;
+    uint64_t *cz = NULL;
+    memset(res, 0, sizeof(*res));
+    const double t0 = dn_now();
+
+    /* the root record: the sampled states, ids 0..K-1 */
+    DN_GROW(recs, n_recs, cap_recs, dn_rec);
+    if (dn_rec_alloc(M, K, &recs[0]) != 0) { status = -1; goto done; }
+    n_recs = 1;
+    iota = (int32_t *)malloc(sizeof(int32_t) * (size_t)K);
+    U = (double *)malloc(sizeof(double) * (size_t)K);
+    L = (double *)malloc(sizeof(double) * (size_t)K);
+    st = (int64_t *)malloc(sizeof(int64_t) * (size_t)K);
+    depths = (int32_t *)calloc((size_t)K, sizeof(int32_t));
+    if (!iota || !U || !L || !st || !depths) { status = -1; goto done; }
+    for (int32_t k = 0; k < K; k++) {
+        or_state s;
+        load_state(M, root, k, &s);
+        store_state(M, &recs[0].states, k, &s);
+        recs[0].ids[k] = (uint32_t)k;
+        iota[k] = k;
+    }
+    or_rollout_bounds(M, C, seed, step, &recs[0].states, recs[0].ids, depths, K, U, L, st, NULL);
+    {
+        double su = 0.0, sl = 0.0;
+        for (int32_t k = 0; k < K; k++) {
+            su += U[k];
+            sl += L[k];
+            res->scenario_steps += st[k];
+        }
+        DN_GROW(nodes, n_nodes, cap_nodes, dn_node);
+        dn_node r0 = {-1, -1, K, 0, su / K, sl / K, 0, iota, -1};
+        nodes[n_nodes++] = r0;
+    }
+    /* per-expansion outputs, sized for the root (the largest node) */
+    {
+        const int32_t cap = K;
+        nch = (int32_t *)malloc(sizeof(int32_t) * A);
+        rm = (double *)malloc(sizeof(double) * A);
+        steps = (int64_t *)malloc(sizeof(int64_t) * 2 * A);
+        cz = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)A * cap);
+        cn = (int32_t *)malloc(sizeof(int32_t) * (size_t)A * cap);
+        coff = (int32_t *)malloc(sizeof(int32_t) * (size_t)A * cap);
+        cu = (double *)malloc(sizeof(double) * (size_t)A * cap);
+        cl = (double *)malloc(sizeof(double) * (size_t)A * cap);
+        if (!nch || !rm || !steps || !cz || !cn || !coff || !cu || !cl) { status = -1; goto done; }
+    }
+
+    for (;;) {
+        if (dn_now() - t0 >= seconds) break;
+        if (max_trials > 0 && res->trials >= max_trials) break;
+        const double gap0 = nodes[0].u - nodes[0].l;
+        if (gap0 <= 0.0) break;
+        /* descend: Eq. 5 then Eq. 7 */
+        int64_t depth_n = 0;
+        int32_t b = 0;
+        int ended = 0; /* the path ended at a node without a positive-E child */
+        DN_GROW(path, depth_n, cap_path, int32_t);
+        path[depth_n++] = 0;
+        while (nodes[b].act_begin >= 0) {
+            int best_a = 0;
+            double best_v = -INFINITY, second_v = -INFINITY;
+            for (int a = 0; a < A; a++) {
+                const dn_act *x = &acts[nodes[b].act_begin + a];
+                double s = 0.0;
+                for (int c = 0; c < x->n_children; c++) {
+                    const dn_node *k = &nodes[x->child_begin + c];
+                    s += (double)k->n / (double)nodes[b].n * k->u;
+                }
+                const double v = x->r + M->gamma * s;
+                if (v > best_v) {
+                    second_v = best_v;
+                    best_v = v;
+                    best_a = a;
+                } else if (v > second_v) {
+                    second_v = v;
+                }
+            }
+            res->near_ties += dn_near(best_v, second_v);
+            const dn_act *x = &acts[nodes[b].act_begin + best_a];
+            int32_t best = -1;
+            double best_e = -INFINITY, second_e = -INFINITY;
+            for (int c = 0; c < x->n_children; c++) {
+                const dn_node *k = &nodes[x->child_begin + c];
+                const double e = (k->u - k->l) - (double)k->n / (double)K * xi * gap0;
+                if (e > best_e) {
+                    second_e = best_e;
+                    best_e = e;
+                    best = x->child_begin + c;
+                } else if (e > second_e) {
+                    second_e = e;
+                }
+            }
+            res->near_ties += dn_near(best_e, second_e) + dn_near(best_e, 0.0);
+            if (best < 0 || best_e <= 0.0) {
+                ended = 1;
+                break;
+            }
+            b = best;
+            DN_GROW(path, depth_n, cap_path, int32_t);
+            path[depth_n++] = b;
+        }
+        res->trials += 1;
+        if (ended) break; /* nothing below the root would change: the step is over */
+        if (nodes[b].depth >= max_depth || nodes[b].n == 0) continue;
+        /* expand the leaf (Sec. III-D) into a new record */
+        DN_GROW(recs, n_recs, cap_recs, dn_rec);
+        const int32_t rid = (int32_t)n_recs;
+        dn_node leaf = nodes[b];
+        if (dn_rec_alloc(M, leaf.n, &recs[rid]) != 0) { status = -1; goto done; }
+        n_recs += 1;
+        or_expand_out o;
+        memset(&o, 0, sizeof(o));
+        int64_t es = 0, rs = 0;
+        o.states = recs[rid].states;
+        o.ids = recs[rid].ids;
+        o.perm = recs[rid].perm;
+        o.n_children = nch;
+        o.child_z = cz;
+        o.child_n = cn;
+        o.child_off = coff;
+        o.child_u0 = cu;
+        o.child_l0 = cl;
+        o.r_mean = rm;
+        o.expand_steps = &es;
+        o.rollout_steps = &rs;
+        o.steps = steps;
+        const int32_t cap = leaf.n;
+        if (or_expand_leaf(M, C, seed, step, &recs[leaf.src].states, recs[leaf.src].ids, leaf.pos, leaf.n,
+                           leaf.depth, leaf.action, cap, &o) != 0) { status = -1; goto done; }
+        res->expansions += 1;
+        res->scenario_steps += es + rs;
+        /* attach the branches (Eq. 11) */
+        nodes[b].act_begin = (int32_t)n_acts;
+        for (int a = 0; a < A; a++) {
+            DN_GROW(acts, n_acts, cap_acts, dn_act);
+            dn_act x = {rm[a], (int32_t)n_nodes, nch[a]};
+            acts[n_acts++] = x;
+            for (int c = 0; c < nch[a]; c++) {
+                DN_GROW(nodes, n_nodes, cap_nodes, dn_node);
+                const int64_t o2 = (int64_t)a * cap + c;
+                dn_node k = {b, a, cn[o2], leaf.depth + 1, cu[o2], cl[o2], rid,
+                             recs[rid].perm + (int64_t)a * leaf.n + coff[o2], -1};
+                nodes[n_nodes++] = k;
+            }
+        }
+        if (leaf.depth + 1 > res->max_depth_reached) res->max_depth_reached = leaf.depth + 1;
+        /* Eq. 4 along the path, leaf first */
+        for (int64_t i = depth_n; i-- > 0;) dn_bellman(M, nodes, acts, path[i]);
+    }
+
+done:
+    res->nodes = n_nodes;
+    if (n_nodes > 0) {
+        res->u_root = nodes[0].u;
+        res->l_root = nodes[0].l;
+    }
+    res->elapsed_s = dn_now() - t0;
+    for (int64_t i = 0; i < n_recs; i++) free(recs[i].buf);
+    free(recs);
+    free(nodes);
+    free(acts);
+    free(path);
+    free(iota);
+    free(U);
+    free(L);
+    free(st);
+    free(depths);
+    free(nch);
+    free(rm);
+    free(steps);
+    free(cz);
+    free(cn);
+    free(coff);
+    free(cu);
+    free(cl);
+    return status;
+}

@@ -9,10 +9,13 @@
 * Threads and the leaf batcher run to completion and expand leaves.
 * Anytime: a zero budget returns the initial bounds; a full device arena
   stops the search cleanly.
+* One thread without exploration bonuses builds the host DESPOT loop's tree
+  (the oracle's trial loop over its own expansion), trial for trial.
 """
 import numpy as np
 import pytest
 
+import oracle
 import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -79,3 +82,34 @@ def test_zero_budget_and_full_arena(ctx):
     res = ctx.search(m, W.rocksample_belief(desc), K=100, n_threads=2, max_depth=30, time_budget_s=5.0,
                      rollout=H.rollout_cfg(0, 30), arena_bytes=1 << 20)
     assert res["arena_full"] == 1 and res["expansions"] >= 1
+
+
+@pytest.mark.parametrize("n,K,R,D", [(5, 2, 0, 8), (9, 4, 0, 14), (12, 1, 0, 10), (12, 4, 2, 14)])
+def test_one_thread_search_makes_the_despot_analogue_choices(ctx, n, K, R, D):
+    """hdx_search on one thread with c_a = c_o = 0 takes DESPOT's choices
+    (Eq. 5 actions, Eq. 7 observation branches, Eq. 4 backups) and so builds
+    the same tree as the host DESPOT loop over the oracle's expansion, trial
+    for trial: equal node and expansion counts and root bounds within 1e-5
+    after the same number of trials.  RockSample without rocks: every
+    choice is decided by more than FP32 resolution or by an exact tie (the
+    analogue counts the choices that are not), so the library's FP32 child
+    bounds and the oracle's FP64 ones must make the same choices; with
+    rollouts shorter than the way out and a depth limit below it (12 x 12,
+    depth 10) the lower bound stays 0 and the search ends on its gap."""
+    from paper_1802_06215_amd import hdx as H
+    desc = W.rocksample_model(n, 0, 1)
+    mdl = ctx.upload_model(desc)
+    belief = W.rocksample_belief(desc)
+    T = 200
+    root = oracle.sample_scenarios(desc, belief, K, 3, 0)
+    ref = oracle.despot(desc, oracle.cfg(0, R, D), root, K, 3, 0, D, 0.95, 60.0, T)
+    print("analogue", ref, flush=True)
+    assert ref["near_ties"] == 0
+    r = ctx.search(mdl, belief, K=K, n_threads=1, max_depth=D, batch_leaves=0, time_budget_s=60.0, max_trials=T,
+                   xi=0.95, c_a=0.0, c_o=0.0, gap_epsilon=0.0, arena_bytes=1 << 28, seed=3, step=0,
+                   rollout=H.rollout_cfg(0, R, D))
+    print("search", {k: r[k] for k in ("trials", "expansions", "nodes", "u_root", "l_root")}, flush=True)
+    assert r["expansions"] == ref["expansions"]
+    assert r["nodes"] == ref["nodes"]
+    for a, b in ((r["u_root"], ref["u_root"]), (r["l_root"], ref["l_root"])):
+        assert abs(a - b) <= 1e-5 * max(abs(b), 1.0)
