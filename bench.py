@@ -665,8 +665,8 @@ def search_config(desc, seconds):
         return ("crowd driving with 6, 12 and 20 pedestrians, 5 goals, K=500, rollouts of 50, max depth 50, "
                 "%.1f s planning step" % seconds)
     if desc["kind"] == 3:
-        return ("navigation %dx%d, %d unknown cells, K in {100, 500, 1000, 2000}, max depth 90, %.1f s planning "
-                "step" % (desc["n"], desc["n"], desc["n_unknown"], seconds))
+        return ("navigation %dx%d, %d unknown cells, K in {100, 500, 1000, 2000, 3000, 5000}, max depth 90, "
+                "%.1f s planning step" % (desc["n"], desc["n"], desc["n_unknown"], seconds))
     return "%s %dx%d, %d rocks, K=500, max depth 90, %.1f s planning step" % (
         "multi-agent RockSample" if desc["kind"] == 2 else "RockSample", desc["n"], desc["n"], desc["m"], seconds)
 
@@ -943,13 +943,13 @@ def main():
 
     if args.workload == "nav13" and args.search_seconds > 0:
         # the scenario-count study: tree size within the planning time at
-        # K = 100 .. 2000, one search thread (GPU-DESPOT analogue) and eight
+        # K = 100 .. 5000, one search thread (GPU-DESPOT analogue) and eight
         # with the leaf batcher (HyP analogue), against the DESPOT analogue
         import workloads as W
         desc = items[0][0]
         m = wl["models"][id(desc)]
         search = []
-        for K in (100, 500, 1000, 2000):
+        for K in (100, 500, 1000, 2000, 3000, 5000):
             row = dict(K=K)
             for name, threads, nb in (("gpu_despot", 1, 0), ("hyp", 8, 8)):
                 extra = dict(c_a=0.0, c_o=0.0) if threads == 1 else {}

@@ -69,6 +69,8 @@ typedef int32_t hdx_status;
 #define HDX_MAX_PEDS 32
 #define HDX_MAX_GOALS 8
 #define HDX_MAX_LEAF_SCENARIOS 2048 /* scenarios of one leaf in one tile */
+#define HDX_MAX_NAV_LEAF_SCENARIOS 5120 /* navigation leaves (scenario counts up to 5000 in Sec. IV,
+                                           effect of the number of scenarios) */
 #define HDX_MAX_HORIZON 4096        /* longest rollout (discount table size) */
 
 #define HDX_POLICY_DEFAULT 0 /* RockSample: move east; driving: brake for a pedestrian ahead, else accelerate */
@@ -256,7 +258,8 @@ hdx_status hdx_sample_scenarios(hdx_ctx *ctx, const hdx_model *model, const hdx_
  * different models, sizes and rollout settings.  Results are written as
  * described for hdx_leaf and do not depend on how leaves are batched or on
  * the launch schedule.  Errors: HDX_E_SHAPE if a leaf has more than
- * HDX_MAX_LEAF_SCENARIOS scenarios or a rollout longer than
+ * HDX_MAX_LEAF_SCENARIOS scenarios (HDX_MAX_NAV_LEAF_SCENARIOS for
+ * navigation) or a rollout longer than
  * HDX_MAX_HORIZON, HDX_E_CAPACITY if cap is too small, HDX_E_INVALID for a
  * missing required pointer; nothing is launched on error. */
 hdx_status hdx_expand_leaf(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves,
@@ -484,7 +487,8 @@ hdx_status hdx_expand_leaf_surrogate(hdx_ctx *ctx, const hdx_leaf *leaves, int32
  * the search stops early (reported in the result).  A failing expansion
  * stops the search and its error is returned (text via hdx_last_error). */
 typedef struct {
-    int32_t K;             /* scenarios sampled at the root */
+    int32_t K;             /* scenarios sampled at the root (up to HDX_MAX_LEAF_SCENARIOS,
+                              HDX_MAX_NAV_LEAF_SCENARIOS for navigation) */
     int32_t n_threads;     /* concurrent search threads (1..64) */
     int32_t max_depth;     /* search horizon D: leaves at this depth are not expanded */
     int32_t batch_leaves;  /* <= 1: one stream per thread; > 1: batcher with this many leaves per launch */

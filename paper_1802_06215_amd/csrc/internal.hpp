@@ -15,6 +15,7 @@ constexpr int kMaxGoals = HDX_MAX_GOALS;
 constexpr int kHorizon = HDX_MAX_HORIZON;
 constexpr int kSenseEntries = 2 * (kMaxGrid - 1) * (kMaxGrid - 1) + 1;  // squared distances
 constexpr int kMaxLeaf = HDX_MAX_LEAF_SCENARIOS;
+constexpr int kMaxNavLeaf = HDX_MAX_NAV_LEAF_SCENARIOS;
 
 enum : uint32_t { kTagStep = 0, kTagInit = 1, kTagPolicy = 2 };
 constexpr uint64_t kEmptyKey = ~0ull;
@@ -180,6 +181,58 @@ __host__ __device__ inline LdsLayout make_layout(int32_t np, bool small = false)
     return L;
 }
 
+// Medium observation alphabet (navigation: every key below kMedKeys).
+// Regions, each in use for the whole tile:
+//   gpow        discount powers, goal points and the navigation cell table
+//   key, rank   per scenario: observation key (16 bits) and its rank among
+//               the scenarios of that key in its wavefront's chunks
+//   ub, lb      per scenario: U and L
+//   perm        grouped order (leaf positions)
+//   su, sl      segmented sums over 64-aligned chunks of the grouped order
+//   wcnt        per run of chunks (one wavefront each) and key: scenario
+//               count, then the key's count in earlier runs
+//   kcnt, koff, kci  per key: count, child offset, child index
+//   cof, cnc    per child: offset, count
+//   chunk_r     per 64-scenario chunk: step reward sum
+// A leaf of up to kMaxMedLeaf scenarios fits one tile.
+constexpr int kMedKeys = 264;  // 257 navigation observations, rounded up
+constexpr int kMedWaves = 16;  // wavefronts of the widest workgroup
+constexpr int kMaxMedLeaf = kMaxNavLeaf;
+struct MedLayout {
+    uint32_t gpow, key, rank, ub, lb, perm, su, sl, wcnt, kcnt, koff, kci, cof, cnc, chunk_r, misc, total;
+    int32_t np;
+};
+__host__ __device__ inline MedLayout make_med_layout(int32_t np) {
+    MedLayout L;
+    if (np < 1) np = 1;
+    L.np = np;
+    const uint32_t n = (uint32_t)np, chunks = (n + 63u) / 64u;
+    uint32_t o = 0;
+    auto take = [&](uint32_t bytes) {
+        uint32_t at = o;
+        o += (bytes + 15u) & ~15u;
+        return at;
+    };
+    L.gpow = take(4u * (kGpowLds + 2 * kMaxGoals) + 2u * HDX_MAX_NAV_GRID * HDX_MAX_NAV_GRID);
+    L.key = take(2u * n);
+    L.rank = take(2u * n);
+    L.ub = take(4u * n);
+    L.lb = take(4u * n);
+    L.perm = take(2u * n);
+    L.su = take(4u * n);
+    L.sl = take(4u * n);
+    L.wcnt = take(4u * (chunks < (uint32_t)kMedWaves ? chunks : (uint32_t)kMedWaves) * kMedKeys);
+    L.kcnt = take(4u * kMedKeys);
+    L.koff = take(4u * kMedKeys);
+    L.kci = take(4u * kMedKeys);
+    L.cof = take(4u * kMedKeys);
+    L.cnc = take(4u * kMedKeys);
+    L.chunk_r = take(4u * chunks);
+    L.misc = take(64 + 4u * 64);
+    L.total = o;
+    return L;
+}
+
 // Kernel variant a set of leaves needs: mode 0 RockSample only, 1 driving
 // only, 2 both; pm = pedestrian capacity of the register state; n_max sizes
 // the LDS carve-up.
@@ -203,7 +256,7 @@ hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue
 // default all leaves of a variant form one group (one dispatch, no fork and
 // join between dispatches), filed under the size class of its largest leaf;
 // split plans give each size class of leaf (n <= 64, 128, 256, 512, 1024,
-// 2048) a group of its own, so small leaves do not pay for the largest one's
+// and larger) a group of its own, so small leaves do not pay for the largest one's
 // footprint, and launch the groups side by side.  Inside a group the tiles
 // are ordered largest leaf first (long tiles start early, short ones fill
 // the tail), a leaf's tiles in action order, and interleaved so that the

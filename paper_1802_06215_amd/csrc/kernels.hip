@@ -635,6 +635,246 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
     __syncthreads();  // LDS is reused by the next tile
 }
 
+// One (leaf, action) tile of a model whose observation keys are all below
+// kMedKeys (navigation: 8 reading bits, or the terminal key 256), for
+// leaves of up to kMaxMedLeaf scenarios.  No hash table and no sort: every
+// key is its own table index.
+//  - ranks: the 64-scenario chunks are split into contiguous runs, one per
+//    wavefront; a wavefront walks its run in order and keeps a running count
+//    per key, so a scenario's rank is the count of its key in earlier chunks
+//    of the run plus the lanes below it in its chunk with the same key;
+//  - a key's count in earlier runs, its child offset (ascending key) and its
+//    child index come from prefix sums over the runs and over the keys;
+//  - the per-child U and L sums are the same segmented scans over 64-aligned
+//    chunks of the grouped order as in the hashed path, chunk partials added
+//    in chunk order, so both paths give identical results for a leaf either
+//    can expand.
+template <class Ops>
+__device__ void run_tile_med(const HDX_CONST LeafTask *T, const int a, unsigned char *lds, const MedLayout &Ly) {
+    static_assert(Ops::kTerminalObs < (uint64_t)kMedKeys, "observation keys exceed the medium alphabet");
+    float *gpow_lds = (float *)(lds + Ly.gpow);
+    const MView M = make_view(T->model, gpow_lds);
+    const int n = T->n;
+    const int cap = T->cap;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = lane_id(), wid = tid >> 6, nw = nt >> 6;
+    uint16_t *keyb = (uint16_t *)(lds + Ly.key);
+    uint16_t *rnk = (uint16_t *)(lds + Ly.rank);
+    float *ub = (float *)(lds + Ly.ub);
+    float *lb = (float *)(lds + Ly.lb);
+    int16_t *permb = (int16_t *)(lds + Ly.perm);
+    float *su = (float *)(lds + Ly.su);
+    float *sl = (float *)(lds + Ly.sl);
+    int32_t *wcnt = (int32_t *)(lds + Ly.wcnt);
+    int32_t *kcnt = (int32_t *)(lds + Ly.kcnt);
+    int32_t *koff = (int32_t *)(lds + Ly.koff);
+    int32_t *kci = (int32_t *)(lds + Ly.kci);
+    int32_t *cof = (int32_t *)(lds + Ly.cof);
+    int32_t *cnc = (int32_t *)(lds + Ly.cnc);
+    float *chunk_r = (float *)(lds + Ly.chunk_r);
+    int32_t *misc = (int32_t *)(lds + Ly.misc);
+    unsigned long long *stepc = (unsigned long long *)(misc + 4);  // expansion, rollout steps
+    int32_t *scan_scratch = misc + 16;
+    const int nch = (n + 63) >> 6;
+    const int run_len = nch > 0 ? (nch + nw - 1) / nw : 1;  // chunks per wavefront run
+    const int runs = (nch + run_len - 1) / run_len;        // <= min(nw, nch)
+
+    for (int i = tid; i < runs * kMedKeys; i += nt) wcnt[i] = 0;
+    if (tid == 0) {
+        stepc[0] = 0;
+        stepc[1] = 0;
+    }
+    stage_gpow(T->model, gpow_lds);
+    stage_cells(T->model, gpow_lds);
+    __syncthreads();
+
+    RolloutParams RP;
+    RP.k0 = T->k0;
+    RP.k1 = T->k1;
+    RP.policy = T->policy;
+    RP.const_action = T->const_action;
+    RP.max_steps = T->max_steps;
+    RP.max_depth = T->max_depth;
+    RP.n_actions = T->n_actions;
+    const int depth = T->depth, last_action = T->last_action;
+    const StatesPtr parent = load_states(&T->parent);
+    const StatesPtr leaf_out = load_states(&T->out);
+    const StatesPtr sprime = load_states(&T->sprime);
+    const bool write_leaf = (a == 0);
+    const bool pair_out = has_states(sprime);
+
+    // -- gather + update + expand + bounds + rollouts (Eq. 10, 12, 13) ------
+    int my_exp = 0, my_roll = 0;
+    for (int base = 0; base < n; base += nt) {
+        const int k = base + tid;
+        const bool valid = k < n;
+        float r = 0.0f;
+        if (valid) {
+            const int p = T->idx[k];
+            const uint32_t id = T->parent_ids[p];
+            typename Ops::State st;
+            Ops::load(M, parent, p, st);
+            if (last_action >= 0) {
+                float r0;
+                uint64_t z0;
+                Ops::template step<false>(M, st, last_action, id, (uint32_t)(depth - 1), RP.k0, RP.k1, r0, z0);
+            }
+            if (write_leaf) {
+                Ops::store(M, leaf_out, k, st);
+                T->ids_out[k] = id;
+            }
+            my_exp += Ops::terminal(st) ? 0 : 1;
+            uint64_t z;
+            Ops::template step<true>(M, st, a, id, (uint32_t)depth, RP.k0, RP.k1, r, z);
+            const float U = Ops::upper(M, st);
+            const int64_t pk = (int64_t)a * n + k;
+            if (pair_out) Ops::store(M, sprime, pk, st);
+            int ns = 0;
+            const float L = rollout<Ops>(M, RP, st, id, depth + 1, ns);
+            my_roll += ns;
+            keyb[k] = (uint16_t)z;
+            ub[k] = U;
+            lb[k] = L;
+            if (T->r) T->r[pk] = r;
+            if (T->z) T->z[pk] = z;
+            if (T->U) T->U[pk] = U;
+            if (T->L) T->L[pk] = L;
+        }
+        // mean step reward: sum of this 64-scenario chunk (lanes past n add 0;
+        // a chunk without a reward sums to +0 without the reduction)
+        const float r_chunk = __ballot(r != 0.0f) ? wave_total(r) : 0.0f;
+        if (lane == 0 && base + wid * 64 < n) chunk_r[(base >> 6) + wid] = r_chunk;
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        my_exp += __shfl_xor(my_exp, d, 64);
+        my_roll += __shfl_xor(my_roll, d, 64);
+    }
+    if (lane == 0) {
+        atomicAdd(&stepc[0], (unsigned long long)my_exp);
+        atomicAdd(&stepc[1], (unsigned long long)my_roll);
+    }
+    __syncthreads();
+
+    // -- ranks inside each wavefront's run of chunks ----------------------------
+    if (wid < runs) {
+        int32_t *cw = wcnt + wid * kMedKeys;
+        const int t_end = min(nch, (wid + 1) * run_len);
+        for (int t = wid * run_len; t < t_end; ++t) {
+            const int k = t * 64 + lane;
+            const bool valid = k < n;
+            const uint32_t key = valid ? keyb[k] : 0xFFFFFFFFu;
+            uint64_t rem = __ballot(valid);
+            int rank = 0;
+            while (rem) {
+                const int leader = __ffsll((unsigned long long)rem) - 1;
+                const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
+                const bool mine = key == v;
+                const uint64_t bv = __ballot(mine);
+                const int before = cw[v];  // one address: a broadcast read
+                if (mine) rank = before + __popcll(bv & __lanemask_lt());
+                if (lane == leader) cw[v] = before + __popcll(bv);
+                rem &= ~bv;
+            }
+            if (valid) rnk[k] = (uint16_t)rank;
+        }
+    }
+    __syncthreads();
+
+    // -- per key: count in earlier runs, total, child offset and index ----------
+    // koff packs the count (low 16 bits, at most kMaxMedLeaf) and presence
+    // (high bits) so one exclusive scan gives both the offset and the index.
+    for (int v = tid; v < kMedKeys; v += nt) {
+        int run = 0;
+        for (int w = 0; w < runs; ++w) {
+            const int c = wcnt[w * kMedKeys + v];
+            wcnt[w * kMedKeys + v] = run;
+            run += c;
+        }
+        kcnt[v] = run;
+        koff[v] = run + (run > 0 ? (1 << 16) : 0);
+    }
+    __syncthreads();
+    block_exclusive_scan(koff, kMedKeys, scan_scratch);
+    const int last = kMedKeys - 1;
+    const int D = (koff[last] >> 16) + (kcnt[last] > 0 ? 1 : 0);
+    for (int v = tid; v < kMedKeys; v += nt) {
+        const int packed = koff[v];
+        const int c = kcnt[v];
+        const int o = packed & 0xFFFF, ci = packed >> 16;
+        koff[v] = o;
+        kci[v] = ci;
+        if (c > 0) {
+            cof[ci] = o;
+            cnc[ci] = c;
+            if (ci < cap) {
+                const int64_t q = (int64_t)a * cap + ci;
+                T->child_z[q] = (uint64_t)v;
+                T->child_n[q] = c;
+                T->child_off[q] = o;
+            }
+        }
+    }
+    if (tid == 0) T->n_children[a] = D;
+    __syncthreads();
+
+    // -- grouped order: child offset + count in earlier runs + rank -------------
+    for (int k = tid; k < n; k += nt) {
+        const int v = keyb[k];
+        const int w = (k >> 6) / run_len;
+        permb[koff[v] + wcnt[w * kMedKeys + v] + rnk[k]] = (int16_t)k;
+        if (T->child_of) T->child_of[(int64_t)a * n + k] = kci[v];
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += nt) T->perm[(int64_t)a * n + i] = permb[i];
+
+    // -- per-child sums: segmented wavefront scans over the grouped order ------
+    for (int t = wid; t < nch; t += nw) {
+        const int i = t * 64 + lane;
+        const bool valid = i < n;
+        const int k = valid ? permb[i] : 0;
+        float vu = valid ? ub[k] : 0.0f;
+        float vl = valid ? lb[k] : 0.0f;
+        const int c = valid ? (int)keyb[k] : -1;
+        const int c_prev = __shfl_up(c, 1, 64);
+        bool head = (lane == 0) || (c_prev != c);
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const float ou = __shfl_up(vu, d, 64);
+            const float ol = __shfl_up(vl, d, 64);
+            const int oh = __shfl_up((int)head, d, 64);
+            if (lane >= d && !head) {
+                vu = ou + vu;
+                vl = ol + vl;
+                head = oh != 0;
+            }
+        }
+        if (valid) {
+            su[i] = vu;
+            sl[i] = vl;
+        }
+    }
+    __syncthreads();
+    for (int c = tid; c < D && c < cap; c += nt) {
+        const int start = cof[c], end = start + cnc[c];
+        float tu = 0.0f, tl = 0.0f;
+        for (int t = start >> 6; t <= (end - 1) >> 6; ++t) {
+            const int e = min(end, (t + 1) * 64) - 1;
+            tu = tu + su[e];
+            tl = tl + sl[e];
+        }
+        T->child_u0[(int64_t)a * cap + c] = tu / (float)cnc[c];
+        T->child_l0[(int64_t)a * cap + c] = tl / (float)cnc[c];
+    }
+    if (tid == 0) {
+        float tr = 0.0f;
+        for (int t = 0; t < nch; ++t) tr = tr + chunk_r[t];
+        T->r_mean[a] = n > 0 ? tr / (float)n : 0.0f;
+        T->steps[2 * a + 0] = (int64_t)stepc[0];
+        T->steps[2 * a + 1] = (int64_t)stepc[1];
+    }
+    __syncthreads();  // LDS is reused by the next tile
+}
+
 template <int PM, bool kGroup>
 __device__ __forceinline__ void run_ped(const HDX_CONST LeafTask *T, int a, unsigned char *lds, const LdsLayout &Ly) {
     run_tile<PedOps<PM>, kGroup>(T, a, lds, Ly);
@@ -666,7 +906,7 @@ __device__ __forceinline__ void run_mode(const HDX_CONST LeafTask *T, int a, uns
     if (MODE == 3) {
         run_tile<MarsOps>(T, a, lds, Ly);
     } else if (MODE == 4) {
-        run_tile<NavOps>(T, a, lds, Ly);
+        run_tile_med<NavOps>(T, a, lds, make_med_layout(Ly.np));
     } else if (MODE == 0 || (MODE == 2 && T->kind == HDX_ROCKSAMPLE)) {
         run_tile<RsOps>(T, a, lds, Ly);
     } else {
@@ -735,6 +975,12 @@ __global__ __launch_bounds__(max_threads<MODE>()) void expand_args(const ArgPack
     run_mode<MODE, PM, true>(T, t - P->tile_begin[i], lds, Ly);
 }
 
+// Dynamic LDS of one workgroup for leaves of up to n_max scenarios.
+template <int MODE>
+uint32_t lds_bytes(int32_t n_max) {
+    return MODE == 4 ? make_med_layout(n_max).total : make_layout(n_max, small_obs_mode<MODE>()).total;
+}
+
 template <int MODE, int PM>
 hipError_t configure_t() {
     hipError_t e = hipFuncSetAttribute((const void *)expand_tiles<MODE, PM>,
@@ -746,25 +992,24 @@ hipError_t configure_t() {
 
 template <int MODE, int PM>
 hipError_t launch_args_t(const ArgPack &pack, const Schedule &sch, hipStream_t stream) {
-    const LdsLayout Ly = make_layout(pack.n_max, small_obs_mode<MODE>());
     const int grid = pack.tile_begin[pack.n_leaves];
     if (grid < 1) return hipSuccess;
     const int threads = sch.threads > max_threads<MODE>() ? max_threads<MODE>() : sch.threads;
-    hipLaunchKernelGGL((expand_args<MODE, PM>), dim3(grid), dim3(threads), Ly.total, stream, pack);
+    hipLaunchKernelGGL((expand_args<MODE, PM>), dim3(grid), dim3(threads), lds_bytes<MODE>(pack.n_max), stream,
+                       pack);
     return hipGetLastError();
 }
 
 template <int MODE, int PM>
 hipError_t launch_expand_t(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queue, int32_t n_tiles,
                            int32_t n_max, const Schedule &sch, int32_t n_cu, hipStream_t stream) {
-    const LdsLayout Ly = make_layout(n_max, small_obs_mode<MODE>());
     // persistent: a fixed grid that drains the tile queue, so a captured
     // graph stays valid for any tile count
     const int grid = sch.persistent > 0 ? n_cu * sch.persistent : n_tiles;
     if (grid < 1) return hipSuccess;
     const int threads = sch.threads > max_threads<MODE>() ? max_threads<MODE>() : sch.threads;
-    hipLaunchKernelGGL((expand_tiles<MODE, PM>), dim3(grid), dim3(threads), Ly.total, stream, d_tasks, d_tiles,
-                       d_queue, n_max, sch.persistent > 0 ? 1 : 0, sch.xcd_remap);
+    hipLaunchKernelGGL((expand_tiles<MODE, PM>), dim3(grid), dim3(threads), lds_bytes<MODE>(n_max), stream, d_tasks,
+                       d_tiles, d_queue, n_max, sch.persistent > 0 ? 1 : 0, sch.xcd_remap);
     return hipGetLastError();
 }
 

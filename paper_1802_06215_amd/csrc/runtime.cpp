@@ -547,7 +547,8 @@ hdx_status validate_leaves(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leave
         if (!L.model) return fail(ctx, HDX_E_INVALID, "leaf without model");
         const hdx_model_desc &d = L.model->desc;
         const int A = d.n_actions;
-        if (L.n < 0 || L.n > kMaxLeaf) return fail(ctx, HDX_E_SHAPE, "leaf scenario count out of range");
+        if (L.n < 0 || L.n > (d.kind == HDX_NAV ? kMaxNavLeaf : kMaxLeaf))
+            return fail(ctx, HDX_E_SHAPE, "leaf scenario count out of range");
         if (L.depth < 0 || L.last_action < -1 || L.last_action >= A || (L.last_action >= 0 && L.depth < 1))
             return fail(ctx, HDX_E_INVALID, "depth / last_action");
         if (L.cap < hdx_model_max_children(L.model, L.n)) return fail(ctx, HDX_E_CAPACITY, "cap too small");

@@ -619,7 +619,8 @@ extern "C" hdx_status hdx_search(hdx_ctx *ctx, const hdx_model *model, const hdx
                                  const hdx_search_cfg *cfg, hdx_search_result *out) {
     if (!ctx || !model || !belief || !cfg || !out) return HDX_E_INVALID;
     const int A = hdx_model_actions(model);
-    if (cfg->K < 1 || cfg->K > HDX_MAX_LEAF_SCENARIOS || cfg->n_threads < 1 || cfg->n_threads > 64 ||
+    const int k_max = hdx_internal_desc(model)->kind == HDX_NAV ? HDX_MAX_NAV_LEAF_SCENARIOS : HDX_MAX_LEAF_SCENARIOS;
+    if (cfg->K < 1 || cfg->K > k_max || cfg->n_threads < 1 || cfg->n_threads > 64 ||
         cfg->max_depth < 1 || cfg->arena_bytes < (1 << 20) || A > HDX_MAX_ACTIONS)
         return HDX_E_INVALID;
     Search S;

@@ -22,6 +22,7 @@ POLICY_DEFAULT, POLICY_CONST, POLICY_RANDOM = 0, 1, 2
 SIZE_CLASSES = 6
 LAUNCH_GROUPS = 36  # model variant (RockSample; driving <= 8, 16, 32 pedestrians; multi-agent; navigation) x size class
 MAX_LEAF_SCENARIOS = 2048
+MAX_NAV_LEAF_SCENARIOS = 5120
 MAX_HORIZON = 4096
 NOALLOC_MAX_LEAVES = 512  # HDX_NOALLOC_MAX_LEAVES
 NOALLOC_MAX_TILES = 65536  # HDX_NOALLOC_MAX_TILES

@@ -2,7 +2,8 @@
 
 The HIP path through the C ABI against the oracle on the same seeded inputs:
 sampling from the prior, leaves of the paper's 13 x 13 map (124 unknown
-cells) at several sizes up to the largest a tile takes, with scenarios
+cells) at several sizes up to the largest a tile takes (5120 scenarios:
+the paper's scenario counts reach 5000), with scenarios
 spread over neighbouring cells or sharing one, both rollout policies, the
 empty and all-terminal leaves, the stand-alone bounds call, a batch mixing
 navigation with the other models (bit-identical to one-leaf calls, both
@@ -26,7 +27,7 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("K", [1, 500, 2048])
+@pytest.mark.parametrize("K", [1, 500, 2048, 5000])
 def test_sample_scenarios_nav(ctx, K):
     from paper_1802_06215_amd import hdx as H
     desc = W.nav_model(1)
@@ -48,6 +49,10 @@ CASES = [
     (800, 333, False, 0, 5),
     (2048, 2048, False, 0, 6),
     (2048, 1500, True, 2, 7),
+    (3000, 3000, False, 0, 8),
+    (5000, 5000, False, 2, 9),
+    (5120, 4097, True, 0, 10),  # one scenario past 64 full chunks
+    (5120, 5120, False, 0, 11),  # the largest leaf
 ]
 
 
@@ -86,6 +91,54 @@ def test_root_and_degenerate_leaves(ctx):
     compare_leaf(desc, gpu, ref, 150)
     assert np.all(gpu["n_children"] == 1) and int(gpu["steps"].sum()) == 0
     assert np.all(gpu["child_z"][:, 0] == 256)
+
+
+def test_large_leaf_is_independent_of_the_schedule(ctx):
+    """A 5000-scenario leaf: every workgroup width splits its 79 chunks
+    into different runs per wavefront, and the results stay bit-identical."""
+    from paper_1802_06215_amd import Batch
+    desc = W.nav_model(2)
+    m = ctx.upload_model(desc)
+    lf = W.nav_leaf(desc, 5000, 5000, 12, p_term=0.05)
+    par, pids = to_dev(oracle.parent_states(desc, lf)), ids_dev(lf["ids"])
+    leaf, out, keep = gpu_leaf_desc(m, par, pids, lf["idx"], lf["depth"], lf["last_action"], 5, 2,
+                                    cfg_pair(0, 1 << 30, 90)[1], per_pair=False)
+    ctx.expand_leaf([leaf])
+    torch.cuda.synchronize()
+    ref = collect(m, out)
+    b = Batch(ctx, 1, desc["n_actions"])
+    b.set_leaves([leaf])
+    for threads, persistent, xcd in ((64, 0, 0), (192, 0, 1), (320, 2, 0), (1024, 0, 0)):
+        print("nav 5000 schedule", threads, persistent, xcd, flush=True)
+        wipe([dict(out=out)])
+        b.set_schedule(threads, persistent, xcd)
+        b.launch()
+        torch.cuda.synchronize()
+        same([collect(m, out)], [ref])
+    b.close()
+
+
+def test_leaf_and_search_size_limits(ctx):
+    from paper_1802_06215_amd import HdxError
+    from paper_1802_06215_amd import hdx as H
+    for desc, n_ok, lf_fn in ((W.nav_model(1), H.MAX_NAV_LEAF_SCENARIOS, W.nav_leaf),
+                              (W.rocksample_model(7, 8, 1), H.MAX_LEAF_SCENARIOS, W.rocksample_leaf)):
+        m = ctx.upload_model(desc)
+        lf = lf_fn(desc, n_ok + 1, n_ok + 1, 3)
+        par, pids = to_dev(oracle.parent_states(desc, lf)), ids_dev(lf["ids"])
+        leaf, out, keep = gpu_leaf_desc(m, par, pids, lf["idx"], lf["depth"], lf["last_action"], 1, 0,
+                                        cfg_pair(0, 1 << 30, 90)[1], per_pair=False)
+        with pytest.raises(HdxError) as e:
+            ctx.expand_leaf([leaf])
+        assert e.value.code == -4
+        belief = W.nav_belief(desc) if desc["kind"] == W.NAV else W.rocksample_belief(desc)
+        with pytest.raises(HdxError) as e:
+            ctx.search(m, belief, K=n_ok + 1, n_threads=1, max_depth=10, time_budget_s=0.1,
+                       rollout=H.rollout_cfg(0, 10), arena_bytes=256 << 20)
+        assert e.value.code == -1
+        res = ctx.search(m, belief, K=n_ok, n_threads=1, max_depth=10, time_budget_s=0.1, max_trials=2,
+                         rollout=H.rollout_cfg(0, 10), arena_bytes=256 << 20)
+        assert res["trials"] >= 1
 
 
 def test_rollout_bounds_nav(ctx):
@@ -209,7 +262,7 @@ def test_mixed_batches_match_single_leaves_and_oracle(ctx):
         compare_leaf(desc, collect(it["m"], it["out"]), want, len(lf["idx"]))
 
 
-@pytest.mark.parametrize("threads,batch,K", [(1, 0, 500), (8, 8, 2000)])
+@pytest.mark.parametrize("threads,batch,K", [(1, 0, 500), (8, 8, 2000), (8, 8, 5000)])
 def test_nav_search(ctx, threads, batch, K):
     from paper_1802_06215_amd import hdx as H
     desc = W.nav_model(1)
