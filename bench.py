@@ -896,13 +896,14 @@ def main():
         arena = (48 << 30) if desc["kind"] == 2 else (8 << 30)
         search = []
         # one thread with plain DESPOT choices (c_a = c_o = 0) is the
-        # GPU-DESPOT analogue; several threads with Eq. 8-9 the HyP-DESPOT one
-        for threads, nb in ((1, 0), (4, 0), (8, 0), (8, 8), (16, 16)):
+        # GPU-DESPOT analogue; several threads with Eq. 8-9 the HyP-DESPOT
+        # one, expanding on a stream each or through the leaf batchers
+        for threads, nb in ((1, 0), (4, 0), (8, 0), (16, 8), (32, 16), (48, 16)):
             extra = dict(c_a=0.0, c_o=0.0) if threads == 1 else {}
             res = ctx.search(m, belief, K=500, n_threads=threads, max_depth=90,
                              batch_leaves=nb, time_budget_s=args.search_seconds,
                              rollout=H.rollout_cfg(0, 1 << 30, 90), seed=3, arena_bytes=arena, **extra)
-            search.append(dict(threads=threads, leaf_batcher=nb > 0,
+            search.append(dict(threads=threads, leaf_batcher=nb > 0, batch_leaves=nb,
                                trials_per_s=round(res["trials"] / res["elapsed_s"], 1),
                                expanding_trials_per_s=round(res["expansions"] / res["elapsed_s"], 1),
                                idle_trials=res["idle_trials"],
@@ -910,7 +911,10 @@ def main():
                                scenario_steps_per_s=round(res["scenario_steps"] / res["elapsed_s"], 1),
                                nodes=res["nodes"], depth=res["max_depth_reached"],
                                root_gap=round(res["u_root"] - res["l_root"], 4),
-                               elapsed_s=round(res["elapsed_s"], 3), arena_full=res["arena_full"]))
+                               elapsed_s=round(res["elapsed_s"], 3), arena_full=res["arena_full"],
+                               thread_s=dict(select=round(res["time_select_s"], 3),
+                                             expand=round(res["time_expand_s"], 3),
+                                             backup=round(res["time_backup_s"], 3))))
             log("search", search[-1])
 
     if args.workload == "ped16" and args.search_seconds > 0:
@@ -923,7 +927,7 @@ def main():
             dp = W.pednav_model(P, 5, 1)
             mp = ctx.upload_model(dp)
             row = dict(peds=P)
-            for name, threads, nb in (("gpu_despot", 1, 0), ("hyp", 8, 8)):
+            for name, threads, nb in (("gpu_despot", 1, 0), ("hyp", 32, 16)):
                 extra = dict(c_a=0.0, c_o=0.0) if threads == 1 else {}
                 res = ctx.search(mp, W.pednav_belief(dp), K=500, n_threads=threads, max_depth=50, batch_leaves=nb,
                                  time_budget_s=args.search_seconds, rollout=H.rollout_cfg(0, 50), seed=3,
@@ -951,7 +955,7 @@ def main():
         search = []
         for K in (100, 500, 1000, 2000, 3000, 5000):
             row = dict(K=K)
-            for name, threads, nb in (("gpu_despot", 1, 0), ("hyp", 8, 8)):
+            for name, threads, nb in (("gpu_despot", 1, 0), ("hyp", 32, 16)):
                 extra = dict(c_a=0.0, c_o=0.0) if threads == 1 else {}
                 res = ctx.search(m, W.nav_belief(desc), K=K, n_threads=threads, max_depth=90, batch_leaves=nb,
                                  time_budget_s=args.search_seconds, rollout=H.rollout_cfg(0, 1 << 30, 90), seed=3,
@@ -989,7 +993,7 @@ def main():
             cpu["despot_analogue"] = dict(desp, planning_s=args.search_seconds,
                                           speedup_gpu_despot=round(one["nodes"] / desp["nodes"], 1),
                                           speedup_hyp_despot=round(best["nodes"] / desp["nodes"], 1),
-                                          hyp_config=dict(threads=best["threads"], leaf_batcher=best["leaf_batcher"]))
+                                          hyp_config=dict(threads=best["threads"], batch_leaves=best["batch_leaves"]))
 
     names = dict(rs15="RS15 leaf expansion: RockSample 15x15, 15 rocks, |A|=20, K=500, horizon 90, move-east "
                       "rollouts; %d synthetic leaves (n in {500,250,125,62,31}, depth 1..30)",

@@ -478,9 +478,13 @@ hdx_status hdx_expand_leaf_surrogate(hdx_ctx *ctx, const hdx_leaf *leaves, int32
  * (Eq. 6-7, 9), stopping where the excess uncertainty is not positive; a
  * leaf it reaches above max_depth is expanded on the GPU (hdx_expand_leaf:
  * Eq. 10-13), its children attached (Eq. 11) and the path backed up (Eq. 4).
- * Leaves are expanded either on one HIP stream per thread (batch_leaves <=
- * 1) or by a batcher thread that fuses up to batch_leaves pending leaves of
- * all threads into one launch.  The search stops at the time budget, after
+ * The threads share the tree without a tree-wide lock: descents read the
+ * bounds as they stand, a leaf is claimed by an atomic state change, and
+ * each backup step locks one node.  Leaves are expanded either on one HIP
+ * stream per thread (batch_leaves <= 1) or by batcher threads (one per
+ * batch_leaves threads, at most eight) that each take up to batch_leaves
+ * pending leaves of all threads and launch them in packs of up to 11
+ * (descriptors in the kernel arguments).  The search stops at the time budget, after
  * max_trials trials (if > 0), or when the root gap u - l falls below
  * gap_epsilon; it returns the action with the largest lower bound.  Device
  * memory for the tree comes from an arena of arena_bytes; when it is full
@@ -491,7 +495,7 @@ typedef struct {
                               HDX_MAX_NAV_LEAF_SCENARIOS for navigation) */
     int32_t n_threads;     /* concurrent search threads (1..64) */
     int32_t max_depth;     /* search horizon D: leaves at this depth are not expanded */
-    int32_t batch_leaves;  /* <= 1: one stream per thread; > 1: batcher with this many leaves per launch */
+    int32_t batch_leaves;  /* <= 1: one stream per thread; > 1: batchers taking up to this many leaves */
     double time_budget_s;  /* planning time */
     int64_t max_trials;    /* 0 = no limit */
     double xi;             /* target uncertainty of Eq. 7 */
@@ -531,6 +535,10 @@ typedef struct {
     double judge_mae;                       /* mean |l0_sur - l0_rollout| per judged child */
     double judge_rel_err;                   /* sum |l0_sur - l0_rollout| / sum |l0_rollout| */
     int32_t surrogate_off;                  /* 1 if the search fell back to rollouts */
+    /* where the threads' time went, summed over threads (seconds): descents
+       (Eq. 7-9), expansions (launch and wait, or the batcher's round trip),
+       attaching children and backups (Eq. 4) */
+    double time_select_s, time_expand_s, time_backup_s;
 } hdx_search_result;
 
 hdx_status hdx_search(hdx_ctx *ctx, const hdx_model *model, const hdx_belief *belief,

@@ -305,8 +305,9 @@ hipError_t launch_classes(const LeafTask *d_tasks, const Tile *d_tiles, TileQueu
 Schedule class_default_schedule(int32_t n_max, int32_t max_threads, int32_t mode = -1);
 hipError_t configure_expand_kernels();
 
-// Up to kArgLeaves leaves passed by value in the kernel arguments.
-constexpr int kArgLeaves = 4;
+// Up to kArgLeaves leaves passed by value in the kernel arguments (the
+// pack stays under the 4 KB kernel-argument limit).
+constexpr int kArgLeaves = 11;
 struct ArgPack {
     LeafTask t[kArgLeaves];
     int32_t tile_begin[kArgLeaves + 1];

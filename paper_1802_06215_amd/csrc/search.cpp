@@ -1,5 +1,7 @@
 // Parallel DESPOT search on the CPU feeding leaf expansion to the GPU
-// (HyP-DESPOT, Sec. III-A and III-C).  Several host threads share one tree:
+// (HyP-DESPOT, Sec. III-A and III-C).  Several host threads share one tree
+// without a tree-wide lock (descents read bounds as they stand, a leaf is
+// claimed by an atomic state change, each backup step locks one node):
 // each trial walks down by the scenario-based PO-UCT action bound (Eq. 8)
 // and the weighted excess uncertainty with virtual loss (Eq. 7, 9), expands
 // the leaf it reaches through hdx_expand_leaf (Eq. 10-13), attaches the
@@ -81,52 +83,103 @@ struct Rec {
     int n = 0;
 };
 
+// One belief node.  The fields above `u` are written once, before the node
+// is published (its parent's state becomes 2 with a release store), and
+// read freely afterwards.  u and l, and the sums of the node's actions, are
+// recomputed under the node's own lock (`lock`) and read without it; a
+// reader sees the old or the new value of each.
 struct Node {
     int32_t parent = -1;
     int32_t action = -1;  // action from the parent
     int32_t n = 0;        // |Phi_b|
     int32_t depth = 0;
-    double u = 0.0, l = 0.0;
-    int32_t parent_rec = -1;          // record holding the parent's states
+    int32_t parent_rec = -1;           // record holding the parent's states
     const int16_t *idx_dev = nullptr;  // positions in that record
-    int32_t state = 0;                // 0 leaf, 1 being expanded, 2 expanded
-    int32_t visits = 0, vloss = 0;
-    int32_t act_begin = -1;
-    int32_t rec = -1;
+    int32_t act_begin = -1;            // set by the expanding thread before state becomes 2
+    int32_t rec = -1;                  // likewise
+    std::atomic<double> u{0.0}, l{0.0};
+    std::atomic<int32_t> state{0};  // 0 leaf, 1 being expanded, 2 expanded
+    std::atomic<int32_t> visits{0}, vloss{0};
+    std::atomic<int32_t> lock{0};
 };
 
-// Append-only store in chunks of 2^16 elements: growth never moves an
-// element (a 625-action tree adds ~20 M nodes a second, and a vector's
-// doubling copies stalled every thread behind the tree lock), and an index
-// costs one shift and one mask.  Guarded by the tree lock like the tree.
+// Append-only store with concurrent appends: a fixed table of chunk
+// pointers (2^16 elements a chunk), ranges reserved by an atomic counter,
+// a chunk allocated by the first thread that reserves into it.  Growth
+// never moves an element, and an index handed over through a release /
+// acquire pair (a node's state) is safe to dereference on the other side.
 template <class T>
 struct ChunkStore {
     static constexpr int kShift = 16;
     static constexpr size_t kMask = (size_t(1) << kShift) - 1;
-    std::vector<std::unique_ptr<T[]>> chunks;
-    size_t n = 0;
-    T &operator[](size_t i) { return chunks[i >> kShift][i & kMask]; }
-    const T &operator[](size_t i) const { return chunks[i >> kShift][i & kMask]; }
-    size_t size() const { return n; }
-    void push_back(const T &v) {
-        if ((n >> kShift) == chunks.size()) chunks.emplace_back(new T[size_t(1) << kShift]);
-        (*this)[n++] = v;
+    static constexpr size_t kMaxChunks = size_t(1) << 14;  // 2^30 elements
+    static constexpr size_t kCapacity = kMaxChunks << kShift;
+    std::unique_ptr<std::atomic<T *>[]> table;
+    std::atomic<size_t> n{0};
+    std::mutex grow;
+    ChunkStore() : table(new std::atomic<T *>[kMaxChunks]) {
+        for (size_t c = 0; c < kMaxChunks; ++c) table[c].store(nullptr, std::memory_order_relaxed);
+    }
+    ~ChunkStore() {
+        for (size_t c = 0; c < kMaxChunks; ++c) delete[] table[c].load(std::memory_order_relaxed);
+    }
+    T &operator[](size_t i) { return table[i >> kShift].load(std::memory_order_relaxed)[i & kMask]; }
+    const T &operator[](size_t i) const { return table[i >> kShift].load(std::memory_order_relaxed)[i & kMask]; }
+    size_t size() const { return std::min(n.load(), kCapacity); }
+    // `count` (> 0) consecutive new elements; the first index, or
+    // kCapacity when the store is full
+    size_t reserve(size_t count) {
+        const size_t at = n.fetch_add(count);
+        if (at + count > kCapacity) return kCapacity;
+        for (size_t c = at >> kShift; c <= (at + count - 1) >> kShift; ++c) {
+            if (table[c].load(std::memory_order_acquire)) continue;
+            std::lock_guard<std::mutex> g(grow);
+            if (!table[c].load(std::memory_order_relaxed))
+                table[c].store(new T[size_t(1) << kShift](), std::memory_order_release);
+        }
+        return at;
     }
 };
 
 struct Act {
-    double r;
-    int32_t child_begin, n_children, visits;
+    double r = 0.0;
+    int32_t child_begin = 0, n_children = 0;
+    std::atomic<int32_t> visits{0};
     // sum over the children of n_child / n_parent times their u and l, in
     // child order; recomputed whenever a child's bounds change, so Eq. 4 and
     // Eq. 8 read one value per action instead of visiting every child
-    double su = 0.0, sl = 0.0;
+    std::atomic<double> su{0.0}, sl{0.0};
 };
 
+template <class T>
+T ld(const std::atomic<T> &x) {
+    return x.load(std::memory_order_relaxed);
+}
+template <class T>
+void put(std::atomic<T> &x, T v) {
+    x.store(v, std::memory_order_relaxed);
+}
+
+// Per-node spin lock, held for a few dozen operations at a time.
+void node_lock(Node &b) {
+    int spins = 0;
+    while (b.lock.exchange(1, std::memory_order_acquire)) {
+        while (b.lock.load(std::memory_order_relaxed)) {
+            if (++spins > 256) {
+                std::this_thread::yield();
+                spins = 0;
+            }
+        }
+    }
+}
+void node_unlock(Node &b) { b.lock.store(0, std::memory_order_release); }
+
+// A leaf handed to the batchers; its thread sleeps on `cv` until a batcher
+// sets `done` (under `m`, so the request outlives the notification).
 struct Request {
     hdx_leaf leaf;
-    const Rec *rec;
-    char *head_host;
+    std::mutex m;
+    std::condition_variable cv;
     bool done = false;
     hdx_status status = HDX_OK;
 };
@@ -205,10 +258,9 @@ struct Search {
     char *arena = nullptr;
     std::atomic<int64_t> arena_used{0};
     std::atomic<int> arena_full{0};
-    std::mutex mu;  // tree
     ChunkStore<Node> nodes;
     ChunkStore<Act> acts;
-    std::deque<Rec> recs;  // stable addresses
+    ChunkStore<Rec> recs;
     std::atomic<int64_t> trials{0}, expansions{0}, steps{0}, launches{0};
     std::atomic<int> max_depth{0};
     std::atomic<bool> stop{false};
@@ -220,9 +272,10 @@ struct Search {
     double j_err = 0.0, j_ref = 0.0;
     int64_t j_leaves = 0, j_children = 0;
     double c_a_abs = 0.0;  // c_a scaled by the initial root gap
-    std::mutex emu;
+    std::mutex emu;        // error state and the time breakdown
     hdx_status error = HDX_OK;
     std::string error_msg;
+    double t_select = 0.0, t_expand = 0.0, t_backup = 0.0;  // thread-seconds
     Clock::time_point t0;
 
     void fail(hdx_status st, const char *where) {
@@ -233,9 +286,9 @@ struct Search {
         }
         stop = true;
     }
-    // batcher
+    // batchers: pending leaves, taken by whichever batcher is free
     std::mutex qmu;
-    std::condition_variable qcv, dcv;
+    std::condition_variable qcv;
     std::deque<Request *> queue;
     bool batcher_exit = false;
 
@@ -254,51 +307,61 @@ struct Search {
         return true;
     }
 
-    double root_gap() const { return std::max(nodes[0].u - nodes[0].l, 0.0); }
+    double root_gap() { return std::max(ld(nodes[0].u) - ld(nodes[0].l), 0.0); }
 
-    // The weighted child sums of one action (the inner sums of Eq. 4).
+    // The weighted child sums of one action (the inner sums of Eq. 4); the
+    // caller holds the lock of the node the action belongs to.
     void refresh(Act &x, int32_t parent_n) {
         double su = 0.0, sl = 0.0;
         for (int c = 0; c < x.n_children; ++c) {
             const Node &k = nodes[x.child_begin + c];
             const double w = (double)k.n / (double)parent_n;
-            su += w * k.u;
-            sl += w * k.l;
+            su += w * ld(k.u);
+            sl += w * ld(k.l);
         }
-        x.su = su;
-        x.sl = sl;
+        put(x.su, su);
+        put(x.sl, sl);
     }
 
-    // Eq. 4 for one expanded node; its new bounds go into its parent
-    // action's sums
+    // Eq. 4 for one expanded node under its lock; then its new bounds go
+    // into its parent action's sums under the parent's lock.  One lock at a
+    // time: the thread that stores a node's last value refreshes the
+    // parent after it, so once every backup has ended each node agrees with
+    // its children.
     void bellman(Node &b) {
+        node_lock(b);
         double bu = -std::numeric_limits<double>::infinity(), bl = bu;
         for (int a = 0; a < A; ++a) {
             const Act &x = acts[b.act_begin + a];
-            bu = std::max(bu, x.r + d.gamma * x.su);
-            bl = std::max(bl, x.r + d.gamma * x.sl);
+            bu = std::max(bu, x.r + d.gamma * ld(x.su));
+            bl = std::max(bl, x.r + d.gamma * ld(x.sl));
         }
-        b.u = bu;
-        b.l = bl;
+        put(b.u, bu);
+        put(b.l, bl);
+        node_unlock(b);
         if (b.parent >= 0) {
-            const Node &p = nodes[b.parent];
+            Node &p = nodes[b.parent];
+            node_lock(p);
             refresh(acts[p.act_begin + b.action], p.n);
+            node_unlock(p);
         }
     }
 
     // Action bound of Eq. 8: u(b,a) plus the scenario-based exploration bonus
-    int choose_action(const Node &b) const {
+    int choose_action(const Node &b) {
         int best = 0;
         double best_v = -std::numeric_limits<double>::infinity();
-        const double nb = (double)b.n * (double)std::max(b.visits, 1);
+        const double nb = (double)b.n * (double)std::max(ld(b.visits), 1);
+        const double log_nb = c_a_abs > 0.0 ? log(nb) : 0.0;
         for (int a = 0; a < A; ++a) {
             const Act &x = acts[b.act_begin + a];
-            double v = x.r + d.gamma * x.su;
+            double v = x.r + d.gamma * ld(x.su);
             if (c_a_abs > 0.0) {
-                if (x.visits == 0) {
+                const int32_t xv = ld(x.visits);
+                if (xv == 0) {
                     v = std::numeric_limits<double>::infinity();
                 } else {
-                    v += c_a_abs * sqrt(log(nb) / ((double)b.n * (double)x.visits));
+                    v += c_a_abs * sqrt(log_nb / ((double)b.n * (double)xv));
                 }
             }
             if (v > best_v) {
@@ -313,8 +376,13 @@ struct Search {
     void judge_leaf(const hdx_leaf &L0, const Rec &r, const char *head_host, Judge &J, hipStream_t stream);
     bool use_surrogate() const { return cfg.surrogate != nullptr && !surrogate_off.load(); }
 
-    void attach(int node_id, const Rec &r, const char *head) {
+    // The children of an expanded node (Eq. 11) from its head block: the
+    // node's actions and children are filled in new ranges of the stores,
+    // then published by the release store of state 2.  False when a store
+    // is full.
+    bool attach(int node_id, const char *head) {
         Node &b = nodes[node_id];
+        const Rec &r = recs[b.rec];
         const int cap = cap_for(b.n);
         const int32_t *nch = (const int32_t *)(head + r.L.n_children);
         const float *rm = (const float *)(head + r.L.r_mean);
@@ -323,35 +391,44 @@ struct Search {
         const int32_t *co = (const int32_t *)(head + r.L.child_off);
         const float *cu = (const float *)(head + r.L.child_u0);
         const float *cl = (const float *)(head + r.L.child_l0);
-        int64_t s = 0;
-        for (int a = 0; a < A; ++a) s += st[2 * a] + st[2 * a + 1];
-        steps += s;
-        const int32_t rec_index = b.rec;
-        const int parent_depth = b.depth;
-        const int parent_n = b.n;
-        nodes[node_id].act_begin = (int32_t)acts.size();
+        int64_t s = 0, total = 0;
         for (int a = 0; a < A; ++a) {
-            const size_t ai = acts.size();
-            acts.push_back(Act{(double)rm[a], (int32_t)nodes.size(), nch[a], 0});
+            s += st[2 * a] + st[2 * a + 1];
+            total += nch[a];
+        }
+        const size_t ab = acts.reserve((size_t)A);
+        const size_t cb = total > 0 ? nodes.reserve((size_t)total) : nodes.size();
+        if (ab >= acts.kCapacity || cb >= nodes.kCapacity) {
+            arena_full = 1;
+            return false;
+        }
+        steps += s;
+        size_t c_at = cb;
+        for (int a = 0; a < A; ++a) {
+            Act &x = acts[ab + a];
+            x.r = (double)rm[a];
+            x.child_begin = (int32_t)c_at;
+            x.n_children = nch[a];
             for (int c = 0; c < nch[a]; ++c) {
-                Node k;
+                Node &k = nodes[c_at++];
                 k.parent = node_id;
                 k.action = a;
                 k.n = cn[a * cap + c];
-                k.depth = parent_depth + 1;
-                k.u = cu[a * cap + c];
-                k.l = cl[a * cap + c];
-                k.parent_rec = rec_index;
-                k.idx_dev = (const int16_t *)(r.dev + r.L.perm) + (size_t)a * parent_n + co[a * cap + c];
-                nodes.push_back(k);
+                k.depth = b.depth + 1;
+                put(k.u, (double)cu[a * cap + c]);
+                put(k.l, (double)cl[a * cap + c]);
+                k.parent_rec = b.rec;
+                k.idx_dev = (const int16_t *)(r.dev + r.L.perm) + (size_t)a * b.n + co[a * cap + c];
             }
-            refresh(acts[ai], parent_n);
+            refresh(x, b.n);
         }
-        nodes[node_id].state = 2;
-        int md = parent_depth + 1;
+        b.act_begin = (int32_t)ab;
+        b.state.store(2, std::memory_order_release);
+        int md = b.depth + 1;
         int cur = max_depth.load();
         while (md > cur && !max_depth.compare_exchange_weak(cur, md)) {
         }
+        return true;
     }
 };
 
@@ -403,27 +480,25 @@ void Search::judge_leaf(const hdx_leaf &L0, const Rec &r, const char *head_host,
 
 bool Search::expand(int node_id, hipStream_t stream, const HeadBuf &hb, Judge *J) {
     char *head_host = hb.host;
-    // builds the leaf descriptor; the caller holds no lock
-    Node b;
-    {
-        std::lock_guard<std::mutex> g(mu);
-        b = nodes[node_id];
-    }
+    Node &b = nodes[node_id];
     Rec r;
     if (!alloc_rec(b.n, &r)) return false;
-    const Rec *parent = nullptr;
-    {
-        std::lock_guard<std::mutex> g(mu);
-        parent = &recs[b.parent_rec];
+    const size_t ri = recs.reserve(1);
+    if (ri >= recs.kCapacity) {
+        arena_full = 1;
+        return false;
     }
+    recs[ri] = r;
+    b.rec = (int32_t)ri;
+    const Rec &parent = recs[b.parent_rec];
     hdx_leaf L;
     memset(&L, 0, sizeof(L));
     L.model = model;
     L.seed = cfg.seed;
     L.step = cfg.step;
     L.rollout = cfg.rollout;
-    L.parent = rec_states(d, *parent);
-    L.parent_ids = (const uint32_t *)(parent->dev + parent->L.ids);
+    L.parent = rec_states(d, parent);
+    L.parent_ids = (const uint32_t *)(parent.dev + parent.L.ids);
     L.idx = b.idx_dev;
     L.n = b.n;
     L.depth = b.depth;
@@ -437,21 +512,14 @@ bool Search::expand(int node_id, hipStream_t stream, const HeadBuf &hb, Judge *J
     if (cfg.batch_leaves > 1 && !judge) {
         Request q;
         q.leaf = L;
-        q.rec = nullptr;
-        q.head_host = head_host;
-        Rec *rp = nullptr;
         {
-            std::lock_guard<std::mutex> g(mu);
-            recs.push_back(r);
-            rp = &recs.back();
-            nodes[node_id].rec = (int32_t)recs.size() - 1;
-        }
-        q.rec = rp;
-        {
-            std::unique_lock<std::mutex> lk(qmu);
+            std::lock_guard<std::mutex> lk(qmu);
             queue.push_back(&q);
-            qcv.notify_one();
-            dcv.wait(lk, [&] { return q.done; });
+        }
+        qcv.notify_one();
+        {
+            std::unique_lock<std::mutex> lk(q.m);
+            q.cv.wait(lk, [&] { return q.done; });
         }
         st = q.status;
     } else {
@@ -474,25 +542,28 @@ bool Search::expand(int node_id, hipStream_t stream, const HeadBuf &hb, Judge *J
             if (st == HDX_OK && judge) judge_leaf(L, r, head_host, *J, stream);
         }
         launches++;
-        std::lock_guard<std::mutex> g(mu);
-        recs.push_back(r);
-        nodes[node_id].rec = (int32_t)recs.size() - 1;
     }
-    if (st != HDX_OK) return false;
-    expansions++;
-    std::lock_guard<std::mutex> g(mu);
-    attach(node_id, recs[nodes[node_id].rec], head_host);
-    return true;
+    return st == HDX_OK;
 }
 
-void batcher_loop(Search *S, hipStream_t stream) {
+// One batcher: takes up to batch_leaves pending leaves, launches them in
+// packs of at most kArgLeaves (descriptors in the kernel arguments, no
+// staging copies) on its own stream, waits once for all of them (their head
+// blocks are mapped host memory) and wakes their threads.  Several batchers
+// keep several batches in flight.
+void batcher_loop(Search *S) {
+    hipStream_t stream = nullptr;
+    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) {
+        S->fail(HDX_E_DEVICE, "batcher stream");
+        stream = nullptr;
+    }
     std::vector<Request *> batch;
     std::vector<hdx_leaf> leaves;
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(S->qmu);
             S->qcv.wait(lk, [&] { return S->batcher_exit || !S->queue.empty(); });
-            if (S->queue.empty() && S->batcher_exit) return;
+            if (S->queue.empty() && S->batcher_exit) break;
             batch.clear();
             while (!S->queue.empty() && (int)batch.size() < S->cfg.batch_leaves) {
                 batch.push_back(S->queue.front());
@@ -501,23 +572,27 @@ void batcher_loop(Search *S, hipStream_t stream) {
         }
         leaves.clear();
         for (Request *q : batch) leaves.push_back(q->leaf);
-        const int32_t nl = (int32_t)leaves.size();
-        hdx_status st = S->use_surrogate() ? hdx_expand_leaf_surrogate(S->ctx, leaves.data(), nl, S->cfg.surrogate,
-                                                                     S->cfg.surrogate_horizon, stream)
-                                         : hdx_expand_leaf(S->ctx, leaves.data(), nl, stream);
-        if (st != HDX_OK) S->fail(st, "batched expand_leaf");
-        // every leaf's head block is mapped host memory: one wait delivers all
-        if (st == HDX_OK && hipStreamSynchronize(stream) != hipSuccess) st = HDX_E_DEVICE;
-        S->launches++;
-        {
-            std::lock_guard<std::mutex> lk(S->qmu);
-            for (Request *q : batch) {
-                q->status = st;
-                q->done = true;
-            }
+        hdx_status st = stream ? HDX_OK : HDX_E_DEVICE;
+        for (size_t i = 0; i < leaves.size() && st == HDX_OK; i += hdx::kArgLeaves) {
+            const int32_t nl = (int32_t)std::min(leaves.size() - i, (size_t)hdx::kArgLeaves);
+            st = S->use_surrogate() ? hdx_expand_leaf_surrogate(S->ctx, leaves.data() + i, nl, S->cfg.surrogate,
+                                                               S->cfg.surrogate_horizon, stream)
+                                    : hdx_expand_leaf(S->ctx, leaves.data() + i, nl, stream);
+            S->launches++;
         }
-        S->dcv.notify_all();
+        if (st != HDX_OK) S->fail(st, "batched expand_leaf");
+        if (st == HDX_OK && hipStreamSynchronize(stream) != hipSuccess) {
+            st = HDX_E_DEVICE;
+            S->fail(st, "batched expansion wait");
+        }
+        for (Request *q : batch) {
+            std::lock_guard<std::mutex> lk(q->m);
+            q->status = st;
+            q->done = true;
+            q->cv.notify_one();
+        }
     }
+    if (stream) hipStreamDestroy(stream);
 }
 
 void worker(Search *S, int tid, size_t head_bytes) {
@@ -536,77 +611,91 @@ void worker(Search *S, int tid, size_t head_bytes) {
         J = &judge;
     std::vector<int> path;
     const double K = (double)S->cfg.K;
+    double t_sel = 0.0, t_exp = 0.0, t_back = 0.0;
+    auto since = [](Clock::time_point t) { return std::chrono::duration<double>(Clock::now() - t).count(); };
     while (!S->stop.load()) {
-        const double elapsed = std::chrono::duration<double>(Clock::now() - S->t0).count();
+        const Clock::time_point ts = Clock::now();
+        const double elapsed = std::chrono::duration<double>(ts - S->t0).count();
         if (elapsed >= S->cfg.time_budget_s || S->arena_full.load()) break;
         if (S->cfg.max_trials > 0 && S->trials.load() >= S->cfg.max_trials) break;
+        const double eps0 = S->root_gap();
+        if (eps0 <= S->cfg.gap_epsilon) {
+            S->stop = true;
+            break;
+        }
+        // descend (Eq. 8 actions, Eq. 7 observation branches with the virtual
+        // loss of Eq. 9); a leaf is claimed by moving its state from 0 to 1
         int leaf = -1;
         path.clear();
-        {
-            std::lock_guard<std::mutex> g(S->mu);
-            if (S->root_gap() <= S->cfg.gap_epsilon) {
-                S->stop = true;
+        int b = 0;
+        path.push_back(0);
+        for (;;) {
+            Node &nb = S->nodes[b];
+            nb.visits.fetch_add(1, std::memory_order_relaxed);
+            const int32_t state = nb.state.load(std::memory_order_acquire);
+            if (state != 2) {
+                int32_t expect = 0;
+                if (state == 0 && nb.depth < S->cfg.max_depth && nb.n > 0 &&
+                    nb.state.compare_exchange_strong(expect, 1, std::memory_order_acq_rel))
+                    leaf = b;
                 break;
             }
-            const double eps0 = S->root_gap();
-            int b = 0;
-            path.push_back(0);
-            for (;;) {
-                Node &nb = S->nodes[b];
-                nb.visits++;
-                if (nb.state != 2) {
-                    if (nb.state == 0 && nb.depth < S->cfg.max_depth && nb.n > 0) {
-                        nb.state = 1;
-                        leaf = b;
-                    }
-                    break;
+            const int a = S->choose_action(nb);
+            Act &x = S->acts[nb.act_begin + a];
+            x.visits.fetch_add(1, std::memory_order_relaxed);
+            int best = -1;
+            double best_e = -std::numeric_limits<double>::infinity(), best_plain = 0.0;
+            for (int c = 0; c < x.n_children; ++c) {
+                const Node &k = S->nodes[x.child_begin + c];
+                const double e = (ld(k.u) - ld(k.l)) - (double)k.n / K * S->cfg.xi * eps0;
+                const double ep = e - (double)ld(k.vloss) * S->cfg.c_o * eps0;
+                if (ep > best_e) {
+                    best_e = ep;
+                    best = x.child_begin + c;
+                    best_plain = e;
                 }
-                const int a = S->choose_action(nb);
-                Act &x = S->acts[nb.act_begin + a];
-                x.visits++;
-                // Eq. 7 with the virtual loss of Eq. 9
-                int best = -1;
-                double best_e = -std::numeric_limits<double>::infinity(), best_plain = 0.0;
-                for (int c = 0; c < x.n_children; ++c) {
-                    const Node &k = S->nodes[x.child_begin + c];
-                    const double e = (k.u - k.l) - (double)k.n / K * S->cfg.xi * eps0;
-                    const double ep = e - (double)k.vloss * S->cfg.c_o * eps0;
-                    if (ep > best_e) {
-                        best_e = ep;
-                        best = x.child_begin + c;
-                        best_plain = e;
-                    }
-                }
-                if (best < 0 || best_plain <= 0.0) break;  // the path ends where E is not positive
-                S->nodes[best].vloss++;
-                b = best;
-                path.push_back(b);
             }
+            if (best < 0 || best_plain <= 0.0) break;  // the path ends where E is not positive
+            S->nodes[best].vloss.fetch_add(1, std::memory_order_relaxed);
+            b = best;
+            path.push_back(b);
         }
+        const Clock::time_point te = Clock::now();
+        t_sel += std::chrono::duration<double>(te - ts).count();
         bool ok = true;
         if (leaf >= 0) {
             ok = S->expand(leaf, stream, hb, J);
-            if (!ok) {
-                std::lock_guard<std::mutex> g(S->mu);
-                S->nodes[leaf].state = 0;
+            t_exp += since(te);
+            const Clock::time_point tb = Clock::now();
+            if (ok) ok = S->attach(leaf, hb.host);
+            if (ok) {
+                S->expansions++;
+            } else {
+                S->nodes[leaf].state.store(0, std::memory_order_release);
             }
+            t_back += since(tb);
         }
-        {
-            std::lock_guard<std::mutex> g(S->mu);
-            for (size_t i = path.size(); i-- > 0;) {
-                Node &nb = S->nodes[path[i]];
-                if (nb.state == 2) S->bellman(nb);
-                if (i > 0) nb.vloss--;
-            }
+        const Clock::time_point tb = Clock::now();
+        for (size_t i = path.size(); i-- > 0;) {
+            Node &nb = S->nodes[path[i]];
+            if (nb.state.load(std::memory_order_acquire) == 2) S->bellman(nb);
+            if (i > 0) nb.vloss.fetch_sub(1, std::memory_order_relaxed);
         }
+        t_back += since(tb);
         if (!ok) break;
         S->trials++;
         if (leaf < 0) {
-            // the path ended where the excess uncertainty is not positive:
-            // nothing was expanded; let the other threads take the lock
+            // the path ended where the excess uncertainty is not positive, or
+            // at a leaf another thread is expanding: nothing was expanded
             S->idle_trials++;
             std::this_thread::yield();
         }
+    }
+    {
+        std::lock_guard<std::mutex> g(S->emu);
+        S->t_select += t_sel;
+        S->t_expand += t_exp;
+        S->t_backup += t_back;
     }
     hb.release();
     judge.head.release();
@@ -684,37 +773,40 @@ extern "C" hdx_status hdx_search(hdx_ctx *ctx, const hdx_model *model, const hdx
         su += hU[k];
         sl += hL[k];
     }
-    S.recs.push_back(root_rec);
-    Node root;
+    S.recs[S.recs.reserve(1)] = root_rec;
+    Node &root = S.nodes[S.nodes.reserve(1)];
     root.n = cfg->K;
-    root.u = su / (double)K;
-    root.l = sl / (double)K;
+    put(root.u, su / (double)K);
+    put(root.l, sl / (double)K);
     root.parent_rec = 0;
     root.idx_dev = iota;
-    S.nodes.push_back(root);
-    out->u0_root = root.u;
-    out->l0_root = root.l;
-    S.c_a_abs = cfg->c_a * std::max(root.u - root.l, 0.0);
+    out->u0_root = ld(root.u);
+    out->l0_root = ld(root.l);
+    S.c_a_abs = cfg->c_a * std::max(out->u0_root - out->l0_root, 0.0);
 
     const RecLayout big = rec_layout(S.d, cfg->K, S.cap_for(cfg->K));
     S.t0 = Clock::now();
-    std::thread batcher;
-    if (cfg->batch_leaves > 1) batcher = std::thread(batcher_loop, &S, main_stream);
+    // one batcher per batch_leaves threads, at most eight
+    std::vector<std::thread> batchers;
+    if (cfg->batch_leaves > 1) {
+        const int nb = std::min(8, std::max(1, (cfg->n_threads + cfg->batch_leaves - 1) / cfg->batch_leaves));
+        for (int i = 0; i < nb; ++i) batchers.emplace_back(batcher_loop, &S);
+    }
     std::vector<std::thread> workers;
     for (int t = 0; t < cfg->n_threads; ++t) workers.emplace_back(worker, &S, t, big.head);
     for (auto &w : workers) w.join();
-    if (batcher.joinable()) {
+    if (!batchers.empty()) {
         {
             std::lock_guard<std::mutex> lk(S.qmu);
             S.batcher_exit = true;
         }
         S.qcv.notify_all();
-        batcher.join();
+        for (auto &b : batchers) b.join();
     }
     out->elapsed_s = std::chrono::duration<double>(Clock::now() - S.t0).count();
     const Node &r = S.nodes[0];
-    out->u_root = r.u;
-    out->l_root = r.l;
+    out->u_root = ld(r.u);
+    out->l_root = ld(r.l);
     out->trials = S.trials.load();
     out->idle_trials = S.idle_trials.load();
     out->expansions = S.expansions.load();
@@ -728,16 +820,19 @@ extern "C" hdx_status hdx_search(hdx_ctx *ctx, const hdx_model *model, const hdx
     out->judge_mae = S.j_children > 0 ? S.j_err / (double)S.j_children : 0.0;
     out->judge_rel_err = S.j_ref > 0.0 ? S.j_err / S.j_ref : 0.0;
     out->surrogate_off = S.surrogate_off.load() ? 1 : 0;
+    out->time_select_s = S.t_select;
+    out->time_expand_s = S.t_expand;
+    out->time_backup_s = S.t_backup;
     out->best_action = 0;
-    if (r.state == 2) {
+    if (ld(r.state) == 2) {
         double best = -std::numeric_limits<double>::infinity();
         for (int a = 0; a < A; ++a) {
             const Act &x = S.acts[r.act_begin + a];
             double sum_u = 0.0, sum_l = 0.0;
             for (int c = 0; c < x.n_children; ++c) {
                 const Node &k = S.nodes[x.child_begin + c];
-                sum_u += (double)k.n / (double)r.n * k.u;
-                sum_l += (double)k.n / (double)r.n * k.l;
+                sum_u += (double)k.n / (double)r.n * ld(k.u);
+                sum_l += (double)k.n / (double)r.n * ld(k.l);
             }
             out->action_u[a] = x.r + S.d.gamma * sum_u;
             out->action_l[a] = x.r + S.d.gamma * sum_l;

@@ -86,7 +86,8 @@ class SearchResult(C.Structure):
                 ("launches", C.c_int64), ("max_depth_reached", C.c_int32), ("arena_full", C.c_int32),
                 ("elapsed_s", C.c_double), ("action_l", C.c_double * MAX_ACTIONS), ("action_u", C.c_double * MAX_ACTIONS),
                 ("judged_leaves", C.c_int64), ("judged_children", C.c_int64), ("judge_mae", C.c_double),
-                ("judge_rel_err", C.c_double), ("surrogate_off", C.c_int32)]
+                ("judge_rel_err", C.c_double), ("surrogate_off", C.c_int32),
+                ("time_select_s", C.c_double), ("time_expand_s", C.c_double), ("time_backup_s", C.c_double)]
 
 
 class Leaf(C.Structure):

@@ -262,7 +262,7 @@ def test_mixed_batches_match_single_leaves_and_oracle(ctx):
         compare_leaf(desc, collect(it["m"], it["out"]), want, len(lf["idx"]))
 
 
-@pytest.mark.parametrize("threads,batch,K", [(1, 0, 500), (8, 8, 2000), (8, 8, 5000)])
+@pytest.mark.parametrize("threads,batch,K", [(1, 0, 500), (8, 8, 2000), (32, 16, 5000)])
 def test_nav_search(ctx, threads, batch, K):
     from paper_1802_06215_amd import hdx as H
     desc = W.nav_model(1)
@@ -275,6 +275,7 @@ def test_nav_search(ctx, threads, batch, K):
     tol = 1e-4 * max(1.0, abs(res["u0_root"]))
     assert res["l0_root"] - tol <= res["l_root"] <= res["u_root"] + tol <= res["u0_root"] + 2 * tol
     assert res["best_action"] == int(np.argmax(res["action_l"]))
+    assert max(res["action_l"]) == res["l_root"] and max(res["action_u"]) == res["u_root"]
 
 
 def test_upload_rejects_bad_maps(ctx):

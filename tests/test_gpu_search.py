@@ -6,7 +6,10 @@
 * Bounds: the upper-bound heuristic is consistent and the rollouts share the
   scenarios' random numbers with the expansion, so backed-up bounds stay
   inside the initial ones: l0 <= l <= u <= u0 at the root (up to FP32).
-* Threads and the leaf batcher run to completion and expand leaves.
+* Threads and the leaf batchers run to completion and expand leaves.  The
+  tree has no tree-wide lock; once the threads have ended every node must
+  agree with its children, so the root's bounds equal the best of its
+  action bounds recomputed from its children, bit for bit.
 * Anytime: a zero budget returns the initial bounds; a full device arena
   stops the search cleanly.
 * One thread without exploration bonuses builds the host DESPOT loop's tree
@@ -43,7 +46,7 @@ def test_no_rocks_search_finds_exit_value(ctx):
     assert res["expansions"] >= 5
 
 
-@pytest.mark.parametrize("threads,batch", [(1, 0), (4, 0), (8, 0), (8, 8), (16, 16)])
+@pytest.mark.parametrize("threads,batch", [(1, 0), (4, 0), (8, 0), (16, 0), (8, 8), (16, 16), (33, 11), (48, 16)])
 def test_rs15_search_bounds(ctx, threads, batch):
     from paper_1802_06215_amd import hdx as H
     desc = W.rocksample_model(15, 15, 1)
@@ -58,6 +61,7 @@ def test_rs15_search_bounds(ctx, threads, batch):
     assert res["l0_root"] - tol <= res["l_root"] <= res["u_root"] + tol <= res["u0_root"] + 2 * tol
     assert 0 <= res["best_action"] < desc["n_actions"]
     assert res["best_action"] == int(np.argmax(res["action_l"]))
+    assert max(res["action_l"]) == res["l_root"] and max(res["action_u"]) == res["u_root"]
     if batch:
         assert res["launches"] <= res["expansions"]
 
