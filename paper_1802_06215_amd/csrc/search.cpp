@@ -10,7 +10,9 @@
 // parent's grouped order, and its own states are materialised when it is
 // expanded.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
+#include <sys/mman.h>
 
 #include <algorithm>
 #include <atomic>
@@ -20,8 +22,10 @@
 #include <limits>
 #include <memory>
 #include <mutex>
+#include <new>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "internal.hpp"
@@ -101,6 +105,10 @@ struct Node {
     std::atomic<int32_t> state{0};  // 0 leaf, 1 being expanded, 2 expanded
     std::atomic<int32_t> visits{0}, vloss{0};
     std::atomic<int32_t> lock{0};
+    Node(int32_t parent_, int32_t action_, int32_t n_, int32_t depth_, int32_t parent_rec_, const int16_t *idx_,
+         double u_, double l_)
+        : parent(parent_), action(action_), n(n_), depth(depth_), parent_rec(parent_rec_), idx_dev(idx_), u(u_),
+          l(l_) {}
 };
 
 // Append-only store with concurrent appends: a fixed table of chunk
@@ -108,8 +116,14 @@ struct Node {
 // a chunk allocated by the first thread that reserves into it.  Growth
 // never moves an element, and an index handed over through a release /
 // acquire pair (a node's state) is safe to dereference on the other side.
+// Chunks are raw memory (2 MB aligned, transparent huge pages asked for):
+// the thread that reserves a range constructs its elements in place, so
+// creating a node is one pass of stores (a large tree adds tens of
+// millions of nodes a second).
 template <class T>
 struct ChunkStore {
+    static_assert(std::is_trivially_destructible<T>::value, "elements are never destroyed");
+    static constexpr size_t kAlign = size_t(2) << 20;
     static constexpr int kShift = 16;
     static constexpr size_t kMask = (size_t(1) << kShift) - 1;
     static constexpr size_t kMaxChunks = size_t(1) << 14;  // 2^30 elements
@@ -121,21 +135,25 @@ struct ChunkStore {
         for (size_t c = 0; c < kMaxChunks; ++c) table[c].store(nullptr, std::memory_order_relaxed);
     }
     ~ChunkStore() {
-        for (size_t c = 0; c < kMaxChunks; ++c) delete[] table[c].load(std::memory_order_relaxed);
+        for (size_t c = 0; c < kMaxChunks; ++c) free(table[c].load(std::memory_order_relaxed));
     }
     T &operator[](size_t i) { return table[i >> kShift].load(std::memory_order_relaxed)[i & kMask]; }
     const T &operator[](size_t i) const { return table[i >> kShift].load(std::memory_order_relaxed)[i & kMask]; }
     size_t size() const { return std::min(n.load(), kCapacity); }
-    // `count` (> 0) consecutive new elements; the first index, or
-    // kCapacity when the store is full
+    // `count` (> 0) consecutive unconstructed elements; the first index, or
+    // kCapacity when the store is full or out of memory
     size_t reserve(size_t count) {
         const size_t at = n.fetch_add(count);
         if (at + count > kCapacity) return kCapacity;
         for (size_t c = at >> kShift; c <= (at + count - 1) >> kShift; ++c) {
             if (table[c].load(std::memory_order_acquire)) continue;
             std::lock_guard<std::mutex> g(grow);
-            if (!table[c].load(std::memory_order_relaxed))
-                table[c].store(new T[size_t(1) << kShift](), std::memory_order_release);
+            if (table[c].load(std::memory_order_relaxed)) continue;
+            const size_t bytes = ((sizeof(T) << kShift) + kAlign - 1) / kAlign * kAlign;
+            void *p = aligned_alloc(kAlign, bytes);
+            if (!p) return kCapacity;
+            madvise(p, bytes, MADV_HUGEPAGE);  // advice only: its failure changes nothing
+            table[c].store((T *)p, std::memory_order_release);
         }
         return at;
     }
@@ -145,6 +163,8 @@ struct Act {
     double r = 0.0;
     int32_t child_begin = 0, n_children = 0;
     std::atomic<int32_t> visits{0};
+    Act(double r_, int32_t child_begin_, int32_t n_children_)
+        : r(r_), child_begin(child_begin_), n_children(n_children_) {}
     // sum over the children of n_child / n_parent times their u and l, in
     // child order; recomputed whenever a child's bounds change, so Eq. 4 and
     // Eq. 8 read one value per action instead of visiting every child
@@ -404,21 +424,13 @@ struct Search {
         }
         steps += s;
         size_t c_at = cb;
+        const int16_t *perm = (const int16_t *)(r.dev + r.L.perm);
         for (int a = 0; a < A; ++a) {
-            Act &x = acts[ab + a];
-            x.r = (double)rm[a];
-            x.child_begin = (int32_t)c_at;
-            x.n_children = nch[a];
+            Act &x = *new (&acts[ab + a]) Act((double)rm[a], (int32_t)c_at, nch[a]);
             for (int c = 0; c < nch[a]; ++c) {
-                Node &k = nodes[c_at++];
-                k.parent = node_id;
-                k.action = a;
-                k.n = cn[a * cap + c];
-                k.depth = b.depth + 1;
-                put(k.u, (double)cu[a * cap + c]);
-                put(k.l, (double)cl[a * cap + c]);
-                k.parent_rec = b.rec;
-                k.idx_dev = (const int16_t *)(r.dev + r.L.perm) + (size_t)a * b.n + co[a * cap + c];
+                const int q = a * cap + c;
+                new (&nodes[c_at++]) Node(node_id, a, cn[q], b.depth + 1, b.rec, perm + (size_t)a * b.n + co[q],
+                                          (double)cu[q], (double)cl[q]);
             }
             refresh(x, b.n);
         }
@@ -488,7 +500,7 @@ bool Search::expand(int node_id, hipStream_t stream, const HeadBuf &hb, Judge *J
         arena_full = 1;
         return false;
     }
-    recs[ri] = r;
+    new (&recs[ri]) Rec(r);
     b.rec = (int32_t)ri;
     const Rec &parent = recs[b.parent_rec];
     hdx_leaf L;
@@ -773,13 +785,14 @@ extern "C" hdx_status hdx_search(hdx_ctx *ctx, const hdx_model *model, const hdx
         su += hU[k];
         sl += hL[k];
     }
-    S.recs[S.recs.reserve(1)] = root_rec;
-    Node &root = S.nodes[S.nodes.reserve(1)];
-    root.n = cfg->K;
-    put(root.u, su / (double)K);
-    put(root.l, sl / (double)K);
-    root.parent_rec = 0;
-    root.idx_dev = iota;
+    const size_t root_at = S.nodes.reserve(1), rec_at = S.recs.reserve(1);
+    if (root_at != 0 || rec_at != 0) {
+        hipStreamDestroy(main_stream);
+        hipFree(S.arena);
+        return HDX_E_NOMEM;
+    }
+    new (&S.recs[0]) Rec(root_rec);
+    const Node &root = *new (&S.nodes[0]) Node(-1, -1, cfg->K, 0, 0, iota, su / (double)K, sl / (double)K);
     out->u0_root = ld(root.u);
     out->l0_root = ld(root.l);
     S.c_a_abs = cfg->c_a * std::max(out->u0_root - out->l0_root, 0.0);
