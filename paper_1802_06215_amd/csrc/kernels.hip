@@ -173,9 +173,10 @@ __device__ void block_exclusive_scan(int32_t *a, int len, int32_t *scratch) {
 __device__ __forceinline__ bool has_states(const StatesPtr &S) { return S.w != nullptr || S.s != nullptr; }
 
 // One (leaf, action) tile.
-// kGroup: compile the element-level rollout of small leaves in (the
-// few-leaf launch a search thread makes; the batched launch leaves it out,
-// since its registers would cost the driving model a wavefront per SIMD).
+// kGroup: compile the element-level expansion of small leaves in (the
+// kernel-argument launches of the search threads and batchers; the staged
+// batched launch leaves it out, since its registers would cost the driving
+// model a wavefront per SIMD).
 template <class Ops, bool kGroup = false>
 __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char *lds, const LdsLayout &Ly) {
     float *gpow_lds = (float *)(lds + Ly.gpow);
@@ -238,7 +239,7 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
     const StatesPtr sprime = load_states(&T->sprime);
     const bool write_leaf = (a == 0);
     const bool pair_out = has_states(sprime);
-    // element-level rollouts when the leaf is small enough for every
+    // element-level expansion when the leaf is small enough for every
     // scenario to get a group of lanes of wavefront 0 (tile-uniform)
     int group_lanes = 0;
     if constexpr (Ops::kGroupRollout && kGroup) {
@@ -277,32 +278,46 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
             Ops::template step<true>(M, st, a, id, (uint32_t)depth, RP.k0, RP.k1, r, z);
         };
         float U = 0.0f;
-        if constexpr (Ops::kWaveUpper) {
-            // every lane of the wavefront takes part in the bound (it shares
-            // per-rock terms across lanes); lanes past n stay terminal
-            Ops::make_terminal(st);
-            if (valid) expand_one();
-            U = Ops::upper_wave(M, st, wave_upper);
-        } else if (valid) {
-            expand_one();
-            U = Ops::upper(M, st);
-        }
         float L = 0.0f;
-        bool rolled = false;
+        bool grouped = false;
         if constexpr (Ops::kGroupRollout && kGroup) {
             if (group_lanes > 0) {
-                // n <= 64: one round, every scenario in wavefront 0; the
-                // stepped state is stored first (the rollout works on a copy)
-                if (valid && pair_out) Ops::store(M, sprime, (int64_t)a * n + k, st);
-                int ns = 0;
-                if (wid == 0) L = Ops::group_rollout(M, RP, st, id, depth + 1, n, group_lanes, ns);
-                if (valid) my_roll += ns;
-                rolled = true;
+                // n * G <= 64: one round; wavefront 0 expands the leaf with
+                // one pedestrian per lane (leaf and stepped states stored
+                // inside) and lane k receives scenario k's results
+                grouped = true;
+                if (wid == 0) {
+                    const typename Ops::GroupOut o =
+                        Ops::group_expand(M, RP, T->idx, T->parent_ids, parent, leaf_out, T->ids_out, sprime,
+                                          write_leaf, pair_out, a, depth, last_action, n, group_lanes);
+                    if (valid) {
+                        r = o.r;
+                        z = o.z;
+                        U = o.U;
+                        L = o.L;
+                        id = o.id;
+                        my_exp += o.expanded;
+                        my_roll += o.steps;
+                    }
+                }
+            }
+        }
+        if (!grouped) {
+            if constexpr (Ops::kWaveUpper) {
+                // every lane of the wavefront takes part in the bound (it
+                // shares per-rock terms across lanes); lanes past n stay
+                // terminal
+                Ops::make_terminal(st);
+                if (valid) expand_one();
+                U = Ops::upper_wave(M, st, wave_upper);
+            } else if (valid) {
+                expand_one();
+                U = Ops::upper(M, st);
             }
         }
         if (valid) {
             const int64_t pk = (int64_t)a * n + k;
-            if (!rolled) {
+            if (!grouped) {
                 if (pair_out) Ops::store(M, sprime, pk, st);
                 int ns = 0;
                 L = rollout<Ops>(M, RP, st, id, depth + 1, ns);

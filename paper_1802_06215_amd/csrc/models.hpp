@@ -632,7 +632,7 @@ struct PedOps {
     static constexpr bool kSmallObs = false;      // 64-bit hashed observations
     static constexpr bool kLdsModel = true;       // discount powers and goal points staged in LDS
     static constexpr bool kWaveUpper = false;     // per-lane upper bound
-    static constexpr bool kGroupRollout = true;   // small leaves: one lane per pedestrian in rollouts
+    static constexpr bool kGroupRollout = true;   // small leaves: one lane per pedestrian (group_expand)
     struct WaveUpper {};
 
     // One pedestrian's walk towards its goal with heading noise from the
@@ -781,46 +781,91 @@ struct PedOps {
         return brake ? 2 : 0;
     }
 
-    // Element-level rollouts of a small leaf (Sec. III-D: the parallelism
-    // inside one step of a scenario): scenario g of the wavefront's first n
-    // lanes runs on lanes [g*G, g*G + G), lane g*G + j stepping pedestrian
-    // j; every lane of a group computes the car, the reward and the value,
-    // and collisions and the braking rule are ORs of the group's ballot
-    // bits.  The operations and their order are those of the one-lane
-    // rollout, so the results are the same bits.  Called by all 64 lanes of
-    // a wavefront (n * G <= 64, G a power of two >= the pedestrian count);
-    // lane k < n receives scenario k's value and step count.
-    __device__ static float group_rollout(const MView &M, const RolloutParams &P, const State &st, uint32_t id,
-                                          int d0, int n, int G, int &nsteps) {
+    // Element-level work on a small leaf (Sec. III-D: the parallelism inside
+    // one step of a scenario).  Scenario g of the wavefront's first n
+    // scenarios runs on lanes [g*G, g*G + G), lane g*G + j holding
+    // pedestrian j (G a power of two >= the pedestrian count, n * G <= 64);
+    // every lane of a group carries the car, the reward and the value;
+    // collisions and the braking rule are ORs of the group's ballot bits, and
+    // the observation hash is chained over the group's lanes in pedestrian
+    // order by shuffles.  The operations and their order are those of the
+    // one-lane step and rollout, so the results are the same bits.
+    struct Lanes {
+        int g, j;        // scenario of the group, pedestrian of the lane
+        bool active;     // g < n
+        bool ped;        // active and j < n_peds
+        uint64_t gmask;  // the group's lanes
+    };
+    __device__ static Lanes lanes(const MView &M, int n, int G) {
+        Lanes L;
         const int lane = (int)__lane_id();
-        const int g = lane / G, j = lane - g * G;
-        const bool active = g < n;
-        const int src = active ? g : 0;
-        float s = __shfl(st.s, src, 64);
-        int level = __shfl(st.level, src, 64);
-        int term = __shfl(st.term, src, 64);
-        const uint32_t sid = (uint32_t)__shfl((int)id, src, 64);
-        float px = 0.0f, py = 0.0f;
-        int goal = 0;
-#pragma unroll
-        for (int q = 0; q < PM; ++q) {
-            const float vx = __shfl(st.px[q], src, 64);
-            const float vy = __shfl(st.py[q], src, 64);
-            const int vg = __shfl(st.goal[q], src, 64);
-            if (j == q) {
-                px = vx;
-                py = vy;
-                goal = vg;
-            }
+        L.g = lane / G;
+        L.j = lane - L.g * G;
+        L.active = L.g < n;
+        L.ped = L.active && L.j < M.h->n_peds;
+        L.gmask = (G >= 64 ? ~0ull : ((1ull << G) - 1ull)) << (L.g * G);
+        return L;
+    }
+
+    // One step of one scenario spread over its group (PedOps::step).
+    template <bool kObs>
+    __device__ static void group_step(const MView &M, const Lanes &E, int G, int a, uint32_t id, uint32_t depth,
+                                      uint32_t k0, uint32_t k1, float &s, int &level, int &term, float &px,
+                                      float &py, int goal, float &r, uint64_t &z) {
+        r = 0.0f;
+        z = kObs ? kPedTerminalObs : 0;
+        if (term) return;  // group-uniform
+        const uint4 u0 = philox(id, depth, 0, kTagStep, k0, k1);
+        const bool failed = (uint64_t)u0.x < M.h->fail_thr;
+        if (a == 0 && !failed && level < M.h->n_levels - 1) level = level + 1;
+        if (a == 2 && !failed && level > 0) level = level - 1;
+        const float v = 0.5f * (float)level;
+        const float s_next = s + v * M.h->dt;
+        if (E.ped) {
+            const uint4 u = philox(id, depth, (uint32_t)(E.j + 1), kTagStep, k0, k1);
+            move_ped(M, u, goal, px, py);
         }
-        const bool ped = active && j < M.h->n_peds;
-        if (!active) term = 1;
-        const uint64_t gmask = (G >= 64 ? ~0ull : ((1ull << G) - 1ull)) << (g * G);
+        bool hit = false;
+        if (level > 0 && E.ped) {
+            const float ddx = px - s_next;
+            const float d2 = ddx * ddx + py * py;
+            hit = d2 < M.h->coll_r2;
+        }
+        const bool collided = (__ballot(hit) & E.gmask) != 0;
+        float reward = M.h->r_step;
+        if (collided) {
+            reward = M.h->r_step + M.h->r_collision;
+            term = 1;
+        } else if (s_next >= M.h->path_len) {
+            reward = M.h->r_step + M.h->r_goal;
+            term = 1;
+        }
+        s = s_next;
+        r = reward;
+        if (!kObs) return;
+        // the chained hash, in pedestrian order: every lane of the group
+        // walks the chain over its group's lanes
+        const int fx = (int32_t)floorf(px), fy = (int32_t)floorf(py);
+        uint64_t h = hash_field(0x243F6A8885A308D3ull, level);
+        const int base = E.g * G;
+        for (int q = 0; q < M.h->n_peds; ++q) {
+            const int qx = __shfl(fx, base + q, 64);
+            const int qy = __shfl(fy, base + q, 64);
+            h = hash_field(h, qx);
+            h = hash_field(h, qy);
+        }
+        if (!term) z = (h == kPedTerminalObs) ? kPedTerminalObs - 1 : h;
+    }
+
+    // The default-policy rollout of one scenario spread over its group,
+    // from the lanes' element state (rollout_loop's operations).
+    __device__ static float group_roll(const MView &M, const RolloutParams &P, const Lanes &E, float s, int level,
+                                       int term, uint32_t sid, float px, float py, int goal, int d0, int &steps) {
         int n_roll = P.max_steps;
         if (P.max_depth >= 0 && P.max_depth - d0 < n_roll) n_roll = P.max_depth - d0;
         if (n_roll > kHorizon) n_roll = kHorizon;
         float value = 0.0f;
-        int steps = 0;
+        steps = 0;
         for (int t = 0; t < n_roll; ++t) {
             if (term) break;
             const uint32_t depth = (uint32_t)(d0 + t);
@@ -831,8 +876,8 @@ struct PedOps {
                 a = (int)(philox(sid, depth, 0, kTagPolicy, P.k0, P.k1).x % (uint32_t)P.n_actions);
             } else {
                 const float ahead = px - s;
-                const bool b = ped && ahead >= 0.0f && ahead <= 3.0f && fabsf(py) < 1.5f;
-                a = (__ballot(b) & gmask) ? 2 : 0;
+                const bool b = E.ped && ahead >= 0.0f && ahead <= 3.0f && fabsf(py) < 1.5f;
+                a = (__ballot(b) & E.gmask) ? 2 : 0;
             }
             const uint4 u0 = philox(sid, depth, 0, kTagStep, P.k0, P.k1);
             const bool failed = (uint64_t)u0.x < M.h->fail_thr;
@@ -840,17 +885,17 @@ struct PedOps {
             if (a == 2 && !failed && level > 0) level = level - 1;
             const float v = 0.5f * (float)level;
             const float s_next = s + v * M.h->dt;
-            if (ped) {
-                const uint4 u = philox(sid, depth, (uint32_t)(j + 1), kTagStep, P.k0, P.k1);
+            if (E.ped) {
+                const uint4 u = philox(sid, depth, (uint32_t)(E.j + 1), kTagStep, P.k0, P.k1);
                 move_ped(M, u, goal, px, py);
             }
             bool hit = false;
-            if (level > 0 && ped) {
+            if (level > 0 && E.ped) {
                 const float ddx = px - s_next;
                 const float d2 = ddx * ddx + py * py;
                 hit = d2 < M.h->coll_r2;
             }
-            const bool collided = (__ballot(hit) & gmask) != 0;
+            const bool collided = (__ballot(hit) & E.gmask) != 0;
             float reward = M.h->r_step;
             if (collided) {
                 reward = M.h->r_step + M.h->r_collision;
@@ -863,9 +908,98 @@ struct PedOps {
             value += M.gpow_uniform(t) * reward;
             ++steps;
         }
-        const int from = (lane < n ? lane : 0) * G;
-        nsteps = __shfl(steps, from, 64);
-        return __shfl(value, from, 64);
+        return value;
+    }
+
+    // What one scenario of a small leaf yields in the element-level
+    // expansion; lane k < n holds scenario k's.
+    struct GroupOut {
+        float r, U, L;
+        uint64_t z;
+        uint32_t id;
+        int expanded, steps;
+    };
+
+    // Element-level expansion of a small leaf's tile: gather and update (the
+    // parent's last action), the step of action a with its observation, the
+    // upper bound and the rollout, all with one pedestrian per lane.  Leaf
+    // states (write_leaf) and stepped states (sprime) are stored by the
+    // owning lanes.  All 64 lanes of a wavefront call this.
+    __device__ static GroupOut group_expand(const MView &M, const RolloutParams &P, const int16_t *idx,
+                                            const uint32_t *parent_ids, const StatesPtr &parent,
+                                            const StatesPtr &leaf_out, uint32_t *ids_out, const StatesPtr &sprime,
+                                            bool write_leaf, bool pair_out, int a, int depth, int last_action, int n,
+                                            int G) {
+        const Lanes E = lanes(M, n, G);
+        float s = 0.0f, px = 0.0f, py = 0.0f;
+        int level = 0, term = 1, goal = 0;
+        uint32_t id = 0;
+        int p = 0;
+        if (E.active) {
+            p = idx[E.g];
+            id = parent_ids[p];
+            s = parent.s[p];
+            const int32_t car = parent.car[p];
+            level = car & 0xff;
+            term = (car >> 8) & 1;
+            if (E.ped) {
+                px = parent.px[E.j * parent.stride + p];
+                py = parent.py[E.j * parent.stride + p];
+                goal = parent.goal[E.j * parent.stride + p];
+            }
+        }
+        float r0;
+        uint64_t z0;
+        if (last_action >= 0)
+            group_step<false>(M, E, G, last_action, id, (uint32_t)(depth - 1), P.k0, P.k1, s, level, term, px, py,
+                              goal, r0, z0);
+        const int k = E.g;
+        if (write_leaf && E.active) {
+            if (E.j == 0) {
+                leaf_out.s[k] = s;
+                leaf_out.car[k] = (level & 0xff) | (term ? 0x100 : 0);
+                ids_out[k] = id;
+            }
+            if (E.ped) {
+                leaf_out.px[E.j * leaf_out.stride + k] = px;
+                leaf_out.py[E.j * leaf_out.stride + k] = py;
+                leaf_out.goal[E.j * leaf_out.stride + k] = (uint8_t)goal;
+            }
+        }
+        const int expanded = term ? 0 : 1;
+        float r;
+        uint64_t z;
+        group_step<true>(M, E, G, a, id, (uint32_t)depth, P.k0, P.k1, s, level, term, px, py, goal, r, z);
+        if (pair_out && E.active) {
+            const int64_t q = (int64_t)a * n + k;
+            if (E.j == 0) {
+                sprime.s[q] = s;
+                sprime.car[q] = (level & 0xff) | (term ? 0x100 : 0);
+            }
+            if (E.ped) {
+                sprime.px[E.j * sprime.stride + q] = px;
+                sprime.py[E.j * sprime.stride + q] = py;
+                sprime.goal[E.j * sprime.stride + q] = (uint8_t)goal;
+            }
+        }
+        State up;
+        up.s = s;
+        up.term = term;
+        const float U = upper(M, up);
+        int steps = 0;
+        const float L = group_roll(M, P, E, s, level, term, id, px, py, goal, depth + 1, steps);
+        // scenario k's results from its group's first lane to lane k
+        const int from = ((int)__lane_id() < n ? (int)__lane_id() : 0) * G;
+        GroupOut o;
+        o.r = __shfl(r, from, 64);
+        o.U = __shfl(U, from, 64);
+        o.L = __shfl(L, from, 64);
+        o.z = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(z >> 32), from, 64) << 32) |
+              (uint32_t)__shfl((int)(uint32_t)z, from, 64);
+        o.id = (uint32_t)__shfl((int)id, from, 64);
+        o.expanded = __shfl(expanded, from, 64);
+        o.steps = __shfl(steps, from, 64);
+        return o;
     }
 };
 

@@ -1,12 +1,15 @@
-"""Element-level rollouts of small driving leaves (one lane per pedestrian).
+"""Element-level expansion of small driving leaves (one lane per pedestrian).
 
 A one-leaf call launches through the kernel arguments; when every scenario
 of the leaf gets a group of lanes (n times the pedestrian count rounded up
-to a power of two is at most 64), its rollouts run element by element.  They
-must give the oracle's values (within the usual FP tolerance) and the
-one-lane rollout's values bit for bit: the stand-alone bounds call (one lane
-per state) on the leaf's stepped states, ids and depth, and the batched
-launch of the same leaf (which never uses the element-level path)."""
+to a power of two is at most 64), its gather, update step, expansion step
+(with the observation hash chained over the group's lanes), upper bound
+and rollout run element by element.  They must give the oracle's states,
+rewards and observations bit for bit and its values within the usual FP
+tolerance, and the one-lane path's results bit for bit: the stand-alone
+bounds call (one lane per state) on the leaf's stepped states, ids and
+depth, and the staged batched launch of the same leaf (which never uses
+the element-level path), field by field."""
 import numpy as np
 import pytest
 import torch
@@ -57,17 +60,30 @@ def test_small_leaf_group_rollout(ctx, peds, n, policy):
     torch.cuda.synchronize()
     assert np.array_equal(host(L1).view(np.uint32), got["L"].reshape(-1).view(np.uint32))
     assert np.array_equal(host(steps1).reshape(A, n).sum(1), got["steps"][:, 1])
-    # and against the batched launch (one lane per scenario)
-    for t in (out.L, out.child_l0, out.steps):
+    # and against the batched launch (one lane per scenario), field by field
+    for t in [out.L, out.U, out.r, out.z, out.child_l0, out.child_u0, out.child_z, out.child_n, out.child_off,
+              out.perm, out.child_of, out.steps, out.r_mean, out.n_children, out.ids]:
         t.fill_(-5)
+    for d in (out.states, out.sprime):
+        for t in d.values():
+            t.fill_(7)
     b = Batch(ctx, 1, A)
     b.set_leaves([leaf])
     b.launch()
     torch.cuda.synchronize()
     got2 = collect(m, out)
-    assert np.array_equal(got2["L"].view(np.uint32), got["L"].view(np.uint32))
-    assert np.array_equal(got2["n_children"], got["n_children"])
+    for key in ("L", "U", "r", "z", "perm", "child_of", "steps", "r_mean", "n_children", "ids"):
+        a1, a2 = np.asarray(got[key]), np.asarray(got2[key])
+        if a1.dtype == np.float32:
+            a1, a2 = a1.view(np.uint32), a2.view(np.uint32)
+        assert np.array_equal(a1, a2), key
+    for d in ("states", "sprime"):
+        for k in got[d]:
+            assert np.array_equal(np.asarray(got[d][k]).view(np.uint8), np.asarray(got2[d][k]).view(np.uint8)), (d, k)
     for a_, nc in enumerate(got["n_children"]):  # slots past a child count are not written
-        assert np.array_equal(got2["child_l0"][a_, :nc].view(np.uint32), got["child_l0"][a_, :nc].view(np.uint32))
-    assert np.array_equal(got2["steps"], got["steps"])
+        for key in ("child_l0", "child_u0", "child_z", "child_n", "child_off"):
+            a1, a2 = got[key][a_, :nc], got2[key][a_, :nc]
+            if a1.dtype == np.float32:
+                a1, a2 = a1.view(np.uint32), a2.view(np.uint32)
+            assert np.array_equal(a1, a2), key
     b.close()
