@@ -433,6 +433,11 @@ def surrogate_section(ctx, args):
     st_one = [rel(t_["rollout"], t_["reference"]) for t_ in same_tree]
     st_abs_sur = [abs(t_["surrogate"] - t_["reference"]) for t_ in same_tree]
     st_abs_one = [abs(t_["rollout"] - t_["reference"]) for t_ in same_tree]
+    # how large a root error is: the two halves of the reference's rollouts
+    # against each other, and the surrogate's frontier error scaled down
+    st_halves = [rel(t_["reference_halves"][0], t_["reference_halves"][1]) for t_ in same_tree]
+    st_scaled = {s_: [rel(t_["surrogate_error_scaled"][s_], t_["reference"]) for t_ in same_tree]
+                 for s_ in same_tree[0]["surrogate_error_scaled"]}
 
     # search at equal budget
     runs = {}
@@ -515,6 +520,9 @@ def surrogate_section(ctx, args):
                        root_rel_err_one_rollout_mean=round(float(np.mean(st_one)), 5),
                        root_rel_err_one_rollout_max=round(float(np.max(st_one)), 5),
                        root_abs_err_surrogate_mean=round(float(np.mean(st_abs_sur)), 5),
+                       root_rel_diff_reference_halves_mean=round(float(np.mean(st_halves)), 5),
+                       root_rel_err_surrogate_error_scaled_mean={str(s_): round(float(np.mean(v)), 5)
+                                                                 for s_, v in st_scaled.items()},
                        root_abs_err_one_rollout_mean=round(float(np.mean(st_abs_one)), 5),
                        frontier_mean_reference=round(float(np.mean([t_["frontier_mean_reference"]
                                                                      for t_ in same_tree])), 5),

@@ -643,10 +643,9 @@ __device__ __forceinline__ uint4 feature_chunk(const HDX_CONST ModelHdr *M, cons
     return v;
 }
 
-// blockIdx.y selects the pack entry; rows of that entry by blockIdx.x.
-__global__ __launch_bounds__(128) void features_kernel(const FeatPack P) {
-    const FeatArgs &A = P.a[blockIdx.y];
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Features of row k of one state array.
+template <class Args>
+__device__ __forceinline__ void features_row(const Args &A, int64_t k) {
     if (k >= A.n) return;
     const HDX_CONST ModelHdr *M = (const HDX_CONST ModelHdr *)&A.model->h;
     const int depth = A.depths ? A.depths[k] : A.depth_const;
@@ -673,6 +672,23 @@ __global__ __launch_bounds__(128) void features_kernel(const FeatPack P) {
     dst[5] = feature_chunk<40>(M, A.states, k, rs, w, x, y, inv, s, car, remain);
     dst[6] = feature_chunk<48>(M, A.states, k, rs, w, x, y, inv, s, car, remain);
     dst[7] = feature_chunk<56>(M, A.states, k, rs, w, x, y, inv, s, car, remain);
+}
+
+// One state array, its arguments by value.
+__global__ __launch_bounds__(128) void features_one(const FeatArgs A) {
+    features_row(A, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Many state arrays, their arguments in device memory (read through the
+// constant address space); blockIdx.y selects the array.
+__global__ __launch_bounds__(128) void features_many(const FeatArgs *args) {
+    const HDX_CONST FeatArgs &A = ((const HDX_CONST FeatArgs *)args)[blockIdx.y];
+    features_row(A, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// A few state arrays, their arguments in the kernel arguments.
+__global__ __launch_bounds__(128) void features_pack(const FeatPack P) {
+    features_row(P.a[blockIdx.y], (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
@@ -745,20 +761,29 @@ hipError_t mlp_refresh_bf16(MlpDev &P, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_features(const FeatArgs *a, int count, hipStream_t s) {
-    for (int i0 = 0; i0 < count; i0 += kFeatPack) {
-        FeatPack P;
-        memset(&P, 0, sizeof(P));
-        int64_t n_max = 0;
-        const int c = std::min(kFeatPack, count - i0);
-        for (int i = 0; i < c; ++i) {
-            P.a[i] = a[i0 + i];
-            n_max = std::max<int64_t>(n_max, a[i0 + i].n);
-        }
-        if (n_max <= 0) continue;
-        const int64_t bx = (n_max + 127) / 128;
-        if (bx > 0x7fffffff) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(features_kernel, dim3((unsigned)bx, c), dim3(128), 0, s, P);
+hipError_t launch_features(const FeatArgs &a, hipStream_t s) {
+    if (a.n <= 0) return hipSuccess;
+    const int64_t bx = (a.n + 127) / 128;
+    if (bx > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(features_one, dim3((unsigned)bx), dim3(128), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_features_pack(const FeatPack &P, int count, int64_t n_max, hipStream_t s) {
+    if (count <= 0 || n_max <= 0) return hipSuccess;
+    const int64_t bx = (n_max + 127) / 128;
+    if (bx > 0x7fffffff || count > kArgPack) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(features_pack, dim3((unsigned)bx, count), dim3(128), 0, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_features_many(const FeatArgs *d_args, int count, int64_t n_max, hipStream_t s) {
+    if (count <= 0 || n_max <= 0) return hipSuccess;
+    const int64_t bx = (n_max + 127) / 128;
+    if (bx > 0x7fffffff) return hipErrorInvalidValue;
+    for (int i0 = 0; i0 < count; i0 += kMaxGridY) {
+        const int c = std::min(kMaxGridY, count - i0);
+        hipLaunchKernelGGL(features_many, dim3((unsigned)bx, c), dim3(128), 0, s, d_args + i0);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -766,15 +791,15 @@ hipError_t launch_features(const FeatArgs *a, int count, hipStream_t s) {
 }
 
 namespace {
-// Surrogate lower bounds of the children of pack entry blockIdx.z: for
-// action a (blockIdx.y) and child c, l0 = mean of the surrogate values of
-// the child's scenarios; per-scenario values copied out on request.  With
-// few children (RockSample: at most three) the wavefront takes one child at
-// a time, lane l summing the child's grouped positions l, l + 64, ... in
+// Surrogate lower bounds of the children of one leaf: for action a
+// (blockIdx.y) and child c, l0 = mean of the surrogate values of the
+// child's scenarios; per-scenario values copied out on request.  With few
+// children (RockSample: at most three) the wavefront takes one child at a
+// time, lane l summing the child's grouped positions l, l + 64, ... in
 // order and a fixed butterfly adding the lanes; with many small children
 // (hashed observations) each lane sums one child in grouped order.
-__global__ __launch_bounds__(64) void surrogate_reduce(const SurPack P) {
-    const SurArgs &A = P.a[blockIdx.z];
+template <class Args>
+__device__ __forceinline__ void child_means(const Args &A) {
     const int a = blockIdx.y;
     if (a >= A.n_actions) return;
     const int n = A.n, lane = threadIdx.x;
@@ -801,20 +826,28 @@ __global__ __launch_bounds__(64) void surrogate_reduce(const SurPack P) {
     if (A.L_out)
         for (int k = lane; k < n; k += 64) A.L_out[(int64_t)a * n + k] = v[k];
 }
+
+// Leaf blockIdx.z of an argument array in device memory.
+__global__ __launch_bounds__(64) void surrogate_reduce(const SurArgs *args) {
+    child_means(((const HDX_CONST SurArgs *)args)[blockIdx.z]);
+}
+
+// Leaf blockIdx.z of a pack in the kernel arguments.
+__global__ __launch_bounds__(64) void surrogate_reduce_pack(const SurPack P) { child_means(P.a[blockIdx.z]); }
 }  // namespace
 
-hipError_t launch_surrogate_reduce(const SurArgs *a, int count, hipStream_t s) {
-    for (int i0 = 0; i0 < count; i0 += kSurPack) {
-        SurPack P;
-        memset(&P, 0, sizeof(P));
-        int A = 0;
-        const int c = std::min(kSurPack, count - i0);
-        for (int i = 0; i < c; ++i) {
-            P.a[i] = a[i0 + i];
-            A = std::max(A, a[i0 + i].n_actions);
-        }
-        if (A <= 0) continue;
-        hipLaunchKernelGGL(surrogate_reduce, dim3(1, A, c), dim3(64), 0, s, P);
+hipError_t launch_surrogate_reduce_pack(const SurPack &P, int count, int32_t n_actions_max, hipStream_t s) {
+    if (count <= 0 || n_actions_max <= 0) return hipSuccess;
+    if (count > kArgPack) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(surrogate_reduce_pack, dim3(1, n_actions_max, count), dim3(64), 0, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_surrogate_reduce(const SurArgs *d_args, int count, int32_t n_actions_max, hipStream_t s) {
+    if (count <= 0 || n_actions_max <= 0) return hipSuccess;
+    for (int i0 = 0; i0 < count; i0 += kMaxGridY) {
+        const int c = std::min(kMaxGridY, count - i0);
+        hipLaunchKernelGGL(surrogate_reduce, dim3(1, n_actions_max, c), dim3(64), 0, s, d_args + i0);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

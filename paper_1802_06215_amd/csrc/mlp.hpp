@@ -64,14 +64,18 @@ hipError_t mlp_backward(const MlpDev &P, const uint16_t *X, const float *t, int 
                         float *loss, hipStream_t s);
 hipError_t mlp_adam(MlpDev &P, const float *grads, float lr, int step, hipStream_t s);
 hipError_t mlp_refresh_bf16(MlpDev &P, hipStream_t s);
-// Features of several state arrays, kFeatPack per launch (kernel arguments,
-// kept under 1 KB).
-constexpr int kFeatPack = 8;
+// Features of one state array (arguments by value), of up to kArgPack
+// arrays (arguments in the kernel arguments), or of `count` arrays whose
+// arguments are in device memory (n_max: the longest array).
+constexpr int kArgPack = 8;       // a surrogate expansion of this many leaves takes the packs
+constexpr int kMaxGridY = 65535;  // arrays per launch of the argument-array kernels
 struct FeatPack {
-    FeatArgs a[kFeatPack];
+    FeatArgs a[kArgPack];
 };
 static_assert(sizeof(FeatPack) <= 1024, "kernel argument pack too large");
-hipError_t launch_features(const FeatArgs *a, int count, hipStream_t s);
+hipError_t launch_features(const FeatArgs &a, hipStream_t s);
+hipError_t launch_features_pack(const FeatPack &P, int count, int64_t n_max, hipStream_t s);
+hipError_t launch_features_many(const FeatArgs *d_args, int count, int64_t n_max, hipStream_t s);
 
 struct SurArgs {
     const float *values;  // [A][n] surrogate value per (action, scenario)
@@ -81,11 +85,13 @@ struct SurArgs {
     float *L_out;  // optional [A][n]
     int32_t n, cap, n_actions, pad;
 };
-constexpr int kSurPack = 12;  // kernel arguments kept under 1 KB
+// Child means of up to kArgPack leaves (a pack in the kernel arguments) or
+// of `count` leaves whose arguments are in device memory.
 struct SurPack {
-    SurArgs a[kSurPack];
+    SurArgs a[kArgPack];
 };
 static_assert(sizeof(SurPack) <= 1024, "kernel argument pack too large");
-hipError_t launch_surrogate_reduce(const SurArgs *a, int count, hipStream_t s);
+hipError_t launch_surrogate_reduce_pack(const SurPack &P, int count, int32_t n_actions_max, hipStream_t s);
+hipError_t launch_surrogate_reduce(const SurArgs *d_args, int count, int32_t n_actions_max, hipStream_t s);
 
 }  // namespace hdx

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -19,6 +20,13 @@ struct hdx_mlp {
     int step = 0;
     void *sur = nullptr;  // scratch of surrogate expansions
     size_t sur_bytes = 0;
+    // pinned staging of a surrogate expansion's per-leaf arguments (features,
+    // child means), copied into `sur` in one transfer; rewritten once the
+    // previous call's copy has run
+    void *h_args = nullptr;
+    size_t h_args_bytes = 0;
+    hipEvent_t args_done = nullptr;
+    bool args_used = false;
     hipEvent_t last = nullptr;  // completion of the latest call (orders calls across streams)
     std::mutex mu;
 };
@@ -90,6 +98,14 @@ StatesPtr to_states(const hdx_states &s) {
 // The handle's weights and scratch are shared by every call: each call
 // waits for the previous one's work, whichever stream it ran on, and marks
 // its own end.  Under stream capture the caller orders the work.
+// HDX_E_DEVICE with the failing step and HIP's text in hdx_last_error.
+hdx_status dev_fail(hdx_ctx *ctx, hipError_t e, const char *what) {
+    char msg[256];
+    snprintf(msg, sizeof msg, "%s: %s", what, hipGetErrorString(e));
+    hdx_internal_set_error(ctx, msg);
+    return HDX_E_DEVICE;
+}
+
 struct Ordered {
     hdx_mlp *m;
     hipStream_t s;
@@ -141,6 +157,8 @@ hdx_status hdx_mlp_destroy(hdx_ctx *ctx, hdx_mlp *m) {
                       (void *)m->loss, m->sur})
         if (ptr) hipFree(ptr);
     if (m->last) hipEventDestroy(m->last);
+    if (m->args_done) hipEventDestroy(m->args_done);
+    if (m->h_args) hipHostFree(m->h_args);
     for (void *ptr : {(void *)m->S.h1, (void *)m->S.h2, (void *)m->S.h3, (void *)m->S.g1, (void *)m->S.g2,
                       (void *)m->S.g3, (void *)m->S.y, (void *)m->S.part})
         if (ptr) hipFree(ptr);
@@ -261,7 +279,7 @@ hdx_status hdx_features(hdx_ctx *ctx, const hdx_model *model, hdx_states states,
     a.horizon = horizon;
     a.depth_const = 0;
     a.X = X;
-    return launch_features(&a, 1, (hipStream_t)stream) == hipSuccess ? HDX_OK : HDX_E_DEVICE;
+    return launch_features(a, (hipStream_t)stream) == hipSuccess ? HDX_OK : HDX_E_DEVICE;
 }
 
 hdx_status hdx_expand_leaf_surrogate(hdx_ctx *ctx, const hdx_leaf *leaves, int32_t n_leaves, hdx_mlp *mlp,
@@ -288,7 +306,9 @@ hdx_status hdx_expand_leaf_surrogate(hdx_ctx *ctx, const hdx_leaf *leaves, int32
     }
     std::lock_guard<std::mutex> g(mlp->mu);
     Ordered o(mlp, (hipStream_t)stream);
-    const size_t need = st_bytes + (size_t)pairs * (kMlpIn * sizeof(uint16_t) + sizeof(float)) + 64;
+    const size_t args_off = (st_bytes + (size_t)pairs * (kMlpIn * sizeof(uint16_t) + sizeof(float)) + 255) & ~(size_t)255;
+    const size_t args_bytes = (size_t)n_leaves * (sizeof(FeatArgs) + sizeof(SurArgs));
+    const size_t need = args_off + args_bytes;
     if (mlp->sur_bytes < need) {
         if (mlp->sur) hipFree(mlp->sur);
         mlp->sur = nullptr;
@@ -355,10 +375,55 @@ hdx_status hdx_expand_leaf_surrogate(hdx_ctx *ctx, const hdx_leaf *leaves, int32
         r.pad = 0;
         sa.push_back(r);
     }
-    if (launch_features(fa.data(), (int)fa.size(), s) != hipSuccess) return HDX_E_DEVICE;
-    if (pairs > 0 && mlp_forward(mlp->P, X, pairs, nullptr, nullptr, nullptr, vals, s) != hipSuccess)
-        return HDX_E_DEVICE;
-    if (launch_surrogate_reduce(sa.data(), (int)sa.size(), s) != hipSuccess) return HDX_E_DEVICE;
+    if (fa.empty()) return HDX_OK;
+    int64_t n_max = 0;
+    int32_t a_max = 0;
+    for (const FeatArgs &a : fa) n_max = std::max<int64_t>(n_max, a.n);
+    for (const SurArgs &r : sa) a_max = std::max(a_max, r.n_actions);
+    hipError_t e = hipSuccess;
+    if (fa.size() <= (size_t)kArgPack) {
+        // a few leaves (a search's expansion): the arguments travel in the
+        // kernel arguments, no staging
+        FeatPack fp;
+        SurPack sp;
+        memset(&fp, 0, sizeof(fp));
+        memset(&sp, 0, sizeof(sp));
+        std::copy(fa.begin(), fa.end(), fp.a);
+        std::copy(sa.begin(), sa.end(), sp.a);
+        if ((e = launch_features_pack(fp, (int)fa.size(), n_max, s)) != hipSuccess) return dev_fail(ctx, e, "features");
+        if (pairs > 0 && (e = mlp_forward(mlp->P, X, pairs, nullptr, nullptr, nullptr, vals, s)) != hipSuccess)
+            return dev_fail(ctx, e, "forward");
+        if ((e = launch_surrogate_reduce_pack(sp, (int)sa.size(), a_max, s)) != hipSuccess)
+            return dev_fail(ctx, e, "child means");
+        return HDX_OK;
+    }
+    // many leaves: both argument arrays in one transfer from pinned staging
+    if (mlp->args_used && (e = hipEventSynchronize(mlp->args_done)) != hipSuccess)
+        return dev_fail(ctx, e, "argument staging wait");
+    mlp->args_used = false;
+    if (mlp->h_args_bytes < args_bytes) {
+        if (mlp->h_args) hipHostFree(mlp->h_args);
+        mlp->h_args = nullptr;
+        mlp->h_args_bytes = 0;
+        if (hipHostMalloc(&mlp->h_args, args_bytes) != hipSuccess) return HDX_E_NOMEM;
+        mlp->h_args_bytes = args_bytes;
+    }
+    if (!mlp->args_done && (e = hipEventCreateWithFlags(&mlp->args_done, hipEventDisableTiming)) != hipSuccess)
+        return dev_fail(ctx, e, "event");
+    const size_t fa_bytes = fa.size() * sizeof(FeatArgs), sa_bytes = sa.size() * sizeof(SurArgs);
+    memcpy(mlp->h_args, fa.data(), fa_bytes);
+    memcpy((char *)mlp->h_args + fa_bytes, sa.data(), sa_bytes);
+    FeatArgs *d_fa = (FeatArgs *)(base + args_off);
+    SurArgs *d_sa = (SurArgs *)(base + args_off + fa_bytes);
+    if ((e = hipMemcpyAsync(d_fa, mlp->h_args, fa_bytes + sa_bytes, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipEventRecord(mlp->args_done, s)) != hipSuccess)
+        return dev_fail(ctx, e, "argument copy");
+    mlp->args_used = true;
+    if ((e = launch_features_many(d_fa, (int)fa.size(), n_max, s)) != hipSuccess) return dev_fail(ctx, e, "features");
+    if (pairs > 0 && (e = mlp_forward(mlp->P, X, pairs, nullptr, nullptr, nullptr, vals, s)) != hipSuccess)
+        return dev_fail(ctx, e, "forward");
+    if ((e = launch_surrogate_reduce(d_sa, (int)sa.size(), a_max, s)) != hipSuccess)
+        return dev_fail(ctx, e, "child means");
     return HDX_OK;
 }
 

@@ -84,7 +84,11 @@ def root_values_same_tree(ctx: "H.Context", model: "H.Model", gamma: float, root
     `key` (that fixes the tree); the grandchildren at depth 2 form the
     frontier; child lower bounds are frontier means over each child's
     scenarios (Eq. 13) and the root value is the Eq. 4 backup of the
-    library's host tree.  Returns the three root values."""
+    library's host tree.  Returns the three root values, and two readings of
+    how large a root error is: the root values of the two halves of the
+    reference's rollouts (its own sampling spread), and of frontier values
+    that keep a fraction s of the surrogate's error (reference + s (surrogate
+    - reference))."""
     dev = root[next(iter(root))].device
     A = model.n_actions
     ids = torch.arange(K, dtype=torch.int32, device=dev)
@@ -109,11 +113,12 @@ def root_values_same_tree(ctx: "H.Context", model: "H.Model", gamma: float, root
     fids = torch.cat([o.ids[:o.n].repeat(A) for o in nodes])
     depths = torch.full((fids.numel(),), 2, dtype=torch.int32, device=dev)
     v_one = torch.cat([o.L[:, :o.n].reshape(-1) for o in nodes])
-    acc = torch.zeros_like(v_one, dtype=torch.float64)
+    half = ref_keys // 2
+    acc = [torch.zeros_like(v_one, dtype=torch.float64) for _ in range(2)]
     for r in range(ref_keys):
         _, L, _ = ctx.rollout_bounds(model, cfg, front, fids, depths, ref_seed + r, 0)
-        acc += L.double()
-    v_ref = acc / ref_keys
+        acc[0 if r < half else 1] += L.double()
+    v_ref = (acc[0] + acc[1]) / ref_keys
     v_sur = mlp.forward(H.features(ctx, model, front, depths, horizon))
     torch.cuda.synchronize()
     host = [dict(n=o.n, nc=o.n_children.cpu().numpy(), z=o.child_z.cpu().numpy().view(np.uint64),
@@ -141,7 +146,10 @@ def root_values_same_tree(ctx: "H.Context", model: "H.Model", gamma: float, root
     ref = v_ref.cpu().numpy()
     sur = v_sur.cpu().numpy().astype(np.float64)
     one = v_one.cpu().numpy().astype(np.float64)
+    halves = [(a / max(h, 1)).cpu().numpy() for a, h in ((acc[0], half), (acc[1], ref_keys - half))]
+    scaled = {s_: root_value(ref + s_ * (sur - ref)) for s_ in (0.5, 0.25, 0.1, 0.05)}
     return dict(rollout=root_value(one), reference=root_value(ref), surrogate=root_value(sur),
+                reference_halves=[root_value(h) for h in halves], surrogate_error_scaled=scaled,
                 depth1_nodes=len(nodes), frontier_pairs=int(fids.numel()),
                 frontier_mean_reference=float(ref.mean()), frontier_bias_surrogate=float((sur - ref).mean()),
                 frontier_mae_surrogate=float(np.abs(sur - ref).mean()),
