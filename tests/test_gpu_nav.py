@@ -71,6 +71,44 @@ def test_leaf_parity(ctx, case):
     compare_leaf(desc, gpu, ref, n_leaf)
 
 
+SMALL = [(n, pol) for n in (1, 2, 3, 5, 8, 12, 16) for pol in (0, 2)] + [(4, 1)]
+
+
+@pytest.mark.parametrize("n,policy", SMALL)
+def test_small_leaf_argument_launch_matches_staged_launch(ctx, n, policy):
+    """A one-leaf call of at most 16 scenarios (a search thread's typical
+    expansion) travels in the kernel arguments; its values and step counts
+    must be the oracle's, and every output the bits of the staged batched
+    launch of the same leaf."""
+    from paper_1802_06215_amd import Batch
+    desc = W.nav_model(n % 3)
+    m = ctx.upload_model(desc)
+    lf = W.nav_leaf(desc, 40, n, 30 + n + policy, p_term=0.05)
+    ocfg, hcfg = cfg_pair(policy, 1 << 30, 90, const_action=3)
+    par_np = oracle.parent_states(desc, lf)
+    par, pids = to_dev(par_np), ids_dev(lf["ids"])
+    print("nav small leaf n=%d policy=%d" % (n, policy), flush=True)
+    leaf, out, keep = gpu_leaf_desc(m, par, pids, lf["idx"], lf["depth"], lf["last_action"], 13, 4, hcfg, True)
+    ctx.expand_leaf([leaf])
+    torch.cuda.synchronize()
+    got = collect(m, out)
+    ref = oracle.expand_leaf(desc, ocfg, par_np, lf["ids"].astype(np.uint32), lf["idx"], lf["depth"],
+                             lf["last_action"], 13, 4, per_pair=True)
+    compare_leaf(desc, got, ref, n)
+    wipe([dict(out=out)])
+    for t in (out.L, out.U):
+        t.fill_(-5)
+    b = Batch(ctx, 1, desc["n_actions"])
+    b.set_leaves([leaf])
+    b.launch()
+    torch.cuda.synchronize()
+    got2 = collect(m, out)
+    same([got2], [got])
+    for key in ("L", "U"):
+        assert np.array_equal(got2[key].view(np.uint32), got[key].view(np.uint32)), key
+    b.close()
+
+
 def test_root_and_degenerate_leaves(ctx):
     desc = W.nav_model(1)
     m = ctx.upload_model(desc)
