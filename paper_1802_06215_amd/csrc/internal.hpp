@@ -45,6 +45,10 @@ struct ModelHdr {
     int32_t nav_goal_x, nav_wall, nav_gate_x[2];
     int16_t nav_cell[HDX_MAX_NAV_GRID * HDX_MAX_NAV_GRID];
     uint64_t err_thr;
+    // navigation rollouts: the known walls as bits 16 y + x (four words) and
+    // each unknown cell's bit position 16 y + x
+    uint64_t nav_wall_bits[4];
+    uint8_t nav_unknown_pos[HDX_MAX_NAV_UNKNOWN];
 };
 
 constexpr int kGpowLds = 256;
@@ -175,8 +179,9 @@ __host__ __device__ inline LdsLayout make_layout(int32_t np, bool small = false)
     L.child = take(4u * np);
     L.perm = take(4u * L.p2);
     L.misc = take(64 + 4u * 64);
-    // discount powers, goal points, and the navigation cell table (int16)
-    L.gpow = take(4u * (kGpowLds + 2 * kMaxGoals) + 2u * HDX_MAX_NAV_GRID * HDX_MAX_NAV_GRID);
+    // discount powers, goal points, the navigation cell table (int16) and
+    // the unknown cells' grid bits
+    L.gpow = take(4u * (kGpowLds + 2 * kMaxGoals) + 2u * HDX_MAX_NAV_GRID * HDX_MAX_NAV_GRID + HDX_MAX_NAV_UNKNOWN);
     L.total = o;
     return L;
 }
@@ -213,7 +218,7 @@ __host__ __device__ inline MedLayout make_med_layout(int32_t np) {
         o += (bytes + 15u) & ~15u;
         return at;
     };
-    L.gpow = take(4u * (kGpowLds + 2 * kMaxGoals) + 2u * HDX_MAX_NAV_GRID * HDX_MAX_NAV_GRID);
+    L.gpow = take(4u * (kGpowLds + 2 * kMaxGoals) + 2u * HDX_MAX_NAV_GRID * HDX_MAX_NAV_GRID + HDX_MAX_NAV_UNKNOWN);
     L.key = take(2u * n);
     L.rank = take(2u * n);
     L.ub = take(4u * n);

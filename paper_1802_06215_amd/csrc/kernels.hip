@@ -664,7 +664,9 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
 //    chunks of the grouped order as in the hashed path, chunk partials added
 //    in chunk order, so both paths give identical results for a leaf either
 //    can expand.
-template <class Ops>
+// kGroup: the kernel-argument launches (a search's small leaves) roll out
+// with the map held as bits in registers (NavOps::rollout_grid).
+template <class Ops, bool kGroup>
 __device__ void run_tile_med(const HDX_CONST LeafTask *T, const int a, unsigned char *lds, const MedLayout &Ly) {
     static_assert(Ops::kTerminalObs < (uint64_t)kMedKeys, "observation keys exceed the medium alphabet");
     float *gpow_lds = (float *)(lds + Ly.gpow);
@@ -744,7 +746,11 @@ __device__ void run_tile_med(const HDX_CONST LeafTask *T, const int a, unsigned 
             const int64_t pk = (int64_t)a * n + k;
             if (pair_out) Ops::store(M, sprime, pk, st);
             int ns = 0;
-            const float L = rollout<Ops>(M, RP, st, id, depth + 1, ns);
+            float L;
+            if constexpr (kGroup)
+                L = Ops::rollout_grid(M, RP, st, id, depth + 1, ns);
+            else
+                L = rollout<Ops>(M, RP, st, id, depth + 1, ns);
             my_roll += ns;
             keyb[k] = (uint16_t)z;
             ub[k] = U;
@@ -921,7 +927,7 @@ __device__ __forceinline__ void run_mode(const HDX_CONST LeafTask *T, int a, uns
     if (MODE == 3) {
         run_tile<MarsOps>(T, a, lds, Ly);
     } else if (MODE == 4) {
-        run_tile_med<NavOps>(T, a, lds, make_med_layout(Ly.np));
+        run_tile_med<NavOps, kGroup>(T, a, lds, make_med_layout(Ly.np));
     } else if (MODE == 0 || (MODE == 2 && T->kind == HDX_ROCKSAMPLE)) {
         run_tile<RsOps>(T, a, lds, Ly);
     } else {

@@ -12,6 +12,8 @@
 // operation order.
 #pragma once
 
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace hdx {
@@ -34,6 +36,7 @@ struct MView {
     const HDX_CONST float *gg;
     const float *gl;
     const int16_t *cl;  // navigation cell table, staged in LDS after the goal points
+    const uint8_t *up;  // navigation: grid bit of each unknown cell, staged after the cell table
     __device__ float gpow_uniform(int j) const { return gg[j]; }
     __device__ float gpow_lane(int j) const { return j < kGpowLds ? gl[j] : gg[j]; }
     // goal point coordinates, staged in LDS after the discount powers
@@ -48,6 +51,7 @@ __device__ __forceinline__ MView make_view(const DevModel *gm, const float *gpow
     v.gg = (const HDX_CONST float *)gm->gpow;
     v.gl = gpow_lds;
     v.cl = (const int16_t *)(gpow_lds + kGpowLds + 2 * kMaxGoals);
+    v.up = (const uint8_t *)(v.cl + HDX_MAX_NAV_GRID * HDX_MAX_NAV_GRID);
     return v;
 }
 
@@ -64,10 +68,11 @@ __device__ __forceinline__ StatesPtr load_states(const HDX_CONST StatesPtr *s) {
 }
 
 // Stage the first kGpowLds discount powers and the goal points of a model
-// into LDS, and for navigation its cell table after them (kModelLdsFloats
-// floats in all; the caller synchronises afterwards).
+// into LDS, and for navigation its cell table and the unknown cells' grid
+// bits after them (kModelLdsFloats floats in all; the caller synchronises
+// afterwards).
 constexpr int kNavCells = HDX_MAX_NAV_GRID * HDX_MAX_NAV_GRID;
-constexpr int kModelLdsFloats = kGpowLds + 2 * kMaxGoals + kNavCells / 2;
+constexpr int kModelLdsFloats = kGpowLds + 2 * kMaxGoals + kNavCells / 2 + HDX_MAX_NAV_UNKNOWN / 4;
 __device__ __forceinline__ void stage_gpow(const DevModel *gm, float *gpow_lds) {
     const HDX_CONST float *g = (const HDX_CONST float *)gm->gpow;
     const HDX_CONST ModelHdr *h = (const HDX_CONST ModelHdr *)&gm->h;
@@ -84,6 +89,8 @@ __device__ __forceinline__ void stage_cells(const DevModel *gm, float *gpow_lds)
     const HDX_CONST ModelHdr *h = (const HDX_CONST ModelHdr *)&gm->h;
     int16_t *cells = (int16_t *)(gpow_lds + kGpowLds + 2 * kMaxGoals);
     for (int c = threadIdx.x; c < kNavCells; c += blockDim.x) cells[c] = h->nav_cell[c];
+    uint8_t *pos = (uint8_t *)(cells + kNavCells);
+    for (int c = threadIdx.x; c < HDX_MAX_NAV_UNKNOWN; c += blockDim.x) pos[c] = h->nav_unknown_pos[c];
 }
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
@@ -514,6 +521,40 @@ struct NavOps {
     }
     __device__ static bool terminal(const State &st) { return (st.p >> 30) & 1; }
 
+    // The scenario's map as bits 16 y + x (a wall or an occupied unknown
+    // cell), built once for a rollout: the walls from the model, then the
+    // grid bit of each occupied unknown cell.
+    struct Grid {
+        uint64_t w0, w1, w2, w3;
+    };
+    __device__ static Grid grid_of(const MView &M, const State &st) {
+        Grid g{M.h->nav_wall_bits[0], M.h->nav_wall_bits[1], M.h->nav_wall_bits[2], M.h->nav_wall_bits[3]};
+        const uint32_t words[4] = {st.m0, st.m1, st.m2, st.m3};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t w = words[q];
+            while (w) {
+                const int c = 32 * q + __builtin_ctz(w);
+                w &= w - 1u;
+                const int bit = M.up[c];
+                const uint64_t b = 1ull << (bit & 63);
+                const int h = bit >> 6;
+                g.w0 |= h == 0 ? b : 0ull;
+                g.w1 |= h == 1 ? b : 0ull;
+                g.w2 |= h == 2 ? b : 0ull;
+                g.w3 |= h == 3 ? b : 0ull;
+            }
+        }
+        return g;
+    }
+    __device__ static int occupied_grid(const MView &M, const Grid &g, int x, int y) {
+        const int n = M.h->grid;
+        if (x < 0 || y < 0 || x >= n || y >= n) return 1;
+        const int bit = 16 * y + x;
+        const uint64_t lo = bit < 64 ? g.w0 : g.w1, hi = bit < 192 ? g.w2 : g.w3;
+        return (int)(((bit < 128 ? lo : hi) >> (bit & 63)) & 1u);
+    }
+
     // Occupied in this scenario; off the map counts as occupied.
     __device__ static int occupied(const MView &M, const State &st, int x, int y) {
         const int n = M.h->grid;
@@ -528,21 +569,20 @@ struct NavOps {
         return (int)((half >> (c & 63)) & 1u);
     }
 
-    template <bool kObs>
-    __device__ static void step(const MView &M, State &st, int a, uint32_t id, uint32_t depth, uint32_t k0,
-                                uint32_t k1, float &r, uint64_t &z) {
-        r = 0.0f;
-        z = kTerminalObs;
-        if ((st.p >> 30) & 1) return;  // absorbing
+    // The motion of a step from a live state, with the failure word (word 0
+    // of the step block) already drawn (a stay draws none) and the cells'
+    // occupancy given by occ(x, y).
+    template <class Occ>
+    __device__ static void move(const MView &M, State &st, int a, uint32_t u_fail, float &r, const Occ &occ) {
         int x = st.p & 15, y = (st.p >> 4) & 15;
         int term = 0;
         if (a == 0) {
             r = -0.2f;
-        } else if ((uint64_t)philox(id, depth, 0, kTagStep, k0, k1).x < M.h->fail_thr) {
+        } else if ((uint64_t)u_fail < M.h->fail_thr) {
             r = -0.1f;  // the move fails: the robot stays
         } else {
             const int tx = x + dx(a), ty = y + dy(a);
-            if (occupied(M, st, tx, ty)) {
+            if (occ(tx, ty)) {
                 r = -1.0f;  // crash: the robot stays
             } else {
                 x = tx;
@@ -556,7 +596,19 @@ struct NavOps {
             }
         }
         st.p = x | (y << 4) | (term << 30);
-        if (!kObs || term) return;
+    }
+
+    template <bool kObs>
+    __device__ static void step(const MView &M, State &st, int a, uint32_t id, uint32_t depth, uint32_t k0,
+                                uint32_t k1, float &r, uint64_t &z) {
+        r = 0.0f;
+        z = kTerminalObs;
+        if ((st.p >> 30) & 1) return;  // absorbing
+        const State s0 = st;
+        move(M, st, a, a == 0 ? 0u : philox(id, depth, 0, kTagStep, k0, k1).x, r,
+             [&](int cx, int cy) { return occupied(M, s0, cx, cy); });
+        if (!kObs || ((st.p >> 30) & 1)) return;
+        const int x = st.p & 15, y = (st.p >> 4) & 15;
         const uint4 b1 = philox(id, depth, 1, kTagStep, k0, k1);
         const uint4 b2 = philox(id, depth, 2, kTagStep, k0, k1);
         const uint32_t words[8] = {b1.x, b1.y, b1.z, b1.w, b2.x, b2.y, b2.z, b2.w};
@@ -584,7 +636,8 @@ struct NavOps {
     // Head for the open gate while above the wall, then for the goal: the
     // diagonal step towards the target, else its vertical part, else its
     // horizontal part, the first that lands on a free cell; else stay.
-    __device__ static int default_action(const MView &M, const State &st) {
+    template <class Occ>
+    __device__ static int default_action_occ(const MView &M, const State &st, const Occ &occ) {
         const int x = st.p & 15, y = (st.p >> 4) & 15;
         int tx = M.h->nav_goal_x, ty = M.h->grid - 1;
         if (y < M.h->nav_wall) {
@@ -599,11 +652,55 @@ struct NavOps {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             if (cx[c] == 0 && cy[c] == 0) continue;
-            if (occupied(M, st, x + cx[c], y + cy[c])) continue;
+            if (occ(x + cx[c], y + cy[c])) continue;
             return (int)((kAction >> (4 * ((cy[c] + 1) * 3 + cx[c] + 1))) & 15u);
         }
         return 0;
     }
+    __device__ static int default_action(const MView &M, const State &st) {
+        return default_action_occ(M, st, [&](int cx, int cy) { return occupied(M, st, cx, cy); });
+    }
+
+    // A rollout (rollout_loop's operations and order) with the map held as
+    // bits in registers for its whole length: the occupancy tests of the
+    // policy and of the moves read no table.  Shorter for the lone
+    // wavefronts of small leaves; a batch of full tiles keeps the table
+    // lookups, which need fewer registers.
+    template <int POL>
+    __device__ static float rollout_grid_p(const MView &M, const RolloutParams &P, State st, uint32_t id, int d0,
+                                           int n_roll, int &nsteps) {
+        float value = 0.0f;
+        if (n_roll <= 0 || terminal(st)) return value;
+        const Grid g = grid_of(M, st);
+        const auto occ = [&](int cx, int cy) { return occupied_grid(M, g, cx, cy); };
+        for (int j = 0; j < n_roll; ++j) {
+            if (terminal(st)) break;
+            const uint32_t depth = (uint32_t)(d0 + j);
+            int a;
+            if (POL == HDX_POLICY_CONST) {
+                a = P.const_action;
+            } else if (POL == HDX_POLICY_RANDOM) {
+                a = (int)(philox(id, depth, 0, kTagPolicy, P.k0, P.k1).x % (uint32_t)P.n_actions);
+            } else {
+                a = default_action_occ(M, st, occ);
+            }
+            float r;
+            move(M, st, a, a == 0 ? 0u : philox(id, depth, 0, kTagStep, P.k0, P.k1).x, r, occ);
+            value += M.gpow_uniform(j) * r;
+            ++nsteps;
+        }
+        return value;
+    }
+    __device__ static float rollout_grid(const MView &M, const RolloutParams &P, const State &st, uint32_t id,
+                                         int d0, int &nsteps) {
+        int n_roll = P.max_steps;
+        if (P.max_depth >= 0 && P.max_depth - d0 < n_roll) n_roll = P.max_depth - d0;
+        if (n_roll > kHorizon) n_roll = kHorizon;
+        if (P.policy == HDX_POLICY_CONST) return rollout_grid_p<HDX_POLICY_CONST>(M, P, st, id, d0, n_roll, nsteps);
+        if (P.policy == HDX_POLICY_RANDOM) return rollout_grid_p<HDX_POLICY_RANDOM>(M, P, st, id, d0, n_roll, nsteps);
+        return rollout_grid_p<HDX_POLICY_DEFAULT>(M, P, st, id, d0, n_roll, nsteps);
+    }
+
 };
 
 // ---------------------------------------------------------------------------

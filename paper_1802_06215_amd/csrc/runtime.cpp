@@ -308,6 +308,12 @@ hdx_status hdx_upload_model(hdx_ctx *ctx, const hdx_model_desc *d, hdx_model **o
         h->nav_gate_x[0] = d->nav_gate_x[0];
         h->nav_gate_x[1] = d->nav_gate_x[1];
         for (int c = 0; c < HDX_MAX_NAV_GRID * HDX_MAX_NAV_GRID; ++c) h->nav_cell[c] = c < n * n ? d->nav_cell[c] : -2;
+        for (int y = 0; y < n; ++y)
+            for (int x = 0; x < n; ++x) {
+                const int v = d->nav_cell[y * n + x], bit = 16 * y + x;
+                if (v == -2) h->nav_wall_bits[bit >> 6] |= 1ull << (bit & 63);
+                if (v >= 0) h->nav_unknown_pos[v] = (uint8_t)bit;
+            }
         h->fail_thr = prob_threshold(d->p_fail);
         h->err_thr = prob_threshold(d->p_err);
     } else if (d->kind == HDX_PEDNAV) {
