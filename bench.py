@@ -450,20 +450,23 @@ def surrogate_section(ctx, args):
     # accuracy of the leaf values from the speed of the search)
     keys = (3, 4, 5)
     EQ_TRIALS = 8000
-    plan = [("%s_key%d" % (nm, k), sur, k, 0) for k in keys for nm, sur in (("rollouts", None), ("surrogate", net))]
-    plan += [("%s_trials_key%d" % (nm, k), sur, k, EQ_TRIALS)
-             for k in keys for nm, sur in (("rollouts", None), ("surrogate", net))]
-    for name, sur, key, max_trials in plan if args.search_seconds > 0 else ():
+    # (the third form adds the judged leaves' mean l0 difference to the
+    # surrogate's child l0, once eight leaves are judged)
+    forms = (("rollouts", None, False), ("surrogate", net, False), ("surrogate_bc", net, True))
+    plan = [("%s_key%d" % (nm, k), sur, bc, k, 0) for k in keys for nm, sur, bc in forms]
+    plan += [("%s_trials_key%d" % (nm, k), sur, bc, k, EQ_TRIALS) for k in keys for nm, sur, bc in forms]
+    for name, sur, bc, key, max_trials in plan if args.search_seconds > 0 else ():
         r = ctx.search(m, W.rocksample_belief(desc), K=500, n_threads=8, max_depth=90, batch_leaves=8,
                        time_budget_s=args.search_seconds if max_trials == 0 else 10.0, max_trials=max_trials,
                        rollout=rcfg, surrogate=sur, surrogate_horizon=90,
-                       surrogate_judge_every=16 if sur is not None else 0, seed=key)
+                       surrogate_judge_every=16 if sur is not None else 0, surrogate_bias_correct=bc, seed=key)
         runs[name] = dict(trials_per_s=round(r["trials"] / r["elapsed_s"], 1),
                           expansions_per_s=round(r["expansions"] / r["elapsed_s"], 1),
                           l_root=round(r["l_root"], 5), u_root=round(r["u_root"], 5),
                           best_action=r["best_action"], nodes=r["nodes"])
         if sur is not None:
             runs[name].update(judged_leaves=r["judged_leaves"], judge_child_l0_mae=round(r["judge_mae"], 5),
+                              judge_child_l0_bias=round(r["judge_bias"], 5),
                               judge_rel_err=round(r["judge_rel_err"], 5), fell_back=bool(r["surrogate_off"]))
         log("search", name, runs[name])
     def stats(form):
@@ -475,8 +478,13 @@ def surrogate_section(ctx, args):
         ls_, ls_se, ts_ = stats("surrogate")
         ef_, ef_se, _ = stats("rollouts_trials")
         es_, es_se, _ = stats("surrogate_trials")
+        lb_, lb_se, tb_ = stats("surrogate_bc")
+        eb_, eb_se, _ = stats("surrogate_bc_trials")
         per_key = [abs(runs["surrogate_trials_key%d" % k]["l_root"] - runs["rollouts_trials_key%d" % k]["l_root"]) /
                    max(abs(runs["rollouts_trials_key%d" % k]["l_root"]), 1e-9) for k in keys]
+        per_key_bc = [abs(runs["surrogate_bc_trials_key%d" % k]["l_root"] -
+                          runs["rollouts_trials_key%d" % k]["l_root"]) /
+                      max(abs(runs["rollouts_trials_key%d" % k]["l_root"]), 1e-9) for k in keys]
     net.close()
     kernels = mlp_section(ctx, args)
     return dict(
@@ -547,7 +555,13 @@ def surrogate_section(ctx, args):
                                  equal_trials=EQ_TRIALS, l_root_rollouts_eq=round(ef_, 5),
                                  l_root_surrogate_eq=round(es_, 5),
                                  root_value_rel_err_eq=round(abs(es_ - ef_) / max(abs(ef_), 1e-9), 5),
-                                 root_value_rel_err_eq_per_key=[round(v, 5) for v in per_key])
+                                 root_value_rel_err_eq_per_key=[round(v, 5) for v in per_key],
+                                 bias_corrected=dict(
+                                     trials_per_s=round(tb_, 1), l_root=round(lb_, 5),
+                                     root_value_rel_err=round(abs(lb_ - lf_) / max(abs(lf_), 1e-9), 5),
+                                     l_root_eq=round(eb_, 5),
+                                     root_value_rel_err_eq=round(abs(eb_ - ef_) / max(abs(ef_), 1e-9), 5),
+                                     root_value_rel_err_eq_per_key=[round(v, 5) for v in per_key_bc]))
                     if runs else None))
 
 

@@ -514,6 +514,9 @@ typedef struct {
     double surrogate_max_rel_err;  /* > 0: once 8 leaves are judged, fall back to rollouts for
                                       the rest of the search if sum|l0_sur - l0| / sum|l0|
                                       exceeds this */
+    int32_t surrogate_bias_correct; /* 1: once 8 leaves are judged, add the judged children's
+                                       mean of (l0_rollout - l0_sur) to every later surrogate
+                                       child l0 (at most the child's u0) */
 } hdx_search_cfg;
 
 typedef struct {
@@ -534,6 +537,7 @@ typedef struct {
     int64_t judged_leaves, judged_children; /* surrogate judge: leaves and children compared */
     double judge_mae;                       /* mean |l0_sur - l0_rollout| per judged child */
     double judge_rel_err;                   /* sum |l0_sur - l0_rollout| / sum |l0_rollout| */
+    double judge_bias;                      /* mean (l0_rollout - l0_sur) per judged child */
     int32_t surrogate_off;                  /* 1 if the search fell back to rollouts */
     /* where the threads' time went, summed over threads (seconds): descents
        (Eq. 7-9), expansions (launch and wait, or the batcher's round trip),

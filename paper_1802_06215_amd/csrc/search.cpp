@@ -289,7 +289,8 @@ struct Search {
     std::atomic<bool> surrogate_off{false};
     std::atomic<int64_t> judge_ctr{0};
     std::mutex jmu;
-    double j_err = 0.0, j_ref = 0.0;
+    double j_err = 0.0, j_ref = 0.0, j_diff = 0.0;
+    std::atomic<double> l0_bias{0.0};  // added to surrogate child l0 once enough leaves are judged
     int64_t j_leaves = 0, j_children = 0;
     double c_a_abs = 0.0;  // c_a scaled by the initial root gap
     std::mutex emu;        // error state and the time breakdown
@@ -392,7 +393,8 @@ struct Search {
         return best;
     }
 
-    bool expand(int node_id, hipStream_t stream, const HeadBuf &hb, Judge *J);
+    // sur_leaf: set when the leaf's child lower bounds came from the surrogate
+    bool expand(int node_id, hipStream_t stream, const HeadBuf &hb, Judge *J, bool *sur_leaf);
     void judge_leaf(const hdx_leaf &L0, const Rec &r, const char *head_host, Judge &J, hipStream_t stream);
     bool use_surrogate() const { return cfg.surrogate != nullptr && !surrogate_off.load(); }
 
@@ -400,7 +402,7 @@ struct Search {
     // node's actions and children are filled in new ranges of the stores,
     // then published by the release store of state 2.  False when a store
     // is full.
-    bool attach(int node_id, const char *head) {
+    bool attach(int node_id, const char *head, double l0_add) {
         Node &b = nodes[node_id];
         const Rec &r = recs[b.rec];
         const int cap = cap_for(b.n);
@@ -429,8 +431,10 @@ struct Search {
             Act &x = *new (&acts[ab + a]) Act((double)rm[a], (int32_t)c_at, nch[a]);
             for (int c = 0; c < nch[a]; ++c) {
                 const int q = a * cap + c;
-                new (&nodes[c_at++]) Node(node_id, a, cn[q], b.depth + 1, b.rec, perm + (size_t)a * b.n + co[q],
-                                          (double)cu[q], (double)cl[q]);
+                const double u = (double)cu[q];
+                double l = (double)cl[q];
+                if (l0_add != 0.0) l = std::min(l + l0_add, u);
+                new (&nodes[c_at++]) Node(node_id, a, cn[q], b.depth + 1, b.rec, perm + (size_t)a * b.n + co[q], u, l);
             }
             refresh(x, b.n);
         }
@@ -473,24 +477,27 @@ void Search::judge_leaf(const hdx_leaf &L0, const Rec &r, const char *head_host,
     const int32_t *nch = (const int32_t *)(head_host + r.L.n_children);
     const float *lf = (const float *)(head_host + r.L.child_l0);
     const float *ls = (const float *)(J.head.host + r.L.child_l0);
-    double e = 0.0, ref = 0.0;
+    double e = 0.0, ref = 0.0, diff = 0.0;
     int64_t nc = 0;
     for (int a = 0; a < A; ++a)
         for (int c = 0; c < nch[a] && c < cap; ++c) {
             e += std::fabs((double)ls[a * cap + c] - (double)lf[a * cap + c]);
+            diff += (double)lf[a * cap + c] - (double)ls[a * cap + c];
             ref += std::fabs((double)lf[a * cap + c]);
             ++nc;
         }
     std::lock_guard<std::mutex> g(jmu);
     j_err += e;
     j_ref += ref;
+    j_diff += diff;
     j_children += nc;
     j_leaves += 1;
+    if (cfg.surrogate_bias_correct && j_leaves >= 8 && j_children > 0) put(l0_bias, j_diff / (double)j_children);
     if (cfg.surrogate_max_rel_err > 0.0 && j_leaves >= 8 && j_err > cfg.surrogate_max_rel_err * j_ref)
         surrogate_off = true;
 }
 
-bool Search::expand(int node_id, hipStream_t stream, const HeadBuf &hb, Judge *J) {
+bool Search::expand(int node_id, hipStream_t stream, const HeadBuf &hb, Judge *J, bool *sur_leaf) {
     char *head_host = hb.host;
     Node &b = nodes[node_id];
     Rec r;
@@ -521,6 +528,7 @@ bool Search::expand(int node_id, hipStream_t stream, const HeadBuf &hb, Judge *J
     const bool sur = use_surrogate();
     const bool judge = sur && J != nullptr && cfg.surrogate_judge_every > 0 &&
                        judge_ctr.fetch_add(1) % cfg.surrogate_judge_every == 0;
+    *sur_leaf = sur && !judge;
     if (cfg.batch_leaves > 1 && !judge) {
         Request q;
         q.leaf = L;
@@ -676,10 +684,11 @@ void worker(Search *S, int tid, size_t head_bytes) {
         t_sel += std::chrono::duration<double>(te - ts).count();
         bool ok = true;
         if (leaf >= 0) {
-            ok = S->expand(leaf, stream, hb, J);
+            bool sur_leaf = false;
+            ok = S->expand(leaf, stream, hb, J, &sur_leaf);
             t_exp += since(te);
             const Clock::time_point tb = Clock::now();
-            if (ok) ok = S->attach(leaf, hb.host);
+            if (ok) ok = S->attach(leaf, hb.host, sur_leaf ? ld(S->l0_bias) : 0.0);
             if (ok) {
                 S->expansions++;
             } else {
@@ -832,6 +841,7 @@ extern "C" hdx_status hdx_search(hdx_ctx *ctx, const hdx_model *model, const hdx
     out->judged_children = S.j_children;
     out->judge_mae = S.j_children > 0 ? S.j_err / (double)S.j_children : 0.0;
     out->judge_rel_err = S.j_ref > 0.0 ? S.j_err / S.j_ref : 0.0;
+    out->judge_bias = S.j_children > 0 ? S.j_diff / (double)S.j_children : 0.0;
     out->surrogate_off = S.surrogate_off.load() ? 1 : 0;
     out->time_select_s = S.t_select;
     out->time_expand_s = S.t_expand;

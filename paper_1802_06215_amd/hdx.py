@@ -75,7 +75,8 @@ class SearchCfg(C.Structure):
                 ("xi", C.c_double), ("c_a", C.c_double), ("c_o", C.c_double), ("gap_epsilon", C.c_double),
                 ("arena_bytes", C.c_int64), ("seed", C.c_uint32), ("step", C.c_uint32),
                 ("rollout", RolloutCfg), ("surrogate", C.c_void_p), ("surrogate_horizon", C.c_int32),
-                ("surrogate_judge_every", C.c_int32), ("surrogate_max_rel_err", C.c_double)]
+                ("surrogate_judge_every", C.c_int32), ("surrogate_max_rel_err", C.c_double),
+                ("surrogate_bias_correct", C.c_int32)]
 
 
 class SearchResult(C.Structure):
@@ -86,7 +87,7 @@ class SearchResult(C.Structure):
                 ("launches", C.c_int64), ("max_depth_reached", C.c_int32), ("arena_full", C.c_int32),
                 ("elapsed_s", C.c_double), ("action_l", C.c_double * MAX_ACTIONS), ("action_u", C.c_double * MAX_ACTIONS),
                 ("judged_leaves", C.c_int64), ("judged_children", C.c_int64), ("judge_mae", C.c_double),
-                ("judge_rel_err", C.c_double), ("surrogate_off", C.c_int32),
+                ("judge_rel_err", C.c_double), ("judge_bias", C.c_double), ("surrogate_off", C.c_int32),
                 ("time_select_s", C.c_double), ("time_expand_s", C.c_double), ("time_backup_s", C.c_double)]
 
 
@@ -529,14 +530,14 @@ class Context:
                c_a: float = 0.1, c_o: float = 0.1, gap_epsilon: float = 0.0, arena_bytes: int = 8 << 30,
                seed: int = 1, step: int = 0, rollout: RolloutCfg | None = None,
                surrogate: "Mlp | None" = None, surrogate_horizon: int = 0, surrogate_judge_every: int = 0,
-               surrogate_max_rel_err: float = 0.0) -> dict:
+               surrogate_max_rel_err: float = 0.0, surrogate_bias_correct: bool = False) -> dict:
         """hdx_search: one planning step of parallel DESPOT over GPU leaf expansion
         (with `surrogate`, leaf lower bounds come from the MLP instead of rollouts)."""
         b, keep = self._belief(model, belief)
         cfg = SearchCfg(K, n_threads, max_depth, batch_leaves, time_budget_s, max_trials, xi, c_a, c_o,
                         gap_epsilon, arena_bytes, seed, step, rollout or rollout_cfg(),
                         surrogate.handle if surrogate is not None else None, surrogate_horizon,
-                        surrogate_judge_every, surrogate_max_rel_err)
+                        surrogate_judge_every, surrogate_max_rel_err, int(bool(surrogate_bias_correct)))
         res = SearchResult()
         self._check(self.lib.hdx_search(self.handle, model.handle, C.byref(b), C.byref(cfg), C.byref(res)))
         out = {f: getattr(res, f) for f, _ in SearchResult._fields_ if not f.startswith("action_")}

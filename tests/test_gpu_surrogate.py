@@ -270,6 +270,13 @@ def test_search_surrogate_judge_and_fallback(ctx, net, threads, batch):
     print(r["judged_leaves"], r["judge_rel_err"], r["surrogate_off"], flush=True)
     assert r["judged_leaves"] >= 8
     assert r["surrogate_off"] == (1 if r["judge_rel_err"] > 1e-12 else 0)
+    # bias correction: the judged children's mean signed difference, bounded
+    # by their mean absolute one; the tree's bounds stay ordered
+    r = ctx.search(m, b, surrogate_bias_correct=True, **common)
+    print("bias", r["judged_leaves"], r["judge_bias"], r["judge_mae"], flush=True)
+    assert r["judged_leaves"] > 0 and np.isfinite(r["judge_bias"])
+    assert abs(r["judge_bias"]) <= r["judge_mae"] + 1e-12
+    assert r["l_root"] <= r["u_root"] + 1e-4 * max(1.0, abs(r["u_root"]))
 
 
 def _oracle_two_level_root(desc, ocfg, root_np, K, key):
