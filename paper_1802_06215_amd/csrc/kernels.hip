@@ -49,6 +49,16 @@ __device__ __forceinline__ float wave_total(float v) {
     v = v + dpp_src<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
+// The same for integers (exact): the wavefront's sum, on every lane.
+__device__ __forceinline__ int wave_total_i(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, true);
+    return __builtin_amdgcn_readlane(v, 63);
+}
 
 __device__ __forceinline__ uint64_t mix_key(uint64_t z) {
     return (z * 0x9E3779B97F4A7C15ull) >> 32;
@@ -239,6 +249,8 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
     const StatesPtr sprime = load_states(&T->sprime);
     const bool write_leaf = (a == 0);
     const bool pair_out = has_states(sprime);
+    // the optional per-pair outputs, tested once per tile rather than per round
+    const bool pair_vals = T->r != nullptr || T->z != nullptr || T->U != nullptr || T->L != nullptr;
     // element-level expansion when the leaf is small enough for every
     // scenario to get a group of lanes of wavefront 0 (tile-uniform)
     int group_lanes = 0;
@@ -328,10 +340,12 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
                 ub[k] = U;
                 lb[k] = L;
             }
-            if (T->r) T->r[pk] = r;
-            if (T->z) T->z[pk] = z;
-            if (T->U) T->U[pk] = U;
-            if (T->L) T->L[pk] = L;
+            if (pair_vals) {
+                if (T->r) T->r[pk] = r;
+                if (T->z) T->z[pk] = z;
+                if (T->U) T->U[pk] = U;
+                if (T->L) T->L[pk] = L;
+            }
         }
         const bool chunk_live = base + wid * 64 < n;  // wavefront-uniform
         if constexpr (Ops::kSmallObs) {
@@ -371,11 +385,8 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
         const float r_chunk = __ballot(r != 0.0f) ? wave_total(r) : 0.0f;
         if (lane == 0 && chunk_live) chunk_r[(base >> 6) + wid] = r_chunk;
     }
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) {
-        my_exp += __shfl_xor(my_exp, d, 64);
-        my_roll += __shfl_xor(my_roll, d, 64);
-    }
+    my_exp = wave_total_i(my_exp);
+    my_roll = wave_total_i(my_roll);
     if (lane == 0) {
         atomicAdd(&stepc[0], (unsigned long long)my_exp);
         atomicAdd(&stepc[1], (unsigned long long)my_roll);
@@ -394,26 +405,36 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
             const uint32_t v = (uint32_t)lane;
             int run = 0;
             float tu = 0.0f, tl = 0.0f;
+            // every chunk's entries are read (an absent key's entry is left
+            // from an earlier tile and discarded), so the reads of several
+            // chunks are in flight together; an entry is rewritten to the
+            // key's count in earlier chunks
+            const int e = (int)(v & 31u);
+#pragma unroll 4
             for (int t = 0; t < nch; ++t) {
-                const uint32_t km = kmask[t];
-                if (lane < 32 && ((km >> v) & 1u)) {
-                    const int c = kc[t * 32 + v];
-                    kc[t * 32 + v] = run;
+                const bool has = lane < 32 && ((kmask[t] >> e) & 1u);
+                const int c = kc[t * 32 + e];
+                const float fu = ku[t * 32 + e], fl = kl[t * 32 + e];
+                if (has) {
+                    kc[t * 32 + e] = run;
                     run += c;
-                    tu = tu + ku[t * 32 + v];
-                    tl = tl + kl[t * 32 + v];
+                    tu = tu + fu;
+                    tl = tl + fl;
                 }
             }
             const bool present = run > 0;
             const uint32_t mask = (uint32_t)__ballot(present);
             D = __popc(mask);
             const int ci = lane < 32 ? __popc(mask & ((1u << v) - 1u)) : 0;
+            // inclusive prefix over lanes 0-31: shifts inside rows of 16
+            // lanes, then row 0's total broadcast into row 1 (lanes past 31
+            // hold 0 counts and are not read)
             int incl = run;
-#pragma unroll
-            for (int d = 1; d < 32; d <<= 1) {
-                const int o = __shfl_up(incl, d, 64);
-                if (lane >= d) incl += o;
-            }
+            incl += __builtin_amdgcn_update_dpp(0, incl, 0x111, 0xf, 0xf, true);  // row_shr:1
+            incl += __builtin_amdgcn_update_dpp(0, incl, 0x112, 0xf, 0xf, true);  // row_shr:2
+            incl += __builtin_amdgcn_update_dpp(0, incl, 0x114, 0xf, 0xf, true);  // row_shr:4
+            incl += __builtin_amdgcn_update_dpp(0, incl, 0x118, 0xf, 0xf, true);  // row_shr:8
+            incl += __builtin_amdgcn_update_dpp(0, incl, 0x142, 0xa, 0xf, true);  // row_bcast:15
             const int off_v = incl - run;
             if (lane < 32) {
                 koff[v] = off_v;
@@ -439,11 +460,12 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
         __syncthreads();
         // grouped order: a scenario's place is its child's offset, plus the
         // key's count in earlier chunks, plus its rank inside its chunk
+        int32_t *const child_of = T->child_of;
         for (int k = tid; k < n; k += nt) {
             const int32_t cw = kchild[k];
             const int v = cw & 31;
             T->perm[(int64_t)a * n + koff[v] + kc[(k >> 6) * 32 + v] + (cw >> 5)] = (int16_t)k;
-            if (T->child_of) T->child_of[(int64_t)a * n + k] = kci[v];
+            if (child_of) child_of[(int64_t)a * n + k] = kci[v];
         }
         __syncthreads();  // LDS is reused by the next tile
         return;
@@ -718,6 +740,8 @@ __device__ void run_tile_med(const HDX_CONST LeafTask *T, const int a, unsigned 
     const StatesPtr sprime = load_states(&T->sprime);
     const bool write_leaf = (a == 0);
     const bool pair_out = has_states(sprime);
+    // the optional per-pair outputs, tested once per tile rather than per round
+    const bool pair_vals = T->r != nullptr || T->z != nullptr || T->U != nullptr || T->L != nullptr;
 
     // -- gather + update + expand + bounds + rollouts (Eq. 10, 12, 13) ------
     int my_exp = 0, my_roll = 0;
@@ -755,21 +779,20 @@ __device__ void run_tile_med(const HDX_CONST LeafTask *T, const int a, unsigned 
             keyb[k] = (uint16_t)z;
             ub[k] = U;
             lb[k] = L;
-            if (T->r) T->r[pk] = r;
-            if (T->z) T->z[pk] = z;
-            if (T->U) T->U[pk] = U;
-            if (T->L) T->L[pk] = L;
+            if (pair_vals) {
+                if (T->r) T->r[pk] = r;
+                if (T->z) T->z[pk] = z;
+                if (T->U) T->U[pk] = U;
+                if (T->L) T->L[pk] = L;
+            }
         }
         // mean step reward: sum of this 64-scenario chunk (lanes past n add 0;
         // a chunk without a reward sums to +0 without the reduction)
         const float r_chunk = __ballot(r != 0.0f) ? wave_total(r) : 0.0f;
         if (lane == 0 && base + wid * 64 < n) chunk_r[(base >> 6) + wid] = r_chunk;
     }
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) {
-        my_exp += __shfl_xor(my_exp, d, 64);
-        my_roll += __shfl_xor(my_roll, d, 64);
-    }
+    my_exp = wave_total_i(my_exp);
+    my_roll = wave_total_i(my_roll);
     if (lane == 0) {
         atomicAdd(&stepc[0], (unsigned long long)my_exp);
         atomicAdd(&stepc[1], (unsigned long long)my_roll);

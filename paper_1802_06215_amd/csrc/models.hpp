@@ -123,6 +123,23 @@ struct RolloutParams {
     int32_t policy, const_action, max_steps, max_depth, n_actions;
 };
 
+// Eq. 12 bound of the rock models from tabulated group sums: entry 16 g + m
+// of `tab0` (groups 0-3) or `tab1` (group 4) is the sum of group g's good
+// rocks' terms when the four quality bits of rocks 4g .. 4g+3 read m.  The
+// five lookups are issued together and added in group order; a group past
+// the last rock tabulates +0 for every pattern, and the running sum of
+// non-negative terms is never -0, so the result equals the sum over the
+// rock groups alone, bit for bit.  `bits` holds rock i's quality in bit i.
+// Called by all 64 lanes of a wavefront.
+__device__ __forceinline__ float group_table_sum(uint32_t bits, float tab0, float tab1) {
+    const float t0 = __shfl(tab0, (int)__builtin_amdgcn_ubfe(bits, 0, 4), 64);
+    const float t1 = __shfl(tab0, 16 + (int)__builtin_amdgcn_ubfe(bits, 4, 4), 64);
+    const float t2 = __shfl(tab0, 32 + (int)__builtin_amdgcn_ubfe(bits, 8, 4), 64);
+    const float t3 = __shfl(tab0, 48 + (int)__builtin_amdgcn_ubfe(bits, 12, 4), 64);
+    const float t4 = __shfl(tab1, (int)__builtin_amdgcn_ubfe(bits, 16, 4), 64);
+    return (((((0.0f + t0) + t1) + t2) + t3) + t4);
+}
+
 // ---------------------------------------------------------------------------
 // RockSample: one packed int32 word per scenario.
 // ---------------------------------------------------------------------------
@@ -222,10 +239,10 @@ struct RsOps {
         const uint64_t lv = __ballot(live);
         if (lv == 0) return 0.0f;
         const int leader = __ffsll((unsigned long long)lv) - 1;
-        const int x0 = __shfl(x, leader, 64), y0 = __shfl(y, leader, 64);
+        const int xs = __builtin_amdgcn_readlane(x, leader), ys = __builtin_amdgcn_readlane(y, leader);
         const int nr = M.h->n_rocks;
         const int ng = (nr + 3) >> 2;
-        if (__ballot(live && (x != x0 || y != y0)) != 0) {
+        if (__ballot(live && (x != xs || y != ys)) != 0) {
             // cells differ: per-lane terms, discount powers read from the model table
             if (!live) return 0.0f;
             float u = 0.0f;
@@ -238,7 +255,6 @@ struct RsOps {
             }
             return u + 10.0f * M.gg[M.h->grid - 1 - x];
         }
-        const int xs = __builtin_amdgcn_readfirstlane(x0), ys = __builtin_amdgcn_readfirstlane(y0);
         if (xs != wu.x || ys != wu.y) {
             const int lane = (int)__lane_id();
             const float ci = lane < nr ? 10.0f * M.gg[abs(xs - M.h->rock_x[lane]) + abs(ys - M.h->rock_y[lane])] : 0.0f;
@@ -258,13 +274,7 @@ struct RsOps {
             wu.x = xs;
             wu.y = ys;
         }
-        float u = 0.0f;
-        for (int g = 0; g < ng; ++g) {
-            const int pat = (int)__builtin_amdgcn_ubfe((uint32_t)st.w, 10 + 4 * g, 4);
-            const float t = g < 4 ? __shfl(wu.tab0, 16 * g + pat, 64) : __shfl(wu.tab1, 16 * (g - 4) + pat, 64);
-            u = u + t;
-        }
-        u = u + wu.exit;
+        const float u = group_table_sum((uint32_t)st.w >> 10, wu.tab0, wu.tab1) + wu.exit;
         return live ? u : 0.0f;
     }
 
@@ -419,11 +429,9 @@ struct MarsOps {
         const uint64_t lv = __ballot(live);
         if (lv == 0) return 0.0f;
         const int leader = __ffsll((unsigned long long)lv) - 1;
-        const int32_t p0 = __shfl(st.p, leader, 64);
-        if (__ballot(live && st.p != p0) != 0) return upper(M, st);
-        const int32_t ps = __builtin_amdgcn_readfirstlane(p0);
+        const int32_t ps = __builtin_amdgcn_readlane(st.p, leader);
+        if (__ballot(live && st.p != ps) != 0) return upper(M, st);
         const int nr = M.h->n_rocks;
-        const int ng = (nr + 3) >> 2;
         if (ps != wu.p) {
             const int lane = (int)__lane_id();
             const float ci = lane < nr ? 10.0f * M.gg[near(ps, M.h->rock_x[lane], M.h->rock_y[lane])] : 0.0f;
@@ -443,12 +451,7 @@ struct MarsOps {
             wu.e1 = ((ps >> (kGone0 + 1)) & 1) ? 0.0f : 10.0f * M.gpow_uniform(n1 - ((ps >> 10) & 31));
             wu.p = ps;
         }
-        float u = 0.0f;
-        for (int g = 0; g < ng; ++g) {
-            const int pat = (int)__builtin_amdgcn_ubfe((uint32_t)st.rk, 4 * g, 4);
-            const float t = g < 4 ? __shfl(wu.tab0, 16 * g + pat, 64) : __shfl(wu.tab1, 16 * (g - 4) + pat, 64);
-            u = u + t;
-        }
+        float u = group_table_sum((uint32_t)st.rk, wu.tab0, wu.tab1);
         u = u + wu.e0;
         u = u + wu.e1;
         return live ? u : 0.0f;
