@@ -103,6 +103,8 @@ def parse():
                     help="rollouts averaged into each training target")
     ap.add_argument("--surrogate-leaves", type=int, default=1024,
                     help="synthetic training leaves of 100 scenarios each (x 20 actions = pairs / 2000)")
+    ap.add_argument("--same-tree-refs", type=int, default=32,
+                    help="independent rollouts averaged into the same-tree reference value of each frontier pair")
     ap.add_argument("--surrogate-planner-seeds", type=int, default=6,
                     help="planner trees (root from the start belief, 8 levels of up to 32 nodes) "
                          "that add training pairs")
@@ -423,12 +425,13 @@ def surrogate_section(ctx, args):
 
     # the same tree, three frontier values: for each key, the root and the
     # children it reaches are expanded (that fixes a two-level tree) and the
-    # depth-2 frontier is valued by single rollouts, by the mean of 32
-    # independent rollouts (the reference) and by the surrogate
+    # depth-2 frontier is valued by single rollouts, by the mean of
+    # --same-tree-refs independent rollouts (the reference) and by the surrogate
     same_tree = []
     for key in range(1, 9):
         root = ctx.sample_scenarios(m, W.rocksample_belief(desc), 500, 40 + key, 0)
-        same_tree.append(S.root_values_same_tree(ctx, m, desc["gamma"], root, 500, rcfg, key, net, 90))
+        same_tree.append(S.root_values_same_tree(ctx, m, desc["gamma"], root, 500, rcfg, key, net, 90,
+                                                 ref_keys=args.same_tree_refs))
         log("same tree", key, same_tree[-1])
     rel = lambda v, ref: abs(v - ref) / max(abs(ref), 1e-9)
     st_sur = [rel(t_["surrogate"], t_["reference"]) for t_ in same_tree]
@@ -521,7 +524,7 @@ def surrogate_section(ctx, args):
                          child_l0_p90_surrogate=round(float(np.percentile(ce_sur, 90)), 5))),
         same_tree=dict(trees=len(same_tree), depth1_nodes=[t_["depth1_nodes"] for t_ in same_tree],
                        frontier_pairs=[t_["frontier_pairs"] for t_ in same_tree],
-                       reference_rollouts_per_pair=32,
+                       reference_rollouts_per_pair=args.same_tree_refs,
                        l_root_reference=[round(t_["reference"], 5) for t_ in same_tree],
                        l_root_rollout=[round(t_["rollout"], 5) for t_ in same_tree],
                        l_root_surrogate=[round(t_["surrogate"], 5) for t_ in same_tree],
