@@ -97,13 +97,15 @@ def parse():
                     help="size_class:threads,persistent,xcd_remap (repeatable; skips the autotuner)")
     ap.add_argument("--split", action="store_true",
                     help="one launch group per size class (with --schedule / --class-schedule)")
-    ap.add_argument("--surrogate-epochs", type=int, default=24,
+    ap.add_argument("--surrogate-epochs", type=int, default=96,
                     help="training epochs of the surrogate comparison (rs15 only; 0 = skip)")
+    ap.add_argument("--surrogate-batch", type=int, default=65536, help="training minibatch rows (a multiple of 64)")
+    ap.add_argument("--surrogate-lr", type=float, default=8e-3, help="initial Adam rate (cosine down to 1e-4)")
     ap.add_argument("--surrogate-targets", type=int, default=16,
                     help="rollouts averaged into each training target")
     ap.add_argument("--surrogate-leaves", type=int, default=1024,
                     help="synthetic training leaves of 100 scenarios each (x 20 actions = pairs / 2000)")
-    ap.add_argument("--same-tree-refs", type=int, default=32,
+    ap.add_argument("--same-tree-refs", type=int, default=1024,
                     help="independent rollouts averaged into the same-tree reference value of each frontier pair")
     ap.add_argument("--surrogate-planner-seeds", type=int, default=6,
                     help="planner trees (root from the start belief, 8 levels of up to 32 nodes) "
@@ -362,7 +364,8 @@ def surrogate_section(ctx, args):
     net = Mlp(ctx, seed=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    hist = S.fit(net, X, t, epochs=args.surrogate_epochs, batch=4096, lr=2e-3, lr_final=1e-4)
+    hist = S.fit(net, X, t, epochs=args.surrogate_epochs, batch=args.surrogate_batch, lr=args.surrogate_lr,
+                 lr_final=1e-4)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     samples = (X.shape[0] // 4096) * 4096 * args.surrogate_epochs
@@ -496,7 +499,8 @@ def surrogate_section(ctx, args):
         train=dict(pairs=n_pairs, synthetic_pairs=n_synth, planner_pairs=n_pairs - n_synth,
                    leaves=args.surrogate_leaves, planner_trees=args.surrogate_planner_seeds,
                    rollouts_per_target=args.surrogate_targets,
-                   data_gen_s=round(gen_s, 3), epochs=args.surrogate_epochs,
+                   data_gen_s=round(gen_s, 3), epochs=args.surrogate_epochs, batch=args.surrogate_batch,
+                   lr=args.surrogate_lr,
                    fit_s=round(train_s, 3), samples_per_s=round(samples / train_s, 1),
                    tflops=round(S.FLOPS_TRAIN * samples / train_s / 1e12, 2), losses=[round(h, 4) for h in hist]),
         kernels=dict(note="the MLP kernels alone on random features (bench.py --mlp-only): forward over 4.65 M rows, "
