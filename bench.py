@@ -87,6 +87,12 @@ def parse():
     ap.add_argument("--mlp-only", action="store_true",
                     help="only the surrogate MLP kernels on random BF16 features: the forward over 4.65 M rows and "
                          "training steps at several batch sizes (prints a JSON object; for profiling the MLP kernels)")
+    ap.add_argument("--episodes", type=int, default=0,
+                    help="only closed-loop RockSample 15x15 episodes (plan, act, observe, update the belief, "
+                         "replan) of this many seeds per thread count; prints a JSON object")
+    ap.add_argument("--episode-seconds", type=float, default=1.0, help="planning time per episode step")
+    ap.add_argument("--episode-threads", default="4,8,16", help="search thread counts of the episode runs")
+    ap.add_argument("--episode-max-steps", type=int, default=100, help="steps before an episode is cut off")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (x3), to scale HBM byte counters")
     ap.add_argument("--search-seconds", type=float, default=1.0,
@@ -799,6 +805,55 @@ def single_leaf_latency(ctx, wl, reps=200):
                 wall_ms_p90=round(float(np.percentile(t, 90)) * 1e3, 4), gpu_ms_back_to_back=round(gpu_ms, 4))
 
 
+def episode_section(ctx, args) -> dict:
+    """Closed-loop RockSample 15x15 (15 rocks, K = 500, depth 90, move-east
+    rollouts): for each thread count, episodes with seeds 1..N, the true
+    rocks good with probability 0.5 (seeded), the robot planning
+    --episode-seconds per step from its belief, acting in the true
+    environment and updating the belief from the observation, until it
+    exits east or --episode-max-steps.  Reports the discounted return, the
+    steps taken and the trials per second of the planning steps."""
+    import numpy as np
+
+    import workloads as W
+    from paper_1802_06215_amd import episode as E
+    from paper_1802_06215_amd import hdx as H
+
+    desc = W.rocksample_model(15, 15, 1)
+    m = ctx.upload_model(desc)
+    out = dict(config="RockSample 15x15, 15 rocks, K=500, max depth 90, move-east rollouts, %.2f s per step, "
+                      "at most %d steps" % (args.episode_seconds, args.episode_max_steps),
+               move_east_return=round(10.0 * desc["gamma"] ** (desc["n"] - 1 - desc["start_x"]), 5), runs=[])
+    for threads in [int(v) for v in args.episode_threads.split(",")]:
+        nb = 8 if threads >= 16 else 0
+        rets, steps, rates, exits = [], [], [], 0
+        for e in range(1, args.episodes + 1):
+            rocks = np.random.default_rng(np.random.SeedSequence([0x45504953, e])).random(desc["m"]) < 0.5
+
+            def on_step(t, a, r, res, e=e):
+                if t % 10 == 0:
+                    log("episode", threads, e, "step", t, "action", a, "reward", r, "trials", res["trials"])
+
+            res = E.run_rocksample(ctx, m, desc, rocks, args.episode_max_steps, env_seed=1000 + e,
+                                   on_step=on_step, K=500, n_threads=threads, max_depth=90, batch_leaves=nb,
+                                   time_budget_s=args.episode_seconds, rollout=H.rollout_cfg(0, 1 << 30, 90),
+                                   seed=e, arena_bytes=8 << 30)
+            rets.append(res["discounted_return"])
+            steps.append(res["steps"])
+            rates.append(sum(res["trials"]) / max(sum(res["planning_s"]), 1e-9))
+            exits += int(res["exited"])
+            log("episode", threads, e, "return %.4f steps %d exited %s" % (res["discounted_return"], res["steps"],
+                                                                            res["exited"]))
+        r = np.asarray(rets)
+        out["runs"].append(dict(threads=threads, leaf_batcher=nb > 0, batch_leaves=nb, episodes=len(rets),
+                                discounted_return_mean=round(float(r.mean()), 4),
+                                discounted_return_se=round(float(r.std(ddof=1) / np.sqrt(len(r))) if len(r) > 1
+                                                           else 0.0, 4),
+                                returns=[round(v, 4) for v in rets], steps=steps, exited=exits,
+                                trials_per_s_mean=round(float(np.mean(rates)), 1)))
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -827,6 +882,10 @@ def main():
         return
     if args.surrogate_only:
         print(json.dumps(dict(surrogate=surrogate_section(ctx, args))), flush=True)
+        ctx.close()
+        return
+    if args.episodes > 0:
+        print(json.dumps(dict(episodes=episode_section(ctx, args))), flush=True)
         ctx.close()
         return
     log("building workload", args.workload)

@@ -49,22 +49,26 @@ class RockSampleEnv:
 
 
 def run_rocksample(ctx: "H.Context", model: "H.Model", desc: dict, true_rocks, max_steps: int,
-                   env_seed: int = 12345, **search_kwargs) -> dict:
+                   env_seed: int = 12345, on_step=None, **search_kwargs) -> dict:
     """One episode: plan, act, observe, update, until the robot exits or
     max_steps.  search_kwargs go to Context.search (K, n_threads, time
-    budget, ...); its step key is the time step."""
+    budget, ...); its step key is the time step.  on_step(t, action,
+    reward, search_result), when given, is called after every step."""
     x0, y0 = int(desc["start_x"]), int(desc["start_y"])
     belief = dict(x=x0, y=y0, p=np.full(desc["m"], 0.5))
     env = RockSampleEnv(ctx, model, x0, y0, true_rocks, env_seed)
     gamma, disc, total = desc["gamma"], 1.0, 0.0
-    actions, rewards, trials = [], [], []
+    actions, rewards, trials, plan_s = [], [], [], []
     for t in range(max_steps):
         res = ctx.search(model, belief, step=t, **search_kwargs)
+        plan_s.append(res["elapsed_s"])
         a = int(res["best_action"])
         r, z = env.step(a)
         actions.append(a)
         rewards.append(r)
         trials.append(res["trials"])
+        if on_step is not None:
+            on_step(t, a, r, res)
         total += disc * r
         disc *= gamma
         if env.term:
@@ -72,4 +76,4 @@ def run_rocksample(ctx: "H.Context", model: "H.Model", desc: dict, true_rocks, m
         belief, _ = H.belief_update(desc, belief, a, z)
         assert (belief["x"], belief["y"]) == (env.x, env.y)
     return dict(actions=actions, rewards=rewards, discounted_return=total, steps=len(actions),
-                exited=env.term, trials=trials)
+                exited=env.term, trials=trials, planning_s=plan_s)
