@@ -300,7 +300,7 @@ def test_mixed_batches_match_single_leaves_and_oracle(ctx):
         compare_leaf(desc, collect(it["m"], it["out"]), want, len(lf["idx"]))
 
 
-@pytest.mark.parametrize("threads,batch,K", [(1, 0, 500), (8, 8, 2000), (32, 16, 5000)])
+@pytest.mark.parametrize("threads,batch,K", [(1, 0, 500), (8, 8, 2000), (32, 16, 5000), (64, 8, 1000)])
 def test_nav_search(ctx, threads, batch, K):
     from paper_1802_06215_amd import hdx as H
     desc = W.nav_model(1)

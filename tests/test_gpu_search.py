@@ -46,7 +46,7 @@ def test_no_rocks_search_finds_exit_value(ctx):
     assert res["expansions"] >= 5
 
 
-@pytest.mark.parametrize("threads,batch", [(1, 0), (4, 0), (8, 0), (16, 0), (8, 8), (16, 16), (33, 11), (48, 16)])
+@pytest.mark.parametrize("threads,batch", [(1, 0), (4, 0), (8, 0), (16, 0), (8, 8), (16, 16), (33, 11), (48, 16), (48, 8), (64, 16)])
 def test_rs15_search_bounds(ctx, threads, batch):
     from paper_1802_06215_amd import hdx as H
     desc = W.rocksample_model(15, 15, 1)
