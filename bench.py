@@ -989,10 +989,10 @@ def main():
         # GPU-DESPOT analogue; several threads with Eq. 8-9 the HyP-DESPOT
         # one, expanding on a stream each or through the leaf batchers
         for threads, nb in ((1, 0), (4, 0), (8, 0), (16, 8), (32, 16), (48, 8), (48, 16), (64, 16)):
-            extra = dict(c_a=0.0, c_o=0.0) if threads == 1 else {}
+            choice = dict(c_a=0.0, c_o=0.0) if threads == 1 else {}
             res = ctx.search(m, belief, K=500, n_threads=threads, max_depth=90,
                              batch_leaves=nb, time_budget_s=args.search_seconds,
-                             rollout=H.rollout_cfg(0, 1 << 30, 90), seed=3, arena_bytes=arena, **extra)
+                             rollout=H.rollout_cfg(0, 1 << 30, 90), seed=3, arena_bytes=arena, **choice)
             search.append(dict(threads=threads, leaf_batcher=nb > 0, batch_leaves=nb,
                                trials_per_s=round(res["trials"] / res["elapsed_s"], 1),
                                expanding_trials_per_s=round(res["expansions"] / res["elapsed_s"], 1),
@@ -1018,10 +1018,10 @@ def main():
             mp = ctx.upload_model(dp)
             row = dict(peds=P)
             for name, threads, nb in (("gpu_despot", 1, 0), ("hyp_32x16", 32, 16), ("hyp_64x8", 64, 8)):
-                extra = dict(c_a=0.0, c_o=0.0) if threads == 1 else {}
+                choice = dict(c_a=0.0, c_o=0.0) if threads == 1 else {}
                 res = ctx.search(mp, W.pednav_belief(dp), K=500, n_threads=threads, max_depth=50, batch_leaves=nb,
                                  time_budget_s=args.search_seconds, rollout=H.rollout_cfg(0, 50), seed=3,
-                                 arena_bytes=8 << 30, **extra)
+                                 arena_bytes=8 << 30, **choice)
                 row[name] = dict(threads=threads, leaf_batcher=nb > 0, batch_leaves=nb,
                                  trials_per_s=round(res["trials"] / res["elapsed_s"], 1),
                                  expansions=res["expansions"], nodes=res["nodes"], depth=res["max_depth_reached"],
@@ -1048,10 +1048,10 @@ def main():
         for K in (100, 500, 1000, 2000, 3000, 5000):
             row = dict(K=K)
             for name, threads, nb in (("gpu_despot", 1, 0), ("hyp_32x16", 32, 16), ("hyp_64x8", 64, 8)):
-                extra = dict(c_a=0.0, c_o=0.0) if threads == 1 else {}
+                choice = dict(c_a=0.0, c_o=0.0) if threads == 1 else {}
                 res = ctx.search(m, W.nav_belief(desc), K=K, n_threads=threads, max_depth=90, batch_leaves=nb,
                                  time_budget_s=args.search_seconds, rollout=H.rollout_cfg(0, 1 << 30, 90), seed=3,
-                                 arena_bytes=32 << 30, **extra)
+                                 arena_bytes=32 << 30, **choice)
                 row[name] = dict(threads=threads, leaf_batcher=nb > 0, batch_leaves=nb,
                                  trials_per_s=round(res["trials"] / res["elapsed_s"], 1),
                                  expansions=res["expansions"], nodes=res["nodes"], depth=res["max_depth_reached"],
