@@ -289,6 +289,95 @@ def build(ctx, args):
                 groups=list(groups.values()))
 
 
+def root_values_same_tree(ctx, model, gamma: float, root: dict, K: int, cfg, key: int, mlp, horizon: int,
+                          ref_keys: int = 32, ref_seed: int = 1 << 20) -> dict:
+    """Measurement harness (not part of the library's path): the root lower
+    bound of one two-level DESPOT tree with its frontier valued three ways:
+    single default-policy rollouts (the plain method), the mean of
+    `ref_keys` independent rollouts per scenario (the reference), and the
+    surrogate.  The root (K scenarios `root`, ids 0..K-1) and every child it
+    reaches are expanded by the library's kernels under random-number key
+    `key` (that fixes the tree); the grandchildren at depth 2 form the
+    frontier; child lower bounds are frontier means over each child's
+    scenarios (Eq. 13) and the root value is the Eq. 4 backup of the
+    library's host tree.  Returns the three root values, and two readings of
+    how large a root error is: the root values of the two halves of the
+    reference's rollouts (its own sampling spread), and of frontier values
+    that keep a fraction s of the surrogate's error (reference + s (surrogate
+    - reference))."""
+    import numpy as np
+    import torch
+
+    from paper_1802_06215_amd import hdx as H
+    from paper_1802_06215_amd import surrogate as S
+
+    dev = root[next(iter(root))].device
+    A = model.n_actions
+    ids = torch.arange(K, dtype=torch.int32, device=dev)
+    idx = torch.arange(K, dtype=torch.int16, device=dev)
+    out0 = H.LeafBuffers(model, K)
+    ctx.expand_leaf([H.make_leaf(model, root, ids, idx, 0, -1, out0, key, 0, cfg)])
+    torch.cuda.synchronize()
+    nc0, off0, cn0 = out0.n_children.cpu().numpy(), out0.child_off.cpu().numpy(), out0.child_n.cpu().numpy()
+    perm0 = out0.perm.cpu().numpy()
+    nodes, keep, leaves = [], [], []
+    for a in range(A):
+        for c in range(int(nc0[a])):
+            seg = torch.from_numpy(perm0[a, off0[a, c]:off0[a, c] + cn0[a, c]].astype(np.int16)).to(dev)
+            out = H.LeafBuffers(model, int(cn0[a, c]), per_pair=True)
+            leaves.append(H.make_leaf(model, root, ids, seg, 1, a, out, key, 0, cfg))
+            nodes.append(out)
+            keep.append(seg)
+    ctx.expand_leaf(leaves)
+    torch.cuda.synchronize()
+    # frontier: every (action, scenario) pair of every depth-1 node, at depth 2
+    front = S._cat_states([{k: v[..., :A * o.n] for k, v in o.sprime.items()} for o in nodes])
+    fids = torch.cat([o.ids[:o.n].repeat(A) for o in nodes])
+    depths = torch.full((fids.numel(),), 2, dtype=torch.int32, device=dev)
+    v_one = torch.cat([o.L[:, :o.n].reshape(-1) for o in nodes])
+    half = ref_keys // 2
+    acc = [torch.zeros_like(v_one, dtype=torch.float64) for _ in range(2)]
+    for r in range(ref_keys):
+        _, L, _ = ctx.rollout_bounds(model, cfg, front, fids, depths, ref_seed + r, 0)
+        acc[0 if r < half else 1] += L.double()
+    v_ref = (acc[0] + acc[1]) / ref_keys
+    v_sur = mlp.forward(H.features(ctx, model, front, depths, horizon))
+    torch.cuda.synchronize()
+    host = [dict(n=o.n, nc=o.n_children.cpu().numpy(), z=o.child_z.cpu().numpy().view(np.uint64),
+                 cn=o.child_n.cpu().numpy(), off=o.child_off.cpu().numpy(), perm=o.perm.cpu().numpy(),
+                 u0=o.child_u0.cpu().numpy(), r=o.r_mean.cpu().numpy(), cap=o.cap) for o in nodes]
+    root_host = [out0.n_children.cpu().numpy(), out0.child_z.cpu().numpy().view(np.uint64), cn0,
+                 out0.child_u0.cpu().numpy(), out0.child_l0.cpu().numpy(), out0.r_mean.cpu().numpy()]
+
+    def root_value(values: np.ndarray) -> float:
+        tree = H.Tree(A, gamma, K, 0.0, 0.0)
+        first = tree.add_children(0, *root_host, out0.cap)
+        o = 0
+        for i, h in enumerate(host):
+            v = values[o:o + A * h["n"]].reshape(A, h["n"])
+            o += A * h["n"]
+            l0 = np.zeros_like(h["u0"])
+            for a in range(A):
+                for c in range(int(h["nc"][a])):
+                    seg = h["perm"][a, h["off"][a, c]:h["off"][a, c] + h["cn"][a, c]]
+                    l0[a, c] = v[a, seg].mean()
+            tree.add_children(first + i, h["nc"], h["z"], h["cn"], h["u0"], l0, h["r"], h["cap"])
+            tree.backup(first + i)
+        return tree.bounds(0)[1]
+
+    ref = v_ref.cpu().numpy()
+    sur = v_sur.cpu().numpy().astype(np.float64)
+    one = v_one.cpu().numpy().astype(np.float64)
+    halves = [(a / max(h, 1)).cpu().numpy() for a, h in ((acc[0], half), (acc[1], ref_keys - half))]
+    scaled = {s_: root_value(ref + s_ * (sur - ref)) for s_ in (0.5, 0.25, 0.1, 0.05)}
+    return dict(rollout=root_value(one), reference=root_value(ref), surrogate=root_value(sur),
+                reference_halves=[root_value(h) for h in halves], surrogate_error_scaled=scaled,
+                depth1_nodes=len(nodes), frontier_pairs=int(fids.numel()),
+                frontier_mean_reference=float(ref.mean()), frontier_bias_surrogate=float((sur - ref).mean()),
+                frontier_mae_surrogate=float(np.abs(sur - ref).mean()),
+                frontier_mae_rollout=float(np.abs(one - ref).mean()))
+
+
 def surrogate_section(ctx, args):
     """Learned rollout values against full rollouts on RockSample 15x15:
     uniform-random rollout policy of depth 90 (the expensive case a
@@ -439,7 +528,7 @@ def surrogate_section(ctx, args):
     same_tree = []
     for key in range(1, 9):
         root = ctx.sample_scenarios(m, W.rocksample_belief(desc), 500, 40 + key, 0)
-        same_tree.append(S.root_values_same_tree(ctx, m, desc["gamma"], root, 500, rcfg, key, net, 90,
+        same_tree.append(root_values_same_tree(ctx, m, desc["gamma"], root, 500, rcfg, key, net, 90,
                                                  ref_keys=args.same_tree_refs))
         log("same tree", key, same_tree[-1])
     rel = lambda v, ref: abs(v - ref) / max(abs(ref), 1e-9)

@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 import torch
 
+import bench
 import oracle
 import workloads as W
 from gpu_util import cfg_pair, collect, gpu_leaf_desc, ids_dev, to_dev, assert_states_equal, bits
@@ -301,7 +302,7 @@ def test_same_tree_root_values_match_oracle(ctx, net):
     the oracle's tree built from its own expansions (1e-5 relative); the
     reference and surrogate variants are finite; the frontier holds every
     (action, scenario) pair of every depth-1 node."""
-    from paper_1802_06215_amd import hdx as H, surrogate as S
+    from paper_1802_06215_amd import hdx as H
     desc = W.rocksample_model(7, 8, 1)
     m = ctx.upload_model(desc)
     K = 48
@@ -310,7 +311,7 @@ def test_same_tree_root_values_match_oracle(ctx, net):
         root = ctx.sample_scenarios(m, W.rocksample_belief(desc), K, 10 + key, 0)
         torch.cuda.synchronize()
         root_np = dict(w=root["w"].cpu().numpy().astype(np.int32))
-        got = S.root_values_same_tree(ctx, m, desc["gamma"], root, K, cfg, key, net, 30, ref_keys=2)
+        got = bench.root_values_same_tree(ctx, m, desc["gamma"], root, K, cfg, key, net, 30, ref_keys=2)
         want = _oracle_two_level_root(desc, oracle.cfg(2, 1 << 30, 30), root_np, K, key)
         print("key", key, got, want, flush=True)
         assert abs(got["rollout"] - want) <= 1e-5 * max(1.0, abs(want)), (got["rollout"], want)
