@@ -73,7 +73,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rs15", choices=["rs15", "rs7", "ped16", "mix64", "mars11", "mars15", "mars20", "nav13"])
+    ap.add_argument("--workload", default="rs15", choices=["rs15", "rs7", "ped16", "ped16s", "mix64", "mars11", "mars15",
+                                                           "mars20", "nav13"])
     ap.add_argument("--leaves", type=int, default=0, help="leaves per batch (0 = workload default)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -233,6 +234,14 @@ def build(ctx, args):
         for i in range(B):
             n_leaf = max(1, 500 >> (i % 3))
             lf = W.pednav_leaf(desc, 500, n_leaf, 1000 + i, depth=1 + i % 12)
+            items.append((desc, lf, 7, (0, 50, -1)))
+    elif wl == "ped16s":
+        # the small leaves a driving search expands below its root (hashed
+        # observations leave a few scenarios per child): 1..4 scenarios
+        B = args.leaves or 1024
+        desc = W.pednav_model(16, 5, 1)
+        for i in range(B):
+            lf = W.pednav_leaf(desc, 40, 1 + i % 4, 1000 + i, depth=1 + i % 12)
             items.append((desc, lf, 7, (0, 50, -1)))
     else:
         inst = W.mixed_instances(64, 42)
@@ -1184,6 +1193,8 @@ def main():
                      "depth 30; %d synthetic leaves",
                  ped16="PED16 leaf expansion: 16 pedestrians, 5 goals, |A|=3, K=500, rollouts of 50; "
                        "%d synthetic leaves",
+                 ped16s="PED16S leaf expansion: 16 pedestrians, 5 goals, |A|=3, rollouts of 50; %d synthetic "
+                        "small leaves (n in {1,2,3,4}), one lane per pedestrian",
                  mix64="MIX64: 64 planner instances (RockSample 7..20 / driving, K in {100,200,500}); "
                        "%d leaves in one launch")
     names["nav13"] = ("NAV13 leaf expansion: navigation in a partially known 13x13 map, 124 unknown cells, |A|=9, "

@@ -243,6 +243,9 @@ __host__ __device__ inline MedLayout make_med_layout(int32_t np) {
 // the LDS carve-up.
 struct Variant {
     int32_t mode, pm, n_max;
+    // driving only: the kernel instance whose tiles expand a leaf one lane
+    // per pedestrian when n times the group width fits a wavefront
+    int32_t group = 0;
 };
 Variant pick_variant(int32_t has_rs, int32_t has_ped, int32_t ped_max, int32_t n_max, int32_t has_mars,
                      int32_t has_nav);

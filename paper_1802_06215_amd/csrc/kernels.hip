@@ -958,7 +958,7 @@ __device__ __forceinline__ void run_mode(const HDX_CONST LeafTask *T, int a, uns
     }
 }
 
-template <int MODE, int PM>
+template <int MODE, int PM, bool kGroup = false>
 __global__ __launch_bounds__(max_threads<MODE>(), min_waves<MODE>()) void expand_tiles(const LeafTask *tasks,
                                                                                        const Tile *tiles,
                                                                                        TileQueue *queue,
@@ -985,7 +985,7 @@ __global__ __launch_bounds__(max_threads<MODE>(), min_waves<MODE>()) void expand
         if (t >= n_tiles) break;
         const HDX_CONST Tile *tile = (const HDX_CONST Tile *)(tiles + t);
         const HDX_CONST LeafTask *T = (const HDX_CONST LeafTask *)(tasks + tile->leaf);
-        run_mode<MODE, PM>(T, tile->action, lds, Ly);
+        run_mode<MODE, PM, kGroup>(T, tile->action, lds, Ly);
     }
     if (persistent && threadIdx.x == 0) {
         __threadfence();
@@ -1030,6 +1030,11 @@ hipError_t configure_t() {
     hipError_t e = hipFuncSetAttribute((const void *)expand_tiles<MODE, PM>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, max_dynamic_lds());
     if (e != hipSuccess) return e;
+    if (MODE == 1) {
+        e = hipFuncSetAttribute((const void *)expand_tiles<MODE, PM, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                max_dynamic_lds());
+        if (e != hipSuccess) return e;
+    }
     return hipFuncSetAttribute((const void *)expand_args<MODE, PM>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                max_dynamic_lds());
 }
@@ -1044,7 +1049,7 @@ hipError_t launch_args_t(const ArgPack &pack, const Schedule &sch, hipStream_t s
     return hipGetLastError();
 }
 
-template <int MODE, int PM>
+template <int MODE, int PM, bool kGroup = false>
 hipError_t launch_expand_t(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queue, int32_t n_tiles,
                            int32_t n_max, const Schedule &sch, int32_t n_cu, hipStream_t stream) {
     // persistent: a fixed grid that drains the tile queue, so a captured
@@ -1052,7 +1057,7 @@ hipError_t launch_expand_t(const LeafTask *d_tasks, const Tile *d_tiles, TileQue
     const int grid = sch.persistent > 0 ? n_cu * sch.persistent : n_tiles;
     if (grid < 1) return hipSuccess;
     const int threads = sch.threads > max_threads<MODE>() ? max_threads<MODE>() : sch.threads;
-    hipLaunchKernelGGL((expand_tiles<MODE, PM>), dim3(grid), dim3(threads), lds_bytes<MODE>(n_max), stream, d_tasks,
+    hipLaunchKernelGGL((expand_tiles<MODE, PM, kGroup>), dim3(grid), dim3(threads), lds_bytes<MODE>(n_max), stream, d_tasks,
                        d_tiles, d_queue, n_max, sch.persistent > 0 ? 1 : 0, sch.xcd_remap);
     return hipGetLastError();
 }
@@ -1219,11 +1224,15 @@ hipError_t configure_expand_kernels() {
 hipError_t launch_expand(const LeafTask *d_tasks, const Tile *d_tiles, TileQueue *d_queue, int32_t n_tiles,
                          const Variant &v, const Schedule &sch, int32_t n_cu, hipStream_t stream) {
 #define HDX_LAUNCH(M, P) launch_expand_t<M, P>(d_tasks, d_tiles, d_queue, n_tiles, v.n_max, sch, n_cu, stream)
+#define HDX_LAUNCH_G(P) launch_expand_t<1, P, true>(d_tasks, d_tiles, d_queue, n_tiles, v.n_max, sch, n_cu, stream)
     if (v.mode == 0) return HDX_LAUNCH(0, 1);
     if (v.mode == 3) return HDX_LAUNCH(3, 1);
     if (v.mode == 4) return HDX_LAUNCH(4, 1);
+    if (v.mode == 1 && v.group)
+        return v.pm == 8 ? HDX_LAUNCH_G(8) : v.pm == 16 ? HDX_LAUNCH_G(16) : HDX_LAUNCH_G(32);
     if (v.mode == 1) return v.pm == 8 ? HDX_LAUNCH(1, 8) : v.pm == 16 ? HDX_LAUNCH(1, 16) : HDX_LAUNCH(1, 32);
     return v.pm == 8 ? HDX_LAUNCH(2, 8) : v.pm == 16 ? HDX_LAUNCH(2, 16) : HDX_LAUNCH(2, 32);
+#undef HDX_LAUNCH_G
 #undef HDX_LAUNCH
 }
 

@@ -710,6 +710,10 @@ hipError_t hdx::launch_classes(const LeafTask *d_tasks, const Tile *d_tiles, Til
         if (plan.count[g] == 0 || !(mask & (1ull << g))) continue;
         Variant vg = group_variant(g);
         vg.n_max = std::max(lds_n[g], plan.n_max[g]);
+        // driving leaves small enough for every scenario's pedestrians to
+        // get lanes of their own (n times the pedestrian bound fits a
+        // wavefront): the element-level instance
+        vg.group = vg.mode == 1 && plan.n_max[g] * vg.pm <= 64 ? 1 : 0;
         // a workgroup no wider than the group's leaves need
         const int need = std::min(variant_max_threads(vg), std::max(64, pow2_at_least(std::max(vg.n_max, 1))));
         Schedule sc = sch[g];

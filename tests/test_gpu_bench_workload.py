@@ -22,7 +22,7 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("workload,sample", [("rs15", 12), ("rs7", 12), ("ped16", 6), ("mix64", 12)])
+@pytest.mark.parametrize("workload,sample", [("rs15", 12), ("rs7", 12), ("ped16", 6), ("ped16s", 16), ("mix64", 12)])
 def test_bench_workload_sampled_leaves(ctx, workload, sample):
     import bench
     from paper_1802_06215_amd import Batch

@@ -8,8 +8,12 @@ and rollout run element by element.  They must give the oracle's states,
 rewards and observations bit for bit and its values within the usual FP
 tolerance, and the one-lane path's results bit for bit: the stand-alone
 bounds call (one lane per state) on the leaf's stepped states, ids and
-depth, and the staged batched launch of the same leaf (which never uses
-the element-level path), field by field."""
+depth, and a staged batched launch of the same leaf on one lane per
+scenario (a larger leaf in the same dispatch keeps it off the
+element-level instance), field by field.  Batches of small leaves take the
+element-level instance of the staged kernel: they must match the oracle
+and the one-leaf calls bit for bit, under both launch plans and in a
+graph."""
 import numpy as np
 import pytest
 import torch
@@ -67,8 +71,14 @@ def test_small_leaf_group_rollout(ctx, peds, n, policy):
     for d in (out.states, out.sprime):
         for t in d.values():
             t.fill_(7)
-    b = Batch(ctx, 1, A)
-    b.set_leaves([leaf])
+    # one dispatch whose largest leaf (100 scenarios) keeps it on one lane
+    # per scenario
+    big = W.pednav_leaf(desc, 200, 100, 5 + peds, p_term=0.1)
+    bpar, bpids = to_dev(oracle.parent_states(desc, big)), ids_dev(big["ids"])
+    bleaf, bout, bidx = gpu_leaf_desc(m, bpar, bpids, big["idx"], big["depth"], big["last_action"], 11, 2, hcfg, True)
+    b = Batch(ctx, 2, 2 * A)
+    b.set_split(False)
+    b.set_leaves([leaf, bleaf])
     b.launch()
     torch.cuda.synchronize()
     got2 = collect(m, out)
@@ -86,4 +96,56 @@ def test_small_leaf_group_rollout(ctx, peds, n, policy):
             if a1.dtype == np.float32:
                 a1, a2 = a1.view(np.uint32), a2.view(np.uint32)
             assert np.array_equal(a1, a2), key
+    b.close()
+
+
+@pytest.mark.parametrize("split,graph", [(True, False), (False, False), (False, True)])
+def test_batched_small_leaves_element_level(ctx, split, graph):
+    """Small driving leaves of three pedestrian bounds (8, 16, 32) in one
+    batch: every dispatch's largest leaf fits its wavefront with a lane per
+    pedestrian, so the staged kernel's element-level instance runs.  Each
+    leaf matches the oracle and its own one-leaf call bit for bit."""
+    from paper_1802_06215_amd import Batch
+    from paper_1802_06215_amd import hdx as H
+    ocfg, hcfg = cfg_pair(0, 50, -1)
+    items = []
+    for peds, ns in ((6, (1, 5, 8)), (16, (1, 2, 3, 4)), (20, (1, 2))):
+        desc = W.pednav_model(peds, 5, 3)
+        m = ctx.upload_model(desc)
+        for j, n in enumerate(ns):
+            lf = W.pednav_leaf(desc, 30, n, 40 + 7 * peds + j, p_term=0.1)
+            par_np = oracle.parent_states(desc, lf)
+            par, pids = to_dev(par_np), ids_dev(lf["ids"])
+            leaf, out, idx = gpu_leaf_desc(m, par, pids, lf["idx"], lf["depth"], lf["last_action"], 13, 1, hcfg,
+                                           True)
+            items.append((desc, m, lf, par_np, par, pids, leaf, out, idx))
+    print("batched element-level leaves", len(items), "split", split, "graph", graph, flush=True)
+    single = []
+    for desc, m, lf, par_np, par, pids, leaf, out, idx in items:
+        ctx.expand_leaf([leaf])
+        torch.cuda.synchronize()
+        single.append(collect(m, out))
+    tiles = sum(it[0]["n_actions"] for it in items)
+    b = Batch(ctx, len(items), tiles)
+    b.set_split(split)
+    b.set_leaves([it[6] for it in items])
+    if graph:
+        b.use_graph(True)
+    for rep in range(2 if graph else 1):
+        for it in items:
+            for t in (it[7].L, it[7].perm, it[7].child_l0, it[7].steps, it[7].n_children):
+                t.fill_(-3)
+        b.launch()
+        torch.cuda.synchronize()
+        for (desc, m, lf, par_np, par, pids, leaf, out, idx), one in zip(items, single):
+            got = collect(m, out)
+            n = len(lf["idx"])
+            ref = oracle.expand_leaf(desc, ocfg, par_np, lf["ids"].astype(np.uint32), lf["idx"], lf["depth"],
+                                     lf["last_action"], 13, 1, per_pair=True)
+            compare_leaf(desc, got, ref, n)
+            for key in ("L", "U", "r", "z", "perm", "child_of", "steps", "r_mean", "n_children", "ids"):
+                a1, a2 = np.asarray(one[key]), np.asarray(got[key])
+                if a1.dtype == np.float32:
+                    a1, a2 = a1.view(np.uint32), a2.view(np.uint32)
+                assert np.array_equal(a1, a2), (key, desc["n_peds"], n)
     b.close()
