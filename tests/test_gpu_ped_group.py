@@ -109,7 +109,7 @@ def test_batched_small_leaves_element_level(ctx, split, graph):
     from paper_1802_06215_amd import hdx as H
     ocfg, hcfg = cfg_pair(0, 50, -1)
     items = []
-    for peds, ns in ((6, (1, 5, 8)), (16, (1, 2, 3, 4)), (20, (1, 2))):
+    for peds, ns in ((6, (1, 5, 8)), (16, (1, 2, 3, 4, 4, 3, 2, 1)), (20, (1, 2))):
         desc = W.pednav_model(peds, 5, 3)
         m = ctx.upload_model(desc)
         for j, n in enumerate(ns):
@@ -125,6 +125,22 @@ def test_batched_small_leaves_element_level(ctx, split, graph):
         ctx.expand_leaf([leaf])
         torch.cuda.synchronize()
         single.append(collect(m, out))
+    if split and not graph:
+        # more leaves than one kernel-argument pack: hdx_expand_leaf stages
+        # them and launches the element-level instance per model
+        assert len(items) > 11
+        for it in items:
+            it[7].L.fill_(-3)
+            it[7].perm.fill_(-3)
+        ctx.expand_leaf([it[6] for it in items])
+        torch.cuda.synchronize()
+        for (desc, m, lf, par_np, par, pids, leaf, out, idx), one in zip(items, single):
+            got = collect(m, out)
+            for key in ("L", "U", "r", "z", "perm", "child_of", "steps", "r_mean", "n_children", "ids"):
+                a1, a2 = np.asarray(one[key]), np.asarray(got[key])
+                if a1.dtype == np.float32:
+                    a1, a2 = a1.view(np.uint32), a2.view(np.uint32)
+                assert np.array_equal(a1, a2), ("staged call", key, desc["n_peds"])
     tiles = sum(it[0]["n_actions"] for it in items)
     b = Batch(ctx, len(items), tiles)
     b.set_split(split)
