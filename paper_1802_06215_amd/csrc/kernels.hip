@@ -274,7 +274,9 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
         typename Ops::State st;
         // gather + update + expansion step of one scenario
         auto expand_one = [&]() {
-            const int p = T->idx[k];
+            // 32-bit unsigned offsets (positions are below 2^15, grouped-order
+            // indices below 2^31) let the loads and stores take a scalar base
+            const uint32_t p = (uint16_t)T->idx[(uint32_t)k];
             id = T->parent_ids[p];
             Ops::load(M, parent, p, st);
             if (last_action >= 0) {
@@ -464,8 +466,8 @@ __device__ void run_tile(const HDX_CONST LeafTask *T, const int a, unsigned char
         for (int k = tid; k < n; k += nt) {
             const int32_t cw = kchild[k];
             const int v = cw & 31;
-            T->perm[(int64_t)a * n + koff[v] + kc[(k >> 6) * 32 + v] + (cw >> 5)] = (int16_t)k;
-            if (child_of) child_of[(int64_t)a * n + k] = kci[v];
+            T->perm[(uint32_t)(a * n + koff[v] + kc[(k >> 6) * 32 + v] + (cw >> 5))] = (int16_t)k;
+            if (child_of) child_of[(uint32_t)(a * n + k)] = kci[v];
         }
         __syncthreads();  // LDS is reused by the next tile
         return;

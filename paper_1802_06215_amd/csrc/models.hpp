@@ -200,7 +200,7 @@ struct RsOps {
             const int i = a - 5;
             const int dx = x - M.h->rock_x[i], dy = y - M.h->rock_y[i];
             const uint32_t u = philox(id, depth, 0, kTagStep, k0, k1).x;
-            const int correct = u <= M.thr[dx * dx + dy * dy];
+            const int correct = u <= M.thr[(uint32_t)(dx * dx + dy * dy)];
             const int truth = (w >> (10 + i)) & 1;
             z = (correct ? truth : !truth) ? 1 : 2;
         }
@@ -257,7 +257,8 @@ struct RsOps {
         }
         if (xs != wu.x || ys != wu.y) {
             const int lane = (int)__lane_id();
-            const float ci = lane < nr ? 10.0f * M.gg[abs(xs - M.h->rock_x[lane]) + abs(ys - M.h->rock_y[lane])] : 0.0f;
+            const float ci =
+                lane < nr ? 10.0f * M.gg[(uint32_t)(abs(xs - M.h->rock_x[lane]) + abs(ys - M.h->rock_y[lane]))] : 0.0f;
             // entry e = 16 g + m: group g's good rocks under pattern m, in index order
             float t0 = 0.0f, t1 = 0.0f;
             const int g0 = lane >> 4, g1 = 4 + (lane >> 4), m = lane & 15;
@@ -355,7 +356,7 @@ struct MarsOps {
         } else if (kObs) {
             const int i = b - 5;
             const int dx = x - M.h->rock_x[i], dy = y - M.h->rock_y[i];
-            const int correct = word <= M.thr[dx * dx + dy * dy];
+            const int correct = word <= M.thr[(uint32_t)(dx * dx + dy * dy)];
             const int truth = (st.rk >> i) & 1;
             zj = (correct ? truth : !truth) ? 1 : 2;
         }
@@ -434,7 +435,7 @@ struct MarsOps {
         const int nr = M.h->n_rocks;
         if (ps != wu.p) {
             const int lane = (int)__lane_id();
-            const float ci = lane < nr ? 10.0f * M.gg[near(ps, M.h->rock_x[lane], M.h->rock_y[lane])] : 0.0f;
+            const float ci = lane < nr ? 10.0f * M.gg[(uint32_t)near(ps, M.h->rock_x[lane], M.h->rock_y[lane])] : 0.0f;
             float t0 = 0.0f, t1 = 0.0f;
             const int g0 = lane >> 4, g1 = 4 + (lane >> 4), m = lane & 15;
 #pragma unroll
