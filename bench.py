@@ -553,12 +553,12 @@ def surrogate_section(ctx, args):
 
     # search at equal budget
     runs = {}
-    # each form under three random-number keys: the root value of equal
+    # each form under five random-number keys: the root value of equal
     # searches varies with the key, so the forms are compared by their means
     # (equal time, then an equal number of trials: the lower bound of the
     # root grows as the tree grows, so the equal-trials runs isolate the
     # accuracy of the leaf values from the speed of the search)
-    keys = (3, 4, 5)
+    keys = (3, 4, 5, 6, 7)
     EQ_TRIALS = 8000
     # (the third form adds the judged leaves' mean l0 difference to the
     # surrogate's child l0, once eight leaves are judged)
