@@ -923,7 +923,7 @@ def episode_section(ctx, args) -> dict:
                       "at most %d steps" % (args.episode_seconds, args.episode_max_steps),
                move_east_return=round(10.0 * desc["gamma"] ** (desc["n"] - 1 - desc["start_x"]), 5), runs=[])
     for threads in [int(v) for v in args.episode_threads.split(",")]:
-        nb = 8 if threads >= 16 else 0
+        nb = 16 if threads >= 32 else 8 if threads >= 16 else 0
         rets, steps, rates, exits = [], [], [], 0
         for e in range(1, args.episodes + 1):
             rocks = np.random.default_rng(np.random.SeedSequence([0x45504953, e])).random(desc["m"]) < 0.5
